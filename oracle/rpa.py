@@ -1,0 +1,195 @@
+"""RPA response, dielectric matrix, inverse and loss (oracle, FP64, numpy).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Written from Sec. II.D of the paper:
+
+* Eq. (RPA): eps_GG'(w, q) = delta_GG' - 4 pi alpha / (V |q+G||q+G'|)
+  sum_{ik, jk'} (f_ik - f_jk') <ik|e^{-i(q+G)r}|jk'><jk'|e^{i(q+G')r}|ik>
+  / (w - (w_jk' - w_ik) + i sgn(w_jk' - w_ik) eta), with k' = k + q and
+  T = 0 occupations f = 2 (occupied) or 0 (empty).
+* Eq. (eps_LFE): eps(w, q+G) = 1 / [eps^{-1}]_GG; the macroscopic eps_M is
+  the G = 0 entry.
+* Eq. (eps_noLFE): off-diagonal entries dropped, eps^noLFE = eps_GG.
+* The loss is Im(-1/eps) (Eq. dynamic_structure_factor uses it).
+
+Readings of points the paper leaves open (each also listed in the design doc):
+
+* Hartree atomic units, so 4 pi alpha -> 4 pi; eV at the boundary with
+  1 Ha = 27.211386245988 eV.
+* The k sum carries the weight 1/N_k (crystal volume N_k V), the standard
+  Adler-Wiser normalisation, so chi0 does not grow with the k grid.
+* Finite eta, evaluated as written (no limit, no Kramers-Kronig): the
+  time-ordered prescription, +i eta on the resonant (v -> c) term and
+  -i eta on the anti-resonant (c -> v) term.
+* Synthetic states are not time-reversal symmetric, so the anti-resonant
+  pair density sigma_vck(Q) = <v,k+q|e^{iQr}|c,k> is kept explicitly.
+* The row index G carries the complex conjugate.
+
+Transition index t = ((s * n_k + k) * n_occ + v) * n_cond + c with s = 0 for
+the resonant pair density rho_vck(Q) = <c,k+q|e^{iQr}|v,k> and s = 1 for
+sigma_vck(Q); both rows are stored in R[t][G].
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import gto
+
+HARTREE_EV = 27.211386245988
+
+
+def q_plus_g(lat, q_cart, G_int) -> np.ndarray:
+    """Cartesian Q_G = q + G for integer reciprocal-basis triples G_int."""
+    b = gto.reciprocal_basis(lat)
+    return np.asarray(q_cart, np.float64)[None, :] + np.asarray(G_int, np.float64) @ b
+
+
+def pair_densities(M: np.ndarray, C_k: np.ndarray, C_kq: np.ndarray, n_occ: int) -> np.ndarray:
+    """R[2][k][v][c][G] from the AO matrix M[k][G][mu][nu].
+
+    rho_vck(G)   = sum_{mu nu} C_mu,c(k+q)^* M_mu,nu(k; Q_G) C_nu,v(k)
+    sigma_vck(G) = sum_{mu nu} C_mu,v(k+q)^* M_mu,nu(k; Q_G) C_nu,c(k)
+    Parity: pinned by orthonormality at Q = 0 and by the all-band sum identity.
+    """
+    nk, ng, nao, _ = M.shape
+    nb = C_k.shape[2]
+    nc = nb - n_occ
+    MC = np.matmul(M, C_k[:, None, :, :])                  # [k][G][mu][b]
+    CqH = np.conj(np.swapaxes(C_kq, 1, 2))[:, None]        # [k][1][b][mu]
+    B = np.matmul(CqH, MC)                                 # [k][G][b'][b] = <b',k+q|..|b,k>
+    R = np.empty((2, nk, n_occ, nc, ng), np.complex128)
+    # resonant: bra c at k+q, ket v at k
+    R[0] = np.transpose(B[:, :, n_occ:, :n_occ], (0, 3, 2, 1))
+    # anti-resonant: bra v at k+q, ket c at k
+    R[1] = np.transpose(B[:, :, :n_occ, n_occ:], (0, 2, 3, 1))
+    return R
+
+
+def pair_densities_from_workload(wl_cell, wl_basis, lattice_range, k_frac, q_cart, G_int,
+                                 C_k, C_kq, n_occ, k_chunk: int = 64) -> np.ndarray:
+    """R for one q, the AO matrix built in k chunks to bound memory."""
+    Q = q_plus_g(wl_cell.lat, q_cart, G_int)
+    F = gto.cell_ft(wl_cell.lat, wl_cell.xyz, wl_basis.shell_atom, wl_basis.shell_l,
+                    wl_basis.shell_exp, lattice_range, Q)
+    nT, nG, nao, _ = F.shape
+    Ff = F.reshape(nT, -1)
+    nk = len(k_frac)
+    nc = C_k.shape[2] - n_occ
+    R = np.empty((2, nk, n_occ, nc, nG), np.complex128)
+    for k0 in range(0, nk, k_chunk):
+        k1 = min(nk, k0 + k_chunk)
+        ph = gto.bloch_phases(k_frac[k0:k1], lattice_range)
+        M = (ph @ Ff).reshape(k1 - k0, nG, nao, nao)
+        R[:, k0:k1] = pair_densities(M, C_k[k0:k1], C_kq[k0:k1], n_occ)
+    return R
+
+
+def transition_energies(E_k, E_kq, n_occ):
+    """Delta[k][v][c] = E_c(k+q) - E_v(k) and Delta'[k][v][c] = E_c(k) - E_v(k+q) (Ha)."""
+    ek = np.asarray(E_k, np.float64) / HARTREE_EV
+    ekq = np.asarray(E_kq, np.float64) / HARTREE_EV
+    d_res = ekq[:, None, n_occ:] - ek[:, :n_occ, None]
+    d_anti = ek[:, None, n_occ:] - ekq[:, :n_occ, None]
+    return d_res, d_anti
+
+
+def transition_weights(E_k, E_kq, n_occ, w_eV, eta_eV, volume) -> np.ndarray:
+    """W[w][t]: the occupation factor, energy denominator and 1/(N_k V) of Eq. (RPA).
+
+    resonant     (i = v at k, j = c at k+q):  2 / (N_k V (w - Delta + i eta))
+    anti-resonant(i = c at k, j = v at k+q): -2 / (N_k V (w + Delta' - i eta))
+    """
+    nk = np.asarray(E_k).shape[0]
+    d_res, d_anti = transition_energies(E_k, E_kq, n_occ)
+    w = np.asarray(w_eV, np.float64)[:, None] / HARTREE_EV
+    eta = float(eta_eV) / HARTREE_EV
+    norm = 1.0 / (nk * float(volume))
+    wr = 2.0 * norm / (w - d_res.reshape(1, -1) + 1j * eta)
+    wa = -2.0 * norm / (w + d_anti.reshape(1, -1) - 1j * eta)
+    return np.concatenate([wr, wa], axis=1)
+
+
+def chi0(R: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """chi0[w][G][G'] = sum_t R[t][G]^* W[w][t] R[t][G'] (row G conjugated).
+
+    Parity: pinned by Hermiticity at w = 0, eta = 0; the sign of the
+    anti-Hermitian part; the large-w moments; k-grid independence of the
+    first moment; a one-transition closed form.
+    """
+    Rt = R.reshape(-1, R.shape[-1])
+    out = np.empty((W.shape[0], Rt.shape[1], Rt.shape[1]), np.complex128)
+    RH = np.conj(Rt).T
+    for iw in range(W.shape[0]):
+        out[iw] = (RH * W[iw][None, :]) @ Rt
+    return out
+
+
+def coulomb_sqrt(Qc: np.ndarray) -> np.ndarray:
+    """sqrt(4 pi) / |q + G| (the symmetrised Coulomb factor)."""
+    qn = np.linalg.norm(np.asarray(Qc, np.float64), axis=1)
+    if np.any(qn == 0.0):
+        raise ValueError("q + G = 0")
+    return math.sqrt(4.0 * math.pi) / qn
+
+
+def epsilon(chi: np.ndarray, Qc: np.ndarray) -> np.ndarray:
+    """eps_GG' = delta_GG' - 4 pi chi0_GG' / (|q+G| |q+G'|)."""
+    v = coulomb_sqrt(Qc)
+    ng = len(v)
+    return np.eye(ng)[None] - v[None, :, None] * chi * v[None, None, :]
+
+
+def inverse_diagonal(eps: np.ndarray) -> np.ndarray:
+    """[eps^{-1}]_GG for each frequency (LAPACK getrf/getri through numpy)."""
+    inv = np.linalg.inv(eps)
+    return np.diagonal(inv, axis1=1, axis2=2).copy()
+
+
+def loss_lfe(eps: np.ndarray) -> np.ndarray:
+    """loss[w][G] = Im(-1/eps(w, q+G)) = -Im [eps^{-1}]_GG (Eq. eps_LFE)."""
+    return -np.imag(inverse_diagonal(eps))
+
+
+def loss_nolfe(eps: np.ndarray) -> np.ndarray:
+    """loss[w][G] = Im(-1/eps_GG) (Eq. eps_noLFE)."""
+    d = np.diagonal(eps, axis1=1, axis2=2)
+    return np.imag(-1.0 / d)
+
+
+def eps_macro(eps: np.ndarray) -> np.ndarray:
+    """eps_M(w) = 1 / [eps^{-1}]_00."""
+    return 1.0 / inverse_diagonal(eps)[:, 0]
+
+
+def solve(cell, basis, lattice_range, k_frac, n_occ, G_int, states, w_eV, eta_eV, lfe=True,
+          return_all=False):
+    """The full path for one q: R -> W -> chi0 -> eps -> loss."""
+    R = pair_densities_from_workload(cell, basis, lattice_range, k_frac, states.q_cart, G_int,
+                                     states.C_k, states.C_kq, n_occ)
+    volume = abs(float(np.linalg.det(np.asarray(cell.lat, np.float64))))
+    W = transition_weights(states.E_k, states.E_kq, n_occ, w_eV, eta_eV, volume)
+    chi = chi0(R, W)
+    Qc = q_plus_g(cell.lat, states.q_cart, G_int)
+    eps = epsilon(chi, Qc)
+    L = loss_lfe(eps) if lfe else loss_nolfe(eps)
+    if return_all:
+        return dict(R=R, W=W, chi0=chi, eps=eps, loss=L, Q=Qc)
+    return L
+
+
+def solve_workload(wl, iq=0, w_idx=None, lfe=True, return_all=False):
+    st = wl.states(iq)
+    w = wl.w_eV if w_idx is None else np.asarray(wl.w_eV)[w_idx]
+    return solve(wl.cell, wl.basis, wl.lattice_range, wl.k_frac, wl.n_occ, wl.G_int, st, w,
+                 wl.eta_eV, lfe=lfe, return_all=return_all)
+
+
+def rel_err_normwise(L: np.ndarray, Lref: np.ndarray) -> float:
+    """max over G of  max_w |L - Lref| / max_w |Lref|  (per-(q,G) curve, normwise)."""
+    num = np.max(np.abs(L - Lref), axis=0)
+    den = np.max(np.abs(Lref), axis=0)
+    den = np.where(den == 0.0, 1.0, den)
+    return float(np.max(num / den))

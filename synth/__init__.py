@@ -1,0 +1,26 @@
+"""Seeded synthetic workloads for the RPA screening path.
+
+This package stands in for the DFT step that, in the paper, supplies Kohn-Sham
+coefficients and energies (Sec. III).  It draws cells, Gaussian shells, grids
+and Lowdin-orthonormal random states from fixed seeds, and is the only code
+shared by the CPU oracle and the HIP path.  It computes no pair density, no
+response function and no dielectric matrix.
+"""
+from .generator import (  # noqa: F401
+    HARTREE_EV,
+    Cell,
+    Basis,
+    Workload,
+    QStates,
+    make_config1,
+    make_config2,
+    make_config3_items,
+    make_config4,
+    make_tiny,
+    fcc_cell,
+    reciprocal_rows,
+    gamma_grid,
+    g_cube,
+    g_shells,
+    draw_states,
+)

@@ -1,0 +1,222 @@
+"""Pins for the oracle's pair densities, chi0, eps, inverse and loss (CPU only).
+
+Each test checks a property that the paper's definitions (Eq. RPA,
+Eq. eps_LFE, Eq. eps_noLFE) or plain mathematics fix, chosen so that a
+dropped term, a swapped index, a wrong sign or a wrong normalisation fails.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gto, rpa
+from synth import make_tiny
+from synth.generator import Basis, Cell, QStates
+
+
+def _vol(cell):
+    return abs(np.linalg.det(cell.lat))
+
+
+# ---------------------------------------------------------------- pair densities
+def test_pair_density_orthonormality_at_q0(tiny):
+    """q = 0, G = 0 with all bands: <b', k|b, k> = delta (C^H S C = I)."""
+    st = tiny.states(0)
+    bs = tiny.basis
+    S = gto.overlap_matrix(tiny.cell.lat, tiny.cell.xyz, bs.shell_atom, bs.shell_l, bs.shell_exp, 1,
+                           tiny.k_frac)
+    # all-band matrix: pair densities with states at k on both sides
+    n = tiny.n_bands
+    for split in (1, tiny.n_occ):
+        R = rpa.pair_densities(S[:, None], st.C_k, st.C_k, split)
+        assert np.max(np.abs(R)) < 1e-12     # off-diagonal bands only
+    # diagonal: duplicate band b in front so that "c" runs over every band
+    for b in (0, n - 1):
+        Cp = np.concatenate([st.C_k[:, :, b:b + 1], st.C_k], axis=2)
+        R = rpa.pair_densities(S[:, None], Cp, Cp, 1)
+        want = np.zeros(n)
+        want[b] = 1.0
+        assert np.max(np.abs(R[0][:, 0, :, 0] - want[None, :])) < 1e-12
+
+
+def test_band_sum_identity(tiny):
+    """sum_j |<j,k+q|e^{iQr}|b,k>|^2 over ALL bands j = m^H S(k+q)^{-1} m, m = M C_b.
+
+    The right side uses a linear solve with the oracle's S(k+q) and no bra
+    coefficients, so it checks conjugation and index order of the band
+    contraction and the completeness of the Lowdin states.
+    """
+    st = tiny.states(0)
+    bs = tiny.basis
+    Q = rpa.q_plus_g(tiny.cell.lat, st.q_cart, tiny.G_int)
+    M = gto.ao_matrix(tiny.cell.lat, tiny.cell.xyz, bs.shell_atom, bs.shell_l, bs.shell_exp, 1,
+                      tiny.k_frac, Q)
+    qf = tiny.cell.lat @ st.q_cart / (2 * math.pi)
+    Skq = gto.overlap_matrix(tiny.cell.lat, tiny.cell.xyz, bs.shell_atom, bs.shell_l, bs.shell_exp, 1,
+                             tiny.k_frac + qf)
+    for b in (0, 3, tiny.n_bands - 1):
+        Cp = np.concatenate([st.C_k[:, :, b:b + 1], st.C_k], axis=2)
+        Cq = np.concatenate([st.C_kq[:, :, b:b + 1], st.C_kq], axis=2)
+        R = rpa.pair_densities(M, Cp, Cq, 1)            # R[0][k][0][j][G]: bra j at k+q, ket b at k
+        lhs = np.sum(np.abs(R[0][:, 0]) ** 2, axis=1)   # [k][G]
+        m = np.einsum("kgmn,kn->kgm", M, st.C_k[:, :, b])
+        rhs = np.real(np.einsum("kgm,kgm->kg", m.conj(), np.linalg.solve(Skq[:, None], m[..., None])[..., 0]))
+        assert np.max(np.abs(lhs - rhs)) < 1e-11 * max(1.0, np.max(np.abs(rhs)))
+
+
+# ---------------------------------------------------------------- chi0
+def _chi_parts(wl, w_eV, eta_eV):
+    st = wl.states(0)
+    R = rpa.pair_densities_from_workload(wl.cell, wl.basis, 1, wl.k_frac, st.q_cart, wl.G_int,
+                                         st.C_k, st.C_kq, wl.n_occ)
+    W = rpa.transition_weights(st.E_k, st.E_kq, wl.n_occ, w_eV, eta_eV, _vol(wl.cell))
+    return st, R, W, None
+
+
+def test_chi0_hermitian_at_zero_frequency_zero_eta(tiny):
+    st, R, W, _ = _chi_parts(tiny, np.array([0.0]), 0.0)
+    chi = rpa.chi0(R, W)[0]
+    assert np.max(np.abs(chi - chi.conj().T)) < 1e-14 * np.max(np.abs(chi))
+
+
+def test_chi0_antihermitian_part_negative(tiny):
+    """For w >= 0 both prescriptions give Im W_t <= 0, so (chi0 - chi0^H)/2i <= 0."""
+    st, R, W, _ = _chi_parts(tiny, np.linspace(0.0, 40.0, 9), tiny.eta_eV)
+    chi = rpa.chi0(R, W)
+    for c in chi:
+        A = (c - c.conj().T) / 2j
+        ev = np.linalg.eigvalsh(A)
+        assert ev.max() < 1e-12 * np.abs(ev).max()
+        assert ev.min() < 0
+
+
+def test_chi0_large_frequency_moments(tiny):
+    """chi0(w) = m1/w + m2/w^2 + O(w^-3) with
+    m1 = 2/(N_k V) [sum_res P_t - sum_anti P_t],
+    m2 = 2/(N_k V) [sum_res (Delta - i eta) P_t + sum_anti (Delta' - i eta) P_t],
+    P_t = rho_t(G)^* rho_t(G'), Delta = E_c(k+q) - E_v(k), Delta' = E_c(k) - E_v(k+q)."""
+    st = tiny.states(0)
+    wbig = 2.0e4  # Ha
+    eta = tiny.eta_eV / rpa.HARTREE_EV
+    _, R, W, _ = _chi_parts(tiny, np.array([wbig * rpa.HARTREE_EV]), tiny.eta_eV)
+    chi = rpa.chi0(R, W)[0]
+    nk = tiny.n_k
+    ha = rpa.HARTREE_EV
+    dres = np.array([[[st.E_kq[k, tiny.n_occ + c] - st.E_k[k, v] for c in range(tiny.n_cond)]
+                      for v in range(tiny.n_occ)] for k in range(nk)]) / ha
+    dant = np.array([[[st.E_k[k, tiny.n_occ + c] - st.E_kq[k, v] for c in range(tiny.n_cond)]
+                      for v in range(tiny.n_occ)] for k in range(nk)]) / ha
+    pref = 2.0 / (nk * _vol(tiny.cell))
+    P0 = np.einsum("kvcg,kvch->gh", R[0].conj(), R[0])
+    P1 = np.einsum("kvcg,kvch->gh", R[1].conj(), R[1])
+    m1 = pref * (P0 - P1)
+    m2 = pref * (np.einsum("kvc,kvcg,kvch->gh", dres - 1j * eta, R[0].conj(), R[0])
+                 + np.einsum("kvc,kvcg,kvch->gh", dant - 1j * eta, R[1].conj(), R[1]))
+    assert np.max(np.abs(wbig * chi - m1)) < 1e-3 * np.max(np.abs(m1)) + 1e-14
+    est_m2 = wbig * wbig * (chi - m1 / wbig)
+    assert np.max(np.abs(est_m2 - m2)) < 2e-3 * np.max(np.abs(m2))
+
+
+def test_chi0_tail_independent_of_kgrid():
+    """At large w, Im chi0_GG -> -(2 eta / (N_k V w^2)) sum_t |R_t(G)|^2: a
+    Brillouin-zone average of a smooth function of k, so it must agree
+    between k grids (this fixes the 1/N_k weight; without it the two grids
+    differ by 512/216)."""
+    tails = []
+    wbig = 1.0e5
+    for n in (6, 8):
+        wl = make_tiny(kgrid=n, n_g=9)
+        st, R, W, _ = _chi_parts(wl, np.array([wbig * rpa.HARTREE_EV]), wl.eta_eV)
+        tails.append(wbig * wbig * np.diagonal(rpa.chi0(R, W)[0]).imag)
+    assert np.all(tails[0] < 0)
+    rel = np.max(np.abs(tails[0] - tails[1]) / np.abs(tails[1]))
+    assert rel < 2e-2, rel
+
+
+def test_chi0_single_transition_conjugates_row():
+    R = np.zeros((2, 1, 1, 1, 3), np.complex128)
+    rho = np.array([0.3 + 0.1j, -0.2 + 0.5j, 0.05 - 0.4j])
+    R[0, 0, 0, 0] = rho
+    W = np.array([[0.7 - 0.2j, 0.0]])
+    chi = rpa.chi0(R, W)[0]
+    assert np.allclose(chi, (0.7 - 0.2j) * np.outer(rho.conj(), rho), atol=1e-15, rtol=0)
+
+
+# ---------------------------------------------------------------- eps
+def test_eps_length_scaling():
+    """Scale every length by s (cell, centres; exponents by 1/s^2; q by 1/s).
+    Pair densities of normalised orbitals are unchanged, chi0 ~ 1/V ~ s^-3 and
+    the Coulomb factor ~ s^2, so (eps - 1) ~ 1/s exactly."""
+    wl = make_tiny(kgrid=2, n_g=9, n_w=5)
+    st = wl.states(0)
+    base = rpa.solve(wl.cell, wl.basis, 1, wl.k_frac, wl.n_occ, wl.G_int, st, wl.w_eV, wl.eta_eV,
+                     return_all=True)["eps"]
+    s = 1.37
+    cell = Cell(wl.cell.name, wl.cell.a * s, wl.cell.lat * s, wl.cell.xyz * s, wl.cell.species)
+    basis = Basis(wl.basis.shell_atom, wl.basis.shell_l, wl.basis.shell_exp / s ** 2)
+    st2 = QStates(st.q_cart / s, st.C_k, st.E_k, st.C_kq, st.E_kq)
+    sc = rpa.solve(cell, basis, 1, wl.k_frac, wl.n_occ, wl.G_int, st2, wl.w_eV, wl.eta_eV,
+                   return_all=True)["eps"]
+    I = np.eye(len(wl.G_int))[None]
+    assert np.max(np.abs((sc - I) * s - (base - I))) < 1e-10 * np.max(np.abs(base - I))
+
+
+def test_eps_tends_to_one_at_large_q(cfg1_oracle):
+    eps = cfg1_oracle["eps"]
+    R = cfg1_oracle["R"].reshape(-1, eps.shape[1])
+    W = cfg1_oracle["W"]
+    Q = cfg1_oracle["Q"]
+    q2 = np.sum(Q * Q, axis=1)
+    bound = 4 * math.pi / q2[None, :] * (np.abs(W) @ (np.abs(R) ** 2))
+    dev = np.abs(np.diagonal(eps, axis1=1, axis2=2) - 1.0)
+    assert np.all(dev <= bound * (1 + 1e-12) + 1e-15)
+    # and the bound itself falls with |q+G|: largest |q+G| deviates far less than G = 0
+    assert dev[:, np.argmax(q2)].max() < 0.1 * dev[:, 0].max()
+
+
+def test_eps_antihermitian_part_psd(cfg1_oracle):
+    for e in cfg1_oracle["eps"][::8]:
+        ev = np.linalg.eigvalsh((e - e.conj().T) / 2j)
+        assert ev.min() > -1e-12 * np.abs(ev).max()
+
+
+# ---------------------------------------------------------------- inverse and loss
+def test_lfe_equals_nolfe_without_offdiagonals(cfg1_oracle):
+    eps = cfg1_oracle["eps"]
+    d = np.einsum("wgg->wg", eps)
+    diag_only = np.zeros_like(eps)
+    idx = np.arange(eps.shape[1])
+    diag_only[:, idx, idx] = d
+    assert np.max(np.abs(rpa.loss_lfe(diag_only) - rpa.loss_nolfe(eps))) < 1e-14
+    one = eps[:, :1, :1]
+    assert np.max(np.abs(rpa.loss_lfe(one) - rpa.loss_nolfe(one))) < 1e-15
+
+
+def test_loss_nonnegative(cfg1_oracle):
+    assert cfg1_oracle["loss"].min() > -1e-15
+    assert rpa.loss_nolfe(cfg1_oracle["eps"]).min() > -1e-15
+
+
+def test_inverse_diagonal_invariances(cfg1_oracle):
+    """diag(eps^-1) is unchanged by transposition and by the non-symmetric
+    Coulomb form eps' = 1 - v(q+G) chi0 (a similar matrix)."""
+    eps = cfg1_oracle["eps"][::16]
+    chi = cfg1_oracle["chi0"][::16]
+    Q = cfg1_oracle["Q"]
+    d = rpa.inverse_diagonal(eps)
+    assert np.max(np.abs(rpa.inverse_diagonal(np.swapaxes(eps, 1, 2)) - d)) < 1e-12
+    v = 4 * math.pi / np.sum(Q * Q, axis=1)
+    eps_ns = np.eye(len(Q))[None] - v[None, :, None] * chi
+    assert np.max(np.abs(rpa.inverse_diagonal(eps_ns) - d)) < 1e-11
+    X = np.linalg.inv(eps)
+    for e, x in zip(eps, X):
+        res = np.linalg.norm(e @ x - np.eye(len(e))) / (np.linalg.norm(e) * np.linalg.norm(x))
+        assert res < 1e-13
+
+
+def test_macroscopic_eps_is_inverse_head(cfg1_oracle):
+    eps = cfg1_oracle["eps"]
+    em = rpa.eps_macro(eps)
+    assert np.allclose(em, 1.0 / np.linalg.inv(eps)[:, 0, 0], rtol=1e-14, atol=0)
+    # loss at G = 0 is Im(-1/eps_M)
+    assert np.allclose(cfg1_oracle["loss"][:, 0], np.imag(-1.0 / em), rtol=1e-12, atol=1e-15)
