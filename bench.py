@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Throughput of the RPA screening hot path on one MI355X.
+
+One step = the whole path for the Si-like workload with N_G = 113 (28 GTOs,
+4 valence + 16 conduction bands, 8^3 k grid, 10 q along [100], 400 frequencies
+over 0-60 eV, eta = 0.1 eV): for each q, set_states (device-resident inputs,
+orthonormality check included), pair_density, chi0, eps_inv and loss.  The
+metric is (q, w) loss points per second with the chi0 bulk in split-BF16 on
+MFMA (FP64 head/wings and inversion); the plain FP32-MFMA form is timed the
+same way and reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2516.6   # MI355X dense BF16 MFMA
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 matrix
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-q", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-sample-w", type=int, default=48)
+    return ap.parse_args()
+
+
+def upload_workload(wl, n_q, torch):
+    """Generate the states and put every input in HBM before timing."""
+    dev = "cuda"
+    qs = []
+    for iq in range(n_q):
+        st = wl.states(iq)
+        qs.append(dict(
+            q=np.asarray(st.q_cart, np.float64),
+            C_k=torch.from_numpy(np.ascontiguousarray(st.C_k)).to(dev),
+            E_k=torch.from_numpy(np.ascontiguousarray(st.E_k)).to(dev),
+            C_kq=torch.from_numpy(np.ascontiguousarray(st.C_kq)).to(dev),
+            E_kq=torch.from_numpy(np.ascontiguousarray(st.E_kq)).to(dev),
+        ))
+    kf = torch.from_numpy(np.ascontiguousarray(wl.k_frac)).to(dev)
+    return qs, kf
+
+
+def run_step(ctx, wl, qs, kf, prec, loss_out):
+    for iq, d in enumerate(qs):
+        ctx.set_states(d["q"], kf, wl.n_occ, d["C_k"], d["E_k"], d["C_kq"], d["E_kq"])
+        ctx.pair_density(wl.G_int)
+        ctx.chi0(wl.w_eV, wl.eta_eV, prec, True)
+        ctx.eps_inv(True)
+        ctx.loss(loss_out[iq])
+
+
+def timed(ctx, wl, qs, kf, prec, loss_out, steps, warmup, torch):
+    for _ in range(warmup):
+        run_step(ctx, wl, qs, kf, prec, loss_out)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_step(ctx, wl, qs, kf, prec, loss_out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    st = ctx.stage_times()
+    ctx.set_timing(False)
+    return (t1 - t0), st
+
+
+def bulk_flops_per_launch(wl):
+    """Real multiply-adds of the Hermitian-form bulk GEMM for one q:
+    2 * (2 n_w rows) * (2 * upper-triangle pairs without G = 0) * N_T."""
+    n_g = len(wl.G_int)
+    pairs = n_g * (n_g + 1) // 2 - n_g
+    return 2.0 * (2 * len(wl.w_eV)) * (2 * pairs) * wl.n_t
+
+
+def normwise(L, Lref):
+    """max over G of max_w |L - Lref| / max_w |Lref| (one loss curve per G)."""
+    num = np.max(np.abs(L - Lref), axis=0)
+    den = np.max(np.abs(Lref), axis=0)
+    return float(np.max(num / np.where(den == 0, 1.0, den)))
+
+
+def cpu_baseline(wl, n_w_sample, gpu_loss_split, gpu_loss_fp32):
+    """The FP64 oracle on one q and a sample of frequencies (host cores)."""
+    from oracle import rpa
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count()
+    idx = np.linspace(0, len(wl.w_eV) - 1, n_w_sample).round().astype(int)
+    t0 = time.perf_counter()
+    ref = rpa.solve_workload(wl, 0, w_idx=idx)
+    dt = time.perf_counter() - t0
+    return dict(value=n_w_sample / dt, unit="points/s", cores=int(threads), kind="oracle",
+                sample=f"q index 0, {n_w_sample} of 400 frequencies, all 113 G "
+                       f"(rho for that q included), {dt:.1f} s",
+                err_split=normwise(gpu_loss_split[idx], ref),
+                err_fp32=normwise(gpu_loss_fp32[idx], ref) if gpu_loss_fp32 is not None else None)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards "
+              "over (q, w) with no exchange in the hot loop, which is not measured here.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2603_12326_amd import Context, build_info
+    from synth import make_config2
+
+    wl = make_config2(n_q=args.n_q)
+    qs, kf = upload_workload(wl, args.n_q, torch)
+    n_g, n_w = len(wl.G_int), len(wl.w_eV)
+    loss_out = [torch.empty((n_w, n_g), dtype=torch.float64, device="cuda") for _ in qs]
+    ctx = Context(0)
+    b = wl.basis
+    ctx.set_cell_basis(wl.cell.lat, wl.cell.xyz, b.shell_atom, b.shell_l, b.shell_exp, 1, 1)
+
+    points = args.n_q * n_w
+    res = {}
+    for prec in (["split_bf16"] + ([] if args.no_fp32 else ["fp32"])):
+        sec, st = timed(ctx, wl, qs, kf, prec, loss_out, args.steps, args.warmup, torch)
+        res[prec] = dict(sec=sec, st=st, loss0=loss_out[0].cpu().numpy().copy())
+
+    s = res["split_bf16"]
+    ms_step = 1e3 * s["sec"] / args.steps
+    value = points * args.steps / s["sec"]
+    nb = max(1, s["st"]["bulk_launches"])
+    avg_bulk_s = 1e-3 * s["st"]["chi0_bulk_ms"] / nb
+    alg = bulk_flops_per_launch(wl)
+    achieved = 3.0 * alg / avg_bulk_s / 1e12       # BF16 MFMA flops (hi*hi, hi*lo, lo*hi)
+    out = {
+        "metric": "(q,w) loss points/s at N_G=113: MFMA split vs plain FP32, rel err 1e-4",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "Si-like fcc a=10.26, 28 GTO (3s2p1d per atom), 4+16 bands, "
+                               "8^3 k, 10 q along [100], N_G=113, 400 w over 0-60 eV, eta=0.1 eV",
+                   "n_g": n_g, "n_q": args.n_q, "n_w": n_w, "n_k": wl.n_k, "n_t": wl.n_t,
+                   "chi0_bulk": "split-bf16 MFMA, fp32 accumulation",
+                   "head_wings": "fp64", "inversion": "fp64"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                     "kernel": "k_bulk<bf16> (chi0 bulk)", "avg_launch_ms": 1e3 * avg_bulk_s,
+                     "flops_per_launch_fp32_equiv": alg},
+        "stages_ms_per_step": {k: (v / args.steps if k.endswith("_ms") else v)
+                               for k, v in s["st"].items()},
+        "build": build_info(),
+    }
+    if "fp32" in res:
+        f = res["fp32"]
+        nbf = max(1, f["st"]["bulk_launches"])
+        avg32 = 1e-3 * f["st"]["chi0_bulk_ms"] / nbf
+        out["fp32_value"] = points * args.steps / f["sec"]
+        out["speedup_split_vs_fp32"] = value / out["fp32_value"]
+        out["fp32_roofline"] = {"achieved": alg / avg32 / 1e12, "peak": PEAK_FP32_TFLOPS,
+                                "frac": alg / avg32 / 1e12 / PEAK_FP32_TFLOPS,
+                                "avg_launch_ms": 1e3 * avg32}
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(wl, args.cpu_sample_w, res["split_bf16"]["loss0"],
+                          res["fp32"]["loss0"] if "fp32" in res else None)
+        out["max_rel_err_split"] = cb.pop("err_split")
+        out["max_rel_err_fp32"] = cb.pop("err_fp32")
+        out["cpu_baseline"] = cb
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * qcx.h - C ABI of the MI355X library for all-electron RPA screening with
+ * local field effects (pair densities -> chi0 -> FP64 eps inversion -> loss).
+ *
+ * The calls follow the statement of the problem in Sec. II.D of the paper:
+ * Eq. (RPA) defines eps_GG'(w, q) from Kohn-Sham states at k and k' = k + q,
+ * Eq. (eps_LFE) the finite-momentum eps(w, q+G) = 1/[eps^-1]_GG (G = 0 gives
+ * the macroscopic eps_M) and Eq. (eps_noLFE) the variant without local field
+ * effects.  Sec. III fixes the Gaussian-type-orbital basis and the shifted k
+ * grid.
+ *
+ * Conventions for every entry point
+ *   - Return value: QCX_OK (0) or a negative QCX_E* code; qcx_last_error()
+ *     then holds a message.  Errors leave the context's previous results
+ *     untouched unless stated otherwise.
+ *   - Units: lengths in bohr, momenta in bohr^-1, energies (band energies,
+ *     frequencies, broadening) in eV.  Internally Hartree atomic units with
+ *     1 Ha = 27.211386245988 eV, so the 4 pi alpha of Eq. (RPA) is 4 pi.
+ *   - Complex numbers are interleaved (re, im) pairs of doubles (c128) or of
+ *     floats (c64).  All arrays are C order (last index fastest).
+ *   - Host arrays passed in are copied before the call returns; the caller
+ *     keeps ownership.  Device pointers are borrowed for the duration of the
+ *     call only, unless stated otherwise.
+ *   - All device work is enqueued on the HIP stream given to qcx_create (for
+ *     PyTorch: torch.cuda.current_stream().cuda_stream).  The library never
+ *     creates or destroys that stream.  Calls that return results on the host
+ *     synchronise it; all others are asynchronous.
+ *   - A context is not thread-safe; use one context per host thread.
+ *   - The call order is qcx_set_cell_basis -> qcx_set_states ->
+ *     qcx_pair_density -> qcx_chi0 -> qcx_eps_inv -> qcx_loss.  A call made
+ *     before its inputs exist returns QCX_ESTATE.  Setting new inputs
+ *     invalidates everything downstream of them.
+ */
+#ifndef QCX_H
+#define QCX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qcx_ctx qcx_ctx;
+
+enum {
+  QCX_OK = 0,
+  QCX_EINVAL = -1,     /* bad shape or value                                */
+  QCX_ESTATE = -2,     /* call order violated                               */
+  QCX_ENONORTH = -3,   /* C^H S(k) C != I, or S(k) not positive definite    */
+  QCX_ESINGULAR = -4,  /* zero pivot in the eps inversion                   */
+  QCX_EDEVICE = -5,    /* HIP runtime error, or the library is not built for
+                          the device                                        */
+  QCX_ENOMEM = -6      /* device allocation failed                          */
+};
+
+enum { QCX_MEM_HOST = 0, QCX_MEM_DEVICE = 1 };
+
+/* Arithmetic of the chi0 bulk (the G, G' != 0 entries).  The head and wings
+ * (G = 0 row and column) and the eps inversion are FP64 unless requested
+ * otherwise (see qcx_chi0). */
+enum {
+  QCX_FP64 = 0,        /* FP64 throughout                                   */
+  QCX_FP32 = 1,        /* FP32 operands on FP32 MFMA, FP32 accumulation     */
+  QCX_SPLIT_BF16 = 2   /* x = hi + lo (bf16 each), hi*hi + hi*lo + lo*hi on
+                          BF16 MFMA with FP32 accumulation                  */
+};
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL means the default stream).  *out receives the
+ * context.  Errors: QCX_EINVAL (out NULL, device out of range),
+ * QCX_EDEVICE (device is not gfx950). */
+int qcx_create(qcx_ctx** out, int device, void* hip_stream);
+
+/* Free every device buffer the context owns.  The stream is not touched.
+ * Safe on NULL. */
+int qcx_destroy(qcx_ctx* ctx);
+
+/* Message describing the last error on this context (static storage owned
+ * by the context, valid until the next call).  ctx may be NULL for errors of
+ * qcx_create. */
+const char* qcx_last_error(const qcx_ctx* ctx);
+
+/* Wait for all work enqueued by this context and report errors detected on
+ * the device since the last call: QCX_ESINGULAR if an eps matrix had a zero
+ * pivot (qcx_last_error names the frequency index). */
+int qcx_sync(qcx_ctx* ctx);
+
+/* Crystal cell and Gaussian basis (Sec. III: Gaussian-type orbitals; one
+ * band per AO).
+ *   lat[9]        rows a1, a2, a3 of the primitive cell (bohr)
+ *   xyz           [n_atoms][3] atomic positions (bohr)
+ *   shell_atom    [n_shells] atom index of each shell
+ *   shell_l       [n_shells] angular momentum, 0, 1 or 2
+ *   shell_exp     [n_shells] Gaussian exponent (bohr^-2), > 0; one primitive
+ *                 per shell, normalised to unit self-overlap
+ *   pure_d        must be 1: d shells are the five real solid harmonics in
+ *                 the order xy, yz, (2z^2-x^2-y^2)/(2 sqrt 3), xz, (x^2-y^2)/2
+ *                 (times the normalised radial Gaussian); p shells are x, y, z
+ *   lattice_range L >= 0: Bloch sums run over cells n1 a1 + n2 a2 + n3 a3 with
+ *                 n in {-L..L}^3 (L = 1: 27 cells) with phase e^{ik.T}
+ * AOs are numbered shell by shell in the given order.  All inputs are host
+ * pointers and are copied.  Invalidates states and all results.
+ * Errors: QCX_EINVAL (l > 2, exponent <= 0, atom index out of range,
+ * singular lattice, pure_d != 1, L > 3). */
+int qcx_set_cell_basis(qcx_ctx* ctx, const double lat[9], int n_atoms, const double* xyz,
+                       int n_shells, const int* shell_atom, const int* shell_l,
+                       const double* shell_exp, int pure_d, int lattice_range);
+
+/* Kohn-Sham states at k and at k + q for one momentum q (Eq. RPA with
+ * k' = k + q; Sec. III: final states on the shifted grid).
+ *   q_cart[3]  q in Cartesian bohr^-1 (host)
+ *   k_frac     [n_k][3] k in reciprocal-basis coordinates (host or device)
+ *   n_occ      bands 0..n_occ-1 are occupied (f = 2), the rest empty (f = 0)
+ *   n_bands    bands per k, n_occ < n_bands <= N_AO
+ *   C_k, C_kq  [n_k][N_AO][n_bands] c128 coefficients of the states at k and
+ *              at k + q on the Bloch sums of the AOs
+ *   E_k, E_kq  [n_k][n_bands] band energies (eV); every empty band must lie
+ *              above every occupied band at each k and k + q
+ *   mem        QCX_MEM_HOST or QCX_MEM_DEVICE for k_frac, C_*, E_*
+ * The states are copied to the device and checked: |C^H S C - I| <= 1e-10 at
+ * every k and k + q with S(k) the library's own overlap (this synchronises
+ * the stream).  Invalidates pair densities and all results.
+ * Errors: QCX_ESTATE (no basis), QCX_EINVAL (sizes, band order),
+ * QCX_ENONORTH, QCX_ENOMEM. */
+int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* k_frac,
+                   int n_occ, int n_bands, const double* C_k, const double* E_k,
+                   const double* C_kq, const double* E_kq, int mem);
+
+/* Pair densities of Eq. (RPA) for the G list (Sec. II.D; Gaussian Fourier
+ * integrals summed over the lattice cells):
+ *   rho_vck(G)   = <c, k+q| e^{i(q+G).r} |v, k>      (resonant,      s = 0)
+ *   sigma_vck(G) = <v, k+q| e^{i(q+G).r} |c, k>      (anti-resonant, s = 1)
+ *   n_G      number of G vectors, 1 <= n_G <= 4096
+ *   G_int    [n_G][3] host, integer reciprocal-basis coefficients;
+ *            G_int[0] must be (0,0,0) and no q + G may vanish
+ *   rho_out  NULL (kept on the device for qcx_chi0) or a device buffer of
+ *            [2][n_k][n_occ][n_cond][n_G] c128 receiving (s, k, v, c, G)
+ * Errors: QCX_ESTATE (no states), QCX_EINVAL, QCX_ENOMEM. */
+int qcx_pair_density(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out);
+
+/* Independent-particle response of Eq. (RPA) at finite broadening:
+ *   chi0_GG'(w) = 1/(N_k V) sum_{k,v,c} [ 2 rho(G)^* rho(G') / (w - D + i eta)
+ *                                        - 2 sigma(G)^* sigma(G') / (w + D' - i eta) ]
+ * with D = E_c(k+q) - E_v(k), D' = E_c(k) - E_v(k+q), V the cell volume; the
+ * row index G carries the conjugate.
+ *   n_w, w_eV      frequencies (host, eV), 1 <= n_w <= 65536
+ *   eta_eV         broadening >= 0 (0 allowed for symmetry checks)
+ *   precision      QCX_FP64, QCX_FP32 or QCX_SPLIT_BF16 for the bulk
+ *   headwings_fp64 1: the G = 0 row and column are computed in FP64 whatever
+ *                  the precision; 0: they use the bulk precision
+ *   chi0_out       NULL, or a device buffer [n_w][n_G][n_G] c128 that receives
+ *                  chi0 (diagnostic; costs an extra pass)
+ * Errors: QCX_ESTATE (no pair densities), QCX_EINVAL, QCX_ENOMEM. */
+int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int precision,
+             int headwings_fp64, void* chi0_out);
+
+/* FP64 dielectric matrix eps_GG' = delta_GG' - 4 pi chi0_GG' / (|q+G||q+G'|)
+ * (the symmetrised form of Eq. RPA) and, per frequency:
+ *   lfe = 1: d_G = [eps^-1]_GG by Gauss-Jordan inversion with partial
+ *            pivoting (Eq. eps_LFE);
+ *   lfe = 0: d_G = 1 / eps_GG (Eq. eps_noLFE).
+ *   diag_out  NULL or device [n_w][n_G] c128 receiving d
+ *   epsM_out  NULL or device [n_w] c128 receiving eps_M = 1/d_0
+ * A zero pivot is reported by qcx_sync / qcx_loss as QCX_ESINGULAR.
+ * Errors: QCX_ESTATE (no chi0), QCX_EINVAL, QCX_ENOMEM. */
+int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out);
+
+/* Loss function at momentum q + G: out[w][G] = Im(-1/eps(w, q+G)) = -Im d_G
+ * (Eq. eps_LFE, or Eq. eps_noLFE when qcx_eps_inv ran with lfe = 0).
+ *   out  [n_w][n_G] doubles, host (mem = QCX_MEM_HOST: synchronises and
+ *        reports deferred errors as qcx_sync does) or device (QCX_MEM_DEVICE:
+ *        asynchronous).
+ * Errors: QCX_ESTATE (no eps_inv), QCX_EINVAL, QCX_ESINGULAR. */
+int qcx_loss(qcx_ctx* ctx, double* out, int mem);
+
+/* Per-stage device time of the most recent calls, in milliseconds, measured
+ * with HIP events on the context's stream (enabled by qcx_set_timing):
+ * t[0] pair_density, t[1] chi0 bulk kernel, t[2] chi0 FP64 head/wings,
+ * t[3] chi0 total, t[4] eps assembly + inversion, t[5] launches of the bulk
+ * kernel counted.  Synchronises the stream.  Values accumulate until
+ * qcx_set_timing is called again. */
+int qcx_stage_times(qcx_ctx* ctx, double t[6]);
+int qcx_set_timing(qcx_ctx* ctx, int enable);
+
+/* Library build description (kernel variants compiled in). */
+const char* qcx_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCX_H */

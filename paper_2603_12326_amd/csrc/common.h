@@ -1,0 +1,126 @@
+// Internal declarations shared by the translation units of libqcx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "qcx.h"
+
+namespace qcx {
+
+constexpr double kHartreeEV = 27.211386245988;  // CODATA 2018
+constexpr double kPi = 3.14159265358979323846;
+
+struct cplx {
+  double re, im;
+};
+
+__host__ __device__ inline cplx cmul(cplx a, cplx b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline cplx cmulc(cplx a, cplx b) {  // conj(a) * b
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+__host__ __device__ inline cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+
+// Device buffer owned by a context; grows, never shrinks, freed on destroy.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t reserve(size_t n) {
+    if (n <= bytes) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// ---------------------------------------------------------------- launchers
+// Gaussian Fourier integrals F[T][g][mu][nu] for every shell pair.
+struct ShellTab {
+  const int* l;        // [n_sh]
+  const double* ex;    // [n_sh]
+  const double* ctr;   // [n_sh][3]
+  const int* off;      // [n_sh] first AO of the shell
+  int n_sh;
+  int n_ao;
+};
+void launch_cell_ft(const ShellTab& sh, const double* tvec, int n_t, const double* Q, int n_q,
+                    cplx* F, hipStream_t st);
+// e^{2 pi i kf.n_T} for kf = k_frac[k] + shift
+void launch_bloch_phase(const double* k_frac, int n_k, const double shift[3], const int* cells,
+                        int n_t, cplx* ph, hipStream_t st);
+// M[k][g][e] = sum_T ph[k0+k][T] F[T][g][e], e = mu*n_ao+nu, for k in [0, nk)
+void launch_phase_sum(const cplx* F, const cplx* ph, int n_t, int n_q, int n_e, int k0, int nk,
+                      cplx* M, hipStream_t st);
+// R64[g][t] (t fastest, stride ldt) for k in [k0, k0+nk) from M chunk
+void launch_band_contract(const cplx* M, const cplx* Ck, const cplx* Ckq, int n_ao, int n_b,
+                          int n_occ, int n_k, int k0, int nk, int n_g, cplx* R, size_t ldt,
+                          hipStream_t st);
+// max_k |C^H S C - I| per k
+void launch_orth_check(const cplx* S, const cplx* C, int n_ao, int n_b, int n_k, double* dev,
+                       hipStream_t st);
+size_t band_contract_lds(int n_ao, int n_b, int n_occ);
+
+// chi0 pieces
+struct Chi0Geom {
+  int n_g, n_t, n_tp;       // transitions, padded to the K tile
+  int n_w, n_rows, n_rowsp; // rows = 2 n_w (Re W, Im W), padded
+  int n_pairs;              // n_g (n_g + 1) / 2 upper-triangle pairs, row-major
+  int p0;                   // first bulk pair (n_g when head/wings run in FP64)
+  int n_bulk, n_bulkp;      // bulk pairs and padded count
+  int ksplit;
+};
+// transition energies Delta_t (Ha) and signs for t in [0, n_t)
+void launch_transition_energies(const double* Ek, const double* Ekq, int n_k, int n_b, int n_occ,
+                                double* dt, hipStream_t st);
+// Weights in fragment order for the MFMA A operand
+void launch_weights_f32(const double* w, const double* dt, double eta, const Chi0Geom& g,
+                        float* Aw, hipStream_t st);
+void launch_weights_bf16(const double* w, const double* dt, double eta, const Chi0Geom& g,
+                         uint16_t* Ahi, uint16_t* Alo, hipStream_t st);
+// R64[g][t] -> R32 slabs [t/16][g][16] (complex float)
+void launch_pack_r32(const cplx* R, size_t ldt, const Chi0Geom& g, int perm, float* R32,
+                     hipStream_t st);
+int bulk_row_frags(const Chi0Geom& g);
+size_t pairs_f64_tc(int n_g);
+void launch_bulk_f32(const float* Aw, const float* R32, const int* pairs, const Chi0Geom& g,
+                     float* C, hipStream_t st);
+void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32,
+                      const int* pairs, const Chi0Geom& g, float* C, hipStream_t st);
+// FP64 X/Y for pairs (G in [ga, gb), all G' >= G); out [ks][n_w][pair][4]
+void launch_pairs_f64(const cplx* R, size_t ldt, const double* w, const double* dt, double eta,
+                      int n_w, int n_t, int n_g, int ga, int gb, int ksplit, double* XY,
+                      hipStream_t st);
+// eps assembly (symmetrised Coulomb, prefactor 2/(N_k V))
+struct AsmArgs {
+  const float* C;       // bulk partials [ks][n_rowsp][2*n_bulkp] or null
+  const double* XY;     // FP64 partials [ks64][n_w][n_pairs64][4] or null
+  int ks, ks64;
+  int n_pairs64;        // pairs held by XY (head/wings: n_g; full: n_pairs)
+  const double* vq;     // sqrt(4 pi)/|q+G|
+  double pref;
+};
+void launch_eps_assemble(const AsmArgs& a, const Chi0Geom& g, cplx* eps, hipStream_t st);
+void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st);
+void launch_nolfe_diag(const cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st);
+void launch_loss(const cplx* diag, int n_g, int n_w, double* loss, cplx* epsM, hipStream_t st);
+void launch_chi0_export(const AsmArgs& a, const Chi0Geom& g, cplx* chi, hipStream_t st);
+void launch_rho_export(const cplx* R, size_t ldt, int n_g, int n_t, cplx* out, hipStream_t st);
+
+}  // namespace qcx

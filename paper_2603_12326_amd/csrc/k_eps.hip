@@ -1,0 +1,352 @@
+// FP64 dielectric matrix, its inverse diagonal and the loss (Eq. eps_LFE,
+// Eq. eps_noLFE).
+//
+// eps_GG' = delta_GG' - v_G v_G' chi0_GG' with v_G = sqrt(4 pi)/|q+G| (the
+// symmetrised Coulomb factor of Eq. RPA).  [eps^-1]_GG for every G comes from
+// an in-place Gauss-Jordan inversion with partial pivoting on column moduli
+// |re| + |im|.  Rows are not swapped: step k picks pivot row p_k among the rows
+// not yet used, and at the end [eps^-1]_kk = B[p_k][k'] where k' is the step at
+// which row k served as pivot.
+#include <limits.h>
+
+#include "common.h"
+
+namespace qcx {
+
+namespace {
+
+__device__ inline void pair_decode(int p, int n_g, int& G, int& Gp) {
+  int g = 0;
+  while (g + 1 < n_g && (g + 1) * n_g - (g + 1) * g / 2 <= p) ++g;
+  G = g;
+  Gp = g + (p - (g * n_g - g * (g - 1) / 2));
+}
+
+// mode 0: eps; mode 1: chi0
+__global__ void k_assemble(AsmArgs a, Chi0Geom g, int mode, cplx* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)g.n_w * g.n_pairs) return;
+  const int j = (int)(i / g.n_pairs), p = (int)(i % g.n_pairs);
+  int G, Gp;
+  pair_decode(p, g.n_g, G, Gp);
+  double Xr = 0.0, Xi = 0.0, Yr = 0.0, Yi = 0.0;
+  if (p < a.n_pairs64) {
+    for (int ks = 0; ks < a.ks64; ++ks) {
+      const double* x = a.XY + (((size_t)ks * g.n_w + j) * a.n_pairs64 + p) * 4;
+      Xr += x[0];
+      Xi += x[1];
+      Yr += x[2];
+      Yi += x[3];
+    }
+  } else {
+    const int b = p - g.p0;
+    for (int ks = 0; ks < a.ks; ++ks) {
+      const size_t r0 = ((size_t)ks * g.n_rowsp + 2 * j) * 2;  // row 2j: Re W
+      const size_t r1 = r0 + 2;                                 // row 2j+1: Im W
+      Xr += (double)a.C[(r0 + 0) * g.n_bulkp + b];
+      Xi += (double)a.C[(r0 + 1) * g.n_bulkp + b];
+      Yr += (double)a.C[(r1 + 0) * g.n_bulkp + b];
+      Yi += (double)a.C[(r1 + 1) * g.n_bulkp + b];
+    }
+  }
+  if (G == Gp) {  // P_t(G, G) = |R_t(G)|^2 is real
+    Xi = 0.0;
+    Yi = 0.0;
+  }
+  cplx cab = {a.pref * (Xr - Yi), a.pref * (Xi + Yr)};  // chi0_{G G'}
+  cplx cba = {a.pref * (Xr + Yi), a.pref * (Yr - Xi)};  // chi0_{G' G}
+  const size_t base = (size_t)j * g.n_g * g.n_g;
+  if (mode == 0) {
+    const double vv = a.vq[G] * a.vq[Gp];
+    cab = {(G == Gp ? 1.0 : 0.0) - vv * cab.re, -vv * cab.im};
+    cba = {(G == Gp ? 1.0 : 0.0) - vv * cba.re, -vv * cba.im};
+  }
+  out[base + (size_t)G * g.n_g + Gp] = cab;
+  if (G != Gp) out[base + (size_t)Gp * g.n_g + G] = cba;
+}
+
+__device__ inline cplx cinv(cplx a) {
+  const double d = 1.0 / (a.re * a.re + a.im * a.im);
+  return {a.re * d, -a.im * d};
+}
+
+// Register-resident Gauss-Jordan for n <= 16*RP and n <= 32*CP.  512 threads:
+// thread (tr, tc) = (tid / 32, tid % 32) owns rows tr + 16 a and columns
+// tc + 32 b.  Three barriers per elimination step.
+template <int RP, int CP>
+__global__ void __launch_bounds__(512) k_gj_reg(const cplx* __restrict__ eps, int n,
+                                                cplx* __restrict__ diag, int* sing) {
+  __shared__ cplx colk[16 * RP], rowp[32 * CP];
+  __shared__ int used[16 * RP], piv[16 * RP], sor[16 * RP];
+  __shared__ double redv[16];
+  __shared__ int redi[16];
+  __shared__ int pivrow;
+  const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
+  const cplx* A = eps + (size_t)blockIdx.x * n * n;
+  cplx m[RP][CP];
+#pragma unroll
+  for (int a = 0; a < RP; ++a)
+#pragma unroll
+    for (int b = 0; b < CP; ++b) {
+      const int i = tr + 16 * a, j = tc + 32 * b;
+      m[a][b] = (i < n && j < n) ? A[(size_t)i * n + j] : cplx{0.0, 0.0};
+    }
+  for (int i = threadIdx.x; i < 16 * RP; i += 512) used[i] = 0;
+  bool singular = false;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const int kb = k >> 5;
+    if (tc == (k & 31)) {
+      double best = -1.0;
+      int bi = INT_MAX;
+#pragma unroll
+      for (int a = 0; a < RP; ++a) {
+        const int i = tr + 16 * a;
+        cplx v = {0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < CP; ++b)
+          if (b == kb) v = m[a][b];
+        if (i < n && !used[i]) {
+          double mag = fabs(v.re) + fabs(v.im);
+          if (mag != mag) mag = INFINITY;  // a NaN entry still selects a row
+          if (mag > best) {
+            best = mag;
+            bi = i;
+          }
+        }
+      }
+      redv[tr] = best;
+      redi[tr] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double best = -1.0;
+      int bi = INT_MAX;
+      for (int r = 0; r < 16; ++r) {
+        if (redi[r] == INT_MAX) continue;
+        if (bi == INT_MAX || redv[r] > best || (redv[r] == best && redi[r] < bi)) {
+          best = redv[r];
+          bi = redi[r];
+        }
+      }
+      if (bi == INT_MAX) bi = 0;  // unreachable: some row is always unused
+      pivrow = bi;
+      used[bi] = 1;
+      piv[k] = bi;
+      sor[bi] = k;
+    }
+    __syncthreads();
+    const int p = pivrow;
+    const int pa = p >> 4;
+    if (tc == (k & 31)) {
+#pragma unroll
+      for (int a = 0; a < RP; ++a) {
+        const int i = tr + 16 * a;
+#pragma unroll
+        for (int b = 0; b < CP; ++b)
+          if (b == kb && i < n) colk[i] = m[a][b];
+      }
+    }
+    if (tr == (p & 15)) {
+#pragma unroll
+      for (int b = 0; b < CP; ++b) {
+        const int j = tc + 32 * b;
+#pragma unroll
+        for (int a = 0; a < RP; ++a)
+          if (a == pa && j < n) rowp[j] = m[a][b];
+      }
+    }
+    __syncthreads();
+    const cplx pv = rowp[k];
+    if (pv.re == 0.0 && pv.im == 0.0) singular = true;
+    const cplx inv = cinv(pv);
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const int i = tr + 16 * a;
+      if (i >= n) continue;
+      if (i == p) {
+#pragma unroll
+        for (int b = 0; b < CP; ++b) {
+          const int j = tc + 32 * b;
+          m[a][b] = (j == k) ? inv : cmul(m[a][b], inv);
+        }
+      } else {
+        const cplx f = cmul(colk[i], inv);
+#pragma unroll
+        for (int b = 0; b < CP; ++b) {
+          const int j = tc + 32 * b;
+          if (j == k) {
+            m[a][b] = {-f.re, -f.im};
+          } else if (j < n) {
+            const cplx r = rowp[j];
+            m[a][b].re -= f.re * r.re - f.im * r.im;
+            m[a][b].im -= f.re * r.im + f.im * r.re;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // [eps^-1]_kk = B[piv[k]][sor[k]]
+  for (int k = 0; k < n; ++k) {
+    const int i = piv[k], j = sor[k];
+    if ((i & 15) == tr && (j & 31) == tc) {
+#pragma unroll
+      for (int a = 0; a < RP; ++a)
+#pragma unroll
+        for (int b = 0; b < CP; ++b)
+          if (a == (i >> 4) && b == (j >> 5)) diag[(size_t)blockIdx.x * n + k] = m[a][b];
+    }
+  }
+  if (singular && threadIdx.x == 0) atomicMin(sing, (int)blockIdx.x);
+}
+
+// Gauss-Jordan in global memory for larger n (one block per matrix, in place).
+__global__ void __launch_bounds__(256) k_gj_global(cplx* __restrict__ eps, int n,
+                                                   cplx* __restrict__ diag, int* sing) {
+  extern __shared__ char smem[];
+  cplx* colk = reinterpret_cast<cplx*>(smem);
+  cplx* rowp = colk + n;
+  int* used = reinterpret_cast<int*>(rowp + n);
+  int* piv = used + n;
+  int* sor = piv + n;
+  __shared__ double redv[256];
+  __shared__ int redi[256];
+  cplx* A = eps + (size_t)blockIdx.x * n * n;
+  for (int i = threadIdx.x; i < n; i += 256) used[i] = 0;
+  bool singular = false;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = INT_MAX;
+    for (int i = threadIdx.x; i < n; i += 256) {
+      if (used[i]) continue;
+      const cplx v = A[(size_t)i * n + k];
+      double mag = fabs(v.re) + fabs(v.im);
+      if (mag != mag) mag = INFINITY;
+      if (mag > best) {
+        best = mag;
+        bi = i;
+      }
+    }
+    redv[threadIdx.x] = best;
+    redi[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        const double o = redv[threadIdx.x + s];
+        const int oi = redi[threadIdx.x + s];
+        if (oi != INT_MAX && (redi[threadIdx.x] == INT_MAX || o > redv[threadIdx.x] ||
+                              (o == redv[threadIdx.x] && oi < redi[threadIdx.x]))) {
+          redv[threadIdx.x] = o;
+          redi[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = redi[0] == INT_MAX ? 0 : redi[0];  // unreachable guard
+    for (int i = threadIdx.x; i < n; i += 256) {
+      colk[i] = A[(size_t)i * n + k];
+      rowp[i] = A[(size_t)p * n + i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      used[p] = 1;
+      piv[k] = p;
+      sor[p] = k;
+    }
+    const cplx pv = rowp[k];
+    if (pv.re == 0.0 && pv.im == 0.0) singular = true;
+    const cplx inv = cinv(pv);
+    for (long e = threadIdx.x; e < (long)n * n; e += 256) {
+      const int i = (int)(e / n), j = (int)(e % n);
+      cplx v = A[e];
+      if (i == p) {
+        v = (j == k) ? inv : cmul(v, inv);
+      } else {
+        const cplx f = cmul(colk[i], inv);
+        if (j == k) {
+          v = {-f.re, -f.im};
+        } else {
+          const cplx r = rowp[j];
+          v.re -= f.re * r.re - f.im * r.im;
+          v.im -= f.re * r.im + f.im * r.re;
+        }
+      }
+      A[e] = v;
+    }
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < n; k += 256)
+    diag[(size_t)blockIdx.x * n + k] = A[(size_t)piv[k] * n + sor[k]];
+  if (singular && threadIdx.x == 0) atomicMin(sing, (int)blockIdx.x);
+}
+
+__global__ void k_nolfe(const cplx* eps, int n, int n_w, cplx* diag, int* sing) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n * n_w) return;
+  const int j = (int)(i / n), G = (int)(i % n);
+  const cplx e = eps[((size_t)j * n + G) * n + G];
+  if (e.re == 0.0 && e.im == 0.0) atomicMin(sing, j);
+  diag[i] = cinv(e);
+}
+
+__global__ void k_loss(const cplx* diag, int n, int n_w, double* loss, cplx* epsM) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n * n_w) return;
+  const cplx d = diag[i];
+  loss[i] = -d.im;
+  if (i % n == 0) epsM[i / n] = cinv(d);
+}
+
+__global__ void k_rho_export(const cplx* R, size_t ldt, int n_g, int n_t, cplx* out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_g * n_t) return;
+  const int t = (int)(i / n_g), g = (int)(i % n_g);
+  out[i] = R[(size_t)g * ldt + t];
+}
+
+}  // namespace
+
+void launch_eps_assemble(const AsmArgs& a, const Chi0Geom& g, cplx* eps, hipStream_t st) {
+  const long total = (long)g.n_w * g.n_pairs;
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, g, 0,
+                     eps);
+}
+
+void launch_chi0_export(const AsmArgs& a, const Chi0Geom& g, cplx* chi, hipStream_t st) {
+  const long total = (long)g.n_w * g.n_pairs;
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, g, 1,
+                     chi);
+}
+
+void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st) {
+  if (n_g <= 64)
+    hipLaunchKernelGGL((k_gj_reg<4, 2>), dim3(n_w), dim3(512), 0, st, eps, n_g, diag, sing);
+  else if (n_g <= 128)
+    hipLaunchKernelGGL((k_gj_reg<8, 4>), dim3(n_w), dim3(512), 0, st, eps, n_g, diag, sing);
+  else {
+    const size_t lds = (size_t)n_g * (2 * sizeof(cplx) + 3 * sizeof(int));
+    hipLaunchKernelGGL(k_gj_global, dim3(n_w), dim3(256), lds, st, eps, n_g, diag, sing);
+  }
+}
+
+void launch_nolfe_diag(const cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st) {
+  const long total = (long)n_g * n_w;
+  hipLaunchKernelGGL(k_nolfe, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, eps, n_g,
+                     n_w, diag, sing);
+}
+
+void launch_loss(const cplx* diag, int n_g, int n_w, double* loss, cplx* epsM, hipStream_t st) {
+  const long total = (long)n_g * n_w;
+  hipLaunchKernelGGL(k_loss, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, diag, n_g,
+                     n_w, loss, epsM);
+}
+
+void launch_rho_export(const cplx* R, size_t ldt, int n_g, int n_t, cplx* out, hipStream_t st) {
+  const long total = (long)n_g * n_t;
+  hipLaunchKernelGGL(k_rho_export, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, R, ldt,
+                     n_g, n_t, out);
+}
+
+}  // namespace qcx

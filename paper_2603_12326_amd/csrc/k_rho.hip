@@ -1,0 +1,447 @@
+// Pair densities of Eq. (RPA) from Gaussian-type-orbital Bloch states.
+//
+// rho_vck(Q) = <c,k+q| e^{iQ.r} |v,k> = sum_{mu nu} C_mu,c(k+q)^* M_mu,nu(k;Q) C_nu,v(k),
+// M_mu,nu(k;Q) = sum_T e^{ik.T} F_mu,nu(Q,T),
+// F_mu,nu(Q,T) = int chi_mu(r - A_mu) e^{iQ.r} chi_nu(r - A_nu - T) d^3r.
+//
+// F is evaluated by the McMurchie-Davidson Hermite expansion: per axis the
+// product of the two Cartesian Gaussians is K_x sum_t E^{ij}_t Lambda_t(x) with
+// Lambda_t = d^t/dP^t e^{-p (x-P)^2}, whose Fourier transform is
+// sqrt(pi/p) e^{-Q^2/4p} (iQ)^t e^{iQP}.
+//
+// Three kernels per q: cell_ft (one thread per shell pair, cell and Q),
+// phase_sum (the 27-cell Bloch sum, one thread per AO pair element holding its
+// 27 lattice terms in registers while it walks over k), band_contract (one
+// block per k and G tile; C(k), C(k+q) and one M(k;Q) staged in LDS).
+#include "common.h"
+
+namespace qcx {
+
+namespace {
+
+// Cartesian monomials per l: l=0: 1; l=1: x, y, z; l=2: xx, xy, xz, yy, yz, zz.
+__device__ __constant__ int kCartPow[10][3] = {
+    {0, 0, 0},                                                    // s
+    {1, 0, 0}, {0, 1, 0}, {0, 0, 1},                              // p
+    {2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}  // d
+};
+
+template <int L>
+struct Shape;
+template <>
+struct Shape<0> {
+  static constexpr int ncart = 1, nsph = 1, first = 0;
+};
+template <>
+struct Shape<1> {
+  static constexpr int ncart = 3, nsph = 3, first = 1;
+};
+template <>
+struct Shape<2> {
+  static constexpr int ncart = 6, nsph = 5, first = 4;
+};
+
+// Real solid harmonics as combinations of the Cartesian monomials above,
+// without the radial normalisation.
+__device__ inline double sph_coef(int l, int m, int c) {
+  if (l < 2) return (m == c) ? 1.0 : 0.0;
+  const double h = 0.28867513459481288225;  // 1/(2 sqrt 3)
+  switch (m) {
+    case 0: return c == 1 ? 1.0 : 0.0;                              // xy
+    case 1: return c == 4 ? 1.0 : 0.0;                              // yz
+    case 2: return c == 5 ? 2.0 * h : ((c == 0 || c == 3) ? -h : 0.0);  // 2zz - xx - yy
+    case 3: return c == 2 ? 1.0 : 0.0;                              // xz
+    default: return c == 0 ? 0.5 : (c == 3 ? -0.5 : 0.0);           // (xx - yy)/2
+  }
+}
+
+// Normalisation of a unit-norm primitive of angular momentum l.
+__device__ inline double prim_norm(int l, double a) {
+  double g = pow(2.0 * a / kPi, 0.75);
+  if (l == 1) return g * sqrt(4.0 * a);
+  if (l == 2) return g * 4.0 * a;
+  return g;
+}
+
+// Hermite coefficients E^{ij}_t for one axis, i <= LA, j <= LB, t <= LA+LB,
+// and the per-axis integral J[i][j] = sum_t E^{ij}_t (iQ)^t (without the
+// common Gaussian factors).
+template <int LA, int LB>
+__device__ inline void axis_j(double xpa, double xpb, double i2p, double qx,
+                              cplx (&J)[LA + 1][LB + 1]) {
+  constexpr int TM = LA + LB + 1;
+  double E[LA + 1][LB + 1][TM + 1];
+#pragma unroll
+  for (int i = 0; i <= LA; ++i)
+#pragma unroll
+    for (int j = 0; j <= LB; ++j)
+#pragma unroll
+      for (int t = 0; t <= TM; ++t) E[i][j][t] = 0.0;
+  E[0][0][0] = 1.0;
+#pragma unroll
+  for (int i = 0; i <= LA; ++i) {
+#pragma unroll
+    for (int j = 0; j <= LB; ++j) {
+      if (i == 0 && j == 0) continue;
+      if (j == 0) {  // raise i
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+          double v = xpa * E[i - 1][0][t] + (t + 1) * E[i - 1][0][t + 1];
+          if (t > 0) v += i2p * E[i - 1][0][t - 1];
+          E[i][0][t] = v;
+        }
+      } else {  // raise j
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+          double v = xpb * E[i][j - 1][t] + (t + 1) * E[i][j - 1][t + 1];
+          if (t > 0) v += i2p * E[i][j - 1][t - 1];
+          E[i][j][t] = v;
+        }
+      }
+    }
+  }
+  // (iQ)^t: 1, iQ, -Q^2, -iQ^3, Q^4
+  double qp[TM];
+  qp[0] = 1.0;
+#pragma unroll
+  for (int t = 1; t < TM; ++t) qp[t] = qp[t - 1] * qx;
+#pragma unroll
+  for (int i = 0; i <= LA; ++i)
+#pragma unroll
+    for (int j = 0; j <= LB; ++j) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int t = 0; t <= i + j; ++t) {
+        double v = E[i][j][t] * qp[t];
+        switch (t & 3) {
+          case 0: re += v; break;
+          case 1: im += v; break;
+          case 2: re -= v; break;
+          default: im -= v; break;
+        }
+      }
+      J[i][j] = {re, im};
+    }
+}
+
+template <int LA, int LB>
+__device__ void pair_block(double a, double b, const double* A, const double* B, const double* Q,
+                           cplx* out, int ld) {
+  const double p = a + b, ip = 1.0 / p, i2p = 0.5 * ip;
+  double P[3], ab2 = 0.0, q2 = 0.0, qp = 0.0;
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    P[x] = (a * A[x] + b * B[x]) * ip;
+    double d = A[x] - B[x];
+    ab2 += d * d;
+    q2 += Q[x] * Q[x];
+    qp += Q[x] * P[x];
+  }
+  // common factor (pi/p)^{3/2} K e^{-Q^2/4p} e^{iQ.P}
+  double mag = pow(kPi * ip, 1.5) * exp(-a * b * ip * ab2 - 0.25 * q2 * ip);
+  double s, c;
+  sincos(qp, &s, &c);
+  const cplx pref = {mag * c, mag * s};
+
+  cplx Jx[LA + 1][LB + 1], Jy[LA + 1][LB + 1], Jz[LA + 1][LB + 1];
+  axis_j<LA, LB>(P[0] - A[0], P[0] - B[0], i2p, Q[0], Jx);
+  axis_j<LA, LB>(P[1] - A[1], P[1] - B[1], i2p, Q[1], Jy);
+  axis_j<LA, LB>(P[2] - A[2], P[2] - B[2], i2p, Q[2], Jz);
+
+  constexpr int NCA = Shape<LA>::ncart, NCB = Shape<LB>::ncart;
+  constexpr int NSA = Shape<LA>::nsph, NSB = Shape<LB>::nsph;
+  cplx cart[NCA][NCB];
+#pragma unroll
+  for (int ca = 0; ca < NCA; ++ca) {
+    const int* pa = kCartPow[Shape<LA>::first + ca];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int* pb = kCartPow[Shape<LB>::first + cb];
+      cart[ca][cb] = cmul(cmul(Jx[pa[0]][pb[0]], Jy[pa[1]][pb[1]]), Jz[pa[2]][pb[2]]);
+    }
+  }
+  const double nn = prim_norm(LA, a) * prim_norm(LB, b);
+#pragma unroll
+  for (int ma = 0; ma < NSA; ++ma) {
+    cplx tmp[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int ca = 0; ca < NCA; ++ca) {
+        double w = sph_coef(LA, ma, ca);
+        re += w * cart[ca][cb].re;
+        im += w * cart[ca][cb].im;
+      }
+      tmp[cb] = {re, im};
+    }
+#pragma unroll
+    for (int mb = 0; mb < NSB; ++mb) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        double w = sph_coef(LB, mb, cb);
+        re += w * tmp[cb].re;
+        im += w * tmp[cb].im;
+      }
+      cplx r = cmul({re * nn, im * nn}, pref);
+      out[ma * ld + mb] = r;
+    }
+  }
+}
+
+// One thread per (shell pair, cell T, Q).  Threads of one shell pair are
+// consecutive, so a wave sees one (la, lb) combination.
+__global__ void __launch_bounds__(256) k_cell_ft(ShellTab sh, const double* tvec, int n_t,
+                                                 const double* Q, int n_q, cplx* F) {
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per_pair = (long)n_t * n_q;
+  const long total = per_pair * sh.n_sh * sh.n_sh;
+  if (tid >= total) return;
+  const int sp = (int)(tid / per_pair);
+  const int rem = (int)(tid % per_pair);
+  const int it = rem / n_q, g = rem % n_q;
+  const int sa = sp / sh.n_sh, sb = sp % sh.n_sh;
+  const double a = sh.ex[sa], b = sh.ex[sb];
+  double A[3], B[3], q[3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    A[x] = sh.ctr[3 * sa + x];
+    B[x] = sh.ctr[3 * sb + x] + tvec[3 * it + x];
+    q[x] = Q[3 * g + x];
+  }
+  const int n = sh.n_ao;
+  cplx* out = F + ((size_t)it * n_q + g) * n * n + (size_t)sh.off[sa] * n + sh.off[sb];
+  const int la = sh.l[sa], lb = sh.l[sb];
+  switch (la * 3 + lb) {
+    case 0: pair_block<0, 0>(a, b, A, B, q, out, n); break;
+    case 1: pair_block<0, 1>(a, b, A, B, q, out, n); break;
+    case 2: pair_block<0, 2>(a, b, A, B, q, out, n); break;
+    case 3: pair_block<1, 0>(a, b, A, B, q, out, n); break;
+    case 4: pair_block<1, 1>(a, b, A, B, q, out, n); break;
+    case 5: pair_block<1, 2>(a, b, A, B, q, out, n); break;
+    case 6: pair_block<2, 0>(a, b, A, B, q, out, n); break;
+    case 7: pair_block<2, 1>(a, b, A, B, q, out, n); break;
+    default: pair_block<2, 2>(a, b, A, B, q, out, n); break;
+  }
+}
+
+__global__ void k_bloch_phase(const double* kf, int n_k, double s0, double s1, double s2,
+                              const int* cells, int n_t, cplx* ph) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_k * n_t) return;
+  const int k = i / n_t, t = i % n_t;
+  // e^{2 pi i kf.n}; sincospi keeps the argument reduction exact for rational kf
+  double arg = (kf[3 * k] + s0) * cells[3 * t] + (kf[3 * k + 1] + s1) * cells[3 * t + 1] +
+               (kf[3 * k + 2] + s2) * cells[3 * t + 2];
+  double s, c;
+  sincospi(2.0 * arg, &s, &c);
+  ph[i] = {c, s};
+}
+
+// M[k][e] = sum_T ph[k0+k][T] F[T][e] for the n_q*n_ao^2 elements e.
+// Each thread keeps its n_t lattice terms in registers (n_t <= 27) and walks
+// over the k chunk; the phases of a k are broadcast from LDS.
+template <int NT>
+__global__ void __launch_bounds__(256) k_phase_sum(const cplx* __restrict__ F,
+                                                   const cplx* __restrict__ ph, long n_el,
+                                                   int k0, int nk, cplx* __restrict__ M) {
+  __shared__ cplx sph[64 * NT];
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  cplx f[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) f[t] = (e < n_el) ? F[(size_t)t * n_el + e] : cplx{0.0, 0.0};
+  for (int kb = 0; kb < nk; kb += 64) {
+    const int kn = min(64, nk - kb);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kn * NT; i += blockDim.x) sph[i] = ph[(size_t)(k0 + kb) * NT + i];
+    __syncthreads();
+    if (e < n_el) {
+      for (int kk = 0; kk < kn; ++kk) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const cplx p = sph[kk * NT + t];
+          re += p.re * f[t].re - p.im * f[t].im;
+          im += p.re * f[t].im + p.im * f[t].re;
+        }
+        M[(size_t)(kb + kk) * n_el + e] = {re, im};
+      }
+    }
+  }
+}
+
+// Generic lattice range: loop over cells from global memory.
+__global__ void __launch_bounds__(256) k_phase_sum_any(const cplx* __restrict__ F,
+                                                       const cplx* __restrict__ ph, int n_t,
+                                                       long n_el, int k0, int nk,
+                                                       cplx* __restrict__ M) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_el) return;
+  for (int kk = 0; kk < nk; ++kk) {
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < n_t; ++t) {
+      const cplx p = ph[(size_t)(k0 + kk) * n_t + t];
+      const cplx f = F[(size_t)t * n_el + e];
+      re += p.re * f.re - p.im * f.im;
+      im += p.re * f.im + p.im * f.re;
+    }
+    M[(size_t)kk * n_el + e] = {re, im};
+  }
+}
+
+constexpr int kGTile = 8;
+
+// One block per (k, tile of kGTile G).  LDS: C(k), C(k+q), M(k;Q), T1 = M C(k).
+// Writes R[g][t] for t = ((s*n_k + k)*n_occ + v)*n_cond + c.
+__global__ void __launch_bounds__(256) k_band_contract(const cplx* __restrict__ M,
+                                                       const cplx* __restrict__ Ck,
+                                                       const cplx* __restrict__ Ckq, int n_ao,
+                                                       int n_b, int n_occ, int n_k, int k0,
+                                                       int n_g, cplx* __restrict__ R,
+                                                       size_t ldt) {
+  extern __shared__ cplx lds[];
+  const int kk = blockIdx.x;   // index inside the chunk
+  const int k = k0 + kk;
+  const int g0 = blockIdx.y * kGTile;
+  const int n_c = n_b - n_occ;
+  const int nab = n_ao * n_b, naa = n_ao * n_ao;
+  cplx* sCk = lds;
+  cplx* sCq = sCk + nab;
+  cplx* sM = sCq + nab;
+  cplx* sT = sM + naa;
+  for (int i = threadIdx.x; i < nab; i += blockDim.x) {
+    sCk[i] = Ck[(size_t)kk * nab + i];   // Ck, Ckq already offset to the chunk
+    sCq[i] = Ckq[(size_t)kk * nab + i];
+  }
+  const size_t nvc = (size_t)n_occ * n_c;
+  const size_t t_res = (size_t)k * nvc;
+  const size_t t_anti = ((size_t)n_k + k) * nvc;
+  for (int gi = 0; gi < kGTile; ++gi) {
+    const int g = g0 + gi;
+    if (g >= n_g) break;
+    __syncthreads();
+    const cplx* Mg = M + ((size_t)kk * n_g + g) * naa;
+    for (int i = threadIdx.x; i < naa; i += blockDim.x) sM[i] = Mg[i];
+    __syncthreads();
+    // T1[mu][b] = sum_nu M[mu][nu] C_k[nu][b]
+    for (int i = threadIdx.x; i < nab; i += blockDim.x) {
+      const int mu = i / n_b, b = i % n_b;
+      double re = 0.0, im = 0.0;
+      for (int nu = 0; nu < n_ao; ++nu) {
+        const cplx m = sM[mu * n_ao + nu], c = sCk[nu * n_b + b];
+        re += m.re * c.re - m.im * c.im;
+        im += m.re * c.im + m.im * c.re;
+      }
+      sT[i] = {re, im};
+    }
+    __syncthreads();
+    // rho[v][c] = sum_mu conj(Ckq[mu][n_occ+c]) T1[mu][v]
+    // sigma[v][c] = sum_mu conj(Ckq[mu][v]) T1[mu][n_occ+c]
+    cplx* Rg = R + (size_t)g * ldt;
+    for (int i = threadIdx.x; i < 2 * (int)nvc; i += blockDim.x) {
+      const int s = i / (int)nvc, vc = i % (int)nvc;
+      const int v = vc / n_c, c = vc % n_c;
+      const int bra = s == 0 ? n_occ + c : v;
+      const int ket = s == 0 ? v : n_occ + c;
+      double re = 0.0, im = 0.0;
+      for (int mu = 0; mu < n_ao; ++mu) {
+        const cplx a = sCq[mu * n_b + bra], t = sT[mu * n_b + ket];
+        re += a.re * t.re + a.im * t.im;
+        im += a.re * t.im - a.im * t.re;
+      }
+      Rg[(s == 0 ? t_res : t_anti) + vc] = {re, im};
+    }
+  }
+}
+
+// dev[k] = max |C^H S C - I| (one block per k)
+__global__ void __launch_bounds__(256) k_orth_check(const cplx* __restrict__ S,
+                                                    const cplx* __restrict__ C, int n_ao,
+                                                    int n_b, double* dev) {
+  extern __shared__ cplx lds[];
+  const int k = blockIdx.x;
+  const int nab = n_ao * n_b, naa = n_ao * n_ao;
+  cplx* sS = lds;
+  cplx* sC = sS + naa;
+  cplx* sT = sC + nab;
+  __shared__ double red[256];
+  for (int i = threadIdx.x; i < naa; i += blockDim.x) sS[i] = S[(size_t)k * naa + i];
+  for (int i = threadIdx.x; i < nab; i += blockDim.x) sC[i] = C[(size_t)k * nab + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < nab; i += blockDim.x) {
+    const int mu = i / n_b, b = i % n_b;
+    cplx acc = {0.0, 0.0};
+    for (int nu = 0; nu < n_ao; ++nu) acc = cadd(acc, cmul(sS[mu * n_ao + nu], sC[nu * n_b + b]));
+    sT[i] = acc;
+  }
+  __syncthreads();
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n_b * n_b; i += blockDim.x) {
+    const int a = i / n_b, b = i % n_b;
+    cplx acc = {a == b ? -1.0 : 0.0, 0.0};
+    for (int mu = 0; mu < n_ao; ++mu) acc = cadd(acc, cmulc(sC[mu * n_b + a], sT[mu * n_b + b]));
+    double m = fabs(acc.re) + fabs(acc.im);
+    if (!(m <= mx)) mx = m;  // NaN propagates
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      double o = red[threadIdx.x + s];
+      if (!(o <= red[threadIdx.x])) red[threadIdx.x] = o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dev[k] = red[0];
+}
+
+}  // namespace
+
+void launch_cell_ft(const ShellTab& sh, const double* tvec, int n_t, const double* Q, int n_q,
+                    cplx* F, hipStream_t st) {
+  const long total = (long)sh.n_sh * sh.n_sh * n_t * n_q;
+  const int blk = 256;
+  hipLaunchKernelGGL(k_cell_ft, dim3((unsigned)((total + blk - 1) / blk)), dim3(blk), 0, st, sh,
+                     tvec, n_t, Q, n_q, F);
+}
+
+void launch_bloch_phase(const double* k_frac, int n_k, const double shift[3], const int* cells,
+                        int n_t, cplx* ph, hipStream_t st) {
+  const int n = n_k * n_t;
+  hipLaunchKernelGGL(k_bloch_phase, dim3((n + 255) / 256), dim3(256), 0, st, k_frac, n_k,
+                     shift[0], shift[1], shift[2], cells, n_t, ph);
+}
+
+void launch_phase_sum(const cplx* F, const cplx* ph, int n_t, int n_q, int n_e, int k0, int nk,
+                      cplx* M, hipStream_t st) {
+  const long n_el = (long)n_q * n_e;
+  const dim3 grid((unsigned)((n_el + 255) / 256));
+  if (n_t == 27)
+    hipLaunchKernelGGL(k_phase_sum<27>, grid, dim3(256), 0, st, F, ph, n_el, k0, nk, M);
+  else if (n_t == 1)
+    hipLaunchKernelGGL(k_phase_sum<1>, grid, dim3(256), 0, st, F, ph, n_el, k0, nk, M);
+  else
+    hipLaunchKernelGGL(k_phase_sum_any, grid, dim3(256), 0, st, F, ph, n_t, n_el, k0, nk, M);
+}
+
+size_t band_contract_lds(int n_ao, int n_b, int /*n_occ*/) {
+  return sizeof(cplx) * (3 * (size_t)n_ao * n_b + (size_t)n_ao * n_ao);
+}
+
+void launch_band_contract(const cplx* M, const cplx* Ck, const cplx* Ckq, int n_ao, int n_b,
+                          int n_occ, int n_k, int k0, int nk, int n_g, cplx* R, size_t ldt,
+                          hipStream_t st) {
+  const size_t lds = band_contract_lds(n_ao, n_b, n_occ);
+  const dim3 grid(nk, (n_g + kGTile - 1) / kGTile);
+  hipLaunchKernelGGL(k_band_contract, grid, dim3(256), lds, st, M, Ck + (size_t)k0 * n_ao * n_b,
+                     Ckq + (size_t)k0 * n_ao * n_b, n_ao, n_b, n_occ, n_k, k0, n_g, R, ldt);
+}
+
+void launch_orth_check(const cplx* S, const cplx* C, int n_ao, int n_b, int n_k, double* dev,
+                       hipStream_t st) {
+  const size_t lds = sizeof(cplx) * ((size_t)n_ao * n_ao + 2 * (size_t)n_ao * n_b);
+  hipLaunchKernelGGL(k_orth_check, dim3(n_k), dim3(256), lds, st, S, C, n_ao, n_b, dev);
+}
+
+}  // namespace qcx

@@ -1,0 +1,740 @@
+// Host runtime behind the C ABI declared in include/qcx.h: context, device
+// buffers, input validation, orchestration of the kernels on the caller's
+// stream and per-stage HIP-event timing.
+#include <limits.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace qcx;
+
+struct qcx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // cell and basis
+  bool have_basis = false;
+  double lat[9], rec[9], vol = 0.0;
+  int n_atoms = 0, n_sh = 0, n_ao = 0, lrange = 1, n_cells = 0;
+  std::vector<int> sh_l, sh_off, cells;
+  std::vector<double> sh_ex, sh_ctr, tvec;
+  DevBuf d_sh_l, d_sh_ex, d_sh_ctr, d_sh_off, d_cells, d_tvec;
+
+  // states
+  bool have_states = false;
+  double q[3] = {0, 0, 0};
+  int n_k = 0, n_occ = 0, n_b = 0, n_c = 0, n_t = 0;
+  DevBuf d_kf, d_Ck, d_Ek, d_Ckq, d_Ekq, d_dt, d_ph, d_phq, d_S, d_F0, d_dev;
+
+  // pair densities
+  bool have_rho = false;
+  int n_g = 0;
+  size_t ldt = 0;
+  DevBuf d_Q, d_vq, d_F, d_M, d_R;
+
+  // chi0
+  bool have_chi0 = false;
+  int n_w = 0, prec = 0, hw64 = 1;
+  double eta = 0.0;
+  Chi0Geom geom{};
+  int ks64 = 1, n_pairs64 = 0;
+  DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_C, d_XY;
+
+  // eps
+  bool have_eps = false;
+  DevBuf d_eps, d_diag, d_epsM, d_loss, d_sing;
+
+  // pinned staging for host -> device copies: reset at the start of each
+  // call once the previous call's copies have completed
+  void* stage = nullptr;
+  size_t stage_cap = 0, stage_off = 0;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
+
+  // timing: event pairs recorded on the stream without synchronising,
+  // resolved by qcx_stage_times
+  struct Span {
+    hipEvent_t a, b;
+    int stage;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Span> spans;
+  double t_acc[6] = {0, 0, 0, 0, 0, 0};
+
+  ~qcx_ctx() {
+    DevBuf* all[] = {&d_sh_l, &d_sh_ex, &d_sh_ctr, &d_sh_off, &d_cells, &d_tvec, &d_kf,
+                     &d_Ck,   &d_Ek,    &d_Ckq,    &d_Ekq,    &d_dt,    &d_ph,   &d_phq,
+                     &d_S,    &d_F0,    &d_dev,    &d_Q,      &d_vq,    &d_F,    &d_M,
+                     &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_C,
+                     &d_XY,   &d_eps,   &d_diag,   &d_epsM,   &d_loss,  &d_sing};
+    for (DevBuf* b : all) b->release();
+    for (const Span& sp : spans) {
+      (void)hipEventDestroy(sp.a);
+      (void)hipEventDestroy(sp.b);
+    }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (stage_done) (void)hipEventDestroy(stage_done);
+    if (stage) (void)hipHostFree(stage);
+  }
+};
+
+namespace {
+
+std::string g_create_err;
+
+int fail(qcx_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCK(call)                                                                   \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? QCX_ENOMEM : QCX_EDEVICE,          \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                 \
+  } while (0)
+
+#define LAUNCHCK(what)                                                                \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, QCX_EDEVICE, std::string("launch ") + what + ": " +            \
+                                        hipGetErrorString(e_));                       \
+  } while (0)
+
+size_t roundup(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+constexpr size_t kStageBytes = (size_t)64 << 20;
+
+// Begin a call that stages host data: wait until the copies of the previous
+// call have left the pinned buffer.
+hipError_t stage_begin(qcx_ctx* c) {
+  if (!c->stage) {
+    hipError_t e = hipHostMalloc(&c->stage, kStageBytes);
+    if (e != hipSuccess) {
+      c->stage = nullptr;
+      return e;
+    }
+    c->stage_cap = kStageBytes;
+    e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  if (c->stage_pending) {
+    hipError_t e = hipEventSynchronize(c->stage_done);
+    if (e != hipSuccess) return e;
+    c->stage_pending = false;
+  }
+  c->stage_off = 0;
+  return hipSuccess;
+}
+
+// Copy n elements to a context buffer on the context's stream.  Host data goes
+// through the pinned arena (or, if it does not fit, a synchronous copy), so the
+// caller's array may be released as soon as the call returns.
+template <class T>
+hipError_t upload(qcx_ctx* c, DevBuf& b, const T* src, size_t n, bool dev_src = false) {
+  const size_t bytes = n * sizeof(T);
+  hipError_t e = b.reserve(bytes + 64);
+  if (e != hipSuccess) return e;
+  if (dev_src) return hipMemcpyAsync(b.p, src, bytes, hipMemcpyDeviceToDevice, c->stream);
+  const size_t off = (c->stage_off + 255) / 256 * 256;
+  if (c->stage && off + bytes <= c->stage_cap) {
+    char* h = static_cast<char*>(c->stage) + off;
+    memcpy(h, src, bytes);
+    c->stage_off = off + bytes;
+    e = hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    // record after every staged copy so that an early error return still
+    // leaves the arena guarded
+    e = hipEventRecord(c->stage_done, c->stream);
+    if (e == hipSuccess) c->stage_pending = true;
+    return e;
+  }
+  e = hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+void inv3(const double m[9], double out[9]) {
+  const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5], g = m[6], h = m[7],
+               i = m[8];
+  const double det = a * (e * i - f * h) - b * (d * i - f * g) + c * (d * h - e * g);
+  out[0] = (e * i - f * h) / det;
+  out[1] = (c * h - b * i) / det;
+  out[2] = (b * f - c * e) / det;
+  out[3] = (f * g - d * i) / det;
+  out[4] = (a * i - c * g) / det;
+  out[5] = (c * d - a * f) / det;
+  out[6] = (d * h - e * g) / det;
+  out[7] = (b * g - a * h) / det;
+  out[8] = (a * e - b * d) / det;
+}
+
+hipError_t take_event(qcx_ctx* c, hipEvent_t* e) {
+  if (!c->ev_pool.empty()) {
+    *e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Open a timed span for `stage`; returns its index in *idx (or -1 when timing
+// is off).
+hipError_t span_begin(qcx_ctx* c, int stage, int* idx) {
+  *idx = -1;
+  if (!c->timing) return hipSuccess;
+  qcx_ctx::Span sp{};
+  hipError_t e = take_event(c, &sp.a);
+  if (e != hipSuccess) return e;
+  e = take_event(c, &sp.b);
+  if (e != hipSuccess) return e;
+  sp.stage = stage;
+  e = hipEventRecord(sp.a, c->stream);
+  if (e != hipSuccess) return e;
+  c->spans.push_back(sp);
+  *idx = (int)c->spans.size() - 1;
+  return hipSuccess;
+}
+
+hipError_t span_end(qcx_ctx* c, int idx) {
+  if (idx < 0) return hipSuccess;
+  return hipEventRecord(c->spans[idx].b, c->stream);
+}
+
+// Resolve every recorded span into t_acc (synchronises the stream).
+hipError_t spans_resolve(qcx_ctx* c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  for (const qcx_ctx::Span& sp : c->spans) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, sp.a, sp.b);
+    if (e != hipSuccess) return e;
+    c->t_acc[sp.stage] += ms;
+    if (sp.stage == 1) c->t_acc[5] += 1.0;
+    c->ev_pool.push_back(sp.a);
+    c->ev_pool.push_back(sp.b);
+  }
+  c->spans.clear();
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qcx_build_info(void) {
+  return "libqcx gfx950: rho FP64 (Hermite FT, 27-cell Bloch sum), chi0 bulk FP32-MFMA "
+         "32x32x2 / split-BF16-MFMA 32x32x16 (hi*hi+hi*lo+lo*hi), FP64 head/wings, FP64 "
+         "Gauss-Jordan diag(eps^-1)";
+}
+
+int qcx_create(qcx_ctx** out, int device, void* hip_stream) {
+  if (!out) {
+    g_create_err = "out is NULL";
+    return QCX_EINVAL;
+  }
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    g_create_err = "no such HIP device";
+    return QCX_EINVAL;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    g_create_err = "hipGetDeviceProperties failed";
+    return QCX_EDEVICE;
+  }
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    g_create_err = std::string("library built for gfx950, device is ") + prop.gcnArchName;
+    return QCX_EDEVICE;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    g_create_err = "hipSetDevice failed";
+    return QCX_EDEVICE;
+  }
+  qcx_ctx* c = new qcx_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return QCX_OK;
+}
+
+int qcx_destroy(qcx_ctx* ctx) {
+  if (!ctx) return QCX_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return QCX_OK;
+}
+
+const char* qcx_last_error(const qcx_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int qcx_set_timing(qcx_ctx* ctx, int enable) {
+  if (!ctx) return QCX_EINVAL;
+  HIPCK(spans_resolve(ctx));
+  ctx->timing = enable != 0;
+  for (double& t : ctx->t_acc) t = 0.0;
+  return QCX_OK;
+}
+
+int qcx_stage_times(qcx_ctx* ctx, double t[6]) {
+  if (!ctx || !t) return QCX_EINVAL;
+  HIPCK(spans_resolve(ctx));
+  for (int i = 0; i < 6; ++i) t[i] = ctx->t_acc[i];
+  return QCX_OK;
+}
+
+int qcx_sync(qcx_ctx* ctx) {
+  if (!ctx) return QCX_EINVAL;
+  HIPCK(hipSetDevice(ctx->device));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  if (ctx->have_eps && ctx->d_sing.p) {
+    int s = INT_MAX;
+    HIPCK(hipMemcpy(&s, ctx->d_sing.p, sizeof(int), hipMemcpyDeviceToHost));
+    if (s != INT_MAX)
+      return fail(ctx, QCX_ESINGULAR,
+                  "zero pivot in eps at frequency index " + std::to_string(s));
+  }
+  return QCX_OK;
+}
+
+int qcx_set_cell_basis(qcx_ctx* ctx, const double lat[9], int n_atoms, const double* xyz,
+                       int n_shells, const int* shell_atom, const int* shell_l,
+                       const double* shell_exp, int pure_d, int lattice_range) {
+  if (!ctx) return QCX_EINVAL;
+  if (!lat || !xyz || !shell_atom || !shell_l || !shell_exp)
+    return fail(ctx, QCX_EINVAL, "NULL argument");
+  if (n_atoms < 1 || n_shells < 1) return fail(ctx, QCX_EINVAL, "need atoms and shells");
+  if (pure_d != 1) return fail(ctx, QCX_EINVAL, "only pure (spherical) d shells are supported");
+  if (lattice_range < 0 || lattice_range > 3)
+    return fail(ctx, QCX_EINVAL, "lattice_range must be 0..3");
+  const double det = lat[0] * (lat[4] * lat[8] - lat[5] * lat[7]) -
+                     lat[1] * (lat[3] * lat[8] - lat[5] * lat[6]) +
+                     lat[2] * (lat[3] * lat[7] - lat[4] * lat[6]);
+  if (!(fabs(det) > 1e-12)) return fail(ctx, QCX_EINVAL, "singular lattice");
+  HIPCK(hipSetDevice(ctx->device));
+  ctx->have_basis = ctx->have_states = ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
+  memcpy(ctx->lat, lat, sizeof(double) * 9);
+  double inv[9];
+  inv3(lat, inv);
+  // rows b_j = 2 pi (inv^T)_j
+  for (int j = 0; j < 3; ++j)
+    for (int x = 0; x < 3; ++x) ctx->rec[3 * j + x] = 2.0 * kPi * inv[3 * x + j];
+  ctx->vol = fabs(det);
+  ctx->n_atoms = n_atoms;
+  ctx->n_sh = n_shells;
+  ctx->sh_l.assign(shell_l, shell_l + n_shells);
+  ctx->sh_ex.assign(shell_exp, shell_exp + n_shells);
+  ctx->sh_ctr.resize(3 * (size_t)n_shells);
+  ctx->sh_off.resize(n_shells);
+  int off = 0;
+  for (int s = 0; s < n_shells; ++s) {
+    if (shell_l[s] < 0 || shell_l[s] > 2) return fail(ctx, QCX_EINVAL, "shell l must be 0..2");
+    if (!(shell_exp[s] > 0.0)) return fail(ctx, QCX_EINVAL, "shell exponent must be > 0");
+    if (shell_atom[s] < 0 || shell_atom[s] >= n_atoms)
+      return fail(ctx, QCX_EINVAL, "shell atom index out of range");
+    for (int x = 0; x < 3; ++x) ctx->sh_ctr[3 * s + x] = xyz[3 * shell_atom[s] + x];
+    ctx->sh_off[s] = off;
+    off += 2 * shell_l[s] + 1;
+  }
+  ctx->n_ao = off;
+  ctx->lrange = lattice_range;
+  ctx->cells.clear();
+  ctx->tvec.clear();
+  for (int a = -lattice_range; a <= lattice_range; ++a)
+    for (int b = -lattice_range; b <= lattice_range; ++b)
+      for (int c = -lattice_range; c <= lattice_range; ++c) {
+        ctx->cells.push_back(a);
+        ctx->cells.push_back(b);
+        ctx->cells.push_back(c);
+        for (int x = 0; x < 3; ++x)
+          ctx->tvec.push_back(a * lat[x] + b * lat[3 + x] + c * lat[6 + x]);
+      }
+  ctx->n_cells = (int)ctx->cells.size() / 3;
+  hipStream_t st = ctx->stream;
+  HIPCK(stage_begin(ctx));
+  HIPCK(upload(ctx, ctx->d_sh_l, ctx->sh_l.data(), ctx->sh_l.size()));
+  HIPCK(upload(ctx, ctx->d_sh_ex, ctx->sh_ex.data(), ctx->sh_ex.size()));
+  HIPCK(upload(ctx, ctx->d_sh_ctr, ctx->sh_ctr.data(), ctx->sh_ctr.size()));
+  HIPCK(upload(ctx, ctx->d_sh_off, ctx->sh_off.data(), ctx->sh_off.size()));
+  HIPCK(upload(ctx, ctx->d_cells, ctx->cells.data(), ctx->cells.size()));
+  HIPCK(upload(ctx, ctx->d_tvec, ctx->tvec.data(), ctx->tvec.size()));
+  ctx->have_basis = true;
+  return QCX_OK;
+}
+
+static ShellTab shell_tab(qcx_ctx* ctx) {
+  ShellTab t;
+  t.l = ctx->d_sh_l.as<int>();
+  t.ex = ctx->d_sh_ex.as<double>();
+  t.ctr = ctx->d_sh_ctr.as<double>();
+  t.off = ctx->d_sh_off.as<int>();
+  t.n_sh = ctx->n_sh;
+  t.n_ao = ctx->n_ao;
+  return t;
+}
+
+int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* k_frac,
+                   int n_occ, int n_bands, const double* C_k, const double* E_k,
+                   const double* C_kq, const double* E_kq, int mem) {
+  if (!ctx) return QCX_EINVAL;
+  if (!ctx->have_basis) return fail(ctx, QCX_ESTATE, "set_cell_basis first");
+  if (!q_cart || !k_frac || !C_k || !E_k || !C_kq || !E_kq)
+    return fail(ctx, QCX_EINVAL, "NULL argument");
+  if (mem != QCX_MEM_HOST && mem != QCX_MEM_DEVICE) return fail(ctx, QCX_EINVAL, "bad mem");
+  if (n_k < 1 || n_occ < 1 || n_bands <= n_occ || n_bands > ctx->n_ao)
+    return fail(ctx, QCX_EINVAL, "need n_k >= 1 and 1 <= n_occ < n_bands <= N_AO");
+  const size_t n_t = 2 * (size_t)n_k * n_occ * (n_bands - n_occ);
+  if (n_t > (size_t)1 << 30) return fail(ctx, QCX_EINVAL, "too many transitions");
+  if (band_contract_lds(ctx->n_ao, n_bands, n_occ) > 160 * 1024)
+    return fail(ctx, QCX_EINVAL, "N_AO x n_bands too large for the band kernel");
+  HIPCK(hipSetDevice(ctx->device));
+  ctx->have_states = ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
+  hipStream_t st = ctx->stream;
+  const bool dev = mem == QCX_MEM_DEVICE;
+  // band order check needs the energies on the host
+  std::vector<double> ek((size_t)n_k * n_bands), ekq((size_t)n_k * n_bands);
+  if (dev) {
+    HIPCK(hipMemcpyAsync(ek.data(), E_k, ek.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(ekq.data(), E_kq, ekq.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+  } else {
+    memcpy(ek.data(), E_k, ek.size() * sizeof(double));
+    memcpy(ekq.data(), E_kq, ekq.size() * sizeof(double));
+  }
+  for (int k = 0; k < n_k; ++k) {
+    double vmax = -1e300, cmin = 1e300;
+    for (int b = 0; b < n_bands; ++b) {
+      const double e1 = ek[(size_t)k * n_bands + b], e2 = ekq[(size_t)k * n_bands + b];
+      if (!std::isfinite(e1) || !std::isfinite(e2)) return fail(ctx, QCX_EINVAL, "non-finite energy");
+      if (b < n_occ)
+        vmax = std::max(vmax, std::max(e1, e2));
+      else
+        cmin = std::min(cmin, std::min(e1, e2));
+    }
+    if (!(cmin > vmax))
+      return fail(ctx, QCX_EINVAL, "an empty band lies below an occupied band at k " +
+                                       std::to_string(k));
+  }
+  memcpy(ctx->q, q_cart, sizeof(double) * 3);
+  ctx->n_k = n_k;
+  ctx->n_occ = n_occ;
+  ctx->n_b = n_bands;
+  ctx->n_c = n_bands - n_occ;
+  ctx->n_t = (int)n_t;
+  const size_t ncoef = (size_t)n_k * ctx->n_ao * n_bands * 2;
+  HIPCK(stage_begin(ctx));
+  HIPCK(upload(ctx, ctx->d_kf, k_frac, (size_t)n_k * 3, dev));
+  HIPCK(upload(ctx, ctx->d_Ck, C_k, ncoef, dev));
+  HIPCK(upload(ctx, ctx->d_Ckq, C_kq, ncoef, dev));
+  HIPCK(upload(ctx, ctx->d_Ek, E_k, (size_t)n_k * n_bands, dev));
+  HIPCK(upload(ctx, ctx->d_Ekq, E_kq, (size_t)n_k * n_bands, dev));
+
+  // S(k) = M(k; 0) and S(k+q), then max |C^H S C - I|
+  const int nT = ctx->n_cells, nao = ctx->n_ao;
+  const double zero3[3] = {0.0, 0.0, 0.0};
+  double qf[3];
+  for (int i = 0; i < 3; ++i)
+    qf[i] = (ctx->lat[3 * i] * q_cart[0] + ctx->lat[3 * i + 1] * q_cart[1] +
+             ctx->lat[3 * i + 2] * q_cart[2]) / (2.0 * kPi);
+  HIPCK(upload(ctx, ctx->d_Q, zero3, 3));
+  HIPCK(ctx->d_F0.reserve(sizeof(cplx) * nT * (size_t)nao * nao));
+  HIPCK(ctx->d_ph.reserve(sizeof(cplx) * (size_t)n_k * nT));
+  HIPCK(ctx->d_phq.reserve(sizeof(cplx) * (size_t)n_k * nT));
+  HIPCK(ctx->d_S.reserve(sizeof(cplx) * (size_t)n_k * nao * nao));
+  HIPCK(ctx->d_dev.reserve(sizeof(double) * 2 * (size_t)n_k));
+  ShellTab sh = shell_tab(ctx);
+  launch_cell_ft(sh, ctx->d_tvec.as<double>(), nT, ctx->d_Q.as<double>(), 1, ctx->d_F0.as<cplx>(), st);
+  LAUNCHCK("cell_ft(S)");
+  launch_bloch_phase(ctx->d_kf.as<double>(), n_k, zero3, ctx->d_cells.as<int>(), nT,
+                     ctx->d_ph.as<cplx>(), st);
+  launch_bloch_phase(ctx->d_kf.as<double>(), n_k, qf, ctx->d_cells.as<int>(), nT,
+                     ctx->d_phq.as<cplx>(), st);
+  LAUNCHCK("bloch_phase");
+  launch_phase_sum(ctx->d_F0.as<cplx>(), ctx->d_ph.as<cplx>(), nT, 1, nao * nao, 0, n_k,
+                   ctx->d_S.as<cplx>(), st);
+  launch_orth_check(ctx->d_S.as<cplx>(), ctx->d_Ck.as<cplx>(), nao, n_bands, n_k,
+                    ctx->d_dev.as<double>(), st);
+  launch_phase_sum(ctx->d_F0.as<cplx>(), ctx->d_phq.as<cplx>(), nT, 1, nao * nao, 0, n_k,
+                   ctx->d_S.as<cplx>(), st);
+  launch_orth_check(ctx->d_S.as<cplx>(), ctx->d_Ckq.as<cplx>(), nao, n_bands, n_k,
+                    ctx->d_dev.as<double>() + n_k, st);
+  LAUNCHCK("orth_check");
+  HIPCK(ctx->d_dt.reserve(sizeof(double) * n_t));
+  launch_transition_energies(ctx->d_Ek.as<double>(), ctx->d_Ekq.as<double>(), n_k, n_bands, n_occ,
+                             ctx->d_dt.as<double>(), st);
+  LAUNCHCK("transition_energies");
+  std::vector<double> devs(2 * (size_t)n_k);
+  HIPCK(hipMemcpyAsync(devs.data(), ctx->d_dev.p, devs.size() * sizeof(double),
+                       hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  for (int i = 0; i < 2 * n_k; ++i) {
+    if (!(devs[i] <= 1e-10)) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "states at %s %d are not orthonormal: max|C^H S C - I| = %.3e",
+               i < n_k ? "k" : "k+q", i % n_k, devs[i]);
+      return fail(ctx, QCX_ENONORTH, buf);
+    }
+  }
+  ctx->have_states = true;
+  return QCX_OK;
+}
+
+int qcx_pair_density(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out) {
+  if (!ctx) return QCX_EINVAL;
+  if (!ctx->have_states) return fail(ctx, QCX_ESTATE, "set_states first");
+  if (n_G < 1 || n_G > 4096 || !G_int) return fail(ctx, QCX_EINVAL, "need 1 <= n_G <= 4096");
+  if (G_int[0] != 0 || G_int[1] != 0 || G_int[2] != 0)
+    return fail(ctx, QCX_EINVAL, "G_int[0] must be (0,0,0)");
+  HIPCK(hipSetDevice(ctx->device));
+  ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
+  hipStream_t st = ctx->stream;
+  std::vector<double> Q(3 * (size_t)n_G), vq(n_G);
+  for (int g = 0; g < n_G; ++g) {
+    double n2 = 0.0;
+    for (int x = 0; x < 3; ++x) {
+      double v = ctx->q[x];
+      for (int j = 0; j < 3; ++j) v += G_int[3 * g + j] * ctx->rec[3 * j + x];
+      Q[3 * g + x] = v;
+      n2 += v * v;
+    }
+    if (!(n2 > 0.0)) return fail(ctx, QCX_EINVAL, "q + G vanishes for G index " + std::to_string(g));
+    vq[g] = sqrt(4.0 * kPi) / sqrt(n2);
+  }
+  ctx->n_g = n_G;
+  HIPCK(stage_begin(ctx));
+  HIPCK(upload(ctx, ctx->d_Q, Q.data(), Q.size()));
+  HIPCK(upload(ctx, ctx->d_vq, vq.data(), vq.size()));
+  const int nT = ctx->n_cells, nao = ctx->n_ao;
+  const size_t nee = (size_t)nao * nao;
+  HIPCK(ctx->d_F.reserve(sizeof(cplx) * nT * (size_t)n_G * nee));
+  ctx->ldt = roundup(ctx->n_t, 256);
+  HIPCK(ctx->d_R.reserve(sizeof(cplx) * ctx->ldt * n_G));
+  HIPCK(hipMemsetAsync(ctx->d_R.p, 0, sizeof(cplx) * ctx->ldt * n_G, st));
+  const size_t per_k = sizeof(cplx) * (size_t)n_G * nee;
+  int kc = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, ((size_t)1 << 30) / per_k));
+  HIPCK(ctx->d_M.reserve(per_k * kc));
+  int sp_rho;
+  HIPCK(span_begin(ctx, 0, &sp_rho));
+  launch_cell_ft(shell_tab(ctx), ctx->d_tvec.as<double>(), nT, ctx->d_Q.as<double>(), n_G,
+                 ctx->d_F.as<cplx>(), st);
+  LAUNCHCK("cell_ft");
+  for (int k0 = 0; k0 < ctx->n_k; k0 += kc) {
+    const int nk = std::min(kc, ctx->n_k - k0);
+    launch_phase_sum(ctx->d_F.as<cplx>(), ctx->d_ph.as<cplx>(), nT, n_G, (int)nee, k0, nk,
+                     ctx->d_M.as<cplx>(), st);
+    launch_band_contract(ctx->d_M.as<cplx>(), ctx->d_Ck.as<cplx>(), ctx->d_Ckq.as<cplx>(), nao,
+                         ctx->n_b, ctx->n_occ, ctx->n_k, k0, nk, n_G, ctx->d_R.as<cplx>(),
+                         ctx->ldt, st);
+    LAUNCHCK("phase_sum/band_contract");
+  }
+  HIPCK(span_end(ctx, sp_rho));
+  if (rho_out) {
+    launch_rho_export(ctx->d_R.as<cplx>(), ctx->ldt, n_G, ctx->n_t, static_cast<cplx*>(rho_out), st);
+    LAUNCHCK("rho_export");
+  }
+  ctx->have_rho = true;
+  return QCX_OK;
+}
+
+static int pick_ksplit(int blocks, int steps) {
+  int ks = 1;
+  while (ks < 16 && blocks * ks < 1024 && steps / (2 * ks) >= 8) ks *= 2;
+  return ks;
+}
+
+int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int precision,
+             int headwings_fp64, void* chi0_out) {
+  if (!ctx) return QCX_EINVAL;
+  if (!ctx->have_rho) return fail(ctx, QCX_ESTATE, "pair_density first");
+  if (n_w < 1 || n_w > 65536 || !w_eV) return fail(ctx, QCX_EINVAL, "need 1 <= n_w <= 65536");
+  if (!(eta_eV >= 0.0) || !std::isfinite(eta_eV)) return fail(ctx, QCX_EINVAL, "eta must be >= 0");
+  if (precision < QCX_FP64 || precision > QCX_SPLIT_BF16)
+    return fail(ctx, QCX_EINVAL, "bad precision");
+  if (precision != QCX_FP64 && 2 * (size_t)ctx->n_g * 16 * 8 > 160 * 1024)
+    return fail(ctx, QCX_EINVAL, "the MFMA bulk path is limited to n_G <= 640");
+  HIPCK(hipSetDevice(ctx->device));
+  ctx->have_chi0 = ctx->have_eps = false;
+  hipStream_t st = ctx->stream;
+  std::vector<double> w(n_w);
+  for (int i = 0; i < n_w; ++i) {
+    if (!std::isfinite(w_eV[i])) return fail(ctx, QCX_EINVAL, "non-finite frequency");
+    w[i] = w_eV[i] / kHartreeEV;
+  }
+  HIPCK(stage_begin(ctx));
+  HIPCK(upload(ctx, ctx->d_w, w.data(), w.size()));
+  ctx->n_w = n_w;
+  ctx->eta = eta_eV / kHartreeEV;
+  ctx->prec = precision;
+  ctx->hw64 = headwings_fp64 ? 1 : 0;
+
+  Chi0Geom& g = ctx->geom;
+  g = Chi0Geom{};
+  g.n_g = ctx->n_g;
+  g.n_t = ctx->n_t;
+  g.n_w = n_w;
+  g.n_rows = 2 * n_w;
+  g.n_pairs = ctx->n_g * (ctx->n_g + 1) / 2;
+  if (precision == QCX_FP64) {
+    ctx->n_pairs64 = g.n_pairs;
+    g.p0 = g.n_pairs;
+  } else {
+    ctx->n_pairs64 = ctx->hw64 ? ctx->n_g : 0;
+    g.p0 = ctx->n_pairs64;
+  }
+  g.n_bulk = g.n_pairs - g.p0;
+  g.n_bulkp = (int)roundup(std::max(g.n_bulk, 1), 128);
+  int sp_all, sp_bulk = -1, sp_hw = -1;
+  HIPCK(span_begin(ctx, 3, &sp_all));
+  if (g.n_bulk > 0) {
+    g.n_rowsp = (int)roundup(g.n_rows, 128);
+    const int af = bulk_row_frags(g);
+    g.n_rowsp = (int)roundup(g.n_rows, 32 * af);
+    const int blocks = (g.n_bulkp / 128) * (g.n_rowsp / (32 * af));
+    g.ksplit = pick_ksplit(blocks, (int)roundup(g.n_t, 16) / 16);
+    g.n_tp = (int)roundup(g.n_t, 16 * g.ksplit);
+    const size_t nA = (size_t)g.n_rowsp * g.n_tp;  // elements
+    const size_t nC = (size_t)g.ksplit * g.n_rowsp * 2 * g.n_bulkp;
+    HIPCK(ctx->d_R32.reserve(sizeof(float) * 2 * (size_t)g.n_g * g.n_tp));
+    HIPCK(ctx->d_C.reserve(sizeof(float) * nC));
+    std::vector<int> pairs(g.n_bulkp, 0);
+    {
+      int b = 0, p = 0;
+      for (int G = 0; G < g.n_g; ++G)
+        for (int Gp = G; Gp < g.n_g; ++Gp, ++p)
+          if (p >= g.p0) pairs[b++] = G | (Gp << 16);
+    }
+    HIPCK(upload(ctx, ctx->d_pairs, pairs.data(), pairs.size()));
+    const bool bf = precision == QCX_SPLIT_BF16;
+    launch_pack_r32(ctx->d_R.as<cplx>(), ctx->ldt, g, bf ? 0 : 1, ctx->d_R32.as<float>(), st);
+    if (bf) {
+      HIPCK(ctx->d_A.reserve(sizeof(uint16_t) * nA));
+      HIPCK(ctx->d_Alo.reserve(sizeof(uint16_t) * nA));
+      launch_weights_bf16(ctx->d_w.as<double>(), ctx->d_dt.as<double>(), ctx->eta, g,
+                          ctx->d_A.as<uint16_t>(), ctx->d_Alo.as<uint16_t>(), st);
+    } else {
+      HIPCK(ctx->d_A.reserve(sizeof(float) * nA));
+      launch_weights_f32(ctx->d_w.as<double>(), ctx->d_dt.as<double>(), ctx->eta, g,
+                         ctx->d_A.as<float>(), st);
+    }
+    LAUNCHCK("weights/pack");
+    HIPCK(span_begin(ctx, 1, &sp_bulk));
+    if (bf)
+      launch_bulk_bf16(ctx->d_A.as<uint16_t>(), ctx->d_Alo.as<uint16_t>(), ctx->d_R32.as<float>(),
+                       ctx->d_pairs.as<int>(), g, ctx->d_C.as<float>(), st);
+    else
+      launch_bulk_f32(ctx->d_A.as<float>(), ctx->d_R32.as<float>(), ctx->d_pairs.as<int>(), g,
+                      ctx->d_C.as<float>(), st);
+    LAUNCHCK("bulk");
+    HIPCK(span_end(ctx, sp_bulk));
+  } else {
+    g.ksplit = 1;
+    g.n_rowsp = 0;
+    g.n_tp = (int)roundup(g.n_t, 16);
+  }
+  if (ctx->n_pairs64 > 0) {
+    const int pt = (ctx->n_pairs64 + 127) / 128, wt = (n_w + 31) / 32;
+    int ks = 1;
+    while (ks < 64 && pt * wt * ks < 1024 && ctx->n_t / (2 * ks) >= 256 &&
+           (size_t)(2 * ks) * n_w * ctx->n_pairs64 * 32 <= ((size_t)1 << 30))
+      ks *= 2;
+    ctx->ks64 = ks;
+    HIPCK(ctx->d_XY.reserve(sizeof(double) * 4 * (size_t)ks * n_w * ctx->n_pairs64));
+    const int gb = precision == QCX_FP64 ? ctx->n_g : 1;
+    HIPCK(span_begin(ctx, 2, &sp_hw));
+    launch_pairs_f64(ctx->d_R.as<cplx>(), ctx->ldt, ctx->d_w.as<double>(), ctx->d_dt.as<double>(),
+                     ctx->eta, n_w, ctx->n_t, ctx->n_g, 0, gb, ks, ctx->d_XY.as<double>(), st);
+    LAUNCHCK("pairs_f64");
+    HIPCK(span_end(ctx, sp_hw));
+  }
+  HIPCK(span_end(ctx, sp_all));
+  ctx->have_chi0 = true;
+  if (chi0_out) {
+    AsmArgs a{};
+    a.C = g.n_bulk > 0 ? ctx->d_C.as<float>() : nullptr;
+    a.XY = ctx->n_pairs64 > 0 ? ctx->d_XY.as<double>() : nullptr;
+    a.ks = g.ksplit;
+    a.ks64 = ctx->ks64;
+    a.n_pairs64 = ctx->n_pairs64;
+    a.vq = ctx->d_vq.as<double>();
+    a.pref = 2.0 / (ctx->n_k * ctx->vol);
+    launch_chi0_export(a, g, static_cast<cplx*>(chi0_out), st);
+    LAUNCHCK("chi0_export");
+  }
+  return QCX_OK;
+}
+
+int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out) {
+  if (!ctx) return QCX_EINVAL;
+  if (!ctx->have_chi0) return fail(ctx, QCX_ESTATE, "chi0 first");
+  if (lfe && ctx->n_g > 2048) return fail(ctx, QCX_EINVAL, "LFE inversion limited to n_G <= 2048");
+  HIPCK(hipSetDevice(ctx->device));
+  ctx->have_eps = false;
+  hipStream_t st = ctx->stream;
+  const Chi0Geom& g = ctx->geom;
+  const int n = ctx->n_g, nw = ctx->n_w;
+  HIPCK(ctx->d_eps.reserve(sizeof(cplx) * (size_t)nw * n * n));
+  HIPCK(ctx->d_diag.reserve(sizeof(cplx) * (size_t)nw * n));
+  HIPCK(ctx->d_epsM.reserve(sizeof(cplx) * (size_t)nw));
+  HIPCK(ctx->d_loss.reserve(sizeof(double) * (size_t)nw * n));
+  HIPCK(ctx->d_sing.reserve(sizeof(int)));
+  HIPCK(hipMemsetD32Async((hipDeviceptr_t)ctx->d_sing.p, INT_MAX, 1, st));
+  int sp_eps;
+  HIPCK(span_begin(ctx, 4, &sp_eps));
+  AsmArgs a{};
+  a.C = g.n_bulk > 0 ? ctx->d_C.as<float>() : nullptr;
+  a.XY = ctx->n_pairs64 > 0 ? ctx->d_XY.as<double>() : nullptr;
+  a.ks = g.ksplit;
+  a.ks64 = ctx->ks64;
+  a.n_pairs64 = ctx->n_pairs64;
+  a.vq = ctx->d_vq.as<double>();
+  a.pref = 2.0 / (ctx->n_k * ctx->vol);
+  launch_eps_assemble(a, g, ctx->d_eps.as<cplx>(), st);
+  LAUNCHCK("eps_assemble");
+  if (lfe)
+    launch_gj_diag(ctx->d_eps.as<cplx>(), n, nw, ctx->d_diag.as<cplx>(), ctx->d_sing.as<int>(), st);
+  else
+    launch_nolfe_diag(ctx->d_eps.as<cplx>(), n, nw, ctx->d_diag.as<cplx>(), ctx->d_sing.as<int>(), st);
+  LAUNCHCK("inverse");
+  launch_loss(ctx->d_diag.as<cplx>(), n, nw, ctx->d_loss.as<double>(), ctx->d_epsM.as<cplx>(), st);
+  LAUNCHCK("loss");
+  HIPCK(span_end(ctx, sp_eps));
+  if (diag_out)
+    HIPCK(hipMemcpyAsync(diag_out, ctx->d_diag.p, sizeof(cplx) * (size_t)nw * n,
+                         hipMemcpyDeviceToDevice, st));
+  if (epsM_out)
+    HIPCK(hipMemcpyAsync(epsM_out, ctx->d_epsM.p, sizeof(cplx) * (size_t)nw,
+                         hipMemcpyDeviceToDevice, st));
+  ctx->have_eps = true;
+  return QCX_OK;
+}
+
+int qcx_loss(qcx_ctx* ctx, double* out, int mem) {
+  if (!ctx) return QCX_EINVAL;
+  if (!ctx->have_eps) return fail(ctx, QCX_ESTATE, "eps_inv first");
+  if (!out) return fail(ctx, QCX_EINVAL, "NULL out");
+  HIPCK(hipSetDevice(ctx->device));
+  const size_t bytes = sizeof(double) * (size_t)ctx->n_w * ctx->n_g;
+  if (mem == QCX_MEM_DEVICE) {
+    HIPCK(hipMemcpyAsync(out, ctx->d_loss.p, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    return QCX_OK;
+  }
+  if (mem != QCX_MEM_HOST) return fail(ctx, QCX_EINVAL, "bad mem");
+  HIPCK(hipMemcpyAsync(out, ctx->d_loss.p, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  return qcx_sync(ctx);
+}
+
+}  // extern "C"

@@ -1,0 +1,234 @@
+"""Thin Python binding of libqcx (include/qcx.h): argument marshalling only.
+
+Every step of the path runs in the HIP library; this module converts numpy
+arrays (host) and torch CUDA tensors (device) to plain pointers, passes the
+caller's torch stream, and raises QcxError on a non-zero status.  There is no
+CPU fallback: if libqcx.so is missing or the device is not gfx950, creating a
+Context fails loudly.
+
+Method names follow the C entry points without their `qcx_` prefix:
+set_cell_basis, set_states, pair_density, chi0, eps_inv, loss, sync,
+stage_times, set_timing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqcx.so")
+
+OK, EINVAL, ESTATE, ENONORTH, ESINGULAR, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6
+MEM_HOST, MEM_DEVICE = 0, 1
+FP64, FP32, SPLIT_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16}
+
+_ERRNAMES = {EINVAL: "QCX_EINVAL", ESTATE: "QCX_ESTATE", ENONORTH: "QCX_ENONORTH",
+             ESINGULAR: "QCX_ESINGULAR", EDEVICE: "QCX_EDEVICE", ENOMEM: "QCX_ENOMEM"}
+
+
+class QcxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+_SIGS = {
+    "qcx_create": [ctypes.POINTER(_P), _I, _P],
+    "qcx_destroy": [_P],
+    "qcx_last_error": [_P],
+    "qcx_sync": [_P],
+    "qcx_set_cell_basis": [_P, _P, _I, _P, _I, _P, _P, _P, _I, _I],
+    "qcx_set_states": [_P, _P, _I, _P, _I, _I, _P, _P, _P, _P, _I],
+    "qcx_pair_density": [_P, _I, _P, _P],
+    "qcx_chi0": [_P, _I, _P, _D, _I, _I, _P],
+    "qcx_eps_inv": [_P, _I, _P, _P],
+    "qcx_loss": [_P, _P, _I],
+    "qcx_stage_times": [_P, _P],
+    "qcx_set_timing": [_P, _I],
+    "qcx_build_info": [],
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libqcx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_2603_12326_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name in ("qcx_last_error", "qcx_build_info") else _I
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _host(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _ptr_host(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _is_torch_cuda(x) -> bool:
+    return hasattr(x, "is_cuda") and hasattr(x, "data_ptr") and bool(x.is_cuda)
+
+
+def _dev_ptr(t, dtype_name: str, numel: int, what: str):
+    import torch
+
+    want = {"f64": torch.float64, "c128": torch.complex128, "i32": torch.int32}[dtype_name]
+    if not _is_torch_cuda(t):
+        raise TypeError(f"{what}: expected a CUDA tensor")
+    if t.dtype != want or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{what}: need contiguous {want} with {numel} elements, got "
+                         f"{t.dtype} {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context on one device and stream."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        self.lib = load_library()
+        if stream is None:
+            import torch
+
+            torch.cuda.set_device(device)
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self._stream = int(stream)
+        h = ctypes.c_void_p()
+        rc = self.lib.qcx_create(ctypes.byref(h), device, ctypes.c_void_p(self._stream))
+        if rc != OK:
+            raise QcxError(rc, self.lib.qcx_last_error(None).decode())
+        self._h = h
+        self.n_g = self.n_w = self.n_k = self.n_occ = self.n_bands = None
+
+    # -- plumbing
+    def _check(self, rc: int):
+        if rc != OK:
+            raise QcxError(rc, self.lib.qcx_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.qcx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- the C entry points
+    def set_cell_basis(self, lat, xyz, shell_atom, shell_l, shell_exp, pure_d: int = 1,
+                       lattice_range: int = 1):
+        lat = _host(lat, np.float64).reshape(9)
+        xyz = _host(xyz, np.float64).reshape(-1, 3)
+        sa = _host(shell_atom, np.int32)
+        sl = _host(shell_l, np.int32)
+        se = _host(shell_exp, np.float64)
+        self._check(self.lib.qcx_set_cell_basis(self._h, _ptr_host(lat), len(xyz), _ptr_host(xyz),
+                                                len(sl), _ptr_host(sa), _ptr_host(sl),
+                                                _ptr_host(se), pure_d, lattice_range))
+
+    def set_states(self, q_cart, k_frac, n_occ: int, C_k, E_k, C_kq, E_kq):
+        """Host numpy arrays, or CUDA tensors (complex128 C, float64 k and E)."""
+        q = _host(q_cart, np.float64).reshape(3)
+        if _is_torch_cuda(C_k):
+            n_k, n_ao, n_b = C_k.shape
+            kf = _dev_ptr(k_frac, "f64", n_k * 3, "k_frac")
+            ptrs = [_dev_ptr(C_k, "c128", n_k * n_ao * n_b, "C_k"),
+                    _dev_ptr(E_k, "f64", n_k * n_b, "E_k"),
+                    _dev_ptr(C_kq, "c128", n_k * n_ao * n_b, "C_kq"),
+                    _dev_ptr(E_kq, "f64", n_k * n_b, "E_kq")]
+            mem = MEM_DEVICE
+            keep = None
+        else:
+            kf_a = _host(k_frac, np.float64)
+            arrs = [_host(C_k, np.complex128), _host(E_k, np.float64),
+                    _host(C_kq, np.complex128), _host(E_kq, np.float64)]
+            n_k, n_ao, n_b = arrs[0].shape
+            kf = _ptr_host(kf_a)
+            ptrs = [_ptr_host(a) for a in arrs]
+            mem = MEM_HOST
+            keep = (kf_a, arrs)
+        self._check(self.lib.qcx_set_states(self._h, _ptr_host(q), n_k, kf, n_occ, n_b, ptrs[0],
+                                            ptrs[1], ptrs[2], ptrs[3], mem))
+        del keep
+        self.n_k, self.n_occ, self.n_bands = n_k, n_occ, n_b
+
+    def pair_density(self, G_int, rho_out=None):
+        G = _host(G_int, np.int32).reshape(-1, 3)
+        out = None
+        if rho_out is not None:
+            n_c = self.n_bands - self.n_occ
+            out = _dev_ptr(rho_out, "c128", 2 * self.n_k * self.n_occ * n_c * len(G), "rho_out")
+        self._check(self.lib.qcx_pair_density(self._h, len(G), _ptr_host(G), out))
+        self.n_g = len(G)
+
+    def chi0(self, w_eV, eta_eV: float, precision=FP64, headwings_fp64: bool = True,
+             chi0_out=None):
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        w = _host(w_eV, np.float64).reshape(-1)
+        out = None
+        if chi0_out is not None:
+            out = _dev_ptr(chi0_out, "c128", len(w) * self.n_g * self.n_g, "chi0_out")
+        self._check(self.lib.qcx_chi0(self._h, len(w), _ptr_host(w), float(eta_eV), int(precision),
+                                      1 if headwings_fp64 else 0, out))
+        self.n_w = len(w)
+
+    def eps_inv(self, lfe: bool = True, diag_out=None, epsM_out=None):
+        d = None if diag_out is None else _dev_ptr(diag_out, "c128", self.n_w * self.n_g, "diag_out")
+        e = None if epsM_out is None else _dev_ptr(epsM_out, "c128", self.n_w, "epsM_out")
+        self._check(self.lib.qcx_eps_inv(self._h, 1 if lfe else 0, d, e))
+
+    def loss(self, out=None):
+        """Host numpy [n_w][n_G] (synchronising) when out is None, else a CUDA tensor."""
+        if out is None:
+            arr = np.empty((self.n_w, self.n_g), np.float64)
+            self._check(self.lib.qcx_loss(self._h, _ptr_host(arr), MEM_HOST))
+            return arr
+        self._check(self.lib.qcx_loss(self._h, _dev_ptr(out, "f64", self.n_w * self.n_g, "out"),
+                                      MEM_DEVICE))
+        return out
+
+    def sync(self):
+        self._check(self.lib.qcx_sync(self._h))
+
+    def set_timing(self, enable: bool = True):
+        self._check(self.lib.qcx_set_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self) -> dict:
+        t = np.zeros(6, np.float64)
+        self._check(self.lib.qcx_stage_times(self._h, _ptr_host(t)))
+        return dict(pair_density_ms=t[0], chi0_bulk_ms=t[1], chi0_headwings_ms=t[2],
+                    chi0_total_ms=t[3], eps_inv_ms=t[4], bulk_launches=int(t[5]))
+
+
+def build_info() -> str:
+    return load_library().qcx_build_info().decode()

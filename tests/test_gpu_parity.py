@@ -1,0 +1,151 @@
+"""HIP path against the FP64 oracle, element by element, through the C ABI.
+
+Tolerances: 1e-10 relative for the FP64 path; 1e-4 normwise on the loss
+(per (q, G) curve: max_w |L - Lref| / max_w |Lref|) for the FP32 and
+split-BF16 bulk with FP64 head/wings and FP64 inversion.
+"""
+import numpy as np
+import pytest
+
+from oracle import rpa
+from synth import make_config1, make_config2, make_tiny
+from tests.gpu_helpers import gpu_solve, normwise, relmax, set_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2603_12326_amd import Context
+
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _oracle(wl, iq=0, w=None, G=None):
+    st = wl.states(iq)
+    G = wl.G_int if G is None else G
+    w = wl.w_eV if w is None else w
+    return rpa.solve(wl.cell, wl.basis, wl.lattice_range, wl.k_frac, wl.n_occ, G, st, w,
+                     wl.eta_eV, return_all=True)
+
+
+def test_native_library_loaded(ctx):
+    from paper_2603_12326_amd import build_info
+
+    assert "gfx950" in build_info()
+
+
+@pytest.mark.parametrize("maker", [make_tiny, make_config1])
+def test_rho_fp64(ctx, maker):
+    wl = maker()
+    ref = _oracle(wl)
+    out = gpu_solve(ctx, wl, precision="fp64", want_rho=True)
+    err = relmax(out["rho"], ref["R"])
+    print(wl.name, "rho rel err", err)
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("maker", [make_tiny, make_config1])
+def test_chi0_and_loss_fp64(ctx, maker):
+    wl = maker()
+    ref = _oracle(wl)
+    out = gpu_solve(ctx, wl, precision="fp64", want_chi0=True)
+    e_chi = relmax(out["chi0"], ref["chi0"])
+    e_loss = normwise(out["loss"], ref["loss"])
+    print(wl.name, "chi0", e_chi, "loss", e_loss)
+    assert e_chi < 1e-10
+    assert e_loss < 1e-10
+    assert np.max(np.abs(out["loss"] - ref["loss"])) < 1e-10 * np.max(np.abs(ref["loss"]))
+
+
+def test_nolfe_fp64(ctx, cfg1):
+    ref = _oracle(cfg1)
+    out = gpu_solve(ctx, cfg1, precision="fp64", lfe=False)
+    assert normwise(out["loss"], rpa.loss_nolfe(ref["eps"])) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("maker", [make_tiny, make_config1])
+def test_loss_reduced_precision(ctx, maker, prec):
+    wl = maker()
+    ref = _oracle(wl)
+    out = gpu_solve(ctx, wl, precision=prec, want_chi0=True)
+    e = normwise(out["loss"], ref["loss"])
+    print(wl.name, prec, "loss normwise", e, "chi0", relmax(out["chi0"], ref["chi0"]))
+    assert e < 1e-4
+
+
+@pytest.mark.parametrize("iq", [0, 9])
+def test_config2_full_size_sampled(ctx, iq):
+    """N_G = 113, 8^3 k, 4+16 bands, 400 w in one launch as the benchmark runs
+    it; every 16th frequency is checked against the oracle."""
+    wl = make_config2()
+    idx = np.arange(0, 400, 16)
+    ref = _oracle(wl, iq, w=wl.w_eV[idx])
+    for prec in ("split_bf16", "fp32"):
+        out = gpu_solve(ctx, wl, iq, precision=prec)
+        e = normwise(out["loss"][idx], ref["loss"])
+        print("config2 q", iq, prec, "normwise", e)
+        assert e < 1e-4
+    out = gpu_solve(ctx, wl, iq, precision="fp64", w_eV=wl.w_eV[idx[:4]])
+    e64 = normwise(out["loss"], ref["loss"][:4])
+    print("config2 q", iq, "fp64", e64)
+    assert e64 < 1e-10
+
+
+def test_ragged_shapes(ctx):
+    """One k point, odd G count that closes no tile, a single frequency, and 37 frequencies."""
+    wl = make_tiny(kgrid=1, n_g=9)
+    G = wl.G_int[:7]
+    for w in (wl.w_eV[:1], np.linspace(0.5, 33.0, 37)):
+        ref = _oracle(wl, w=w, G=G)
+        for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4), ("split_bf16", 1e-4)):
+            out = gpu_solve(ctx, wl, precision=prec, w_eV=w, G_int=G)
+            assert normwise(out["loss"], ref["loss"]) < tol, (prec, len(w))
+
+
+def test_headwings_flag_consistent(ctx, cfg1):
+    ref = _oracle(cfg1)
+    for hw in (True, False):
+        out = gpu_solve(ctx, cfg1, precision="split_bf16", hw64=hw)
+        assert normwise(out["loss"], ref["loss"]) < 1e-4
+
+
+def test_deterministic(ctx, cfg1):
+    for prec in ("fp64", "split_bf16"):
+        a = gpu_solve(ctx, cfg1, precision=prec)["loss"]
+        b = gpu_solve(ctx, cfg1, precision=prec)["loss"]
+        assert np.array_equal(a, b)
+
+
+def test_error_paths(ctx, cfg1):
+    from paper_2603_12326_amd import Context, QcxError
+    from paper_2603_12326_amd import qcx as q
+
+    c2 = Context(0)
+    with pytest.raises(QcxError) as e:
+        c2.pair_density(cfg1.G_int)
+    assert e.value.code == q.ESTATE
+    st = set_inputs(c2, cfg1)
+    with pytest.raises(QcxError) as e:
+        c2.pair_density(cfg1.G_int[1:])          # G[0] != 0
+    assert e.value.code == q.EINVAL
+    with pytest.raises(QcxError) as e:
+        c2.eps_inv()
+    assert e.value.code == q.ESTATE
+    bad = st.C_kq.copy()
+    bad[3] *= 1.001
+    with pytest.raises(QcxError) as e:
+        c2.set_states(st.q_cart, cfg1.k_frac, cfg1.n_occ, st.C_k, st.E_k, bad, st.E_kq)
+    assert e.value.code == q.ENONORTH
+    ebad = st.E_k.copy()
+    ebad[0, cfg1.n_occ] = -20.0
+    with pytest.raises(QcxError) as e:
+        c2.set_states(st.q_cart, cfg1.k_frac, cfg1.n_occ, st.C_k, ebad, st.C_kq, st.E_kq)
+    assert e.value.code == q.EINVAL
+    c2.close()
