@@ -98,21 +98,27 @@ void launch_weights_bf16(const double* w, const double* dt, double eta, const Ch
 void launch_pack_r32(const cplx* R, size_t ldt, const Chi0Geom& g, int perm, float* R32,
                      hipStream_t st);
 int bulk_row_frags(const Chi0Geom& g);
-size_t pairs_f64_tc(int n_g);
 void launch_bulk_f32(const float* Aw, const float* R32, const int* pairs, const Chi0Geom& g,
                      float* C, hipStream_t st);
 void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32,
                       const int* pairs, const Chi0Geom& g, float* C, hipStream_t st);
-// FP64 X/Y for pairs (G in [ga, gb), all G' >= G); out [ks][n_w][pair][4]
+// FP64 pairs on FP64 MFMA: out[split][row][col], rows (Re W, Im W) per
+// frequency, columns (Re P, Im P) per pair slot; slot ps holds (G | G' << 16).
+struct Geom64 {
+  int n_w, n_t, n_ps;
+  int n_rowsp, n_colp;
+  int ksplit, chunk_t;
+};
+void geom64_init(Geom64& g, int n_w, int n_t, int n_ps, size_t max_bytes);
 void launch_pairs_f64(const cplx* R, size_t ldt, const double* w, const double* dt, double eta,
-                      int n_w, int n_t, int n_g, int ga, int gb, int ksplit, double* XY,
-                      hipStream_t st);
+                      const Geom64& g, const int* pairs, double* out, hipStream_t st);
 // eps assembly (symmetrised Coulomb, prefactor 2/(N_k V))
 struct AsmArgs {
-  const float* C;       // bulk partials [ks][n_rowsp][2*n_bulkp] or null
-  const double* XY;     // FP64 partials [ks64][n_w][n_pairs64][4] or null
+  const float* C;       // bulk partials [ks][n_rowsp][2][n_bulkp] or null
+  const double* XY;     // FP64 partials [ks64][n_rowsp64][n_colp64] or null
   int ks, ks64;
-  int n_pairs64;        // pairs held by XY (head/wings: n_g; full: n_pairs)
+  int n_rowsp64, n_colp64;
+  int n_pairs64;        // pairs (flat indices 0..n_pairs64-1) held by XY
   const double* vq;     // sqrt(4 pi)/|q+G|
   double pref;
 };

@@ -132,27 +132,99 @@ __global__ void k_pack_r32(const cplx* R, size_t ldt, int n_g, int n_tp, int per
 // ---------------------------------------------------------------------------
 // Bulk kernel.  Block = 4 waves; block tile = AF*32 rows x 128 pairs (each
 // wave: all AF*32 rows and 32 pairs, i.e. two B fragments, Re P and Im P).
-// The R slab of the current K step (all G, 16 transitions, complex float) is
-// double-buffered in LDS; the A fragments come straight from global memory in
-// fragment order.  grid = (pair tiles, row tiles, K splits).
+// Per K step (16 transitions) the block stages in LDS, double-buffered through
+// registers: the R slab (all G x 16 transitions, complex float; rows padded to
+// 144 bytes so that lanes reading consecutive G hit distinct banks) and the
+// block's AF A fragments (2 KB each: bf16 hi and lo, or the f32 values).
+// grid = (pair tiles, row tiles, K splits).
 // ---------------------------------------------------------------------------
-template <bool BF16, int AF, int MAXF4>
-__global__ void __launch_bounds__(256) k_bulk(const void* __restrict__ Ahi_,
-                                              const void* __restrict__ Alo_,
-                                              const float* __restrict__ R32,
+// Block scheduling across the 8 XCDs (each with its own L2): workgroup i is
+// dispatched to XCD i % 8.  Blocks that share a K range (the same R slab and
+// A fragments) are given ids on one XCD, so that their common operands are
+// fetched from HBM once per XCD and then served from that XCD's L2.
+// Returns (x, y, z) for a logical grid gx * gy * gz with gz % 8 == 0 and the
+// z index (K split) kept on one XCD; other shapes map linearly.
+struct Blk3 {
+  int x, y, z;
+};
+__device__ inline Blk3 xcd_block(int gx, int gy, int gz) {
+  const int id = blockIdx.x;
+  if (gz % 8 != 0) return {id % gx, (id / gx) % gy, id / (gx * gy)};
+  const int xcd = id & 7, local = id >> 3;
+  const int per = gx * gy;
+  const int z = xcd + 8 * (local / per);
+  const int rem = local % per;
+  return {rem % gx, rem / gx, z};
+}
+
+constexpr int SLAB_LD4 = 9;  // float4 per padded slab row (8 used)
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Copy one 1 KB chunk (64 lanes x 16 bytes) from global memory straight into
+// LDS (gfx950 global_load_lds_dwordx4): lane l's float4 lands at dst + l.
+__device__ inline void lds_dma16(const float4* src, float4* dst) {
+  __builtin_amdgcn_global_load_lds((const void*)src, (lds_ptr_t)dst, 16, 0, 0);
+}
+
+template <bool BF16, int AF, int MAXR>
+__global__ void __launch_bounds__(256) k_bulk(const float4* __restrict__ Ahi,
+                                              const float4* __restrict__ Alo,
+                                              const float4* __restrict__ R32,
                                               const int* __restrict__ pairs, Chi0Geom g,
                                               float* __restrict__ C) {
-  extern __shared__ float4 slab[];  // 2 buffers of n_g * 16 complex floats
+  constexpr int NAC = 2 * AF;                 // A chunks per step (hi/lo or two f32 quads)
+  constexpr int MAXA = (NAC + 3) / 4;         // A chunks per wave
+  extern __shared__ float4 lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
   const int ntb = g.n_tp / KSTEP;
   const int steps = ntb / g.ksplit;
-  const int tb0 = blockIdx.z * steps;
-  const int rb0 = blockIdx.y * AF;
-  const int b = blockIdx.x * 128 + wave * 32 + (lane & 31);
+  const Blk3 bk = xcd_block(g.n_bulkp / 128, g.n_rowsp / (32 * AF), g.ksplit);
+  const int tb0 = bk.z * steps;
+  const int rb0 = bk.y * AF;
+  const int b = bk.x * 128 + wave * 32 + (lane & 31);
   const int pk = pairs[b];
   const int G = pk & 0xffff, Gp = pk >> 16;
-  const int slab_f4 = g.n_g * KSTEP * 2 / 4;  // float4 per slab
-  const float4* src = reinterpret_cast<const float4*>(R32);
+  const int nr4 = g.n_g * 8;                  // float4 of one slab in global memory
+  const int nrc = (g.n_g * SLAB_LD4 + 63) / 64;  // R chunks (padded rows) per step
+  const int abase = nrc * 64;                 // A fragments after the slab chunks
+  const int buf4 = abase + NAC * 64;
+
+  // Per-lane source offsets of this wave's chunks (K step added per step).
+  // R chunk c: LDS slot 64c + lane = padded row / column; pad slots read a
+  // harmless valid address and are never used.
+  int r_off[MAXR];
+#pragma unroll
+  for (int i = 0; i < MAXR; ++i) {
+    const int slot = 64 * (wave + 4 * i) + lane;
+    const int row = slot / SLAB_LD4, col = slot % SLAB_LD4;
+    r_off[i] = (row < g.n_g && col < 8) ? row * 8 + col : 0;
+  }
+  const float4* a_src[MAXA];
+#pragma unroll
+  for (int i = 0; i < MAXA; ++i) {
+    const int c = wave + 4 * i;
+    const int cc = c < NAC ? c : 0;
+    const int f = cc >> 1, half = cc & 1;
+    const size_t fr = (size_t)(rb0 + f) * ntb * 64 + lane;
+    if constexpr (BF16)
+      a_src[i] = (half ? Alo : Ahi) + fr;
+    else
+      a_src[i] = Ahi + fr * 2 + half;
+  }
+  constexpr int ASTEP = BF16 ? 64 : 128;  // float4 between K steps of one fragment
+  auto stage = [&](int tb, float4* buf) {
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+      const int c = wave + 4 * i;
+      if (c < nrc) lds_dma16(R32 + (size_t)tb * nr4 + r_off[i], buf + 64 * c);
+    }
+#pragma unroll
+    for (int i = 0; i < MAXA; ++i) {
+      const int c = wave + 4 * i;
+      if (c < NAC) lds_dma16(a_src[i] + (size_t)tb * ASTEP, buf + abase + 64 * c);
+    }
+  };
 
   f32x16 acc[AF][2];
 #pragma unroll
@@ -164,31 +236,44 @@ __global__ void __launch_bounds__(256) k_bulk(const void* __restrict__ Ahi_,
     }
   }
 
-  // prologue: slab tb0 -> buffer 0
-  for (int i = threadIdx.x; i < slab_f4; i += 256) slab[i] = src[(size_t)tb0 * slab_f4 + i];
+  stage(tb0, lds);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
   for (int st = 0; st < steps; ++st) {
     const int tb = tb0 + st;
-    const float4* cur = slab + (st & 1) * slab_f4;
-    // prefetch the next slab into registers
-    float4 nxt[MAXF4];
-    const bool more = st + 1 < steps;
-    const float4* nsrc = src + (size_t)(more ? tb + 1 : tb) * slab_f4;
+    const float4* cur = lds + (st & 1) * buf4;
+    // 1. every LDS read of this step first ...
+    const float4* rG = cur + G * SLAB_LD4 + 4 * h;    // 8 complex = 4 float4
+    const float4* rGp = cur + Gp * SLAB_LD4 + 4 * h;
+    float4 xg[4], yg[4];
 #pragma unroll
-    for (int u = 0; u < MAXF4; ++u) {
-      const int i = threadIdx.x + u * 256;
-      nxt[u] = nsrc[i < slab_f4 ? i : 0];
+    for (int i = 0; i < 4; ++i) {
+      xg[i] = rG[i];
+      yg[i] = rGp[i];
     }
-    // B operand: P_t(G, G') for this lane's pair and 8 transitions
-    const float2* s2 = reinterpret_cast<const float2*>(cur);
+    const float4* As = cur + abase;
+    float4 a0[AF], a1[AF];
+#pragma unroll
+    for (int f = 0; f < AF; ++f) {
+      a0[f] = As[f * 128 + lane];
+      a1[f] = As[f * 128 + 64 + lane];
+    }
+    // 2. ... then the copies of the next step into the other buffer (no LDS
+    // read follows them in this step, so no wait is needed before the MFMAs)
+    __builtin_amdgcn_sched_barrier(0);
+    if (st + 1 < steps) stage(tb + 1, lds + ((st + 1) & 1) * buf4);
+    __builtin_amdgcn_sched_barrier(0);
+    // 3. B operand: P_t(G, G') for this lane's pair and 8 transitions
     float pre[8], pim[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const float2 x = s2[G * KSTEP + 8 * h + i];
-      const float2 y = s2[Gp * KSTEP + 8 * h + i];
-      pre[i] = x.x * y.x + x.y * y.y;
-      pim[i] = x.x * y.y - x.y * y.x;
+    for (int i = 0; i < 4; ++i) {
+      const float2 x0 = {xg[i].x, xg[i].y}, x1 = {xg[i].z, xg[i].w};
+      const float2 y0 = {yg[i].x, yg[i].y}, y1 = {yg[i].z, yg[i].w};
+      pre[2 * i] = x0.x * y0.x + x0.y * y0.y;
+      pim[2 * i] = x0.x * y0.y - x0.y * y0.x;
+      pre[2 * i + 1] = x1.x * y1.x + x1.y * y1.y;
+      pim[2 * i + 1] = x1.x * y1.y - x1.y * y1.x;
     }
     if constexpr (BF16) {
       bf16x8 bre_hi, bre_lo, bim_hi, bim_lo;
@@ -201,39 +286,47 @@ __global__ void __launch_bounds__(256) k_bulk(const void* __restrict__ Ahi_,
         bre_lo[i] = (__bf16)(pre[i] - (float)rh);
         bim_lo[i] = (__bf16)(pim[i] - (float)ih);
       }
-      const bf16x8* Ahi = reinterpret_cast<const bf16x8*>(Ahi_);
-      const bf16x8* Alo = reinterpret_cast<const bf16x8*>(Alo_);
+      // three sweeps over the 2*AF independent accumulators, so that no MFMA
+      // waits on the one issued just before it
+      bf16x8 ah[AF], al[AF];
 #pragma unroll
       for (int f = 0; f < AF; ++f) {
-        const size_t fi = ((size_t)(rb0 + f) * ntb + tb) * 64 + lane;
-        const bf16x8 ah = Ahi[fi], al = Alo[fi];
-        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bre_hi, acc[f][0], 0, 0, 0);
-        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bim_hi, acc[f][1], 0, 0, 0);
-        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bre_lo, acc[f][0], 0, 0, 0);
-        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bim_lo, acc[f][1], 0, 0, 0);
-        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bre_hi, acc[f][0], 0, 0, 0);
-        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bim_hi, acc[f][1], 0, 0, 0);
+        ah[f] = __builtin_bit_cast(bf16x8, a0[f]);
+        al[f] = __builtin_bit_cast(bf16x8, a1[f]);
+      }
+#pragma unroll
+      for (int f = 0; f < AF; ++f) {
+        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], bre_hi, acc[f][0], 0, 0, 0);
+        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], bim_hi, acc[f][1], 0, 0, 0);
+      }
+#pragma unroll
+      for (int f = 0; f < AF; ++f) {
+        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], bre_lo, acc[f][0], 0, 0, 0);
+        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], bim_lo, acc[f][1], 0, 0, 0);
+      }
+#pragma unroll
+      for (int f = 0; f < AF; ++f) {
+        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[f], bre_hi, acc[f][0], 0, 0, 0);
+        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[f], bim_hi, acc[f][1], 0, 0, 0);
       }
     } else {
-      const float4* A4 = reinterpret_cast<const float4*>(Ahi_);
+      float av[AF][8];
 #pragma unroll
       for (int f = 0; f < AF; ++f) {
-        const size_t fi = (((size_t)(rb0 + f) * ntb + tb) * 64 + lane) * 2;
-        const float4 a0 = A4[fi], a1 = A4[fi + 1];
-        const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        av[f][0] = a0[f].x; av[f][1] = a0[f].y; av[f][2] = a0[f].z; av[f][3] = a0[f].w;
+        av[f][4] = a1[f].x; av[f][5] = a1[f].y; av[f][6] = a1[f].z; av[f][7] = a1[f].w;
+      }
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], pre[s], acc[f][0], 0, 0, 0);
-          acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], pim[s], acc[f][1], 0, 0, 0);
+      for (int s = 0; s < 8; ++s) {
+#pragma unroll
+        for (int f = 0; f < AF; ++f) {
+          acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[f][s], pre[s], acc[f][0], 0, 0, 0);
+          acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[f][s], pim[s], acc[f][1], 0, 0, 0);
         }
       }
     }
-    float4* dst = slab + ((st + 1) & 1) * slab_f4;
-#pragma unroll
-    for (int u = 0; u < MAXF4; ++u) {
-      const int i = threadIdx.x + u * 256;
-      if (more && i < slab_f4) dst[i] = nxt[u];
-    }
+    __builtin_amdgcn_sched_barrier(0);  // issue every MFMA of the step before waiting
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's LDS copies landed
     __syncthreads();
   }
 
@@ -245,7 +338,7 @@ __global__ void __launch_bounds__(256) k_bulk(const void* __restrict__ Ahi_,
       const int row = (rb0 + f) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
 #pragma unroll
       for (int ri = 0; ri < 2; ++ri) {
-        const size_t o = (((size_t)blockIdx.z * g.n_rowsp + row) * 2 + ri) * g.n_bulkp + b;
+        const size_t o = (((size_t)bk.z * g.n_rowsp + row) * 2 + ri) * g.n_bulkp + b;
         C[o] = acc[f][ri][r];
       }
     }
@@ -255,101 +348,107 @@ __global__ void __launch_bounds__(256) k_bulk(const void* __restrict__ Ahi_,
 template <bool BF16, int AF>
 void launch_bulk_t(const void* Ahi, const void* Alo, const float* R32, const int* pairs,
                    const Chi0Geom& g, float* C, hipStream_t st) {
-  const dim3 grid(g.n_bulkp / 128, g.n_rowsp / (32 * AF), g.ksplit);
-  const size_t lds = 2 * (size_t)g.n_g * KSTEP * 8;
-  const int f4 = (g.n_g * KSTEP * 2 / 4 + 255) / 256;
-  if (f4 <= 4)
-    hipLaunchKernelGGL((k_bulk<BF16, AF, 4>), grid, dim3(256), lds, st, Ahi, Alo, R32, pairs, g, C);
-  else if (f4 <= 8)
-    hipLaunchKernelGGL((k_bulk<BF16, AF, 8>), grid, dim3(256), lds, st, Ahi, Alo, R32, pairs, g, C);
+  const dim3 grid((g.n_bulkp / 128) * (g.n_rowsp / (32 * AF)) * g.ksplit);
+  const int nrc = (g.n_g * SLAB_LD4 + 63) / 64;
+  const size_t lds = 2 * sizeof(float4) * ((size_t)nrc * 64 + 2 * AF * 64);
+  const int rpw = (nrc + 3) / 4;  // R chunks per wave
+  const float4* ah = static_cast<const float4*>(Ahi);
+  const float4* al = static_cast<const float4*>(Alo);
+  const float4* r = reinterpret_cast<const float4*>(R32);
+  if (rpw <= 1)
+    hipLaunchKernelGGL((k_bulk<BF16, AF, 1>), grid, dim3(256), lds, st, ah, al, r, pairs, g, C);
+  else if (rpw <= 4)
+    hipLaunchKernelGGL((k_bulk<BF16, AF, 4>), grid, dim3(256), lds, st, ah, al, r, pairs, g, C);
+  else if (rpw <= 9)
+    hipLaunchKernelGGL((k_bulk<BF16, AF, 9>), grid, dim3(256), lds, st, ah, al, r, pairs, g, C);
   else
-    hipLaunchKernelGGL((k_bulk<BF16, AF, 24>), grid, dim3(256), lds, st, Ahi, Alo, R32, pairs, g, C);
+    hipLaunchKernelGGL((k_bulk<BF16, AF, 17>), grid, dim3(256), lds, st, ah, al, r, pairs, g, C);
 }
 
 // ---------------------------------------------------------------------------
-// FP64 pairs (head/wings, or every pair for the FP64 path).  Block = 256
-// threads = 8 frequency groups (4 w each) x 32 pair groups (4 pairs each);
-// grid = (pair tiles of 128, frequency tiles of 32, K splits).  Per chunk of
-// TC transitions the weights of the block's 32 frequencies and R[g][t] for all
-// G are staged in LDS.
+// FP64 pairs on FP64 MFMA (v_mfma_f64_16x16x4f64): the head and wings (pairs
+// (0, G')) or, for the FP64 path, every pair.  Real GEMM
+//     out[row][col] = sum_t W[row][t] P[t][col],
+// rows (Re W(w_j), Im W(w_j)), columns (Re P, Im P) of the pair-slot table.
+// Block = 4 waves = 64 rows x (NCF*16) columns; wave w owns row fragment w and
+// all NCF column fragments.  Per chunk of KC transitions the block computes W
+// (FP64 reciprocal) and P = R(G)^* R(G') once into LDS.  grid = (column tiles,
+// row tiles, K splits); out = [split][n_rowsp][n_colp] partial sums.
+// Lane layouts: A 16x4, lane l holds A[l%16][l/16]; B 4x16, lane l holds
+// B[l/16][l%16]; D 16x16, lane l holds D[4v + l/16][l%16], v = 0..3.
 // ---------------------------------------------------------------------------
-__device__ inline int pair_flat0(int G, int n_g) { return G * n_g - G * (G - 1) / 2; }
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int KC = 32;          // transitions per LDS chunk
+constexpr int NCF = 15;         // column fragments per block
+constexpr int COLS64 = NCF * 16;
+constexpr int SW_LD = KC + 1;   // padded LDS strides (bank spread)
+constexpr int SP_LD = COLS64 + 1;
 
-__global__ void __launch_bounds__(256) k_pairs_f64(const cplx* __restrict__ R, size_t ldt,
-                                                   const double* __restrict__ w,
-                                                   const double* __restrict__ dt, double eta,
-                                                   int n_w, int n_t, int n_g, int pa, int n_pl,
-                                                   int tc, int chunk, double* __restrict__ XY) {
-  extern __shared__ cplx sm[];
-  cplx* sW = sm;              // [32][tc]
-  cplx* sR = sm + 32 * tc;    // [n_g][tc]
-  const int wg = threadIdx.x >> 5, pg = threadIdx.x & 31;
-  const int j0 = blockIdx.y * 32 + wg * 4;
-  int Gs[4], Gps[4];
-  bool ok[4];
+__global__ void __launch_bounds__(256) k_pairs_mfma64(const cplx* __restrict__ R, size_t ldt,
+                                                      const double* __restrict__ w,
+                                                      const double* __restrict__ dt, double eta,
+                                                      int n_w, int n_t,
+                                                      const int* __restrict__ pairs, int n_ps,
+                                                      int chunk_t, int n_rowsp, int n_colp,
+                                                      double* __restrict__ out) {
+  __shared__ double sW[64 * SW_LD];
+  __shared__ double sP[KC * SP_LD];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const Blk3 bk = xcd_block(n_colp / COLS64, n_rowsp / 64, gridDim.x / ((n_colp / COLS64) * (n_rowsp / 64)));
+  const int row0 = bk.y * 64;                 // first row of the block
+  const int j0 = row0 / 2;                    // first frequency
+  const int c0 = bk.x * COLS64;               // first column of the block
+  const int ps0 = c0 / 2;                     // first pair slot
+  f64x4 acc[NCF];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int pl = blockIdx.x * 128 + pg * 4 + u;
-    ok[u] = pl < n_pl;
-    int p = pa + (ok[u] ? pl : 0);
-    int G = 0;
-    while (G + 1 < n_g && pair_flat0(G + 1, n_g) <= p) ++G;
-    Gs[u] = G;
-    Gps[u] = G + (p - pair_flat0(G, n_g));
-  }
-  double acc[4][4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][u][c] = 0.0;
+  for (int c = 0; c < NCF; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  const int t_begin = blockIdx.z * chunk;
-  const int t_end = min(n_t, t_begin + chunk);
-  for (int t0 = t_begin; t0 < t_end; t0 += tc) {
-    const int tn = min(tc, t_end - t0);
+  const int t_begin = bk.z * chunk_t;
+  const int t_end = min(n_t, t_begin + chunk_t);
+  for (int t0 = t_begin; t0 < t_end; t0 += KC) {
     __syncthreads();
-    for (int i = threadIdx.x; i < 32 * tc; i += 256) {
-      const int jj = i / tc, tt = i % tc;
-      sW[i] = (tt < tn) ? weight(w, dt, eta, blockIdx.y * 32 + jj, t0 + tt, n_w, n_t)
-                        : cplx{0.0, 0.0};
+    // W for 32 frequencies x KC transitions (zero outside the ranges)
+    for (int i = threadIdx.x; i < 32 * KC; i += 256) {
+      const int jj = i / KC, tt = i % KC;
+      const int t = t0 + tt;
+      const cplx W = (t < t_end) ? weight(w, dt, eta, j0 + jj, t, n_w, n_t) : cplx{0.0, 0.0};
+      sW[(2 * jj) * SW_LD + tt] = W.re;
+      sW[(2 * jj + 1) * SW_LD + tt] = W.im;
     }
-    for (int i = threadIdx.x; i < n_g * tc; i += 256) {
-      const int gg = i / tc, tt = i % tc;
-      sR[i] = (tt < tn) ? R[(size_t)gg * ldt + t0 + tt] : cplx{0.0, 0.0};
+    // P for KC transitions x COLS64/2 pair slots; consecutive threads walk t
+    for (int i = threadIdx.x; i < KC * (COLS64 / 2); i += 256) {
+      const int tt = i % KC, pp = i / KC;
+      const int t = t0 + tt, ps = ps0 + pp;
+      double re = 0.0, im = 0.0;
+      if (t < t_end && ps < n_ps) {
+        const int pk = pairs[ps];
+        const cplx a = R[(size_t)(pk & 0xffff) * ldt + t];
+        const cplx b = R[(size_t)(pk >> 16) * ldt + t];
+        re = a.re * b.re + a.im * b.im;
+        im = a.re * b.im - a.im * b.re;
+      }
+      sP[tt * SP_LD + 2 * pp] = re;
+      sP[tt * SP_LD + 2 * pp + 1] = im;
     }
     __syncthreads();
-    for (int tt = 0; tt < tn; ++tt) {
-      cplx P[4];
+#pragma unroll 2
+    for (int s = 0; s < KC / 4; ++s) {
+      const int k = 4 * s + (lane >> 4);
+      const double a = sW[(16 * wave + (lane & 15)) * SW_LD + k];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) P[u] = cmulc(sR[Gs[u] * tc + tt], sR[Gps[u] * tc + tt]);
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const cplx W = sW[(wg * 4 + a) * tc + tt];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          acc[a][u][0] += W.re * P[u].re;
-          acc[a][u][1] += W.re * P[u].im;
-          acc[a][u][2] += W.im * P[u].re;
-          acc[a][u][3] += W.im * P[u].im;
-        }
+      for (int c = 0; c < NCF; ++c) {
+        const double b = sP[k * SP_LD + 16 * c + (lane & 15)];
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
       }
     }
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int j = j0 + a;
-    if (j >= n_w) continue;
+  for (int c = 0; c < NCF; ++c) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (!ok[u]) continue;
-      const int pl = blockIdx.x * 128 + pg * 4 + u;
-      double* o = XY + (((size_t)blockIdx.z * n_w + j) * n_pl + pl) * 4;
-      o[0] = acc[a][u][0];
-      o[1] = acc[a][u][1];
-      o[2] = acc[a][u][2];
-      o[3] = acc[a][u][3];
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + 16 * wave + 4 * v + (lane >> 4);
+      const int col = c0 + 16 * c + (lane & 15);
+      out[((size_t)bk.z * n_rowsp + row) * n_colp + col] = acc[c][v];
     }
   }
 }
@@ -406,25 +505,27 @@ void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32
     launch_bulk_t<true, 4>(Ahi, Alo, R32, pairs, g, C, st);
 }
 
-size_t pairs_f64_tc(int n_g) {
-  size_t tc = 65536 / (16 * (size_t)(n_g + 32));
-  if (tc > 64) tc = 64;
-  if (tc < 1) tc = 1;
-  return tc;
+void launch_pairs_f64(const cplx* R, size_t ldt, const double* w, const double* dt, double eta,
+                      const Geom64& g, const int* pairs, double* out, hipStream_t st) {
+  const dim3 grid((g.n_colp / COLS64) * (g.n_rowsp / 64) * g.ksplit);
+  hipLaunchKernelGGL(k_pairs_mfma64, grid, dim3(256), 0, st, R, ldt, w, dt, eta, g.n_w, g.n_t,
+                     pairs, g.n_ps, g.chunk_t, g.n_rowsp, g.n_colp, out);
 }
 
-void launch_pairs_f64(const cplx* R, size_t ldt, const double* w, const double* dt, double eta,
-                      int n_w, int n_t, int n_g, int ga, int gb, int ksplit, double* XY,
-                      hipStream_t st) {
-  auto flat0 = [n_g](int G) { return G * n_g - G * (G - 1) / 2; };
-  const int pa = flat0(ga);
-  const int n_pl = (gb >= n_g ? n_g * (n_g + 1) / 2 : flat0(gb)) - pa;
-  const int tc = (int)pairs_f64_tc(n_g);
-  const int chunk = (n_t + ksplit - 1) / ksplit;
-  const size_t lds = sizeof(cplx) * (size_t)tc * (32 + n_g);
-  const dim3 grid((n_pl + 127) / 128, (n_w + 31) / 32, ksplit);
-  hipLaunchKernelGGL(k_pairs_f64, grid, dim3(256), lds, st, R, ldt, w, dt, eta, n_w, n_t, n_g, pa,
-                     n_pl, tc, chunk, XY);
+void geom64_init(Geom64& g, int n_w, int n_t, int n_ps, size_t max_bytes) {
+  g.n_w = n_w;
+  g.n_t = n_t;
+  g.n_ps = n_ps;
+  g.n_rowsp = (2 * n_w + 63) / 64 * 64;
+  g.n_colp = (2 * n_ps + COLS64 - 1) / COLS64 * COLS64;
+  const int blocks = (g.n_colp / COLS64) * (g.n_rowsp / 64);
+  const int chunks = (n_t + KC - 1) / KC;
+  int ks = 1;
+  while (ks < 128 && blocks * ks < 2048 && chunks / (2 * ks) >= 4 &&
+         (size_t)(2 * ks) * g.n_rowsp * g.n_colp * sizeof(double) <= max_bytes)
+    ks *= 2;
+  g.ksplit = ks;
+  g.chunk_t = (chunks + ks - 1) / ks * KC;
 }
 
 }  // namespace qcx

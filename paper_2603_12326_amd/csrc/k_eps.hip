@@ -32,11 +32,12 @@ __global__ void k_assemble(AsmArgs a, Chi0Geom g, int mode, cplx* __restrict__ o
   double Xr = 0.0, Xi = 0.0, Yr = 0.0, Yi = 0.0;
   if (p < a.n_pairs64) {
     for (int ks = 0; ks < a.ks64; ++ks) {
-      const double* x = a.XY + (((size_t)ks * g.n_w + j) * a.n_pairs64 + p) * 4;
-      Xr += x[0];
-      Xi += x[1];
-      Yr += x[2];
-      Yi += x[3];
+      const double* x0 = a.XY + ((size_t)ks * a.n_rowsp64 + 2 * j) * a.n_colp64 + 2 * p;
+      const double* x1 = x0 + a.n_colp64;
+      Xr += x0[0];
+      Xi += x0[1];
+      Yr += x1[0];
+      Yi += x1[1];
     }
   } else {
     const int b = p - g.p0;
@@ -70,16 +71,20 @@ __device__ inline cplx cinv(cplx a) {
   return {a.re * d, -a.im * d};
 }
 
-// Register-resident Gauss-Jordan for n <= 16*RP and n <= 32*CP.  512 threads:
-// thread (tr, tc) = (tid / 32, tid % 32) owns rows tr + 16 a and columns
-// tc + 32 b.  Three barriers per elimination step.
+// Register-resident Gauss-Jordan for n <= 32*RP and n <= 32*CP.  1024 threads:
+// thread (tr, tc) = (tid / 32, tid % 32) owns rows tr + 32 a and columns
+// tc + 32 b.  Step k (column block kb = k / 32 known at compile time) picks the
+// pivot row p among unused rows, publishes column k and row p through LDS and
+// applies the uniform rank-1 update m <- m0 - u w^T, where m0 is m with column
+// k replaced by e_p, u = column k with u_p = piv - 1 and w = row p / piv with
+// w_k = 1 / piv.  Three barriers per step.
 template <int RP, int CP>
-__global__ void __launch_bounds__(512) k_gj_reg(const cplx* __restrict__ eps, int n,
-                                                cplx* __restrict__ diag, int* sing) {
-  __shared__ cplx colk[16 * RP], rowp[32 * CP];
-  __shared__ int used[16 * RP], piv[16 * RP], sor[16 * RP];
-  __shared__ double redv[16];
-  __shared__ int redi[16];
+__global__ void __launch_bounds__(1024) k_gj_reg(const cplx* __restrict__ eps, int n,
+                                                 cplx* __restrict__ diag, int* sing) {
+  __shared__ cplx colk[32 * RP], rowp[32 * CP];
+  __shared__ int used[32 * RP], piv[32 * RP], sor[32 * RP];
+  __shared__ double redv[32];
+  __shared__ int redi[32];
   __shared__ int pivrow;
   const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
   const cplx* A = eps + (size_t)blockIdx.x * n * n;
@@ -88,100 +93,104 @@ __global__ void __launch_bounds__(512) k_gj_reg(const cplx* __restrict__ eps, in
   for (int a = 0; a < RP; ++a)
 #pragma unroll
     for (int b = 0; b < CP; ++b) {
-      const int i = tr + 16 * a, j = tc + 32 * b;
+      const int i = tr + 32 * a, j = tc + 32 * b;
       m[a][b] = (i < n && j < n) ? A[(size_t)i * n + j] : cplx{0.0, 0.0};
     }
-  for (int i = threadIdx.x; i < 16 * RP; i += 512) used[i] = 0;
+  for (int i = threadIdx.x; i < 32 * RP; i += 1024) used[i] = 0;
   bool singular = false;
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const int kb = k >> 5;
-    if (tc == (k & 31)) {
-      double best = -1.0;
-      int bi = INT_MAX;
 #pragma unroll
-      for (int a = 0; a < RP; ++a) {
-        const int i = tr + 16 * a;
-        cplx v = {0.0, 0.0};
+  for (int kb = 0; kb < CP; ++kb) {
+    for (int kk = 0; kk < 32; ++kk) {
+      const int k = 32 * kb + kk;
+      if (k >= n) break;
+      // pivot search over column k by its 32 owners (one per row group)
+      if (tc == kk) {
+        double best = -1.0;
+        int bi = INT_MAX;
 #pragma unroll
-        for (int b = 0; b < CP; ++b)
-          if (b == kb) v = m[a][b];
-        if (i < n && !used[i]) {
-          double mag = fabs(v.re) + fabs(v.im);
-          if (mag != mag) mag = INFINITY;  // a NaN entry still selects a row
-          if (mag > best) {
-            best = mag;
-            bi = i;
+        for (int a = 0; a < RP; ++a) {
+          const int i = tr + 32 * a;
+          if (i < n && !used[i]) {
+            double mag = fabs(m[a][kb].re) + fabs(m[a][kb].im);
+            if (mag != mag) mag = INFINITY;  // a NaN entry still selects a row
+            if (mag > best) {
+              best = mag;
+              bi = i;
+            }
           }
         }
+        redv[tr] = best;
+        redi[tr] = bi;
       }
-      redv[tr] = best;
-      redi[tr] = bi;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double best = -1.0;
-      int bi = INT_MAX;
-      for (int r = 0; r < 16; ++r) {
-        if (redi[r] == INT_MAX) continue;
-        if (bi == INT_MAX || redv[r] > best || (redv[r] == best && redi[r] < bi)) {
-          best = redv[r];
-          bi = redi[r];
+      __syncthreads();
+      if (threadIdx.x < 64) {  // wave 0 reduces the 32 candidates by shuffles
+        double best = -1.0;
+        int bi = INT_MAX;
+        if (threadIdx.x < 32) {
+          best = redv[threadIdx.x];
+          bi = redi[threadIdx.x];
+        }
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) {
+          const double ov = __shfl_xor(best, off, 32);
+          const int oi = __shfl_xor(bi, off, 32);
+          if (oi != INT_MAX && (bi == INT_MAX || ov > best || (ov == best && oi < bi))) {
+            best = ov;
+            bi = oi;
+          }
+        }
+        if (threadIdx.x == 0) {
+          if (bi == INT_MAX) bi = 0;  // unreachable: some row is always unused
+          pivrow = bi;
+          used[bi] = 1;
+          piv[k] = bi;
+          sor[bi] = k;
         }
       }
-      if (bi == INT_MAX) bi = 0;  // unreachable: some row is always unused
-      pivrow = bi;
-      used[bi] = 1;
-      piv[k] = bi;
-      sor[bi] = k;
-    }
-    __syncthreads();
-    const int p = pivrow;
-    const int pa = p >> 4;
-    if (tc == (k & 31)) {
+      __syncthreads();
+      const int p = pivrow;
+      // publish row p (before column k is overwritten: one thread may own both)
+      if (tr == (p & 31)) {
+        const int pa = p >> 5;
 #pragma unroll
-      for (int a = 0; a < RP; ++a) {
-        const int i = tr + 16 * a;
+        for (int b = 0; b < CP; ++b) {
+          const int j = tc + 32 * b;
+          cplx v = m[0][b];
 #pragma unroll
-        for (int b = 0; b < CP; ++b)
-          if (b == kb && i < n) colk[i] = m[a][b];
+          for (int a = 1; a < RP; ++a)
+            if (a == pa) v = m[a][b];
+          if (j < n) rowp[j] = v;
+        }
       }
-    }
-    if (tr == (p & 15)) {
+      if (tc == kk) {
+#pragma unroll
+        for (int a = 0; a < RP; ++a) {
+          const int i = tr + 32 * a;
+          if (i < n) colk[i] = m[a][kb];
+          m[a][kb] = {i == p ? 1.0 : 0.0, 0.0};
+        }
+      }
+      __syncthreads();
+      const cplx pv = rowp[k];
+      if (pv.re == 0.0 && pv.im == 0.0) singular = true;
+      const cplx inv = cinv(pv);
+      cplx wv[CP];
 #pragma unroll
       for (int b = 0; b < CP; ++b) {
         const int j = tc + 32 * b;
-#pragma unroll
-        for (int a = 0; a < RP; ++a)
-          if (a == pa && j < n) rowp[j] = m[a][b];
+        wv[b] = (j < n) ? cmul(rowp[j], inv) : cplx{0.0, 0.0};
       }
-    }
-    __syncthreads();
-    const cplx pv = rowp[k];
-    if (pv.re == 0.0 && pv.im == 0.0) singular = true;
-    const cplx inv = cinv(pv);
+      if (tc == kk) wv[kb] = inv;
 #pragma unroll
-    for (int a = 0; a < RP; ++a) {
-      const int i = tr + 16 * a;
-      if (i >= n) continue;
-      if (i == p) {
+      for (int a = 0; a < RP; ++a) {
+        const int i = tr + 32 * a;
+        cplx u = (i < n) ? colk[i] : cplx{0.0, 0.0};
+        if (i == p) u.re -= 1.0;
 #pragma unroll
         for (int b = 0; b < CP; ++b) {
-          const int j = tc + 32 * b;
-          m[a][b] = (j == k) ? inv : cmul(m[a][b], inv);
-        }
-      } else {
-        const cplx f = cmul(colk[i], inv);
-#pragma unroll
-        for (int b = 0; b < CP; ++b) {
-          const int j = tc + 32 * b;
-          if (j == k) {
-            m[a][b] = {-f.re, -f.im};
-          } else if (j < n) {
-            const cplx r = rowp[j];
-            m[a][b].re -= f.re * r.re - f.im * r.im;
-            m[a][b].im -= f.re * r.im + f.im * r.re;
-          }
+          m[a][b].re -= u.re * wv[b].re - u.im * wv[b].im;
+          m[a][b].im -= u.re * wv[b].im + u.im * wv[b].re;
         }
       }
     }
@@ -190,12 +199,14 @@ __global__ void __launch_bounds__(512) k_gj_reg(const cplx* __restrict__ eps, in
   // [eps^-1]_kk = B[piv[k]][sor[k]]
   for (int k = 0; k < n; ++k) {
     const int i = piv[k], j = sor[k];
-    if ((i & 15) == tr && (j & 31) == tc) {
+    if ((i & 31) == tr && (j & 31) == tc) {
+      cplx v = {0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < RP; ++a)
 #pragma unroll
         for (int b = 0; b < CP; ++b)
-          if (a == (i >> 4) && b == (j >> 5)) diag[(size_t)blockIdx.x * n + k] = m[a][b];
+          if (a == (i >> 5) && b == (j >> 5)) v = m[a][b];
+      diag[(size_t)blockIdx.x * n + k] = v;
     }
   }
   if (singular && threadIdx.x == 0) atomicMin(sing, (int)blockIdx.x);
@@ -322,9 +333,9 @@ void launch_chi0_export(const AsmArgs& a, const Chi0Geom& g, cplx* chi, hipStrea
 
 void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st) {
   if (n_g <= 64)
-    hipLaunchKernelGGL((k_gj_reg<4, 2>), dim3(n_w), dim3(512), 0, st, eps, n_g, diag, sing);
+    hipLaunchKernelGGL((k_gj_reg<2, 2>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
   else if (n_g <= 128)
-    hipLaunchKernelGGL((k_gj_reg<8, 4>), dim3(n_w), dim3(512), 0, st, eps, n_g, diag, sing);
+    hipLaunchKernelGGL((k_gj_reg<4, 4>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
   else {
     const size_t lds = (size_t)n_g * (2 * sizeof(cplx) + 3 * sizeof(int));
     hipLaunchKernelGGL(k_gj_global, dim3(n_w), dim3(256), lds, st, eps, n_g, diag, sing);

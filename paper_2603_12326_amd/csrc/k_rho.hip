@@ -240,34 +240,33 @@ __global__ void k_bloch_phase(const double* kf, int n_k, double s0, double s1, d
 }
 
 // M[k][e] = sum_T ph[k0+k][T] F[T][e] for the n_q*n_ao^2 elements e.
-// Each thread keeps its n_t lattice terms in registers (n_t <= 27) and walks
-// over the k chunk; the phases of a k are broadcast from LDS.
+// grid = (element tiles of 256, k chunks of kch): each thread keeps its n_t
+// lattice terms in registers (n_t <= 27) and walks its k chunk; the phases of
+// the chunk are broadcast from LDS.  Consecutive threads write consecutive e.
 template <int NT>
 __global__ void __launch_bounds__(256) k_phase_sum(const cplx* __restrict__ F,
                                                    const cplx* __restrict__ ph, long n_el,
-                                                   int k0, int nk, cplx* __restrict__ M) {
-  __shared__ cplx sph[64 * NT];
+                                                   int k0, int nk, int kch,
+                                                   cplx* __restrict__ M) {
+  extern __shared__ cplx sph[];  // [kch][NT]
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int kb = blockIdx.y * kch;
+  const int kn = min(kch, nk - kb);
+  for (int i = threadIdx.x; i < kn * NT; i += blockDim.x) sph[i] = ph[(size_t)(k0 + kb) * NT + i];
+  __syncthreads();
+  if (e >= n_el) return;
   cplx f[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) f[t] = (e < n_el) ? F[(size_t)t * n_el + e] : cplx{0.0, 0.0};
-  for (int kb = 0; kb < nk; kb += 64) {
-    const int kn = min(64, nk - kb);
-    __syncthreads();
-    for (int i = threadIdx.x; i < kn * NT; i += blockDim.x) sph[i] = ph[(size_t)(k0 + kb) * NT + i];
-    __syncthreads();
-    if (e < n_el) {
-      for (int kk = 0; kk < kn; ++kk) {
-        double re = 0.0, im = 0.0;
+  for (int t = 0; t < NT; ++t) f[t] = F[(size_t)t * n_el + e];
+  for (int kk = 0; kk < kn; ++kk) {
+    double re = 0.0, im = 0.0;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const cplx p = sph[kk * NT + t];
-          re += p.re * f[t].re - p.im * f[t].im;
-          im += p.re * f[t].im + p.im * f[t].re;
-        }
-        M[(size_t)(kb + kk) * n_el + e] = {re, im};
-      }
+    for (int t = 0; t < NT; ++t) {
+      const cplx p = sph[kk * NT + t];
+      re += p.re * f[t].re - p.im * f[t].im;
+      im += p.re * f[t].im + p.im * f[t].re;
     }
+    M[(size_t)(kb + kk) * n_el + e] = {re, im};
   }
 }
 
@@ -416,13 +415,22 @@ void launch_bloch_phase(const double* k_frac, int n_k, const double shift[3], co
 void launch_phase_sum(const cplx* F, const cplx* ph, int n_t, int n_q, int n_e, int k0, int nk,
                       cplx* M, hipStream_t st) {
   const long n_el = (long)n_q * n_e;
-  const dim3 grid((unsigned)((n_el + 255) / 256));
-  if (n_t == 27)
-    hipLaunchKernelGGL(k_phase_sum<27>, grid, dim3(256), 0, st, F, ph, n_el, k0, nk, M);
-  else if (n_t == 1)
-    hipLaunchKernelGGL(k_phase_sum<1>, grid, dim3(256), 0, st, F, ph, n_el, k0, nk, M);
-  else
-    hipLaunchKernelGGL(k_phase_sum_any, grid, dim3(256), 0, st, F, ph, n_t, n_el, k0, nk, M);
+  const long etiles = (n_el + 255) / 256;
+  if (n_t == 27 || n_t == 1) {
+    // k chunk: enough blocks to fill the device, at most 64 k per thread
+    long kch = (etiles * nk + 1023) / 1024;
+    kch = kch < 4 ? 4 : (kch > 64 ? 64 : kch);
+    if (kch > nk) kch = nk;
+    const dim3 grid((unsigned)etiles, (unsigned)((nk + kch - 1) / kch));
+    const size_t lds = sizeof(cplx) * kch * n_t;
+    if (n_t == 27)
+      hipLaunchKernelGGL(k_phase_sum<27>, grid, dim3(256), lds, st, F, ph, n_el, k0, nk, (int)kch, M);
+    else
+      hipLaunchKernelGGL(k_phase_sum<1>, grid, dim3(256), lds, st, F, ph, n_el, k0, nk, (int)kch, M);
+  } else {
+    hipLaunchKernelGGL(k_phase_sum_any, dim3((unsigned)etiles), dim3(256), 0, st, F, ph, n_t, n_el,
+                       k0, nk, M);
+  }
 }
 
 size_t band_contract_lds(int n_ao, int n_b, int /*n_occ*/) {

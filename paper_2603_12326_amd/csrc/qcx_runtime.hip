@@ -46,7 +46,8 @@ struct qcx_ctx {
   double eta = 0.0;
   Chi0Geom geom{};
   int ks64 = 1, n_pairs64 = 0;
-  DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_C, d_XY;
+  Geom64 geom64{};
+  DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_pairs64, d_C, d_XY;
 
   // eps
   bool have_eps = false;
@@ -74,7 +75,7 @@ struct qcx_ctx {
     DevBuf* all[] = {&d_sh_l, &d_sh_ex, &d_sh_ctr, &d_sh_off, &d_cells, &d_tvec, &d_kf,
                      &d_Ck,   &d_Ek,    &d_Ckq,    &d_Ekq,    &d_dt,    &d_ph,   &d_phq,
                      &d_S,    &d_F0,    &d_dev,    &d_Q,      &d_vq,    &d_F,    &d_M,
-                     &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_C,
+                     &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_pairs64, &d_C,
                      &d_XY,   &d_eps,   &d_diag,   &d_epsM,   &d_loss,  &d_sing};
     for (DevBuf* b : all) b->release();
     for (const Span& sp : spans) {
@@ -564,8 +565,8 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
   if (!(eta_eV >= 0.0) || !std::isfinite(eta_eV)) return fail(ctx, QCX_EINVAL, "eta must be >= 0");
   if (precision < QCX_FP64 || precision > QCX_SPLIT_BF16)
     return fail(ctx, QCX_EINVAL, "bad precision");
-  if (precision != QCX_FP64 && 2 * (size_t)ctx->n_g * 16 * 8 > 160 * 1024)
-    return fail(ctx, QCX_EINVAL, "the MFMA bulk path is limited to n_G <= 640");
+  if (precision != QCX_FP64 && ctx->n_g > 480)
+    return fail(ctx, QCX_EINVAL, "the MFMA bulk path is limited to n_G <= 480");
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_chi0 = ctx->have_eps = false;
   hipStream_t st = ctx->stream;
@@ -646,17 +647,20 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
     g.n_tp = (int)roundup(g.n_t, 16);
   }
   if (ctx->n_pairs64 > 0) {
-    const int pt = (ctx->n_pairs64 + 127) / 128, wt = (n_w + 31) / 32;
-    int ks = 1;
-    while (ks < 64 && pt * wt * ks < 1024 && ctx->n_t / (2 * ks) >= 256 &&
-           (size_t)(2 * ks) * n_w * ctx->n_pairs64 * 32 <= ((size_t)1 << 30))
-      ks *= 2;
-    ctx->ks64 = ks;
-    HIPCK(ctx->d_XY.reserve(sizeof(double) * 4 * (size_t)ks * n_w * ctx->n_pairs64));
-    const int gb = precision == QCX_FP64 ? ctx->n_g : 1;
+    Geom64& g64 = ctx->geom64;
+    geom64_init(g64, n_w, ctx->n_t, ctx->n_pairs64, (size_t)512 << 20);
+    ctx->ks64 = g64.ksplit;
+    std::vector<int> tab(ctx->n_pairs64);
+    {
+      int p = 0;
+      for (int G = 0; G < ctx->n_g && p < ctx->n_pairs64; ++G)
+        for (int Gp = G; Gp < ctx->n_g && p < ctx->n_pairs64; ++Gp, ++p) tab[p] = G | (Gp << 16);
+    }
+    HIPCK(upload(ctx, ctx->d_pairs64, tab.data(), tab.size()));
+    HIPCK(ctx->d_XY.reserve(sizeof(double) * (size_t)g64.ksplit * g64.n_rowsp * g64.n_colp));
     HIPCK(span_begin(ctx, 2, &sp_hw));
     launch_pairs_f64(ctx->d_R.as<cplx>(), ctx->ldt, ctx->d_w.as<double>(), ctx->d_dt.as<double>(),
-                     ctx->eta, n_w, ctx->n_t, ctx->n_g, 0, gb, ks, ctx->d_XY.as<double>(), st);
+                     ctx->eta, g64, ctx->d_pairs64.as<int>(), ctx->d_XY.as<double>(), st);
     LAUNCHCK("pairs_f64");
     HIPCK(span_end(ctx, sp_hw));
   }
@@ -668,6 +672,8 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
     a.XY = ctx->n_pairs64 > 0 ? ctx->d_XY.as<double>() : nullptr;
     a.ks = g.ksplit;
     a.ks64 = ctx->ks64;
+    a.n_rowsp64 = ctx->geom64.n_rowsp;
+    a.n_colp64 = ctx->geom64.n_colp;
     a.n_pairs64 = ctx->n_pairs64;
     a.vq = ctx->d_vq.as<double>();
     a.pref = 2.0 / (ctx->n_k * ctx->vol);
@@ -699,6 +705,8 @@ int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out) {
   a.XY = ctx->n_pairs64 > 0 ? ctx->d_XY.as<double>() : nullptr;
   a.ks = g.ksplit;
   a.ks64 = ctx->ks64;
+  a.n_rowsp64 = ctx->geom64.n_rowsp;
+  a.n_colp64 = ctx->geom64.n_colp;
   a.n_pairs64 = ctx->n_pairs64;
   a.vq = ctx->d_vq.as<double>();
   a.pref = 2.0 / (ctx->n_k * ctx->vol);
