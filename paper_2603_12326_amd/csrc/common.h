@@ -105,11 +105,11 @@ void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32
 // FP64 pairs on FP64 MFMA: out[split][row][col], rows (Re W, Im W) per
 // frequency, columns (Re P, Im P) per pair slot; slot ps holds (G | G' << 16).
 struct Geom64 {
-  int n_w, n_t, n_ps;
+  int n_g, n_w, n_t, n_ps;
   int n_rowsp, n_colp;
   int ksplit, chunk_t;
 };
-void geom64_init(Geom64& g, int n_w, int n_t, int n_ps, size_t max_bytes);
+void geom64_init(Geom64& g, int n_g, int n_w, int n_t, int n_ps, size_t max_bytes);
 void launch_pairs_f64(const cplx* R, size_t ldt, const double* w, const double* dt, double eta,
                       const Geom64& g, const int* pairs, double* out, hipStream_t st);
 // eps assembly (symmetrised Coulomb, prefactor 2/(N_k V))

@@ -384,7 +384,7 @@ constexpr int COLS64 = NCF * 16;
 constexpr int SW_LD = KC + 1;   // padded LDS strides (bank spread)
 constexpr int SP_LD = COLS64 + 1;
 
-__global__ void __launch_bounds__(256) k_pairs_mfma64(const cplx* __restrict__ R, size_t ldt,
+__global__ void __launch_bounds__(256) k_pairs_mfma64_direct(const cplx* __restrict__ R, size_t ldt,
                                                       const double* __restrict__ w,
                                                       const double* __restrict__ dt, double eta,
                                                       int n_w, int n_t,
@@ -453,6 +453,140 @@ __global__ void __launch_bounds__(256) k_pairs_mfma64(const cplx* __restrict__ R
   }
 }
 
+// DMA-staged variant for n_g <= NGC: per chunk of KC8 transitions the R rows
+// of every G are copied global -> LDS (global_load_lds_dwordx4) into one of
+// two named buffers while the MFMAs of the previous chunk run from P and W,
+// which live in other named LDS arrays (so the copies need no wait before
+// those reads).  Two barriers per chunk.
+constexpr int KC8 = 8;
+constexpr int SW8_LD = KC8 + 1;
+
+template <int NGC>
+__device__ inline void pairs64_stage(const cplx* __restrict__ R, size_t ldt, int n_g, int t0,
+                                     float4* buf) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nch = (n_g + 7) / 8;  // 8 rows of 8 transitions per 1 KB chunk
+  for (int c = wave; c < nch; c += 4) {
+    const int row = 8 * c + (lane >> 3);
+    const int rr = row < n_g ? row : 0;
+    const float4* src = reinterpret_cast<const float4*>(R + (size_t)rr * ldt + t0 + (lane & 7));
+    lds_dma16(src, buf + 64 * c);
+  }
+}
+
+template <int NGC>
+__device__ inline void pairs64_chunk(const float4* sRc, double* sW, double* sP,
+                                     const double* __restrict__ w,
+                                     const double* __restrict__ dt, double eta, int n_w,
+                                     int n_t, int j0, int t0, int t_end, const int* G_of,
+                                     const int* Gp_of, int ps0, int n_ps) {
+  // W for 32 frequencies x KC8 transitions
+  {
+    const int jj = threadIdx.x >> 3, tt = threadIdx.x & 7;
+    const int t = t0 + tt;
+    const cplx W = (t < t_end) ? weight(w, dt, eta, j0 + jj, t, n_w, n_t) : cplx{0.0, 0.0};
+    sW[(2 * jj) * SW8_LD + tt] = W.re;
+    sW[(2 * jj + 1) * SW8_LD + tt] = W.im;
+  }
+  // P for KC8 transitions x COLS64/2 pair slots
+  const cplx* R = reinterpret_cast<const cplx*>(sRc);
+  for (int i = threadIdx.x; i < KC8 * (COLS64 / 2); i += 256) {
+    const int tt = i & 7, pp = i >> 3;
+    const int ps = ps0 + pp;
+    double re = 0.0, im = 0.0;
+    if (ps < n_ps && t0 + tt < t_end) {
+      const cplx a = R[G_of[pp] * KC8 + tt];
+      const cplx b = R[Gp_of[pp] * KC8 + tt];
+      re = a.re * b.re + a.im * b.im;
+      im = a.re * b.im - a.im * b.re;
+    }
+    sP[tt * SP_LD + 2 * pp] = re;
+    sP[tt * SP_LD + 2 * pp + 1] = im;
+  }
+}
+
+template <int NGC>
+__global__ void __launch_bounds__(256) k_pairs_mfma64(const cplx* __restrict__ R, size_t ldt,
+                                                      const double* __restrict__ w,
+                                                      const double* __restrict__ dt, double eta,
+                                                      int n_w, int n_t, int n_g,
+                                                      const int* __restrict__ pairs, int n_ps,
+                                                      int chunk_t, int n_rowsp, int n_colp,
+                                                      double* __restrict__ out) {
+  __shared__ float4 sR0[NGC * KC8];  // [g][KC8] complex
+  __shared__ float4 sR1[NGC * KC8];
+  __shared__ double sW[64 * SW8_LD];
+  __shared__ double sP[KC8 * SP_LD];
+  __shared__ int G_of[COLS64 / 2], Gp_of[COLS64 / 2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const Blk3 bk = xcd_block(n_colp / COLS64, n_rowsp / 64,
+                            gridDim.x / ((n_colp / COLS64) * (n_rowsp / 64)));
+  const int row0 = bk.y * 64, j0 = row0 / 2;
+  const int c0 = bk.x * COLS64, ps0 = c0 / 2;
+  for (int i = threadIdx.x; i < COLS64 / 2; i += 256) {
+    const int ps = ps0 + i;
+    const int pk = ps < n_ps ? pairs[ps] : 0;
+    G_of[i] = pk & 0xffff;
+    Gp_of[i] = pk >> 16;
+  }
+  f64x4 acc[NCF];
+#pragma unroll
+  for (int c = 0; c < NCF; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  const int t_begin = bk.z * chunk_t;
+  const int t_end = min(n_t, t_begin + chunk_t);
+  const int nchunk = t_end > t_begin ? (t_end - t_begin + KC8 - 1) / KC8 : 0;
+
+  auto mfma_chunk = [&]() {
+#pragma unroll
+    for (int s = 0; s < KC8 / 4; ++s) {
+      const int k = 4 * s + (lane >> 4);
+      const double a = sW[(16 * wave + (lane & 15)) * SW8_LD + k];
+#pragma unroll
+      for (int c = 0; c < NCF; ++c) {
+        const double b = sP[k * SP_LD + 16 * c + (lane & 15)];
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+      }
+    }
+  };
+
+  if (nchunk > 0) pairs64_stage<NGC>(R, ldt, n_g, t_begin, sR0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int ci = 0; ci < nchunk; ci += 2) {
+    // even chunk: R in sR0, prefetch into sR1
+    {
+      const int t0 = t_begin + ci * KC8;
+      pairs64_chunk<NGC>(sR0, sW, sP, w, dt, eta, n_w, n_t, j0, t0, t_end, G_of, Gp_of, ps0, n_ps);
+      __syncthreads();
+      if (ci + 1 < nchunk) pairs64_stage<NGC>(R, ldt, n_g, t0 + KC8, sR1);
+      mfma_chunk();
+      __builtin_amdgcn_sched_barrier(0);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+    if (ci + 1 < nchunk) {  // odd chunk: R in sR1, prefetch into sR0
+      const int t0 = t_begin + (ci + 1) * KC8;
+      pairs64_chunk<NGC>(sR1, sW, sP, w, dt, eta, n_w, n_t, j0, t0, t_end, G_of, Gp_of, ps0, n_ps);
+      __syncthreads();
+      if (ci + 2 < nchunk) pairs64_stage<NGC>(R, ldt, n_g, t0 + KC8, sR0);
+      mfma_chunk();
+      __builtin_amdgcn_sched_barrier(0);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCF; ++c) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + 16 * wave + 4 * v + (lane >> 4);
+      const int col = c0 + 16 * c + (lane & 15);
+      out[((size_t)bk.z * n_rowsp + row) * n_colp + col] = acc[c][v];
+    }
+  }
+}
+
 }  // namespace
 
 void launch_transition_energies(const double* Ek, const double* Ekq, int n_k, int n_b, int n_occ,
@@ -508,11 +642,19 @@ void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32
 void launch_pairs_f64(const cplx* R, size_t ldt, const double* w, const double* dt, double eta,
                       const Geom64& g, const int* pairs, double* out, hipStream_t st) {
   const dim3 grid((g.n_colp / COLS64) * (g.n_rowsp / 64) * g.ksplit);
-  hipLaunchKernelGGL(k_pairs_mfma64, grid, dim3(256), 0, st, R, ldt, w, dt, eta, g.n_w, g.n_t,
-                     pairs, g.n_ps, g.chunk_t, g.n_rowsp, g.n_colp, out);
+  if (g.n_g <= 128)
+    hipLaunchKernelGGL(k_pairs_mfma64<128>, grid, dim3(256), 0, st, R, ldt, w, dt, eta, g.n_w,
+                       g.n_t, g.n_g, pairs, g.n_ps, g.chunk_t, g.n_rowsp, g.n_colp, out);
+  else if (g.n_g <= 256)
+    hipLaunchKernelGGL(k_pairs_mfma64<256>, grid, dim3(256), 0, st, R, ldt, w, dt, eta, g.n_w,
+                       g.n_t, g.n_g, pairs, g.n_ps, g.chunk_t, g.n_rowsp, g.n_colp, out);
+  else
+    hipLaunchKernelGGL(k_pairs_mfma64_direct, grid, dim3(256), 0, st, R, ldt, w, dt, eta, g.n_w,
+                       g.n_t, pairs, g.n_ps, g.chunk_t, g.n_rowsp, g.n_colp, out);
 }
 
-void geom64_init(Geom64& g, int n_w, int n_t, int n_ps, size_t max_bytes) {
+void geom64_init(Geom64& g, int n_g, int n_w, int n_t, int n_ps, size_t max_bytes) {
+  g.n_g = n_g;
   g.n_w = n_w;
   g.n_t = n_t;
   g.n_ps = n_ps;

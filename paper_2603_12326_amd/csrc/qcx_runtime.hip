@@ -522,7 +522,7 @@ int qcx_pair_density(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out) {
   const int nT = ctx->n_cells, nao = ctx->n_ao;
   const size_t nee = (size_t)nao * nao;
   HIPCK(ctx->d_F.reserve(sizeof(cplx) * nT * (size_t)n_G * nee));
-  ctx->ldt = roundup(ctx->n_t, 256);
+  ctx->ldt = roundup(ctx->n_t + 16, 256);  // zero tail: chunked readers may run past n_t
   HIPCK(ctx->d_R.reserve(sizeof(cplx) * ctx->ldt * n_G));
   HIPCK(hipMemsetAsync(ctx->d_R.p, 0, sizeof(cplx) * ctx->ldt * n_G, st));
   const size_t per_k = sizeof(cplx) * (size_t)n_G * nee;
@@ -648,7 +648,7 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
   }
   if (ctx->n_pairs64 > 0) {
     Geom64& g64 = ctx->geom64;
-    geom64_init(g64, n_w, ctx->n_t, ctx->n_pairs64, (size_t)512 << 20);
+    geom64_init(g64, ctx->n_g, n_w, ctx->n_t, ctx->n_pairs64, (size_t)512 << 20);
     ctx->ks64 = g64.ksplit;
     std::vector<int> tab(ctx->n_pairs64);
     {
