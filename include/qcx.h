@@ -173,6 +173,32 @@ int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out);
  * Errors: QCX_ESTATE (no eps_inv), QCX_EINVAL, QCX_ESINGULAR. */
 int qcx_loss(qcx_ctx* ctx, double* out, int mem);
 
+/* One item of a batch: the frequencies of one context's q point. */
+typedef struct qcx_item {
+  int ctx;              /* index into the context array; its pair densities are used */
+  int n_w;              /* number of frequencies, 1..65536 */
+  const double* w_eV;   /* host [n_w] frequencies (eV) */
+  double eta_eV;        /* broadening (eV), >= 0 */
+  double* loss_out;     /* device [n_w][n_G of that context]: the loss of Eq. (eps_LFE) */
+} qcx_item;
+
+/* Batched chi0 -> eps -> loss for uneven items (different cells, q points,
+ * frequency lists and N_G; Eq. RPA per item).  Every context in ctxs must have
+ * current pair densities (qcx_pair_density) and all must be on one device; the
+ * work is enqueued on the stream of ctxs[0].  The chi0 bulk of all items runs
+ * in one persistent launch over a shared tile list; the FP64 head/wings,
+ * assembly, inversion and loss of every item follow.  The sequence is captured
+ * once per batch signature (items, frequencies, buffers) into a hipGraph owned
+ * by ctxs[0] and replayed on later calls with the same signature; new states
+ * or pair densities of the same shapes are picked up by the replay.
+ *   precision, headwings_fp64, lfe as for qcx_chi0 / qcx_eps_inv.
+ * Asynchronous; qcx_batch_sync(ctxs[0]) waits and reports QCX_ESINGULAR.
+ * Errors: QCX_EINVAL (sizes, devices, NULL loss_out), QCX_ESTATE (a context
+ * without pair densities), QCX_ENOMEM, QCX_EDEVICE. */
+int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_items,
+                  int precision, int headwings_fp64, int lfe);
+int qcx_batch_sync(qcx_ctx* ctx);
+
 /* Per-stage device time of the most recent calls, in milliseconds, measured
  * with HIP events on the context's stream (enabled by qcx_set_timing):
  * t[0] pair_density, t[1] chi0 bulk kernel, t[2] chi0 FP64 head/wings,

@@ -102,6 +102,22 @@ void launch_bulk_f32(const float* Aw, const float* R32, const int* pairs, const 
                      float* C, hipStream_t st);
 void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32,
                       const int* pairs, const Chi0Geom& g, float* C, hipStream_t st);
+// One item of a batched bulk launch (its own weights, R, pairs and partials).
+struct BulkItem {
+  const float4* A;
+  const float4* Alo;
+  const float4* R32;
+  const int* pairs;
+  Chi0Geom g;
+  float* C;
+};
+// Persistent bulk kernel over tiles {item, pair tile, row tile, K split};
+// AF = 4 row fragments; max_ng sizes the LDS.
+void launch_bulk_persistent(bool bf16, const BulkItem* items, const int4* tiles, int n_tiles,
+                            int* counter, int max_ng, int grid, hipStream_t st);
+void launch_set_int(int* p, int v, hipStream_t st);
+constexpr int kBatchAF = 4;
+
 // FP64 pairs on FP64 MFMA: out[split][row][col], rows (Re W, Im W) per
 // frequency, columns (Re P, Im P) per pair slot; slot ps holds (G | G' << 16).
 struct Geom64 {

@@ -1,0 +1,243 @@
+// Internal: the context behind the C ABI and host-side helpers shared by the
+// runtime translation units.
+#pragma once
+
+#include <limits.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace qcx;
+
+namespace qcx {
+struct BatchPlan;
+void destroy_plan(BatchPlan* p);
+}  // namespace qcx
+
+struct qcx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // cell and basis
+  bool have_basis = false;
+  double lat[9], rec[9], vol = 0.0;
+  int n_atoms = 0, n_sh = 0, n_ao = 0, lrange = 1, n_cells = 0;
+  std::vector<int> sh_l, sh_off, cells;
+  std::vector<double> sh_ex, sh_ctr, tvec;
+  DevBuf d_sh_l, d_sh_ex, d_sh_ctr, d_sh_off, d_cells, d_tvec;
+
+  // states
+  bool have_states = false;
+  double q[3] = {0, 0, 0};
+  int n_k = 0, n_occ = 0, n_b = 0, n_c = 0, n_t = 0;
+  DevBuf d_kf, d_Ck, d_Ek, d_Ckq, d_Ekq, d_dt, d_ph, d_phq, d_S, d_F0, d_dev;
+
+  // pair densities
+  bool have_rho = false;
+  int n_g = 0;
+  size_t ldt = 0;
+  DevBuf d_Q, d_vq, d_F, d_M, d_R;
+
+  // chi0
+  bool have_chi0 = false;
+  int n_w = 0, prec = 0, hw64 = 1;
+  double eta = 0.0;
+  Chi0Geom geom{};
+  int ks64 = 1, n_pairs64 = 0;
+  Geom64 geom64{};
+  DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_pairs64, d_C, d_XY;
+
+  // eps
+  bool have_eps = false;
+  DevBuf d_eps, d_diag, d_epsM, d_loss, d_sing;
+
+  // pinned staging for host -> device copies: reset at the start of each
+  // call once the previous call's copies have completed
+  void* stage = nullptr;
+  size_t stage_cap = 0, stage_off = 0;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
+
+  // timing: event pairs recorded on the stream without synchronising,
+  // resolved by qcx_stage_times
+  struct Span {
+    hipEvent_t a, b;
+    int stage;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Span> spans;
+  double t_acc[6] = {0, 0, 0, 0, 0, 0};
+
+  // batch plan owned by the first context of a batch (see qcx_batch.hip)
+  qcx::BatchPlan* plan = nullptr;
+
+  ~qcx_ctx() {
+    if (plan) qcx::destroy_plan(plan);
+    DevBuf* all[] = {&d_sh_l, &d_sh_ex, &d_sh_ctr, &d_sh_off, &d_cells, &d_tvec, &d_kf,
+                     &d_Ck,   &d_Ek,    &d_Ckq,    &d_Ekq,    &d_dt,    &d_ph,   &d_phq,
+                     &d_S,    &d_F0,    &d_dev,    &d_Q,      &d_vq,    &d_F,    &d_M,
+                     &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_pairs64, &d_C,
+                     &d_XY,   &d_eps,   &d_diag,   &d_epsM,   &d_loss,  &d_sing};
+    for (DevBuf* b : all) b->release();
+    for (const Span& sp : spans) {
+      (void)hipEventDestroy(sp.a);
+      (void)hipEventDestroy(sp.b);
+    }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (stage_done) (void)hipEventDestroy(stage_done);
+    if (stage) (void)hipHostFree(stage);
+  }
+};
+
+namespace qcx {
+
+inline int fail(qcx_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCK(call)                                                                   \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? QCX_ENOMEM : QCX_EDEVICE,          \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                 \
+  } while (0)
+
+#define LAUNCHCK(what)                                                                \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, QCX_EDEVICE, std::string("launch ") + what + ": " +            \
+                                        hipGetErrorString(e_));                       \
+  } while (0)
+
+inline size_t roundup(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+constexpr size_t kStageBytes = (size_t)64 << 20;
+
+// Begin a call that stages host data: wait until the copies of the previous
+// call have left the pinned buffer.
+inline hipError_t stage_begin(qcx_ctx* c) {
+  if (!c->stage) {
+    hipError_t e = hipHostMalloc(&c->stage, kStageBytes);
+    if (e != hipSuccess) {
+      c->stage = nullptr;
+      return e;
+    }
+    c->stage_cap = kStageBytes;
+    e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  if (c->stage_pending) {
+    hipError_t e = hipEventSynchronize(c->stage_done);
+    if (e != hipSuccess) return e;
+    c->stage_pending = false;
+  }
+  c->stage_off = 0;
+  return hipSuccess;
+}
+
+// Copy n elements to a context buffer on the context's stream.  Host data goes
+// through the pinned arena (or, if it does not fit, a synchronous copy), so the
+// caller's array may be released as soon as the call returns.
+template <class T>
+inline hipError_t upload(qcx_ctx* c, DevBuf& b, const T* src, size_t n, bool dev_src = false) {
+  const size_t bytes = n * sizeof(T);
+  hipError_t e = b.reserve(bytes + 64);
+  if (e != hipSuccess) return e;
+  if (dev_src) return hipMemcpyAsync(b.p, src, bytes, hipMemcpyDeviceToDevice, c->stream);
+  const size_t off = (c->stage_off + 255) / 256 * 256;
+  if (c->stage && off + bytes <= c->stage_cap) {
+    char* h = static_cast<char*>(c->stage) + off;
+    memcpy(h, src, bytes);
+    c->stage_off = off + bytes;
+    e = hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    // record after every staged copy so that an early error return still
+    // leaves the arena guarded
+    e = hipEventRecord(c->stage_done, c->stream);
+    if (e == hipSuccess) c->stage_pending = true;
+    return e;
+  }
+  e = hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+inline void inv3(const double m[9], double out[9]) {
+  const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5], g = m[6], h = m[7],
+               i = m[8];
+  const double det = a * (e * i - f * h) - b * (d * i - f * g) + c * (d * h - e * g);
+  out[0] = (e * i - f * h) / det;
+  out[1] = (c * h - b * i) / det;
+  out[2] = (b * f - c * e) / det;
+  out[3] = (f * g - d * i) / det;
+  out[4] = (a * i - c * g) / det;
+  out[5] = (c * d - a * f) / det;
+  out[6] = (d * h - e * g) / det;
+  out[7] = (b * g - a * h) / det;
+  out[8] = (a * e - b * d) / det;
+}
+
+inline hipError_t take_event(qcx_ctx* c, hipEvent_t* e) {
+  if (!c->ev_pool.empty()) {
+    *e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Open a timed span for `stage`; returns its index in *idx (or -1 when timing
+// is off).
+inline hipError_t span_begin(qcx_ctx* c, int stage, int* idx) {
+  *idx = -1;
+  if (!c->timing) return hipSuccess;
+  qcx_ctx::Span sp{};
+  hipError_t e = take_event(c, &sp.a);
+  if (e != hipSuccess) return e;
+  e = take_event(c, &sp.b);
+  if (e != hipSuccess) return e;
+  sp.stage = stage;
+  e = hipEventRecord(sp.a, c->stream);
+  if (e != hipSuccess) return e;
+  c->spans.push_back(sp);
+  *idx = (int)c->spans.size() - 1;
+  return hipSuccess;
+}
+
+inline hipError_t span_end(qcx_ctx* c, int idx) {
+  if (idx < 0) return hipSuccess;
+  return hipEventRecord(c->spans[idx].b, c->stream);
+}
+
+// Resolve every recorded span into t_acc (synchronises the stream).
+inline hipError_t spans_resolve(qcx_ctx* c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  for (const qcx_ctx::Span& sp : c->spans) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, sp.a, sp.b);
+    if (e != hipSuccess) return e;
+    c->t_acc[sp.stage] += ms;
+    if (sp.stage == 1) c->t_acc[5] += 1.0;
+    c->ev_pool.push_back(sp.a);
+    c->ev_pool.push_back(sp.b);
+  }
+  c->spans.clear();
+  return hipSuccess;
+}
+
+}  // namespace qcx
+

@@ -167,19 +167,18 @@ __device__ inline void lds_dma16(const float4* src, float4* dst) {
   __builtin_amdgcn_global_load_lds((const void*)src, (lds_ptr_t)dst, 16, 0, 0);
 }
 
+// One block tile of the bulk GEMM: pair tile bk.x, row tile bk.y, K split
+// bk.z, staged through `lds` (2 buffers).
 template <bool BF16, int AF, int MAXR>
-__global__ void __launch_bounds__(256) k_bulk(const float4* __restrict__ Ahi,
-                                              const float4* __restrict__ Alo,
-                                              const float4* __restrict__ R32,
-                                              const int* __restrict__ pairs, Chi0Geom g,
-                                              float* __restrict__ C) {
+__device__ inline void bulk_tile(const float4* __restrict__ Ahi, const float4* __restrict__ Alo,
+                                 const float4* __restrict__ R32, const int* __restrict__ pairs,
+                                 const Chi0Geom& g, float* __restrict__ C, Blk3 bk,
+                                 float4* lds) {
   constexpr int NAC = 2 * AF;                 // A chunks per step (hi/lo or two f32 quads)
   constexpr int MAXA = (NAC + 3) / 4;         // A chunks per wave
-  extern __shared__ float4 lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
   const int ntb = g.n_tp / KSTEP;
   const int steps = ntb / g.ksplit;
-  const Blk3 bk = xcd_block(g.n_bulkp / 128, g.n_rowsp / (32 * AF), g.ksplit);
   const int tb0 = bk.z * steps;
   const int rb0 = bk.y * AF;
   const int b = bk.x * 128 + wave * 32 + (lane & 31);
@@ -344,6 +343,42 @@ __global__ void __launch_bounds__(256) k_bulk(const float4* __restrict__ Ahi,
     }
   }
 }
+
+template <bool BF16, int AF, int MAXR>
+__global__ void __launch_bounds__(256) k_bulk(const float4* __restrict__ Ahi,
+                                              const float4* __restrict__ Alo,
+                                              const float4* __restrict__ R32,
+                                              const int* __restrict__ pairs, Chi0Geom g,
+                                              float* __restrict__ C) {
+  extern __shared__ float4 lds[];
+  const Blk3 bk = xcd_block(g.n_bulkp / 128, g.n_rowsp / (32 * AF), g.ksplit);
+  bulk_tile<BF16, AF, MAXR>(Ahi, Alo, R32, pairs, g, C, bk, lds);
+}
+
+// Persistent form for a batch of uneven items: each block takes tiles from a
+// global list (ordered by decreasing cost) with an atomic counter until the
+// list is exhausted, so items with small N_G or few frequencies fill the gaps
+// left by large ones in one launch.
+template <bool BF16, int AF, int MAXR>
+__global__ void __launch_bounds__(256) k_bulk_persistent(const BulkItem* __restrict__ items,
+                                                         const int4* __restrict__ tiles,
+                                                         int n_tiles, int* counter) {
+  extern __shared__ float4 lds[];
+  __shared__ int tix;
+  for (;;) {
+    if (threadIdx.x == 0) tix = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = tix;
+    if (t >= n_tiles) break;
+    const int4 td = tiles[t];
+    const BulkItem& it = items[td.x];
+    bulk_tile<BF16, AF, MAXR>(it.A, it.Alo, it.R32, it.pairs, it.g, it.C, Blk3{td.y, td.z, td.w},
+                              lds);
+    __syncthreads();  // tix and the LDS buffers are reused by the next tile
+  }
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
 
 template <bool BF16, int AF>
 void launch_bulk_t(const void* Ahi, const void* Alo, const float* R32, const int* pairs,
@@ -637,6 +672,33 @@ void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32
     launch_bulk_t<true, 5>(Ahi, Alo, R32, pairs, g, C, st);
   else
     launch_bulk_t<true, 4>(Ahi, Alo, R32, pairs, g, C, st);
+}
+
+void launch_bulk_persistent(bool bf16, const BulkItem* items, const int4* tiles, int n_tiles,
+                            int* counter, int max_ng, int grid, hipStream_t st) {
+  constexpr int AF = kBatchAF;
+  const int nrc = (max_ng * SLAB_LD4 + 63) / 64;
+  const size_t lds = 2 * sizeof(float4) * ((size_t)nrc * 64 + 2 * AF * 64);
+  const int rpw = (nrc + 3) / 4;
+#define QCX_PERSIST(B, R)                                                                   \
+  hipLaunchKernelGGL((k_bulk_persistent<B, AF, R>), dim3(grid), dim3(256), lds, st, items, \
+                     tiles, n_tiles, counter)
+  if (bf16) {
+    if (rpw <= 1) QCX_PERSIST(true, 1);
+    else if (rpw <= 4) QCX_PERSIST(true, 4);
+    else if (rpw <= 9) QCX_PERSIST(true, 9);
+    else QCX_PERSIST(true, 17);
+  } else {
+    if (rpw <= 1) QCX_PERSIST(false, 1);
+    else if (rpw <= 4) QCX_PERSIST(false, 4);
+    else if (rpw <= 9) QCX_PERSIST(false, 9);
+    else QCX_PERSIST(false, 17);
+  }
+#undef QCX_PERSIST
+}
+
+void launch_set_int(int* p, int v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, v);
 }
 
 void launch_pairs_f64(const cplx* R, size_t ldt, const double* w, const double* dt, double eta,

@@ -1,0 +1,326 @@
+// Batched path for many uneven (cell, q, frequency list, N_G) items.
+//
+// The pair densities of each item come from its own context (qcx_pair_density
+// already called).  A plan is built once per batch signature: per-item
+// weights, R32 packs per context, pair tables, one tile list for the
+// persistent bulk kernel (ordered by decreasing cost, so that small items fill
+// the gaps left by large ones), per-item FP64 head/wings, and per-item
+// assembly, inversion and loss.  The whole sequence is captured into one
+// hipGraph; later calls with the same signature replay it with a single
+// launch.  Capture records kernels only (counters and flags are reset by a
+// one-thread kernel, not by memset nodes).
+#include "ctx.h"
+
+namespace qcx {
+
+struct PlanItem {
+  int ctx = 0;
+  Chi0Geom g{};
+  Geom64 g64{};
+  int n_pairs64 = 0;
+  double eta = 0.0, pref = 0.0;
+  double* loss_out = nullptr;
+  DevBuf w, A, Alo, pairs, pairs64, C, XY, eps, diag, epsM, loss;
+};
+
+struct BatchPlan {
+  std::vector<double> key;
+  int precision = 0, lfe = 1, hw64 = 1, n_items = 0;
+  std::vector<PlanItem> items;
+  std::vector<DevBuf> r32;  // per context
+  DevBuf d_items, d_tiles, d_counter, d_sing;
+  int n_tiles = 0, max_ng = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~BatchPlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (PlanItem& it : items) {
+      DevBuf* b[] = {&it.w, &it.A, &it.Alo, &it.pairs, &it.pairs64, &it.C, &it.XY,
+                     &it.eps, &it.diag, &it.epsM, &it.loss};
+      for (DevBuf* x : b) x->release();
+    }
+    for (DevBuf& b : r32) b.release();
+    d_items.release();
+    d_tiles.release();
+    d_counter.release();
+    d_sing.release();
+  }
+};
+
+void destroy_plan(BatchPlan* p) { delete p; }
+
+namespace {
+
+std::vector<double> batch_key(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_items,
+                              int precision, int lfe, int hw64) {
+  std::vector<double> k = {(double)n_items, (double)precision, (double)lfe, (double)hw64,
+                           (double)n_ctx};
+  for (int c = 0; c < n_ctx; ++c) {
+    const qcx_ctx* x = ctxs[c];
+    k.push_back((double)(uintptr_t)x);
+    k.push_back((double)(uintptr_t)x->d_R.p);
+    k.push_back((double)(uintptr_t)x->d_dt.p);
+    k.push_back((double)(uintptr_t)x->d_vq.p);
+    k.push_back((double)x->n_g);
+    k.push_back((double)x->n_t);
+    k.push_back((double)x->ldt);
+    k.push_back((double)x->n_k);
+    k.push_back(x->vol);
+  }
+  for (int i = 0; i < n_items; ++i) {
+    k.push_back((double)items[i].ctx);
+    k.push_back((double)items[i].n_w);
+    k.push_back(items[i].eta_eV);
+    k.push_back((double)(uintptr_t)items[i].loss_out);
+    for (int j = 0; j < items[i].n_w; ++j) k.push_back(items[i].w_eV[j]);
+  }
+  return k;
+}
+
+int ksplit_for(int ntb, int target_steps) {
+  int ks = 1;
+  while (ks < 16 && ntb / (2 * ks) >= target_steps) ks *= 2;
+  return ks;
+}
+
+int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_items,
+               int precision, int lfe, int hw64, BatchPlan* P) {
+  hipStream_t st = ctx->stream;
+  P->precision = precision;
+  P->lfe = lfe;
+  P->hw64 = hw64;
+  P->n_items = n_items;
+  P->items.resize(n_items);
+  P->r32.resize(n_ctx);
+  const bool bulk = precision != QCX_FP64;
+  const bool bf = precision == QCX_SPLIT_BF16;
+  std::vector<int> ctx_ntp(n_ctx, 0);
+  std::vector<BulkItem> bitems(n_items);
+  std::vector<int4> tiles;
+  HIPCK(stage_begin(ctx));
+  for (int i = 0; i < n_items; ++i) {
+    PlanItem& it = P->items[i];
+    const qcx_item& in = items[i];
+    qcx_ctx* c = ctxs[in.ctx];
+    it.ctx = in.ctx;
+    it.eta = in.eta_eV / kHartreeEV;
+    it.pref = 2.0 / (c->n_k * c->vol);
+    it.loss_out = in.loss_out;
+    std::vector<double> w(in.n_w);
+    for (int j = 0; j < in.n_w; ++j) w[j] = in.w_eV[j] / kHartreeEV;
+    HIPCK(upload(ctx, it.w, w.data(), w.size()));
+    Chi0Geom& g = it.g;
+    g = Chi0Geom{};
+    g.n_g = c->n_g;
+    g.n_t = c->n_t;
+    g.n_w = in.n_w;
+    g.n_rows = 2 * in.n_w;
+    g.n_pairs = c->n_g * (c->n_g + 1) / 2;
+    it.n_pairs64 = bulk ? (hw64 ? c->n_g : 0) : g.n_pairs;
+    g.p0 = bulk ? it.n_pairs64 : g.n_pairs;
+    g.n_bulk = g.n_pairs - g.p0;
+    g.n_bulkp = (int)roundup(std::max(g.n_bulk, 1), 128);
+    if (bulk && g.n_bulk > 0) {
+      g.n_rowsp = (int)roundup(g.n_rows, 32 * kBatchAF);
+      const int ntb0 = (int)roundup(g.n_t, 16) / 16;
+      g.ksplit = ksplit_for(ntb0, 256);
+      g.n_tp = (int)roundup(g.n_t, 16 * g.ksplit);
+      ctx_ntp[in.ctx] = std::max(ctx_ntp[in.ctx], g.n_tp);
+      const size_t nA = (size_t)g.n_rowsp * g.n_tp;
+      HIPCK(it.A.reserve(sizeof(uint16_t) * nA * (bf ? 1 : 2)));
+      if (bf) HIPCK(it.Alo.reserve(sizeof(uint16_t) * nA));
+      HIPCK(it.C.reserve(sizeof(float) * (size_t)g.ksplit * g.n_rowsp * 2 * g.n_bulkp));
+      std::vector<int> pr(g.n_bulkp, 0);
+      int b = 0, p = 0;
+      for (int G = 0; G < g.n_g; ++G)
+        for (int Gp = G; Gp < g.n_g; ++Gp, ++p)
+          if (p >= g.p0) pr[b++] = G | (Gp << 16);
+      HIPCK(upload(ctx, it.pairs, pr.data(), pr.size()));
+      for (int z = 0; z < g.ksplit; ++z)
+        for (int y = 0; y < g.n_rowsp / (32 * kBatchAF); ++y)
+          for (int x = 0; x < g.n_bulkp / 128; ++x) tiles.push_back(make_int4(i, x, y, z));
+      P->max_ng = std::max(P->max_ng, g.n_g);
+    } else {
+      g.ksplit = 1;
+      g.n_rowsp = 0;
+      g.n_tp = (int)roundup(g.n_t, 16);
+    }
+    if (it.n_pairs64 > 0) {
+      geom64_init(it.g64, c->n_g, in.n_w, c->n_t, it.n_pairs64, (size_t)256 << 20);
+      std::vector<int> tab(it.n_pairs64);
+      int p = 0;
+      for (int G = 0; G < c->n_g && p < it.n_pairs64; ++G)
+        for (int Gp = G; Gp < c->n_g && p < it.n_pairs64; ++Gp, ++p) tab[p] = G | (Gp << 16);
+      HIPCK(upload(ctx, it.pairs64, tab.data(), tab.size()));
+      HIPCK(it.XY.reserve(sizeof(double) * (size_t)it.g64.ksplit * it.g64.n_rowsp *
+                          it.g64.n_colp));
+    }
+    const int n = c->n_g;
+    HIPCK(it.eps.reserve(sizeof(cplx) * (size_t)in.n_w * n * n));
+    HIPCK(it.diag.reserve(sizeof(cplx) * (size_t)in.n_w * n));
+    HIPCK(it.epsM.reserve(sizeof(cplx) * (size_t)in.n_w));
+    if (!it.loss_out) HIPCK(it.loss.reserve(sizeof(double) * (size_t)in.n_w * n));
+  }
+  for (int c = 0; c < n_ctx; ++c)
+    if (ctx_ntp[c] > 0)
+      HIPCK(P->r32[c].reserve(sizeof(float) * 2 * (size_t)ctxs[c]->n_g * ctx_ntp[c]));
+  for (int i = 0; i < n_items; ++i) {
+    PlanItem& it = P->items[i];
+    bitems[i] = BulkItem{it.A.as<float4>(), it.Alo.as<float4>(), P->r32[it.ctx].as<float4>(),
+                         it.pairs.as<int>(), it.g, it.C.as<float>()};
+  }
+  // cost order: longest K range first (all tiles of one item are equal)
+  std::stable_sort(tiles.begin(), tiles.end(), [&](const int4& a, const int4& b) {
+    const Chi0Geom& ga = P->items[a.x].g;
+    const Chi0Geom& gb = P->items[b.x].g;
+    return (ga.n_tp / ga.ksplit) > (gb.n_tp / gb.ksplit);
+  });
+  P->n_tiles = (int)tiles.size();
+  HIPCK(upload(ctx, P->d_items, bitems.data(), bitems.size()));
+  if (!tiles.empty()) HIPCK(upload(ctx, P->d_tiles, tiles.data(), tiles.size()));
+  HIPCK(P->d_counter.reserve(sizeof(int)));
+  HIPCK(P->d_sing.reserve(sizeof(int) * (size_t)n_items));
+  HIPCK(hipStreamSynchronize(st));  // uploads complete before capture begins
+
+  // ---- capture on a private stream (the caller's may be the legacy default
+  // stream, which cannot be captured); the graph is replayed on the caller's
+  hipStream_t cap = nullptr;
+  HIPCK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  st = cap;
+  hipError_t ecap = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (ecap != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return fail(ctx, QCX_EDEVICE, std::string("begin capture: ") + hipGetErrorString(ecap));
+  }
+  for (int c = 0; c < n_ctx; ++c) {
+    if (ctx_ntp[c] == 0) continue;
+    Chi0Geom gp{};
+    gp.n_g = ctxs[c]->n_g;
+    gp.n_tp = ctx_ntp[c];
+    launch_pack_r32(ctxs[c]->d_R.as<cplx>(), ctxs[c]->ldt, gp, bf ? 0 : 1, P->r32[c].as<float>(),
+                    st);
+  }
+  for (int i = 0; i < n_items; ++i) {
+    PlanItem& it = P->items[i];
+    qcx_ctx* c = ctxs[it.ctx];
+    if (bulk && it.g.n_bulk > 0) {
+      if (bf)
+        launch_weights_bf16(it.w.as<double>(), c->d_dt.as<double>(), it.eta, it.g,
+                            it.A.as<uint16_t>(), it.Alo.as<uint16_t>(), st);
+      else
+        launch_weights_f32(it.w.as<double>(), c->d_dt.as<double>(), it.eta, it.g,
+                           it.A.as<float>(), st);
+    }
+  }
+  if (P->n_tiles > 0) {
+    launch_set_int(P->d_counter.as<int>(), 0, st);
+    const int grid = std::min(P->n_tiles, 2 * 256);
+    launch_bulk_persistent(bf, P->d_items.as<BulkItem>(), P->d_tiles.as<int4>(), P->n_tiles,
+                           P->d_counter.as<int>(), P->max_ng, grid, st);
+  }
+  for (int i = 0; i < n_items; ++i) {
+    PlanItem& it = P->items[i];
+    qcx_ctx* c = ctxs[it.ctx];
+    if (it.n_pairs64 > 0)
+      launch_pairs_f64(c->d_R.as<cplx>(), c->ldt, it.w.as<double>(), c->d_dt.as<double>(), it.eta,
+                       it.g64, it.pairs64.as<int>(), it.XY.as<double>(), st);
+  }
+  for (int i = 0; i < n_items; ++i) {
+    PlanItem& it = P->items[i];
+    qcx_ctx* c = ctxs[it.ctx];
+    launch_set_int(P->d_sing.as<int>() + i, INT_MAX, st);
+    AsmArgs a{};
+    a.C = (bulk && it.g.n_bulk > 0) ? it.C.as<float>() : nullptr;
+    a.XY = it.n_pairs64 > 0 ? it.XY.as<double>() : nullptr;
+    a.ks = it.g.ksplit;
+    a.ks64 = it.g64.ksplit;
+    a.n_rowsp64 = it.g64.n_rowsp;
+    a.n_colp64 = it.g64.n_colp;
+    a.n_pairs64 = it.n_pairs64;
+    a.vq = c->d_vq.as<double>();
+    a.pref = it.pref;
+    launch_eps_assemble(a, it.g, it.eps.as<cplx>(), st);
+    if (lfe)
+      launch_gj_diag(it.eps.as<cplx>(), c->n_g, it.g.n_w, it.diag.as<cplx>(),
+                     P->d_sing.as<int>() + i, st);
+    else
+      launch_nolfe_diag(it.eps.as<cplx>(), c->n_g, it.g.n_w, it.diag.as<cplx>(),
+                        P->d_sing.as<int>() + i, st);
+    launch_loss(it.diag.as<cplx>(), c->n_g, it.g.n_w,
+                it.loss_out ? it.loss_out : it.loss.as<double>(), it.epsM.as<cplx>(), st);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t ec = hipStreamEndCapture(st, &graph);
+  (void)hipStreamDestroy(cap);
+  if (ec != hipSuccess) return fail(ctx, QCX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+  P->graph = graph;
+  HIPCK(hipGraphInstantiate(&P->exec, graph, nullptr, nullptr, 0));
+  return QCX_OK;
+}
+
+}  // namespace
+}  // namespace qcx
+
+extern "C" {
+
+int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_items,
+                  int precision, int headwings_fp64, int lfe) {
+  if (!ctxs || n_ctx < 1 || !ctxs[0]) return QCX_EINVAL;
+  qcx_ctx* ctx = ctxs[0];
+  if (!items || n_items < 1) return fail(ctx, QCX_EINVAL, "no items");
+  if (precision < QCX_FP64 || precision > QCX_SPLIT_BF16) return fail(ctx, QCX_EINVAL, "bad precision");
+  for (int c = 0; c < n_ctx; ++c) {
+    if (!ctxs[c]) return fail(ctx, QCX_EINVAL, "NULL context");
+    if (ctxs[c]->device != ctx->device) return fail(ctx, QCX_EINVAL, "contexts on different devices");
+    if (!ctxs[c]->have_rho) return fail(ctx, QCX_ESTATE, "context " + std::to_string(c) + " has no pair densities");
+    if (precision != QCX_FP64 && ctxs[c]->n_g > 480)
+      return fail(ctx, QCX_EINVAL, "the MFMA bulk path is limited to n_G <= 480");
+    if (lfe && ctxs[c]->n_g > 2048) return fail(ctx, QCX_EINVAL, "LFE inversion limited to n_G <= 2048");
+  }
+  for (int i = 0; i < n_items; ++i) {
+    const qcx_item& it = items[i];
+    if (it.ctx < 0 || it.ctx >= n_ctx) return fail(ctx, QCX_EINVAL, "item context out of range");
+    if (it.n_w < 1 || it.n_w > 65536 || !it.w_eV) return fail(ctx, QCX_EINVAL, "item frequencies");
+    if (!(it.eta_eV >= 0.0)) return fail(ctx, QCX_EINVAL, "item eta");
+    if (!it.loss_out) return fail(ctx, QCX_EINVAL, "item loss_out must be a device buffer");
+    for (int j = 0; j < it.n_w; ++j)
+      if (!std::isfinite(it.w_eV[j])) return fail(ctx, QCX_EINVAL, "non-finite frequency");
+  }
+  HIPCK(hipSetDevice(ctx->device));
+  const int hw64 = headwings_fp64 ? 1 : 0;
+  std::vector<double> key = batch_key(ctxs, n_ctx, items, n_items, precision, lfe ? 1 : 0, hw64);
+  if (!ctx->plan || ctx->plan->key != key) {
+    if (ctx->plan) destroy_plan(ctx->plan);
+    ctx->plan = new BatchPlan();
+    ctx->plan->key = key;
+    const int rc = build_plan(ctx, ctxs, n_ctx, items, n_items, precision, lfe ? 1 : 0, hw64,
+                              ctx->plan);
+    if (rc != QCX_OK) {
+      destroy_plan(ctx->plan);
+      ctx->plan = nullptr;
+      return rc;
+    }
+  }
+  int sp;
+  HIPCK(span_begin(ctx, 3, &sp));
+  HIPCK(hipGraphLaunch(ctx->plan->exec, ctx->stream));
+  HIPCK(span_end(ctx, sp));
+  return QCX_OK;
+}
+
+int qcx_batch_sync(qcx_ctx* ctx) {
+  if (!ctx) return QCX_EINVAL;
+  HIPCK(hipSetDevice(ctx->device));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  if (!ctx->plan) return QCX_OK;
+  std::vector<int> s(ctx->plan->n_items);
+  HIPCK(hipMemcpy(s.data(), ctx->plan->d_sing.p, sizeof(int) * s.size(), hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < s.size(); ++i)
+    if (s[i] != INT_MAX)
+      return fail(ctx, QCX_ESINGULAR, "zero pivot in item " + std::to_string(i) + " at frequency index " +
+                                          std::to_string(s[i]));
+  return QCX_OK;
+}
+
+}  // extern "C"

@@ -149,3 +149,18 @@ def test_error_paths(ctx, cfg1):
         c2.set_states(st.q_cart, cfg1.k_frac, cfg1.n_occ, st.C_k, ebad, st.C_kq, st.E_kq)
     assert e.value.code == q.EINVAL
     c2.close()
+
+
+@pytest.mark.parametrize("n_g", [181, 259])
+def test_large_ng_blocked_inversion(ctx, n_g):
+    """N_G above the register-resident limit: blocked Gauss-Jordan (panels of
+    32 columns in LDS, rank-32 trailing updates) and the 256-row FP64 stage."""
+    wl = make_tiny(kgrid=2, n_g=n_g, n_w=12)
+    ref = _oracle(wl)
+    out = gpu_solve(ctx, wl, precision="fp64")
+    e64 = normwise(out["loss"], ref["loss"])
+    out = gpu_solve(ctx, wl, precision="split_bf16")
+    esp = normwise(out["loss"], ref["loss"])
+    print("n_g", n_g, "fp64", e64, "split", esp)
+    assert e64 < 1e-10
+    assert esp < 1e-4
