@@ -67,8 +67,11 @@ enum {
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`
  * (a hipStream_t; NULL means the default stream).  *out receives the
- * context.  Errors: QCX_EINVAL (out NULL, device out of range),
- * QCX_EDEVICE (device is not gfx950). */
+ * context.  The library uses whichever HIP runtime (libamdhip64.so.7) the
+ * process has loaded; a process that also uses PyTorch must load PyTorch's
+ * first, since two HIP runtimes in one process cannot share the device.
+ * Errors: QCX_EINVAL (out NULL, device out of range), QCX_EDEVICE (HIP
+ * runtime not usable, or device is not gfx950). */
 int qcx_create(qcx_ctx** out, int device, void* hip_stream);
 
 /* Free every device buffer the context owns.  The stream is not touched.

@@ -12,6 +12,8 @@ from .qcx import (  # noqa: F401
     SPLIT_BF16,
     Context,
     QcxError,
+    batch_sync,
+    run_batch,
     build_info,
     exported_symbols,
     load_library,

@@ -32,7 +32,12 @@ int qcx_create(qcx_ctx** out, int device, void* hip_stream) {
   }
   *out = nullptr;
   int n = 0;
-  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+  const hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) {
+    g_create_err = std::string("hipGetDeviceCount: ") + hipGetErrorString(e);
+    return QCX_EDEVICE;
+  }
+  if (device < 0 || device >= n) {
     g_create_err = "no such HIP device";
     return QCX_EINVAL;
   }

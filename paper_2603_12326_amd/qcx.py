@@ -56,7 +56,14 @@ _SIGS = {
     "qcx_stage_times": [_P, _P],
     "qcx_set_timing": [_P, _I],
     "qcx_build_info": [],
+    "qcx_run_batch": [_P, _I, _P, _I, _I, _I, _I],
+    "qcx_batch_sync": [_P],
 }
+
+
+class QcxItem(ctypes.Structure):
+    """struct qcx_item of include/qcx.h."""
+    _fields_ = [("ctx", _I), ("n_w", _I), ("w_eV", _P), ("eta_eV", _D), ("loss_out", _P)]
 
 
 def load_library(path: str = LIB_PATH):
@@ -64,6 +71,11 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own libamdhip64.so.7 and HSA runtime; load them first so
+    # that libqcx's dependency resolves to the same copy (a second HIP runtime
+    # in the process cannot open the device).
+    import torch  # noqa: F401
+
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not found: build it with `python -m paper_2603_12326_amd.build`")
     lib = ctypes.CDLL(path)
@@ -228,6 +240,37 @@ class Context:
         self._check(self.lib.qcx_stage_times(self._h, _ptr_host(t)))
         return dict(pair_density_ms=t[0], chi0_bulk_ms=t[1], chi0_headwings_ms=t[2],
                     chi0_total_ms=t[3], eps_inv_ms=t[4], bulk_launches=int(t[5]))
+
+
+def run_batch(contexts, items, precision=SPLIT_BF16, headwings_fp64: bool = True,
+              lfe: bool = True):
+    """Batched chi0 -> eps -> loss (qcx_run_batch).
+
+    contexts: list of Context with pair densities; items: list of dicts with
+    keys ctx (index), w_eV, eta_eV, loss_out (CUDA float64 tensor [n_w][n_G]).
+    Asynchronous; call batch_sync(contexts[0]) to wait and check errors.
+    """
+    lib = load_library()
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    handles = (ctypes.c_void_p * len(contexts))(*[c._h.value for c in contexts])
+    arr = (QcxItem * len(items))()
+    keep = []
+    for i, it in enumerate(items):
+        w = _host(it["w_eV"], np.float64).reshape(-1)
+        keep.append(w)
+        c = contexts[it["ctx"]]
+        out = _dev_ptr(it["loss_out"], "f64", len(w) * c.n_g, "loss_out")
+        arr[i] = QcxItem(int(it["ctx"]), len(w), w.ctypes.data, float(it["eta_eV"]), out.value)
+    rc = lib.qcx_run_batch(handles, len(contexts), ctypes.cast(arr, ctypes.c_void_p), len(items),
+                           int(precision), 1 if headwings_fp64 else 0, 1 if lfe else 0)
+    del keep
+    if rc != OK:
+        raise QcxError(rc, lib.qcx_last_error(contexts[0]._h).decode())
+
+
+def batch_sync(ctx0):
+    ctx0._check(ctx0.lib.qcx_batch_sync(ctx0._h))
 
 
 def build_info() -> str:
