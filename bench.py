@@ -15,8 +15,10 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +29,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_BF16_TFLOPS = 2516.6   # MI355X dense BF16 MFMA
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 matrix
+# HBM traffic of the bulk kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (one pass each) and scaled by the same counters on a copy of known size;
+# valid only while the kernel source hashes to the recorded value.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_bf16_config2_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_12326_amd", "csrc", f)
+                  for f in ("k_chi0.hip", "common.h")]
 
 
 def parse():
@@ -37,8 +45,41 @@ def parse():
     ap.add_argument("--n-q", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-sample-w", type=int, default=48)
+    ap.add_argument("--cpu-sample-w", type=int, default=400)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB elementwise copy before timing (HBM counter calibration)")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """Bytes per bulk launch from the committed counter summary, or None when
+    the summary is missing or the kernel source changed since it was taken."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m_h = re.search(r"source_sha256_16:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_h or not m_b or m_h.group(1) != kernel_source_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def calib_copy(torch):
+    """out = x * 1 over 2^27 float64: reads and writes exactly 1 GiB each."""
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    del x, y
 
 
 def upload_workload(wl, n_q, torch):
@@ -67,7 +108,12 @@ def run_step(ctx, wl, qs, kf, prec, loss_out):
         ctx.loss(loss_out[iq])
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def timed(ctx, wl, qs, kf, prec, loss_out, steps, warmup, torch):
+    log(f"{prec}: {warmup} warmup + {steps} timed steps")
     for _ in range(warmup):
         run_step(ctx, wl, qs, kf, prec, loss_out)
     ctx.sync()
@@ -130,7 +176,10 @@ def main():
     from paper_2603_12326_amd import Context, build_info
     from synth import make_config2
 
+    if args.calib_copy:
+        calib_copy(torch)
     wl = make_config2(n_q=args.n_q)
+    log(f"generating and uploading {args.n_q} q points")
     qs, kf = upload_workload(wl, args.n_q, torch)
     n_g, n_w = len(wl.G_int), len(wl.w_eV)
     loss_out = [torch.empty((n_w, n_g), dtype=torch.float64, device="cuda") for _ in qs]
@@ -170,7 +219,8 @@ def main():
                    "chi0_bulk": "split-bf16 MFMA, fp32 accumulation",
                    "head_wings": "fp64", "inversion": "fp64"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS,
+                     "traffic": recorded_traffic(), "kernel_source_sha256_16": kernel_source_hash(),
                      "kernel": "k_bulk<bf16> (chi0 bulk)", "avg_launch_ms": 1e3 * avg_bulk_s,
                      "flops_per_launch_fp32_equiv": alg},
         "stages_ms_per_step": {k: (v / args.steps if k.endswith("_ms") else v)
@@ -187,6 +237,7 @@ def main():
                                 "frac": alg / avg32 / 1e12 / PEAK_FP32_TFLOPS,
                                 "avg_launch_ms": 1e3 * avg32}
     if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle on a sample)")
         cb = cpu_baseline(wl, args.cpu_sample_w, res["split_bf16"]["loss0"],
                           res["fp32"]["loss0"] if "fp32" in res else None)
         out["max_rel_err_split"] = cb.pop("err_split")
