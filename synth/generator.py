@@ -278,6 +278,7 @@ class Workload:
     seed: int
     energy_ranges: Sequence = ()
     smooth: bool = True
+    smooth_bands: bool = False
     _x: Optional[tuple] = field(default=None, repr=False)
     _s: Optional[tuple] = field(default=None, repr=False)
     _ek: Optional[np.ndarray] = field(default=None, repr=False)
@@ -310,6 +311,29 @@ def _energies(rng, n_k, ranges):
     return np.ascontiguousarray(np.concatenate(cols, axis=1))
 
 
+def _band_model(rng, ranges, amp=0.06):
+    """Smooth periodic bands: per band a level drawn in its range plus three
+    cosine harmonics e^{2 pi i kf.h} (h = unit vectors) with amplitude amp x
+    the range width and random phases."""
+    levels, amps, phases = [], [], []
+    for cnt, lo, hi in ranges:
+        levels.append(np.sort(rng.uniform(lo, hi, size=cnt)))
+        amps.append(amp * (hi - lo) * rng.uniform(0.5, 1.0, size=(cnt, 3)))
+        phases.append(rng.uniform(0.0, 2 * math.pi, size=(cnt, 3)))
+    return levels, amps, phases
+
+
+def _band_energies(model, ranges, k_frac):
+    """E_n(k) of the band model, sorted within each group and kept in range."""
+    levels, amps, phases = model
+    cols = []
+    for (cnt, lo, hi), lv, am, ph in zip(ranges, levels, amps, phases):
+        arg = 2 * math.pi * k_frac[:, None, :] + ph[None, :, :]        # [nk][cnt][3]
+        e = lv[None, :] + np.sum(am[None] * np.cos(arg), axis=2)
+        cols.append(np.sort(np.clip(e, lo, hi), axis=1))
+    return np.ascontiguousarray(np.concatenate(cols, axis=1))
+
+
 def _coeffs(wl: Workload, k_frac: np.ndarray, rng_iid=None):
     if wl._s is None:
         wl._s = real_space_overlaps(wl.cell, wl.basis, wl.lattice_range)
@@ -333,14 +357,21 @@ def draw_states(wl: Workload, iq: int) -> QStates:
     kids = ss.spawn(3 + len(wl.q_list))
     if wl._x is None:
         wl._x = _smooth_x(np.random.default_rng(kids[0]), wl.n_ao, wl.n_bands)
+    bands = _band_model(np.random.default_rng(kids[2]), wl.energy_ranges) if wl.smooth_bands else None
     if wl._ck is None:
         rk = np.random.default_rng(kids[1])
-        wl._ek = _energies(rk, wl.n_k, wl.energy_ranges)
+        if bands is not None:
+            wl._ek = _band_energies(bands, wl.energy_ranges, wl.k_frac)
+        else:
+            wl._ek = _energies(rk, wl.n_k, wl.energy_ranges)
         wl._ck = _coeffs(wl, wl.k_frac, rk)
     q = np.asarray(wl.q_list[iq], np.float64)
     qf = wl.cell.lat @ q / (2.0 * math.pi)
     rq = np.random.default_rng(kids[3 + iq])
-    e_kq = _energies(rq, wl.n_k, wl.energy_ranges)
+    if bands is not None:
+        e_kq = _band_energies(bands, wl.energy_ranges, wl.k_frac + qf[None, :])
+    else:
+        e_kq = _energies(rq, wl.n_k, wl.energy_ranges)
     c_kq = _coeffs(wl, wl.k_frac + qf[None, :], rq)
     return QStates(q_cart=q, C_k=wl._ck, E_k=wl._ek, C_kq=c_kq, E_kq=e_kq)
 
