@@ -202,6 +202,70 @@ int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_
                   int precision, int headwings_fp64, int lfe);
 int qcx_batch_sync(qcx_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Surrogate of the loss (not part of the paper's method): an ensemble of
+ * small networks mapping a momentum transfer and an energy to
+ * log Im[-1/eps_LFE](Q, w), the quantity of Eq. (eps_LFE) that the rate
+ * integral sweeps.  Each member is 5 -> 256 -> 256 -> 256 -> 256 -> 1 with
+ * SiLU after the hidden layers; FP32 master weights, bf16 copies for the
+ * products (v_mfma_f32_32x32x16_bf16, FP32 accumulation), Adam training on
+ * the mean squared error.  Members run on the device and stream of the
+ * context they were created from; errors are reported through
+ * qcx_last_error of that context.
+ *
+ * Parameter vector (QCX_MLP_NPARAM floats): per layer l = 1..5 the weight
+ * matrix W_l[n_out][n_in] (row-major), then the bias b_l[n_out].
+ * ------------------------------------------------------------------------ */
+#define QCX_MLP_NPARAM 199169
+typedef struct qcx_mlp qcx_mlp;
+
+/* Create n_members (1..16) networks with zero parameters on ctx. */
+int qcx_mlp_create(qcx_mlp** out, qcx_ctx* ctx, int n_members);
+/* Free the networks (synchronises the context's stream).  Safe on NULL. */
+int qcx_mlp_destroy(qcx_mlp* m);
+/* Copy host params[QCX_MLP_NPARAM] into member `member` and reset its Adam
+ * state.  Synchronous.  Errors: QCX_EINVAL (index, NULL, non-finite). */
+int qcx_mlp_set_params(qcx_mlp* m, int member, const float* params);
+/* Copy member `member`'s FP32 parameters to host params.  Synchronous. */
+int qcx_mlp_get_params(qcx_mlp* m, int member, float* params);
+/* Network output y[i] for device inputs x[n][5] (device y[n]).  Async. */
+int qcx_mlp_forward(qcx_mlp* m, int member, int n, const float* x, float* y);
+/* Gradient of mean_i (y_i - t_i)^2 over device x[n][5], t[n] (n <= 16384)
+ * into host grad[QCX_MLP_NPARAM]; the loss into *loss if not NULL.  No
+ * update.  Synchronous. */
+int qcx_mlp_grad(qcx_mlp* m, int member, int n, const float* x, const float* t, float* grad,
+                 float* loss);
+/* n_steps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on
+ * mini-batches: step s uses samples order[s*batch .. (s+1)*batch) of the
+ * device data x[n_data][5], t[n_data]; order is a device int array of
+ * n_steps*batch indices in [0, n_data) (checked before the first step).
+ * Learning rate lr1 + (lr0 - lr1)(1 + cos(pi s / n_steps))/2.  batch
+ * 1..16384.  Per-step losses into host loss_hist[n_steps] if not NULL (then
+ * synchronous; otherwise asynchronous). */
+int qcx_mlp_train(qcx_mlp* m, int member, int n_data, const float* x, const float* t, int batch,
+                  int n_steps, const int* order, float lr0, float lr1, float* loss_hist);
+/* Input and output scaling shared by qcx_mlp_encode and qcx_mlp_query:
+ * features x = (2|Q|/q_max - 1, Q/|Q|, 2w/w_max - 1) and target
+ * t = (log max(L, 1e-30) - mu)/sigma; the error estimate of a query is
+ * calib * sigma * (sample standard deviation of the members' outputs), an
+ * estimate of the relative error of the returned loss. */
+int qcx_mlp_set_encoding(qcx_mlp* m, double q_max, double w_max_eV, double mu, double sigma,
+                         double calib);
+/* Features x[n][5] (device float) of device queries qw[n][4] = (Qx, Qy, Qz
+ * in bohr^-1, w in eV), and, if loss (device double [n]) and t are not
+ * NULL, the training targets t[n].  Errors: QCX_ESTATE before
+ * qcx_mlp_set_encoding.  Async. */
+int qcx_mlp_encode(qcx_mlp* m, int n, const double* qw, const double* loss, float* x, float* t);
+/* Surrogate answer for device queries qw[n][4]: loss[n] = exp(mu + sigma *
+ * mean of the members), err[n] (may be NULL) the error estimate.  If
+ * reject_idx is not NULL (then err and n_reject must be too), the indices
+ * with err > tol are written to reject_idx in ascending order and their
+ * number to the host *n_reject; the caller recomputes those points with the
+ * method itself (qcx_chi0 / qcx_eps_inv / qcx_loss).  Synchronous when
+ * rejecting, otherwise asynchronous. */
+int qcx_mlp_query(qcx_mlp* m, int n, const double* qw, double* loss, double* err, double tol,
+                  int* reject_idx, int* n_reject);
+
 /* Per-stage device time of the most recent calls, in milliseconds, measured
  * with HIP events on the context's stream (enabled by qcx_set_timing):
  * t[0] pair_density, t[1] chi0 bulk kernel, t[2] chi0 FP64 head/wings,

@@ -176,3 +176,29 @@ def train(theta, X, t, order, batch, lr0, lr1, widths=WIDTHS, bf16=False):
         hist.append(loss)
         theta = opt.step(theta, g, cosine_lr(s, n_steps, lr0, lr1))
     return theta, np.array(hist)
+
+
+# ---------------------------------------------------------------------------
+# surrogate input / output scaling
+# ---------------------------------------------------------------------------
+def encode(qw: np.ndarray, q_max: float, w_max: float) -> np.ndarray:
+    """Features of queries qw[n] = (Qx, Qy, Qz, w): (2|Q|/q_max - 1, Q/|Q|,
+    2 w/w_max - 1); the direction of Q = 0 is taken as (0, 0, 0)."""
+    Q = np.asarray(qw, np.float64)[:, :3]
+    q = np.linalg.norm(Q, axis=1)
+    d = np.where(q[:, None] > 0, Q / np.where(q > 0, q, 1.0)[:, None], 0.0)
+    return np.column_stack([2 * q / q_max - 1, d, 2 * np.asarray(qw)[:, 3] / w_max - 1])
+
+
+def target(loss: np.ndarray, mu: float, sigma: float) -> np.ndarray:
+    """Standardised log of the loss, floored at 1e-30."""
+    return (np.log(np.maximum(loss, 1e-30)) - mu) / sigma
+
+
+def decode(ys: np.ndarray, mu: float, sigma: float, calib: float):
+    """Ensemble outputs ys[K][n] -> (loss, relative-error estimate):
+    exp(mu + sigma * mean) and calib * sigma * sample standard deviation."""
+    ys = np.asarray(ys, np.float64)
+    m = ys.mean(axis=0)
+    sd = ys.std(axis=0, ddof=1) if len(ys) > 1 else np.zeros_like(m)
+    return np.exp(mu + sigma * m), calib * sigma * sd

@@ -11,6 +11,7 @@ from .qcx import (  # noqa: F401
     FP64,
     SPLIT_BF16,
     Context,
+    Mlp,
     QcxError,
     batch_sync,
     run_batch,

@@ -58,7 +58,18 @@ _SIGS = {
     "qcx_build_info": [],
     "qcx_run_batch": [_P, _I, _P, _I, _I, _I, _I],
     "qcx_batch_sync": [_P],
+    "qcx_mlp_create": [ctypes.POINTER(_P), _P, _I],
+    "qcx_mlp_destroy": [_P],
+    "qcx_mlp_set_params": [_P, _I, _P],
+    "qcx_mlp_get_params": [_P, _I, _P],
+    "qcx_mlp_forward": [_P, _I, _I, _P, _P],
+    "qcx_mlp_grad": [_P, _I, _I, _P, _P, _P, _P],
+    "qcx_mlp_train": [_P, _I, _I, _P, _P, _I, _I, _P, ctypes.c_float, ctypes.c_float, _P],
+    "qcx_mlp_set_encoding": [_P, _D, _D, _D, _D, _D],
+    "qcx_mlp_encode": [_P, _I, _P, _P, _P, _P],
+    "qcx_mlp_query": [_P, _I, _P, _P, _P, _D, _P, _P],
 }
+MLP_NPARAM = 199169
 
 
 class QcxItem(ctypes.Structure):
@@ -106,7 +117,8 @@ def _is_torch_cuda(x) -> bool:
 def _dev_ptr(t, dtype_name: str, numel: int, what: str):
     import torch
 
-    want = {"f64": torch.float64, "c128": torch.complex128, "i32": torch.int32}[dtype_name]
+    want = {"f64": torch.float64, "f32": torch.float32, "c128": torch.complex128,
+            "i32": torch.int32}[dtype_name]
     if not _is_torch_cuda(t):
         raise TypeError(f"{what}: expected a CUDA tensor")
     if t.dtype != want or not t.is_contiguous() or t.numel() != numel:
@@ -271,6 +283,89 @@ def run_batch(contexts, items, precision=SPLIT_BF16, headwings_fp64: bool = True
 
 def batch_sync(ctx0):
     ctx0._check(ctx0.lib.qcx_batch_sync(ctx0._h))
+
+
+class Mlp:
+    """Surrogate ensemble (qcx_mlp_*) on a Context's device and stream."""
+
+    def __init__(self, ctx: Context, n_members: int = 4):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.n_members = n_members
+        h = ctypes.c_void_p()
+        ctx._check(self.lib.qcx_mlp_create(ctypes.byref(h), ctx._h, n_members))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.qcx_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, member: int, params):
+        p = _host(params, np.float32).reshape(-1)
+        if len(p) != MLP_NPARAM:
+            raise ValueError(f"need {MLP_NPARAM} parameters")
+        self.ctx._check(self.lib.qcx_mlp_set_params(self._h, member, _ptr_host(p)))
+
+    def get_params(self, member: int) -> np.ndarray:
+        p = np.empty(MLP_NPARAM, np.float32)
+        self.ctx._check(self.lib.qcx_mlp_get_params(self._h, member, _ptr_host(p)))
+        return p
+
+    def forward(self, member: int, x, y):
+        n = x.shape[0]
+        self.ctx._check(self.lib.qcx_mlp_forward(self._h, member, n, _dev_ptr(x, "f32", n * 5, "x"),
+                                                 _dev_ptr(y, "f32", n, "y")))
+        return y
+
+    def grad(self, member: int, x, t):
+        n = x.shape[0]
+        g = np.empty(MLP_NPARAM, np.float32)
+        loss = ctypes.c_float()
+        self.ctx._check(self.lib.qcx_mlp_grad(self._h, member, n, _dev_ptr(x, "f32", n * 5, "x"),
+                                              _dev_ptr(t, "f32", n, "t"), _ptr_host(g),
+                                              ctypes.byref(loss)))
+        return g, loss.value
+
+    def train(self, member: int, x, t, batch: int, order, lr0: float, lr1: float,
+              want_hist: bool = True):
+        n = x.shape[0]
+        n_steps = order.numel() // batch
+        hist = np.empty(n_steps, np.float32) if want_hist else None
+        self.ctx._check(self.lib.qcx_mlp_train(
+            self._h, member, n, _dev_ptr(x, "f32", n * 5, "x"), _dev_ptr(t, "f32", n, "t"), batch,
+            n_steps, _dev_ptr(order, "i32", order.numel(), "order"), float(lr0), float(lr1),
+            _ptr_host(hist) if want_hist else None))
+        return hist
+
+    def set_encoding(self, q_max, w_max_eV, mu, sigma, calib=1.0):
+        self.ctx._check(self.lib.qcx_mlp_set_encoding(self._h, q_max, w_max_eV, mu, sigma, calib))
+
+    def encode(self, qw, loss=None, x=None, t=None):
+        n = qw.shape[0]
+        self.ctx._check(self.lib.qcx_mlp_encode(
+            self._h, n, _dev_ptr(qw, "f64", n * 4, "qw"),
+            None if loss is None else _dev_ptr(loss, "f64", n, "loss"),
+            _dev_ptr(x, "f32", n * 5, "x"), None if t is None else _dev_ptr(t, "f32", n, "t")))
+
+    def query(self, qw, loss, err=None, tol=None, reject_idx=None):
+        """Returns the number of rejected points when reject_idx is given."""
+        n = qw.shape[0]
+        nrej = ctypes.c_int(0)
+        rej = reject_idx is not None
+        self.ctx._check(self.lib.qcx_mlp_query(
+            self._h, n, _dev_ptr(qw, "f64", n * 4, "qw"), _dev_ptr(loss, "f64", n, "loss"),
+            None if err is None else _dev_ptr(err, "f64", n, "err"),
+            float(tol) if tol is not None else 0.0,
+            _dev_ptr(reject_idx, "i32", n, "reject_idx") if rej else None,
+            ctypes.byref(nrej) if rej else None))
+        return nrej.value if rej else None
 
 
 def build_info() -> str:
