@@ -242,14 +242,20 @@ def _smooth_x(rng, n_ao, n_bands, amp=0.35):
     return coef, harm
 
 
-def lowdin(x: np.ndarray, s: np.ndarray) -> np.ndarray:
-    """C = X (X^H S X)^{-1/2} for one k."""
+def _lowdin_once(x: np.ndarray, s: np.ndarray) -> np.ndarray:
     m = x.conj().T @ s @ x
     m = 0.5 * (m + m.conj().T)
     w, u = np.linalg.eigh(m)
     if w.min() <= 1e-12 * w.max():
         raise RuntimeError("rank-deficient random coefficients")
     return x @ (u * (1.0 / np.sqrt(w))) @ u.conj().T
+
+
+def lowdin(x: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """C = X (X^H S X)^{-1/2} for one k, applied twice: where X is nearly
+    singular the first pass leaves C^H S C - I at ~eps cond(X)^2; the second
+    pass starts from the well-conditioned C and brings it to ~eps."""
+    return _lowdin_once(_lowdin_once(x, s), s)
 
 
 @dataclass
