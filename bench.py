@@ -191,7 +191,8 @@ def main():
     res = {}
     for prec in (["split_bf16"] + ([] if args.no_fp32 else ["fp32"])):
         sec, st = timed(ctx, wl, qs, kf, prec, loss_out, args.steps, args.warmup, torch)
-        res[prec] = dict(sec=sec, st=st, loss0=loss_out[0].cpu().numpy().copy())
+        res[prec] = dict(sec=sec, st=st, loss0=loss_out[0].cpu().numpy().copy(),
+                         tile=ctx.bulk_config())
 
     s = res["split_bf16"]
     ms_step = 1e3 * s["sec"] / args.steps
@@ -222,7 +223,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS,
                      "traffic": recorded_traffic(), "kernel_source_sha256_16": kernel_source_hash(),
                      "kernel": "k_bulk<bf16> (chi0 bulk)", "avg_launch_ms": 1e3 * avg_bulk_s,
-                     "flops_per_launch_fp32_equiv": alg},
+                     "flops_per_launch_fp32_equiv": alg, "tile": s["tile"]},
         "stages_ms_per_step": {k: (v / args.steps if k.endswith("_ms") else v)
                                for k, v in s["st"].items()},
         "build": build_info(),
@@ -235,7 +236,7 @@ def main():
         out["speedup_split_vs_fp32"] = value / out["fp32_value"]
         out["fp32_roofline"] = {"achieved": alg / avg32 / 1e12, "peak": PEAK_FP32_TFLOPS,
                                 "frac": alg / avg32 / 1e12 / PEAK_FP32_TFLOPS,
-                                "avg_launch_ms": 1e3 * avg32}
+                                "avg_launch_ms": 1e3 * avg32, "tile": f["tile"]}
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle on a sample)")
         cb = cpu_baseline(wl, args.cpu_sample_w, res["split_bf16"]["loss0"],

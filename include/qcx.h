@@ -266,6 +266,22 @@ int qcx_mlp_encode(qcx_mlp* m, int n, const double* qw, const double* loss, floa
 int qcx_mlp_query(qcx_mlp* m, int n, const double* qw, double* loss, double* err, double tol,
                   int* reject_idx, int* n_reject);
 
+/* Tile selection of the chi0 bulk kernel (qcx_chi0 with FP32 or split-BF16).
+ * mode 1 (default): on the first qcx_chi0 of each shape (device, precision,
+ * N_G, padded N_T, padded rows), every candidate configuration - K split
+ * 1..16 and a 2- or 3-stage LDS pipeline, within 160 KB of LDS and 2 GB of
+ * partial sums - is timed on the real operands with HIP events and the
+ * fastest is kept for the process; that call synchronises the stream.  The
+ * result used is always computed with the chosen configuration.  mode 0: a
+ * fixed heuristic.  Tuning is skipped while the stream is being captured.
+ * Errors: QCX_EINVAL (mode). */
+int qcx_set_autotune(qcx_ctx* ctx, int mode);
+/* Configuration of the last bulk launch: cfg = {K split, pipeline stages,
+ * row fragments per wave} (zeros if there was no bulk), and the time spent
+ * tuning in that call (ms, 0 when the shape was cached).  Errors:
+ * QCX_ESTATE before qcx_chi0. */
+int qcx_bulk_config(qcx_ctx* ctx, int cfg[3], double* tune_ms);
+
 /* Per-stage device time of the most recent calls, in milliseconds, measured
  * with HIP events on the context's stream (enabled by qcx_set_timing):
  * t[0] pair_density, t[1] chi0 bulk kernel, t[2] chi0 FP64 head/wings,

@@ -97,11 +97,16 @@ void launch_weights_bf16(const double* w, const double* dt, double eta, const Ch
 // R64[g][t] -> R32 slabs [t/16][g][16] (complex float)
 void launch_pack_r32(const cplx* R, size_t ldt, const Chi0Geom& g, int perm, float* R32,
                      hipStream_t st);
+constexpr int KSTEP_T = 16;  // transitions per bulk K step (one MFMA K block)
 int bulk_row_frags(const Chi0Geom& g);
+// LDS bytes of one bulk block: nst pipeline stages of the R slab (n_g rows)
+// and af A fragment pairs
+size_t bulk_lds_bytes(int n_g, int af, int nst);
+// bulk launches; nst = 2 or 3 LDS pipeline stages
 void launch_bulk_f32(const float* Aw, const float* R32, const int* pairs, const Chi0Geom& g,
-                     float* C, hipStream_t st);
+                     int nst, float* C, hipStream_t st);
 void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32,
-                      const int* pairs, const Chi0Geom& g, float* C, hipStream_t st);
+                      const int* pairs, const Chi0Geom& g, int nst, float* C, hipStream_t st);
 // One item of a batched bulk launch (its own weights, R, pairs and partials).
 struct BulkItem {
   const float4* A;

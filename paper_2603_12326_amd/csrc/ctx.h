@@ -53,6 +53,10 @@ struct qcx_ctx {
   double eta = 0.0;
   Chi0Geom geom{};
   int ks64 = 1, n_pairs64 = 0;
+  int bulk_nst = 2;           // LDS pipeline stages of the last bulk launch
+  int bulk_af = 4;            // row fragments per wave of the last bulk launch
+  int autotune = 1;           // 0: fixed heuristic, 1: time candidates per shape
+  double tune_ms = 0.0;       // time spent tuning in the last qcx_chi0
   Geom64 geom64{};
   DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_pairs64, d_C, d_XY;
 

@@ -167,16 +167,40 @@ __device__ inline void lds_dma16(const float4* src, float4* dst) {
   __builtin_amdgcn_global_load_lds((const void*)src, (lds_ptr_t)dst, 16, 0, 0);
 }
 
+// LDS of one pipeline stage of a bulk block: the R slab (RCH chunks of 1 KB:
+// padded rows of 16 complex floats) and the A fragments (NAC chunks).  Each
+// stage is its own __shared__ object, so the compiler can see that copies
+// into one stage never alias the reads of another: a step issues the copies
+// of a later step first and then reads its own stage without waiting.
+template <int RCH, int NAC>
+struct BulkStage {
+  float4 r[RCH * 64];
+  float4 a[NAC * 64];
+};
+
+// R chunks per wave (template bucket) for n_g slab rows
+inline int bulk_maxr(int n_g) {
+  const int rpw = ((n_g * SLAB_LD4 + 63) / 64 + 3) / 4;
+  return rpw <= 1 ? 1 : rpw <= 4 ? 4 : rpw <= 9 ? 9 : rpw <= 17 ? 17 : 0;
+}
+
 // One block tile of the bulk GEMM: pair tile bk.x, row tile bk.y, K split
-// bk.z, staged through `lds` (2 buffers).
-template <bool BF16, int AF, int MAXR>
-__device__ inline void bulk_tile(const float4* __restrict__ Ahi, const float4* __restrict__ Alo,
-                                 const float4* __restrict__ R32, const int* __restrict__ pairs,
-                                 const Chi0Geom& g, float* __restrict__ C, Blk3 bk,
-                                 float4* lds) {
+// bk.z, staged through NST stages s0, s1 (, s2).  Step s issues the copies of
+// step s + NST - 1 into the stage freed by step s - 1, then computes from its
+// own stage; the end-of-step wait covers only the copies of step s + 1, so
+// with NST = 3 the load latency hides behind two steps of MFMA work.
+template <bool BF16, int AF, int MAXR, int NST, class L>
+__device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
+                                          const float4* __restrict__ Alo,
+                                          const float4* __restrict__ R32,
+                                          const int* __restrict__ pairs, const Chi0Geom& g,
+                                          float* __restrict__ C, Blk3 bk, L& s0, L& s1, L& s2) {
   constexpr int NAC = 2 * AF;                 // A chunks per step (hi/lo or two f32 quads)
   constexpr int MAXA = (NAC + 3) / 4;         // A chunks per wave
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
+  // the wave index is uniform across the wave: keep it (and everything
+  // derived from it alone) in scalar registers
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ntb = g.n_tp / KSTEP;
   const int steps = ntb / g.ksplit;
   const int tb0 = bk.z * steps;
@@ -186,24 +210,28 @@ __device__ inline void bulk_tile(const float4* __restrict__ Ahi, const float4* _
   const int G = pk & 0xffff, Gp = pk >> 16;
   const int nr4 = g.n_g * 8;                  // float4 of one slab in global memory
   const int nrc = (g.n_g * SLAB_LD4 + 63) / 64;  // R chunks (padded rows) per step
-  const int abase = nrc * 64;                 // A fragments after the slab chunks
-  const int buf4 = abase + NAC * 64;
 
-  // Per-lane source offsets of this wave's chunks (K step added per step).
-  // R chunk c: LDS slot 64c + lane = padded row / column; pad slots read a
-  // harmless valid address and are never used.
+  // Per-lane source offset of this wave's R chunk i (K step added per step):
+  // LDS slot 64c + lane = padded row / column; pad slots read a harmless
+  // valid address and are never used.
   int r_off[MAXR];
 #pragma unroll
   for (int i = 0; i < MAXR; ++i) {
     const int slot = 64 * (wave + 4 * i) + lane;
-    const int row = slot / SLAB_LD4, col = slot % SLAB_LD4;
+    const int row = slot / SLAB_LD4, col = slot - row * SLAB_LD4;
     r_off[i] = (row < g.n_g && col < 8) ? row * 8 + col : 0;
   }
+  // A chunk of copy slot i: chunks beyond NAC repeat a real chunk (the same
+  // bytes to the same LDS place), so that every wave issues the same number
+  // of copies per step and every wait below is an exact compile-time count
+  auto a_chunk = [&](int i) {
+    const int c = wave + 4 * i;
+    return c < NAC ? c : c - NAC;
+  };
   const float4* a_src[MAXA];
 #pragma unroll
   for (int i = 0; i < MAXA; ++i) {
-    const int c = wave + 4 * i;
-    const int cc = c < NAC ? c : 0;
+    const int cc = a_chunk(i);
     const int f = cc >> 1, half = cc & 1;
     const size_t fr = (size_t)(rb0 + f) * ntb * 64 + lane;
     if constexpr (BF16)
@@ -212,18 +240,24 @@ __device__ inline void bulk_tile(const float4* __restrict__ Ahi, const float4* _
       a_src[i] = Ahi + fr * 2 + half;
   }
   constexpr int ASTEP = BF16 ? 64 : 128;  // float4 between K steps of one fragment
-  auto stage = [&](int tb, float4* buf) {
+  // Copies of K step tb into stage d: MAXR + MAXA per wave, always.  R
+  // chunks beyond the slab (c >= nrc) copy a valid row into the unused tail
+  // of the stage's R buffer (RCH = 4 MAXR chunks).
+  (void)nrc;
+  auto stage = [&](int tb, L& d) {
 #pragma unroll
-    for (int i = 0; i < MAXR; ++i) {
-      const int c = wave + 4 * i;
-      if (c < nrc) lds_dma16(R32 + (size_t)tb * nr4 + r_off[i], buf + 64 * c);
-    }
+    for (int i = 0; i < MAXR; ++i)
+      lds_dma16(R32 + (size_t)tb * nr4 + r_off[i], d.r + 64 * (wave + 4 * i));
 #pragma unroll
-    for (int i = 0; i < MAXA; ++i) {
-      const int c = wave + 4 * i;
-      if (c < NAC) lds_dma16(a_src[i] + (size_t)tb * ASTEP, buf + abase + 64 * c);
-    }
+    for (int i = 0; i < MAXA; ++i)
+      lds_dma16(a_src[i] + (size_t)tb * ASTEP, d.a + 64 * a_chunk(i));
   };
+  constexpr int NCOPY = MAXR + MAXA;  // copies per wave per stage (vmcnt of one stage)
+  // s_waitcnt with only the vector-memory counter limited (expcnt 7 and
+  // lgkmcnt 15 mean "no wait" in the gfx9 encoding)
+  constexpr int WAIT_ONE = (NCOPY & 15) | ((NCOPY >> 4) << 14) | (7 << 4) | (15 << 8);
+  constexpr int WAIT_ALL = (7 << 4) | (15 << 8);
+  const int tb_last = tb0 + steps - 1;
 
   f32x16 acc[AF][2];
 #pragma unroll
@@ -235,45 +269,20 @@ __device__ inline void bulk_tile(const float4* __restrict__ Ahi, const float4* _
     }
   }
 
-  stage(tb0, lds);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-
-  for (int st = 0; st < steps; ++st) {
-    const int tb = tb0 + st;
-    const float4* cur = lds + (st & 1) * buf4;
-    // 1. every LDS read of this step first ...
-    const float4* rG = cur + G * SLAB_LD4 + 4 * h;    // 8 complex = 4 float4
-    const float4* rGp = cur + Gp * SLAB_LD4 + 4 * h;
-    float4 xg[4], yg[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      xg[i] = rG[i];
-      yg[i] = rGp[i];
-    }
-    const float4* As = cur + abase;
-    float4 a0[AF], a1[AF];
-#pragma unroll
-    for (int f = 0; f < AF; ++f) {
-      a0[f] = As[f * 128 + lane];
-      a1[f] = As[f * 128 + 64 + lane];
-    }
-    // 2. ... then the copies of the next step into the other buffer (no LDS
-    // read follows them in this step, so no wait is needed before the MFMAs)
-    __builtin_amdgcn_sched_barrier(0);
-    if (st + 1 < steps) stage(tb + 1, lds + ((st + 1) & 1) * buf4);
-    __builtin_amdgcn_sched_barrier(0);
-    // 3. B operand: P_t(G, G') for this lane's pair and 8 transitions
+  auto compute = [&](const L& cur) {
+    // B operand: P_t(G, G') for this lane's pair and 8 transitions (FP32)
+    const float4* rG = cur.r + G * SLAB_LD4 + 4 * h;    // 8 complex = 4 float4
+    const float4* rGp = cur.r + Gp * SLAB_LD4 + 4 * h;
     float pre[8], pim[8];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float2 x0 = {xg[i].x, xg[i].y}, x1 = {xg[i].z, xg[i].w};
-      const float2 y0 = {yg[i].x, yg[i].y}, y1 = {yg[i].z, yg[i].w};
-      pre[2 * i] = x0.x * y0.x + x0.y * y0.y;
-      pim[2 * i] = x0.x * y0.y - x0.y * y0.x;
-      pre[2 * i + 1] = x1.x * y1.x + x1.y * y1.y;
-      pim[2 * i + 1] = x1.x * y1.y - x1.y * y1.x;
+      const float4 xg = rG[i], yg = rGp[i];
+      pre[2 * i] = xg.x * yg.x + xg.y * yg.y;
+      pim[2 * i] = xg.x * yg.y - xg.y * yg.x;
+      pre[2 * i + 1] = xg.z * yg.z + xg.w * yg.w;
+      pim[2 * i + 1] = xg.z * yg.w - xg.w * yg.z;
     }
+    const float4* As = cur.a;
     if constexpr (BF16) {
       bf16x8 bre_hi, bre_lo, bim_hi, bim_lo;
 #pragma unroll
@@ -287,12 +296,9 @@ __device__ inline void bulk_tile(const float4* __restrict__ Ahi, const float4* _
       }
       // three sweeps over the 2*AF independent accumulators, so that no MFMA
       // waits on the one issued just before it
-      bf16x8 ah[AF], al[AF];
+      bf16x8 ah[AF];
 #pragma unroll
-      for (int f = 0; f < AF; ++f) {
-        ah[f] = __builtin_bit_cast(bf16x8, a0[f]);
-        al[f] = __builtin_bit_cast(bf16x8, a1[f]);
-      }
+      for (int f = 0; f < AF; ++f) ah[f] = __builtin_bit_cast(bf16x8, As[f * 128 + lane]);
 #pragma unroll
       for (int f = 0; f < AF; ++f) {
         acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], bre_hi, acc[f][0], 0, 0, 0);
@@ -305,29 +311,63 @@ __device__ inline void bulk_tile(const float4* __restrict__ Ahi, const float4* _
       }
 #pragma unroll
       for (int f = 0; f < AF; ++f) {
-        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[f], bre_hi, acc[f][0], 0, 0, 0);
-        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[f], bim_hi, acc[f][1], 0, 0, 0);
+        const bf16x8 al = __builtin_bit_cast(bf16x8, As[f * 128 + 64 + lane]);
+        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bre_hi, acc[f][0], 0, 0, 0);
+        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bim_hi, acc[f][1], 0, 0, 0);
       }
     } else {
-      float av[AF][8];
 #pragma unroll
       for (int f = 0; f < AF; ++f) {
-        av[f][0] = a0[f].x; av[f][1] = a0[f].y; av[f][2] = a0[f].z; av[f][3] = a0[f].w;
-        av[f][4] = a1[f].x; av[f][5] = a1[f].y; av[f][6] = a1[f].z; av[f][7] = a1[f].w;
-      }
+        const float4 a0 = As[f * 128 + lane], a1 = As[f * 128 + 64 + lane];
+        const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-#pragma unroll
-        for (int f = 0; f < AF; ++f) {
-          acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[f][s], pre[s], acc[f][0], 0, 0, 0);
-          acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[f][s], pim[s], acc[f][1], 0, 0, 0);
+        for (int s = 0; s < 8; ++s) {
+          acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], pre[s], acc[f][0], 0, 0, 0);
+          acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], pim[s], acc[f][1], 0, 0, 0);
         }
       }
     }
+  };
+
+  // Workgroup barrier without the release fence of __syncthreads(): that
+  // fence would drain every outstanding copy into LDS, including those of
+  // step st + 2.  Each wave first waits for its own copies that the next
+  // step reads; the memory clobber keeps the compiler from moving LDS
+  // accesses across the barrier.
+  auto barrier = [] { asm volatile("s_barrier" ::: "memory"); };
+  auto one = [&](int st, const L& cur, L& nxt) {
+    // copies of step st + NST - 1 (past the end of the tile: the last step
+    // again, never read, so that the copy count stays uniform)
+    stage(min(tb0 + st + NST - 1, tb_last), nxt);
+    compute(cur);
     __builtin_amdgcn_sched_barrier(0);  // issue every MFMA of the step before waiting
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's LDS copies landed
-    __syncthreads();
+    // this wave's copies of step st + 1 landed (with NST = 3 those of st + 2
+    // may still be in flight); its LDS reads of `cur` completed
+    __builtin_amdgcn_s_waitcnt(NST == 3 ? WAIT_ONE : WAIT_ALL);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    barrier();
+  };
+
+  stage(tb0, s0);
+  if constexpr (NST == 3) {
+    stage(min(tb0 + 1, tb_last), s1);
+    __builtin_amdgcn_s_waitcnt(WAIT_ONE);
+  } else {
+    __builtin_amdgcn_s_waitcnt(WAIT_ALL);
   }
+  barrier();
+  for (int st = 0; st < steps; st += NST) {
+    if constexpr (NST == 3) {
+      one(st, s0, s2);
+      if (st + 1 < steps) one(st + 1, s1, s0);
+      if (st + 2 < steps) one(st + 2, s2, s1);
+    } else {
+      one(st, s0, s1);
+      if (st + 1 < steps) one(st + 1, s1, s0);
+    }
+  }
+  // the trailing copies must land before the LDS is reused or released
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 
   // epilogue: C[((ks*n_rowsp + row)*2 + ri)*n_bulkp + b]
 #pragma unroll
@@ -344,15 +384,20 @@ __device__ inline void bulk_tile(const float4* __restrict__ Ahi, const float4* _
   }
 }
 
-template <bool BF16, int AF, int MAXR>
-__global__ void __launch_bounds__(256) k_bulk(const float4* __restrict__ Ahi,
-                                              const float4* __restrict__ Alo,
-                                              const float4* __restrict__ R32,
-                                              const int* __restrict__ pairs, Chi0Geom g,
-                                              float* __restrict__ C) {
-  extern __shared__ float4 lds[];
+template <bool BF16, int AF, int MAXR, int NST>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_bulk(const float4* __restrict__ Ahi, const float4* __restrict__ Alo,
+       const float4* __restrict__ R32, const int* __restrict__ pairs, Chi0Geom g,
+       float* __restrict__ C) {
+  using L = BulkStage<4 * MAXR, 2 * AF>;
   const Blk3 bk = xcd_block(g.n_bulkp / 128, g.n_rowsp / (32 * AF), g.ksplit);
-  bulk_tile<BF16, AF, MAXR>(Ahi, Alo, R32, pairs, g, C, bk, lds);
+  if constexpr (NST == 3) {
+    __shared__ L s0, s1, s2;
+    bulk_tile<BF16, AF, MAXR, 3>(Ahi, Alo, R32, pairs, g, C, bk, s0, s1, s2);
+  } else {
+    __shared__ L s0, s1;
+    bulk_tile<BF16, AF, MAXR, 2>(Ahi, Alo, R32, pairs, g, C, bk, s0, s1, s0);
+  }
 }
 
 // Persistent form for a batch of uneven items: each block takes tiles from a
@@ -360,10 +405,11 @@ __global__ void __launch_bounds__(256) k_bulk(const float4* __restrict__ Ahi,
 // list is exhausted, so items with small N_G or few frequencies fill the gaps
 // left by large ones in one launch.
 template <bool BF16, int AF, int MAXR>
-__global__ void __launch_bounds__(256) k_bulk_persistent(const BulkItem* __restrict__ items,
-                                                         const int4* __restrict__ tiles,
-                                                         int n_tiles, int* counter) {
-  extern __shared__ float4 lds[];
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_bulk_persistent(const BulkItem* __restrict__ items, const int4* __restrict__ tiles, int n_tiles,
+                  int* counter) {
+  using L = BulkStage<4 * MAXR, 2 * AF>;
+  __shared__ L s0, s1;
   __shared__ int tix;
   for (;;) {
     if (threadIdx.x == 0) tix = atomicAdd(counter, 1);
@@ -372,32 +418,40 @@ __global__ void __launch_bounds__(256) k_bulk_persistent(const BulkItem* __restr
     if (t >= n_tiles) break;
     const int4 td = tiles[t];
     const BulkItem& it = items[td.x];
-    bulk_tile<BF16, AF, MAXR>(it.A, it.Alo, it.R32, it.pairs, it.g, it.C, Blk3{td.y, td.z, td.w},
-                              lds);
-    __syncthreads();  // tix and the LDS buffers are reused by the next tile
+    bulk_tile<BF16, AF, MAXR, 2>(it.A, it.Alo, it.R32, it.pairs, it.g, it.C,
+                                 Blk3{td.y, td.z, td.w}, s0, s1, s0);
+    __syncthreads();  // tix and the LDS stages are reused by the next tile
   }
 }
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
-template <bool BF16, int AF>
+size_t lds_bytes_of(int n_g, int af, int nst) {
+  const int maxr = bulk_maxr(n_g);
+  if (maxr == 0) return (size_t)1 << 40;  // no bucket: never fits
+  return (size_t)nst * sizeof(float4) * 64 * (4 * maxr + 2 * af);
+}
+
+template <bool BF16, int AF, int NST>
 void launch_bulk_t(const void* Ahi, const void* Alo, const float* R32, const int* pairs,
                    const Chi0Geom& g, float* C, hipStream_t st) {
   const dim3 grid((g.n_bulkp / 128) * (g.n_rowsp / (32 * AF)) * g.ksplit);
-  const int nrc = (g.n_g * SLAB_LD4 + 63) / 64;
-  const size_t lds = 2 * sizeof(float4) * ((size_t)nrc * 64 + 2 * AF * 64);
-  const int rpw = (nrc + 3) / 4;  // R chunks per wave
   const float4* ah = static_cast<const float4*>(Ahi);
   const float4* al = static_cast<const float4*>(Alo);
   const float4* r = reinterpret_cast<const float4*>(R32);
-  if (rpw <= 1)
-    hipLaunchKernelGGL((k_bulk<BF16, AF, 1>), grid, dim3(256), lds, st, ah, al, r, pairs, g, C);
-  else if (rpw <= 4)
-    hipLaunchKernelGGL((k_bulk<BF16, AF, 4>), grid, dim3(256), lds, st, ah, al, r, pairs, g, C);
-  else if (rpw <= 9)
-    hipLaunchKernelGGL((k_bulk<BF16, AF, 9>), grid, dim3(256), lds, st, ah, al, r, pairs, g, C);
-  else
-    hipLaunchKernelGGL((k_bulk<BF16, AF, 17>), grid, dim3(256), lds, st, ah, al, r, pairs, g, C);
+  switch (bulk_maxr(g.n_g)) {
+    case 1:
+      hipLaunchKernelGGL((k_bulk<BF16, AF, 1, NST>), grid, dim3(256), 0, st, ah, al, r, pairs, g, C);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_bulk<BF16, AF, 4, NST>), grid, dim3(256), 0, st, ah, al, r, pairs, g, C);
+      break;
+    case 9:
+      hipLaunchKernelGGL((k_bulk<BF16, AF, 9, NST>), grid, dim3(256), 0, st, ah, al, r, pairs, g, C);
+      break;
+    default:  // 17: two stages only (three do not fit in LDS)
+      hipLaunchKernelGGL((k_bulk<BF16, AF, 17, 2>), grid, dim3(256), 0, st, ah, al, r, pairs, g, C);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -624,6 +678,8 @@ __global__ void __launch_bounds__(256) k_pairs_mfma64(const cplx* __restrict__ R
 
 }  // namespace
 
+size_t bulk_lds_bytes(int n_g, int af, int nst) { return lds_bytes_of(n_g, af, nst); }
+
 void launch_transition_energies(const double* Ek, const double* Ekq, int n_k, int n_b, int n_occ,
                                 double* dt, hipStream_t st) {
   const int n = 2 * n_k * n_occ * (n_b - n_occ);
@@ -659,39 +715,47 @@ int bulk_row_frags(const Chi0Geom& g) {
 }
 
 void launch_bulk_f32(const float* Aw, const float* R32, const int* pairs, const Chi0Geom& g,
-                     float* C, hipStream_t st) {
-  if (g.n_rowsp % 160 == 0 && bulk_row_frags(g) == 5)
-    launch_bulk_t<false, 5>(Aw, nullptr, R32, pairs, g, C, st);
+                     int nst, float* C, hipStream_t st) {
+  const bool af5 = g.n_rowsp % 160 == 0 && bulk_row_frags(g) == 5;
+  if (af5 && nst == 3)
+    launch_bulk_t<false, 5, 3>(Aw, nullptr, R32, pairs, g, C, st);
+  else if (af5)
+    launch_bulk_t<false, 5, 2>(Aw, nullptr, R32, pairs, g, C, st);
+  else if (nst == 3)
+    launch_bulk_t<false, 4, 3>(Aw, nullptr, R32, pairs, g, C, st);
   else
-    launch_bulk_t<false, 4>(Aw, nullptr, R32, pairs, g, C, st);
+    launch_bulk_t<false, 4, 2>(Aw, nullptr, R32, pairs, g, C, st);
 }
 
 void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32,
-                      const int* pairs, const Chi0Geom& g, float* C, hipStream_t st) {
-  if (g.n_rowsp % 160 == 0 && bulk_row_frags(g) == 5)
-    launch_bulk_t<true, 5>(Ahi, Alo, R32, pairs, g, C, st);
+                      const int* pairs, const Chi0Geom& g, int nst, float* C, hipStream_t st) {
+  const bool af5 = g.n_rowsp % 160 == 0 && bulk_row_frags(g) == 5;
+  if (af5 && nst == 3)
+    launch_bulk_t<true, 5, 3>(Ahi, Alo, R32, pairs, g, C, st);
+  else if (af5)
+    launch_bulk_t<true, 5, 2>(Ahi, Alo, R32, pairs, g, C, st);
+  else if (nst == 3)
+    launch_bulk_t<true, 4, 3>(Ahi, Alo, R32, pairs, g, C, st);
   else
-    launch_bulk_t<true, 4>(Ahi, Alo, R32, pairs, g, C, st);
+    launch_bulk_t<true, 4, 2>(Ahi, Alo, R32, pairs, g, C, st);
 }
 
 void launch_bulk_persistent(bool bf16, const BulkItem* items, const int4* tiles, int n_tiles,
                             int* counter, int max_ng, int grid, hipStream_t st) {
   constexpr int AF = kBatchAF;
-  const int nrc = (max_ng * SLAB_LD4 + 63) / 64;
-  const size_t lds = 2 * sizeof(float4) * ((size_t)nrc * 64 + 2 * AF * 64);
-  const int rpw = (nrc + 3) / 4;
-#define QCX_PERSIST(B, R)                                                                   \
-  hipLaunchKernelGGL((k_bulk_persistent<B, AF, R>), dim3(grid), dim3(256), lds, st, items, \
+#define QCX_PERSIST(B, R)                                                                 \
+  hipLaunchKernelGGL((k_bulk_persistent<B, AF, R>), dim3(grid), dim3(256), 0, st, items, \
                      tiles, n_tiles, counter)
+  const int maxr = bulk_maxr(max_ng);
   if (bf16) {
-    if (rpw <= 1) QCX_PERSIST(true, 1);
-    else if (rpw <= 4) QCX_PERSIST(true, 4);
-    else if (rpw <= 9) QCX_PERSIST(true, 9);
+    if (maxr == 1) QCX_PERSIST(true, 1);
+    else if (maxr == 4) QCX_PERSIST(true, 4);
+    else if (maxr == 9) QCX_PERSIST(true, 9);
     else QCX_PERSIST(true, 17);
   } else {
-    if (rpw <= 1) QCX_PERSIST(false, 1);
-    else if (rpw <= 4) QCX_PERSIST(false, 4);
-    else if (rpw <= 9) QCX_PERSIST(false, 9);
+    if (maxr == 1) QCX_PERSIST(false, 1);
+    else if (maxr == 4) QCX_PERSIST(false, 4);
+    else if (maxr == 9) QCX_PERSIST(false, 9);
     else QCX_PERSIST(false, 17);
   }
 #undef QCX_PERSIST

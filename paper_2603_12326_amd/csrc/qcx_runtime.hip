@@ -8,8 +8,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
+
+#include <chrono>
 
 #include "ctx.h"
 
@@ -78,6 +83,24 @@ int qcx_set_timing(qcx_ctx* ctx, int enable) {
   HIPCK(spans_resolve(ctx));
   ctx->timing = enable != 0;
   for (double& t : ctx->t_acc) t = 0.0;
+  return QCX_OK;
+}
+
+int qcx_set_autotune(qcx_ctx* ctx, int mode) {
+  if (!ctx) return QCX_EINVAL;
+  if (mode != 0 && mode != 1) return fail(ctx, QCX_EINVAL, "mode must be 0 or 1");
+  ctx->autotune = mode;
+  return QCX_OK;
+}
+
+int qcx_bulk_config(qcx_ctx* ctx, int cfg[3], double* tune_ms) {
+  if (!ctx || !cfg) return QCX_EINVAL;
+  if (!ctx->have_chi0) return fail(ctx, QCX_ESTATE, "chi0 first");
+  const bool bulk = ctx->geom.n_bulk > 0;
+  cfg[0] = bulk ? ctx->geom.ksplit : 0;
+  cfg[1] = bulk ? ctx->bulk_nst : 0;
+  cfg[2] = bulk ? ctx->bulk_af : 0;
+  if (tune_ms) *tune_ms = ctx->tune_ms;
   return QCX_OK;
 }
 
@@ -347,6 +370,48 @@ static int pick_ksplit(int blocks, int steps) {
   return ks;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner of the bulk launch: per (device, precision, N_G, padded N_T,
+// padded rows) shape, every candidate (K split, LDS pipeline depth) is timed
+// on the real operands with HIP events and the fastest is kept for the
+// process.  The weights and R slabs are padded to a multiple of 256
+// transitions, so every K split up to 16 divides the same operands.
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+  int dev, prec, n_g, n_tp, n_rowsp, n_bulkp;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, prec, n_g, n_tp, n_rowsp, n_bulkp) <
+           std::tie(o.dev, o.prec, o.n_g, o.n_tp, o.n_rowsp, o.n_bulkp);
+  }
+};
+struct TuneVal {
+  int ks, nst;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+constexpr int kMaxKsplit = 16;
+constexpr size_t kMaxPartialBytes = (size_t)2 << 30;
+constexpr size_t kLdsBytes = 160 * 1024;
+
+struct Cand {
+  int ks, nst;
+};
+
+std::vector<Cand> bulk_candidates(const Chi0Geom& g, int af) {
+  std::vector<Cand> c;
+  const int ntb = g.n_tp / KSTEP_T;
+  for (int ks = 1; ks <= kMaxKsplit; ks *= 2) {
+    if (ks > 1 && ntb / ks < 4) break;
+    if ((size_t)ks * g.n_rowsp * 2 * g.n_bulkp * sizeof(float) > kMaxPartialBytes) break;
+    for (int nst = 2; nst <= 3; ++nst)
+      if (bulk_lds_bytes(g.n_g, af, nst) <= kLdsBytes) c.push_back({ks, nst});
+  }
+  return c;
+}
+}  // namespace
+
 int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int precision,
              int headwings_fp64, void* chi0_out) {
   if (!ctx) return QCX_EINVAL;
@@ -395,10 +460,33 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
     const int af = bulk_row_frags(g);
     g.n_rowsp = (int)roundup(g.n_rows, 32 * af);
     const int blocks = (g.n_bulkp / 128) * (g.n_rowsp / (32 * af));
-    g.ksplit = pick_ksplit(blocks, (int)roundup(g.n_t, 16) / 16);
-    g.n_tp = (int)roundup(g.n_t, 16 * g.ksplit);
+    g.n_tp = (int)roundup(g.n_t, KSTEP_T * kMaxKsplit);
+    const std::vector<Cand> cands = bulk_candidates(g, af);
+    if (cands.empty()) return fail(ctx, QCX_EINVAL, "no bulk tile configuration fits");
+    // heuristic choice, used when tuning is off, under graph capture, or as
+    // the candidate to beat
+    Cand pick{pick_ksplit(blocks, g.n_tp / KSTEP_T), 2};
+    if (std::none_of(cands.begin(), cands.end(),
+                     [&](const Cand& c) { return c.ks == pick.ks && c.nst == pick.nst; }))
+      pick = cands.front();
+    const TuneKey key{ctx->device, precision, g.n_g, g.n_tp, g.n_rowsp, g.n_bulkp};
+    bool tune = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end())
+        pick = {it->second.ks, it->second.nst};
+      else
+        tune = ctx->autotune != 0;
+    }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCK(hipStreamIsCapturing(st, &cap));
+    if (cap != hipStreamCaptureStatusNone) tune = false;
+    int max_ks = pick.ks;
+    if (tune)
+      for (const Cand& c : cands) max_ks = std::max(max_ks, c.ks);
     const size_t nA = (size_t)g.n_rowsp * g.n_tp;  // elements
-    const size_t nC = (size_t)g.ksplit * g.n_rowsp * 2 * g.n_bulkp;
+    const size_t nC = (size_t)max_ks * g.n_rowsp * 2 * g.n_bulkp;
     HIPCK(ctx->d_R32.reserve(sizeof(float) * 2 * (size_t)g.n_g * g.n_tp));
     HIPCK(ctx->d_C.reserve(sizeof(float) * nC));
     std::vector<int> pairs(g.n_bulkp, 0);
@@ -422,13 +510,51 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
                          ctx->d_A.as<float>(), st);
     }
     LAUNCHCK("weights/pack");
+    auto run_bulk = [&](const Cand& c) {
+      g.ksplit = c.ks;
+      if (bf)
+        launch_bulk_bf16(ctx->d_A.as<uint16_t>(), ctx->d_Alo.as<uint16_t>(),
+                         ctx->d_R32.as<float>(), ctx->d_pairs.as<int>(), g, c.nst,
+                         ctx->d_C.as<float>(), st);
+      else
+        launch_bulk_f32(ctx->d_A.as<float>(), ctx->d_R32.as<float>(), ctx->d_pairs.as<int>(), g,
+                        c.nst, ctx->d_C.as<float>(), st);
+    };
+    ctx->tune_ms = 0.0;
+    if (tune) {
+      const auto t0 = std::chrono::steady_clock::now();
+      hipEvent_t e0, e1;
+      HIPCK(hipEventCreate(&e0));
+      HIPCK(hipEventCreate(&e1));
+      float best = 1e30f;
+      for (const Cand& c : cands) {
+        run_bulk(c);  // warm
+        HIPCK(hipEventRecord(e0, st));
+        run_bulk(c);
+        run_bulk(c);
+        HIPCK(hipEventRecord(e1, st));
+        LAUNCHCK("bulk (tuning)");
+        HIPCK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          pick = c;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = {pick.ks, pick.nst};
+      }
+      ctx->tune_ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    ctx->bulk_nst = pick.nst;
+    ctx->bulk_af = af;
     HIPCK(span_begin(ctx, 1, &sp_bulk));
-    if (bf)
-      launch_bulk_bf16(ctx->d_A.as<uint16_t>(), ctx->d_Alo.as<uint16_t>(), ctx->d_R32.as<float>(),
-                       ctx->d_pairs.as<int>(), g, ctx->d_C.as<float>(), st);
-    else
-      launch_bulk_f32(ctx->d_A.as<float>(), ctx->d_R32.as<float>(), ctx->d_pairs.as<int>(), g,
-                      ctx->d_C.as<float>(), st);
+    run_bulk(pick);
     LAUNCHCK("bulk");
     HIPCK(span_end(ctx, sp_bulk));
   } else {

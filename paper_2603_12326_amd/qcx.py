@@ -56,6 +56,8 @@ _SIGS = {
     "qcx_stage_times": [_P, _P],
     "qcx_set_timing": [_P, _I],
     "qcx_build_info": [],
+    "qcx_set_autotune": [_P, _I],
+    "qcx_bulk_config": [_P, _P, _P],
     "qcx_run_batch": [_P, _I, _P, _I, _I, _I, _I],
     "qcx_batch_sync": [_P],
     "qcx_mlp_create": [ctypes.POINTER(_P), _P, _I],
@@ -246,6 +248,16 @@ class Context:
 
     def set_timing(self, enable: bool = True):
         self._check(self.lib.qcx_set_timing(self._h, 1 if enable else 0))
+
+    def set_autotune(self, mode: int = 1):
+        self._check(self.lib.qcx_set_autotune(self._h, int(mode)))
+
+    def bulk_config(self) -> dict:
+        cfg = np.zeros(3, np.int32)
+        ms = ctypes.c_double(0.0)
+        self._check(self.lib.qcx_bulk_config(self._h, _ptr_host(cfg), ctypes.byref(ms)))
+        return dict(ksplit=int(cfg[0]), stages=int(cfg[1]), row_frags=int(cfg[2]),
+                    tune_ms=ms.value)
 
     def stage_times(self) -> dict:
         t = np.zeros(6, np.float64)
