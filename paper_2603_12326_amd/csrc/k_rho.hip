@@ -13,6 +13,9 @@
 // phase_sum (the 27-cell Bloch sum, one thread per AO pair element holding its
 // 27 lattice terms in registers while it walks over k), band_contract (one
 // block per k and G tile; C(k), C(k+q) and one M(k;Q) staged in LDS).
+#include <algorithm>
+#include <utility>
+
 #include "common.h"
 
 namespace qcx {
@@ -289,67 +292,132 @@ __global__ void __launch_bounds__(256) k_phase_sum_any(const cplx* __restrict__ 
   }
 }
 
-constexpr int kGTile = 8;
+// Band contraction.  A block owns one k and a contiguous range of G tiles
+// (GT vectors each); C(k) and C(k+q) are staged in LDS once and read as
+// broadcasts.  Per tile:
+//   step 1: T1_G[mu][b] = sum_nu M_G[mu][nu] C_k[nu][b]; a thread owns
+//           (G, mu, BQ consecutive b) and keeps its BQ sums in registers, so
+//           one LDS read of M feeds BQ complex multiply-adds.  M rows are
+//           padded to n_ao + 1 in LDS (consecutive rows then start in
+//           different banks);
+//   step 2: rho_G[v][c] = sum_mu conj(C_kq[mu][n_occ+c]) T1_G[mu][v] and
+//           sigma_G[v][c] = sum_mu conj(C_kq[mu][v]) T1_G[mu][n_occ+c],
+//           written to R[g][t], t = ((s*n_k + k)*n_occ + v)*n_cond + c.
+// The next tile's M is loaded into registers while the current one is
+// computed (MPF = per-thread capacity in complex values; when a tile does
+// not fit, the remainder is loaded synchronously).
+// ALIAS: every thread owns at most one step-1 item, so T1 overwrites the M
+// tile after a barrier (less LDS, larger tiles).
+constexpr int kBQ = 10;
+constexpr int kMPF = 16;
 
-// One block per (k, tile of kGTile G).  LDS: C(k), C(k+q), M(k;Q), T1 = M C(k).
-// Writes R[g][t] for t = ((s*n_k + k)*n_occ + v)*n_cond + c.
+template <int GT, bool ALIAS>
 __global__ void __launch_bounds__(256) k_band_contract(const cplx* __restrict__ M,
                                                        const cplx* __restrict__ Ck,
                                                        const cplx* __restrict__ Ckq, int n_ao,
                                                        int n_b, int n_occ, int n_k, int k0,
-                                                       int n_g, cplx* __restrict__ R,
-                                                       size_t ldt) {
+                                                       int n_g, int tiles_per_block,
+                                                       cplx* __restrict__ R, size_t ldt) {
   extern __shared__ cplx lds[];
   const int kk = blockIdx.x;   // index inside the chunk
   const int k = k0 + kk;
-  const int g0 = blockIdx.y * kGTile;
+  const int n_tiles = (n_g + GT - 1) / GT;
+  const int tile0 = blockIdx.y * tiles_per_block;
+  const int tile1 = min(n_tiles, tile0 + tiles_per_block);
   const int n_c = n_b - n_occ;
-  const int nab = n_ao * n_b, naa = n_ao * n_ao;
+  const int nab = n_ao * n_b, naa = n_ao * n_ao, lda = n_ao + 1;
+  const int nthr = blockDim.x, tid = threadIdx.x;
   cplx* sCk = lds;
   cplx* sCq = sCk + nab;
-  cplx* sM = sCq + nab;
-  cplx* sT = sM + naa;
-  for (int i = threadIdx.x; i < nab; i += blockDim.x) {
+  cplx* sM = sCq + nab;                                   // [GT][n_ao][lda]
+  cplx* sT = ALIAS ? sM : sM + (size_t)GT * n_ao * lda;   // [GT][n_ao][n_b]
+  for (int i = tid; i < nab; i += nthr) {
     sCk[i] = Ck[(size_t)kk * nab + i];   // Ck, Ckq already offset to the chunk
     sCq[i] = Ckq[(size_t)kk * nab + i];
   }
-  const size_t nvc = (size_t)n_occ * n_c;
+  const int nbq = (n_b + kBQ - 1) / kBQ;
+  const int nvc = n_occ * n_c;
   const size_t t_res = (size_t)k * nvc;
   const size_t t_anti = ((size_t)n_k + k) * nvc;
-  for (int gi = 0; gi < kGTile; ++gi) {
-    const int g = g0 + gi;
-    if (g >= n_g) break;
+
+  // register prefetch of a tile's M (element i of the tile = tid + j*nthr)
+  cplx pf[kMPF];
+  auto fetch = [&](int tile) {
+    const int g0 = tile * GT, ng = min(GT, n_g - g0);
+    const cplx* Mk = M + ((size_t)kk * n_g + g0) * naa;
+#pragma unroll
+    for (int j = 0; j < kMPF; ++j) {
+      const int i = tid + j * nthr;
+      if (i < ng * naa) pf[j] = Mk[i];
+    }
+  };
+  auto put = [&](int tile) {
+    const int g0 = tile * GT, ng = min(GT, n_g - g0);
+    const cplx* Mk = M + ((size_t)kk * n_g + g0) * naa;
+    auto store = [&](int i, cplx v) {
+      const int g = i / naa, e = i - g * naa;
+      const int mu = e / n_ao, nu = e - mu * n_ao;
+      sM[(g * n_ao + mu) * lda + nu] = v;
+    };
+#pragma unroll
+    for (int j = 0; j < kMPF; ++j) {
+      const int i = tid + j * nthr;
+      if (i < ng * naa) store(i, pf[j]);
+    }
+    for (int i = tid + kMPF * nthr; i < ng * naa; i += nthr) store(i, Mk[i]);
+  };
+  if (tile0 < tile1) fetch(tile0);
+  for (int tile = tile0; tile < tile1; ++tile) {
+    const int g0 = tile * GT, ng = min(GT, n_g - g0);
+    __syncthreads();  // the previous tile's step 2 has finished with the LDS
+    put(tile);
     __syncthreads();
-    const cplx* Mg = M + ((size_t)kk * n_g + g) * naa;
-    for (int i = threadIdx.x; i < naa; i += blockDim.x) sM[i] = Mg[i];
-    __syncthreads();
-    // T1[mu][b] = sum_nu M[mu][nu] C_k[nu][b]
-    for (int i = threadIdx.x; i < nab; i += blockDim.x) {
-      const int mu = i / n_b, b = i % n_b;
-      double re = 0.0, im = 0.0;
-      for (int nu = 0; nu < n_ao; ++nu) {
-        const cplx m = sM[mu * n_ao + nu], c = sCk[nu * n_b + b];
-        re += m.re * c.re - m.im * c.im;
-        im += m.re * c.im + m.im * c.re;
+    if (tile + 1 < tile1) fetch(tile + 1);  // in flight during this tile's work
+    // step 1
+    const int n_items = ng * n_ao * nbq;
+    for (int w0 = 0; w0 < n_items; w0 += nthr) {
+      const int w = w0 + tid;
+      const bool live = w < n_items;
+      const int g = live ? w / (n_ao * nbq) : 0, rem = live ? w - g * n_ao * nbq : 0;
+      const int mu = rem / nbq, b0 = (rem - mu * nbq) * kBQ;
+      double re[kBQ], im[kBQ];
+#pragma unroll
+      for (int j = 0; j < kBQ; ++j) re[j] = im[j] = 0.0;
+      const cplx* mrow = sM + (g * n_ao + mu) * lda;
+      for (int nu = 0; nu < (live ? n_ao : 0); ++nu) {
+        const cplx m = mrow[nu];
+        const cplx* crow = sCk + nu * n_b + b0;
+#pragma unroll
+        for (int j = 0; j < kBQ; ++j) {
+          if (b0 + j < n_b) {
+            const cplx c = crow[j];
+            re[j] += m.re * c.re - m.im * c.im;
+            im[j] += m.re * c.im + m.im * c.re;
+          }
+        }
       }
-      sT[i] = {re, im};
+      if (ALIAS) __syncthreads();  // every read of M done before T1 overwrites it
+      cplx* trow = sT + (g * n_ao + mu) * n_b + b0;
+#pragma unroll
+      for (int j = 0; j < kBQ; ++j)
+        if (live && b0 + j < n_b) trow[j] = {re[j], im[j]};
     }
     __syncthreads();
-    // rho[v][c] = sum_mu conj(Ckq[mu][n_occ+c]) T1[mu][v]
-    // sigma[v][c] = sum_mu conj(Ckq[mu][v]) T1[mu][n_occ+c]
-    cplx* Rg = R + (size_t)g * ldt;
-    for (int i = threadIdx.x; i < 2 * (int)nvc; i += blockDim.x) {
-      const int s = i / (int)nvc, vc = i % (int)nvc;
-      const int v = vc / n_c, c = vc % n_c;
+    // step 2
+    for (int w = tid; w < ng * 2 * nvc; w += nthr) {
+      const int g = w / (2 * nvc), i = w - g * 2 * nvc;
+      const int s = i / nvc, vc = i - s * nvc;
+      const int v = vc / n_c, c = vc - v * n_c;
       const int bra = s == 0 ? n_occ + c : v;
       const int ket = s == 0 ? v : n_occ + c;
+      const cplx* T = sT + (size_t)g * n_ao * n_b;
       double re = 0.0, im = 0.0;
       for (int mu = 0; mu < n_ao; ++mu) {
-        const cplx a = sCq[mu * n_b + bra], t = sT[mu * n_b + ket];
+        const cplx a = sCq[mu * n_b + bra], t = T[mu * n_b + ket];
         re += a.re * t.re + a.im * t.im;
         im += a.re * t.im - a.im * t.re;
       }
-      Rg[(s == 0 ? t_res : t_anti) + vc] = {re, im};
+      R[(size_t)(g0 + g) * ldt + (s == 0 ? t_res : t_anti) + vc] = {re, im};
     }
   }
 }
@@ -433,17 +501,49 @@ void launch_phase_sum(const cplx* F, const cplx* ph, int n_t, int n_q, int n_e, 
   }
 }
 
+static size_t band_lds(int n_ao, int n_b, int gt, bool alias) {
+  const size_t m = (size_t)gt * n_ao * (n_ao + 1), t = (size_t)gt * n_ao * n_b;
+  return sizeof(cplx) * (2 * (size_t)n_ao * n_b + (alias ? std::max(m, t) : m + t));
+}
+
+// the single-G tile without aliasing is the floor: the configuration check
+// uses it
 size_t band_contract_lds(int n_ao, int n_b, int /*n_occ*/) {
-  return sizeof(cplx) * (3 * (size_t)n_ao * n_b + (size_t)n_ao * n_ao);
+  return band_lds(n_ao, n_b, 1, false);
 }
 
 void launch_band_contract(const cplx* M, const cplx* Ck, const cplx* Ckq, int n_ao, int n_b,
                           int n_occ, int n_k, int k0, int nk, int n_g, cplx* R, size_t ldt,
                           hipStream_t st) {
-  const size_t lds = band_contract_lds(n_ao, n_b, n_occ);
-  const dim3 grid(nk, (n_g + kGTile - 1) / kGTile);
-  hipLaunchKernelGGL(k_band_contract, grid, dim3(256), lds, st, M, Ck + (size_t)k0 * n_ao * n_b,
-                     Ckq + (size_t)k0 * n_ao * n_b, n_ao, n_b, n_occ, n_k, k0, n_g, R, ldt);
+  const cplx* ck = Ck + (size_t)k0 * n_ao * n_b;
+  const cplx* cq = Ckq + (size_t)k0 * n_ao * n_b;
+  const int nbq = (n_b + kBQ - 1) / kBQ;
+  const size_t cap = 80 * 1024;  // two blocks per CU
+  // G tiles of each k shared out over enough blocks to fill the chip
+  auto grid_y = [&](int gt) {
+    const int n_tiles = (n_g + gt - 1) / gt;
+    const int want = std::max(1, std::min(n_tiles, (2048 + nk - 1) / nk));
+    return std::make_pair((n_tiles + want - 1) / want, want);
+  };
+  // the largest G tile that keeps one step-1 item per thread and two blocks
+  // per CU; otherwise single-G tiles
+#define QCX_BC(GT, AL)                                                                          \
+  do {                                                                                          \
+    const auto tb = grid_y(GT);                                                                 \
+    hipLaunchKernelGGL((k_band_contract<GT, AL>), dim3(nk, (unsigned)((n_g + GT - 1) / GT +    \
+                                                                      tb.first - 1) / tb.first), \
+                       dim3(256), band_lds(n_ao, n_b, GT, AL), st, M, ck, cq, n_ao, n_b, n_occ,   \
+                       n_k, k0, n_g, tb.first, R, ldt);                                         \
+  } while (0)
+  if (4 * n_ao * nbq <= 256 && band_lds(n_ao, n_b, 4, true) <= cap)
+    QCX_BC(4, true);
+  else if (2 * n_ao * nbq <= 256 && band_lds(n_ao, n_b, 2, true) <= cap)
+    QCX_BC(2, true);
+  else if (n_ao * nbq <= 256)
+    QCX_BC(1, true);
+  else
+    QCX_BC(1, false);
+#undef QCX_BC
 }
 
 void launch_orth_check(const cplx* S, const cplx* C, int n_ao, int n_b, int n_k, double* dev,

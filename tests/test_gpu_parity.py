@@ -164,3 +164,26 @@ def test_large_ng_blocked_inversion(ctx, n_g):
     print("n_g", n_g, "fp64", e64, "split", esp)
     assert e64 < 1e-10
     assert esp < 1e-4
+
+
+def test_autotuned_bulk(ctx, cfg1):
+    """The bulk autotuner: the first call of a new shape times every candidate
+    (tune_ms > 0), later calls reuse the choice (tune_ms == 0); the heuristic
+    configuration and the tuned one both meet the oracle bar."""
+    w = np.linspace(0.5, 35.0, 77)            # 77 frequencies: a shape no other test uses
+    ref = _oracle(cfg1, w=w)
+    ctx.set_autotune(1)
+    a = gpu_solve(ctx, cfg1, precision="split_bf16", w_eV=w)
+    c1 = ctx.bulk_config()
+    b = gpu_solve(ctx, cfg1, precision="split_bf16", w_eV=w)
+    c2 = ctx.bulk_config()
+    print("tuned", c1, "then", c2)
+    assert c1["tune_ms"] > 0.0 and c2["tune_ms"] == 0.0
+    assert (c1["ksplit"], c1["stages"]) == (c2["ksplit"], c2["stages"])
+    assert c1["ksplit"] in (1, 2, 4, 8, 16) and c1["stages"] in (2, 3) and c1["row_frags"] in (4, 5)
+    assert np.array_equal(a["loss"], b["loss"])
+    ctx.set_autotune(0)
+    h = gpu_solve(ctx, cfg1, precision="split_bf16", w_eV=w)
+    ctx.set_autotune(1)
+    for out in (a, h):
+        assert normwise(out["loss"], ref["loss"]) < 1e-4
