@@ -273,7 +273,8 @@ int qcx_mlp_query(qcx_mlp* m, int n, const double* qw, double* loss, double* err
  * partial sums - is timed on the real operands with HIP events and the
  * fastest is kept for the process; that call synchronises the stream.  The
  * result used is always computed with the chosen configuration.  mode 0: a
- * fixed heuristic.  Tuning is skipped while the stream is being captured.
+ * fixed heuristic.  Tuning is skipped while the stream is being captured and
+ * for shapes whose single launch is estimated above 0.5 s.
  * Errors: QCX_EINVAL (mode). */
 int qcx_set_autotune(qcx_ctx* ctx, int mode);
 /* Configuration of the last bulk launch: cfg = {K split, pipeline stages,

@@ -85,6 +85,7 @@ struct Chi0Geom {
   int p0;                   // first bulk pair (n_g when head/wings run in FP64)
   int n_bulk, n_bulkp;      // bulk pairs and padded count
   int ksplit;
+  int gather;               // 1: per-tile row lists (N_G >= kGatherMinNg)
 };
 // transition energies Delta_t (Ha) and signs for t in [0, n_t)
 void launch_transition_energies(const double* Ek, const double* Ekq, int n_k, int n_b, int n_occ,
@@ -98,28 +99,41 @@ void launch_weights_bf16(const double* w, const double* dt, double eta, const Ch
 void launch_pack_r32(const cplx* R, size_t ldt, const Chi0Geom& g, int perm, float* R32,
                      hipStream_t st);
 constexpr int KSTEP_T = 16;  // transitions per bulk K step (one MFMA K block)
+// Row-gather mode of the bulk kernel: a tile of 128 consecutive upper-triangle
+// pairs touches at most 129 distinct G (checked when the tables are built),
+// so for large N_G each tile stages only its own slab rows, listed in
+// rows[tile][kGatherRows], and the pair table holds tile-local indices.
+constexpr int kGatherRows = 129;
+constexpr int kGatherMinNg = 129;
+// Fill the local pair table and the per-tile row lists from the global pair
+// table (G | G' << 16 per bulk column, n_bulkp columns).  Returns false if a
+// tile needs more than kGatherRows rows (it cannot: see above).
+bool bulk_gather_tables(const std::vector<int>& pairs_global, std::vector<int>& pairs_local,
+                        std::vector<int>& rows);
 int bulk_row_frags(const Chi0Geom& g);
 // LDS bytes of one bulk block: nst pipeline stages of the R slab (n_g rows)
 // and af A fragment pairs
 size_t bulk_lds_bytes(int n_g, int af, int nst);
 // bulk launches; nst = 2 or 3 LDS pipeline stages
-void launch_bulk_f32(const float* Aw, const float* R32, const int* pairs, const Chi0Geom& g,
-                     int nst, float* C, hipStream_t st);
+void launch_bulk_f32(const float* Aw, const float* R32, const int* pairs, const int* rows,
+                     const Chi0Geom& g, int nst, float* C, hipStream_t st);
 void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32,
-                      const int* pairs, const Chi0Geom& g, int nst, float* C, hipStream_t st);
+                      const int* pairs, const int* rows, const Chi0Geom& g, int nst, float* C,
+                      hipStream_t st);
 // One item of a batched bulk launch (its own weights, R, pairs and partials).
 struct BulkItem {
   const float4* A;
   const float4* Alo;
   const float4* R32;
   const int* pairs;
+  const int* rows;   // per-tile row lists (gather mode) or NULL
   Chi0Geom g;
   float* C;
 };
 // Persistent bulk kernel over tiles {item, pair tile, row tile, K split};
 // AF = 4 row fragments; max_ng sizes the LDS.
-void launch_bulk_persistent(bool bf16, const BulkItem* items, const int4* tiles, int n_tiles,
-                            int* counter, int max_ng, int grid, hipStream_t st);
+void launch_bulk_persistent(bool bf16, bool gather, const BulkItem* items, const int4* tiles,
+                            int n_tiles, int* counter, int max_ng, int grid, hipStream_t st);
 void launch_set_int(int* p, int v, hipStream_t st);
 constexpr int kBatchAF = 4;
 

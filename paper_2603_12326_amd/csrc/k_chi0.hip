@@ -14,6 +14,9 @@
 // multiply-adds of the plain complex product.  A is precomputed per q in the
 // MFMA fragment order; B is formed on the fly from R in FP32 (and split into
 // bf16 hi + lo for the split path) inside the kernel.
+#include <algorithm>
+#include <vector>
+
 #include "common.h"
 
 namespace qcx {
@@ -178,10 +181,12 @@ struct BulkStage {
   float4 a[NAC * 64];
 };
 
-// R chunks per wave (template bucket) for n_g slab rows
+// R chunks per wave (template bucket) for n_g slab rows; gather mode stages
+// kGatherRows rows
 inline int bulk_maxr(int n_g) {
-  const int rpw = ((n_g * SLAB_LD4 + 63) / 64 + 3) / 4;
-  return rpw <= 1 ? 1 : rpw <= 4 ? 4 : rpw <= 9 ? 9 : rpw <= 17 ? 17 : 0;
+  const int rows = n_g >= kGatherMinNg ? kGatherRows : n_g;
+  const int rpw = ((rows * SLAB_LD4 + 63) / 64 + 3) / 4;
+  return rpw <= 1 ? 1 : rpw <= 4 ? 4 : 5;
 }
 
 // One block tile of the bulk GEMM: pair tile bk.x, row tile bk.y, K split
@@ -189,11 +194,12 @@ inline int bulk_maxr(int n_g) {
 // step s + NST - 1 into the stage freed by step s - 1, then computes from its
 // own stage; the end-of-step wait covers only the copies of step s + 1, so
 // with NST = 3 the load latency hides behind two steps of MFMA work.
-template <bool BF16, int AF, int MAXR, int NST, class L>
+template <bool BF16, int AF, int MAXR, int NST, bool GATHER, class L>
 __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
                                           const float4* __restrict__ Alo,
                                           const float4* __restrict__ R32,
-                                          const int* __restrict__ pairs, const Chi0Geom& g,
+                                          const int* __restrict__ pairs,
+                                          const int* __restrict__ rows, const Chi0Geom& g,
                                           float* __restrict__ C, Blk3 bk, L& s0, L& s1, L& s2) {
   constexpr int NAC = 2 * AF;                 // A chunks per step (hi/lo or two f32 quads)
   constexpr int MAXA = (NAC + 3) / 4;         // A chunks per wave
@@ -209,7 +215,10 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
   const int pk = pairs[b];
   const int G = pk & 0xffff, Gp = pk >> 16;
   const int nr4 = g.n_g * 8;                  // float4 of one slab in global memory
-  const int nrc = (g.n_g * SLAB_LD4 + 63) / 64;  // R chunks (padded rows) per step
+  // slab rows staged per step: all n_g, or the tile's own rows (gather mode;
+  // G and G' above are then indices into the tile's row list)
+  const int n_rows_st = GATHER ? kGatherRows : g.n_g;
+  const int* trows = GATHER ? rows + (size_t)bk.x * kGatherRows : nullptr;
 
   // Per-lane source offset of this wave's R chunk i (K step added per step):
   // LDS slot 64c + lane = padded row / column; pad slots read a harmless
@@ -219,7 +228,8 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
   for (int i = 0; i < MAXR; ++i) {
     const int slot = 64 * (wave + 4 * i) + lane;
     const int row = slot / SLAB_LD4, col = slot - row * SLAB_LD4;
-    r_off[i] = (row < g.n_g && col < 8) ? row * 8 + col : 0;
+    const bool ok = row < n_rows_st && col < 8;
+    r_off[i] = ok ? (GATHER ? trows[row] : row) * 8 + col : 0;
   }
   // A chunk of copy slot i: chunks beyond NAC repeat a real chunk (the same
   // bytes to the same LDS place), so that every wave issues the same number
@@ -241,9 +251,8 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
   }
   constexpr int ASTEP = BF16 ? 64 : 128;  // float4 between K steps of one fragment
   // Copies of K step tb into stage d: MAXR + MAXA per wave, always.  R
-  // chunks beyond the slab (c >= nrc) copy a valid row into the unused tail
-  // of the stage's R buffer (RCH = 4 MAXR chunks).
-  (void)nrc;
+  // chunks beyond the slab copy a valid row into the unused tail of the
+  // stage's R buffer (RCH = 4 MAXR chunks).
   auto stage = [&](int tb, L& d) {
 #pragma unroll
     for (int i = 0; i < MAXR; ++i)
@@ -384,19 +393,19 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
   }
 }
 
-template <bool BF16, int AF, int MAXR, int NST>
+template <bool BF16, int AF, int MAXR, int NST, bool GATHER>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_bulk(const float4* __restrict__ Ahi, const float4* __restrict__ Alo,
-       const float4* __restrict__ R32, const int* __restrict__ pairs, Chi0Geom g,
-       float* __restrict__ C) {
+       const float4* __restrict__ R32, const int* __restrict__ pairs,
+       const int* __restrict__ rows, Chi0Geom g, float* __restrict__ C) {
   using L = BulkStage<4 * MAXR, 2 * AF>;
   const Blk3 bk = xcd_block(g.n_bulkp / 128, g.n_rowsp / (32 * AF), g.ksplit);
   if constexpr (NST == 3) {
     __shared__ L s0, s1, s2;
-    bulk_tile<BF16, AF, MAXR, 3>(Ahi, Alo, R32, pairs, g, C, bk, s0, s1, s2);
+    bulk_tile<BF16, AF, MAXR, 3, GATHER>(Ahi, Alo, R32, pairs, rows, g, C, bk, s0, s1, s2);
   } else {
     __shared__ L s0, s1;
-    bulk_tile<BF16, AF, MAXR, 2>(Ahi, Alo, R32, pairs, g, C, bk, s0, s1, s0);
+    bulk_tile<BF16, AF, MAXR, 2, GATHER>(Ahi, Alo, R32, pairs, rows, g, C, bk, s0, s1, s0);
   }
 }
 
@@ -404,7 +413,7 @@ k_bulk(const float4* __restrict__ Ahi, const float4* __restrict__ Alo,
 // global list (ordered by decreasing cost) with an atomic counter until the
 // list is exhausted, so items with small N_G or few frequencies fill the gaps
 // left by large ones in one launch.
-template <bool BF16, int AF, int MAXR>
+template <bool BF16, int AF, int MAXR, bool GATHER>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_bulk_persistent(const BulkItem* __restrict__ items, const int4* __restrict__ tiles, int n_tiles,
                   int* counter) {
@@ -418,8 +427,8 @@ k_bulk_persistent(const BulkItem* __restrict__ items, const int4* __restrict__ t
     if (t >= n_tiles) break;
     const int4 td = tiles[t];
     const BulkItem& it = items[td.x];
-    bulk_tile<BF16, AF, MAXR, 2>(it.A, it.Alo, it.R32, it.pairs, it.g, it.C,
-                                 Blk3{td.y, td.z, td.w}, s0, s1, s0);
+    bulk_tile<BF16, AF, MAXR, 2, GATHER>(it.A, it.Alo, it.R32, it.pairs, it.rows, it.g, it.C,
+                                         Blk3{td.y, td.z, td.w}, s0, s1, s0);
     __syncthreads();  // tix and the LDS stages are reused by the next tile
   }
 }
@@ -434,24 +443,22 @@ size_t lds_bytes_of(int n_g, int af, int nst) {
 
 template <bool BF16, int AF, int NST>
 void launch_bulk_t(const void* Ahi, const void* Alo, const float* R32, const int* pairs,
-                   const Chi0Geom& g, float* C, hipStream_t st) {
+                   const int* rows, const Chi0Geom& g, float* C, hipStream_t st) {
   const dim3 grid((g.n_bulkp / 128) * (g.n_rowsp / (32 * AF)) * g.ksplit);
   const float4* ah = static_cast<const float4*>(Ahi);
   const float4* al = static_cast<const float4*>(Alo);
   const float4* r = reinterpret_cast<const float4*>(R32);
-  switch (bulk_maxr(g.n_g)) {
-    case 1:
-      hipLaunchKernelGGL((k_bulk<BF16, AF, 1, NST>), grid, dim3(256), 0, st, ah, al, r, pairs, g, C);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_bulk<BF16, AF, 4, NST>), grid, dim3(256), 0, st, ah, al, r, pairs, g, C);
-      break;
-    case 9:
-      hipLaunchKernelGGL((k_bulk<BF16, AF, 9, NST>), grid, dim3(256), 0, st, ah, al, r, pairs, g, C);
-      break;
-    default:  // 17: two stages only (three do not fit in LDS)
-      hipLaunchKernelGGL((k_bulk<BF16, AF, 17, 2>), grid, dim3(256), 0, st, ah, al, r, pairs, g, C);
-  }
+#define QCX_BULK(MR, GA) \
+  hipLaunchKernelGGL((k_bulk<BF16, AF, MR, NST, GA>), grid, dim3(256), 0, st, ah, al, r, pairs, rows, g, C)
+  if (g.gather)
+    QCX_BULK(5, true);
+  else if (bulk_maxr(g.n_g) == 1)
+    QCX_BULK(1, false);
+  else if (bulk_maxr(g.n_g) == 4)
+    QCX_BULK(4, false);
+  else
+    QCX_BULK(5, false);
+#undef QCX_BULK
 }
 
 // ---------------------------------------------------------------------------
@@ -714,51 +721,79 @@ int bulk_row_frags(const Chi0Geom& g) {
   return r5 < r4 ? 5 : 4;
 }
 
-void launch_bulk_f32(const float* Aw, const float* R32, const int* pairs, const Chi0Geom& g,
-                     int nst, float* C, hipStream_t st) {
+void launch_bulk_f32(const float* Aw, const float* R32, const int* pairs, const int* rows,
+                     const Chi0Geom& g, int nst, float* C, hipStream_t st) {
   const bool af5 = g.n_rowsp % 160 == 0 && bulk_row_frags(g) == 5;
   if (af5 && nst == 3)
-    launch_bulk_t<false, 5, 3>(Aw, nullptr, R32, pairs, g, C, st);
+    launch_bulk_t<false, 5, 3>(Aw, nullptr, R32, pairs, rows, g, C, st);
   else if (af5)
-    launch_bulk_t<false, 5, 2>(Aw, nullptr, R32, pairs, g, C, st);
+    launch_bulk_t<false, 5, 2>(Aw, nullptr, R32, pairs, rows, g, C, st);
   else if (nst == 3)
-    launch_bulk_t<false, 4, 3>(Aw, nullptr, R32, pairs, g, C, st);
+    launch_bulk_t<false, 4, 3>(Aw, nullptr, R32, pairs, rows, g, C, st);
   else
-    launch_bulk_t<false, 4, 2>(Aw, nullptr, R32, pairs, g, C, st);
+    launch_bulk_t<false, 4, 2>(Aw, nullptr, R32, pairs, rows, g, C, st);
 }
 
 void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32,
-                      const int* pairs, const Chi0Geom& g, int nst, float* C, hipStream_t st) {
+                      const int* pairs, const int* rows, const Chi0Geom& g, int nst, float* C,
+                      hipStream_t st) {
   const bool af5 = g.n_rowsp % 160 == 0 && bulk_row_frags(g) == 5;
   if (af5 && nst == 3)
-    launch_bulk_t<true, 5, 3>(Ahi, Alo, R32, pairs, g, C, st);
+    launch_bulk_t<true, 5, 3>(Ahi, Alo, R32, pairs, rows, g, C, st);
   else if (af5)
-    launch_bulk_t<true, 5, 2>(Ahi, Alo, R32, pairs, g, C, st);
+    launch_bulk_t<true, 5, 2>(Ahi, Alo, R32, pairs, rows, g, C, st);
   else if (nst == 3)
-    launch_bulk_t<true, 4, 3>(Ahi, Alo, R32, pairs, g, C, st);
+    launch_bulk_t<true, 4, 3>(Ahi, Alo, R32, pairs, rows, g, C, st);
   else
-    launch_bulk_t<true, 4, 2>(Ahi, Alo, R32, pairs, g, C, st);
+    launch_bulk_t<true, 4, 2>(Ahi, Alo, R32, pairs, rows, g, C, st);
 }
 
-void launch_bulk_persistent(bool bf16, const BulkItem* items, const int4* tiles, int n_tiles,
-                            int* counter, int max_ng, int grid, hipStream_t st) {
+void launch_bulk_persistent(bool bf16, bool gather, const BulkItem* items, const int4* tiles,
+                            int n_tiles, int* counter, int max_ng, int grid, hipStream_t st) {
   constexpr int AF = kBatchAF;
-#define QCX_PERSIST(B, R)                                                                 \
-  hipLaunchKernelGGL((k_bulk_persistent<B, AF, R>), dim3(grid), dim3(256), 0, st, items, \
+#define QCX_PERSIST(B, R, GA)                                                                 \
+  hipLaunchKernelGGL((k_bulk_persistent<B, AF, R, GA>), dim3(grid), dim3(256), 0, st, items, \
                      tiles, n_tiles, counter)
-  const int maxr = bulk_maxr(max_ng);
+  const int maxr = gather ? 5 : bulk_maxr(max_ng);
   if (bf16) {
-    if (maxr == 1) QCX_PERSIST(true, 1);
-    else if (maxr == 4) QCX_PERSIST(true, 4);
-    else if (maxr == 9) QCX_PERSIST(true, 9);
-    else QCX_PERSIST(true, 17);
+    if (gather) QCX_PERSIST(true, 5, true);
+    else if (maxr == 1) QCX_PERSIST(true, 1, false);
+    else if (maxr == 4) QCX_PERSIST(true, 4, false);
+    else QCX_PERSIST(true, 5, false);
   } else {
-    if (maxr == 1) QCX_PERSIST(false, 1);
-    else if (maxr == 4) QCX_PERSIST(false, 4);
-    else if (maxr == 9) QCX_PERSIST(false, 9);
-    else QCX_PERSIST(false, 17);
+    if (gather) QCX_PERSIST(false, 5, true);
+    else if (maxr == 1) QCX_PERSIST(false, 1, false);
+    else if (maxr == 4) QCX_PERSIST(false, 4, false);
+    else QCX_PERSIST(false, 5, false);
   }
 #undef QCX_PERSIST
+}
+
+bool bulk_gather_tables(const std::vector<int>& pairs_global, std::vector<int>& pairs_local,
+                        std::vector<int>& rows) {
+  const size_t nb = pairs_global.size();
+  const size_t n_tiles = nb / 128;
+  pairs_local.assign(nb, 0);
+  rows.assign(n_tiles * kGatherRows, 0);
+  std::vector<int> list;
+  for (size_t t = 0; t < n_tiles; ++t) {
+    list.clear();
+    for (size_t b = t * 128; b < (t + 1) * 128; ++b) {
+      list.push_back(pairs_global[b] & 0xffff);
+      list.push_back(pairs_global[b] >> 16);
+    }
+    std::sort(list.begin(), list.end());
+    list.erase(std::unique(list.begin(), list.end()), list.end());
+    if (list.size() > (size_t)kGatherRows) return false;
+    for (size_t r = 0; r < (size_t)kGatherRows; ++r)
+      rows[t * kGatherRows + r] = list[r < list.size() ? r : 0];
+    auto local = [&](int G) {
+      return (int)(std::lower_bound(list.begin(), list.end(), G) - list.begin());
+    };
+    for (size_t b = t * 128; b < (t + 1) * 128; ++b)
+      pairs_local[b] = local(pairs_global[b] & 0xffff) | (local(pairs_global[b] >> 16) << 16);
+  }
+  return true;
 }
 
 void launch_set_int(int* p, int v, hipStream_t st) {

@@ -15,11 +15,18 @@ namespace qcx {
 
 namespace {
 
+// Upper-triangle pair index p -> (G, G'), G <= G', row-major.  Row g starts
+// at s(g) = g n - g (g - 1) / 2; the quadratic is inverted in double and the
+// rounding fixed by at most a step either way.
 __device__ inline void pair_decode(int p, int n_g, int& G, int& Gp) {
-  int g = 0;
-  while (g + 1 < n_g && (g + 1) * n_g - (g + 1) * g / 2 <= p) ++g;
+  auto start = [&](long gg) { return gg * n_g - gg * (gg - 1) / 2; };
+  const double b = 2.0 * n_g + 1.0;
+  int g = (int)floor(0.5 * (b - sqrt(fmax(b * b - 8.0 * p, 0.0))));
+  g = max(0, min(g, n_g - 1));
+  while (g > 0 && start(g) > p) --g;
+  while (g + 1 < n_g && start(g + 1) <= p) ++g;
   G = g;
-  Gp = g + (p - (g * n_g - g * (g - 1) / 2));
+  Gp = g + (int)(p - start(g));
 }
 
 // mode 0: eps; mode 1: chi0

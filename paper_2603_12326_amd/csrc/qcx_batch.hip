@@ -20,7 +20,7 @@ struct PlanItem {
   int n_pairs64 = 0;
   double eta = 0.0, pref = 0.0;
   double* loss_out = nullptr;
-  DevBuf w, A, Alo, pairs, pairs64, C, XY, eps, diag, epsM, loss;
+  DevBuf w, A, Alo, pairs, rows, pairs64, C, XY, eps, diag, epsM, loss;
 };
 
 struct BatchPlan {
@@ -30,13 +30,14 @@ struct BatchPlan {
   std::vector<DevBuf> r32;  // per context
   DevBuf d_items, d_tiles, d_counter, d_sing;
   int n_tiles = 0, max_ng = 0;
+  bool gather = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~BatchPlan() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (PlanItem& it : items) {
-      DevBuf* b[] = {&it.w, &it.A, &it.Alo, &it.pairs, &it.pairs64, &it.C, &it.XY,
+      DevBuf* b[] = {&it.w, &it.A, &it.Alo, &it.pairs, &it.rows, &it.pairs64, &it.C, &it.XY,
                      &it.eps, &it.diag, &it.epsM, &it.loss};
       for (DevBuf* x : b) x->release();
     }
@@ -98,6 +99,11 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
   std::vector<int> ctx_ntp(n_ctx, 0);
   std::vector<BulkItem> bitems(n_items);
   std::vector<int4> tiles;
+  // one bulk kernel serves every item: row-gather mode for all of them when
+  // any item is large
+  if (bulk)
+    for (int i = 0; i < n_items; ++i)
+      P->gather = P->gather || ctxs[items[i].ctx]->n_g >= kGatherMinNg;
   HIPCK(stage_begin(ctx));
   for (int i = 0; i < n_items; ++i) {
     PlanItem& it = P->items[i];
@@ -136,7 +142,16 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
       for (int G = 0; G < g.n_g; ++G)
         for (int Gp = G; Gp < g.n_g; ++Gp, ++p)
           if (p >= g.p0) pr[b++] = G | (Gp << 16);
-      HIPCK(upload(ctx, it.pairs, pr.data(), pr.size()));
+      g.gather = P->gather ? 1 : 0;
+      if (P->gather) {
+        std::vector<int> local, rows;
+        if (!bulk_gather_tables(pr, local, rows))
+          return fail(ctx, QCX_EDEVICE, "internal: a pair tile needs more rows than staged");
+        HIPCK(upload(ctx, it.pairs, local.data(), local.size()));
+        HIPCK(upload(ctx, it.rows, rows.data(), rows.size()));
+      } else {
+        HIPCK(upload(ctx, it.pairs, pr.data(), pr.size()));
+      }
       for (int z = 0; z < g.ksplit; ++z)
         for (int y = 0; y < g.n_rowsp / (32 * kBatchAF); ++y)
           for (int x = 0; x < g.n_bulkp / 128; ++x) tiles.push_back(make_int4(i, x, y, z));
@@ -168,7 +183,8 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
   for (int i = 0; i < n_items; ++i) {
     PlanItem& it = P->items[i];
     bitems[i] = BulkItem{it.A.as<float4>(), it.Alo.as<float4>(), P->r32[it.ctx].as<float4>(),
-                         it.pairs.as<int>(), it.g, it.C.as<float>()};
+                         it.pairs.as<int>(), P->gather ? it.rows.as<int>() : nullptr, it.g,
+                         it.C.as<float>()};
   }
   // cost order: longest K range first (all tiles of one item are equal)
   std::stable_sort(tiles.begin(), tiles.end(), [&](const int4& a, const int4& b) {
@@ -216,7 +232,8 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
   if (P->n_tiles > 0) {
     launch_set_int(P->d_counter.as<int>(), 0, st);
     const int grid = std::min(P->n_tiles, 2 * 256);
-    launch_bulk_persistent(bf, P->d_items.as<BulkItem>(), P->d_tiles.as<int4>(), P->n_tiles,
+    launch_bulk_persistent(bf, P->gather, P->d_items.as<BulkItem>(), P->d_tiles.as<int4>(),
+                           P->n_tiles,
                            P->d_counter.as<int>(), P->max_ng, grid, st);
   }
   for (int i = 0; i < n_items; ++i) {
@@ -274,8 +291,6 @@ int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_
     if (!ctxs[c]) return fail(ctx, QCX_EINVAL, "NULL context");
     if (ctxs[c]->device != ctx->device) return fail(ctx, QCX_EINVAL, "contexts on different devices");
     if (!ctxs[c]->have_rho) return fail(ctx, QCX_ESTATE, "context " + std::to_string(c) + " has no pair densities");
-    if (precision != QCX_FP64 && ctxs[c]->n_g > 480)
-      return fail(ctx, QCX_EINVAL, "the MFMA bulk path is limited to n_G <= 480");
     if (lfe && ctxs[c]->n_g > 2048) return fail(ctx, QCX_EINVAL, "LFE inversion limited to n_G <= 2048");
   }
   for (int i = 0; i < n_items; ++i) {

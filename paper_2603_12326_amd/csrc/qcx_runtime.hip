@@ -420,8 +420,7 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
   if (!(eta_eV >= 0.0) || !std::isfinite(eta_eV)) return fail(ctx, QCX_EINVAL, "eta must be >= 0");
   if (precision < QCX_FP64 || precision > QCX_SPLIT_BF16)
     return fail(ctx, QCX_EINVAL, "bad precision");
-  if (precision != QCX_FP64 && ctx->n_g > 480)
-    return fail(ctx, QCX_EINVAL, "the MFMA bulk path is limited to n_G <= 480");
+
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_chi0 = ctx->have_eps = false;
   hipStream_t st = ctx->stream;
@@ -482,6 +481,10 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIPCK(hipStreamIsCapturing(st, &cap));
     if (cap != hipStreamCaptureStatusNone) tune = false;
+    // very large shapes: a launch takes longer than tuning could repay
+    // (estimated at 300 TFLOP/s FP32-equivalent), keep the heuristic
+    const double est_ms = 2.0 * g.n_rowsp * 2.0 * g.n_bulkp * g.n_tp / 3e14 * 1e3;
+    if (est_ms > 500.0) tune = false;
     int max_ks = pick.ks;
     if (tune)
       for (const Cand& c : cands) max_ks = std::max(max_ks, c.ks);
@@ -496,7 +499,17 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
         for (int Gp = G; Gp < g.n_g; ++Gp, ++p)
           if (p >= g.p0) pairs[b++] = G | (Gp << 16);
     }
-    HIPCK(upload(ctx, ctx->d_pairs, pairs.data(), pairs.size()));
+    g.gather = g.n_g >= kGatherMinNg ? 1 : 0;
+    if (g.gather) {
+      std::vector<int> local, rows;
+      if (!bulk_gather_tables(pairs, local, rows))
+        return fail(ctx, QCX_EDEVICE, "internal: a pair tile needs more rows than staged");
+      HIPCK(upload(ctx, ctx->d_pairs, local.data(), local.size()));
+      HIPCK(upload(ctx, ctx->d_rows, rows.data(), rows.size()));
+    } else {
+      HIPCK(upload(ctx, ctx->d_pairs, pairs.data(), pairs.size()));
+    }
+    const int* rows_dev = g.gather ? ctx->d_rows.as<int>() : nullptr;
     const bool bf = precision == QCX_SPLIT_BF16;
     launch_pack_r32(ctx->d_R.as<cplx>(), ctx->ldt, g, bf ? 0 : 1, ctx->d_R32.as<float>(), st);
     if (bf) {
@@ -514,11 +527,11 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
       g.ksplit = c.ks;
       if (bf)
         launch_bulk_bf16(ctx->d_A.as<uint16_t>(), ctx->d_Alo.as<uint16_t>(),
-                         ctx->d_R32.as<float>(), ctx->d_pairs.as<int>(), g, c.nst,
+                         ctx->d_R32.as<float>(), ctx->d_pairs.as<int>(), rows_dev, g, c.nst,
                          ctx->d_C.as<float>(), st);
       else
-        launch_bulk_f32(ctx->d_A.as<float>(), ctx->d_R32.as<float>(), ctx->d_pairs.as<int>(), g,
-                        c.nst, ctx->d_C.as<float>(), st);
+        launch_bulk_f32(ctx->d_A.as<float>(), ctx->d_R32.as<float>(), ctx->d_pairs.as<int>(),
+                        rows_dev, g, c.nst, ctx->d_C.as<float>(), st);
     };
     ctx->tune_ms = 0.0;
     if (tune) {
@@ -527,10 +540,9 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
       HIPCK(hipEventCreate(&e0));
       HIPCK(hipEventCreate(&e1));
       float best = 1e30f;
+      run_bulk(cands.front());  // warm (code objects, caches)
       for (const Cand& c : cands) {
-        run_bulk(c);  // warm
         HIPCK(hipEventRecord(e0, st));
-        run_bulk(c);
         run_bulk(c);
         HIPCK(hipEventRecord(e1, st));
         LAUNCHCK("bulk (tuning)");
