@@ -269,9 +269,12 @@ int qcx_mlp_query(qcx_mlp* m, int n, const double* qw, double* loss, double* err
 /* Tile selection of the chi0 bulk kernel (qcx_chi0 with FP32 or split-BF16).
  * mode 1 (default): on the first qcx_chi0 of each shape (device, precision,
  * N_G, padded N_T, padded rows), every candidate configuration - K split
- * 1..16 and a 2- or 3-stage LDS pipeline, within 160 KB of LDS and 2 GB of
- * partial sums - is timed on the real operands with HIP events and the
- * fastest is kept for the process; that call synchronises the stream.  The
+ * (a power of two up to 64, at least enough that no split sums more than
+ * 1024 MFMA steps of 16 transitions in FP32: the splits are added in FP64)
+ * and a 2- or 3-stage LDS pipeline, within 160 KB of LDS - is timed on the
+ * real operands with HIP events and the fastest is kept for the process;
+ * that call synchronises the stream.  Shapes whose FP32 partial sums would
+ * exceed 8 GB run in chunks of frequency rows reduced into FP64.  The
  * result used is always computed with the chosen configuration.  mode 0: a
  * fixed heuristic.  Tuning is skipped while the stream is being captured and
  * for shapes whose single launch is estimated above 0.5 s.

@@ -86,6 +86,8 @@ struct Chi0Geom {
   int n_bulk, n_bulkp;      // bulk pairs and padded count
   int ksplit;
   int gather;               // 1: per-tile row lists (N_G >= kGatherMinNg)
+  int row_tile0;            // first row tile of this launch (row chunks)
+  int c_rows;               // rows held by the partial buffer C (n_rowsp unless chunked)
 };
 // transition energies Delta_t (Ha) and signs for t in [0, n_t)
 void launch_transition_energies(const double* Ek, const double* Ekq, int n_k, int n_b, int n_occ,
@@ -135,6 +137,10 @@ struct BulkItem {
 void launch_bulk_persistent(bool bf16, bool gather, const BulkItem* items, const int4* tiles,
                             int n_tiles, int* counter, int max_ng, int grid, hipStream_t st);
 void launch_set_int(int* p, int v, hipStream_t st);
+// C64[r][ri][b] = sum over ks splits of C[ks][r][ri][b] for the rows of one
+// chunk (C holds n_rows rows; C64 points at the chunk's first row)
+void launch_reduce_partials(const float* C, int ks, int n_rows, int n_bulkp, double* C64,
+                            hipStream_t st);
 constexpr int kBatchAF = 4;
 
 // FP64 pairs on FP64 MFMA: out[split][row][col], rows (Re W, Im W) per
@@ -150,6 +156,7 @@ void launch_pairs_f64(const cplx* R, size_t ldt, const double* w, const double* 
 // eps assembly (symmetrised Coulomb, prefactor 2/(N_k V))
 struct AsmArgs {
   const float* C;       // bulk partials [ks][n_rowsp][2][n_bulkp] or null
+  const double* C64;    // or: reduced FP64 partials [n_rowsp][2][n_bulkp] (row chunks)
   const double* XY;     // FP64 partials [ks64][n_rowsp64][n_colp64] or null
   int ks, ks64;
   int n_rowsp64, n_colp64;

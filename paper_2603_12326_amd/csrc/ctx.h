@@ -58,7 +58,8 @@ struct qcx_ctx {
   int autotune = 1;           // 0: fixed heuristic, 1: time candidates per shape
   double tune_ms = 0.0;       // time spent tuning in the last qcx_chi0
   Geom64 geom64{};
-  DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_rows, d_pairs64, d_C, d_XY;
+  DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_rows, d_pairs64, d_C, d_C64, d_XY;
+  bool bulk_c64 = false;      // bulk partials reduced to FP64 (row chunks)
 
   // eps
   bool have_eps = false;
@@ -90,7 +91,7 @@ struct qcx_ctx {
     DevBuf* all[] = {&d_sh_l, &d_sh_ex, &d_sh_ctr, &d_sh_off, &d_cells, &d_tvec, &d_kf,
                      &d_Ck,   &d_Ek,    &d_Ckq,    &d_Ekq,    &d_dt,    &d_ph,   &d_phq,
                      &d_S,    &d_F0,    &d_dev,    &d_Q,      &d_vq,    &d_F,    &d_M,
-                     &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_rows, &d_pairs64, &d_C,
+                     &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_rows, &d_pairs64, &d_C, &d_C64,
                      &d_XY,   &d_eps,   &d_diag,   &d_epsM,   &d_loss,  &d_sing};
     for (DevBuf* b : all) b->release();
     for (const Span& sp : spans) {

@@ -210,7 +210,8 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
   const int ntb = g.n_tp / KSTEP;
   const int steps = ntb / g.ksplit;
   const int tb0 = bk.z * steps;
-  const int rb0 = bk.y * AF;
+  const int rb0 = (g.row_tile0 + bk.y) * AF;  // first 32-row fragment (weights)
+  const int rc0 = bk.y * AF;                   // first fragment in the partial buffer
   const int b = bk.x * 128 + wave * 32 + (lane & 31);
   const int pk = pairs[b];
   const int G = pk & 0xffff, Gp = pk >> 16;
@@ -378,15 +379,15 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
   // the trailing copies must land before the LDS is reused or released
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 
-  // epilogue: C[((ks*n_rowsp + row)*2 + ri)*n_bulkp + b]
+  // epilogue: C[((ks*c_rows + row)*2 + ri)*n_bulkp + b], row local to the chunk
 #pragma unroll
   for (int f = 0; f < AF; ++f) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int row = (rb0 + f) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+      const int row = (rc0 + f) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
 #pragma unroll
       for (int ri = 0; ri < 2; ++ri) {
-        const size_t o = (((size_t)bk.z * g.n_rowsp + row) * 2 + ri) * g.n_bulkp + b;
+        const size_t o = (((size_t)bk.z * g.c_rows + row) * 2 + ri) * g.n_bulkp + b;
         C[o] = acc[f][ri][r];
       }
     }
@@ -399,7 +400,7 @@ k_bulk(const float4* __restrict__ Ahi, const float4* __restrict__ Alo,
        const float4* __restrict__ R32, const int* __restrict__ pairs,
        const int* __restrict__ rows, Chi0Geom g, float* __restrict__ C) {
   using L = BulkStage<4 * MAXR, 2 * AF>;
-  const Blk3 bk = xcd_block(g.n_bulkp / 128, g.n_rowsp / (32 * AF), g.ksplit);
+  const Blk3 bk = xcd_block(g.n_bulkp / 128, g.c_rows / (32 * AF), g.ksplit);
   if constexpr (NST == 3) {
     __shared__ L s0, s1, s2;
     bulk_tile<BF16, AF, MAXR, 3, GATHER>(Ahi, Alo, R32, pairs, rows, g, C, bk, s0, s1, s2);
@@ -444,7 +445,7 @@ size_t lds_bytes_of(int n_g, int af, int nst) {
 template <bool BF16, int AF, int NST>
 void launch_bulk_t(const void* Ahi, const void* Alo, const float* R32, const int* pairs,
                    const int* rows, const Chi0Geom& g, float* C, hipStream_t st) {
-  const dim3 grid((g.n_bulkp / 128) * (g.n_rowsp / (32 * AF)) * g.ksplit);
+  const dim3 grid((g.n_bulkp / 128) * (g.c_rows / (32 * AF)) * g.ksplit);
   const float4* ah = static_cast<const float4*>(Ahi);
   const float4* al = static_cast<const float4*>(Alo);
   const float4* r = reinterpret_cast<const float4*>(R32);
@@ -794,6 +795,21 @@ bool bulk_gather_tables(const std::vector<int>& pairs_global, std::vector<int>& 
       pairs_local[b] = local(pairs_global[b] & 0xffff) | (local(pairs_global[b] >> 16) << 16);
   }
   return true;
+}
+
+__global__ void k_reduce_partials(const float* __restrict__ C, int ks, long n, double* C64) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < ks; ++k) s += (double)C[(size_t)k * n + i];
+  C64[i] = s;
+}
+
+void launch_reduce_partials(const float* C, int ks, int n_rows, int n_bulkp, double* C64,
+                            hipStream_t st) {
+  const long n = (long)n_rows * 2 * n_bulkp;
+  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, C, ks,
+                     n, C64);
 }
 
 void launch_set_int(int* p, int v, hipStream_t st) {

@@ -46,6 +46,13 @@ __global__ void k_assemble(AsmArgs a, Chi0Geom g, int mode, cplx* __restrict__ o
       Yr += x1[0];
       Yi += x1[1];
     }
+  } else if (a.C64) {
+    const int b = p - g.p0;
+    const size_t r0 = (size_t)(2 * j) * 2, r1 = r0 + 2;
+    Xr = a.C64[(r0 + 0) * g.n_bulkp + b];
+    Xi = a.C64[(r0 + 1) * g.n_bulkp + b];
+    Yr = a.C64[(r1 + 0) * g.n_bulkp + b];
+    Yi = a.C64[(r1 + 1) * g.n_bulkp + b];
   } else {
     const int b = p - g.p0;
     for (int ks = 0; ks < a.ks; ++ks) {

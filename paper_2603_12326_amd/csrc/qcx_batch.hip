@@ -129,6 +129,7 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
     g.n_bulkp = (int)roundup(std::max(g.n_bulk, 1), 128);
     if (bulk && g.n_bulk > 0) {
       g.n_rowsp = (int)roundup(g.n_rows, 32 * kBatchAF);
+      g.c_rows = g.n_rowsp;
       const int ntb0 = (int)roundup(g.n_t, 16) / 16;
       g.ksplit = ksplit_for(ntb0, 256);
       g.n_tp = (int)roundup(g.n_t, 16 * g.ksplit);

@@ -391,20 +391,34 @@ struct TuneVal {
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
 
-constexpr int kMaxKsplit = 16;
-constexpr size_t kMaxPartialBytes = (size_t)2 << 30;
+constexpr int kMaxKsplit = 64;
+// FP32 partial sums of one launch are kept within this budget; larger shapes
+// run in chunks of frequency rows, each reduced into FP64 partials
+constexpr size_t kPartialBudget = (size_t)8 << 30;
+// Accuracy: one K split sums at most this many K steps (16 transitions
+// each) in its FP32 accumulators; the splits are added in FP64
+constexpr int kMaxStepsPerSplit = 1024;
 constexpr size_t kLdsBytes = 160 * 1024;
 
 struct Cand {
   int ks, nst;
 };
 
-std::vector<Cand> bulk_candidates(const Chi0Geom& g, int af) {
+// smallest K split (power of two) that keeps every split within
+// kMaxStepsPerSplit sequential FP32 accumulations
+int ksplit_for_accuracy(int ntb) {
+  int ks = 1;
+  while (ks < kMaxKsplit && (size_t)ntb > (size_t)ks * kMaxStepsPerSplit) ks *= 2;
+  return ks;
+}
+
+std::vector<Cand> bulk_candidates(const Chi0Geom& g, int af, int ks_min) {
   std::vector<Cand> c;
   const int ntb = g.n_tp / KSTEP_T;
-  for (int ks = 1; ks <= kMaxKsplit; ks *= 2) {
-    if (ks > 1 && ntb / ks < 4) break;
-    if ((size_t)ks * g.n_rowsp * 2 * g.n_bulkp * sizeof(float) > kMaxPartialBytes) break;
+  for (int ks = ks_min; ks <= kMaxKsplit; ks *= 2) {
+    if (ks > ks_min && ntb / ks < 4) break;
+    if (ks > ks_min && (size_t)ks * g.c_rows * 2 * g.n_bulkp * sizeof(float) > kPartialBudget)
+      break;
     for (int nst = 2; nst <= 3; ++nst)
       if (bulk_lds_bytes(g.n_g, af, nst) <= kLdsBytes) c.push_back({ks, nst});
   }
@@ -460,11 +474,22 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
     g.n_rowsp = (int)roundup(g.n_rows, 32 * af);
     const int blocks = (g.n_bulkp / 128) * (g.n_rowsp / (32 * af));
     g.n_tp = (int)roundup(g.n_t, KSTEP_T * kMaxKsplit);
-    const std::vector<Cand> cands = bulk_candidates(g, af);
+    const int ks_acc = ksplit_for_accuracy(g.n_tp / KSTEP_T);
+    // row chunks when even the smallest admissible split count overflows
+    // the partial-sum budget
+    const size_t row_bytes = 2 * (size_t)g.n_bulkp * sizeof(float);
+    int chunk_rows = g.n_rowsp;
+    if ((size_t)ks_acc * g.n_rowsp * row_bytes > kPartialBudget)
+      chunk_rows = std::max(32 * af, (int)(kPartialBudget / (ks_acc * row_bytes)) / (32 * af) *
+                                         (32 * af));
+    const bool chunked = chunk_rows < g.n_rowsp;
+    g.row_tile0 = 0;
+    g.c_rows = chunk_rows;
+    const std::vector<Cand> cands = bulk_candidates(g, af, ks_acc);
     if (cands.empty()) return fail(ctx, QCX_EINVAL, "no bulk tile configuration fits");
     // heuristic choice, used when tuning is off, under graph capture, or as
     // the candidate to beat
-    Cand pick{pick_ksplit(blocks, g.n_tp / KSTEP_T), 2};
+    Cand pick{std::max(ks_acc, pick_ksplit(blocks, g.n_tp / KSTEP_T)), 2};
     if (std::none_of(cands.begin(), cands.end(),
                      [&](const Cand& c) { return c.ks == pick.ks && c.nst == pick.nst; }))
       pick = cands.front();
@@ -484,14 +509,16 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
     // very large shapes: a launch takes longer than tuning could repay
     // (estimated at 300 TFLOP/s FP32-equivalent), keep the heuristic
     const double est_ms = 2.0 * g.n_rowsp * 2.0 * g.n_bulkp * g.n_tp / 3e14 * 1e3;
-    if (est_ms > 500.0) tune = false;
+    if (est_ms > 500.0 || chunked) tune = false;
     int max_ks = pick.ks;
     if (tune)
       for (const Cand& c : cands) max_ks = std::max(max_ks, c.ks);
     const size_t nA = (size_t)g.n_rowsp * g.n_tp;  // elements
-    const size_t nC = (size_t)max_ks * g.n_rowsp * 2 * g.n_bulkp;
+    const size_t nC = (size_t)max_ks * g.c_rows * 2 * g.n_bulkp;
     HIPCK(ctx->d_R32.reserve(sizeof(float) * 2 * (size_t)g.n_g * g.n_tp));
     HIPCK(ctx->d_C.reserve(sizeof(float) * nC));
+    if (chunked) HIPCK(ctx->d_C64.reserve(sizeof(double) * 2 * (size_t)g.n_rowsp * g.n_bulkp));
+    ctx->bulk_c64 = chunked;
     std::vector<int> pairs(g.n_bulkp, 0);
     {
       int b = 0, p = 0;
@@ -566,7 +593,19 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
     ctx->bulk_nst = pick.nst;
     ctx->bulk_af = af;
     HIPCK(span_begin(ctx, 1, &sp_bulk));
-    run_bulk(pick);
+    if (!chunked) {
+      run_bulk(pick);
+    } else {
+      for (int r0 = 0; r0 < g.n_rowsp; r0 += chunk_rows) {
+        g.row_tile0 = r0 / (32 * af);
+        g.c_rows = std::min(chunk_rows, g.n_rowsp - r0);
+        run_bulk(pick);
+        launch_reduce_partials(ctx->d_C.as<float>(), pick.ks, g.c_rows, g.n_bulkp,
+                               ctx->d_C64.as<double>() + (size_t)r0 * 2 * g.n_bulkp, st);
+      }
+      g.row_tile0 = 0;
+      g.c_rows = g.n_rowsp;
+    }
     LAUNCHCK("bulk");
     HIPCK(span_end(ctx, sp_bulk));
   } else {
@@ -596,7 +635,8 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
   ctx->have_chi0 = true;
   if (chi0_out) {
     AsmArgs a{};
-    a.C = g.n_bulk > 0 ? ctx->d_C.as<float>() : nullptr;
+    a.C = (g.n_bulk > 0 && !ctx->bulk_c64) ? ctx->d_C.as<float>() : nullptr;
+    a.C64 = (g.n_bulk > 0 && ctx->bulk_c64) ? ctx->d_C64.as<double>() : nullptr;
     a.XY = ctx->n_pairs64 > 0 ? ctx->d_XY.as<double>() : nullptr;
     a.ks = g.ksplit;
     a.ks64 = ctx->ks64;
@@ -629,7 +669,8 @@ int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out) {
   int sp_eps;
   HIPCK(span_begin(ctx, 4, &sp_eps));
   AsmArgs a{};
-  a.C = g.n_bulk > 0 ? ctx->d_C.as<float>() : nullptr;
+  a.C = (g.n_bulk > 0 && !ctx->bulk_c64) ? ctx->d_C.as<float>() : nullptr;
+    a.C64 = (g.n_bulk > 0 && ctx->bulk_c64) ? ctx->d_C64.as<double>() : nullptr;
   a.XY = ctx->n_pairs64 > 0 ? ctx->d_XY.as<double>() : nullptr;
   a.ks = g.ksplit;
   a.ks64 = ctx->ks64;
