@@ -84,8 +84,9 @@ int qcx_destroy(qcx_ctx* ctx);
 const char* qcx_last_error(const qcx_ctx* ctx);
 
 /* Wait for all work enqueued by this context and report errors detected on
- * the device since the last call: QCX_ESINGULAR if an eps matrix had a zero
- * pivot (qcx_last_error names the frequency index). */
+ * the device since the last call: QCX_EINVAL / QCX_ENONORTH for device-input
+ * states that failed their checks (qcx_set_states), QCX_ESINGULAR if an eps
+ * matrix had a zero pivot (qcx_last_error names the index). */
 int qcx_sync(qcx_ctx* ctx);
 
 /* Crystal cell and Gaussian basis (Sec. III: Gaussian-type orbitals; one
@@ -120,9 +121,14 @@ int qcx_set_cell_basis(qcx_ctx* ctx, const double lat[9], int n_atoms, const dou
  *   E_k, E_kq  [n_k][n_bands] band energies (eV); every empty band must lie
  *              above every occupied band at each k and k + q
  *   mem        QCX_MEM_HOST or QCX_MEM_DEVICE for k_frac, C_*, E_*
- * The states are copied to the device and checked: |C^H S C - I| <= 1e-10 at
- * every k and k + q with S(k) the library's own overlap (this synchronises
- * the stream).  Invalidates pair densities and all results.
+ * The states are copied to the device and checked: finite energies with the
+ * band order above, and |C^H S C - I| <= 1e-10 at every k and k + q with S(k)
+ * the library's own overlap.  Host inputs (QCX_MEM_HOST) are checked before
+ * this call returns (it synchronises the stream).  Device inputs are checked
+ * on the stream without a round trip: a failure is reported (QCX_EINVAL or
+ * QCX_ENONORTH, results computed from those states being invalid) by the
+ * context's next synchronising call: qcx_sync, qcx_loss to host memory or
+ * qcx_batch_sync.  Invalidates pair densities and all results.
  * Errors: QCX_ESTATE (no basis), QCX_EINVAL (sizes, band order),
  * QCX_ENONORTH, QCX_ENOMEM. */
 int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* k_frac,

@@ -73,6 +73,10 @@ void launch_band_contract(const cplx* M, const cplx* Ck, const cplx* Ckq, int n_
                           int n_occ, int n_k, int k0, int nk, int n_g, cplx* R, size_t ldt,
                           hipStream_t st);
 // max_k |C^H S C - I| per k
+// deferred state checks: flags[0] band order / finiteness (first bad k),
+// flags[1] orthonormality (first bad index of dev[2 n_k]); INT_MAX when fine
+void launch_state_flags(const double* Ek, const double* Ekq, int n_k, int n_b, int n_occ,
+                        const double* dev, double tol, int* flags, hipStream_t st);
 void launch_orth_check(const cplx* S, const cplx* C, int n_ao, int n_b, int n_k, double* dev,
                        hipStream_t st);
 size_t band_contract_lds(int n_ao, int n_b, int n_occ);

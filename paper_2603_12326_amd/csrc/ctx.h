@@ -39,7 +39,9 @@ struct qcx_ctx {
   bool have_states = false;
   double q[3] = {0, 0, 0};
   int n_k = 0, n_occ = 0, n_b = 0, n_c = 0, n_t = 0;
-  DevBuf d_kf, d_Ck, d_Ek, d_Ckq, d_Ekq, d_dt, d_ph, d_phq, d_S, d_F0, d_dev;
+  DevBuf d_kf, d_Ck, d_Ek, d_Ckq, d_Ekq, d_dt, d_ph, d_phq, d_S, d_F0, d_dev, d_flags;
+  bool check_pending = false;  // device-input state checks not yet read back
+  int check_nk = 0;
 
   // pair densities
   bool have_rho = false;
@@ -90,7 +92,7 @@ struct qcx_ctx {
     if (plan) qcx::destroy_plan(plan);
     DevBuf* all[] = {&d_sh_l, &d_sh_ex, &d_sh_ctr, &d_sh_off, &d_cells, &d_tvec, &d_kf,
                      &d_Ck,   &d_Ek,    &d_Ckq,    &d_Ekq,    &d_dt,    &d_ph,   &d_phq,
-                     &d_S,    &d_F0,    &d_dev,    &d_Q,      &d_vq,    &d_F,    &d_M,
+                     &d_S,    &d_F0,    &d_dev,    &d_flags,    &d_Q,      &d_vq,    &d_F,    &d_M,
                      &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_rows, &d_pairs64, &d_C, &d_C64,
                      &d_XY,   &d_eps,   &d_diag,   &d_epsM,   &d_loss,  &d_sing};
     for (DevBuf* b : all) b->release();
@@ -105,6 +107,9 @@ struct qcx_ctx {
 };
 
 namespace qcx {
+
+// deferred state checks of device-resident inputs (qcx_runtime.hip)
+int check_deferred(qcx_ctx* ctx);
 
 inline int fail(qcx_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;

@@ -546,6 +546,41 @@ void launch_band_contract(const cplx* M, const cplx* Ck, const cplx* Ckq, int n_
 #undef QCX_BC
 }
 
+// Device-side state checks (deferred reporting): flags[0] = smallest k whose
+// energies are non-finite or whose empty bands do not all lie above its
+// occupied bands (at k and at k+q); flags[1] = smallest index i of dev (k,
+// then n_k + k for k+q) with max|C^H S C - I| above tol.  Both stay INT_MAX
+// when the states pass, and accumulate (minimum) until read and reset.
+__global__ void k_band_check(const double* __restrict__ Ek, const double* __restrict__ Ekq,
+                             int n_k, int n_b, int n_occ, int* flags) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_k) return;
+  double vmax = -1e300, cmin = 1e300;
+  bool bad = false;
+  for (int b = 0; b < n_b; ++b) {
+    const double e1 = Ek[(size_t)k * n_b + b], e2 = Ekq[(size_t)k * n_b + b];
+    if (!isfinite(e1) || !isfinite(e2)) bad = true;
+    if (b < n_occ)
+      vmax = fmax(vmax, fmax(e1, e2));
+    else
+      cmin = fmin(cmin, fmin(e1, e2));
+  }
+  if (bad || !(cmin > vmax)) atomicMin(&flags[0], k);
+}
+
+__global__ void k_orth_flag(const double* __restrict__ dev, int n, double tol, int* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !(dev[i] <= tol)) atomicMin(&flags[1], i);
+}
+
+void launch_state_flags(const double* Ek, const double* Ekq, int n_k, int n_b, int n_occ,
+                        const double* dev, double tol, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_band_check, dim3((n_k + 255) / 256), dim3(256), 0, st, Ek, Ekq, n_k, n_b,
+                     n_occ, flags);
+  hipLaunchKernelGGL(k_orth_flag, dim3((2 * n_k + 255) / 256), dim3(256), 0, st, dev, 2 * n_k,
+                     tol, flags);
+}
+
 void launch_orth_check(const cplx* S, const cplx* C, int n_ao, int n_b, int n_k, double* dev,
                        hipStream_t st) {
   const size_t lds = sizeof(cplx) * ((size_t)n_ao * n_ao + 2 * (size_t)n_ao * n_b);

@@ -329,6 +329,7 @@ int qcx_batch_sync(qcx_ctx* ctx) {
   if (!ctx) return QCX_EINVAL;
   HIPCK(hipSetDevice(ctx->device));
   HIPCK(hipStreamSynchronize(ctx->stream));
+  if (int rc = check_deferred(ctx)) return rc;
   if (!ctx->plan) return QCX_OK;
   std::vector<int> s(ctx->plan->n_items);
   HIPCK(hipMemcpy(s.data(), ctx->plan->d_sing.p, sizeof(int) * s.size(), hipMemcpyDeviceToHost));

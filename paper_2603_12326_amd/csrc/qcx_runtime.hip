@@ -22,6 +22,90 @@ namespace {
 std::string g_create_err;
 }  // namespace
 
+// Read back the deferred checks of device-resident states (stream already
+// synchronised by the caller) and reset them.
+int qcx::check_deferred(qcx_ctx* ctx) {
+  if (!ctx->check_pending) return QCX_OK;
+  int f[2] = {INT_MAX, INT_MAX};
+  HIPCK(hipMemcpy(f, ctx->d_flags.p, sizeof(f), hipMemcpyDeviceToHost));
+  const int reset[2] = {INT_MAX, INT_MAX};
+  HIPCK(hipMemcpy(ctx->d_flags.p, reset, sizeof(reset), hipMemcpyHostToDevice));
+  ctx->check_pending = false;
+  if (f[0] != INT_MAX || f[1] != INT_MAX) {
+    ctx->have_states = ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
+    if (f[0] != INT_MAX)
+      return fail(ctx, QCX_EINVAL, "device states: non-finite energy or an empty band below an "
+                                   "occupied band at k " + std::to_string(f[0]));
+    const int nk = ctx->check_nk;
+    return fail(ctx, QCX_ENONORTH,
+                std::string("device states at ") + (f[1] < nk ? "k " : "k+q ") +
+                    std::to_string(f[1] % nk) + " are not orthonormal (max|C^H S C - I| > 1e-10)");
+  }
+  return QCX_OK;
+}
+
+static int pick_ksplit(int blocks, int steps) {
+  int ks = 1;
+  while (ks < 16 && blocks * ks < 1024 && steps / (2 * ks) >= 8) ks *= 2;
+  return ks;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner of the bulk launch: per (device, precision, N_G, padded N_T,
+// padded rows) shape, every candidate (K split, LDS pipeline depth) is timed
+// on the real operands with HIP events and the fastest is kept for the
+// process.  The weights and R slabs are padded to a multiple of 256
+// transitions, so every K split up to 16 divides the same operands.
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+  int dev, prec, n_g, n_tp, n_rowsp, n_bulkp;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, prec, n_g, n_tp, n_rowsp, n_bulkp) <
+           std::tie(o.dev, o.prec, o.n_g, o.n_tp, o.n_rowsp, o.n_bulkp);
+  }
+};
+struct TuneVal {
+  int ks, nst;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+constexpr int kMaxKsplit = 64;
+// FP32 partial sums of one launch are kept within this budget; larger shapes
+// run in chunks of frequency rows, each reduced into FP64 partials
+constexpr size_t kPartialBudget = (size_t)8 << 30;
+// Accuracy: one K split sums at most this many K steps (16 transitions
+// each) in its FP32 accumulators; the splits are added in FP64
+constexpr int kMaxStepsPerSplit = 1024;
+constexpr size_t kLdsBytes = 160 * 1024;
+
+struct Cand {
+  int ks, nst;
+};
+
+// smallest K split (power of two) that keeps every split within
+// kMaxStepsPerSplit sequential FP32 accumulations
+int ksplit_for_accuracy(int ntb) {
+  int ks = 1;
+  while (ks < kMaxKsplit && (size_t)ntb > (size_t)ks * kMaxStepsPerSplit) ks *= 2;
+  return ks;
+}
+
+std::vector<Cand> bulk_candidates(const Chi0Geom& g, int af, int ks_min) {
+  std::vector<Cand> c;
+  const int ntb = g.n_tp / KSTEP_T;
+  for (int ks = ks_min; ks <= kMaxKsplit; ks *= 2) {
+    if (ks > ks_min && ntb / ks < 4) break;
+    if (ks > ks_min && (size_t)ks * g.c_rows * 2 * g.n_bulkp * sizeof(float) > kPartialBudget)
+      break;
+    for (int nst = 2; nst <= 3; ++nst)
+      if (bulk_lds_bytes(g.n_g, af, nst) <= kLdsBytes) c.push_back({ks, nst});
+  }
+  return c;
+}
+}  // namespace
+
 extern "C" {
 
 const char* qcx_build_info(void) {
@@ -115,6 +199,7 @@ int qcx_sync(qcx_ctx* ctx) {
   if (!ctx) return QCX_EINVAL;
   HIPCK(hipSetDevice(ctx->device));
   HIPCK(hipStreamSynchronize(ctx->stream));
+  if (int rc = check_deferred(ctx)) return rc;
   if (ctx->have_eps && ctx->d_sing.p) {
     int s = INT_MAX;
     HIPCK(hipMemcpy(&s, ctx->d_sing.p, sizeof(int), hipMemcpyDeviceToHost));
@@ -219,17 +304,11 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
   ctx->have_states = ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
   hipStream_t st = ctx->stream;
   const bool dev = mem == QCX_MEM_DEVICE;
-  // band order check needs the energies on the host
-  std::vector<double> ek((size_t)n_k * n_bands), ekq((size_t)n_k * n_bands);
-  if (dev) {
-    HIPCK(hipMemcpyAsync(ek.data(), E_k, ek.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCK(hipMemcpyAsync(ekq.data(), E_kq, ekq.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCK(hipStreamSynchronize(st));
-  } else {
-    memcpy(ek.data(), E_k, ek.size() * sizeof(double));
-    memcpy(ekq.data(), E_kq, ekq.size() * sizeof(double));
-  }
-  for (int k = 0; k < n_k; ++k) {
+  // Host inputs are checked here; device inputs on the device, read back by
+  // the next synchronising call (no round trip per call)
+  const std::vector<double> ek = dev ? std::vector<double>() : std::vector<double>(E_k, E_k + (size_t)n_k * n_bands);
+  const std::vector<double> ekq = dev ? std::vector<double>() : std::vector<double>(E_kq, E_kq + (size_t)n_k * n_bands);
+  for (int k = 0; k < (dev ? 0 : n_k); ++k) {
     double vmax = -1e300, cmin = 1e300;
     for (int b = 0; b < n_bands; ++b) {
       const double e1 = ek[(size_t)k * n_bands + b], e2 = ekq[(size_t)k * n_bands + b];
@@ -291,6 +370,20 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
   launch_transition_energies(ctx->d_Ek.as<double>(), ctx->d_Ekq.as<double>(), n_k, n_bands, n_occ,
                              ctx->d_dt.as<double>(), st);
   LAUNCHCK("transition_energies");
+  if (dev) {
+    if (!ctx->d_flags.p) {
+      HIPCK(ctx->d_flags.reserve(2 * sizeof(int)));
+      const int init[2] = {INT_MAX, INT_MAX};
+      HIPCK(hipMemcpy(ctx->d_flags.p, init, sizeof(init), hipMemcpyHostToDevice));
+    }
+    launch_state_flags(ctx->d_Ek.as<double>(), ctx->d_Ekq.as<double>(), n_k, n_bands, n_occ,
+                       ctx->d_dev.as<double>(), 1e-10, ctx->d_flags.as<int>(), st);
+    LAUNCHCK("state checks");
+    ctx->check_pending = true;
+    ctx->check_nk = n_k;
+    ctx->have_states = true;
+    return QCX_OK;
+  }
   std::vector<double> devs(2 * (size_t)n_k);
   HIPCK(hipMemcpyAsync(devs.data(), ctx->d_dev.p, devs.size() * sizeof(double),
                        hipMemcpyDeviceToHost, st));
@@ -364,67 +457,7 @@ int qcx_pair_density(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out) {
   return QCX_OK;
 }
 
-static int pick_ksplit(int blocks, int steps) {
-  int ks = 1;
-  while (ks < 16 && blocks * ks < 1024 && steps / (2 * ks) >= 8) ks *= 2;
-  return ks;
-}
 
-// ---------------------------------------------------------------------------
-// Autotuner of the bulk launch: per (device, precision, N_G, padded N_T,
-// padded rows) shape, every candidate (K split, LDS pipeline depth) is timed
-// on the real operands with HIP events and the fastest is kept for the
-// process.  The weights and R slabs are padded to a multiple of 256
-// transitions, so every K split up to 16 divides the same operands.
-// ---------------------------------------------------------------------------
-namespace {
-struct TuneKey {
-  int dev, prec, n_g, n_tp, n_rowsp, n_bulkp;
-  bool operator<(const TuneKey& o) const {
-    return std::tie(dev, prec, n_g, n_tp, n_rowsp, n_bulkp) <
-           std::tie(o.dev, o.prec, o.n_g, o.n_tp, o.n_rowsp, o.n_bulkp);
-  }
-};
-struct TuneVal {
-  int ks, nst;
-};
-std::mutex g_tune_mu;
-std::map<TuneKey, TuneVal> g_tune;
-
-constexpr int kMaxKsplit = 64;
-// FP32 partial sums of one launch are kept within this budget; larger shapes
-// run in chunks of frequency rows, each reduced into FP64 partials
-constexpr size_t kPartialBudget = (size_t)8 << 30;
-// Accuracy: one K split sums at most this many K steps (16 transitions
-// each) in its FP32 accumulators; the splits are added in FP64
-constexpr int kMaxStepsPerSplit = 1024;
-constexpr size_t kLdsBytes = 160 * 1024;
-
-struct Cand {
-  int ks, nst;
-};
-
-// smallest K split (power of two) that keeps every split within
-// kMaxStepsPerSplit sequential FP32 accumulations
-int ksplit_for_accuracy(int ntb) {
-  int ks = 1;
-  while (ks < kMaxKsplit && (size_t)ntb > (size_t)ks * kMaxStepsPerSplit) ks *= 2;
-  return ks;
-}
-
-std::vector<Cand> bulk_candidates(const Chi0Geom& g, int af, int ks_min) {
-  std::vector<Cand> c;
-  const int ntb = g.n_tp / KSTEP_T;
-  for (int ks = ks_min; ks <= kMaxKsplit; ks *= 2) {
-    if (ks > ks_min && ntb / ks < 4) break;
-    if (ks > ks_min && (size_t)ks * g.c_rows * 2 * g.n_bulkp * sizeof(float) > kPartialBudget)
-      break;
-    for (int nst = 2; nst <= 3; ++nst)
-      if (bulk_lds_bytes(g.n_g, af, nst) <= kLdsBytes) c.push_back({ks, nst});
-  }
-  return c;
-}
-}  // namespace
 
 int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int precision,
              int headwings_fp64, void* chi0_out) {
@@ -576,6 +609,9 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
         HIPCK(hipEventSynchronize(e1));
         float ms = 0.0f;
         HIPCK(hipEventElapsedTime(&ms, e0, e1));
+        // each split's partials are read once more by the assembly: add that
+        // traffic at 5 TB/s so that more splits must earn their keep
+        ms += (float)((double)c.ks * g.c_rows * 2 * g.n_bulkp * sizeof(float) / 5e9);
         if (ms < best) {
           best = ms;
           pick = c;

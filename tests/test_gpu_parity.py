@@ -235,3 +235,41 @@ def test_config4_full_size():
     print(f"config4 full size: split 1000 w in {t1 - t0:.2f} s, split vs fp64 {e:.3g}")
     assert e < 1e-4
     c.close()
+
+
+def test_device_state_checks_deferred(cfg1):
+    """Device-resident states are checked on the stream: a bad coefficient
+    matrix does not raise at set_states but at the next synchronising call;
+    good states pass and the check is reset."""
+    import torch
+
+    from paper_2603_12326_amd import Context, QcxError
+    from paper_2603_12326_amd import qcx as q
+
+    c = Context(0)
+    st = set_inputs(c, cfg1)
+    dev = lambda a, t: torch.from_numpy(np.ascontiguousarray(a)).to(t).cuda()  # noqa: E731
+    kf = dev(cfg1.k_frac, torch.float64)
+    bad = st.C_kq.copy()
+    bad[5] *= 1.001
+    c.set_states(st.q_cart, kf, cfg1.n_occ, dev(st.C_k, torch.complex128),
+                 dev(st.E_k, torch.float64), dev(bad, torch.complex128), dev(st.E_kq, torch.float64))
+    with pytest.raises(QcxError) as e:
+        c.sync()
+    assert e.value.code == q.ENONORTH and "k+q 5" in str(e.value)
+    ebad = st.E_k.copy()
+    ebad[3, cfg1.n_occ] = -20.0
+    c.set_states(st.q_cart, kf, cfg1.n_occ, dev(st.C_k, torch.complex128),
+                 dev(ebad, torch.float64), dev(st.C_kq, torch.complex128), dev(st.E_kq, torch.float64))
+    with pytest.raises(QcxError) as e:
+        c.sync()
+    assert e.value.code == q.EINVAL and "k 3" in str(e.value)
+    c.set_states(st.q_cart, kf, cfg1.n_occ, dev(st.C_k, torch.complex128),
+                 dev(st.E_k, torch.float64), dev(st.C_kq, torch.complex128), dev(st.E_kq, torch.float64))
+    c.sync()
+    c.pair_density(cfg1.G_int)
+    c.chi0(cfg1.w_eV, cfg1.eta_eV, "fp64")
+    c.eps_inv()
+    ref = _oracle(cfg1)
+    assert normwise(c.loss(), ref["loss"]) < 1e-10
+    c.close()
