@@ -85,88 +85,102 @@ __device__ inline cplx cinv(cplx a) {
   return {a.re * d, -a.im * d};
 }
 
-// Register-resident Gauss-Jordan for n <= 32*RP and n <= 32*CP.  1024 threads:
-// thread (tr, tc) = (tid / 32, tid % 32) owns rows tr + 32 a and columns
-// tc + 32 b.  Step k (column block kb = k / 32 known at compile time) picks the
-// pivot row p among unused rows, publishes column k and row p through LDS and
-// applies the uniform rank-1 update m <- m0 - u w^T, where m0 is m with column
-// k replaced by e_p, u = column k with u_p = piv - 1 and w = row p / piv with
-// w_k = 1 / piv.  Three barriers per step.
-template <int RP, int CP>
-__global__ void __launch_bounds__(1024) k_gj_reg(const cplx* __restrict__ eps, int n,
-                                                 cplx* __restrict__ diag, int* sing) {
-  __shared__ cplx colk[32 * RP], rowp[32 * CP];
-  __shared__ int used[32 * RP], piv[32 * RP], sor[32 * RP];
-  __shared__ double redv[32];
-  __shared__ int redi[32];
-  __shared__ int pivrow;
-  const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
+// Register-resident Gauss-Jordan for n <= NTR*RP and n <= 32*CP with 32*NTR
+// threads: thread (tr, tc) = (tid / 32, tid % 32) owns rows tr + NTR a and
+// columns tc + 32 b; wave w holds row groups 2w and 2w + 1.  Step k (column
+// block kb = k / 32 known at compile time):
+//   1. the owners of column k propose the largest |re| + |im| among their
+//      unused rows; the two proposals of a wave are combined by a shuffle and
+//      written to LDS (one entry per wave);
+//   -- barrier --
+//   2. every wave reduces the proposals itself (same result everywhere, ties
+//      to the smaller row), which gives the pivot row p;
+//   3. the 32 owners of row p divide it by the pivot (the pivot value comes by
+//      shuffle from its owner) and publish w = row p / piv with w_k = 1 / piv;
+//      the owners of column k publish u = column k with u_p = piv - 1 and
+//      replace column k by e_p;
+//   -- barrier --
+//   4. every thread applies m <- m - u w^T to its RP x CP block.
+// Two barriers per step; the used-row marks live in registers.
+template <int RP, int CP, int NTR>
+__global__ void __launch_bounds__(32 * NTR) k_gj_reg(const cplx* __restrict__ eps, int n,
+                                                     cplx* __restrict__ diag, int* sing) {
+  constexpr int NWV = NTR / 2;  // waves
+  __shared__ cplx colk[NTR * RP], rowp[32 * CP];
+  __shared__ int piv[NTR * RP], sor[NTR * RP];
+  __shared__ double cand_v[NWV];
+  __shared__ int cand_i[NWV];
+  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31, lane = tid & 63;
   const cplx* A = eps + (size_t)blockIdx.x * n * n;
   cplx m[RP][CP];
 #pragma unroll
   for (int a = 0; a < RP; ++a)
 #pragma unroll
     for (int b = 0; b < CP; ++b) {
-      const int i = tr + 32 * a, j = tc + 32 * b;
+      const int i = tr + NTR * a, j = tc + 32 * b;
       m[a][b] = (i < n && j < n) ? A[(size_t)i * n + j] : cplx{0.0, 0.0};
     }
-  for (int i = threadIdx.x; i < 32 * RP; i += 1024) used[i] = 0;
+  unsigned used = 0;  // bit a: row tr + NTR a already served as pivot
   bool singular = false;
-  __syncthreads();
 #pragma unroll
   for (int kb = 0; kb < CP; ++kb) {
     for (int kk = 0; kk < 32; ++kk) {
       const int k = 32 * kb + kk;
       if (k >= n) break;
-      // pivot search over column k by its 32 owners (one per row group)
-      if (tc == kk) {
-        double best = -1.0;
-        int bi = INT_MAX;
+      // 1. proposals from the owners of column k
+      double best = -1.0;
+      int bi = INT_MAX;
 #pragma unroll
-        for (int a = 0; a < RP; ++a) {
-          const int i = tr + 32 * a;
-          if (i < n && !used[i]) {
-            double mag = fabs(m[a][kb].re) + fabs(m[a][kb].im);
-            if (mag != mag) mag = INFINITY;  // a NaN entry still selects a row
-            if (mag > best) {
-              best = mag;
-              bi = i;
-            }
+      for (int a = 0; a < RP; ++a) {
+        const int i = tr + NTR * a;
+        if (i < n && !((used >> a) & 1u)) {
+          double mag = fabs(m[a][kb].re) + fabs(m[a][kb].im);
+          if (mag != mag) mag = INFINITY;  // a NaN entry still selects a row
+          if (mag > best) {
+            best = mag;
+            bi = i;
           }
         }
-        redv[tr] = best;
-        redi[tr] = bi;
+      }
+      {
+        const double ob = __shfl_xor(best, 32, 64);
+        const int oi = __shfl_xor(bi, 32, 64);
+        if (oi != INT_MAX && (bi == INT_MAX || ob > best || (ob == best && oi < bi))) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == kk) {
+        cand_v[tid >> 6] = best;
+        cand_i[tid >> 6] = bi;
       }
       __syncthreads();
-      if (threadIdx.x < 64) {  // wave 0 reduces the 32 candidates by shuffles
-        double best = -1.0;
-        int bi = INT_MAX;
-        if (threadIdx.x < 32) {
-          best = redv[threadIdx.x];
-          bi = redi[threadIdx.x];
-        }
+      // 2. every wave reduces the proposals
+      double cb = lane < NWV ? cand_v[lane] : -1.0;
+      int ci = lane < NWV ? cand_i[lane] : INT_MAX;
 #pragma unroll
-        for (int off = 16; off > 0; off >>= 1) {
-          const double ov = __shfl_xor(best, off, 32);
-          const int oi = __shfl_xor(bi, off, 32);
-          if (oi != INT_MAX && (bi == INT_MAX || ov > best || (ov == best && oi < bi))) {
-            best = ov;
-            bi = oi;
-          }
-        }
-        if (threadIdx.x == 0) {
-          if (bi == INT_MAX) bi = 0;  // unreachable: some row is always unused
-          pivrow = bi;
-          used[bi] = 1;
-          piv[k] = bi;
-          sor[bi] = k;
+      for (int off = NWV / 2; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(cb, off, 64);
+        const int oi = __shfl_xor(ci, off, 64);
+        if (oi != INT_MAX && (ci == INT_MAX || ob > cb || (ob == cb && oi < ci))) {
+          cb = ob;
+          ci = oi;
         }
       }
-      __syncthreads();
-      const int p = pivrow;
-      // publish row p (before column k is overwritten: one thread may own both)
-      if (tr == (p & 31)) {
-        const int pa = p >> 5;
+      int p = __shfl(ci, 0, 64);
+      if (p == INT_MAX) p = 0;  // unreachable: some row is always unused
+      const int pa = p / NTR, pt = p - pa * NTR;
+      // 3. publish w (row p / piv) and u (column k, u_p = piv - 1)
+      if (tr == pt) {
+        cplx pv = m[0][kb];
+#pragma unroll
+        for (int a = 1; a < RP; ++a)
+          if (a == pa) pv = m[a][kb];
+        // the pivot sits in column k, i.e. with lane tc == kk of this half-wave
+        pv.re = __shfl(pv.re, (lane & 32) + kk, 64);
+        pv.im = __shfl(pv.im, (lane & 32) + kk, 64);
+        if (pv.re == 0.0 && pv.im == 0.0) singular = true;
+        const cplx inv = cinv(pv);
 #pragma unroll
         for (int b = 0; b < CP; ++b) {
           const int j = tc + 32 * b;
@@ -174,33 +188,35 @@ __global__ void __launch_bounds__(1024) k_gj_reg(const cplx* __restrict__ eps, i
 #pragma unroll
           for (int a = 1; a < RP; ++a)
             if (a == pa) v = m[a][b];
-          if (j < n) rowp[j] = v;
+          if (j < n) rowp[j] = (j == k) ? inv : cmul(v, inv);
+        }
+        if (tc == kk) {
+          colk[p] = {pv.re - 1.0, pv.im};
+          piv[k] = p;
+          sor[p] = k;
         }
       }
       if (tc == kk) {
 #pragma unroll
         for (int a = 0; a < RP; ++a) {
-          const int i = tr + 32 * a;
-          if (i < n) colk[i] = m[a][kb];
+          const int i = tr + NTR * a;
+          if (i < n && i != p) colk[i] = m[a][kb];
           m[a][kb] = {i == p ? 1.0 : 0.0, 0.0};
         }
       }
+      if (pt == tr) used |= 1u << pa;
       __syncthreads();
-      const cplx pv = rowp[k];
-      if (pv.re == 0.0 && pv.im == 0.0) singular = true;
-      const cplx inv = cinv(pv);
+      // 4. rank-1 update
       cplx wv[CP];
 #pragma unroll
       for (int b = 0; b < CP; ++b) {
         const int j = tc + 32 * b;
-        wv[b] = (j < n) ? cmul(rowp[j], inv) : cplx{0.0, 0.0};
+        wv[b] = j < n ? rowp[j] : cplx{0.0, 0.0};
       }
-      if (tc == kk) wv[kb] = inv;
 #pragma unroll
       for (int a = 0; a < RP; ++a) {
-        const int i = tr + 32 * a;
-        cplx u = (i < n) ? colk[i] : cplx{0.0, 0.0};
-        if (i == p) u.re -= 1.0;
+        const int i = tr + NTR * a;
+        const cplx u = i < n ? colk[i] : cplx{0.0, 0.0};
 #pragma unroll
         for (int b = 0; b < CP; ++b) {
           m[a][b].re -= u.re * wv[b].re - u.im * wv[b].im;
@@ -213,17 +229,17 @@ __global__ void __launch_bounds__(1024) k_gj_reg(const cplx* __restrict__ eps, i
   // [eps^-1]_kk = B[piv[k]][sor[k]]
   for (int k = 0; k < n; ++k) {
     const int i = piv[k], j = sor[k];
-    if ((i & 31) == tr && (j & 31) == tc) {
+    if (i % NTR == tr && (j & 31) == tc) {
       cplx v = {0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < RP; ++a)
 #pragma unroll
         for (int b = 0; b < CP; ++b)
-          if (a == (i >> 5) && b == (j >> 5)) v = m[a][b];
+          if (a == i / NTR && b == (j >> 5)) v = m[a][b];
       diag[(size_t)blockIdx.x * n + k] = v;
     }
   }
-  if (singular && threadIdx.x == 0) atomicMin(sing, (int)blockIdx.x);
+  if (singular) atomicMin(sing, (int)blockIdx.x);
 }
 
 // Blocked Gauss-Jordan for n > 128 (one block of 256 threads per matrix; the
@@ -433,9 +449,9 @@ void launch_chi0_export(const AsmArgs& a, const Chi0Geom& g, cplx* chi, hipStrea
 
 void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st) {
   if (n_g <= 64)
-    hipLaunchKernelGGL((k_gj_reg<2, 2>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
+    hipLaunchKernelGGL((k_gj_reg<2, 2, 32>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
   else if (n_g <= 128)
-    hipLaunchKernelGGL((k_gj_reg<4, 4>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
+    hipLaunchKernelGGL((k_gj_reg<4, 4, 32>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
   else if (gj_blocked_lds(n_g, 32) <= 160 * 1024)
     hipLaunchKernelGGL(k_gj_blocked<32>, dim3(n_w), dim3(256), gj_blocked_lds(n_g, 32), st, eps,
                        n_g, diag, sing);
