@@ -201,12 +201,28 @@ typedef struct qcx_item {
  * by ctxs[0] and replayed on later calls with the same signature; new states
  * or pair densities of the same shapes are picked up by the replay.
  *   precision, headwings_fp64, lfe as for qcx_chi0 / qcx_eps_inv.
- * Asynchronous; qcx_batch_sync(ctxs[0]) waits and reports QCX_ESINGULAR.
+ * The K split of each item follows from a target number of MFMA steps (16
+ * transitions each) per split, never more than 1024 steps per split in FP32
+ * (splits are added in FP64).  With autotuning on (qcx_set_autotune, FP32 and
+ * split-BF16), the first call of a signature builds a plan for each target in
+ * {128, 256, 512, 1024}, replays and times each with HIP events on ctxs[0]'s
+ * stream and keeps the fastest (that call synchronises the stream; tuning is
+ * skipped while the stream is being captured).  Every replay computes the
+ * complete result, so the outputs are those of the kept plan.
+ * Asynchronous otherwise; qcx_batch_sync(ctxs[0]) waits and reports
+ * QCX_ESINGULAR.  With timing on (qcx_set_timing on ctxs[0]),
+ * qcx_stage_times reports t[1] the persistent bulk launch, t[4] head/wings +
+ * assembly + inversion + loss, t[3] the whole batch.
  * Errors: QCX_EINVAL (sizes, devices, NULL loss_out), QCX_ESTATE (a context
  * without pair densities), QCX_ENOMEM, QCX_EDEVICE. */
 int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_items,
                   int precision, int headwings_fp64, int lfe);
 int qcx_batch_sync(qcx_ctx* ctx);
+/* Plan of the last batch run on ctx (the ctxs[0] of qcx_run_batch):
+ * cfg = {target MFMA steps per K split, tiles in the persistent list, blocks
+ * launched}, and the wall time spent tuning when the plan was built (ms, 0
+ * without tuning).  Errors: QCX_ESTATE (no batch yet). */
+int qcx_batch_config(qcx_ctx* ctx, int cfg[3], double* tune_ms);
 
 /* ---------------------------------------------------------------------------
  * Surrogate of the loss (not part of the paper's method): an ensemble of

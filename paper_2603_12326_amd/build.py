@@ -25,7 +25,7 @@ LIB = os.path.join(HERE, "libqcx.so")
 ARCH = os.environ.get("QCX_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
     f"-I{INCLUDE}", f"-I{CSRC}",

@@ -9,6 +9,8 @@
 // which row k served as pivot.
 #include <limits.h>
 
+#include <utility>
+
 #include "common.h"
 
 namespace qcx {
@@ -85,161 +87,413 @@ __device__ inline cplx cinv(cplx a) {
   return {a.re * d, -a.im * d};
 }
 
-// Register-resident Gauss-Jordan for n <= NTR*RP and n <= 32*CP with 32*NTR
-// threads: thread (tr, tc) = (tid / 32, tid % 32) owns rows tr + NTR a and
-// columns tc + 32 b; wave w holds row groups 2w and 2w + 1.  Step k (column
-// block kb = k / 32 known at compile time):
-//   1. the owners of column k propose the largest |re| + |im| among their
-//      unused rows; the two proposals of a wave are combined by a shuffle and
-//      written to LDS (one entry per wave);
-//   -- barrier --
-//   2. every wave reduces the proposals itself (same result everywhere, ties
-//      to the smaller row), which gives the pivot row p;
-//   3. the 32 owners of row p divide it by the pivot (the pivot value comes by
-//      shuffle from its owner) and publish w = row p / piv with w_k = 1 / piv;
-//      the owners of column k publish u = column k with u_p = piv - 1 and
-//      replace column k by e_p;
-//   -- barrier --
-//   4. every thread applies m <- m - u w^T to its RP x CP block.
-// Two barriers per step; the used-row marks live in registers.
-template <int RP, int CP, int NTR>
-__global__ void __launch_bounds__(32 * NTR) k_gj_reg(const cplx* __restrict__ eps, int n,
-                                                     cplx* __restrict__ diag, int* sing) {
-  constexpr int NWV = NTR / 2;  // waves
-  __shared__ cplx colk[NTR * RP], rowp[32 * CP];
-  __shared__ int piv[NTR * RP], sor[NTR * RP];
-  __shared__ double cand_v[NWV];
-  __shared__ int cand_i[NWV];
-  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31, lane = tid & 63;
+// Pivot key for an LDS atomic maximum: the modulus |re| + |im| in the high
+// bits (non-negative doubles order like their bit patterns), the complement
+// of the row index in the low 12 bits, so that moduli equal to 40 bits go to
+// the smaller row.  A NaN entry counts as infinite so that it still selects a
+// row (and poisons the result instead of hiding).  Every key is > 0.
+__device__ inline unsigned long long pivot_key(cplx v, int row) {
+  double mag = fabs(v.re) + fabs(v.im);
+  if (mag != mag) mag = INFINITY;
+  const unsigned long long b = (unsigned long long)__double_as_longlong(mag);
+  return (b & ~0xFFFull) | (unsigned long long)(0xFFF - row);
+}
+
+// An empty asm statement makes x opaque, so that choosing one element of a
+// register array by a run-time index (a == pa, b == jt / 16) stays a choice
+// between values instead of becoming an indexed load that would move the
+// whole array to scratch memory.
+__device__ inline cplx opaque(cplx x) {
+  asm volatile("" : "+v"(x.re), "+v"(x.im));
+  return x;
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Maximum of a 64-bit value over the wave: butterflies inside each row of 16
+// lanes by DPP (lane xor 1, xor 2, half-row mirror, row mirror), then the four
+// row results by readlane.  Needs every lane active.
+__device__ inline unsigned long long wave_max_u64(unsigned long long x) {
+  auto step = [&](auto ctrl) {
+    constexpr int c = decltype(ctrl)::value;
+    const int lo = __builtin_amdgcn_update_dpp((int)x, (int)x, c, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(x >> 32), (int)(x >> 32), c, 0xF, 0xF, false);
+    const unsigned long long o = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    x = o > x ? o : x;
+  };
+  step(std::integral_constant<int, 0xB1>{});   // quad_perm [1,0,3,2]
+  step(std::integral_constant<int, 0x4E>{});   // quad_perm [2,3,0,1]
+  step(std::integral_constant<int, 0x141>{});  // row_half_mirror
+  step(std::integral_constant<int, 0x140>{});  // row_mirror
+  unsigned long long r = 0ull;
+#pragma unroll
+  for (int row = 0; row < 4; ++row) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)x, 16 * row);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), 16 * row);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    r = o > r ? o : r;
+  }
+  return r;
+}
+
+// Register-resident Gauss-Jordan for n <= 64 RP and n <= 16 CP with 16 waves:
+// lane l of wave v owns rows l + 64 a and columns v + 16 b, so column k lives
+// in wave k % 16 alone.  Step k applies m <- m - u w^T with the pivot folded
+// into u: u_i = c_i / piv (u_p = (piv - 1) / piv) and w = row p as it stands
+// except w_k = piv + 1, where c = column k and piv = m[p][k].  This is the
+// Gauss-Jordan sweep (row p / piv, column k -c / piv, pivot 1 / piv, the rest
+// m - c row_p / piv) with no per-element fix-ups.
+//
+// One barrier per step.  Before it, the owner of column k has chosen the pivot
+// (largest unused |re| + |im|, by a wave-wide maximum of 64-bit keys) and
+// published u and p through LDS.  After it, every wave reads row p of its own
+// columns from its lane p % 64 with readlane (scalar registers, no LDS
+// traffic: the LDS pipe is shared by all 16 waves and is the tighter
+// resource) and updates its block; the owner of column k + 1 updates that
+// column first and then chooses and publishes the next pivot while the other
+// waves are still in their FMAs.  u and p are double-buffered by the parity
+// of k; u is zero past row n; used-row marks live in registers.
+template <int RP, int CP>
+__global__ void __launch_bounds__(1024) k_gj_reg(const cplx* __restrict__ eps, int n,
+                                                 cplx* __restrict__ diag, int* sing) {
+  constexpr int NW = 16;
+  __shared__ cplx ucol[2][64 * RP];
+  __shared__ int prow[2], sor[64 * RP];
+  const int tid = threadIdx.x, l = tid & 63;
+  const int v = __builtin_amdgcn_readfirstlane(tid >> 6);
   const cplx* A = eps + (size_t)blockIdx.x * n * n;
   cplx m[RP][CP];
 #pragma unroll
   for (int a = 0; a < RP; ++a)
 #pragma unroll
     for (int b = 0; b < CP; ++b) {
-      const int i = tr + NTR * a, j = tc + 32 * b;
+      const int i = l + 64 * a, j = v + NW * b;
       m[a][b] = (i < n && j < n) ? A[(size_t)i * n + j] : cplx{0.0, 0.0};
     }
-  unsigned used = 0;  // bit a: row tr + NTR a already served as pivot
+  for (int e = tid; e < 2 * 64 * RP; e += 1024) (&ucol[0][0])[e] = {0.0, 0.0};
+  __syncthreads();
+  unsigned used = 0;       // bit a: row l + 64 a already served as pivot
   bool singular = false;
+  cplx wk = {0.0, 0.0};    // piv + 1 of the column this wave owns next
+
+  // Owner wave of column kc (current values c): choose the pivot, publish u
+  // into buffer pb, p and sor[p].
+  auto choose = [&](const cplx (&c)[RP], int kc, int pb) {
+    unsigned long long best = 0ull;
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const int i = l + 64 * a;
+      if (i < n && !((used >> a) & 1u)) best = max(best, pivot_key(c[a], i));
+    }
+    best = wave_max_u64(best);
+    const int p = __builtin_amdgcn_readfirstlane(0xFFF - (int)(best & 0xFFFull));
+    const int pl = p & 63, pa = p >> 6;
+    cplx pv = {0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const cplx x = {readlane_d(c[a].re, pl), readlane_d(c[a].im, pl)};
+      if (a == pa) pv = x;
+    }
+    if (pv.re == 0.0 && pv.im == 0.0) singular = true;
+    const cplx inv = cinv(pv);
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const int i = l + 64 * a;
+      cplx x = c[a];
+      if (i == p) x.re -= 1.0;
+      if (i < n) ucol[pb][i] = cmul(x, inv);
+    }
+    if (l == 0) {
+      prow[pb] = p;
+      sor[p] = kc;
+    }
+    wk = {pv.re + 1.0, pv.im};
+  };
+
+  if (v == 0) {
+    cplx c[RP];
+#pragma unroll
+    for (int a = 0; a < RP; ++a) c[a] = m[a][0];
+    choose(c, 0, 0);
+  }
+  // Step k = 16 kb + kk; with kb and t unrolled every register index is
+  // static.  Columns are visited from slot kb onwards, so column k + 1 (slot
+  // kb, or kb + 1 when kk = 15) is updated first or second by its owner.
 #pragma unroll
   for (int kb = 0; kb < CP; ++kb) {
-    for (int kk = 0; kk < 32; ++kk) {
-      const int k = 32 * kb + kk;
+    for (int kk = 0; kk < NW; ++kk) {
+      const int k = NW * kb + kk;
       if (k >= n) break;
-      // 1. proposals from the owners of column k
-      double best = -1.0;
-      int bi = INT_MAX;
-#pragma unroll
-      for (int a = 0; a < RP; ++a) {
-        const int i = tr + NTR * a;
-        if (i < n && !((used >> a) & 1u)) {
-          double mag = fabs(m[a][kb].re) + fabs(m[a][kb].im);
-          if (mag != mag) mag = INFINITY;  // a NaN entry still selects a row
-          if (mag > best) {
-            best = mag;
-            bi = i;
-          }
-        }
-      }
-      {
-        const double ob = __shfl_xor(best, 32, 64);
-        const int oi = __shfl_xor(bi, 32, 64);
-        if (oi != INT_MAX && (bi == INT_MAX || ob > best || (ob == best && oi < bi))) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (lane == kk) {
-        cand_v[tid >> 6] = best;
-        cand_i[tid >> 6] = bi;
-      }
-      __syncthreads();
-      // 2. every wave reduces the proposals
-      double cb = lane < NWV ? cand_v[lane] : -1.0;
-      int ci = lane < NWV ? cand_i[lane] : INT_MAX;
-#pragma unroll
-      for (int off = NWV / 2; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(cb, off, 64);
-        const int oi = __shfl_xor(ci, off, 64);
-        if (oi != INT_MAX && (ci == INT_MAX || ob > cb || (ob == cb && oi < ci))) {
-          cb = ob;
-          ci = oi;
-        }
-      }
-      int p = __shfl(ci, 0, 64);
-      if (p == INT_MAX) p = 0;  // unreachable: some row is always unused
-      const int pa = p / NTR, pt = p - pa * NTR;
-      // 3. publish w (row p / piv) and u (column k, u_p = piv - 1)
-      if (tr == pt) {
-        cplx pv = m[0][kb];
-#pragma unroll
-        for (int a = 1; a < RP; ++a)
-          if (a == pa) pv = m[a][kb];
-        // the pivot sits in column k, i.e. with lane tc == kk of this half-wave
-        pv.re = __shfl(pv.re, (lane & 32) + kk, 64);
-        pv.im = __shfl(pv.im, (lane & 32) + kk, 64);
-        if (pv.re == 0.0 && pv.im == 0.0) singular = true;
-        const cplx inv = cinv(pv);
-#pragma unroll
-        for (int b = 0; b < CP; ++b) {
-          const int j = tc + 32 * b;
-          cplx v = m[0][b];
-#pragma unroll
-          for (int a = 1; a < RP; ++a)
-            if (a == pa) v = m[a][b];
-          if (j < n) rowp[j] = (j == k) ? inv : cmul(v, inv);
-        }
-        if (tc == kk) {
-          colk[p] = {pv.re - 1.0, pv.im};
-          piv[k] = p;
-          sor[p] = k;
-        }
-      }
-      if (tc == kk) {
-#pragma unroll
-        for (int a = 0; a < RP; ++a) {
-          const int i = tr + NTR * a;
-          if (i < n && i != p) colk[i] = m[a][kb];
-          m[a][kb] = {i == p ? 1.0 : 0.0, 0.0};
-        }
-      }
-      if (pt == tr) used |= 1u << pa;
-      __syncthreads();
-      // 4. rank-1 update
-      cplx wv[CP];
+      const int par = k & 1;
+      __syncthreads();  // u, p of column k published
+      const int p = __builtin_amdgcn_readfirstlane(prow[par]);
+      const int pl = p & 63, pa = p >> 6;
+      if (l == pl) used |= 1u << pa;
+      cplx wr[CP];  // row p of this wave's columns (lane pl), wave-uniform
 #pragma unroll
       for (int b = 0; b < CP; ++b) {
-        const int j = tc + 32 * b;
-        wv[b] = j < n ? rowp[j] : cplx{0.0, 0.0};
+        cplx x = m[0][b];
+#pragma unroll
+        for (int a = 1; a < RP; ++a)
+          if (a == pa) x = opaque(m[a][b]);
+        wr[b] = {readlane_d(x.re, pl), readlane_d(x.im, pl)};
       }
+      if (v == kk) wr[kb] = wk;  // owner of column k: w_k = piv + 1
+      cplx u[RP];
 #pragma unroll
-      for (int a = 0; a < RP; ++a) {
-        const int i = tr + NTR * a;
-        const cplx u = i < n ? colk[i] : cplx{0.0, 0.0};
+      for (int a = 0; a < RP; ++a) u[a] = ucol[par][l + 64 * a];
+      const int k1 = k + 1;
+      const bool owner1 = k1 < n && v == k1 % NW;  // owns column k + 1
+      const bool next = kk == NW - 1;               // column k + 1 in slot kb + 1
 #pragma unroll
-        for (int b = 0; b < CP; ++b) {
-          m[a][b].re -= u.re * wv[b].re - u.im * wv[b].im;
-          m[a][b].im -= u.re * wv[b].im + u.im * wv[b].re;
+      for (int t = 0; t < CP; ++t) {
+        const int b = (kb + t) % CP;
+        if (v + NW * b < n) {
+          const cplx w = wr[b];
+#pragma unroll
+          for (int a = 0; a < RP; ++a) {
+            m[a][b].re = fma(-u[a].re, w.re, m[a][b].re);
+            m[a][b].re = fma(u[a].im, w.im, m[a][b].re);
+            m[a][b].im = fma(-u[a].re, w.im, m[a][b].im);
+            m[a][b].im = fma(-u[a].im, w.re, m[a][b].im);
+          }
+        }
+        if (owner1 && ((t == 0 && !next) || (t == 1 && next))) {
+          cplx c[RP];
+#pragma unroll
+          for (int a = 0; a < RP; ++a) c[a] = m[a][b];
+          choose(c, k1, par ^ 1);
         }
       }
     }
   }
   __syncthreads();
-  // [eps^-1]_kk = B[piv[k]][sor[k]]
-  for (int k = 0; k < n; ++k) {
-    const int i = piv[k], j = sor[k];
-    if (i % NTR == tr && (j & 31) == tc) {
-      cplx v = {0.0, 0.0};
+  // [eps^-1]_kk sits at row piv[k] (the row whose sor is k) and column sor[k]
 #pragma unroll
-      for (int a = 0; a < RP; ++a)
+  for (int a = 0; a < RP; ++a) {
+    const int i = l + 64 * a;
+    if (i >= n) continue;
+    const int k = sor[i], jt = sor[k];
+    if (jt % NW != v) continue;
 #pragma unroll
-        for (int b = 0; b < CP; ++b)
-          if (a == i / NTR && b == (j >> 5)) v = m[a][b];
-      diag[(size_t)blockIdx.x * n + k] = v;
-    }
+    for (int b = 0; b < CP; ++b)
+      if (b == jt / NW) diag[(size_t)blockIdx.x * n + k] = opaque(m[a][b]);
   }
   if (singular) atomicMin(sing, (int)blockIdx.x);
+}
+
+// Blocked Gauss-Jordan for 128 < n <= 64 RP (RP <= 16) with 1024 threads per
+// matrix; the matrix stays in global memory and is swept in panels of 16
+// columns.  For each panel:
+//  1. lane l of wave v holds rows l + 64 a of panel column k0 + v in
+//     registers, and the panel's 16 pivot steps run as in k_gj_reg (one
+//     barrier per step, the next column's owner chooses its pivot while the
+//     others update), restricted to the panel columns;
+//  2. the swept panel is written back, and every other column j receives the
+//     deferred rank-16 update  T[:, j] += Z Y[:, j]  with Y = T[P][j] (the 16
+//     pivot rows before this update) and Z = swept panel with 1 subtracted
+//     at (p_a, a).  The update is a register-tiled complex GEMM: Z (in chunks
+//     of at most 512 rows) and a 16 x 32 tile of Y are staged in LDS, each
+//     thread accumulates up to 4 rows x 4 columns and updates them in place.
+// Y tiles are read before any row of that tile is updated, so pivot rows see
+// their old values; when Z needs several chunks, all chunks of one column
+// tile are done before the next tile.  LDS: Z (ZR x 16, aliased by the pivot
+// column buffers during step 1), one Y tile, piv and sor.
+template <int RP>
+__global__ void __launch_bounds__(1024) k_gj_panel(cplx* __restrict__ eps, int n,
+                                                   cplx* __restrict__ diag, int* sing) {
+  constexpr int NW = 16, MB = 16, JT = 32;
+  constexpr int ZR = 64 * RP < 512 ? 64 * RP : 512;
+  constexpr int QP = 1;  // row slots per thread per pass of the update
+  extern __shared__ __align__(16) char smem[];
+  cplx* Zs = reinterpret_cast<cplx*>(smem);  // [ZR][MB]
+  cplx* ucol = Zs;                           // [2][64 RP] during the pivot steps
+  cplx* Ys = Zs + (size_t)ZR * MB;           // [2][MB][JT]
+  int* piv = reinterpret_cast<int*>(Ys + 2 * MB * JT);  // [n] pivot row of step k
+  int* sor = piv + n;                               // [n] step of pivot row i
+  __shared__ int prow[2];
+  const int tid = threadIdx.x, l = tid & 63;
+  const int v = __builtin_amdgcn_readfirstlane(tid >> 6);
+  cplx* A = eps + (size_t)blockIdx.x * n * n;
+  unsigned used = 0;  // bit a: row l + 64 a already served as pivot
+  bool singular = false;
+  cplx wk = {0.0, 0.0};
+
+  auto choose = [&](const cplx (&c)[RP], int kc, int pb) {
+    unsigned long long best = 0ull;
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const int i = l + 64 * a;
+      if (i < n && !((used >> a) & 1u)) best = max(best, pivot_key(c[a], i));
+    }
+    best = wave_max_u64(best);
+    const int p = __builtin_amdgcn_readfirstlane(0xFFF - (int)(best & 0xFFFull));
+    const int pl = p & 63, pa = p >> 6;
+    cplx x = c[0];
+#pragma unroll
+    for (int a = 1; a < RP; ++a)
+      if (a == pa) x = opaque(c[a]);
+    const cplx pv = {readlane_d(x.re, pl), readlane_d(x.im, pl)};
+    if (pv.re == 0.0 && pv.im == 0.0) singular = true;
+    const cplx inv = cinv(pv);
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const int i = l + 64 * a;
+      cplx y = c[a];
+      if (i == p) y.re -= 1.0;
+      if (i < n) ucol[pb * 64 * RP + i] = cmul(y, inv);
+    }
+    if (l == 0) {
+      prow[pb] = p;
+      piv[kc] = p;
+      sor[p] = kc;
+    }
+    wk = {pv.re + 1.0, pv.im};
+  };
+
+  for (int k0 = 0; k0 < n; k0 += MB) {
+    const int mb = min(MB, n - k0);
+    const bool hascol = v < mb;
+    const int jc = k0 + v;
+    __syncthreads();  // the previous panel's update is complete
+    cplx pm[RP];
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const int i = l + 64 * a;
+      pm[a] = (hascol && i < n) ? A[(size_t)i * n + jc] : cplx{0.0, 0.0};
+    }
+    if (v == 0) choose(pm, k0, k0 & 1);
+    for (int kk = 0; kk < mb; ++kk) {
+      const int k = k0 + kk, par = k & 1;
+      __syncthreads();  // u, p of column k published
+      const int p = __builtin_amdgcn_readfirstlane(prow[par]);
+      const int pl = p & 63, pa = p >> 6;
+      if (l == pl) used |= 1u << pa;
+      if (hascol) {
+        cplx x = pm[0];
+#pragma unroll
+        for (int a = 1; a < RP; ++a)
+          if (a == pa) x = opaque(pm[a]);
+        cplx w = {readlane_d(x.re, pl), readlane_d(x.im, pl)};
+        if (v == kk) w = wk;  // owner of column k: w_k = piv + 1
+#pragma unroll
+        for (int a = 0; a < RP; ++a) {
+          const int i = l + 64 * a;
+          const cplx u = i < n ? ucol[par * 64 * RP + i] : cplx{0.0, 0.0};
+          pm[a].re = fma(-u.re, w.re, pm[a].re);
+          pm[a].re = fma(u.im, w.im, pm[a].re);
+          pm[a].im = fma(-u.re, w.im, pm[a].im);
+          pm[a].im = fma(-u.im, w.re, pm[a].im);
+          // keep the scheduler from hoisting all RP loads of u at once
+          if ((a & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        if (kk + 1 < mb && v == kk + 1) choose(pm, k + 1, par ^ 1);
+      }
+    }
+    if (hascol) {
+#pragma unroll
+      for (int a = 0; a < RP; ++a) {
+        const int i = l + 64 * a;
+        if (i < n) A[(size_t)i * n + jc] = pm[a];
+      }
+    }
+    __syncthreads();  // swept panel in memory; pivot buffers free
+    // ---- deferred rank-mb update of every column outside the panel
+    const int nch = (n + ZR - 1) / ZR;
+    auto load_z = [&](int r0) {
+      for (int e = tid; e < ZR * MB; e += 1024) {
+        const int r = e >> 4, a = e & 15, i = r0 + r;
+        cplx z = (i < n && a < mb) ? A[(size_t)i * n + k0 + a] : cplx{0.0, 0.0};
+        if (a < mb && i == piv[k0 + a]) z.re -= 1.0;
+        Zs[e] = z;
+      }
+    };
+    const int cg = tid & 7, rg = tid >> 3;  // 4 columns, rows rg + 128 q
+    // One pass: rows r0 + rp + rg + 128 q (q < QP) x columns jt + 4 cg + c of
+    // Z (rows of the current chunk in LDS) times Y (tile ys).  The targets
+    // are loaded before the FMAs so that their latency is hidden.
+    auto pass = [&](int r0, int rp, int jt, const cplx* ys) {
+      cplx acc[QP][4], t[QP][4];
+#pragma unroll
+      for (int q = 0; q < QP; ++q) {
+        const int i = r0 + rp + rg + 128 * q;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int j = jt + 4 * cg + c;
+          acc[q][c] = {0.0, 0.0};
+          t[q][c] = (rp + rg + 128 * q < ZR && i < n && j < n) ? A[(size_t)i * n + j]
+                                                             : cplx{0.0, 0.0};
+        }
+      }
+      for (int a = 0; a < mb; ++a) {
+        cplx y[4], z[QP];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) y[c] = ys[a * JT + 4 * cg + c];
+#pragma unroll
+        for (int q = 0; q < QP; ++q) {
+          const int r = rp + rg + 128 * q;
+          z[q] = r < ZR ? Zs[r * MB + a] : cplx{0.0, 0.0};
+        }
+#pragma unroll
+        for (int q = 0; q < QP; ++q)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            acc[q][c].re = fma(z[q].re, y[c].re, acc[q][c].re);
+            acc[q][c].re = fma(-z[q].im, y[c].im, acc[q][c].re);
+            acc[q][c].im = fma(z[q].re, y[c].im, acc[q][c].im);
+            acc[q][c].im = fma(z[q].im, y[c].re, acc[q][c].im);
+          }
+      }
+#pragma unroll
+      for (int q = 0; q < QP; ++q) {
+        const int r = rp + rg + 128 * q, i = r0 + r;
+        if (r >= ZR || i >= n) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int j = jt + 4 * cg + c;
+          if (j < n && (j < k0 || j >= k0 + mb))
+            A[(size_t)i * n + j] = {t[q][c].re + acc[q][c].re, t[q][c].im + acc[q][c].im};
+        }
+      }
+    };
+    // Y tiles are double-buffered: the next tile's pivot-row values are read
+    // into a register during this tile's FMAs (other columns, so not yet
+    // updated) and stored after it.
+    auto y_elem = [&](int jt, int e) -> cplx {
+      const int a = e / JT, j = jt + e % JT;
+      return (e < MB * JT && a < mb && j < n) ? A[(size_t)piv[k0 + a] * n + j] : cplx{0.0, 0.0};
+    };
+    if (nch == 1) load_z(0);
+    if (tid < MB * JT) Ys[tid] = y_elem(0, tid);
+    int cur = 0;
+    for (int jt = 0; jt < n; jt += JT) {
+      const cplx yn = (jt + JT < n) ? y_elem(jt + JT, tid) : cplx{0.0, 0.0};
+      const cplx* ys = Ys + cur * MB * JT;
+      for (int c = 0; c < nch; ++c) {
+        __syncthreads();  // Y staged (and Z, or the previous chunk's reads done)
+        if (nch > 1) {
+          load_z(c * ZR);
+          __syncthreads();
+        }
+        for (int rp = 0; rp < ZR; rp += 128 * QP) pass(c * ZR, rp, jt, ys);
+      }
+      if (tid < MB * JT) Ys[(cur ^ 1) * MB * JT + tid] = yn;
+      cur ^= 1;
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < n; k += 1024) diag[(size_t)blockIdx.x * n + k] = A[(size_t)piv[k] * n + sor[k]];
+  if (singular) atomicMin(sing, (int)blockIdx.x);
+}
+
+size_t gj_panel_lds(int n, int rp) {
+  const int zr = 64 * rp < 512 ? 64 * rp : 512;
+  return sizeof(cplx) * ((size_t)zr * 16 + 2 * 16 * 32) + sizeof(int) * 2 * (size_t)n;
 }
 
 // Blocked Gauss-Jordan for n > 128 (one block of 256 threads per matrix; the
@@ -449,10 +703,21 @@ void launch_chi0_export(const AsmArgs& a, const Chi0Geom& g, cplx* chi, hipStrea
 
 void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st) {
   if (n_g <= 64)
-    hipLaunchKernelGGL((k_gj_reg<2, 2, 32>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
+    hipLaunchKernelGGL((k_gj_reg<1, 4>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
   else if (n_g <= 128)
-    hipLaunchKernelGGL((k_gj_reg<4, 4, 32>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
-  else if (gj_blocked_lds(n_g, 32) <= 160 * 1024)
+    hipLaunchKernelGGL((k_gj_reg<2, 8>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
+  else if (n_g <= 1024) {
+#define QCX_GJP(R)                                                                             \
+  hipLaunchKernelGGL(k_gj_panel<R>, dim3(n_w), dim3(1024), gj_panel_lds(n_g, R), st, eps, n_g, diag, \
+                     sing)
+    if (n_g <= 192) QCX_GJP(3);
+    else if (n_g <= 256) QCX_GJP(4);
+    else if (n_g <= 320) QCX_GJP(5);
+    else if (n_g <= 512) QCX_GJP(8);
+    else if (n_g <= 768) QCX_GJP(12);
+    else QCX_GJP(16);
+#undef QCX_GJP
+  } else if (gj_blocked_lds(n_g, 32) <= 160 * 1024)
     hipLaunchKernelGGL(k_gj_blocked<32>, dim3(n_w), dim3(256), gj_blocked_lds(n_g, 32), st, eps,
                        n_g, diag, sing);
   else if (gj_blocked_lds(n_g, 16) <= 160 * 1024)

@@ -5,10 +5,19 @@
 // weights, R32 packs per context, pair tables, one tile list for the
 // persistent bulk kernel (ordered by decreasing cost, so that small items fill
 // the gaps left by large ones), per-item FP64 head/wings, and per-item
-// assembly, inversion and loss.  The whole sequence is captured into one
-// hipGraph; later calls with the same signature replay it with a single
-// launch.  Capture records kernels only (counters and flags are reset by a
-// one-thread kernel, not by memset nodes).
+// assembly, inversion and loss.  The sequence is captured into three hipGraphs
+// (operand preparation, the persistent bulk launch, everything after it) so
+// that the bulk kernel can be timed on its own; later calls with the same
+// signature replay them.  Capture records kernels only (counters and flags are
+// reset by a one-thread kernel, not by memset nodes).
+//
+// Autotuning: the K split of every item follows from a target number of MFMA
+// steps per split (more splits = more tiles to balance the persistent grid,
+// fewer = less partial-sum traffic).  With autotuning on, a plan is built for
+// each candidate target, its graphs are replayed and timed with HIP events,
+// and the fastest plan is kept.
+#include <chrono>
+
 #include "ctx.h"
 
 namespace qcx {
@@ -29,13 +38,16 @@ struct BatchPlan {
   std::vector<PlanItem> items;
   std::vector<DevBuf> r32;  // per context
   DevBuf d_items, d_tiles, d_counter, d_sing;
-  int n_tiles = 0, max_ng = 0;
+  int n_tiles = 0, max_ng = 0, target_steps = 0, grid = 0;
+  double tune_ms = 0.0;
   bool gather = false;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
   ~BatchPlan() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (int i = 0; i < 3; ++i) {
+      if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+      if (graph[i]) (void)hipGraphDestroy(graph[i]);
+    }
     for (PlanItem& it : items) {
       DevBuf* b[] = {&it.w, &it.A, &it.Alo, &it.pairs, &it.rows, &it.pairs64, &it.C, &it.XY,
                      &it.eps, &it.diag, &it.epsM, &it.loss};
@@ -79,15 +91,59 @@ std::vector<double> batch_key(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* i
   return k;
 }
 
+// K split of one item: the largest power of two (up to 64) that keeps at
+// least target_steps MFMA steps per split, raised until no split sums more
+// than 1024 steps in FP32 (the splits are added in FP64 by the assembly).
 int ksplit_for(int ntb, int target_steps) {
   int ks = 1;
-  while (ks < 16 && ntb / (2 * ks) >= target_steps) ks *= 2;
+  while (ks < 64 && ntb / (2 * ks) >= target_steps) ks *= 2;
+  while (ks < 64 && ntb > ks * 1024) ks *= 2;
   return ks;
 }
 
+// Capture the work enqueued by fn on a private stream into P->graph[i] and
+// instantiate it (the caller's stream may be the legacy default stream, which
+// cannot be captured).
+template <class F>
+int capture(qcx_ctx* ctx, BatchPlan* P, int i, F&& fn) {
+  hipStream_t cap = nullptr;
+  HIPCK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return fail(ctx, QCX_EDEVICE, std::string("begin capture: ") + hipGetErrorString(e));
+  }
+  fn(cap);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cap, &graph);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) return fail(ctx, QCX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  P->graph[i] = graph;
+  e = hipGraphInstantiate(&P->exec[i], graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return fail(ctx, QCX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return QCX_OK;
+}
+
+// Replay a plan on the context's stream; timed spans (when timing is on):
+// stage 1 the persistent bulk launch, stage 4 head/wings + assembly +
+// inversion + loss, stage 3 the whole batch.
+hipError_t launch_plan(qcx_ctx* ctx, const BatchPlan* P) {
+  int sp_all = -1, sp = -1;
+  hipError_t e = span_begin(ctx, 3, &sp_all);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < 3; ++i) {
+    if (!P->exec[i]) continue;
+    if (i > 0 && (e = span_begin(ctx, i == 1 ? 1 : 4, &sp)) != hipSuccess) return e;
+    if ((e = hipGraphLaunch(P->exec[i], ctx->stream)) != hipSuccess) return e;
+    if (i > 0 && (e = span_end(ctx, sp)) != hipSuccess) return e;
+  }
+  return span_end(ctx, sp_all);
+}
+
 int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_items,
-               int precision, int lfe, int hw64, BatchPlan* P) {
+               int precision, int lfe, int hw64, int target_steps, BatchPlan* P) {
   hipStream_t st = ctx->stream;
+  P->target_steps = target_steps;
   P->precision = precision;
   P->lfe = lfe;
   P->hw64 = hw64;
@@ -131,7 +187,7 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
       g.n_rowsp = (int)roundup(g.n_rows, 32 * kBatchAF);
       g.c_rows = g.n_rowsp;
       const int ntb0 = (int)roundup(g.n_t, 16) / 16;
-      g.ksplit = ksplit_for(ntb0, 256);
+      g.ksplit = ksplit_for(ntb0, target_steps);
       g.n_tp = (int)roundup(g.n_t, 16 * g.ksplit);
       ctx_ntp[in.ctx] = std::max(ctx_ntp[in.ctx], g.n_tp);
       const size_t nA = (size_t)g.n_rowsp * g.n_tp;
@@ -200,80 +256,93 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
   HIPCK(P->d_sing.reserve(sizeof(int) * (size_t)n_items));
   HIPCK(hipStreamSynchronize(st));  // uploads complete before capture begins
 
-  // ---- capture on a private stream (the caller's may be the legacy default
-  // stream, which cannot be captured); the graph is replayed on the caller's
-  hipStream_t cap = nullptr;
-  HIPCK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-  st = cap;
-  hipError_t ecap = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-  if (ecap != hipSuccess) {
-    (void)hipStreamDestroy(cap);
-    return fail(ctx, QCX_EDEVICE, std::string("begin capture: ") + hipGetErrorString(ecap));
-  }
-  for (int c = 0; c < n_ctx; ++c) {
-    if (ctx_ntp[c] == 0) continue;
-    Chi0Geom gp{};
-    gp.n_g = ctxs[c]->n_g;
-    gp.n_tp = ctx_ntp[c];
-    launch_pack_r32(ctxs[c]->d_R.as<cplx>(), ctxs[c]->ldt, gp, bf ? 0 : 1, P->r32[c].as<float>(),
-                    st);
-  }
-  for (int i = 0; i < n_items; ++i) {
-    PlanItem& it = P->items[i];
-    qcx_ctx* c = ctxs[it.ctx];
-    if (bulk && it.g.n_bulk > 0) {
-      if (bf)
-        launch_weights_bf16(it.w.as<double>(), c->d_dt.as<double>(), it.eta, it.g,
-                            it.A.as<uint16_t>(), it.Alo.as<uint16_t>(), st);
-      else
-        launch_weights_f32(it.w.as<double>(), c->d_dt.as<double>(), it.eta, it.g,
-                           it.A.as<float>(), st);
-    }
+  P->grid = std::min(P->n_tiles, 2 * 256);
+  if (bulk) {
+    int rc = capture(ctx, P, 0, [&](hipStream_t cs) {
+      for (int c = 0; c < n_ctx; ++c) {
+        if (ctx_ntp[c] == 0) continue;
+        Chi0Geom gp{};
+        gp.n_g = ctxs[c]->n_g;
+        gp.n_tp = ctx_ntp[c];
+        launch_pack_r32(ctxs[c]->d_R.as<cplx>(), ctxs[c]->ldt, gp, bf ? 0 : 1,
+                        P->r32[c].as<float>(), cs);
+      }
+      for (int i = 0; i < n_items; ++i) {
+        PlanItem& it = P->items[i];
+        qcx_ctx* c = ctxs[it.ctx];
+        if (it.g.n_bulk == 0) continue;
+        if (bf)
+          launch_weights_bf16(it.w.as<double>(), c->d_dt.as<double>(), it.eta, it.g,
+                              it.A.as<uint16_t>(), it.Alo.as<uint16_t>(), cs);
+        else
+          launch_weights_f32(it.w.as<double>(), c->d_dt.as<double>(), it.eta, it.g,
+                             it.A.as<float>(), cs);
+      }
+    });
+    if (rc != QCX_OK) return rc;
   }
   if (P->n_tiles > 0) {
-    launch_set_int(P->d_counter.as<int>(), 0, st);
-    const int grid = std::min(P->n_tiles, 2 * 256);
-    launch_bulk_persistent(bf, P->gather, P->d_items.as<BulkItem>(), P->d_tiles.as<int4>(),
-                           P->n_tiles,
-                           P->d_counter.as<int>(), P->max_ng, grid, st);
+    int rc = capture(ctx, P, 1, [&](hipStream_t cs) {
+      launch_set_int(P->d_counter.as<int>(), 0, cs);
+      launch_bulk_persistent(bf, P->gather, P->d_items.as<BulkItem>(), P->d_tiles.as<int4>(),
+                             P->n_tiles, P->d_counter.as<int>(), P->max_ng, P->grid, cs);
+    });
+    if (rc != QCX_OK) return rc;
   }
-  for (int i = 0; i < n_items; ++i) {
-    PlanItem& it = P->items[i];
-    qcx_ctx* c = ctxs[it.ctx];
-    if (it.n_pairs64 > 0)
-      launch_pairs_f64(c->d_R.as<cplx>(), c->ldt, it.w.as<double>(), c->d_dt.as<double>(), it.eta,
-                       it.g64, it.pairs64.as<int>(), it.XY.as<double>(), st);
-  }
-  for (int i = 0; i < n_items; ++i) {
-    PlanItem& it = P->items[i];
-    qcx_ctx* c = ctxs[it.ctx];
-    launch_set_int(P->d_sing.as<int>() + i, INT_MAX, st);
-    AsmArgs a{};
-    a.C = (bulk && it.g.n_bulk > 0) ? it.C.as<float>() : nullptr;
-    a.XY = it.n_pairs64 > 0 ? it.XY.as<double>() : nullptr;
-    a.ks = it.g.ksplit;
-    a.ks64 = it.g64.ksplit;
-    a.n_rowsp64 = it.g64.n_rowsp;
-    a.n_colp64 = it.g64.n_colp;
-    a.n_pairs64 = it.n_pairs64;
-    a.vq = c->d_vq.as<double>();
-    a.pref = it.pref;
-    launch_eps_assemble(a, it.g, it.eps.as<cplx>(), st);
-    if (lfe)
-      launch_gj_diag(it.eps.as<cplx>(), c->n_g, it.g.n_w, it.diag.as<cplx>(),
-                     P->d_sing.as<int>() + i, st);
-    else
-      launch_nolfe_diag(it.eps.as<cplx>(), c->n_g, it.g.n_w, it.diag.as<cplx>(),
-                        P->d_sing.as<int>() + i, st);
-    launch_loss(it.diag.as<cplx>(), c->n_g, it.g.n_w,
-                it.loss_out ? it.loss_out : it.loss.as<double>(), it.epsM.as<cplx>(), st);
-  }
-  hipGraph_t graph = nullptr;
-  hipError_t ec = hipStreamEndCapture(st, &graph);
-  (void)hipStreamDestroy(cap);
-  if (ec != hipSuccess) return fail(ctx, QCX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
-  P->graph = graph;
-  HIPCK(hipGraphInstantiate(&P->exec, graph, nullptr, nullptr, 0));
+  return capture(ctx, P, 2, [&](hipStream_t cs) {
+    for (int i = 0; i < n_items; ++i) {
+      PlanItem& it = P->items[i];
+      qcx_ctx* c = ctxs[it.ctx];
+      if (it.n_pairs64 > 0)
+        launch_pairs_f64(c->d_R.as<cplx>(), c->ldt, it.w.as<double>(), c->d_dt.as<double>(),
+                         it.eta, it.g64, it.pairs64.as<int>(), it.XY.as<double>(), cs);
+    }
+    for (int i = 0; i < n_items; ++i) {
+      PlanItem& it = P->items[i];
+      qcx_ctx* c = ctxs[it.ctx];
+      launch_set_int(P->d_sing.as<int>() + i, INT_MAX, cs);
+      AsmArgs a{};
+      a.C = (bulk && it.g.n_bulk > 0) ? it.C.as<float>() : nullptr;
+      a.XY = it.n_pairs64 > 0 ? it.XY.as<double>() : nullptr;
+      a.ks = it.g.ksplit;
+      a.ks64 = it.g64.ksplit;
+      a.n_rowsp64 = it.g64.n_rowsp;
+      a.n_colp64 = it.g64.n_colp;
+      a.n_pairs64 = it.n_pairs64;
+      a.vq = c->d_vq.as<double>();
+      a.pref = it.pref;
+      launch_eps_assemble(a, it.g, it.eps.as<cplx>(), cs);
+      if (lfe)
+        launch_gj_diag(it.eps.as<cplx>(), c->n_g, it.g.n_w, it.diag.as<cplx>(),
+                       P->d_sing.as<int>() + i, cs);
+      else
+        launch_nolfe_diag(it.eps.as<cplx>(), c->n_g, it.g.n_w, it.diag.as<cplx>(),
+                          P->d_sing.as<int>() + i, cs);
+      launch_loss(it.diag.as<cplx>(), c->n_g, it.g.n_w,
+                  it.loss_out ? it.loss_out : it.loss.as<double>(), it.epsM.as<cplx>(), cs);
+    }
+  });
+}
+
+// Time one plan: one warm replay, then the mean of two timed replays (ms).
+int time_plan(qcx_ctx* ctx, const BatchPlan* P, double* ms) {
+  const bool was = ctx->timing;
+  ctx->timing = false;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCK(hipEventCreate(&a));
+  HIPCK(hipEventCreate(&b));
+  hipError_t e = launch_plan(ctx, P);
+  if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
+  for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_plan(ctx, P);
+  if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  ctx->timing = was;
+  HIPCK(e);
+  *ms = 0.5 * t;
   return QCX_OK;
 }
 
@@ -308,20 +377,49 @@ int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_
   std::vector<double> key = batch_key(ctxs, n_ctx, items, n_items, precision, lfe ? 1 : 0, hw64);
   if (!ctx->plan || ctx->plan->key != key) {
     if (ctx->plan) destroy_plan(ctx->plan);
-    ctx->plan = new BatchPlan();
-    ctx->plan->key = key;
-    const int rc = build_plan(ctx, ctxs, n_ctx, items, n_items, precision, lfe ? 1 : 0, hw64,
-                              ctx->plan);
-    if (rc != QCX_OK) {
-      destroy_plan(ctx->plan);
-      ctx->plan = nullptr;
-      return rc;
+    ctx->plan = nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCK(hipStreamIsCapturing(ctx->stream, &cs));
+    const bool tune = ctx->autotune && precision != QCX_FP64 && cs == hipStreamCaptureStatusNone;
+    std::vector<int> cands = tune ? std::vector<int>{128, 256, 512, 1024} : std::vector<int>{256};
+    const auto t0 = std::chrono::steady_clock::now();
+    BatchPlan* best = nullptr;
+    double best_ms = 0.0;
+    for (int target : cands) {
+      BatchPlan* P = new BatchPlan();
+      P->key = key;
+      int rc = build_plan(ctx, ctxs, n_ctx, items, n_items, precision, lfe ? 1 : 0, hw64, target, P);
+      double ms = 0.0;
+      if (rc == QCX_OK && cands.size() > 1) rc = time_plan(ctx, P, &ms);
+      if (rc != QCX_OK) {
+        destroy_plan(P);
+        if (best) destroy_plan(best);
+        return rc;
+      }
+      if (!best || ms < best_ms) {
+        if (best) destroy_plan(best);
+        best = P;
+        best_ms = ms;
+      } else {
+        destroy_plan(P);
+      }
     }
+    best->tune_ms = cands.size() > 1
+                        ? std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count()
+                        : 0.0;
+    ctx->plan = best;
   }
-  int sp;
-  HIPCK(span_begin(ctx, 3, &sp));
-  HIPCK(hipGraphLaunch(ctx->plan->exec, ctx->stream));
-  HIPCK(span_end(ctx, sp));
+  HIPCK(launch_plan(ctx, ctx->plan));
+  return QCX_OK;
+}
+
+int qcx_batch_config(qcx_ctx* ctx, int cfg[3], double* tune_ms) {
+  if (!ctx || !cfg) return QCX_EINVAL;
+  if (!ctx->plan) return fail(ctx, QCX_ESTATE, "no batch has run on this context");
+  cfg[0] = ctx->plan->target_steps;
+  cfg[1] = ctx->plan->n_tiles;
+  cfg[2] = ctx->plan->grid;
+  if (tune_ms) *tune_ms = ctx->plan->tune_ms;
   return QCX_OK;
 }
 

@@ -60,6 +60,7 @@ _SIGS = {
     "qcx_bulk_config": [_P, _P, _P],
     "qcx_run_batch": [_P, _I, _P, _I, _I, _I, _I],
     "qcx_batch_sync": [_P],
+    "qcx_batch_config": [_P, _P, _P],
     "qcx_mlp_create": [ctypes.POINTER(_P), _P, _I],
     "qcx_mlp_destroy": [_P],
     "qcx_mlp_set_params": [_P, _I, _P],
@@ -257,6 +258,14 @@ class Context:
         ms = ctypes.c_double(0.0)
         self._check(self.lib.qcx_bulk_config(self._h, _ptr_host(cfg), ctypes.byref(ms)))
         return dict(ksplit=int(cfg[0]), stages=int(cfg[1]), row_frags=int(cfg[2]),
+                    tune_ms=ms.value)
+
+    def batch_config(self) -> dict:
+        """Plan of the last batch whose first context is this one."""
+        cfg = np.zeros(3, np.int32)
+        ms = ctypes.c_double(0.0)
+        self._check(self.lib.qcx_batch_config(self._h, _ptr_host(cfg), ctypes.byref(ms)))
+        return dict(target_steps=int(cfg[0]), tiles=int(cfg[1]), blocks=int(cfg[2]),
                     tune_ms=ms.value)
 
     def stage_times(self) -> dict:

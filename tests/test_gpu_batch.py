@@ -108,6 +108,38 @@ def test_batch_replay_and_new_states(full_batch):
     ctxs[0].pair_density(items[0].G_int)
 
 
+def test_batch_plan_tuned_and_fixed(full_batch):
+    """The tuner keeps one of its candidate plans; with tuning off the fixed
+    target is used; both plans give the same loss to the split-BF16 bar (they
+    differ only in how the transition sum is split)."""
+    import torch
+
+    from paper_2603_12326_amd import Context, QcxError
+
+    items, ctxs = full_batch
+    bufs = [[torch.empty((len(wl.w_eV), len(wl.G_int)), dtype=torch.float64, device="cuda")
+             for wl in items] for _ in range(2)]
+    a, _ = _batch(ctxs, items, "split_bf16", outs=bufs[0])
+    cfg = ctxs[0].batch_config()
+    print("tuned plan", cfg)
+    assert cfg["target_steps"] in (128, 256, 512, 1024)
+    assert cfg["tiles"] > 0 and 0 < cfg["blocks"] <= 512
+    ctxs[0].set_autotune(0)
+    try:
+        # a new signature (other loss buffers) forces a new plan
+        b, _ = _batch(ctxs, items, "split_bf16", outs=bufs[1])
+        fixed = ctxs[0].batch_config()
+    finally:
+        ctxs[0].set_autotune(1)
+    assert fixed["target_steps"] == 256 and fixed["tune_ms"] == 0.0
+    for x, y in zip(a, b):
+        assert normwise(x, y) < 1e-4
+    c = Context(0)
+    with pytest.raises(QcxError):
+        c.batch_config()
+    c.close()
+
+
 def test_batch_against_oracle():
     """Items 0, 6, 12, 19 (N_G 59, 113, 181, 259; n_w 5..195) on a 2^3 k grid."""
     pick = [0, 6, 12, 19]
