@@ -17,6 +17,8 @@ namespace qcx {
 
 namespace {
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 // Upper-triangle pair index p -> (G, G'), G <= G', row-major.  Row g starts
 // at s(g) = g n - g (g - 1) / 2; the quadratic is inverted in double and the
 // rounding fixed by at most a step either way.
@@ -297,24 +299,29 @@ __global__ void __launch_bounds__(1024) k_gj_reg(const cplx* __restrict__ eps, i
 //  2. the swept panel is written back, and every other column j receives the
 //     deferred rank-16 update  T[:, j] += Z Y[:, j]  with Y = T[P][j] (the 16
 //     pivot rows before this update) and Z = swept panel with 1 subtracted
-//     at (p_a, a).  The update is a register-tiled complex GEMM: Z (in chunks
-//     of at most 512 rows) and a 16 x 32 tile of Y are staged in LDS, each
-//     thread accumulates up to 4 rows x 4 columns and updates them in place.
-// Y tiles are read before any row of that tile is updated, so pivot rows see
-// their old values; when Z needs several chunks, all chunks of one column
-// tile are done before the next tile.  LDS: Z (ZR x 16, aliased by the pivot
-// column buffers during step 1), one Y tile, piv and sor.
+//     at (p_a, a).
+// The update runs on FP64 MFMA (v_mfma_f64_16x16x4f64) as two real products
+// with K = 32:  Re T += [Re Z | Im Z] [Re Y ; -Im Y],
+//               Im T += [Re Z | Im Z] [Im Y ;  Re Y].
+// Z (chunks of at most ZR rows) and a 64-column tile of Y are staged in LDS
+// k-major (lane-consecutive rows / columns); each wave owns 32 x 16 output
+// blocks (2 MFMA tiles, re and im) and updates them in place.  A K step reads
+// 4 doubles per lane for 4 MFMAs.  Y tiles are read before any row of
+// that tile is updated, so pivot rows see their old values; with several Z
+// chunks, all chunks of one column tile are done before the next tile.
+// MFMA layouts: A 16x4, lane l holds A[l%16][l/16]; B 4x16, lane l holds
+// B[l/16][l%16]; D 16x16, lane l holds D[4r + l/16][l%16], r = 0..3.
 template <int RP>
 __global__ void __launch_bounds__(1024) k_gj_panel(cplx* __restrict__ eps, int n,
                                                    cplx* __restrict__ diag, int* sing) {
-  constexpr int NW = 16, MB = 16, JT = 32;
-  constexpr int ZR = 64 * RP < 512 ? 64 * RP : 512;
-  constexpr int QP = 1;  // row slots per thread per pass of the update
+  constexpr int NW = 16, MB = 16, JT = 64, KR = 2 * MB;
+  constexpr int ZR = 64 * RP < 384 ? 64 * RP : 384;
   extern __shared__ __align__(16) char smem[];
-  cplx* Zs = reinterpret_cast<cplx*>(smem);  // [ZR][MB]
-  cplx* ucol = Zs;                           // [2][64 RP] during the pivot steps
-  cplx* Ys = Zs + (size_t)ZR * MB;           // [2][MB][JT]
-  int* piv = reinterpret_cast<int*>(Ys + 2 * MB * JT);  // [n] pivot row of step k
+  double* Zt = reinterpret_cast<double*>(smem);    // [KR][ZR]: k' < 16 Re Z, else Im Z
+  cplx* ucol = reinterpret_cast<cplx*>(smem);      // [2][64 RP] during the pivot steps
+  double* Yr = Zt + (size_t)KR * ZR;               // [KR][JT]: Re Y ; -Im Y
+  double* Yi = Yr + KR * JT;                       // [KR][JT]: Im Y ;  Re Y
+  int* piv = reinterpret_cast<int*>(Yi + KR * JT);  // [n] pivot row of step k
   int* sor = piv + n;                               // [n] step of pivot row i
   __shared__ int prow[2];
   const int tid = threadIdx.x, l = tid & 63;
@@ -410,80 +417,67 @@ __global__ void __launch_bounds__(1024) k_gj_panel(cplx* __restrict__ eps, int n
         const int r = e >> 4, a = e & 15, i = r0 + r;
         cplx z = (i < n && a < mb) ? A[(size_t)i * n + k0 + a] : cplx{0.0, 0.0};
         if (a < mb && i == piv[k0 + a]) z.re -= 1.0;
-        Zs[e] = z;
+        Zt[a * ZR + r] = z.re;
+        Zt[(MB + a) * ZR + r] = z.im;
       }
     };
-    const int cg = tid & 7, rg = tid >> 3;  // 4 columns, rows rg + 128 q
-    // One pass: rows r0 + rp + rg + 128 q (q < QP) x columns jt + 4 cg + c of
-    // Z (rows of the current chunk in LDS) times Y (tile ys).  The targets
-    // are loaded before the FMAs so that their latency is hidden.
-    auto pass = [&](int r0, int rp, int jt, const cplx* ys) {
-      cplx acc[QP][4], t[QP][4];
-#pragma unroll
-      for (int q = 0; q < QP; ++q) {
-        const int i = r0 + rp + rg + 128 * q;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int j = jt + 4 * cg + c;
-          acc[q][c] = {0.0, 0.0};
-          t[q][c] = (rp + rg + 128 * q < ZR && i < n && j < n) ? A[(size_t)i * n + j]
-                                                             : cplx{0.0, 0.0};
-        }
-      }
-      for (int a = 0; a < mb; ++a) {
-        cplx y[4], z[QP];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) y[c] = ys[a * JT + 4 * cg + c];
-#pragma unroll
-        for (int q = 0; q < QP; ++q) {
-          const int r = rp + rg + 128 * q;
-          z[q] = r < ZR ? Zs[r * MB + a] : cplx{0.0, 0.0};
-        }
-#pragma unroll
-        for (int q = 0; q < QP; ++q)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            acc[q][c].re = fma(z[q].re, y[c].re, acc[q][c].re);
-            acc[q][c].re = fma(-z[q].im, y[c].im, acc[q][c].re);
-            acc[q][c].im = fma(z[q].re, y[c].im, acc[q][c].im);
-            acc[q][c].im = fma(z[q].im, y[c].re, acc[q][c].im);
-          }
-      }
-#pragma unroll
-      for (int q = 0; q < QP; ++q) {
-        const int r = rp + rg + 128 * q, i = r0 + r;
-        if (r >= ZR || i >= n) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int j = jt + 4 * cg + c;
-          if (j < n && (j < k0 || j >= k0 + mb))
-            A[(size_t)i * n + j] = {t[q][c].re + acc[q][c].re, t[q][c].im + acc[q][c].im};
-        }
+    auto load_y = [&](int jt) {
+      for (int e = tid; e < MB * JT; e += 1024) {
+        const int a = e / JT, c = e % JT, j = jt + c;
+        const cplx y = (a < mb && j < n) ? A[(size_t)piv[k0 + a] * n + j] : cplx{0.0, 0.0};
+        Yr[a * JT + c] = y.re;
+        Yr[(MB + a) * JT + c] = -y.im;
+        Yi[a * JT + c] = y.im;
+        Yi[(MB + a) * JT + c] = y.re;
       }
     };
-    // Y tiles are double-buffered: the next tile's pivot-row values are read
-    // into a register during this tile's FMAs (other columns, so not yet
-    // updated) and stored after it.
-    auto y_elem = [&](int jt, int e) -> cplx {
-      const int a = e / JT, j = jt + e % JT;
-      return (e < MB * JT && a < mb && j < n) ? A[(size_t)piv[k0 + a] * n + j] : cplx{0.0, 0.0};
+    const int li = l & 15, lk = l >> 4;
+    // one 32 x 16 output block: rows r0 + 32 rb .., columns jt + 16 cb ..
+    auto block = [&](int r0, int rb, int jt, int cb) {
+      f64x4 acc[2][2];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        acc[rt][0] = f64x4{0.0, 0.0, 0.0, 0.0};
+        acc[rt][1] = f64x4{0.0, 0.0, 0.0, 0.0};
+      }
+#pragma unroll 2
+      for (int s = 0; s < KR / 4; ++s) {
+        const int kr = 4 * s + lk;
+        const double br = Yr[kr * JT + 16 * cb + li], bi = Yi[kr * JT + 16 * cb + li];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+          const double za = Zt[kr * ZR + 32 * rb + 16 * rt + li];
+          acc[rt][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(za, br, acc[rt][0], 0, 0, 0);
+          acc[rt][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(za, bi, acc[rt][1], 0, 0, 0);
+        }
+      }
+      const int j = jt + 16 * cb + li;
+      if (j >= n || (j >= k0 && j < k0 + mb)) return;
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rr = 32 * rb + 16 * rt + 4 * r + lk, i = r0 + rr;
+          if (rr >= ZR || i >= n) continue;
+          cplx t = A[(size_t)i * n + j];
+          t.re += acc[rt][0][r];
+          t.im += acc[rt][1][r];
+          A[(size_t)i * n + j] = t;
+        }
     };
+    constexpr int NRB = (ZR + 31) / 32, NU = NRB * (JT / 16);
     if (nch == 1) load_z(0);
-    if (tid < MB * JT) Ys[tid] = y_elem(0, tid);
-    int cur = 0;
     for (int jt = 0; jt < n; jt += JT) {
-      const cplx yn = (jt + JT < n) ? y_elem(jt + JT, tid) : cplx{0.0, 0.0};
-      const cplx* ys = Ys + cur * MB * JT;
+      load_y(jt);
       for (int c = 0; c < nch; ++c) {
-        __syncthreads();  // Y staged (and Z, or the previous chunk's reads done)
+        __syncthreads();  // Y staged; Z staged or the previous chunk's reads done
         if (nch > 1) {
           load_z(c * ZR);
           __syncthreads();
         }
-        for (int rp = 0; rp < ZR; rp += 128 * QP) pass(c * ZR, rp, jt, ys);
+        for (int u = v; u < NU; u += NW) block(c * ZR, u % NRB, jt, u / NRB);
       }
-      if (tid < MB * JT) Ys[(cur ^ 1) * MB * JT + tid] = yn;
-      cur ^= 1;
+      __syncthreads();  // this tile's updates and Y reads done before the next Y
     }
   }
   __syncthreads();
@@ -492,8 +486,8 @@ __global__ void __launch_bounds__(1024) k_gj_panel(cplx* __restrict__ eps, int n
 }
 
 size_t gj_panel_lds(int n, int rp) {
-  const int zr = 64 * rp < 512 ? 64 * rp : 512;
-  return sizeof(cplx) * ((size_t)zr * 16 + 2 * 16 * 32) + sizeof(int) * 2 * (size_t)n;
+  const int zr = 64 * rp < 384 ? 64 * rp : 384;
+  return sizeof(double) * ((size_t)32 * zr + 2 * 32 * 64) + sizeof(int) * 2 * (size_t)n;
 }
 
 // Blocked Gauss-Jordan for n > 128 (one block of 256 threads per matrix; the
