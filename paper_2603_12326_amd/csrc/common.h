@@ -170,6 +170,18 @@ struct AsmArgs {
 };
 void launch_eps_assemble(const AsmArgs& a, const Chi0Geom& g, cplx* eps, hipStream_t st);
 void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st);
+// One item of a multi-item inversion launch: its n_w matrices are blocks
+// [block0, block0 + n_w) of the launch.
+struct GjJob {
+  cplx* eps;   // [n_w][n][n], overwritten
+  cplx* diag;  // [n_w][n] diagonal of the inverse
+  int* sing;   // lowest frequency index with a zero pivot (atomic minimum)
+  int n, n_w, block0;
+};
+// Kernel class of an inversion of size n_g (items of one class share a
+// launch); class 8 has no multi-item form.
+int gj_class(int n_g);
+void launch_gj_jobs(int cls, const GjJob* jobs, int n_jobs, int n_blocks, int max_n, hipStream_t st);
 void launch_nolfe_diag(const cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st);
 void launch_loss(const cplx* diag, int n_g, int n_w, double* loss, cplx* epsM, hipStream_t st);
 void launch_chi0_export(const AsmArgs& a, const Chi0Geom& g, cplx* chi, hipStream_t st);

@@ -160,15 +160,16 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long x) {
 // column first and then chooses and publishes the next pivot while the other
 // waves are still in their FMAs.  u and p are double-buffered by the parity
 // of k; u is zero past row n; used-row marks live in registers.
+// Body of one 1024-thread block: matrix A (n x n), diagonal of the inverse
+// into drow[n]; a zero pivot sets *sing to at most widx.
 template <int RP, int CP>
-__global__ void __launch_bounds__(1024) k_gj_reg(const cplx* __restrict__ eps, int n,
-                                                 cplx* __restrict__ diag, int* sing) {
+__device__ __forceinline__ void gj_reg_body(const cplx* __restrict__ A, int n,
+                                            cplx* __restrict__ drow, int* sing, int widx) {
   constexpr int NW = 16;
   __shared__ cplx ucol[2][64 * RP];
   __shared__ int prow[2], sor[64 * RP];
   const int tid = threadIdx.x, l = tid & 63;
   const int v = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const cplx* A = eps + (size_t)blockIdx.x * n * n;
   cplx m[RP][CP];
 #pragma unroll
   for (int a = 0; a < RP; ++a)
@@ -284,9 +285,9 @@ __global__ void __launch_bounds__(1024) k_gj_reg(const cplx* __restrict__ eps, i
     if (jt % NW != v) continue;
 #pragma unroll
     for (int b = 0; b < CP; ++b)
-      if (b == jt / NW) diag[(size_t)blockIdx.x * n + k] = opaque(m[a][b]);
+      if (b == jt / NW) drow[k] = opaque(m[a][b]);
   }
-  if (singular) atomicMin(sing, (int)blockIdx.x);
+  if (singular) atomicMin(sing, widx);
 }
 
 // Blocked Gauss-Jordan for 128 < n <= 64 RP (RP <= 16) with 1024 threads per
@@ -312,8 +313,8 @@ __global__ void __launch_bounds__(1024) k_gj_reg(const cplx* __restrict__ eps, i
 // MFMA layouts: A 16x4, lane l holds A[l%16][l/16]; B 4x16, lane l holds
 // B[l/16][l%16]; D 16x16, lane l holds D[4r + l/16][l%16], r = 0..3.
 template <int RP>
-__global__ void __launch_bounds__(1024) k_gj_panel(cplx* __restrict__ eps, int n,
-                                                   cplx* __restrict__ diag, int* sing) {
+__device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
+                                              cplx* __restrict__ drow, int* sing, int widx) {
   constexpr int NW = 16, MB = 16, JT = 64, KR = 2 * MB;
   constexpr int ZR = 64 * RP < 384 ? 64 * RP : 384;
   extern __shared__ __align__(16) char smem[];
@@ -326,7 +327,6 @@ __global__ void __launch_bounds__(1024) k_gj_panel(cplx* __restrict__ eps, int n
   __shared__ int prow[2];
   const int tid = threadIdx.x, l = tid & 63;
   const int v = __builtin_amdgcn_readfirstlane(tid >> 6);
-  cplx* A = eps + (size_t)blockIdx.x * n * n;
   unsigned used = 0;  // bit a: row l + 64 a already served as pivot
   bool singular = false;
   cplx wk = {0.0, 0.0};
@@ -481,8 +481,45 @@ __global__ void __launch_bounds__(1024) k_gj_panel(cplx* __restrict__ eps, int n
     }
   }
   __syncthreads();
-  for (int k = tid; k < n; k += 1024) diag[(size_t)blockIdx.x * n + k] = A[(size_t)piv[k] * n + sor[k]];
-  if (singular) atomicMin(sing, (int)blockIdx.x);
+  for (int k = tid; k < n; k += 1024) drow[k] = A[(size_t)piv[k] * n + sor[k]];
+  if (singular) atomicMin(sing, widx);
+}
+
+template <int RP, int CP>
+__global__ void __launch_bounds__(1024) k_gj_reg(const cplx* __restrict__ eps, int n,
+                                                 cplx* __restrict__ diag, int* sing) {
+  gj_reg_body<RP, CP>(eps + (size_t)blockIdx.x * n * n, n, diag + (size_t)blockIdx.x * n, sing,
+                      blockIdx.x);
+}
+
+template <int RP>
+__global__ void __launch_bounds__(1024) k_gj_panel(cplx* __restrict__ eps, int n,
+                                                   cplx* __restrict__ diag, int* sing) {
+  gj_panel_body<RP>(eps + (size_t)blockIdx.x * n * n, n, diag + (size_t)blockIdx.x * n, sing,
+                    blockIdx.x);
+}
+
+// The job of this block in a multi-item launch: blocks [block0, block0 +
+// n_w) of a launch belong to job j (jobs sorted by block0).
+__device__ inline GjJob find_job(const GjJob* __restrict__ jobs, int n_jobs, int& w) {
+  int j = 0;
+  while (j + 1 < n_jobs && (int)blockIdx.x >= jobs[j + 1].block0) ++j;
+  w = (int)blockIdx.x - jobs[j].block0;
+  return jobs[j];
+}
+
+template <int RP, int CP>
+__global__ void __launch_bounds__(1024) k_gj_reg_jobs(const GjJob* __restrict__ jobs, int n_jobs) {
+  int w;
+  const GjJob J = find_job(jobs, n_jobs, w);
+  gj_reg_body<RP, CP>(J.eps + (size_t)w * J.n * J.n, J.n, J.diag + (size_t)w * J.n, J.sing, w);
+}
+
+template <int RP>
+__global__ void __launch_bounds__(1024) k_gj_panel_jobs(const GjJob* __restrict__ jobs, int n_jobs) {
+  int w;
+  const GjJob J = find_job(jobs, n_jobs, w);
+  gj_panel_body<RP>(J.eps + (size_t)w * J.n * J.n, J.n, J.diag + (size_t)w * J.n, J.sing, w);
 }
 
 size_t gj_panel_lds(int n, int rp) {
@@ -695,23 +732,32 @@ void launch_chi0_export(const AsmArgs& a, const Chi0Geom& g, cplx* chi, hipStrea
                      chi);
 }
 
+int gj_class(int n_g) {
+  if (n_g <= 64) return 0;
+  if (n_g <= 128) return 1;
+  if (n_g <= 192) return 2;
+  if (n_g <= 256) return 3;
+  if (n_g <= 320) return 4;
+  if (n_g <= 512) return 5;
+  if (n_g <= 768) return 6;
+  if (n_g <= 1024) return 7;
+  return 8;  // LDS-blocked kernel, single item only
+}
+
 void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st) {
-  if (n_g <= 64)
-    hipLaunchKernelGGL((k_gj_reg<1, 4>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
-  else if (n_g <= 128)
-    hipLaunchKernelGGL((k_gj_reg<2, 8>), dim3(n_w), dim3(1024), 0, st, eps, n_g, diag, sing);
-  else if (n_g <= 1024) {
-#define QCX_GJP(R)                                                                             \
-  hipLaunchKernelGGL(k_gj_panel<R>, dim3(n_w), dim3(1024), gj_panel_lds(n_g, R), st, eps, n_g, diag, \
-                     sing)
-    if (n_g <= 192) QCX_GJP(3);
-    else if (n_g <= 256) QCX_GJP(4);
-    else if (n_g <= 320) QCX_GJP(5);
-    else if (n_g <= 512) QCX_GJP(8);
-    else if (n_g <= 768) QCX_GJP(12);
-    else QCX_GJP(16);
-#undef QCX_GJP
-  } else if (gj_blocked_lds(n_g, 32) <= 160 * 1024)
+  const dim3 g(n_w), b(1024);
+  switch (gj_class(n_g)) {
+    case 0: hipLaunchKernelGGL((k_gj_reg<1, 4>), g, b, 0, st, eps, n_g, diag, sing); return;
+    case 1: hipLaunchKernelGGL((k_gj_reg<2, 8>), g, b, 0, st, eps, n_g, diag, sing); return;
+    case 2: hipLaunchKernelGGL(k_gj_panel<3>, g, b, gj_panel_lds(n_g, 3), st, eps, n_g, diag, sing); return;
+    case 3: hipLaunchKernelGGL(k_gj_panel<4>, g, b, gj_panel_lds(n_g, 4), st, eps, n_g, diag, sing); return;
+    case 4: hipLaunchKernelGGL(k_gj_panel<5>, g, b, gj_panel_lds(n_g, 5), st, eps, n_g, diag, sing); return;
+    case 5: hipLaunchKernelGGL(k_gj_panel<8>, g, b, gj_panel_lds(n_g, 8), st, eps, n_g, diag, sing); return;
+    case 6: hipLaunchKernelGGL(k_gj_panel<12>, g, b, gj_panel_lds(n_g, 12), st, eps, n_g, diag, sing); return;
+    case 7: hipLaunchKernelGGL(k_gj_panel<16>, g, b, gj_panel_lds(n_g, 16), st, eps, n_g, diag, sing); return;
+    default: break;
+  }
+  if (gj_blocked_lds(n_g, 32) <= 160 * 1024)
     hipLaunchKernelGGL(k_gj_blocked<32>, dim3(n_w), dim3(256), gj_blocked_lds(n_g, 32), st, eps,
                        n_g, diag, sing);
   else if (gj_blocked_lds(n_g, 16) <= 160 * 1024)
@@ -720,6 +766,21 @@ void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStrea
   else
     hipLaunchKernelGGL(k_gj_blocked<8>, dim3(n_w), dim3(256), gj_blocked_lds(n_g, 8), st, eps,
                        n_g, diag, sing);
+}
+
+void launch_gj_jobs(int cls, const GjJob* jobs, int n_jobs, int n_blocks, int max_n, hipStream_t st) {
+  const dim3 g(n_blocks), b(1024);
+  switch (cls) {
+    case 0: hipLaunchKernelGGL((k_gj_reg_jobs<1, 4>), g, b, 0, st, jobs, n_jobs); return;
+    case 1: hipLaunchKernelGGL((k_gj_reg_jobs<2, 8>), g, b, 0, st, jobs, n_jobs); return;
+    case 2: hipLaunchKernelGGL(k_gj_panel_jobs<3>, g, b, gj_panel_lds(max_n, 3), st, jobs, n_jobs); return;
+    case 3: hipLaunchKernelGGL(k_gj_panel_jobs<4>, g, b, gj_panel_lds(max_n, 4), st, jobs, n_jobs); return;
+    case 4: hipLaunchKernelGGL(k_gj_panel_jobs<5>, g, b, gj_panel_lds(max_n, 5), st, jobs, n_jobs); return;
+    case 5: hipLaunchKernelGGL(k_gj_panel_jobs<8>, g, b, gj_panel_lds(max_n, 8), st, jobs, n_jobs); return;
+    case 6: hipLaunchKernelGGL(k_gj_panel_jobs<12>, g, b, gj_panel_lds(max_n, 12), st, jobs, n_jobs); return;
+    case 7: hipLaunchKernelGGL(k_gj_panel_jobs<16>, g, b, gj_panel_lds(max_n, 16), st, jobs, n_jobs); return;
+    default: return;
+  }
 }
 
 void launch_nolfe_diag(const cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st) {

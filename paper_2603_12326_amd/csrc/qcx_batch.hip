@@ -5,7 +5,8 @@
 // weights, R32 packs per context, pair tables, one tile list for the
 // persistent bulk kernel (ordered by decreasing cost, so that small items fill
 // the gaps left by large ones), per-item FP64 head/wings, and per-item
-// assembly, inversion and loss.  The sequence is captured into three hipGraphs
+// assembly, inversion (one launch per inversion kernel class, covering every
+// item of that class) and loss.  The sequence is captured into three hipGraphs
 // (operand preparation, the persistent bulk launch, everything after it) so
 // that the bulk kernel can be timed on its own; later calls with the same
 // signature replay them.  Capture records kernels only (counters and flags are
@@ -38,6 +39,12 @@ struct BatchPlan {
   std::vector<PlanItem> items;
   std::vector<DevBuf> r32;  // per context
   DevBuf d_items, d_tiles, d_counter, d_sing;
+  // multi-item inversion launches, one per kernel class present
+  struct GjGroup {
+    int cls = 0, n_jobs = 0, n_blocks = 0, max_n = 0;
+    DevBuf jobs;
+  };
+  std::vector<GjGroup> gj;
   int n_tiles = 0, max_ng = 0, target_steps = 0, grid = 0;
   double tune_ms = 0.0;
   bool gather = false;
@@ -54,6 +61,7 @@ struct BatchPlan {
       for (DevBuf* x : b) x->release();
     }
     for (DevBuf& b : r32) b.release();
+    for (GjGroup& g : gj) g.jobs.release();
     d_items.release();
     d_tiles.release();
     d_counter.release();
@@ -254,6 +262,35 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
   if (!tiles.empty()) HIPCK(upload(ctx, P->d_tiles, tiles.data(), tiles.size()));
   HIPCK(P->d_counter.reserve(sizeof(int)));
   HIPCK(P->d_sing.reserve(sizeof(int) * (size_t)n_items));
+  // inversions: items of one kernel class share a launch, so that small items
+  // do not leave the chip idle one after another
+  std::vector<int> single_gj;  // items whose size has no multi-item kernel
+  if (lfe) {
+    std::vector<std::vector<GjJob>> by(8);
+    std::vector<int> blocks(8, 0), maxn(8, 0);
+    for (int i = 0; i < n_items; ++i) {
+      PlanItem& it = P->items[i];
+      const int n = ctxs[it.ctx]->n_g, cls = gj_class(n);
+      if (cls >= 8) {
+        single_gj.push_back(i);
+        continue;
+      }
+      by[cls].push_back(GjJob{it.eps.as<cplx>(), it.diag.as<cplx>(), P->d_sing.as<int>() + i, n,
+                              it.g.n_w, blocks[cls]});
+      blocks[cls] += it.g.n_w;
+      maxn[cls] = std::max(maxn[cls], n);
+    }
+    for (int c = 0; c < 8; ++c) {
+      if (by[c].empty()) continue;
+      BatchPlan::GjGroup g;
+      g.cls = c;
+      g.n_jobs = (int)by[c].size();
+      g.n_blocks = blocks[c];
+      g.max_n = maxn[c];
+      HIPCK(upload(ctx, g.jobs, by[c].data(), by[c].size()));
+      P->gj.push_back(std::move(g));
+    }
+  }
   HIPCK(hipStreamSynchronize(st));  // uploads complete before capture begins
 
   P->grid = std::min(P->n_tiles, 2 * 256);
@@ -312,10 +349,20 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
       a.vq = c->d_vq.as<double>();
       a.pref = it.pref;
       launch_eps_assemble(a, it.g, it.eps.as<cplx>(), cs);
-      if (lfe)
-        launch_gj_diag(it.eps.as<cplx>(), c->n_g, it.g.n_w, it.diag.as<cplx>(),
+    }
+    if (lfe) {
+      for (const BatchPlan::GjGroup& g : P->gj)
+        launch_gj_jobs(g.cls, g.jobs.as<GjJob>(), g.n_jobs, g.n_blocks, g.max_n, cs);
+      for (int i : single_gj) {
+        PlanItem& it = P->items[i];
+        launch_gj_diag(it.eps.as<cplx>(), ctxs[it.ctx]->n_g, it.g.n_w, it.diag.as<cplx>(),
                        P->d_sing.as<int>() + i, cs);
-      else
+      }
+    }
+    for (int i = 0; i < n_items; ++i) {
+      PlanItem& it = P->items[i];
+      qcx_ctx* c = ctxs[it.ctx];
+      if (!lfe)
         launch_nolfe_diag(it.eps.as<cplx>(), c->n_g, it.g.n_w, it.diag.as<cplx>(),
                           P->d_sing.as<int>() + i, cs);
       launch_loss(it.diag.as<cplx>(), c->n_g, it.g.n_w,
