@@ -182,6 +182,25 @@ int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out);
  * Errors: QCX_ESTATE (no eps_inv), QCX_EINVAL, QCX_ESINGULAR. */
 int qcx_loss(qcx_ctx* ctx, double* out, int mem);
 
+/* Loss without local field effects, Eq. (eps_noLFE), for a G list of any
+ * length (Sec. III: the high-momentum part of the composite dielectric
+ * function, where only the diagonal of Eq. (RPA) is needed):
+ *   chi0_GG(w) = 1/(N_k V) sum_{k,v,c} [ 2 |rho(G)|^2 / (w - D + i eta)
+ *                                        - 2 |sigma(G)|^2 / (w + D' - i eta) ],
+ *   eps_GG = 1 - 4 pi chi0_GG / |q + G|^2,  loss_G(w) = Im(-1 / eps_GG).
+ * Works on the states of qcx_set_states; the G list is processed in chunks of
+ * 4096 (pair densities, then the diagonal contraction on MFMA in FP32 or
+ * split-BF16, or on FP64 MFMA for QCX_FP64).
+ *   n_G        >= 1; G_int [n_G][3] host, reciprocal-basis coefficients; no
+ *              q + G may vanish; G = 0 is not required
+ *   n_w, w_eV, eta_eV, precision as for qcx_chi0
+ *   loss_out   device [n_w][n_G] float64
+ * Asynchronous.  Replaces the context's pair densities (qcx_pair_density
+ * must be called again before qcx_chi0).
+ * Errors: QCX_ESTATE (no states), QCX_EINVAL, QCX_ENOMEM. */
+int qcx_loss_diag(qcx_ctx* ctx, int n_G, const int* G_int, int n_w, const double* w_eV,
+                  double eta_eV, int precision, double* loss_out);
+
 /* One item of a batch: the frequencies of one context's q point. */
 typedef struct qcx_item {
   int ctx;              /* index into the context array; its pair densities are used */

@@ -10,7 +10,9 @@ Written from Sec. II.D of the paper:
   T = 0 occupations f = 2 (occupied) or 0 (empty).
 * Eq. (eps_LFE): eps(w, q+G) = 1 / [eps^{-1}]_GG; the macroscopic eps_M is
   the G = 0 entry.
-* Eq. (eps_noLFE): off-diagonal entries dropped, eps^noLFE = eps_GG.
+* Eq. (eps_noLFE): off-diagonal entries dropped, eps^noLFE = eps_GG; for the
+  many high-momentum G of the composite dielectric function of Sec. III only
+  the diagonal of chi0 is formed (loss_diag, loss_composite).
 * The loss is Im(-1/eps) (Eq. dynamic_structure_factor uses it).
 
 Readings of points the paper leaves open (each also listed in the design doc):
@@ -157,6 +159,54 @@ def loss_nolfe(eps: np.ndarray) -> np.ndarray:
     """loss[w][G] = Im(-1/eps_GG) (Eq. eps_noLFE)."""
     d = np.diagonal(eps, axis1=1, axis2=2)
     return np.imag(-1.0 / d)
+
+
+def chi0_diagonal(R: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """chi0[w][G] = sum_t W[w][t] |R[t][G]|^2, the diagonal of Eq. (RPA) alone
+    (what Eq. eps_noLFE needs).  Parity: equals the diagonal of chi0()."""
+    Rt = R.reshape(-1, R.shape[-1])
+    return W @ (np.abs(Rt) ** 2)
+
+
+def loss_diag(cell, basis, lattice_range, k_frac, n_occ, G_int, states, w_eV, eta_eV):
+    """noLFE loss for any G list (Eq. eps_noLFE; no G = 0 needed):
+    Im(-1 / eps_GG) with eps_GG = 1 - 4 pi chi0_GG / |q + G|^2.
+    Parity: equals loss_nolfe() of the full path on the same G."""
+    R = pair_densities_from_workload(cell, basis, lattice_range, k_frac, states.q_cart, G_int,
+                                     states.C_k, states.C_kq, n_occ)
+    volume = abs(float(np.linalg.det(np.asarray(cell.lat, np.float64))))
+    W = transition_weights(states.E_k, states.E_kq, n_occ, w_eV, eta_eV, volume)
+    chi = chi0_diagonal(R, W)
+    v = coulomb_sqrt(q_plus_g(cell.lat, states.q_cart, G_int))
+    return np.imag(-1.0 / (1.0 - (v * v)[None, :] * chi))
+
+
+def composite_split(lat, q_cart, G_int, q_lfe: float):
+    """Indices of the G with |q + G| <= q_lfe (the LFE block, in the given
+    order; it must start with G = 0) and of the rest (Sec. III, the composite
+    dielectric function)."""
+    qn = np.linalg.norm(q_plus_g(lat, q_cart, G_int), axis=1)
+    inner = np.nonzero(qn <= q_lfe)[0]
+    outer = np.nonzero(qn > q_lfe)[0]
+    if len(inner) == 0 or inner[0] != 0 or np.any(np.asarray(G_int)[0] != 0):
+        raise ValueError("the LFE block must start with G = 0")
+    return inner, outer
+
+
+def loss_composite(cell, basis, lattice_range, k_frac, n_occ, G_int, states, w_eV, eta_eV,
+                   q_lfe: float):
+    """Composite loss (Sec. III): Eq. (eps_LFE) from the inverse of eps over
+    the G with |q + G| <= q_lfe, Eq. (eps_noLFE) for the G beyond; result in
+    the order of G_int."""
+    G = np.asarray(G_int)
+    inner, outer = composite_split(cell.lat, states.q_cart, G, q_lfe)
+    out = np.empty((len(w_eV), len(G)))
+    out[:, inner] = solve(cell, basis, lattice_range, k_frac, n_occ, G[inner], states, w_eV,
+                          eta_eV, lfe=True)
+    if len(outer):
+        out[:, outer] = loss_diag(cell, basis, lattice_range, k_frac, n_occ, G[outer], states,
+                                  w_eV, eta_eV)
+    return out
 
 
 def eps_macro(eps: np.ndarray) -> np.ndarray:

@@ -711,6 +711,36 @@ __global__ void k_loss(const cplx* diag, int n, int n_w, double* loss, cplx* eps
   if (i % n == 0) epsM[i / n] = cinv(d);
 }
 
+// noLFE loss of Eq. (eps_noLFE) for a list of G from diagonal-only partial
+// sums: chi0_GG = pref (Xr + i Yr) with Xr, Yr the Re W and Im W rows of the
+// G-th diagonal pair (P_t(G, G) = |R_t(G)|^2 is real), eps_GG = 1 - v_G^2
+// chi0_GG, loss = Im(-1 / eps_GG) = Im eps_GG / |eps_GG|^2.  Partials come
+// from the bulk (a.C, [ks][n_rowsp][2][n_bulkp]) or the FP64 pairs kernel
+// (a.XY, [ks64][n_rowsp64][n_colp64]); column b of chunk G-index b.
+__global__ void k_diag_loss(AsmArgs a, Chi0Geom g, int n_g, int n_w, double* __restrict__ loss,
+                            int ldl, int g0) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_w * n_g) return;
+  const int j = (int)(i / n_g), b = (int)(i % n_g);
+  double Xr = 0.0, Yr = 0.0;
+  if (a.XY) {
+    for (int ks = 0; ks < a.ks64; ++ks) {
+      const double* x0 = a.XY + ((size_t)ks * a.n_rowsp64 + 2 * j) * a.n_colp64 + 2 * b;
+      Xr += x0[0];
+      Yr += x0[a.n_colp64];
+    }
+  } else {
+    for (int ks = 0; ks < a.ks; ++ks) {
+      const size_t r0 = ((size_t)ks * g.n_rowsp + 2 * j) * 2;
+      Xr += (double)a.C[r0 * g.n_bulkp + b];
+      Yr += (double)a.C[(r0 + 2) * g.n_bulkp + b];
+    }
+  }
+  const double vv = a.vq[b] * a.vq[b];
+  const double er = 1.0 - vv * a.pref * Xr, ei = -vv * a.pref * Yr;
+  loss[(size_t)j * ldl + g0 + b] = ei / (er * er + ei * ei);
+}
+
 __global__ void k_rho_export(const cplx* R, size_t ldt, int n_g, int n_t, cplx* out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long)n_g * n_t) return;
@@ -793,6 +823,13 @@ void launch_loss(const cplx* diag, int n_g, int n_w, double* loss, cplx* epsM, h
   const long total = (long)n_g * n_w;
   hipLaunchKernelGGL(k_loss, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, diag, n_g,
                      n_w, loss, epsM);
+}
+
+void launch_diag_loss(const AsmArgs& a, const Chi0Geom& g, int n_g, int n_w, double* loss, int ldl,
+                      int g0, hipStream_t st) {
+  const long total = (long)n_g * n_w;
+  hipLaunchKernelGGL(k_diag_loss, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, g,
+                     n_g, n_w, loss, ldl, g0);
 }
 
 void launch_rho_export(const cplx* R, size_t ldt, int n_g, int n_t, cplx* out, hipStream_t st) {

@@ -400,11 +400,13 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
   return QCX_OK;
 }
 
-int qcx_pair_density(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out) {
+// Pair densities of the G list into ctx->d_R (shared by qcx_pair_density and
+// the chunks of qcx_loss_diag, which has no G = 0 requirement).
+static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out, bool need_g0) {
   if (!ctx) return QCX_EINVAL;
   if (!ctx->have_states) return fail(ctx, QCX_ESTATE, "set_states first");
   if (n_G < 1 || n_G > 4096 || !G_int) return fail(ctx, QCX_EINVAL, "need 1 <= n_G <= 4096");
-  if (G_int[0] != 0 || G_int[1] != 0 || G_int[2] != 0)
+  if (need_g0 && (G_int[0] != 0 || G_int[1] != 0 || G_int[2] != 0))
     return fail(ctx, QCX_EINVAL, "G_int[0] must be (0,0,0)");
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
@@ -457,7 +459,126 @@ int qcx_pair_density(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out) {
   return QCX_OK;
 }
 
+int qcx_pair_density(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out) {
+  return pair_density_impl(ctx, n_G, G_int, rho_out, true);
+}
 
+int qcx_loss_diag(qcx_ctx* ctx, int n_G, const int* G_int, int n_w, const double* w_eV,
+                  double eta_eV, int precision, double* loss_out) {
+  if (!ctx) return QCX_EINVAL;
+  if (!ctx->have_states) return fail(ctx, QCX_ESTATE, "set_states first");
+  if (n_G < 1 || !G_int) return fail(ctx, QCX_EINVAL, "need n_G >= 1");
+  if (n_w < 1 || n_w > 65536 || !w_eV) return fail(ctx, QCX_EINVAL, "need 1 <= n_w <= 65536");
+  if (!(eta_eV >= 0.0) || !std::isfinite(eta_eV)) return fail(ctx, QCX_EINVAL, "eta must be >= 0");
+  if (precision < QCX_FP64 || precision > QCX_SPLIT_BF16) return fail(ctx, QCX_EINVAL, "bad precision");
+  if (!loss_out) return fail(ctx, QCX_EINVAL, "loss_out must be a device buffer");
+  HIPCK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  std::vector<double> w(n_w);
+  for (int i = 0; i < n_w; ++i) {
+    if (!std::isfinite(w_eV[i])) return fail(ctx, QCX_EINVAL, "non-finite frequency");
+    w[i] = w_eV[i] / kHartreeEV;
+  }
+  HIPCK(stage_begin(ctx));
+  HIPCK(upload(ctx, ctx->d_w, w.data(), w.size()));
+  const double eta = eta_eV / kHartreeEV;
+  const bool bulk = precision != QCX_FP64, bf = precision == QCX_SPLIT_BF16;
+  constexpr int kChunk = 4096;
+  // weights of the bulk once (they do not depend on G)
+  Chi0Geom g{};
+  g.n_t = ctx->n_t;
+  g.n_w = n_w;
+  g.n_rows = 2 * n_w;
+  const int af = bulk_row_frags(g);
+  g.n_rowsp = (int)roundup(g.n_rows, 32 * af);
+  g.c_rows = g.n_rowsp;
+  g.n_tp = (int)roundup(g.n_t, KSTEP_T * kMaxKsplit);
+  if (bulk) {
+    const size_t nA = (size_t)g.n_rowsp * g.n_tp;
+    if (bf) {
+      HIPCK(ctx->d_A.reserve(sizeof(uint16_t) * nA));
+      HIPCK(ctx->d_Alo.reserve(sizeof(uint16_t) * nA));
+      launch_weights_bf16(ctx->d_w.as<double>(), ctx->d_dt.as<double>(), eta, g,
+                          ctx->d_A.as<uint16_t>(), ctx->d_Alo.as<uint16_t>(), st);
+    } else {
+      HIPCK(ctx->d_A.reserve(sizeof(float) * nA));
+      launch_weights_f32(ctx->d_w.as<double>(), ctx->d_dt.as<double>(), eta, g, ctx->d_A.as<float>(),
+                         st);
+    }
+    LAUNCHCK("weights");
+  }
+  int sp_all;
+  HIPCK(span_begin(ctx, 3, &sp_all));
+  for (int g0 = 0; g0 < n_G; g0 += kChunk) {
+    const int nch = std::min(kChunk, n_G - g0);
+    if (int rc = pair_density_impl(ctx, nch, G_int + 3 * (size_t)g0, nullptr, false)) return rc;
+    HIPCK(stage_begin(ctx));
+    std::vector<int> pairs;
+    AsmArgs a{};
+    a.vq = ctx->d_vq.as<double>();
+    a.pref = 2.0 / (ctx->n_k * ctx->vol);
+    g.n_g = nch;
+    g.n_pairs = nch;
+    g.p0 = 0;
+    g.n_bulk = nch;
+    g.n_bulkp = (int)roundup(nch, 128);
+    if (bulk) {
+      pairs.assign(g.n_bulkp, 0);
+      for (int b = 0; b < nch; ++b) pairs[b] = b | (b << 16);
+      g.gather = nch >= kGatherMinNg ? 1 : 0;
+      if (g.gather) {
+        std::vector<int> local, rows;
+        if (!bulk_gather_tables(pairs, local, rows))
+          return fail(ctx, QCX_EDEVICE, "internal: a pair tile needs more rows than staged");
+        HIPCK(upload(ctx, ctx->d_pairs, local.data(), local.size()));
+        HIPCK(upload(ctx, ctx->d_rows, rows.data(), rows.size()));
+      } else {
+        HIPCK(upload(ctx, ctx->d_pairs, pairs.data(), pairs.size()));
+      }
+      const int blocks = (g.n_bulkp / 128) * (g.n_rowsp / (32 * af));
+      g.ksplit = std::max(ksplit_for_accuracy(g.n_tp / KSTEP_T), pick_ksplit(blocks, g.n_tp / KSTEP_T));
+      HIPCK(ctx->d_R32.reserve(sizeof(float) * 2 * (size_t)g.n_g * g.n_tp));
+      HIPCK(ctx->d_C.reserve(sizeof(float) * (size_t)g.ksplit * g.n_rowsp * 2 * g.n_bulkp));
+      launch_pack_r32(ctx->d_R.as<cplx>(), ctx->ldt, g, bf ? 0 : 1, ctx->d_R32.as<float>(), st);
+      const int* rows_dev = g.gather ? ctx->d_rows.as<int>() : nullptr;
+      int sp;
+      HIPCK(span_begin(ctx, 1, &sp));
+      if (bf)
+        launch_bulk_bf16(ctx->d_A.as<uint16_t>(), ctx->d_Alo.as<uint16_t>(), ctx->d_R32.as<float>(),
+                         ctx->d_pairs.as<int>(), rows_dev, g, 2, ctx->d_C.as<float>(), st);
+      else
+        launch_bulk_f32(ctx->d_A.as<float>(), ctx->d_R32.as<float>(), ctx->d_pairs.as<int>(), rows_dev,
+                        g, 2, ctx->d_C.as<float>(), st);
+      HIPCK(span_end(ctx, sp));
+      LAUNCHCK("bulk (diagonal)");
+      a.C = ctx->d_C.as<float>();
+      a.ks = g.ksplit;
+    } else {
+      pairs.resize(nch);
+      for (int b = 0; b < nch; ++b) pairs[b] = b | (b << 16);
+      HIPCK(upload(ctx, ctx->d_pairs64, pairs.data(), pairs.size()));
+      Geom64& g64 = ctx->geom64;
+      geom64_init(g64, nch, n_w, ctx->n_t, nch, (size_t)512 << 20);
+      HIPCK(ctx->d_XY.reserve(sizeof(double) * (size_t)g64.ksplit * g64.n_rowsp * g64.n_colp));
+      int sp;
+      HIPCK(span_begin(ctx, 2, &sp));
+      launch_pairs_f64(ctx->d_R.as<cplx>(), ctx->ldt, ctx->d_w.as<double>(), ctx->d_dt.as<double>(),
+                       eta, g64, ctx->d_pairs64.as<int>(), ctx->d_XY.as<double>(), st);
+      HIPCK(span_end(ctx, sp));
+      LAUNCHCK("pairs_f64 (diagonal)");
+      a.XY = ctx->d_XY.as<double>();
+      a.ks64 = g64.ksplit;
+      a.n_rowsp64 = g64.n_rowsp;
+      a.n_colp64 = g64.n_colp;
+    }
+    launch_diag_loss(a, g, nch, n_w, loss_out, n_G, g0, st);
+    LAUNCHCK("diag_loss");
+  }
+  HIPCK(span_end(ctx, sp_all));
+  // the pair densities left behind belong to the last chunk only
+  ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
+  return QCX_OK;
+}
 
 int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int precision,
              int headwings_fp64, void* chi0_out) {

@@ -61,6 +61,7 @@ _SIGS = {
     "qcx_run_batch": [_P, _I, _P, _I, _I, _I, _I],
     "qcx_batch_sync": [_P],
     "qcx_batch_config": [_P, _P, _P],
+    "qcx_loss_diag": [_P, _I, _P, _I, _P, _D, _I, _P],
     "qcx_mlp_create": [ctypes.POINTER(_P), _P, _I],
     "qcx_mlp_destroy": [_P],
     "qcx_mlp_set_params": [_P, _I, _P],
@@ -242,6 +243,22 @@ class Context:
             return arr
         self._check(self.lib.qcx_loss(self._h, _dev_ptr(out, "f64", self.n_w * self.n_g, "out"),
                                       MEM_DEVICE))
+        return out
+
+    def loss_diag(self, G_int, w_eV, eta_eV: float, precision="split_bf16", out=None):
+        """noLFE loss for any number of G (qcx_loss_diag): CUDA float64 tensor
+        [n_w][n_G] (allocated when out is None).  Replaces the pair densities."""
+        import torch
+
+        G = _host(G_int, np.int32).reshape(-1, 3)
+        w = _host(w_eV, np.float64).reshape(-1)
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        if out is None:
+            out = torch.empty((len(w), len(G)), dtype=torch.float64, device="cuda")
+        self._check(self.lib.qcx_loss_diag(self._h, len(G), _ptr_host(G), len(w), _ptr_host(w),
+                                           float(eta_eV), int(precision),
+                                           _dev_ptr(out, "f64", len(w) * len(G), "out")))
         return out
 
     def sync(self):

@@ -220,3 +220,47 @@ def test_macroscopic_eps_is_inverse_head(cfg1_oracle):
     assert np.allclose(em, 1.0 / np.linalg.inv(eps)[:, 0, 0], rtol=1e-14, atol=0)
     # loss at G = 0 is Im(-1/eps_M)
     assert np.allclose(cfg1_oracle["loss"][:, 0], np.imag(-1.0 / em), rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------- noLFE diagonal and composite
+def test_chi0_diagonal_is_diagonal_of_chi0(cfg1_oracle):
+    d = rpa.chi0_diagonal(cfg1_oracle["R"], cfg1_oracle["W"])
+    full = np.einsum("wgg->wg", cfg1_oracle["chi0"])
+    assert np.max(np.abs(d - full)) <= 1e-14 * np.max(np.abs(full))
+
+
+def test_loss_diag_matches_nolfe_of_full_path(cfg1, cfg1_oracle):
+    st = cfg1.states(0)
+    L = rpa.loss_diag(cfg1.cell, cfg1.basis, cfg1.lattice_range, cfg1.k_frac, cfg1.n_occ,
+                      cfg1.G_int, st, cfg1.w_eV, cfg1.eta_eV)
+    ref = rpa.loss_nolfe(cfg1_oracle["eps"])
+    assert np.max(np.abs(L - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_loss_diag_per_g_independent_of_list(cfg1):
+    """Each G's diagonal depends on that G alone: any subset, order or
+    duplication (no G = 0) gives the same columns."""
+    st = cfg1.states(0)
+    G = np.asarray(cfg1.G_int)
+    args = (cfg1.cell, cfg1.basis, cfg1.lattice_range, cfg1.k_frac, cfg1.n_occ)
+    w = cfg1.w_eV[::16]
+    full = rpa.loss_diag(*args, G, st, w, cfg1.eta_eV)
+    pick = np.array([5, 3, 26, 5, 11])
+    sub = rpa.loss_diag(*args, G[pick], st, w, cfg1.eta_eV)
+    assert np.max(np.abs(sub - full[:, pick])) <= 1e-13 * np.max(np.abs(full))
+
+
+def test_composite_limits(cfg1, cfg1_oracle):
+    """q_lfe above every |q+G|: the LFE loss; q_lfe between |q| and the next
+    |q+G|: a 1 x 1 LFE block, i.e. the noLFE loss everywhere."""
+    st = cfg1.states(0)
+    args = (cfg1.cell, cfg1.basis, cfg1.lattice_range, cfg1.k_frac, cfg1.n_occ, cfg1.G_int, st,
+            cfg1.w_eV, cfg1.eta_eV)
+    qn = np.linalg.norm(cfg1_oracle["Q"], axis=1)
+    hi = rpa.loss_composite(*args, q_lfe=qn.max() * 1.01)
+    assert np.max(np.abs(hi - cfg1_oracle["loss"])) <= 1e-13 * np.max(np.abs(cfg1_oracle["loss"]))
+    lo = rpa.loss_composite(*args, q_lfe=0.5 * (qn[0] + np.sort(qn)[1]))
+    ref = rpa.loss_nolfe(cfg1_oracle["eps"])
+    assert np.max(np.abs(lo - ref)) <= 1e-13 * np.max(np.abs(ref))
+    with pytest.raises(ValueError):
+        rpa.composite_split(cfg1.cell.lat, st.q_cart, np.asarray(cfg1.G_int)[1:], qn.max())
