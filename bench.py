@@ -13,7 +13,10 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 Prints one JSON line.  --workload mixed-batch measures the batched engine
 instead: 20 uneven items (five fcc cells, N_G 59-259, 6^3-10^3 k, 2000
 (q, w) points) through one persistent bulk launch and replayed hipGraphs,
-against the same items run one by one.
+against the same items run one by one.  --workload composite measures the
+composite dielectric function at the Si-like benchmark cell for one q: LFE
+block |q+G| <= 6 bohr^-1 (about 950 G, inverted), noLFE diagonal for every
+other G up to |q+G| <= 25 bohr^-1 (about 71,000 G in all).
 """
 from __future__ import annotations
 
@@ -49,7 +52,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample-w", type=int, default=400)
-    ap.add_argument("--workload", choices=["si-ng113", "mixed-batch"], default="si-ng113")
+    ap.add_argument("--workload", choices=["si-ng113", "mixed-batch", "composite"], default="si-ng113")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB elementwise copy before timing (HBM counter calibration)")
     return ap.parse_args()
@@ -313,6 +316,104 @@ def main_batch(args):
     print(json.dumps(out))
 
 
+def composite_g(lat, q_cart, q_max):
+    """Every G with |q + G| <= q_max, sorted by |q + G| (then the triple)."""
+    b = 2.0 * np.pi * np.linalg.inv(np.asarray(lat, np.float64)).T
+    R = int(q_max / np.linalg.svd(b, compute_uv=False).min()) + 2
+    r = np.arange(-R, R + 1)
+    G = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    qn = np.linalg.norm(np.asarray(q_cart)[None, :] + G @ b, axis=1)
+    keep = qn <= q_max
+    G, qn = G[keep], qn[keep]
+    order = np.lexsort((G[:, 2], G[:, 1], G[:, 0], np.round(qn, 12)))
+    return np.ascontiguousarray(G[order].astype(np.int32))
+
+
+def main_composite(args):
+    """Composite loss for one q of the Si-like benchmark cell."""
+    import torch
+
+    from paper_2603_12326_amd import Context, build_info
+    from paper_2603_12326_amd import composite as C
+    from synth import make_config2
+
+    Q_MAX, Q_LFE = 25.0, 6.0
+    wl = make_config2(n_q=1)
+    qs, kf = upload_workload(wl, 1, torch)
+    d = qs[0]
+    G = composite_g(wl.cell.lat, d["q"], Q_MAX)
+    n_w, n_g = len(wl.w_eV), len(G)
+    ctx = Context(0)
+    b = wl.basis
+    ctx.set_cell_basis(wl.cell.lat, wl.cell.xyz, b.shell_atom, b.shell_l, b.shell_exp, 1, 1)
+    res = {}
+
+    def step():
+        ctx.set_states(d["q"], kf, wl.n_occ, d["C_k"], d["E_k"], d["C_kq"], d["E_kq"])
+        res["parts"] = C.composite_loss(ctx, wl.cell.lat, d["q"], G, wl.w_eV, wl.eta_eV, Q_LFE,
+                                        "split_bf16")
+
+    log(f"composite: {n_g} G, {args.warmup} warmup + {args.steps} timed steps")
+    for _ in range(max(1, args.warmup)):
+        step()
+    ctx.sync()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    st = ctx.stage_times()
+    ctx.set_timing(False)
+    inner, L_in, outer, L_out = res["parts"]
+    vals = n_w * n_g
+    out = {
+        "metric": "composite loss (w, q+G) values/s: LFE block inverted, noLFE diagonal beyond",
+        "value": vals * args.steps / sec,
+        "unit": "values/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "Si-like fcc a=10.26, 28 GTO, 4+16 bands, 8^3 k, q=0.1*2pi/a x, "
+                               f"400 w over 0-60 eV, eta=0.1 eV; LFE |q+G|<={Q_LFE} bohr^-1 "
+                               f"({len(inner)} G), noLFE up to {Q_MAX} bohr^-1 ({len(outer)} G)",
+                   "n_g_lfe": int(len(inner)), "n_g_nolfe": int(len(outer))},
+        "stages_ms_per_step": {k: (v / args.steps if k.endswith("_ms") else v) for k, v in st.items()},
+        "build": build_info(),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import rpa
+        n_s, w_idx = 300, np.arange(0, n_w, 100)
+        pick = np.asarray(outer)[np.linspace(0, len(outer) - 1, n_s).round().astype(int)]
+        log(f"cpu baseline (oracle noLFE diagonal, {n_s} G x {len(w_idx)} w)")
+        s0 = wl.states(0)
+        t0 = time.perf_counter()
+        ref = rpa.loss_diag(wl.cell, wl.basis, wl.lattice_range, wl.k_frac, wl.n_occ, G[pick], s0,
+                            wl.w_eV[w_idx], wl.eta_eV)
+        dt = time.perf_counter() - t0
+        pos = np.searchsorted(np.asarray(outer), pick)
+        got = L_out.cpu().numpy()[np.ix_(w_idx, pos)]
+        out["max_rel_err_nolfe_sample"] = normwise(got, ref)
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        except Exception:
+            threads = os.cpu_count()
+        out["cpu_baseline"] = dict(value=ref.size / dt, unit="values/s", cores=int(threads),
+                                   kind="oracle",
+                                   sample=f"noLFE diagonal, {n_s} G x {len(w_idx)} w, rho included, "
+                                          f"{dt:.1f} s")
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -322,6 +423,8 @@ def main():
         sys.exit(2)
     if args.workload == "mixed-batch":
         return main_batch(args)
+    if args.workload == "composite":
+        return main_composite(args)
     import torch
 
     from paper_2603_12326_amd import Context, build_info
