@@ -182,6 +182,32 @@ int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out);
  * Errors: QCX_ESTATE (no eps_inv), QCX_EINVAL, QCX_ESINGULAR. */
 int qcx_loss(qcx_ctx* ctx, double* out, int mem);
 
+/* chi0 by way of the spectral part (Sec. II.D, Eq. eRPA_spectral and the
+ * Kramers-Kronig relations): the pair products of every transition are
+ * binned by energy with hat functions of width bin_eV on the grid
+ * w_b = b * bin_eV (resonant and anti-resonant transitions separately),
+ *   S_b(G, G') = sum_t h_b(D_t) rho_t(G)^* rho_t(G'),
+ * and the response at each frequency follows from the binned spectral
+ * function carried through the energy denominator exactly:
+ *   chi0_GG'(w) = 2/(N_k V) sum_b [ S^r_b K(w - w_b + i eta) - S^a_b K(w + w_b - i eta) ],
+ *   K(x) = int h(x') / (x - x') dx' / bin_eV (closed form; at eta = 0 the
+ *   principal value minus i pi times the binned spectral density).
+ * As bin_eV -> 0 this converges to qcx_chi0 at the same eta (error of order
+ * (bin_eV / eta)^2); at eta = 0 its imaginary part is the binned spectral
+ * part and its real part the Kramers-Kronig transform of it.  The binning
+ * runs on the chi0 bulk kernel (MFMA, FP32 or split-BF16) over energy-sorted
+ * transitions, each bin tile visiting only the transitions that reach it;
+ * bins are summed in FP64 and transformed by an FP64 MFMA product.  With
+ * headwings_fp64 the G = 0 row and column take the direct FP64 route of
+ * qcx_chi0 instead.  Afterwards qcx_eps_inv / qcx_loss work as after
+ * qcx_chi0.
+ *   n_w, w_eV, eta_eV (>= 0), chi0_out as for qcx_chi0; bin_eV > 0
+ *   precision  QCX_FP32 or QCX_SPLIT_BF16
+ * Errors: QCX_ESTATE (no pair densities), QCX_EINVAL (sizes, more than
+ * 262144 bins or 8 GB of partial sums: widen bin_eV), QCX_ENOMEM. */
+int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double bin_eV,
+                int precision, int headwings_fp64, void* chi0_out);
+
 /* Loss without local field effects, Eq. (eps_noLFE), for a G list of any
  * length (Sec. III: the high-momentum part of the composite dielectric
  * function, where only the diagonal of Eq. (RPA) is needed):

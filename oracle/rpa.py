@@ -209,6 +209,82 @@ def loss_composite(cell, basis, lattice_range, k_frac, n_occ, G_int, states, w_e
     return out
 
 
+# --------------------------------------------------------------------------
+# Kramers-Kronig route (Sec. II.D, Eq. eRPA_spectral): the spectral part of
+# Eq. (RPA) binned by transition energy, then carried back to every
+# frequency.  Each transition's delta function is shared between its two
+# nearest bins with hat weights h_b(x) = max(0, 1 - |x - w_b| / d); the binned
+# spectral density is the piecewise-linear function sum_b S_b h_b(x) / d, and
+# its response at w is the integral of that density against the energy
+# denominator, which for one hat is K(x) = I(x / d) / d with
+#     I(z) = int_{-1}^{1} (1 - |y|) / (z - y) dy.
+# --------------------------------------------------------------------------
+def hat_kernel(z) -> np.ndarray:
+    """I(z) in closed form: (z + 1) log(z + 1) - 2 z log z + (z - 1) log(z - 1),
+    principal complex logarithm (Im z != 0 keeps the segment [z - 1, z + 1]
+    off the branch cut); on the real axis the sign of the zero imaginary part
+    selects the limit from above (+0) or below (-0); 0 log 0 = 0.
+    Parity: pinned by numerical quadrature of the defining integral."""
+    z = np.asarray(z, np.complex128)
+
+    def xlogx(u):
+        out = np.zeros_like(u)
+        nz = u != 0
+        out[nz] = u[nz] * np.log(u[nz])
+        return out
+
+    def shift(u, a):  # u + a with the imaginary part (and the sign of a zero) kept
+        v = np.empty_like(u)
+        v.real = u.real + a
+        v.imag = u.imag
+        return v
+
+    return xlogx(shift(z, 1.0)) - 2.0 * xlogx(z) + xlogx(shift(z, -1.0))
+
+
+def spectral_bins(E: np.ndarray, bin_eV: float):
+    """Bin centres b d (Ha) covering every energy of E (Ha) and hat weights
+    H[b][t] (each column sums to 1)."""
+    d = bin_eV / HARTREE_EV
+    b_lo = int(np.floor(E.min() / d)) - 1
+    b_hi = int(np.floor(E.max() / d)) + 2
+    centres = np.arange(b_lo, b_hi + 1) * d
+    H = np.maximum(0.0, 1.0 - np.abs(E[None, :] - centres[:, None]) / d)
+    return centres, H
+
+
+def chi0_kk(R, E_k, E_kq, n_occ, w_eV, eta_eV, bin_eV, volume) -> np.ndarray:
+    """chi0[w][G][G'] from the binned spectral part:
+    sum_b S^r_b K(w - w_b + i eta) - sum_b S^a_b K(w + w_b - i eta), with
+    S_b = 2/(N_k V) sum_t h_b(D_t) R_t(G)^* R_t(G') per side (D = E_c(k+q) -
+    E_v(k) resonant, D' = E_c(k) - E_v(k+q) anti-resonant).  eta = 0 gives the
+    spectral part as the imaginary part and its Kramers-Kronig transform as
+    the real part.
+    Parity: tends to chi0() at the same eta as bin_eV -> 0 (second order)."""
+    nk = np.asarray(E_k).shape[0]
+    d = bin_eV / HARTREE_EV
+    eta = float(eta_eV) / HARTREE_EV
+    w = np.asarray(w_eV, np.float64) / HARTREE_EV
+    d_res, d_anti = transition_energies(E_k, E_kq, n_occ)
+    ng = R.shape[-1]
+    norm = 2.0 / (nk * float(volume))
+    out = np.zeros((len(w), ng, ng), np.complex128)
+    for side, E, sgn in ((0, d_res.reshape(-1), 1.0), (1, d_anti.reshape(-1), -1.0)):
+        Rs = R[side].reshape(-1, ng)
+        centres, H = spectral_bins(E, bin_eV)
+        RH = np.conj(Rs).T
+        S = np.stack([(RH * H[b][None, :]) @ Rs for b in range(len(centres))]) * norm
+        # resonant K(w - w_b + i eta), limit from above at eta = 0;
+        # anti-resonant -K(w + w_b - i eta), limit from below at eta = 0
+        x = (w[:, None] - sgn * centres[None, :]) / d
+        z = np.empty(x.shape, np.complex128)
+        z.real = x
+        z.imag = sgn * eta / d if eta > 0 else sgn * 0.0   # signed zero picks the side
+        K = hat_kernel(z) / d
+        out += sgn * np.einsum("wb,bgh->wgh", K, S)
+    return out
+
+
 def eps_macro(eps: np.ndarray) -> np.ndarray:
     """eps_M(w) = 1 / [eps^{-1}]_00."""
     return 1.0 / inverse_diagonal(eps)[:, 0]

@@ -61,6 +61,9 @@ struct qcx_ctx {
   double tune_ms = 0.0;       // time spent tuning in the last qcx_chi0
   Geom64 geom64{};
   DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_rows, d_pairs64, d_C, d_C64, d_XY;
+  // Kramers-Kronig route: energy order, sorted energies and sides, K ranges
+  // per row tile, reduced bins, transform matrix
+  DevBuf d_kk_order, d_kk_es, d_kk_sd, d_kk_kr, d_kk_S, d_kk_K;
   bool bulk_c64 = false;      // bulk partials reduced to FP64 (row chunks)
 
   // eps
@@ -94,7 +97,8 @@ struct qcx_ctx {
                      &d_Ck,   &d_Ek,    &d_Ckq,    &d_Ekq,    &d_dt,    &d_ph,   &d_phq,
                      &d_S,    &d_F0,    &d_dev,    &d_flags,    &d_Q,      &d_vq,    &d_F,    &d_M,
                      &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_rows, &d_pairs64, &d_C, &d_C64,
-                     &d_XY,   &d_eps,   &d_diag,   &d_epsM,   &d_loss,  &d_sing};
+                     &d_XY,   &d_eps,   &d_diag,   &d_epsM,   &d_loss,  &d_sing,
+                     &d_kk_order, &d_kk_es, &d_kk_sd, &d_kk_kr, &d_kk_S, &d_kk_K};
     for (DevBuf* b : all) b->release();
     for (const Span& sp : spans) {
       (void)hipEventDestroy(sp.a);

@@ -808,6 +808,203 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
   return QCX_OK;
 }
 
+int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double bin_eV,
+                int precision, int headwings_fp64, void* chi0_out) {
+  if (!ctx) return QCX_EINVAL;
+  if (!ctx->have_rho) return fail(ctx, QCX_ESTATE, "pair_density first");
+  if (n_w < 1 || n_w > 65536 || !w_eV) return fail(ctx, QCX_EINVAL, "need 1 <= n_w <= 65536");
+  if (!(eta_eV >= 0.0) || !std::isfinite(eta_eV)) return fail(ctx, QCX_EINVAL, "eta must be >= 0");
+  if (!(bin_eV > 0.0) || !std::isfinite(bin_eV)) return fail(ctx, QCX_EINVAL, "bin width must be > 0");
+  if (precision != QCX_FP32 && precision != QCX_SPLIT_BF16)
+    return fail(ctx, QCX_EINVAL, "the binned route runs in FP32 or split-BF16");
+  HIPCK(hipSetDevice(ctx->device));
+  ctx->have_chi0 = ctx->have_eps = false;
+  hipStream_t st = ctx->stream;
+  std::vector<double> w(n_w);
+  for (int i = 0; i < n_w; ++i) {
+    if (!std::isfinite(w_eV[i])) return fail(ctx, QCX_EINVAL, "non-finite frequency");
+    w[i] = w_eV[i] / kHartreeEV;
+  }
+  const double d = bin_eV / kHartreeEV, eta = eta_eV / kHartreeEV;
+  const bool bf = precision == QCX_SPLIT_BF16;
+  const int n_t = ctx->n_t, n_half = n_t / 2;
+  // transition energies in energy order within each side
+  std::vector<double> dt(n_t);
+  HIPCK(hipMemcpyAsync(dt.data(), ctx->d_dt.p, sizeof(double) * n_t, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  std::vector<int> order(n_t);
+  for (int t = 0; t < n_t; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.begin() + n_half, [&](int a, int b) { return dt[a] < dt[b]; });
+  std::stable_sort(order.begin() + n_half, order.end(), [&](int a, int b) { return dt[a] < dt[b]; });
+  std::vector<double> es(n_t);
+  std::vector<int> sd(n_t);
+  for (int t = 0; t < n_t; ++t) {
+    es[t] = dt[order[t]];
+    sd[t] = t < n_half ? 0 : 1;
+    if (!std::isfinite(es[t])) return fail(ctx, QCX_EINVAL, "non-finite transition energy");
+  }
+  // bins w_b = (b0 + b) d covering each side's energies with one bin to spare
+  auto bins = [&](int lo, int hi, int& b0, int& nb) {
+    b0 = (int)std::floor(es[lo] / d) - 1;
+    nb = (int)std::ceil(es[hi - 1] / d) + 1 - b0 + 1;
+  };
+  int b0r, nr, b0a, na;
+  bins(0, n_half, b0r, nr);
+  bins(n_half, n_t, b0a, na);
+  if ((double)nr + na > 262144.0) return fail(ctx, QCX_EINVAL, "too many bins: widen bin_eV");
+
+  Chi0Geom g{};
+  g.n_g = ctx->n_g;
+  g.n_t = n_t;
+  g.n_w = n_w;
+  g.n_rows = nr + na;
+  const int af = bulk_row_frags(g);
+  g.n_rowsp = (int)roundup(g.n_rows, 32 * af);
+  g.c_rows = g.n_rowsp;
+  g.n_tp = (int)roundup(n_t, KSTEP_T * kMaxKsplit);
+  g.n_pairs = ctx->n_g * (ctx->n_g + 1) / 2;
+  ctx->n_pairs64 = headwings_fp64 ? ctx->n_g : 0;
+  g.p0 = ctx->n_pairs64;
+  g.n_bulk = g.n_pairs - g.p0;
+  g.n_bulkp = (int)roundup(std::max(g.n_bulk, 1), 128);
+  // K-step range of every row tile: the transitions whose hat functions reach
+  // its bins
+  const int rows_t = 32 * af, n_tiles = g.n_rowsp / rows_t;
+  std::vector<int> kr(2 * n_tiles, 0);
+  int max_span = 1;
+  for (int r = 0; r < n_tiles; ++r) {
+    int lo = INT_MAX, hi = 0;
+    const int r0 = r * rows_t, r1 = std::min(g.n_rows, r0 + rows_t);
+    auto cover = [&](int row_lo, int row_hi, int b0, int t_lo, int t_hi) {  // rows of one side
+      if (row_lo >= row_hi) return;
+      const double e_lo = (b0 + row_lo) * d - d, e_hi = (b0 + row_hi - 1) * d + d;
+      const int a = (int)(std::lower_bound(es.begin() + t_lo, es.begin() + t_hi, e_lo) - es.begin());
+      const int b = (int)(std::upper_bound(es.begin() + t_lo, es.begin() + t_hi, e_hi) - es.begin());
+      if (a < b) {
+        lo = std::min(lo, a);
+        hi = std::max(hi, b);
+      }
+    };
+    cover(std::max(r0, 0), std::min(r1, nr), b0r, 0, n_half);
+    cover(std::max(r0, nr) - nr, std::max(std::min(r1, nr + na), nr) - nr, b0a, n_half, n_t);
+    if (lo < hi) {
+      kr[2 * r] = lo / KSTEP_T;
+      kr[2 * r + 1] = (hi + KSTEP_T - 1) / KSTEP_T;
+      max_span = std::max(max_span, kr[2 * r + 1] - kr[2 * r]);
+    }
+  }
+  const int blocks = (g.n_bulkp / 128) * n_tiles;
+  g.ksplit = std::max(ksplit_for_accuracy(max_span), pick_ksplit(blocks, max_span));
+  const size_t nC = (size_t)g.ksplit * g.n_rowsp * 2 * g.n_bulkp;
+  if (nC * sizeof(float) > kPartialBudget) return fail(ctx, QCX_EINVAL, "binned partials exceed 8 GB: widen bin_eV");
+
+  HIPCK(stage_begin(ctx));
+  HIPCK(upload(ctx, ctx->d_w, w.data(), w.size()));
+  HIPCK(upload(ctx, ctx->d_kk_order, order.data(), order.size()));
+  HIPCK(upload(ctx, ctx->d_kk_es, es.data(), es.size()));
+  HIPCK(upload(ctx, ctx->d_kk_sd, sd.data(), sd.size()));
+  HIPCK(upload(ctx, ctx->d_kk_kr, kr.data(), kr.size()));
+  ctx->n_w = n_w;
+  ctx->eta = eta;
+  ctx->prec = precision;
+  ctx->hw64 = headwings_fp64 ? 1 : 0;
+  int sp_all, sp_bulk = -1, sp_hw = -1;
+  HIPCK(span_begin(ctx, 3, &sp_all));
+  if (g.n_bulk > 0) {
+    std::vector<int> pairs(g.n_bulkp, 0);
+    {
+      int b = 0, p = 0;
+      for (int G = 0; G < g.n_g; ++G)
+        for (int Gp = G; Gp < g.n_g; ++Gp, ++p)
+          if (p >= g.p0) pairs[b++] = G | (Gp << 16);
+    }
+    g.gather = g.n_g >= kGatherMinNg ? 1 : 0;
+    if (g.gather) {
+      std::vector<int> local, rows;
+      if (!bulk_gather_tables(pairs, local, rows))
+        return fail(ctx, QCX_EDEVICE, "internal: a pair tile needs more rows than staged");
+      HIPCK(upload(ctx, ctx->d_pairs, local.data(), local.size()));
+      HIPCK(upload(ctx, ctx->d_rows, rows.data(), rows.size()));
+    } else {
+      HIPCK(upload(ctx, ctx->d_pairs, pairs.data(), pairs.size()));
+    }
+    const int* rows_dev = g.gather ? ctx->d_rows.as<int>() : nullptr;
+    const size_t nA = (size_t)g.n_rowsp * g.n_tp;
+    HIPCK(ctx->d_R32.reserve(sizeof(float) * 2 * (size_t)g.n_g * g.n_tp));
+    HIPCK(ctx->d_C.reserve(sizeof(float) * nC));
+    HIPCK(ctx->d_kk_S.reserve(sizeof(double) * (size_t)g.n_rowsp * 2 * g.n_bulkp));
+    HIPCK(ctx->d_A.reserve((bf ? sizeof(uint16_t) : sizeof(float)) * nA));
+    if (bf) HIPCK(ctx->d_Alo.reserve(sizeof(uint16_t) * nA));
+    launch_pack_r32_order(ctx->d_R.as<cplx>(), ctx->ldt, g, bf ? 0 : 1, ctx->d_kk_order.as<int>(),
+                          ctx->d_R32.as<float>(), st);
+    launch_hat_weights(ctx->d_kk_es.as<double>(), ctx->d_kk_sd.as<int>(), nr, na, b0r, b0a, d, g, bf,
+                       ctx->d_A.p, bf ? ctx->d_Alo.p : nullptr, st);
+    LAUNCHCK("hat weights / pack");
+    g.kr = ctx->d_kk_kr.as<int>();
+    HIPCK(span_begin(ctx, 1, &sp_bulk));
+    if (bf)
+      launch_bulk_bf16(ctx->d_A.as<uint16_t>(), ctx->d_Alo.as<uint16_t>(), ctx->d_R32.as<float>(),
+                       ctx->d_pairs.as<int>(), rows_dev, g, 2, ctx->d_C.as<float>(), st);
+    else
+      launch_bulk_f32(ctx->d_A.as<float>(), ctx->d_R32.as<float>(), ctx->d_pairs.as<int>(), rows_dev,
+                      g, 2, ctx->d_C.as<float>(), st);
+    HIPCK(span_end(ctx, sp_bulk));
+    LAUNCHCK("bulk (binning)");
+    g.kr = nullptr;
+    launch_reduce_partials(ctx->d_C.as<float>(), g.ksplit, g.n_rowsp, g.n_bulkp,
+                           ctx->d_kk_S.as<double>(), st);
+    // transform: rows (Re, Im) per frequency x bins, times the bins x (Re P, Im P)
+    const int m = 2 * n_w, ncol = 2 * g.n_bulkp;
+    HIPCK(ctx->d_kk_K.reserve(sizeof(double) * (size_t)m * g.n_rowsp));
+    HIPCK(ctx->d_C64.reserve(sizeof(double) * (size_t)m * ncol));
+    launch_kk_matrix(ctx->d_w.as<double>(), n_w, eta, d, nr, na, b0r, b0a, g.n_rowsp, m,
+                     ctx->d_kk_K.as<double>(), st);
+    launch_gemm64(ctx->d_kk_K.as<double>(), g.n_rowsp, ctx->d_kk_S.as<double>(), ncol,
+                  ctx->d_C64.as<double>(), ncol, m, ncol, g.n_rowsp, st);
+    LAUNCHCK("transform");
+  }
+  if (ctx->n_pairs64 > 0) {
+    Geom64& g64 = ctx->geom64;
+    geom64_init(g64, ctx->n_g, n_w, ctx->n_t, ctx->n_pairs64, (size_t)512 << 20);
+    ctx->ks64 = g64.ksplit;
+    std::vector<int> tab(ctx->n_pairs64);
+    for (int p = 0; p < ctx->n_pairs64; ++p) tab[p] = 0 | (p << 16);
+    HIPCK(upload(ctx, ctx->d_pairs64, tab.data(), tab.size()));
+    HIPCK(ctx->d_XY.reserve(sizeof(double) * (size_t)g64.ksplit * g64.n_rowsp * g64.n_colp));
+    HIPCK(span_begin(ctx, 2, &sp_hw));
+    launch_pairs_f64(ctx->d_R.as<cplx>(), ctx->ldt, ctx->d_w.as<double>(), ctx->d_dt.as<double>(),
+                     eta, g64, ctx->d_pairs64.as<int>(), ctx->d_XY.as<double>(), st);
+    LAUNCHCK("pairs_f64");
+    HIPCK(span_end(ctx, sp_hw));
+  }
+  HIPCK(span_end(ctx, sp_all));
+  // what the assembly reads: one FP64 partial of 2 n_w rows per pair
+  Chi0Geom ga = g;
+  ga.n_rows = 2 * n_w;
+  ga.n_rowsp = 2 * n_w;
+  ga.c_rows = 2 * n_w;
+  ga.ksplit = 1;
+  ga.kr = nullptr;
+  ctx->geom = ga;
+  ctx->bulk_c64 = true;
+  ctx->have_chi0 = true;
+  if (chi0_out) {
+    AsmArgs a{};
+    a.C64 = g.n_bulk > 0 ? ctx->d_C64.as<double>() : nullptr;
+    a.XY = ctx->n_pairs64 > 0 ? ctx->d_XY.as<double>() : nullptr;
+    a.ks = 1;
+    a.ks64 = ctx->ks64;
+    a.n_rowsp64 = ctx->geom64.n_rowsp;
+    a.n_colp64 = ctx->geom64.n_colp;
+    a.n_pairs64 = ctx->n_pairs64;
+    a.vq = ctx->d_vq.as<double>();
+    a.pref = 2.0 / (ctx->n_k * ctx->vol);
+    launch_chi0_export(a, ga, static_cast<cplx*>(chi0_out), st);
+    LAUNCHCK("chi0_export");
+  }
+  return QCX_OK;
+}
+
 int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out) {
   if (!ctx) return QCX_EINVAL;
   if (!ctx->have_chi0) return fail(ctx, QCX_ESTATE, "chi0 first");

@@ -62,6 +62,7 @@ _SIGS = {
     "qcx_batch_sync": [_P],
     "qcx_batch_config": [_P, _P, _P],
     "qcx_loss_diag": [_P, _I, _P, _I, _P, _D, _I, _P],
+    "qcx_chi0_kk": [_P, _I, _P, _D, _D, _I, _I, _P],
     "qcx_mlp_create": [ctypes.POINTER(_P), _P, _I],
     "qcx_mlp_destroy": [_P],
     "qcx_mlp_set_params": [_P, _I, _P],
@@ -228,6 +229,20 @@ class Context:
             out = _dev_ptr(chi0_out, "c128", len(w) * self.n_g * self.n_g, "chi0_out")
         self._check(self.lib.qcx_chi0(self._h, len(w), _ptr_host(w), float(eta_eV), int(precision),
                                       1 if headwings_fp64 else 0, out))
+        self.n_w = len(w)
+
+    def chi0_kk(self, w_eV, eta_eV: float, bin_eV: float, precision=SPLIT_BF16,
+                headwings_fp64: bool = False, chi0_out=None):
+        """chi0 from the binned spectral part (qcx_chi0_kk)."""
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        w = _host(w_eV, np.float64).reshape(-1)
+        out = None
+        if chi0_out is not None:
+            out = _dev_ptr(chi0_out, "c128", len(w) * self.n_g * self.n_g, "chi0_out")
+        self._check(self.lib.qcx_chi0_kk(self._h, len(w), _ptr_host(w), float(eta_eV),
+                                         float(bin_eV), int(precision),
+                                         1 if headwings_fp64 else 0, out))
         self.n_w = len(w)
 
     def eps_inv(self, lfe: bool = True, diag_out=None, epsM_out=None):

@@ -264,3 +264,94 @@ def test_composite_limits(cfg1, cfg1_oracle):
     assert np.max(np.abs(lo - ref)) <= 1e-13 * np.max(np.abs(ref))
     with pytest.raises(ValueError):
         rpa.composite_split(cfg1.cell.lat, st.q_cart, np.asarray(cfg1.G_int)[1:], qn.max())
+
+
+# ---------------------------------------------------------------- Kramers-Kronig route
+def _quad_hat(z):
+    """int_{-1}^{1} (1 - |y|) / (z - y) dy by adaptive quadrature (Cauchy
+    principal value for real z inside (-1, 1))."""
+    from scipy.integrate import quad
+    if z.imag != 0.0:
+        f = lambda y, part: getattr((1 - abs(y)) / (z - y), part)
+        return sum(quad(f, a, b, args=(p,), limit=400)[0] * (1 if p == "real" else 1j)
+                   for a, b in ((-1, 0), (0, 1)) for p in ("real", "imag"))
+    x = z.real
+    # PV int g(y)/(x - y) = -PV int g(y)/(y - x): quad's weight 'cauchy' computes PV int f/(y - x)
+    pv = 0.0
+    for a, b, g in ((-1.0, 0.0, lambda y: 1 + y), (0.0, 1.0, lambda y: 1 - y)):
+        if a < x < b:
+            pv -= quad(g, a, b, weight="cauchy", wvar=x)[0]
+        else:
+            pv += quad(lambda y: g(y) / (x - y), a, b)[0]
+    return pv
+
+
+def test_hat_kernel_against_quadrature():
+    for z in (2 + 0.5j, -0.3 + 0.01j, 0.4 - 0.2j, 30 + 0.1j, -7 - 3j, 1e-3 + 1e-3j):
+        assert abs(rpa.hat_kernel(np.array([z]))[0] - _quad_hat(z)) < 1e-12 * max(1.0, abs(z) ** -1)
+    # real axis: principal value, and -/+ i pi (1 - |x|) from above / below
+    for x in (-0.5, 0.3, 0.999, 1.7, -3.0):
+        up = rpa.hat_kernel(np.array([complex(x, 0.0)]))[0]
+        dn = rpa.hat_kernel(np.array([complex(x, -0.0)]))[0]
+        pv = _quad_hat(complex(x, 0.0))
+        spec = -np.pi * max(0.0, 1 - abs(x))
+        assert abs(up.real - pv) < 1e-10 and abs(dn.real - pv) < 1e-10
+        assert abs(up.imag - spec) < 1e-12 and abs(dn.imag + spec) < 1e-12
+
+
+def test_spectral_bins_partition_of_unity():
+    E = np.random.default_rng(1).uniform(0.05, 0.9, 500)
+    c, H = rpa.spectral_bins(E, 0.3)
+    assert np.max(np.abs(H.sum(axis=0) - 1.0)) < 1e-13
+    assert np.max(np.abs(c @ H - E)) < 1e-13       # first moment kept too
+
+
+def test_chi0_kk_converges_to_direct(cfg1_oracle, cfg1):
+    """At fixed eta the binned route tends to Eq. (RPA) at second order in the
+    bin width: halving the width divides the error by about four."""
+    st = cfg1.states(0)
+    vol = _vol(cfg1.cell)
+    w = cfg1.w_eV[::8]
+    W = rpa.transition_weights(st.E_k, st.E_kq, cfg1.n_occ, w, cfg1.eta_eV, vol)
+    direct = rpa.chi0(cfg1_oracle["R"], W)
+    errs = []
+    for b in (0.08, 0.04, 0.02):
+        kk = rpa.chi0_kk(cfg1_oracle["R"], st.E_k, st.E_kq, cfg1.n_occ, w, cfg1.eta_eV, b, vol)
+        errs.append(np.max(np.abs(kk - direct)) / np.max(np.abs(direct)))
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0, errs
+    assert errs[2] < 2e-3
+
+
+def test_chi0_kk_zero_eta_is_kramers_kronig_pair(cfg1_oracle, cfg1):
+    """eta = 0: Im chi0 is -pi times the binned spectral density, and Re chi0
+    is its Kramers-Kronig (Hilbert) transform, checked for the head by an
+    independent quadrature over the piecewise-linear density."""
+    from scipy.integrate import quad
+    st = cfg1.states(0)
+    vol = _vol(cfg1.cell)
+    b = 0.1
+    w = np.array([3.03, 7.57, 12.01, 20.04])   # poles inside segments, not on bin centres
+    kk = rpa.chi0_kk(cfg1_oracle["R"], st.E_k, st.E_kq, cfg1.n_occ, w, 0.0, b, vol)[:, 0, 0]
+    # spectral densities (per Ha) of the head, both sides, as piecewise-linear functions
+    d_res, d_anti = rpa.transition_energies(st.E_k, st.E_kq, cfg1.n_occ)
+    norm = 2.0 / (len(cfg1.k_frac) * vol)
+    dens = []
+    for side, E in ((0, d_res.reshape(-1)), (1, d_anti.reshape(-1))):
+        c, H = rpa.spectral_bins(E, b)
+        S = norm * (H @ (np.abs(cfg1_oracle["R"][side].reshape(-1, 27)[:, 0]) ** 2))
+        dens.append((c, S / (b / rpa.HARTREE_EV)))
+    wh = w / rpa.HARTREE_EV
+    for j in range(len(w)):
+        c, s = dens[0]
+        assert abs(kk[j].imag + np.pi * np.interp(wh[j], c, s, left=0, right=0)) < 1e-10 * np.max(np.abs(kk))
+        re = 0.0
+        for side, sgn in ((0, 1.0), (1, -1.0)):
+            c, s = dens[side]
+            x0 = sgn * wh[j]                          # pole of 1/(w - x) or -1/(w + x)
+            for a, bb, sa, sb in zip(c[:-1], c[1:], s[:-1], s[1:]):   # linear on each segment
+                f = lambda x: sa + (sb - sa) * (x - a) / (bb - a)
+                if a < x0 < bb:     # PV int f/(w - x) = -PV int f/(x - w)
+                    re -= sgn * quad(f, a, bb, weight="cauchy", wvar=x0)[0]
+                else:
+                    re += quad(lambda x: sgn * f(x) / (wh[j] - sgn * x), a, bb)[0]
+        assert abs(kk[j].real - re) < 1e-9 * np.max(np.abs(kk)), (j, kk[j].real, re)
