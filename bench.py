@@ -16,7 +16,10 @@ instead: 20 uneven items (five fcc cells, N_G 59-259, 6^3-10^3 k, 2000
 against the same items run one by one.  --workload composite measures the
 composite dielectric function at the Si-like benchmark cell for one q: LFE
 block |q+G| <= 6 bohr^-1 (about 950 G, inverted), noLFE diagonal for every
-other G up to |q+G| <= 25 bohr^-1 (about 71,000 G in all).
+other G up to |q+G| <= 25 bohr^-1 (about 71,000 G in all).  --workload kk
+runs the Si-like N_G = 113 step through the Kramers-Kronig route instead
+(spectral part binned at --kk-bin eV, FP64 transform), against the direct
+route on the same inputs.
 """
 from __future__ import annotations
 
@@ -35,6 +38,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_BF16_TFLOPS = 2516.6   # MI355X dense BF16 MFMA
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 matrix
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 matrix and FP64 vector
+HARTREE_EV = 27.211386245988
 # HBM traffic of the bulk kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (one pass each) and scaled by the same counters on a copy of known size;
 # valid only while the kernel source hashes to the recorded value.
@@ -52,7 +57,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample-w", type=int, default=400)
-    ap.add_argument("--workload", choices=["si-ng113", "mixed-batch", "composite"], default="si-ng113")
+    ap.add_argument("--workload", choices=["si-ng113", "mixed-batch", "composite", "kk"],
+                    default="si-ng113")
+    ap.add_argument("--kk-bin", type=float, default=0.025, help="bin width (eV) of --workload kk")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB elementwise copy before timing (HBM counter calibration)")
     return ap.parse_args()
@@ -415,6 +422,145 @@ def main_composite(args):
     ctx.close()
     print(json.dumps(out))
 
+def kk_bins(wl, qs_states, bin_eV):
+    """Bins of the Kramers-Kronig route per q (both sides), as the library
+    forms them: floor(D / d) spans of each side plus one."""
+    d = bin_eV / HARTREE_EV
+    out = []
+    for st in qs_states:
+        ek = np.asarray(st.E_k, np.float64) / HARTREE_EV
+        ekq = np.asarray(st.E_kq, np.float64) / HARTREE_EV
+        n = 0
+        for D in (ekq[:, None, wl.n_occ:] - ek[:, :wl.n_occ, None],
+                  ek[:, None, wl.n_occ:] - ekq[:, :wl.n_occ, None]):
+            u = D.reshape(-1) / d
+            n += int(np.floor(u.max())) - int(np.floor(u.min())) + 2
+        out.append(n)
+    return out
+
+
+def main_kk(args):
+    """Si-like N_G = 113 step through the Kramers-Kronig route."""
+    import torch
+
+    from paper_2603_12326_amd import Context, build_info
+    from synth import make_config2
+
+    BIN = args.kk_bin
+    wl = make_config2(n_q=args.n_q)
+    log(f"generating and uploading {args.n_q} q points")
+    states = [wl.states(iq) for iq in range(args.n_q)]
+    qs, kf = upload_workload(wl, args.n_q, torch)
+    n_g, n_w = len(wl.G_int), len(wl.w_eV)
+    loss_kk = [torch.empty((n_w, n_g), dtype=torch.float64, device="cuda") for _ in qs]
+    loss_dir = [torch.empty((n_w, n_g), dtype=torch.float64, device="cuda") for _ in qs]
+    ctx = Context(0)
+    b = wl.basis
+    ctx.set_cell_basis(wl.cell.lat, wl.cell.xyz, b.shell_atom, b.shell_l, b.shell_exp, 1, 1)
+
+    def step(kk, out):
+        for iq, d in enumerate(qs):
+            ctx.set_states(d["q"], kf, wl.n_occ, d["C_k"], d["E_k"], d["C_kq"], d["E_kq"])
+            ctx.pair_density(wl.G_int)
+            if kk:
+                ctx.chi0_kk(wl.w_eV, wl.eta_eV, BIN)
+            else:
+                ctx.chi0(wl.w_eV, wl.eta_eV, "split_bf16", True)
+            ctx.eps_inv(True)
+            ctx.loss(out[iq])
+
+    def timed_steps(kk, out, name):
+        log(f"{name}: {args.warmup} warmup + {args.steps} timed steps")
+        for _ in range(max(1, args.warmup)):
+            step(kk, out)
+        ctx.sync()
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(kk, out)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        st = ctx.stage_times()
+        ctx.set_timing(False)
+        return sec, st
+
+    sec, st = timed_steps(True, loss_kk, "kk route")
+    sec_d, _ = timed_steps(False, loss_dir, "direct route (split-BF16, FP64 head/wings)")
+    Lk = [o.cpu().numpy() for o in loss_kk]
+    Ld = [o.cpu().numpy() for o in loss_dir]
+    bins = kk_bins(wl, states, BIN)
+    n_pairs = n_g * (n_g + 1) // 2
+    n_launch = args.steps * args.n_q
+    gemm_s = 1e-3 * st["kk_transform_ms"] / n_launch
+    bin_s = 1e-3 * st["chi0_bulk_ms"] / n_launch
+    gemm_flops = float(np.mean([2.0 * (2 * n_w) * nb * (2 * n_pairs) for nb in bins]))
+    bin_flops = 16.0 * wl.n_t * n_pairs           # 8 FP64 FMA per transition and pair
+    points = args.n_q * n_w
+    value = points * args.steps / sec
+    out = {
+        "metric": "(q,w) loss points/s at N_G=113 via the Kramers-Kronig route (FP64)",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Si-like fcc a=10.26, 28 GTO (3s2p1d per atom), 4+16 bands, "
+                               "8^3 k, 10 q along [100], N_G=113, 400 w over 0-60 eV, eta=0.1 eV, "
+                               f"spectral bins {BIN} eV",
+                   "n_g": n_g, "n_q": args.n_q, "n_w": n_w, "n_t": wl.n_t,
+                   "bins_per_q": bins},
+        "roofline": {"bound": "mfma", "achieved": gemm_flops / gemm_s / 1e12,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": gemm_flops / gemm_s / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "k_gemm_f64 (transform, [2 n_w][bins] x [bins][2 n_pairs])",
+                     "avg_launch_ms": 1e3 * gemm_s, "flops_per_launch": gemm_flops},
+        "binning_roofline": {"bound": "alu", "achieved": bin_flops / bin_s / 1e12,
+                             "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                             "frac": bin_flops / bin_s / 1e12 / PEAK_FP64_TFLOPS,
+                             "kernel": "k_kk_bin", "avg_launch_ms": 1e3 * bin_s,
+                             "flops_per_launch": bin_flops},
+        "stages_ms_per_step": {k: (v / args.steps if k.endswith("_ms") else v) for k, v in st.items()},
+        "direct_value": points * args.steps / sec_d,
+        "speedup_kk_vs_direct": sec_d / sec,
+        "max_rel_diff_kk_vs_direct_loss": max(normwise(a, b) for a, b in zip(Lk, Ld)),
+        "build": build_info(),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import rpa
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        except Exception:
+            threads = os.cpu_count()
+        KS = 32
+        s0 = states[0]
+        log(f"cpu baseline (oracle Kramers-Kronig route, q 0, every {KS}th k point)")
+        t0 = time.perf_counter()
+        R = rpa.pair_densities_from_workload(wl.cell, wl.basis, wl.lattice_range, wl.k_frac[::KS],
+                                             s0.q_cart, wl.G_int, s0.C_k[::KS], s0.C_kq[::KS],
+                                             wl.n_occ)
+        chi = rpa.chi0_kk(R, s0.E_k[::KS], s0.E_kq[::KS], wl.n_occ, wl.w_eV, wl.eta_eV, BIN,
+                          abs(float(np.linalg.det(np.asarray(wl.cell.lat)))))
+        Q = rpa.q_plus_g(wl.cell.lat, s0.q_cart, wl.G_int)
+        rpa.loss_lfe(rpa.epsilon(chi, Q))
+        dt = time.perf_counter() - t0
+        n_k = len(wl.k_frac)
+        out["cpu_baseline"] = dict(
+            value=n_w / (dt * n_k / len(wl.k_frac[::KS])), unit="points/s", cores=int(threads),
+            kind="oracle",
+            sample=f"q index 0, {len(wl.k_frac[::KS])} of {n_k} k points (every {KS}th), all "
+                   f"113 G and 400 w, rho included, {dt:.1f} s; scaled by the k fraction (the "
+                   "oracle's cost is linear in the number of transitions)")
+    ctx.close()
+    print(json.dumps(out))
+
 
 def main():
     args = parse()
@@ -427,6 +573,8 @@ def main():
         return main_batch(args)
     if args.workload == "composite":
         return main_composite(args)
+    if args.workload == "kk":
+        return main_kk(args)
     import torch
 
     from paper_2603_12326_amd import Context, build_info

@@ -185,7 +185,9 @@ int qcx_loss(qcx_ctx* ctx, double* out, int mem);
 /* chi0 by way of the spectral part (Sec. II.D, Eq. eRPA_spectral and the
  * Kramers-Kronig relations): the pair products of every transition are
  * binned by energy with hat functions of width bin_eV on the grid
- * w_b = b * bin_eV (resonant and anti-resonant transitions separately),
+ * w_b = b * bin_eV (resonant and anti-resonant transitions separately; a
+ * transition at (i + x) bin_eV, 0 <= x < 1, weighs 1 - x on bin i and x on
+ * bin i + 1),
  *   S_b(G, G') = sum_t h_b(D_t) rho_t(G)^* rho_t(G'),
  * and the response at each frequency follows from the binned spectral
  * function carried through the energy denominator exactly:
@@ -194,19 +196,21 @@ int qcx_loss(qcx_ctx* ctx, double* out, int mem);
  *   principal value minus i pi times the binned spectral density).
  * As bin_eV -> 0 this converges to qcx_chi0 at the same eta (error of order
  * (bin_eV / eta)^2); at eta = 0 its imaginary part is the binned spectral
- * part and its real part the Kramers-Kronig transform of it.  The binning
- * runs on the chi0 bulk kernel (MFMA, FP32 or split-BF16) over energy-sorted
- * transitions, each bin tile visiting only the transitions that reach it;
- * bins are summed in FP64 and transformed by an FP64 MFMA product.  With
- * headwings_fp64 the G = 0 row and column take the direct FP64 route of
- * qcx_chi0 instead.  Afterwards qcx_eps_inv / qcx_loss work as after
- * qcx_chi0.
+ * part and its real part the Kramers-Kronig transform of it.  Everything
+ * runs in FP64: the binning on the vector units over energy-sorted
+ * transitions (each bin written once, no atomics: the result does not depend
+ * on the launch), the transform as one FP64 MFMA product of the
+ * [2 n_w][bins] kernel matrix with the [bins][2 n_pairs] spectral function.
+ * Afterwards qcx_eps_inv / qcx_loss work as after qcx_chi0.  The transition
+ * energies are read back to the host (the call synchronises the stream).
  *   n_w, w_eV, eta_eV (>= 0), chi0_out as for qcx_chi0; bin_eV > 0
- *   precision  QCX_FP32 or QCX_SPLIT_BF16
- * Errors: QCX_ESTATE (no pair densities), QCX_EINVAL (sizes, more than
- * 262144 bins or 8 GB of partial sums: widen bin_eV), QCX_ENOMEM. */
+ * Device memory: S takes bins x n_G (n_G + 1) x 8 bytes (bins = the energy
+ * span of the transitions / bin_eV, both sides).
+ * Errors: QCX_ESTATE (no pair densities), QCX_EINVAL (sizes, non-finite
+ * values, more than 2^20 bins per side or S above 16 GB: widen bin_eV),
+ * QCX_ENOMEM. */
 int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double bin_eV,
-                int precision, int headwings_fp64, void* chi0_out);
+                void* chi0_out);
 
 /* Loss without local field effects, Eq. (eps_noLFE), for a G list of any
  * length (Sec. III: the high-momentum part of the composite dielectric
@@ -357,9 +361,10 @@ int qcx_bulk_config(qcx_ctx* ctx, int cfg[3], double* tune_ms);
  * with HIP events on the context's stream (enabled by qcx_set_timing):
  * t[0] pair_density, t[1] chi0 bulk kernel, t[2] chi0 FP64 head/wings,
  * t[3] chi0 total, t[4] eps assembly + inversion, t[5] launches of the bulk
- * kernel counted.  Synchronises the stream.  Values accumulate until
+ * kernel counted (after qcx_chi0_kk: t[1] is the binning kernel), t[6] the
+ * FP64 transform product of qcx_chi0_kk.  Synchronises the stream.  Values accumulate until
  * qcx_set_timing is called again. */
-int qcx_stage_times(qcx_ctx* ctx, double t[6]);
+int qcx_stage_times(qcx_ctx* ctx, double t[7]);
 int qcx_set_timing(qcx_ctx* ctx, int enable);
 
 /* Library build description (kernel variants compiled in). */

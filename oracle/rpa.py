@@ -223,9 +223,12 @@ def hat_kernel(z) -> np.ndarray:
     """I(z) in closed form: (z + 1) log(z + 1) - 2 z log z + (z - 1) log(z - 1),
     principal complex logarithm (Im z != 0 keeps the segment [z - 1, z + 1]
     off the branch cut); on the real axis the sign of the zero imaginary part
-    selects the limit from above (+0) or below (-0); 0 log 0 = 0.
+    selects the limit from above (+0) or below (-0); 0 log 0 = 0.  The three
+    terms grow like |z| log|z| while I(z) falls like 1/z, so the sum loses
+    about log10(|z|^2 log|z|) digits: it is evaluated in extended precision
+    (x86 long double, 64-bit mantissa) and returned in complex128.
     Parity: pinned by numerical quadrature of the defining integral."""
-    z = np.asarray(z, np.complex128)
+    z = np.asarray(z, np.clongdouble)
 
     def xlogx(u):
         out = np.zeros_like(u)
@@ -239,7 +242,7 @@ def hat_kernel(z) -> np.ndarray:
         v.imag = u.imag
         return v
 
-    return xlogx(shift(z, 1.0)) - 2.0 * xlogx(z) + xlogx(shift(z, -1.0))
+    return (xlogx(shift(z, 1.0)) - 2.0 * xlogx(z) + xlogx(shift(z, -1.0))).astype(np.complex128)
 
 
 def spectral_bins(E: np.ndarray, bin_eV: float):

@@ -92,10 +92,6 @@ struct Chi0Geom {
   int gather;               // 1: per-tile row lists (N_G >= kGatherMinNg)
   int row_tile0;            // first row tile of this launch (row chunks)
   int c_rows;               // rows held by the partial buffer C (n_rowsp unless chunked)
-  // optional device table: K-step range [kr[2 r], kr[2 r + 1]) of row tile r
-  // (rows whose weights vanish outside it; the range is split among the K
-  // splits); null: every row tile runs over all K steps
-  const int* kr;
 };
 // transition energies Delta_t (Ha) and signs for t in [0, n_t)
 void launch_transition_energies(const double* Ek, const double* Ekq, int n_k, int n_b, int n_occ,
@@ -105,22 +101,6 @@ void launch_weights_f32(const double* w, const double* dt, double eta, const Chi
                         float* Aw, hipStream_t st);
 void launch_weights_bf16(const double* w, const double* dt, double eta, const Chi0Geom& g,
                          uint16_t* Ahi, uint16_t* Alo, hipStream_t st);
-// Kramers-Kronig route: hat-function bin weights (rows: nr resonant bins at
-// (b0r + b) d, then na anti-resonant bins at (b0a + b) d) over transitions in
-// energy order es[t'] with sides sd[t']; FP32 (Ahi only) or BF16 hi/lo
-void launch_hat_weights(const double* es, const int* sd, int nr, int na, int b0r, int b0a,
-                        double d, const Chi0Geom& g, bool bf16, void* Ahi, void* Alo,
-                        hipStream_t st);
-// R32 slabs with the transitions in the order order[t'] (zero past n_t)
-void launch_pack_r32_order(const cplx* R, size_t ldt, const Chi0Geom& g, int perm, const int* order,
-                           float* R32, hipStream_t st);
-// Kramers-Kronig transform matrix Kt[m_p][n_cols] (rows Re/Im per frequency,
-// columns the bins of launch_hat_weights) and a plain FP64 GEMM on MFMA:
-// C[M][N] = A[M][K] B[K][N], row-major
-void launch_kk_matrix(const double* w, int n_w, double eta, double d, int nr, int na, int b0r,
-                      int b0a, int n_cols, int m_p, double* Kt, hipStream_t st);
-void launch_gemm64(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int M,
-                   int N, int K, hipStream_t st);
 // R64[g][t] -> R32 slabs [t/16][g][16] (complex float)
 void launch_pack_r32(const cplx* R, size_t ldt, const Chi0Geom& g, int perm, float* R32,
                      hipStream_t st);

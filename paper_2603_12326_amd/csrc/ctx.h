@@ -63,7 +63,7 @@ struct qcx_ctx {
   DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_rows, d_pairs64, d_C, d_C64, d_XY;
   // Kramers-Kronig route: energy order, sorted energies and sides, K ranges
   // per row tile, reduced bins, transform matrix
-  DevBuf d_kk_order, d_kk_es, d_kk_sd, d_kk_kr, d_kk_S, d_kk_K;
+  DevBuf d_kk_order, d_kk_ib, d_kk_xf, d_kk_chunks, d_kk_Rs, d_kk_S, d_kk_K;
   bool bulk_c64 = false;      // bulk partials reduced to FP64 (row chunks)
 
   // eps
@@ -86,7 +86,7 @@ struct qcx_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<Span> spans;
-  double t_acc[6] = {0, 0, 0, 0, 0, 0};
+  double t_acc[7] = {0, 0, 0, 0, 0, 0, 0};
 
   // batch plan owned by the first context of a batch (see qcx_batch.hip)
   qcx::BatchPlan* plan = nullptr;
@@ -98,7 +98,7 @@ struct qcx_ctx {
                      &d_S,    &d_F0,    &d_dev,    &d_flags,    &d_Q,      &d_vq,    &d_F,    &d_M,
                      &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_rows, &d_pairs64, &d_C, &d_C64,
                      &d_XY,   &d_eps,   &d_diag,   &d_epsM,   &d_loss,  &d_sing,
-                     &d_kk_order, &d_kk_es, &d_kk_sd, &d_kk_kr, &d_kk_S, &d_kk_K};
+                     &d_kk_order, &d_kk_ib, &d_kk_xf, &d_kk_chunks, &d_kk_Rs, &d_kk_S, &d_kk_K};
     for (DevBuf* b : all) b->release();
     for (const Span& sp : spans) {
       (void)hipEventDestroy(sp.a);

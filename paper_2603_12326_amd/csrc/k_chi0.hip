@@ -118,82 +118,6 @@ __global__ void k_weights_bf16(const double* w, const double* dt, double eta, Ch
   reinterpret_cast<uint4*>(Alo)[i] = l;
 }
 
-// Spectral binning weights (Kramers-Kronig route) in the same two fragment
-// orders.  Rows [0, nr) are the bins of the resonant side, rows [nr, nr+na)
-// those of the anti-resonant side; bin b of a side sits at w_b = (b0 + b) d.
-// Column t' is the t'-th transition in energy order (es, side sd); the weight
-// is the hat function max(0, 1 - |es - w_b| / d) when the sides match, else 0.
-struct HatArgs {
-  const double* es;  // [n_t] transition energies (Ha), sorted within each side
-  const int* sd;     // [n_t] 0 resonant, 1 anti-resonant
-  int nr, na, b0r, b0a;
-  double d;          // bin width (Ha)
-};
-__device__ inline double hat_w(const HatArgs& h, int row, int t, int n_t) {
-  if (t >= n_t || row >= h.nr + h.na) return 0.0;
-  const int side = row < h.nr ? 0 : 1;
-  if (h.sd[t] != side) return 0.0;
-  const int b = side ? row - h.nr + h.b0a : row + h.b0r;
-  const double x = fabs(h.es[t] - b * h.d) / h.d;
-  return x < 1.0 ? 1.0 - x : 0.0;
-}
-
-__global__ void k_hat_f32(HatArgs hw, Chi0Geom g, float* Aw) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int ntb = g.n_tp / KSTEP;
-  const long total = (long)(g.n_rowsp / 32) * ntb * 64;
-  if (i >= total) return;
-  const int lane = (int)(i % 64);
-  const long fr = i / 64;
-  const int tb = (int)(fr % ntb), rb = (int)(fr / ntb);
-  const int row = rb * 32 + lane % 32;
-  float out[8];
-#pragma unroll
-  for (int s = 0; s < 8; ++s) out[s] = (float)hat_w(hw, row, tb * KSTEP + 2 * s + lane / 32, g.n_t);
-  float4* dst = reinterpret_cast<float4*>(Aw + i * 8);
-  dst[0] = make_float4(out[0], out[1], out[2], out[3]);
-  dst[1] = make_float4(out[4], out[5], out[6], out[7]);
-}
-
-__global__ void k_hat_bf16(HatArgs hw, Chi0Geom g, uint16_t* Ahi, uint16_t* Alo) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int ntb = g.n_tp / KSTEP;
-  const long total = (long)(g.n_rowsp / 32) * ntb * 64;
-  if (i >= total) return;
-  const int lane = (int)(i % 64);
-  const long fr = i / 64;
-  const int tb = (int)(fr % ntb), rb = (int)(fr / ntb);
-  const int row = rb * 32 + lane % 32;
-  uint16_t hi[8], lo[8];
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const double x = hat_w(hw, row, tb * KSTEP + 8 * (lane / 32) + s, g.n_t);
-    hi[s] = bf16_bits((float)x);
-    lo[s] = bf16_bits((float)(x - (double)bf16_val(hi[s])));
-  }
-  uint4 h, l;
-  h.x = hi[0] | ((uint32_t)hi[1] << 16); h.y = hi[2] | ((uint32_t)hi[3] << 16);
-  h.z = hi[4] | ((uint32_t)hi[5] << 16); h.w = hi[6] | ((uint32_t)hi[7] << 16);
-  l.x = lo[0] | ((uint32_t)lo[1] << 16); l.y = lo[2] | ((uint32_t)lo[3] << 16);
-  l.z = lo[4] | ((uint32_t)lo[5] << 16); l.w = lo[6] | ((uint32_t)lo[7] << 16);
-  reinterpret_cast<uint4*>(Ahi)[i] = h;
-  reinterpret_cast<uint4*>(Alo)[i] = l;
-}
-
-// R32 in energy order: column t' takes transition order[t'] (zero past n_t).
-__global__ void k_pack_r32_order(const cplx* R, size_t ldt, int n_g, int n_t, int n_tp, int perm,
-                                 const int* order, float* R32) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long total = (long)n_g * n_tp;
-  if (i >= total) return;
-  const int t = (int)(i % n_tp), g = (int)(i / n_tp);
-  const cplx v = t < n_t ? R[(size_t)g * ldt + order[t]] : cplx{0.0, 0.0};
-  const int tb = t / KSTEP, ti = t % KSTEP;
-  const int tp = perm ? ((ti & 1) * 8 + (ti >> 1)) : ti;
-  float2* dst = reinterpret_cast<float2*>(R32);
-  dst[((size_t)tb * n_g + g) * KSTEP + tp] = make_float2((float)v.re, (float)v.im);
-}
-
 // R32[tb][g][16] complex float.  perm = 1 stores t' = (t%2)*8 + t/2 inside the
 // step so that a lane's eight K values of the 32x32x2 f32 MFMA are contiguous.
 __global__ void k_pack_r32(const cplx* R, size_t ldt, int n_g, int n_tp, int perm, float* R32) {
@@ -284,14 +208,8 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ntb = g.n_tp / KSTEP;
-  int steps = ntb / g.ksplit;
-  int tb0 = bk.z * steps;
-  if (g.kr) {  // this row tile's own K range, split evenly (uniform per block)
-    const int lo = g.kr[2 * (g.row_tile0 + bk.y)], hi = g.kr[2 * (g.row_tile0 + bk.y) + 1];
-    const int per = (hi - lo + g.ksplit - 1) / g.ksplit;
-    tb0 = lo + bk.z * per;
-    steps = min(per, hi - tb0);
-  }
+  const int steps = ntb / g.ksplit;
+  const int tb0 = bk.z * steps;
   const int rb0 = (g.row_tile0 + bk.y) * AF;  // first 32-row fragment (weights)
   const int rc0 = bk.y * AF;                   // first fragment in the partial buffer
   const int b = bk.x * 128 + wave * 32 + (lane & 31);
@@ -359,25 +277,6 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
       acc[f][0][r] = 0.f;
       acc[f][1][r] = 0.f;
     }
-  }
-  auto epilogue = [&] {
-    // C[((ks*c_rows + row)*2 + ri)*n_bulkp + b], row local to the chunk
-#pragma unroll
-    for (int f = 0; f < AF; ++f) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = (rc0 + f) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-#pragma unroll
-        for (int ri = 0; ri < 2; ++ri) {
-          const size_t o = (((size_t)bk.z * g.c_rows + row) * 2 + ri) * g.n_bulkp + b;
-          C[o] = acc[f][ri][r];
-        }
-      }
-    }
-  };
-  if (steps <= 0) {  // an empty K range (uniform per block): zero partials
-    epilogue();
-    return;
   }
 
   auto compute = [&](const L& cur) {
@@ -479,7 +378,20 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
   }
   // the trailing copies must land before the LDS is reused or released
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  epilogue();
+
+  // epilogue: C[((ks*c_rows + row)*2 + ri)*n_bulkp + b], row local to the chunk
+#pragma unroll
+  for (int f = 0; f < AF; ++f) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = (rc0 + f) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri) {
+        const size_t o = (((size_t)bk.z * g.c_rows + row) * 2 + ri) * g.n_bulkp + b;
+        C[o] = acc[f][ri][r];
+      }
+    }
+  }
 }
 
 template <bool BF16, int AF, int MAXR, int NST, bool GATHER>
@@ -802,26 +714,6 @@ void launch_pack_r32(const cplx* R, size_t ldt, const Chi0Geom& g, int perm, flo
   const long total = (long)g.n_g * g.n_tp;
   hipLaunchKernelGGL(k_pack_r32, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, R, ldt,
                      g.n_g, g.n_tp, perm, R32);
-}
-
-void launch_hat_weights(const double* es, const int* sd, int nr, int na, int b0r, int b0a,
-                        double d, const Chi0Geom& g, bool bf16, void* Ahi, void* Alo,
-                        hipStream_t st) {
-  const HatArgs h{es, sd, nr, na, b0r, b0a, d};
-  const long total = (long)(g.n_rowsp / 32) * (g.n_tp / KSTEP) * 64;
-  const dim3 grid((unsigned)((total + 255) / 256));
-  if (bf16)
-    hipLaunchKernelGGL(k_hat_bf16, grid, dim3(256), 0, st, h, g, static_cast<uint16_t*>(Ahi),
-                       static_cast<uint16_t*>(Alo));
-  else
-    hipLaunchKernelGGL(k_hat_f32, grid, dim3(256), 0, st, h, g, static_cast<float*>(Ahi));
-}
-
-void launch_pack_r32_order(const cplx* R, size_t ldt, const Chi0Geom& g, int perm, const int* order,
-                           float* R32, hipStream_t st) {
-  const long total = (long)g.n_g * g.n_tp;
-  hipLaunchKernelGGL(k_pack_r32_order, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, R,
-                     ldt, g.n_g, g.n_t, g.n_tp, perm, order, R32);
 }
 
 int bulk_row_frags(const Chi0Geom& g) {

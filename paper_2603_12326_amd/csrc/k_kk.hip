@@ -1,7 +1,6 @@
-// Kramers-Kronig route of Sec. II.D: the spectral part of Eq. (RPA) is binned
-// (k_bulk with hat-function weights, see launch_hat_weights) and the full
-// response at each frequency follows from the binned spectral function by a
-// linear transform:
+// Kramers-Kronig route of Sec. II.D: the spectral part of Eq. (RPA), binned
+// with hat functions, and its transform back to the response at each
+// frequency,
 //   chi0(w) = sum_b S^r_b K(w - w_b + i eta) - sum_b S^a_b K(w + w_b - i eta),
 //   K(x) = (1/d) I(x / d),  I(z) = int_{-1}^{1} (1 - |y|) / (z - y) dy,
 // i.e. every hat-shaped piece of the spectral density is carried through the
@@ -12,7 +11,10 @@
 // principal value plus -i pi times the spectral density.  For |z| >= 8 the
 // expansion I(z) = sum_n 2 / ((2n+1)(2n+2)) z^-(2n+1) avoids the cancellation
 // between the three logarithms.
-#include "common.h"
+//
+// Binning is a sparse accumulation (two bins per transition), done on the
+// FP64 vector units; the transform is a dense FP64 product on MFMA.
+#include "kk.h"
 
 namespace qcx {
 
@@ -20,6 +22,150 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// ------------------------------------------------------------------ packing
+__global__ void k_kk_pack(const cplx* __restrict__ R, size_t ldt, int n_g, int n_gp, int n_t,
+                          const int* __restrict__ order, cplx* __restrict__ Rs) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_t * n_gp) return;
+  const int t = (int)(i / n_gp), g = (int)(i % n_gp);
+  Rs[i] = g < n_g ? R[(size_t)g * ldt + order[t]] : cplx{0.0, 0.0};
+}
+
+// ------------------------------------------------------------------ binning
+// Block = one 64 x 64 tile (ti <= tj) of the (G, G') plane and one chunk of
+// bins; thread (ty, tx) owns G = g0 + ty + 16 k, G' = h0 + tx + 16 l
+// (k, l < 4).  The transitions of the chunk are walked in energy order, 16 at
+// a time staged in LDS.  Two accumulators per pair hold the bins i and i + 1
+// of the current interval; when the interval changes, finished bins are
+// stored (each bin of the chunk exactly once, empty bins as zero), so the
+// result needs no atomics and does not depend on the launch.
+constexpr int KB_TC = 16;
+
+__device__ inline void tile_of(int p, int T, int& ti, int& tj) {
+  int r = 0, s = T;
+  while (p >= s) {  // row r of the upper triangle holds T - r tiles
+    p -= s;
+    ++r;
+    --s;
+  }
+  ti = r;
+  tj = r + p;
+}
+
+__global__ void __launch_bounds__(256) k_kk_bin(const cplx* __restrict__ Rs, int n_gp, int n_g,
+                                                const int* __restrict__ ib,
+                                                const double* __restrict__ xf,
+                                                const KkChunk* __restrict__ chunks,
+                                                double* __restrict__ S) {
+  __shared__ cplx sa[KB_TC][kKkTile], sb[KB_TC][kKkTile];
+  __shared__ int sib[KB_TC];
+  __shared__ double sx[KB_TC];
+  int ti, tj;
+  tile_of(blockIdx.y, n_gp / kKkTile, ti, tj);
+  const KkChunk ch = chunks[blockIdx.x];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int g0 = ti * kKkTile, h0 = tj * kKkTile;
+  const size_t n_pairs = (size_t)n_g * (n_g + 1) / 2;
+
+  double lr[4][4], li[4][4], hr[4][4], hi[4][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int l = 0; l < 4; ++l) lr[k][l] = li[k][l] = hr[k][l] = hi[k][l] = 0.0;
+
+  // bin j of the chunk (0 <= j < nb) <- (vr, vi) for this thread's pairs
+  auto store = [&](int j, const double (&vr)[4][4], const double (&vi)[4][4], bool zero) {
+    const size_t base = (size_t)(ch.row0 + j) * 2 * n_pairs;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int G = g0 + ty + 16 * k;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const int Gp = h0 + tx + 16 * l;
+        if (G < n_g && Gp < n_g && G <= Gp) {
+          const size_t p = (size_t)G * n_g - (size_t)G * (G - 1) / 2 + (Gp - G);
+          S[base + p] = zero ? 0.0 : vr[k][l];
+          S[base + n_pairs + p] = zero ? 0.0 : vi[k][l];
+        }
+      }
+    }
+  };
+  int wn = 0;  // next bin of the chunk not yet stored
+  auto put = [&](int j, const double (&vr)[4][4], const double (&vi)[4][4]) {
+    if (j < 0 || j >= ch.nb) return;
+    for (; wn < j; ++wn) store(wn, vr, vi, true);
+    store(j, vr, vi, false);
+    wn = j + 1;
+  };
+
+  int cur = ch.k0 - 1;  // interval of the accumulators (bins cur, cur + 1)
+  for (int t0 = ch.ta; t0 < ch.tb; t0 += KB_TC) {
+    const int nt = min(KB_TC, ch.tb - t0);
+    __syncthreads();
+    for (int e = tid; e < KB_TC * kKkTile; e += 256) {
+      const int tt = e / kKkTile, gg = e % kKkTile;
+      cplx va = {0.0, 0.0}, vb = {0.0, 0.0};
+      if (tt < nt) {
+        const cplx* row = Rs + (size_t)(t0 + tt) * n_gp;
+        va = row[g0 + gg];
+        vb = row[h0 + gg];
+      }
+      sa[tt][gg] = va;
+      sb[tt][gg] = vb;
+    }
+    if (tid < nt) {
+      sib[tid] = ib[t0 + tid];
+      sx[tid] = xf[t0 + tid];
+    }
+    __syncthreads();
+    for (int tt = 0; tt < nt; ++tt) {
+      const int i = sib[tt];
+      if (i != cur) {  // the same for every thread of the block
+        put(cur - ch.k0, lr, li);
+        if (i == cur + 1) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+              lr[k][l] = hr[k][l];
+              li[k][l] = hi[k][l];
+              hr[k][l] = hi[k][l] = 0.0;
+            }
+        } else {
+          put(cur + 1 - ch.k0, hr, hi);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int l = 0; l < 4; ++l) lr[k][l] = li[k][l] = hr[k][l] = hi[k][l] = 0.0;
+        }
+        cur = i;
+      }
+      const double x = sx[tt], wl = 1.0 - x;
+      cplx a[4], b[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        a[k] = sa[tt][ty + 16 * k];
+        b[k] = sb[tt][tx + 16 * k];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const double pr = a[k].re * b[l].re + a[k].im * b[l].im;  // conj(a) b
+          const double pi = a[k].re * b[l].im - a[k].im * b[l].re;
+          lr[k][l] += wl * pr;
+          li[k][l] += wl * pi;
+          hr[k][l] += x * pr;
+          hi[k][l] += x * pi;
+        }
+    }
+  }
+  put(cur - ch.k0, lr, li);
+  put(cur + 1 - ch.k0, hr, hi);
+  for (; wn < ch.nb; ++wn) store(wn, lr, li, true);
+}
+
+// ---------------------------------------------------------------- transform
 struct c64 {
   double re, im;
 };
@@ -52,23 +198,20 @@ __device__ inline c64 hat_kernel(c64 z) {
   return {a.re - 2.0 * b.re + c.re, a.im - 2.0 * b.im + c.im};
 }
 
-// Transform matrix Kt[2 n_w (padded m_p)][n_rowsp]: row 2j = Re, 2j + 1 = Im of
-// the kernel of frequency w_j for bin column c (resonant bins, then
-// anti-resonant bins, then zero padding).
 __global__ void k_kk_matrix(const double* __restrict__ w, int n_w, double eta, double d, int nr,
-                            int na, int b0r, int b0a, int n_cols, int m_p, double* __restrict__ Kt) {
+                            int na, int br, int ba, int ldk, double* __restrict__ Kt) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)m_p * n_cols) return;
-  const int row = (int)(i / n_cols), c = (int)(i % n_cols);
+  if (i >= (long)2 * n_w * ldk) return;
+  const int row = (int)(i / ldk), c = (int)(i % ldk);
   const int j = row >> 1, ri = row & 1;
   double v = 0.0;
-  if (j < n_w && c < nr + na) {
+  if (c < nr + na) {
     c64 k;
     if (c < nr) {  // resonant: K(w - w_b + i eta), limit from above at eta = 0
-      const double wb = (b0r + c) * d;
+      const double wb = (br + c) * d;
       k = hat_kernel({(w[j] - wb) / d, eta / d});
     } else {       // anti-resonant: -K(w + w_b - i eta), limit from below
-      const double wb = (b0a + c - nr) * d;
+      const double wb = (ba + c - nr) * d;
       k = hat_kernel({(w[j] + wb) / d, eta > 0.0 ? -eta / d : -0.0});
       k = {-k.re, -k.im};
     }
@@ -77,73 +220,127 @@ __global__ void k_kk_matrix(const double* __restrict__ w, int n_w, double eta, d
   Kt[i] = v;
 }
 
-// C[M][N] = A[M][K] B[K][N] (row-major FP64) on FP64 MFMA 16x16x4: block
-// 64 x 64 of C, wave 32 x 32 (2 x 2 tiles), K staged 16 at a time k-major in
-// LDS.  Layouts: A 16x4, lane l holds A[l%16][l/16]; B 4x16, lane l holds
-// B[l/16][l%16]; D 16x16, lane l holds D[4r + l/16][l%16].
-__global__ void __launch_bounds__(256) k_gemm64(const double* __restrict__ A, int lda,
-                                                const double* __restrict__ B, int ldb,
-                                                double* __restrict__ C, int ldc, int M, int N, int K) {
-  __shared__ double sA[16][65], sB[16][65];
+// C[M][N] = A[M][K] B[K][N] (row-major FP64) on v_mfma_f64_16x16x4f64.
+// Block 128 x 128 of C, four waves of 64 x 64 (4 x 4 MFMA tiles), K staged 16
+// at a time in LDS (A k-major, B as is), the next stage's global loads in
+// flight during the MFMAs.  Layouts: A 16x4, lane l holds A[l%16][l/16];
+// B 4x16, lane l holds B[l/16][l%16]; D 16x16, lane l holds D[4r + l/16][l%16].
+// Blocks are renumbered so that the ones sharing a column panel of B run on
+// the same XCD (blocks are dealt to the 8 XCDs round-robin).
+constexpr int GM = 128, GN = 128, GK = 16, GPAD = 16;
+
+__global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, int lda,
+                                                  const double* __restrict__ B, int ldb,
+                                                  double* __restrict__ C, int ldc, int M, int N,
+                                                  int K, int n_mt, int n_nt) {
+  __shared__ double sA[GK][GM + GPAD], sB[GK][GN + GPAD];
+  const int nblk = n_mt * n_nt, bid = blockIdx.x;
+  const int q = nblk / 8, r8 = nblk % 8, xcd = bid % 8;
+  const int lt = xcd * q + min(xcd, r8) + bid / 8;
+  const int m0 = (lt % n_mt) * GM, n0 = (lt / n_mt) * GN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const int wm = 32 * (w >> 1), wn = 32 * (w & 1);
+  const int wm = 64 * (w >> 1), wn = 64 * (w & 1);
   const int li = lane & 15, lk = lane >> 4;
-  f64x4 acc[2][2];
+  const int am = tid >> 1, ak = (tid & 1) * 8;   // A: row am, k ak..ak+7
+  const int bk = tid >> 4, bn = (tid & 15) * 8;  // B: k row bk, n bn..bn+7
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+    const int gm = m0 + am, gka = k0 + ak;
+    if (gm < M && gka + 8 <= K) {
+      const double2* p = reinterpret_cast<const double2*>(A + (size_t)gm * lda + gka);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+      for (int e = 0; e < 4; ++e) {
+        const double2 v = p[e];
+        ra[2 * e] = v.x;
+        ra[2 * e + 1] = v.y;
+      }
+    } else {
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+      for (int e = 0; e < 8; ++e) ra[e] = (gm < M && gka + e < K) ? A[(size_t)gm * lda + gka + e] : 0.0;
+    }
+    const int gkb = k0 + bk, gn = n0 + bn;
+    if (gkb < K && gn + 8 <= N) {
+      const double2* p = reinterpret_cast<const double2*>(B + (size_t)gkb * ldb + gn);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double2 v = p[e];
+        rb[2 * e] = v.x;
+        rb[2 * e + 1] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rb[e] = (gkb < K && gn + e < N) ? B[(size_t)gkb * ldb + gn + e] : 0.0;
+    }
+  };
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += GK) {
     __syncthreads();
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int m = e >> 4, kk = e & 15;  // A: consecutive threads along k
-      const int gm = m0 + m, gk = k0 + kk;
-      sA[kk][m] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : 0.0;
-      const int kb = e >> 6, n = e & 63;  // B: consecutive threads along n
-      const int gkb = k0 + kb, gn = n0 + n;
-      sB[kb][n] = (gkb < K && gn < N) ? B[(size_t)gkb * ldb + gn] : 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      sA[ak + e][am] = ra[e];
+      sB[bk][bn + e] = rb[e];
     }
     __syncthreads();
+    if (k0 + GK < K) load(k0 + GK);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
-      double a[2], b[2];
+    for (int kk = 0; kk < GK; kk += 4) {
+      double a[4], b[4];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t] = sA[kk + lk][wm + 16 * t + li];
-        b[t] = sB[kk + lk][wn + 16 * t + li];
+      for (int f = 0; f < 4; ++f) {
+        a[f] = sA[kk + lk][wm + 16 * f + li];
+        b[f] = sB[kk + lk][wn + 16 * f + li];
       }
 #pragma unroll
-      for (int ra = 0; ra < 2; ++ra)
+      for (int fa = 0; fa < 4; ++fa)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-          acc[ra][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ra], b[cb], acc[ra][cb], 0, 0, 0);
+        for (int fb = 0; fb < 4; ++fb)
+          acc[fa][fb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[fa], b[fb], acc[fa][fb], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int ra = 0; ra < 2; ++ra)
+  for (int fa = 0; fa < 4; ++fa)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int fb = 0; fb < 4; ++fb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + 16 * ra + 4 * r + lk, gn = n0 + wn + 16 * cb + li;
-        if (gm < M && gn < N) C[(size_t)gm * ldc + gn] = acc[ra][cb][r];
+        const int gm = m0 + wm + 16 * fa + 4 * r + lk, gn = n0 + wn + 16 * fb + li;
+        if (gm < M && gn < N) C[(size_t)gm * ldc + gn] = acc[fa][fb][r];
       }
 }
 
 }  // namespace
 
-void launch_kk_matrix(const double* w, int n_w, double eta, double d, int nr, int na, int b0r,
-                      int b0a, int n_cols, int m_p, double* Kt, hipStream_t st) {
-  const long total = (long)m_p * n_cols;
-  hipLaunchKernelGGL(k_kk_matrix, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, w, n_w,
-                     eta, d, nr, na, b0r, b0a, n_cols, m_p, Kt);
+void launch_kk_pack(const cplx* R, size_t ldt, int n_g, int n_gp, int n_t, const int* order,
+                    cplx* Rs, hipStream_t st) {
+  const long total = (long)n_t * n_gp;
+  hipLaunchKernelGGL(k_kk_pack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, R, ldt,
+                     n_g, n_gp, n_t, order, Rs);
 }
 
-void launch_gemm64(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int M,
-                   int N, int K, hipStream_t st) {
-  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
-  hipLaunchKernelGGL(k_gemm64, grid, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K);
+void launch_kk_bin(const cplx* Rs, int n_gp, int n_g, const int* ib, const double* xf,
+                   const KkChunk* chunks, int n_chunks, double* S, hipStream_t st) {
+  const int T = n_gp / kKkTile;
+  hipLaunchKernelGGL(k_kk_bin, dim3((unsigned)n_chunks, (unsigned)(T * (T + 1) / 2)), dim3(256), 0,
+                     st, Rs, n_gp, n_g, ib, xf, chunks, S);
+}
+
+void launch_kk_matrix(const double* w, int n_w, double eta, double d, int nr, int na, int br,
+                      int ba, int ldk, double* Kt, hipStream_t st) {
+  const long total = (long)2 * n_w * ldk;
+  hipLaunchKernelGGL(k_kk_matrix, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, w, n_w,
+                     eta, d, nr, na, br, ba, ldk, Kt);
+}
+
+void launch_gemm_f64(const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                     int M, int N, int K, hipStream_t st) {
+  const int n_mt = (M + GM - 1) / GM, n_nt = (N + GN - 1) / GN;
+  hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)(n_mt * n_nt)), dim3(256), 0, st, A, lda, B, ldb,
+                     C, ldc, M, N, K, n_mt, n_nt);
 }
 
 }  // namespace qcx

@@ -1,0 +1,41 @@
+// Kramers-Kronig route of Sec. II.D (internal launchers).
+//
+// The spectral part of Eq. (RPA) is binned on a uniform grid w_b = b d with
+// hat functions: a transition at energy D = (i + x) d (i = floor(D / d),
+// 0 <= x < 1) puts weight 1 - x on bin i and x on bin i + 1, so that
+//   S_b(G, G') = sum_t h_b(D_t) conj(R_t(G)) R_t(G')          (per side)
+// is a piecewise-linear spectral density carrying the zeroth and first
+// energy moments of every transition exactly.  The full response follows
+// from S by the exact transform of each hat piece through the energy
+// denominator (see k_kk.hip), one dense FP64 product over the bins.
+#pragma once
+
+#include "common.h"
+
+namespace qcx {
+
+// One run of consecutive bins [k0, k0 + nb) of one side, rows row0 + (0..nb)
+// of S, and the transitions [ta, tb) (energy order) whose hat functions reach
+// them: intervals k0 - 1 .. k0 + nb - 1.
+struct KkChunk {
+  int row0, k0, nb, ta, tb;
+};
+
+constexpr int kKkTile = 64;  // G and G' rows of one binning block
+
+// Rs[t'][n_gp] = R[G][order[t']] (zero for G >= n_g)
+void launch_kk_pack(const cplx* R, size_t ldt, int n_g, int n_gp, int n_t, const int* order,
+                    cplx* Rs, hipStream_t st);
+// S[row][2][n_pairs] (Re, Im) for every chunk and upper-triangle pair (G <= G')
+void launch_kk_bin(const cplx* Rs, int n_gp, int n_g, const int* ib, const double* xf,
+                   const KkChunk* chunks, int n_chunks, double* S, hipStream_t st);
+// Kt[2 n_w][ldk]: row 2j = Re, 2j + 1 = Im of the transform kernel of w_j for
+// bin column c: resonant bins c < nr at (br + c) d, anti-resonant bins
+// nr <= c < nr + na at (ba + c - nr) d, zero for nr + na <= c < ldk
+void launch_kk_matrix(const double* w, int n_w, double eta, double d, int nr, int na, int br,
+                      int ba, int ldk, double* Kt, hipStream_t st);
+// C[M][N] = A[M][K] B[K][N], row-major FP64 on MFMA; lda and ldb even
+void launch_gemm_f64(const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                     int M, int N, int K, hipStream_t st);
+
+}  // namespace qcx

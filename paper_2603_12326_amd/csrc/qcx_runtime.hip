@@ -17,6 +17,7 @@
 #include <chrono>
 
 #include "ctx.h"
+#include "kk.h"
 
 namespace {
 std::string g_create_err;
@@ -75,6 +76,11 @@ constexpr int kMaxKsplit = 64;
 // FP32 partial sums of one launch are kept within this budget; larger shapes
 // run in chunks of frequency rows, each reduced into FP64 partials
 constexpr size_t kPartialBudget = (size_t)8 << 30;
+// Kramers-Kronig route: bins per side, transitions per binning chunk, and the
+// largest binned spectral function S[bins][2][pairs] held in HBM
+constexpr int kKkMaxBins = 1 << 20;
+constexpr int kKkChunkT = 256;
+constexpr double kKkSpectralBudget = 16.0 * (1 << 30);
 // Accuracy: one K split sums at most this many K steps (16 transitions
 // each) in its FP32 accumulators; the splits are added in FP64
 constexpr int kMaxStepsPerSplit = 1024;
@@ -188,10 +194,10 @@ int qcx_bulk_config(qcx_ctx* ctx, int cfg[3], double* tune_ms) {
   return QCX_OK;
 }
 
-int qcx_stage_times(qcx_ctx* ctx, double t[6]) {
+int qcx_stage_times(qcx_ctx* ctx, double t[7]) {
   if (!ctx || !t) return QCX_EINVAL;
   HIPCK(spans_resolve(ctx));
-  for (int i = 0; i < 6; ++i) t[i] = ctx->t_acc[i];
+  for (int i = 0; i < 7; ++i) t[i] = ctx->t_acc[i];
   return QCX_OK;
 }
 
@@ -793,7 +799,7 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
   if (chi0_out) {
     AsmArgs a{};
     a.C = (g.n_bulk > 0 && !ctx->bulk_c64) ? ctx->d_C.as<float>() : nullptr;
-    a.C64 = (g.n_bulk > 0 && ctx->bulk_c64) ? ctx->d_C64.as<double>() : nullptr;
+  a.C64 = (g.n_bulk > 0 && ctx->bulk_c64) ? ctx->d_C64.as<double>() : nullptr;
     a.XY = ctx->n_pairs64 > 0 ? ctx->d_XY.as<double>() : nullptr;
     a.ks = g.ksplit;
     a.ks64 = ctx->ks64;
@@ -809,14 +815,12 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
 }
 
 int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double bin_eV,
-                int precision, int headwings_fp64, void* chi0_out) {
+                void* chi0_out) {
   if (!ctx) return QCX_EINVAL;
   if (!ctx->have_rho) return fail(ctx, QCX_ESTATE, "pair_density first");
   if (n_w < 1 || n_w > 65536 || !w_eV) return fail(ctx, QCX_EINVAL, "need 1 <= n_w <= 65536");
   if (!(eta_eV >= 0.0) || !std::isfinite(eta_eV)) return fail(ctx, QCX_EINVAL, "eta must be >= 0");
   if (!(bin_eV > 0.0) || !std::isfinite(bin_eV)) return fail(ctx, QCX_EINVAL, "bin width must be > 0");
-  if (precision != QCX_FP32 && precision != QCX_SPLIT_BF16)
-    return fail(ctx, QCX_EINVAL, "the binned route runs in FP32 or split-BF16");
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_chi0 = ctx->have_eps = false;
   hipStream_t st = ctx->stream;
@@ -826,177 +830,113 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
     w[i] = w_eV[i] / kHartreeEV;
   }
   const double d = bin_eV / kHartreeEV, eta = eta_eV / kHartreeEV;
-  const bool bf = precision == QCX_SPLIT_BF16;
-  const int n_t = ctx->n_t, n_half = n_t / 2;
-  // transition energies in energy order within each side
+  const int n_t = ctx->n_t, n_half = n_t / 2, n_g = ctx->n_g;
   std::vector<double> dt(n_t);
   HIPCK(hipMemcpyAsync(dt.data(), ctx->d_dt.p, sizeof(double) * n_t, hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
-  std::vector<int> order(n_t);
-  for (int t = 0; t < n_t; ++t) order[t] = t;
-  std::stable_sort(order.begin(), order.begin() + n_half, [&](int a, int b) { return dt[a] < dt[b]; });
-  std::stable_sort(order.begin() + n_half, order.end(), [&](int a, int b) { return dt[a] < dt[b]; });
-  std::vector<double> es(n_t);
-  std::vector<int> sd(n_t);
-  for (int t = 0; t < n_t; ++t) {
-    es[t] = dt[order[t]];
-    sd[t] = t < n_half ? 0 : 1;
-    if (!std::isfinite(es[t])) return fail(ctx, QCX_EINVAL, "non-finite transition energy");
-  }
-  // bins w_b = (b0 + b) d covering each side's energies with one bin to spare
-  auto bins = [&](int lo, int hi, int& b0, int& nb) {
-    b0 = (int)std::floor(es[lo] / d) - 1;
-    nb = (int)std::ceil(es[hi - 1] / d) + 1 - b0 + 1;
-  };
-  int b0r, nr, b0a, na;
-  bins(0, n_half, b0r, nr);
-  bins(n_half, n_t, b0a, na);
-  if ((double)nr + na > 262144.0) return fail(ctx, QCX_EINVAL, "too many bins: widen bin_eV");
 
-  Chi0Geom g{};
-  g.n_g = ctx->n_g;
-  g.n_t = n_t;
-  g.n_w = n_w;
-  g.n_rows = nr + na;
-  const int af = bulk_row_frags(g);
-  g.n_rowsp = (int)roundup(g.n_rows, 32 * af);
-  g.c_rows = g.n_rowsp;
-  g.n_tp = (int)roundup(n_t, KSTEP_T * kMaxKsplit);
-  g.n_pairs = ctx->n_g * (ctx->n_g + 1) / 2;
-  ctx->n_pairs64 = headwings_fp64 ? ctx->n_g : 0;
-  g.p0 = ctx->n_pairs64;
-  g.n_bulk = g.n_pairs - g.p0;
-  g.n_bulkp = (int)roundup(std::max(g.n_bulk, 1), 128);
-  // K-step range of every row tile: the transitions whose hat functions reach
-  // its bins
-  const int rows_t = 32 * af, n_tiles = g.n_rowsp / rows_t;
-  std::vector<int> kr(2 * n_tiles, 0);
-  int max_span = 1;
-  for (int r = 0; r < n_tiles; ++r) {
-    int lo = INT_MAX, hi = 0;
-    const int r0 = r * rows_t, r1 = std::min(g.n_rows, r0 + rows_t);
-    auto cover = [&](int row_lo, int row_hi, int b0, int t_lo, int t_hi) {  // rows of one side
-      if (row_lo >= row_hi) return;
-      const double e_lo = (b0 + row_lo) * d - d, e_hi = (b0 + row_hi - 1) * d + d;
-      const int a = (int)(std::lower_bound(es.begin() + t_lo, es.begin() + t_hi, e_lo) - es.begin());
-      const int b = (int)(std::upper_bound(es.begin() + t_lo, es.begin() + t_hi, e_hi) - es.begin());
-      if (a < b) {
-        lo = std::min(lo, a);
-        hi = std::max(hi, b);
-      }
-    };
-    cover(std::max(r0, 0), std::min(r1, nr), b0r, 0, n_half);
-    cover(std::max(r0, nr) - nr, std::max(std::min(r1, nr + na), nr) - nr, b0a, n_half, n_t);
-    if (lo < hi) {
-      kr[2 * r] = lo / KSTEP_T;
-      kr[2 * r + 1] = (hi + KSTEP_T - 1) / KSTEP_T;
-      max_span = std::max(max_span, kr[2 * r + 1] - kr[2 * r]);
+  // Per side: interval floor(D / d) of every transition relative to the
+  // side's lowest, a stable counting sort by interval, and the chunks.
+  std::vector<int> order(n_t), ib(n_t);
+  std::vector<double> xf(n_t);
+  std::vector<KkChunk> chunks;
+  int base[2] = {0, 0}, nbin[2] = {0, 0}, rows = 0;
+  for (int s = 0; s < 2; ++s) {
+    const int t_lo = s ? n_half : 0, t_hi = s ? n_t : n_half, cnt_t = t_hi - t_lo;
+    double umin = INFINITY, umax = -INFINITY;
+    for (int t = t_lo; t < t_hi; ++t) {
+      const double u = dt[t] / d;
+      if (!std::isfinite(u)) return fail(ctx, QCX_EINVAL, "non-finite transition energy");
+      umin = std::min(umin, u);
+      umax = std::max(umax, u);
     }
+    if (!(std::fabs(umin) < 1e9 && std::fabs(umax) < 1e9) ||
+        std::floor(umax) - std::floor(umin) + 2 > (double)kKkMaxBins)
+      return fail(ctx, QCX_EINVAL, "too many bins: widen bin_eV");
+    base[s] = (int)std::floor(umin);
+    const int n_int = (int)std::floor(umax) - base[s] + 1;
+    nbin[s] = n_int + 1;
+    std::vector<int> iv(cnt_t), off(n_int + 1, 0);
+    for (int t = 0; t < cnt_t; ++t) {
+      iv[t] = (int)std::floor(dt[t_lo + t] / d) - base[s];
+      ++off[iv[t] + 1];
+    }
+    for (int i = 0; i < n_int; ++i) off[i + 1] += off[i];
+    std::vector<int> pos(off.begin(), off.end() - 1);
+    for (int t = 0; t < cnt_t; ++t) {
+      const int k = t_lo + pos[iv[t]]++;
+      const double u = dt[t_lo + t] / d;
+      order[k] = t_lo + t;
+      ib[k] = iv[t];
+      xf[k] = u - std::floor(u);
+    }
+    // bins [k0, k1) take the transitions of intervals k0 - 1 .. k1 - 1
+    for (int k0 = 0; k0 < nbin[s];) {
+      const int a = std::max(k0 - 1, 0);
+      int k1 = k0 + 1;
+      while (k1 < nbin[s] && off[std::min(k1 + 1, n_int)] - off[a] <= kKkChunkT) ++k1;
+      chunks.push_back({rows + k0, k0, k1 - k0, t_lo + off[a], t_lo + off[std::min(k1, n_int)]});
+      k0 = k1;
+    }
+    rows += nbin[s];
   }
-  const int blocks = (g.n_bulkp / 128) * n_tiles;
-  g.ksplit = std::max(ksplit_for_accuracy(max_span), pick_ksplit(blocks, max_span));
-  const size_t nC = (size_t)g.ksplit * g.n_rowsp * 2 * g.n_bulkp;
-  if (nC * sizeof(float) > kPartialBudget) return fail(ctx, QCX_EINVAL, "binned partials exceed 8 GB: widen bin_eV");
+  const int n_gp = (int)roundup(n_g, kKkTile);
+  const size_t n_pairs = (size_t)n_g * (n_g + 1) / 2;
+  const int ldk = (int)roundup(rows, 2);
+  if ((double)rows * 2 * n_pairs * sizeof(double) > kKkSpectralBudget)
+    return fail(ctx, QCX_EINVAL, "binned spectral function exceeds 16 GB: widen bin_eV");
+  if (chunks.size() > (size_t)INT_MAX) return fail(ctx, QCX_EINVAL, "too many bins");
 
   HIPCK(stage_begin(ctx));
   HIPCK(upload(ctx, ctx->d_w, w.data(), w.size()));
   HIPCK(upload(ctx, ctx->d_kk_order, order.data(), order.size()));
-  HIPCK(upload(ctx, ctx->d_kk_es, es.data(), es.size()));
-  HIPCK(upload(ctx, ctx->d_kk_sd, sd.data(), sd.size()));
-  HIPCK(upload(ctx, ctx->d_kk_kr, kr.data(), kr.size()));
+  HIPCK(upload(ctx, ctx->d_kk_ib, ib.data(), ib.size()));
+  HIPCK(upload(ctx, ctx->d_kk_xf, xf.data(), xf.size()));
+  HIPCK(upload(ctx, ctx->d_kk_chunks, chunks.data(), chunks.size()));
+  HIPCK(ctx->d_kk_Rs.reserve(sizeof(cplx) * (size_t)n_t * n_gp));
+  HIPCK(ctx->d_kk_S.reserve(sizeof(double) * (size_t)rows * 2 * n_pairs));
+  HIPCK(ctx->d_kk_K.reserve(sizeof(double) * (size_t)2 * n_w * ldk));
+  HIPCK(ctx->d_C64.reserve(sizeof(double) * (size_t)2 * n_w * 2 * n_pairs));
   ctx->n_w = n_w;
   ctx->eta = eta;
-  ctx->prec = precision;
-  ctx->hw64 = headwings_fp64 ? 1 : 0;
-  int sp_all, sp_bulk = -1, sp_hw = -1;
+  ctx->prec = QCX_FP64;
+  ctx->hw64 = 0;
+  ctx->n_pairs64 = 0;
+  int sp_all, sp_bin, sp_tr;
   HIPCK(span_begin(ctx, 3, &sp_all));
-  if (g.n_bulk > 0) {
-    std::vector<int> pairs(g.n_bulkp, 0);
-    {
-      int b = 0, p = 0;
-      for (int G = 0; G < g.n_g; ++G)
-        for (int Gp = G; Gp < g.n_g; ++Gp, ++p)
-          if (p >= g.p0) pairs[b++] = G | (Gp << 16);
-    }
-    g.gather = g.n_g >= kGatherMinNg ? 1 : 0;
-    if (g.gather) {
-      std::vector<int> local, rows;
-      if (!bulk_gather_tables(pairs, local, rows))
-        return fail(ctx, QCX_EDEVICE, "internal: a pair tile needs more rows than staged");
-      HIPCK(upload(ctx, ctx->d_pairs, local.data(), local.size()));
-      HIPCK(upload(ctx, ctx->d_rows, rows.data(), rows.size()));
-    } else {
-      HIPCK(upload(ctx, ctx->d_pairs, pairs.data(), pairs.size()));
-    }
-    const int* rows_dev = g.gather ? ctx->d_rows.as<int>() : nullptr;
-    const size_t nA = (size_t)g.n_rowsp * g.n_tp;
-    HIPCK(ctx->d_R32.reserve(sizeof(float) * 2 * (size_t)g.n_g * g.n_tp));
-    HIPCK(ctx->d_C.reserve(sizeof(float) * nC));
-    HIPCK(ctx->d_kk_S.reserve(sizeof(double) * (size_t)g.n_rowsp * 2 * g.n_bulkp));
-    HIPCK(ctx->d_A.reserve((bf ? sizeof(uint16_t) : sizeof(float)) * nA));
-    if (bf) HIPCK(ctx->d_Alo.reserve(sizeof(uint16_t) * nA));
-    launch_pack_r32_order(ctx->d_R.as<cplx>(), ctx->ldt, g, bf ? 0 : 1, ctx->d_kk_order.as<int>(),
-                          ctx->d_R32.as<float>(), st);
-    launch_hat_weights(ctx->d_kk_es.as<double>(), ctx->d_kk_sd.as<int>(), nr, na, b0r, b0a, d, g, bf,
-                       ctx->d_A.p, bf ? ctx->d_Alo.p : nullptr, st);
-    LAUNCHCK("hat weights / pack");
-    g.kr = ctx->d_kk_kr.as<int>();
-    HIPCK(span_begin(ctx, 1, &sp_bulk));
-    if (bf)
-      launch_bulk_bf16(ctx->d_A.as<uint16_t>(), ctx->d_Alo.as<uint16_t>(), ctx->d_R32.as<float>(),
-                       ctx->d_pairs.as<int>(), rows_dev, g, 2, ctx->d_C.as<float>(), st);
-    else
-      launch_bulk_f32(ctx->d_A.as<float>(), ctx->d_R32.as<float>(), ctx->d_pairs.as<int>(), rows_dev,
-                      g, 2, ctx->d_C.as<float>(), st);
-    HIPCK(span_end(ctx, sp_bulk));
-    LAUNCHCK("bulk (binning)");
-    g.kr = nullptr;
-    launch_reduce_partials(ctx->d_C.as<float>(), g.ksplit, g.n_rowsp, g.n_bulkp,
-                           ctx->d_kk_S.as<double>(), st);
-    // transform: rows (Re, Im) per frequency x bins, times the bins x (Re P, Im P)
-    const int m = 2 * n_w, ncol = 2 * g.n_bulkp;
-    HIPCK(ctx->d_kk_K.reserve(sizeof(double) * (size_t)m * g.n_rowsp));
-    HIPCK(ctx->d_C64.reserve(sizeof(double) * (size_t)m * ncol));
-    launch_kk_matrix(ctx->d_w.as<double>(), n_w, eta, d, nr, na, b0r, b0a, g.n_rowsp, m,
-                     ctx->d_kk_K.as<double>(), st);
-    launch_gemm64(ctx->d_kk_K.as<double>(), g.n_rowsp, ctx->d_kk_S.as<double>(), ncol,
-                  ctx->d_C64.as<double>(), ncol, m, ncol, g.n_rowsp, st);
-    LAUNCHCK("transform");
-  }
-  if (ctx->n_pairs64 > 0) {
-    Geom64& g64 = ctx->geom64;
-    geom64_init(g64, ctx->n_g, n_w, ctx->n_t, ctx->n_pairs64, (size_t)512 << 20);
-    ctx->ks64 = g64.ksplit;
-    std::vector<int> tab(ctx->n_pairs64);
-    for (int p = 0; p < ctx->n_pairs64; ++p) tab[p] = 0 | (p << 16);
-    HIPCK(upload(ctx, ctx->d_pairs64, tab.data(), tab.size()));
-    HIPCK(ctx->d_XY.reserve(sizeof(double) * (size_t)g64.ksplit * g64.n_rowsp * g64.n_colp));
-    HIPCK(span_begin(ctx, 2, &sp_hw));
-    launch_pairs_f64(ctx->d_R.as<cplx>(), ctx->ldt, ctx->d_w.as<double>(), ctx->d_dt.as<double>(),
-                     eta, g64, ctx->d_pairs64.as<int>(), ctx->d_XY.as<double>(), st);
-    LAUNCHCK("pairs_f64");
-    HIPCK(span_end(ctx, sp_hw));
-  }
+  launch_kk_pack(ctx->d_R.as<cplx>(), ctx->ldt, n_g, n_gp, n_t, ctx->d_kk_order.as<int>(),
+                 ctx->d_kk_Rs.as<cplx>(), st);
+  HIPCK(span_begin(ctx, 1, &sp_bin));
+  launch_kk_bin(ctx->d_kk_Rs.as<cplx>(), n_gp, n_g, ctx->d_kk_ib.as<int>(), ctx->d_kk_xf.as<double>(),
+                ctx->d_kk_chunks.as<KkChunk>(), (int)chunks.size(), ctx->d_kk_S.as<double>(), st);
+  HIPCK(span_end(ctx, sp_bin));
+  LAUNCHCK("kk binning");
+  launch_kk_matrix(ctx->d_w.as<double>(), n_w, eta, d, nbin[0], nbin[1], base[0], base[1], ldk,
+                   ctx->d_kk_K.as<double>(), st);
+  HIPCK(span_begin(ctx, 6, &sp_tr));
+  launch_gemm_f64(ctx->d_kk_K.as<double>(), ldk, ctx->d_kk_S.as<double>(), (int)(2 * n_pairs),
+                  ctx->d_C64.as<double>(), (int)(2 * n_pairs), 2 * n_w, (int)(2 * n_pairs), rows, st);
+  HIPCK(span_end(ctx, sp_tr));
+  LAUNCHCK("kk transform");
   HIPCK(span_end(ctx, sp_all));
-  // what the assembly reads: one FP64 partial of 2 n_w rows per pair
-  Chi0Geom ga = g;
-  ga.n_rows = 2 * n_w;
-  ga.n_rowsp = 2 * n_w;
-  ga.c_rows = 2 * n_w;
+  // what the assembly reads: one FP64 value of 2 n_w rows (Re K, Im K) x
+  // (Re S, Im S) per pair
+  Chi0Geom ga{};
+  ga.n_g = n_g;
+  ga.n_t = n_t;
+  ga.n_w = n_w;
+  ga.n_rows = ga.n_rowsp = ga.c_rows = 2 * n_w;
+  ga.n_pairs = (int)n_pairs;
+  ga.p0 = 0;
+  ga.n_bulk = ga.n_bulkp = (int)n_pairs;
   ga.ksplit = 1;
-  ga.kr = nullptr;
   ctx->geom = ga;
   ctx->bulk_c64 = true;
   ctx->have_chi0 = true;
   if (chi0_out) {
     AsmArgs a{};
-    a.C64 = g.n_bulk > 0 ? ctx->d_C64.as<double>() : nullptr;
-    a.XY = ctx->n_pairs64 > 0 ? ctx->d_XY.as<double>() : nullptr;
+    a.C64 = ctx->d_C64.as<double>();
     a.ks = 1;
-    a.ks64 = ctx->ks64;
-    a.n_rowsp64 = ctx->geom64.n_rowsp;
-    a.n_colp64 = ctx->geom64.n_colp;
-    a.n_pairs64 = ctx->n_pairs64;
     a.vq = ctx->d_vq.as<double>();
     a.pref = 2.0 / (ctx->n_k * ctx->vol);
     launch_chi0_export(a, ga, static_cast<cplx*>(chi0_out), st);
@@ -1024,7 +964,7 @@ int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out) {
   HIPCK(span_begin(ctx, 4, &sp_eps));
   AsmArgs a{};
   a.C = (g.n_bulk > 0 && !ctx->bulk_c64) ? ctx->d_C.as<float>() : nullptr;
-    a.C64 = (g.n_bulk > 0 && ctx->bulk_c64) ? ctx->d_C64.as<double>() : nullptr;
+  a.C64 = (g.n_bulk > 0 && ctx->bulk_c64) ? ctx->d_C64.as<double>() : nullptr;
   a.XY = ctx->n_pairs64 > 0 ? ctx->d_XY.as<double>() : nullptr;
   a.ks = g.ksplit;
   a.ks64 = ctx->ks64;

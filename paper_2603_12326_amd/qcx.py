@@ -62,7 +62,7 @@ _SIGS = {
     "qcx_batch_sync": [_P],
     "qcx_batch_config": [_P, _P, _P],
     "qcx_loss_diag": [_P, _I, _P, _I, _P, _D, _I, _P],
-    "qcx_chi0_kk": [_P, _I, _P, _D, _D, _I, _I, _P],
+    "qcx_chi0_kk": [_P, _I, _P, _D, _D, _P],
     "qcx_mlp_create": [ctypes.POINTER(_P), _P, _I],
     "qcx_mlp_destroy": [_P],
     "qcx_mlp_set_params": [_P, _I, _P],
@@ -231,18 +231,14 @@ class Context:
                                       1 if headwings_fp64 else 0, out))
         self.n_w = len(w)
 
-    def chi0_kk(self, w_eV, eta_eV: float, bin_eV: float, precision=SPLIT_BF16,
-                headwings_fp64: bool = False, chi0_out=None):
-        """chi0 from the binned spectral part (qcx_chi0_kk)."""
-        if isinstance(precision, str):
-            precision = PRECISIONS[precision]
+    def chi0_kk(self, w_eV, eta_eV: float, bin_eV: float, chi0_out=None):
+        """chi0 from the binned spectral part, all FP64 (qcx_chi0_kk)."""
         w = _host(w_eV, np.float64).reshape(-1)
         out = None
         if chi0_out is not None:
             out = _dev_ptr(chi0_out, "c128", len(w) * self.n_g * self.n_g, "chi0_out")
         self._check(self.lib.qcx_chi0_kk(self._h, len(w), _ptr_host(w), float(eta_eV),
-                                         float(bin_eV), int(precision),
-                                         1 if headwings_fp64 else 0, out))
+                                         float(bin_eV), out))
         self.n_w = len(w)
 
     def eps_inv(self, lfe: bool = True, diag_out=None, epsM_out=None):
@@ -301,10 +297,11 @@ class Context:
                     tune_ms=ms.value)
 
     def stage_times(self) -> dict:
-        t = np.zeros(6, np.float64)
+        t = np.zeros(7, np.float64)
         self._check(self.lib.qcx_stage_times(self._h, _ptr_host(t)))
         return dict(pair_density_ms=t[0], chi0_bulk_ms=t[1], chi0_headwings_ms=t[2],
-                    chi0_total_ms=t[3], eps_inv_ms=t[4], bulk_launches=int(t[5]))
+                    chi0_total_ms=t[3], eps_inv_ms=t[4], bulk_launches=int(t[5]),
+                    kk_transform_ms=t[6])
 
 
 def run_batch(contexts, items, precision=SPLIT_BF16, headwings_fp64: bool = True,

@@ -299,6 +299,17 @@ def test_hat_kernel_against_quadrature():
         assert abs(up.imag - spec) < 1e-12 and abs(dn.imag + spec) < 1e-12
 
 
+def test_hat_kernel_far_field_series():
+    """Far from the hat, 1/(z - y) = sum_m y^m / z^(m+1) integrates term by
+    term to I(z) = sum_n 2 / ((2n+1)(2n+2)) z^-(2n+1); the closed form must
+    keep that to near working precision where its three terms nearly cancel."""
+    for z in (12.0 + 0.2j, -40.0 + 1.0j, 500.0 + 0.3j, -1800.0 - 0.05j, 3000.0 + 0.0j):
+        n = np.arange(12)
+        ser = np.sum(2.0 / ((2 * n + 1) * (2 * n + 2)) * complex(z) ** (-(2 * n + 1)))
+        got = rpa.hat_kernel(np.array([z]))[0]
+        assert abs(got - ser) < 1e-11 * abs(ser), (z, got, ser)
+
+
 def test_spectral_bins_partition_of_unity():
     E = np.random.default_rng(1).uniform(0.05, 0.9, 500)
     c, H = rpa.spectral_bins(E, 0.3)
