@@ -519,7 +519,7 @@ def main_kk(args):
         "roofline": {"bound": "mfma", "achieved": gemm_flops / gemm_s / 1e12,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": gemm_flops / gemm_s / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "k_gemm_f64 (transform, [2 n_w][bins] x [bins][2 n_pairs])",
+                     "kernel": "rocblas_dgemm (transform, [2 n_w][bins] x [bins][2 n_pairs])",
                      "avg_launch_ms": 1e3 * gemm_s, "flops_per_launch": gemm_flops},
         "binning_roofline": {"bound": "alu", "achieved": bin_flops / bin_s / 1e12,
                              "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",

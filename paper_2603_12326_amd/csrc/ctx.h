@@ -13,6 +13,8 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "common.h"
 
 using namespace qcx;
@@ -75,6 +77,16 @@ struct qcx_ctx {
   void* stage = nullptr;
   size_t stage_cap = 0, stage_off = 0;
   hipEvent_t stage_done = nullptr;
+  // transition energies copied to pinned host memory right after
+  // qcx_set_states computes them, once the Kramers-Kronig route has been
+  // used (its host-side sort then overlaps the pair densities on the device)
+  // rocBLAS handle for the plain FP64 product of the Kramers-Kronig route
+  // (created on first use, bound to the context's stream)
+  rocblas_handle blas = nullptr;
+  double* h_dt = nullptr;
+  size_t h_dt_cap = 0;
+  hipEvent_t ev_dt = nullptr;
+  bool dt_prefetch = false, dt_valid = false, dt_pending = false;
   bool stage_pending = false;
 
   // timing: event pairs recorded on the stream without synchronising,
@@ -107,6 +119,10 @@ struct qcx_ctx {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (stage_done) (void)hipEventDestroy(stage_done);
     if (stage) (void)hipHostFree(stage);
+    if (dt_pending && ev_dt) (void)hipEventSynchronize(ev_dt);
+    if (h_dt) (void)hipHostFree(h_dt);
+    if (blas) (void)rocblas_destroy_handle(blas);
+    if (ev_dt) (void)hipEventDestroy(ev_dt);
   }
 };
 
@@ -187,6 +203,31 @@ inline hipError_t upload(qcx_ctx* c, DevBuf& b, const T* src, size_t n, bool dev
   e = hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(c->stream);
+}
+
+// Queue a copy of the transition energies (d_dt, n_t values) to h_dt on the
+// stream and record ev_dt after it.
+inline hipError_t dt_to_host(qcx_ctx* c, int n_t) {
+  hipError_t e = hipSuccess;
+  if (!c->ev_dt && (e = hipEventCreateWithFlags(&c->ev_dt, hipEventDisableTiming)) != hipSuccess)
+    return e;
+  if (c->h_dt_cap < (size_t)n_t) {
+    if (c->dt_pending && (e = hipEventSynchronize(c->ev_dt)) != hipSuccess) return e;
+    c->dt_pending = false;
+    if (c->h_dt) (void)hipHostFree(c->h_dt);
+    c->h_dt = nullptr;
+    c->h_dt_cap = 0;
+    if ((e = hipHostMalloc((void**)&c->h_dt, sizeof(double) * n_t)) != hipSuccess) {
+      c->h_dt = nullptr;
+      return e;
+    }
+    c->h_dt_cap = n_t;
+  }
+  e = hipMemcpyAsync(c->h_dt, c->d_dt.p, sizeof(double) * n_t, hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(c->ev_dt, c->stream)) != hipSuccess) return e;
+  c->dt_pending = true;
+  return hipSuccess;
 }
 
 inline void inv3(const double m[9], double out[9]) {

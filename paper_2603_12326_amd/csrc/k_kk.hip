@@ -13,14 +13,13 @@
 // between the three logarithms.
 //
 // Binning is a sparse accumulation (two bins per transition), done on the
-// FP64 vector units; the transform is a dense FP64 product on MFMA.
+// FP64 vector units; the transform is a plain dense FP64 product, left to
+// rocBLAS (qcx_chi0_kk).
 #include "kk.h"
 
 namespace qcx {
 
 namespace {
-
-typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ packing
 __global__ void k_kk_pack(const cplx* __restrict__ R, size_t ldt, int n_g, int n_gp, int n_t,
@@ -220,99 +219,6 @@ __global__ void k_kk_matrix(const double* __restrict__ w, int n_w, double eta, d
   Kt[i] = v;
 }
 
-// C[M][N] = A[M][K] B[K][N] (row-major FP64) on v_mfma_f64_16x16x4f64.
-// Block 128 x 128 of C, four waves of 64 x 64 (4 x 4 MFMA tiles), K staged 16
-// at a time in LDS (A k-major, B as is), the next stage's global loads in
-// flight during the MFMAs.  Layouts: A 16x4, lane l holds A[l%16][l/16];
-// B 4x16, lane l holds B[l/16][l%16]; D 16x16, lane l holds D[4r + l/16][l%16].
-// Blocks are renumbered so that the ones sharing a column panel of B run on
-// the same XCD (blocks are dealt to the 8 XCDs round-robin).
-constexpr int GM = 128, GN = 128, GK = 16, GPAD = 16;
-
-__global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, int lda,
-                                                  const double* __restrict__ B, int ldb,
-                                                  double* __restrict__ C, int ldc, int M, int N,
-                                                  int K, int n_mt, int n_nt) {
-  __shared__ double sA[GK][GM + GPAD], sB[GK][GN + GPAD];
-  const int nblk = n_mt * n_nt, bid = blockIdx.x;
-  const int q = nblk / 8, r8 = nblk % 8, xcd = bid % 8;
-  const int lt = xcd * q + min(xcd, r8) + bid / 8;
-  const int m0 = (lt % n_mt) * GM, n0 = (lt / n_mt) * GN;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = 64 * (w >> 1), wn = 64 * (w & 1);
-  const int li = lane & 15, lk = lane >> 4;
-  const int am = tid >> 1, ak = (tid & 1) * 8;   // A: row am, k ak..ak+7
-  const int bk = tid >> 4, bn = (tid & 15) * 8;  // B: k row bk, n bn..bn+7
-  double ra[8], rb[8];
-  auto load = [&](int k0) {
-    const int gm = m0 + am, gka = k0 + ak;
-    if (gm < M && gka + 8 <= K) {
-      const double2* p = reinterpret_cast<const double2*>(A + (size_t)gm * lda + gka);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const double2 v = p[e];
-        ra[2 * e] = v.x;
-        ra[2 * e + 1] = v.y;
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) ra[e] = (gm < M && gka + e < K) ? A[(size_t)gm * lda + gka + e] : 0.0;
-    }
-    const int gkb = k0 + bk, gn = n0 + bn;
-    if (gkb < K && gn + 8 <= N) {
-      const double2* p = reinterpret_cast<const double2*>(B + (size_t)gkb * ldb + gn);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const double2 v = p[e];
-        rb[2 * e] = v.x;
-        rb[2 * e + 1] = v.y;
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) rb[e] = (gkb < K && gn + e < N) ? B[(size_t)gkb * ldb + gn + e] : 0.0;
-    }
-  };
-  f64x4 acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  load(0);
-  for (int k0 = 0; k0 < K; k0 += GK) {
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      sA[ak + e][am] = ra[e];
-      sB[bk][bn + e] = rb[e];
-    }
-    __syncthreads();
-    if (k0 + GK < K) load(k0 + GK);
-#pragma unroll
-    for (int kk = 0; kk < GK; kk += 4) {
-      double a[4], b[4];
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        a[f] = sA[kk + lk][wm + 16 * f + li];
-        b[f] = sB[kk + lk][wn + 16 * f + li];
-      }
-#pragma unroll
-      for (int fa = 0; fa < 4; ++fa)
-#pragma unroll
-        for (int fb = 0; fb < 4; ++fb)
-          acc[fa][fb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[fa], b[fb], acc[fa][fb], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int fa = 0; fa < 4; ++fa)
-#pragma unroll
-    for (int fb = 0; fb < 4; ++fb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + 16 * fa + 4 * r + lk, gn = n0 + wn + 16 * fb + li;
-        if (gm < M && gn < N) C[(size_t)gm * ldc + gn] = acc[fa][fb][r];
-      }
-}
-
 }  // namespace
 
 void launch_kk_pack(const cplx* R, size_t ldt, int n_g, int n_gp, int n_t, const int* order,
@@ -334,13 +240,6 @@ void launch_kk_matrix(const double* w, int n_w, double eta, double d, int nr, in
   const long total = (long)2 * n_w * ldk;
   hipLaunchKernelGGL(k_kk_matrix, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, w, n_w,
                      eta, d, nr, na, br, ba, ldk, Kt);
-}
-
-void launch_gemm_f64(const double* A, int lda, const double* B, int ldb, double* C, int ldc,
-                     int M, int N, int K, hipStream_t st) {
-  const int n_mt = (M + GM - 1) / GM, n_nt = (N + GN - 1) / GN;
-  hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)(n_mt * n_nt)), dim3(256), 0, st, A, lda, B, ldb,
-                     C, ldc, M, N, K, n_mt, n_nt);
 }
 
 }  // namespace qcx

@@ -7,7 +7,8 @@
 // is a piecewise-linear spectral density carrying the zeroth and first
 // energy moments of every transition exactly.  The full response follows
 // from S by the exact transform of each hat piece through the energy
-// denominator (see k_kk.hip), one dense FP64 product over the bins.
+// denominator (see k_kk.hip), one dense FP64 product over the bins
+// (rocBLAS dgemm).
 #pragma once
 
 #include "common.h"
@@ -34,8 +35,5 @@ void launch_kk_bin(const cplx* Rs, int n_gp, int n_g, const int* ib, const doubl
 // nr <= c < nr + na at (ba + c - nr) d, zero for nr + na <= c < ldk
 void launch_kk_matrix(const double* w, int n_w, double eta, double d, int nr, int na, int br,
                       int ba, int ldk, double* Kt, hipStream_t st);
-// C[M][N] = A[M][K] B[K][N], row-major FP64 on MFMA; lda and ldb even
-void launch_gemm_f64(const double* A, int lda, const double* B, int ldb, double* C, int ldc,
-                     int M, int N, int K, hipStream_t st);
 
 }  // namespace qcx

@@ -376,6 +376,11 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
   launch_transition_energies(ctx->d_Ek.as<double>(), ctx->d_Ekq.as<double>(), n_k, n_bands, n_occ,
                              ctx->d_dt.as<double>(), st);
   LAUNCHCK("transition_energies");
+  ctx->dt_valid = false;
+  if (ctx->dt_prefetch) {
+    HIPCK(dt_to_host(ctx, (int)n_t));
+    ctx->dt_valid = true;
+  }
   if (dev) {
     if (!ctx->d_flags.p) {
       HIPCK(ctx->d_flags.reserve(2 * sizeof(int)));
@@ -831,9 +836,15 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
   }
   const double d = bin_eV / kHartreeEV, eta = eta_eV / kHartreeEV;
   const int n_t = ctx->n_t, n_half = n_t / 2, n_g = ctx->n_g;
-  std::vector<double> dt(n_t);
-  HIPCK(hipMemcpyAsync(dt.data(), ctx->d_dt.p, sizeof(double) * n_t, hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
+  // transition energies on the host: queued by qcx_set_states once this route
+  // has run (so the wait below ends before the pair densities do), else now
+  if (!ctx->dt_valid) {
+    HIPCK(dt_to_host(ctx, n_t));
+    ctx->dt_prefetch = ctx->dt_valid = true;
+  }
+  HIPCK(hipEventSynchronize(ctx->ev_dt));
+  ctx->dt_pending = false;
+  const double* dt = ctx->h_dt;
 
   // Per side: interval floor(D / d) of every transition relative to the
   // side's lowest, a stable counting sort by interval, and the chunks.
@@ -913,10 +924,24 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
   LAUNCHCK("kk binning");
   launch_kk_matrix(ctx->d_w.as<double>(), n_w, eta, d, nbin[0], nbin[1], base[0], base[1], ldk,
                    ctx->d_kk_K.as<double>(), st);
+  // C64[2 n_w][2 n_pairs] = Kt[2 n_w][rows] S[rows][2 n_pairs], row-major:
+  // the column-major product C64^T = S^T Kt^T
+  if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
+    ctx->blas = nullptr;
+    return fail(ctx, QCX_EDEVICE, "rocblas_create_handle failed");
+  }
+  if (rocblas_set_stream(ctx->blas, st) != rocblas_status_success)
+    return fail(ctx, QCX_EDEVICE, "rocblas_set_stream failed");
+  const double one = 1.0, zero = 0.0;
+  const int nc = (int)(2 * n_pairs);
   HIPCK(span_begin(ctx, 6, &sp_tr));
-  launch_gemm_f64(ctx->d_kk_K.as<double>(), ldk, ctx->d_kk_S.as<double>(), (int)(2 * n_pairs),
-                  ctx->d_C64.as<double>(), (int)(2 * n_pairs), 2 * n_w, (int)(2 * n_pairs), rows, st);
+  const rocblas_status bs = rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none,
+                                          nc, 2 * n_w, rows, &one, ctx->d_kk_S.as<double>(), nc,
+                                          ctx->d_kk_K.as<double>(), ldk, &zero,
+                                          ctx->d_C64.as<double>(), nc);
   HIPCK(span_end(ctx, sp_tr));
+  if (bs != rocblas_status_success)
+    return fail(ctx, QCX_EDEVICE, "rocblas_dgemm failed (status " + std::to_string((int)bs) + ")");
   LAUNCHCK("kk transform");
   HIPCK(span_end(ctx, sp_all));
   // what the assembly reads: one FP64 value of 2 n_w rows (Re K, Im K) x
