@@ -225,11 +225,13 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
  *              q + G may vanish; G = 0 is not required
  *   n_w, w_eV, eta_eV, precision as for qcx_chi0
  *   loss_out   device [n_w][n_G] float64
+ *   inv_out    NULL or device [n_w][n_G] c128 receiving 1 / eps_GG (the
+ *              value qcx_qbin_add bins with kind QCX_QBIN_INV)
  * Asynchronous.  Replaces the context's pair densities (qcx_pair_density
  * must be called again before qcx_chi0).
  * Errors: QCX_ESTATE (no states), QCX_EINVAL, QCX_ENOMEM. */
 int qcx_loss_diag(qcx_ctx* ctx, int n_G, const int* G_int, int n_w, const double* w_eV,
-                  double eta_eV, int precision, double* loss_out);
+                  double eta_eV, int precision, double* loss_out, void* inv_out);
 
 /* One item of a batch: the frequencies of one context's q point. */
 typedef struct qcx_item {
@@ -336,6 +338,87 @@ int qcx_mlp_encode(qcx_mlp* m, int n, const double* qw, const double* loss, floa
  * rejecting, otherwise asynchronous. */
 int qcx_mlp_query(qcx_mlp* m, int n, const double* qw, double* loss, double* err, double tol,
                   int* reject_idx, int* n_reject);
+
+/* ------------------------------------------------------------------------
+ * From the dielectric function to scattering rates (Sec. III binning, Eq.
+ * dynamic_structure_factor, Eq. general_rate with the nonrelativistic cross
+ * section of Eq. cross_section).
+ *
+ * A qcx_qbin accumulates the finite-momentum dielectric function
+ * eps(w, q + G) of any number of (q, G) entries into a three-dimensional
+ * momentum grid: n_shell spherical shells of width dq (bohr^-1 = alpha m_e;
+ * shell s holds s dq <= |q| < (s + 1) dq), each split into n_theta x n_phi
+ * angular bins uniform in theta = acos(q_z / |q|) on [0, pi] and in
+ * phi = atan2(q_y, q_x) on [0, 2 pi); bin (s, i, j) has index
+ * (s n_theta + i) n_phi + j.  The paper uses n_theta = 9, n_phi = 16,
+ * dq = 0.02.  A bin's value is the mean of the complex eps of its entries.
+ * Work runs on the context's device and stream; errors are reported through
+ * qcx_last_error of that context.
+ * ------------------------------------------------------------------------ */
+typedef struct qcx_qbin qcx_qbin;
+enum { QCX_QBIN_EPS = 0, QCX_QBIN_INV = 1 };
+
+/* Empty table for n_w frequencies (1..65536), n_shell >= 1, dq > 0,
+ * 1 <= n_theta <= 360, 1 <= n_phi <= 720, at most 2^26 bins and 32 GB
+ * (n_w x bins x 16 bytes of device memory).  Errors: QCX_EINVAL, QCX_ENOMEM. */
+int qcx_qbin_create(qcx_qbin** out, qcx_ctx* ctx, int n_w, int n_shell, double dq, int n_theta,
+                    int n_phi);
+/* Free the table (synchronises the stream).  Safe on NULL. */
+int qcx_qbin_destroy(qcx_qbin* b);
+/* Forget every entry. */
+int qcx_qbin_reset(qcx_qbin* b);
+/* Add n entries: momenta qvec[n][3] (host, Cartesian, bohr^-1) and values
+ * vals (device c128, vals[w * ld + e], ld >= n): eps itself
+ * (kind = QCX_QBIN_EPS) or 1/eps (kind = QCX_QBIN_INV: [eps^-1]_GG of
+ * qcx_eps_inv's diag_out, or inv_out of qcx_loss_diag).  Entries with
+ * |q| >= n_shell dq are skipped.  The bins of the entries are found on the
+ * host; the sums run on the device, deterministically.  Asynchronous
+ * (vals must stay valid until the stream reaches the call).
+ * Errors: QCX_EINVAL (sizes, kind, non-finite momenta). */
+int qcx_qbin_add(qcx_qbin* b, int n, const double* qvec, const void* vals, int ld, int kind);
+/* Bin means, interpolation of bins without entries, and the isotropic
+ * dynamic structure factor.  Interpolation runs in sweeps: every empty bin
+ * with at least one filled neighbour among its 26 adjacent bins (phi
+ * periodic; shell and theta not) takes the mean of those neighbours, using
+ * only bins filled before the sweep, until no bin changes.  Then
+ *   S_out[w][s] = solid-angle weighted mean over the filled bins of shell s
+ *                 of q_s^2 / (2 pi alpha) Im(-1 / eps),  q_s = (s + 1/2) dq
+ * in (alpha m_e)^2 (NaN for a shell no sweep reaches).
+ *   eps_out    NULL or device [n_w][bins] c128 (the binned eps)
+ *   S_out      device [n_w][n_shell] float64
+ *   state_out  NULL or host [bins]: 1 entries, 2 interpolated, 0 empty
+ * The table keeps its entries (more may be added and finish called again).
+ * Errors: QCX_EINVAL, QCX_ENOMEM. */
+int qcx_qbin_finish(qcx_qbin* b, void* eps_out, double* S_out, int* state_out);
+
+/* Dark-matter halo and interaction for qcx_qbin_rate_halo: the standard
+ * truncated Maxwell-Boltzmann halo (Galactic dispersion v0, escape speed
+ * vesc, Earth speed vE, local density rho_chi) and a mediator of mass m_med
+ * (F_DM(q) = ((alpha m_e)^2 + m_med^2) / (q^2 + m_med^2), Eq. F_DM;
+ * m_med = INFINITY: heavy limit F_DM = 1; m_med = 0: light limit). */
+typedef struct qcx_halo {
+  double m_chi_eV;         /* dark-matter mass */
+  double m_med_eV;         /* mediator mass, >= 0 or INFINITY */
+  double sigma_e_cm2;      /* reference cross section */
+  double rho_T_g_cm3;      /* target mass density */
+  double rho_chi_GeV_cm3;  /* 0.3 in the paper */
+  double v0_kms;           /* 238 */
+  double vE_kms;           /* 250.2 in the paper */
+  double vesc_kms;         /* 544 in the paper */
+} qcx_halo;
+
+/* Halo scattering rate per unit target mass (events / kg / year / eV) at
+ * the n_w frequencies w_eV (host, >= 0) of the table, from S_iso (device
+ * [n_w][n_shell], qcx_qbin_finish's S_out):
+ *   dR/dw = rho_chi / (m_chi rho_T) sigma_e / (4 pi mu^2)
+ *           sum_s dq q_s |F_DM(q_s)|^2 S(w, q_s) eta(v_min(q_s, w)),
+ * v_min = q / (2 m_chi) + w / q, eta(v) = int d^3u f(u) / |u| over |u| > v
+ * (the halo's mean inverse speed, closed form), mu the DM-electron reduced
+ * mass; shells where S is NaN contribute nothing.  Natural units inside;
+ * CODATA 2018 constants, year = 365.25 days.  rate_out: device [n_w].
+ * Asynchronous.  Errors: QCX_EINVAL (non-positive parameters). */
+int qcx_qbin_rate_halo(qcx_qbin* b, const double* w_eV, const double* S_iso, const qcx_halo* h,
+                       double* rate_out);
 
 /* Tile selection of the chi0 bulk kernel (qcx_chi0 with FP32 or split-BF16).
  * mode 1 (default): on the first qcx_chi0 of each shape (device, precision,

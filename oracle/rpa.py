@@ -21,9 +21,11 @@ Readings of points the paper leaves open (each also listed in the design doc):
   1 Ha = 27.211386245988 eV.
 * The k sum carries the weight 1/N_k (crystal volume N_k V), the standard
   Adler-Wiser normalisation, so chi0 does not grow with the k grid.
-* Finite eta, evaluated as written (no limit, no Kramers-Kronig): the
-  time-ordered prescription, +i eta on the resonant (v -> c) term and
-  -i eta on the anti-resonant (c -> v) term.
+* Finite eta, evaluated as written by chi0(): the time-ordered
+  prescription, +i eta on the resonant (v -> c) term and -i eta on the
+  anti-resonant (c -> v) term.  chi0_kk() is the binned spectral route of
+  Sec. II.D (hat-function bins, exact transform; at eta = 0 the
+  Kramers-Kronig form).
 * Synthetic states are not time-reversal symmetric, so the anti-resonant
   pair density sigma_vck(Q) = <v,k+q|e^{iQr}|c,k> is kept explicitly.
 * The row index G carries the complex conjugate.
@@ -168,17 +170,24 @@ def chi0_diagonal(R: np.ndarray, W: np.ndarray) -> np.ndarray:
     return W @ (np.abs(Rt) ** 2)
 
 
-def loss_diag(cell, basis, lattice_range, k_frac, n_occ, G_int, states, w_eV, eta_eV):
-    """noLFE loss for any G list (Eq. eps_noLFE; no G = 0 needed):
-    Im(-1 / eps_GG) with eps_GG = 1 - 4 pi chi0_GG / |q + G|^2.
-    Parity: equals loss_nolfe() of the full path on the same G."""
+def eps_diag(cell, basis, lattice_range, k_frac, n_occ, G_int, states, w_eV, eta_eV):
+    """eps_GG = 1 - 4 pi chi0_GG / |q + G|^2 for any G list (Eq. eps_noLFE's
+    diagonal; no G = 0 needed), complex [n_w][n_G]."""
     R = pair_densities_from_workload(cell, basis, lattice_range, k_frac, states.q_cart, G_int,
                                      states.C_k, states.C_kq, n_occ)
     volume = abs(float(np.linalg.det(np.asarray(cell.lat, np.float64))))
     W = transition_weights(states.E_k, states.E_kq, n_occ, w_eV, eta_eV, volume)
     chi = chi0_diagonal(R, W)
     v = coulomb_sqrt(q_plus_g(cell.lat, states.q_cart, G_int))
-    return np.imag(-1.0 / (1.0 - (v * v)[None, :] * chi))
+    return 1.0 - (v * v)[None, :] * chi
+
+
+def loss_diag(cell, basis, lattice_range, k_frac, n_occ, G_int, states, w_eV, eta_eV):
+    """noLFE loss for any G list (Eq. eps_noLFE; no G = 0 needed):
+    Im(-1 / eps_GG) with eps_GG = 1 - 4 pi chi0_GG / |q + G|^2.
+    Parity: equals loss_nolfe() of the full path on the same G."""
+    return np.imag(-1.0 / eps_diag(cell, basis, lattice_range, k_frac, n_occ, G_int, states, w_eV,
+                                   eta_eV))
 
 
 def composite_split(lat, q_cart, G_int, q_lfe: float):

@@ -12,6 +12,7 @@ from .qcx import (  # noqa: F401
     SPLIT_BF16,
     Context,
     Mlp,
+    QBins,
     QcxError,
     batch_sync,
     run_batch,

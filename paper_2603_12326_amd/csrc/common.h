@@ -172,8 +172,10 @@ void launch_eps_assemble(const AsmArgs& a, const Chi0Geom& g, cplx* eps, hipStre
 void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st);
 // noLFE loss from diagonal-only partials of n_g G (chunk columns 0..n_g-1)
 // into loss[j * ldl + g0 + b]
-void launch_diag_loss(const AsmArgs& a, const Chi0Geom& g, int n_g, int n_w, double* loss, int ldl,
-                      int g0, hipStream_t st);
+// loss[w][g0 + b] (and, if inv is not null, inv[w][g0 + b] = 1 / eps_GG) for
+// the n_g diagonal entries of one chunk; row stride ldl
+void launch_diag_loss(const AsmArgs& a, const Chi0Geom& g, int n_g, int n_w, double* loss,
+                      cplx* inv, int ldl, int g0, hipStream_t st);
 // One item of a multi-item inversion launch: its n_w matrices are blocks
 // [block0, block0 + n_w) of the launch.
 struct GjJob {

@@ -718,7 +718,7 @@ __global__ void k_loss(const cplx* diag, int n, int n_w, double* loss, cplx* eps
 // from the bulk (a.C, [ks][n_rowsp][2][n_bulkp]) or the FP64 pairs kernel
 // (a.XY, [ks64][n_rowsp64][n_colp64]); column b of chunk G-index b.
 __global__ void k_diag_loss(AsmArgs a, Chi0Geom g, int n_g, int n_w, double* __restrict__ loss,
-                            int ldl, int g0) {
+                            cplx* __restrict__ inv, int ldl, int g0) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long)n_w * n_g) return;
   const int j = (int)(i / n_g), b = (int)(i % n_g);
@@ -738,7 +738,9 @@ __global__ void k_diag_loss(AsmArgs a, Chi0Geom g, int n_g, int n_w, double* __r
   }
   const double vv = a.vq[b] * a.vq[b];
   const double er = 1.0 - vv * a.pref * Xr, ei = -vv * a.pref * Yr;
-  loss[(size_t)j * ldl + g0 + b] = ei / (er * er + ei * ei);
+  const double d2 = er * er + ei * ei;
+  loss[(size_t)j * ldl + g0 + b] = ei / d2;
+  if (inv) inv[(size_t)j * ldl + g0 + b] = {er / d2, -ei / d2};  // 1 / eps_GG
 }
 
 __global__ void k_rho_export(const cplx* R, size_t ldt, int n_g, int n_t, cplx* out) {
@@ -825,11 +827,11 @@ void launch_loss(const cplx* diag, int n_g, int n_w, double* loss, cplx* epsM, h
                      n_w, loss, epsM);
 }
 
-void launch_diag_loss(const AsmArgs& a, const Chi0Geom& g, int n_g, int n_w, double* loss, int ldl,
-                      int g0, hipStream_t st) {
+void launch_diag_loss(const AsmArgs& a, const Chi0Geom& g, int n_g, int n_w, double* loss,
+                      cplx* inv, int ldl, int g0, hipStream_t st) {
   const long total = (long)n_g * n_w;
   hipLaunchKernelGGL(k_diag_loss, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, g,
-                     n_g, n_w, loss, ldl, g0);
+                     n_g, n_w, loss, inv, ldl, g0);
 }
 
 void launch_rho_export(const cplx* R, size_t ldt, int n_g, int n_t, cplx* out, hipStream_t st) {

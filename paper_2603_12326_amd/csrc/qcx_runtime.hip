@@ -475,7 +475,7 @@ int qcx_pair_density(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out) {
 }
 
 int qcx_loss_diag(qcx_ctx* ctx, int n_G, const int* G_int, int n_w, const double* w_eV,
-                  double eta_eV, int precision, double* loss_out) {
+                  double eta_eV, int precision, double* loss_out, void* inv_out) {
   if (!ctx) return QCX_EINVAL;
   if (!ctx->have_states) return fail(ctx, QCX_ESTATE, "set_states first");
   if (n_G < 1 || !G_int) return fail(ctx, QCX_EINVAL, "need n_G >= 1");
@@ -582,7 +582,7 @@ int qcx_loss_diag(qcx_ctx* ctx, int n_G, const int* G_int, int n_w, const double
       a.n_rowsp64 = g64.n_rowsp;
       a.n_colp64 = g64.n_colp;
     }
-    launch_diag_loss(a, g, nch, n_w, loss_out, n_G, g0, st);
+    launch_diag_loss(a, g, nch, n_w, loss_out, static_cast<cplx*>(inv_out), n_G, g0, st);
     LAUNCHCK("diag_loss");
   }
   HIPCK(span_end(ctx, sp_all));

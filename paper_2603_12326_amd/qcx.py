@@ -61,7 +61,7 @@ _SIGS = {
     "qcx_run_batch": [_P, _I, _P, _I, _I, _I, _I],
     "qcx_batch_sync": [_P],
     "qcx_batch_config": [_P, _P, _P],
-    "qcx_loss_diag": [_P, _I, _P, _I, _P, _D, _I, _P],
+    "qcx_loss_diag": [_P, _I, _P, _I, _P, _D, _I, _P, _P],
     "qcx_chi0_kk": [_P, _I, _P, _D, _D, _P],
     "qcx_mlp_create": [ctypes.POINTER(_P), _P, _I],
     "qcx_mlp_destroy": [_P],
@@ -73,8 +73,20 @@ _SIGS = {
     "qcx_mlp_set_encoding": [_P, _D, _D, _D, _D, _D],
     "qcx_mlp_encode": [_P, _I, _P, _P, _P, _P],
     "qcx_mlp_query": [_P, _I, _P, _P, _P, _D, _P, _P],
+    "qcx_qbin_create": [ctypes.POINTER(_P), _P, _I, _I, _D, _I, _I],
+    "qcx_qbin_destroy": [_P],
+    "qcx_qbin_reset": [_P],
+    "qcx_qbin_add": [_P, _I, _P, _P, _I, _I],
+    "qcx_qbin_finish": [_P, _P, _P, _P],
+    "qcx_qbin_rate_halo": [_P, _P, _P, _P, _P],
 }
+QBIN_EPS, QBIN_INV = 0, 1
 MLP_NPARAM = 199169
+
+
+class QcxHalo(ctypes.Structure):
+    _fields_ = [("m_chi_eV", _D), ("m_med_eV", _D), ("sigma_e_cm2", _D), ("rho_T_g_cm3", _D),
+                ("rho_chi_GeV_cm3", _D), ("v0_kms", _D), ("vE_kms", _D), ("vesc_kms", _D)]
 
 
 class QcxItem(ctypes.Structure):
@@ -256,9 +268,11 @@ class Context:
                                       MEM_DEVICE))
         return out
 
-    def loss_diag(self, G_int, w_eV, eta_eV: float, precision="split_bf16", out=None):
+    def loss_diag(self, G_int, w_eV, eta_eV: float, precision="split_bf16", out=None,
+                  inv_out=None):
         """noLFE loss for any number of G (qcx_loss_diag): CUDA float64 tensor
-        [n_w][n_G] (allocated when out is None).  Replaces the pair densities."""
+        [n_w][n_G] (allocated when out is None); inv_out (CUDA complex128
+        [n_w][n_G]) receives 1/eps_GG.  Replaces the pair densities."""
         import torch
 
         G = _host(G_int, np.int32).reshape(-1, 3)
@@ -269,7 +283,9 @@ class Context:
             out = torch.empty((len(w), len(G)), dtype=torch.float64, device="cuda")
         self._check(self.lib.qcx_loss_diag(self._h, len(G), _ptr_host(G), len(w), _ptr_host(w),
                                            float(eta_eV), int(precision),
-                                           _dev_ptr(out, "f64", len(w) * len(G), "out")))
+                                           _dev_ptr(out, "f64", len(w) * len(G), "out"),
+                                           None if inv_out is None else
+                                           _dev_ptr(inv_out, "c128", len(w) * len(G), "inv_out")))
         return out
 
     def sync(self):
@@ -416,6 +432,74 @@ class Mlp:
             _dev_ptr(reject_idx, "i32", n, "reject_idx") if rej else None,
             ctypes.byref(nrej) if rej else None))
         return nrej.value if rej else None
+
+
+class QBins:
+    """Momentum binning of eps(w, q+G), isotropic S(w, q) and the halo rate
+    (qcx_qbin_*) on a Context's device and stream.  Momenta in bohr^-1
+    (= alpha m_e); paper defaults n_theta = 9, n_phi = 16, dq = 0.02."""
+
+    def __init__(self, ctx: Context, n_w: int, n_shell: int, dq: float = 0.02,
+                 n_theta: int = 9, n_phi: int = 16):
+        self.ctx, self.lib = ctx, ctx.lib
+        self.n_w, self.n_shell, self.dq = n_w, n_shell, dq
+        self.n_bins = n_shell * n_theta * n_phi
+        h = ctypes.c_void_p()
+        ctx._check(self.lib.qcx_qbin_create(ctypes.byref(h), ctx._h, n_w, n_shell, float(dq),
+                                            n_theta, n_phi))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.qcx_qbin_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self):
+        self.ctx._check(self.lib.qcx_qbin_reset(self._h))
+
+    def add(self, qvec, vals, kind: str = "inv"):
+        """qvec: host [n][3]; vals: CUDA complex128 [n_w][n] (eps, or 1/eps for kind "inv")."""
+        q = _host(qvec, np.float64).reshape(-1, 3)
+        n = len(q)
+        ld = vals.shape[-1] if hasattr(vals, "shape") else n
+        self.ctx._check(self.lib.qcx_qbin_add(self._h, n, _ptr_host(q),
+                                              _dev_ptr(vals, "c128", self.n_w * ld, "vals"), ld,
+                                              QBIN_INV if kind == "inv" else QBIN_EPS))
+
+    def finish(self, want_eps: bool = False):
+        """(S_iso CUDA float64 [n_w][n_shell], state numpy [bins], eps CUDA or None)."""
+        import torch
+
+        S = torch.empty((self.n_w, self.n_shell), dtype=torch.float64, device="cuda")
+        eps = (torch.empty((self.n_w, self.n_bins), dtype=torch.complex128, device="cuda")
+               if want_eps else None)
+        state = np.zeros(self.n_bins, np.int32)
+        self.ctx._check(self.lib.qcx_qbin_finish(
+            self._h, None if eps is None else _dev_ptr(eps, "c128", eps.numel(), "eps"),
+            _dev_ptr(S, "f64", S.numel(), "S"), _ptr_host(state)))
+        return S, state, eps
+
+    def rate_halo(self, w_eV, S_iso, m_chi_eV: float, m_med_eV: float = float("inf"),
+                  sigma_e_cm2: float = 1e-39, rho_T_g_cm3: float = 2.33,
+                  rho_chi_GeV_cm3: float = 0.3, v0_kms: float = 238.0, vE_kms: float = 250.2,
+                  vesc_kms: float = 544.0):
+        """dR/dw (events / kg / year / eV), CUDA float64 [n_w]."""
+        import torch
+
+        w = _host(w_eV, np.float64).reshape(-1)
+        h = QcxHalo(m_chi_eV, m_med_eV, sigma_e_cm2, rho_T_g_cm3, rho_chi_GeV_cm3, v0_kms, vE_kms,
+                    vesc_kms)
+        out = torch.empty(self.n_w, dtype=torch.float64, device="cuda")
+        self.ctx._check(self.lib.qcx_qbin_rate_halo(self._h, _ptr_host(w),
+                                                    _dev_ptr(S_iso, "f64", self.n_w * self.n_shell, "S_iso"),
+                                                    ctypes.byref(h), _dev_ptr(out, "f64", self.n_w, "out")))
+        return out
 
 
 def build_info() -> str:

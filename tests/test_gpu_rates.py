@@ -1,0 +1,178 @@
+"""Momentum binning, isotropic S(w, q) and the halo rate (qcx_qbin_*) against
+oracle/rates.py.
+
+* Random entries (three adds, eps and 1/eps, some beyond the last shell) on
+  12 shells x 9 x 16 bins: bin states exactly, binned eps to 1e-13, S to
+  1e-12 of its largest value; empty inner bins exercise the interpolation.
+* The smallest workload through the library: the 27-G LFE block (diag of
+  eps^-1) and 300 noLFE G (1/eps_GG of qcx_loss_diag) binned and compared
+  with the oracle's eps on the same entries.
+* The rate for heavy, light and massive mediators and two DM masses against
+  the oracle (closed-form eta on the GPU, quadrature of its definition in
+  the oracle): 1e-9.
+* Error paths and an empty table.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import rates, rpa
+from tests.gpu_helpers import set_inputs
+
+pytestmark = pytest.mark.gpu
+
+NT, NP = 9, 16
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2603_12326_amd import Context
+
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _oracle(entries, n_w, dq, n_shell):
+    e, cnt = rates.bin_eps(entries, n_w, dq, n_shell, NT, NP)
+    e, st = rates.fill_missing(e, cnt, n_shell, NT, NP)
+    qs, S = rates.isotropic_s(e, st, dq, n_shell, NT, NP)
+    return e, st, qs, S
+
+
+def _check(gpu, ref):
+    S, state, eb = gpu
+    e_ref, st_ref, _, S_ref = ref
+    assert np.array_equal(state, st_ref)
+    ok = st_ref > 0
+    assert _rel(eb.cpu().numpy()[:, ok], e_ref[:, ok]) < 1e-13
+    S = S.cpu().numpy()
+    assert np.array_equal(np.isnan(S), np.isnan(S_ref))
+    f = np.isfinite(S_ref)
+    assert _rel(S[f], S_ref[f]) < 1e-12
+    return S
+
+
+def test_binning_random(ctx):
+    import torch
+
+    from paper_2603_12326_amd import QBins
+
+    rng = np.random.default_rng(11)
+    n_w, n_shell, dq = 7, 12, 0.15
+    qb = QBins(ctx, n_w, n_shell, dq, NT, NP)
+    entries = []
+    for it, kind in enumerate(("eps", "inv", "eps")):
+        n = 3000
+        q = rng.normal(size=(n, 3)) * 0.8
+        eps = (1.0 + rng.uniform(0, 5, (n_w, n))) + 1j * rng.uniform(0.01, 3, (n_w, n))
+        vals = eps if kind == "eps" else 1.0 / eps
+        qb.add(q, torch.from_numpy(np.ascontiguousarray(vals)).cuda(), kind)
+        entries.append((q, eps))
+    gpu = qb.finish(want_eps=True)
+    ref = _oracle(entries, n_w, dq, n_shell)
+    assert (ref[1] == 2).sum() > 0 and (ref[1] == 1).sum() > 0
+    _check(gpu, ref)
+    # finish keeps the entries: a second finish gives the same bits
+    S2, _, _ = qb.finish()
+    assert np.array_equal(S2.cpu().numpy(), gpu[0].cpu().numpy(), equal_nan=True)
+    qb.close()
+
+
+def test_binning_workload(ctx, cfg1, cfg1_oracle):
+    import torch
+
+    from paper_2603_12326_amd import QBins
+
+    st = set_inputs(ctx, cfg1)
+    w = cfg1.w_eV[::4]
+    n_w, n_g = len(w), len(cfg1.G_int)
+    ctx.pair_density(cfg1.G_int)
+    ctx.chi0(w, cfg1.eta_eV, "fp64", True)
+    d = torch.empty((n_w, n_g), dtype=torch.complex128, device="cuda")
+    ctx.eps_inv(True, diag_out=d)
+    Q = rpa.q_plus_g(cfg1.cell.lat, st.q_cart, cfg1.G_int)
+    # noLFE entries: 300 G beyond the LFE block
+    r = np.arange(-4, 5)
+    G = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    b = 2.0 * np.pi * np.linalg.inv(np.asarray(cfg1.cell.lat, np.float64)).T
+    G = G[np.argsort(np.linalg.norm(G @ b, axis=1), kind="stable")][27:327].astype(np.int32)
+    Qn = rpa.q_plus_g(cfg1.cell.lat, st.q_cart, G)
+    inv = torch.empty((n_w, len(G)), dtype=torch.complex128, device="cuda")
+    ctx.loss_diag(G, w, cfg1.eta_eV, "fp64", inv_out=inv)
+    dq, n_shell = 0.1, 40
+    qb = QBins(ctx, n_w, n_shell, dq, NT, NP)
+    qb.add(Q, d, "inv")
+    qb.add(Qn, inv, "inv")
+    gpu = qb.finish(want_eps=True)
+    eps_lfe = 1.0 / rpa.inverse_diagonal(cfg1_oracle["eps"][::4])
+    eps_nol = rpa.eps_diag(cfg1.cell, cfg1.basis, cfg1.lattice_range, cfg1.k_frac, cfg1.n_occ, G,
+                           st, w, cfg1.eta_eV)
+    ref = _oracle([(Q, eps_lfe), (Qn, eps_nol)], n_w, dq, n_shell)
+    # FP64 path: the library's eps agrees with the oracle's to ~1e-13
+    S_ref = ref[3]
+    S, state, eb = gpu
+    assert np.array_equal(state, ref[1])
+    S = S.cpu().numpy()
+    f = np.isfinite(S_ref)
+    assert np.array_equal(np.isfinite(S), f) and _rel(S[f], S_ref[f]) < 1e-10
+    # the rate from these S
+    for m_chi, m_med in ((1e9, math.inf), (1e7, 0.0)):
+        rg = qb.rate_halo(w, gpu[0], m_chi, m_med).cpu().numpy()
+        rr = rates.rate_halo(w, ref[2], S_ref, dq, m_chi, m_med, 1e-39, 2.33)
+        assert _rel(rg, rr) < 1e-9, (m_chi, m_med)
+    qb.close()
+
+
+def test_rate_against_oracle(ctx):
+    import torch
+
+    from paper_2603_12326_amd import QBins
+
+    n_w, n_shell, dq = 9, 60, 0.2
+    qb = QBins(ctx, n_w, n_shell, dq, NT, NP)
+    qs = (np.arange(n_shell) + 0.5) * dq
+    w = np.linspace(0.0, 40.0, n_w)
+    S = (qs[None, :] ** 2 * np.exp(-((qs[None, :] - 5.0) ** 2) / 8.0) * (0.1 + w[:, None] / 20.0))
+    S[:, 3] = np.nan                       # a shell without data
+    S_d = torch.from_numpy(S).cuda()
+    for m_chi in (1e9, 3e7):
+        for m_med in (math.inf, 0.0, 2000.0):
+            rg = qb.rate_halo(w, S_d, m_chi, m_med, sigma_e_cm2=1e-40, rho_T_g_cm3=5.3).cpu().numpy()
+            rr = rates.rate_halo(w, qs, S, dq, m_chi, m_med, 1e-40, 5.3)
+            assert _rel(rg, rr) < 1e-9, (m_chi, m_med, rg, rr)
+    qb.close()
+
+
+def test_empty_and_errors(ctx):
+    import torch
+
+    from paper_2603_12326_amd import QBins, QcxError
+    from paper_2603_12326_amd import qcx as q
+
+    qb = QBins(ctx, 3, 4, 0.1)
+    S, state, _ = qb.finish()
+    assert np.all(state == 0) and np.all(np.isnan(S.cpu().numpy()))
+    v = torch.ones((3, 5), dtype=torch.complex128, device="cuda")
+    with pytest.raises(QcxError) as e:
+        qb.add(np.full((5, 3), np.nan), v)
+    assert e.value.code == q.EINVAL
+    q0 = np.ones((5, 3))
+    assert qb.lib.qcx_qbin_add(qb._h, 5, q._ptr_host(q0), q._dev_ptr(v, "c128", 15, "v"), 4, 1) == q.EINVAL
+    assert qb.lib.qcx_qbin_add(qb._h, 5, q._ptr_host(q0), q._dev_ptr(v, "c128", 15, "v"), 5, 7) == q.EINVAL
+    assert qb.lib.qcx_qbin_finish(qb._h, None, None, None) == q.EINVAL
+    with pytest.raises(QcxError):
+        qb.rate_halo(np.zeros(3), S, -1.0)
+    with pytest.raises(QcxError):
+        QBins(ctx, 3, 0, 0.1)
+    with pytest.raises(QcxError):
+        QBins(ctx, 3, 4, -0.1)
+    qb.close()
