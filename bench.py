@@ -19,7 +19,10 @@ block |q+G| <= 6 bohr^-1 (about 950 G, inverted), noLFE diagonal for every
 other G up to |q+G| <= 25 bohr^-1 (about 71,000 G in all).  --workload kk
 runs the Si-like N_G = 113 step through the Kramers-Kronig route instead
 (spectral part binned at --kk-bin eV, FP64 transform), against the direct
-route on the same inputs.
+route on the same inputs.  --workload rates adds to the composite workload
+the momentum binning of all ~71,000 (q + G) entries (shells of 0.02 bohr^-1
+to 25 bohr^-1, 9 x 16 angular bins), the isotropic S(w, q) and the halo
+rate for a 1 GeV dark-matter particle (heavy and light mediator).
 """
 from __future__ import annotations
 
@@ -57,7 +60,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample-w", type=int, default=400)
-    ap.add_argument("--workload", choices=["si-ng113", "mixed-batch", "composite", "kk"],
+    ap.add_argument("--workload", choices=["si-ng113", "mixed-batch", "composite", "kk", "rates"],
                     default="si-ng113")
     ap.add_argument("--kk-bin", type=float, default=0.025, help="bin width (eV) of --workload kk")
     ap.add_argument("--calib-copy", action="store_true",
@@ -562,6 +565,126 @@ def main_kk(args):
     print(json.dumps(out))
 
 
+def main_rates(args):
+    """Composite eps of one q, binned in momentum, S(w, q) and halo rates."""
+    import math
+
+    import torch
+
+    from paper_2603_12326_amd import Context, QBins, build_info
+    from paper_2603_12326_amd import composite as C
+    from paper_2603_12326_amd import rates as RT
+    from synth import make_config2
+
+    Q_MAX, Q_LFE, DQ, NT, NP = 25.0, 6.0, 0.02, 9, 16
+    M_CHI, SIG, RHO_T = 1e9, 1e-39, 2.33
+    wl = make_config2(n_q=1)
+    qs, kf = upload_workload(wl, 1, torch)
+    d = qs[0]
+    G = composite_g(wl.cell.lat, d["q"], Q_MAX)
+    n_w, n_g = len(wl.w_eV), len(G)
+    n_shell = int(math.ceil(Q_MAX / DQ))
+    ctx = Context(0)
+    b = wl.basis
+    ctx.set_cell_basis(wl.cell.lat, wl.cell.xyz, b.shell_atom, b.shell_l, b.shell_exp, 1, 1)
+    qb = QBins(ctx, n_w, n_shell, DQ, NT, NP)
+    res = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t_bin = []
+
+    def step():
+        ctx.set_states(d["q"], kf, wl.n_occ, d["C_k"], d["E_k"], d["C_kq"], d["E_kq"])
+        parts = C.composite_loss(ctx, wl.cell.lat, d["q"], G, wl.w_eV, wl.eta_eV, Q_LFE,
+                                 "split_bf16", with_inv=True)
+        ev[0].record()
+        t0 = time.perf_counter()
+        qb.reset()
+        RT.bin_composite(qb, wl.cell.lat, d["q"], G, parts)
+        S, state, _ = qb.finish()
+        rh = qb.rate_halo(wl.w_eV, S, M_CHI, float("inf"), SIG, RHO_T)
+        rl = qb.rate_halo(wl.w_eV, S, M_CHI, 0.0, SIG, RHO_T)
+        ev[1].record()
+        res.update(parts=parts, S=S, state=state, rh=rh, rl=rl, host_s=time.perf_counter() - t0)
+
+    log(f"rates: {n_g} G, {args.warmup} warmup + {args.steps} timed steps")
+    for _ in range(max(1, args.warmup)):
+        step()
+    ctx.sync()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        t_bin.append(res["host_s"])
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    st = ctx.stage_times()
+    ctx.set_timing(False)
+    bin_dev_ms = ev[0].elapsed_time(ev[1])
+    state = res["state"]
+    w = np.asarray(wl.w_eV)
+    rh, rl = res["rh"].cpu().numpy(), res["rl"].cpu().numpy()
+    dw = w[1] - w[0]
+    out = {
+        "metric": "(w, q+G) values taken to binned S(w,q) and dR/dw per second (composite eps, one q)",
+        "value": n_w * n_g * args.steps / sec,
+        "unit": "values/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "Si-like fcc a=10.26, 28 GTO, 4+16 bands, 8^3 k, q=0.1*2pi/a x, "
+                               f"400 w over 0-60 eV, eta=0.1 eV; LFE |q+G|<={Q_LFE}, noLFE to "
+                               f"{Q_MAX} bohr^-1 ({n_g} G); bins dq={DQ} bohr^-1 x {NT} x {NP} "
+                               f"({n_shell} shells); halo rate m_chi=1 GeV, sigma_e=1e-39 cm^2, "
+                               f"rho_T={RHO_T} g/cm^3",
+                   "n_g": n_g, "n_bins": int(len(state))},
+        "bins": {"with_entries": int((state == 1).sum()), "interpolated": int((state == 2).sum()),
+                 "empty": int((state == 0).sum())},
+        "binning_and_rate_ms_last_step": {"wall": 1e3 * res["host_s"], "device_events": bin_dev_ms},
+        "rate_events_per_kg_year": {"heavy": float(np.sum(rh) * dw), "light": float(np.sum(rl) * dw)},
+        "stages_ms_per_step": {k: (v / args.steps if k.endswith("_ms") else v) for k, v in st.items()},
+        "build": build_info(),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import rates
+        widx = np.arange(0, n_w, 50)
+        inner, _, outer, _, D_in, D_out = res["parts"]
+        Q = RT.qvectors(wl.cell.lat, d["q"], G)
+        e_in = 1.0 / D_in.cpu().numpy()[widx]
+        e_out = 1.0 / D_out.cpu().numpy()[widx]
+        log(f"cpu baseline (oracle binning, interpolation, S and rates on {len(widx)} frequencies)")
+        t0 = time.perf_counter()
+        eb, cnt = rates.bin_eps([(Q[inner], e_in), (Q[outer], e_out)], len(widx), DQ, n_shell, NT, NP)
+        eb, st_ref = rates.fill_missing(eb, cnt, n_shell, NT, NP)
+        qsh, S_ref = rates.isotropic_s(eb, st_ref, DQ, n_shell, NT, NP)
+        r_ref = rates.rate_halo(w[widx], qsh, S_ref, DQ, M_CHI, float("inf"), SIG, RHO_T)
+        dt = time.perf_counter() - t0
+        S_gpu = res["S"].cpu().numpy()[widx]
+        f = np.isfinite(S_ref)
+        out["bins_state_equal_oracle"] = bool(np.array_equal(state, st_ref))
+        out["max_rel_err_S_vs_oracle"] = float(np.max(np.abs(S_gpu[f] - S_ref[f])) / np.max(np.abs(S_ref[f])))
+        out["max_rel_err_rate_vs_oracle"] = float(np.max(np.abs(rh[widx] - r_ref)) / np.max(np.abs(r_ref)))
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        except Exception:
+            threads = os.cpu_count()
+        out["cpu_baseline"] = dict(value=len(widx) * n_g / dt, unit="values/s", cores=int(threads),
+                                   kind="oracle",
+                                   sample=f"binning, interpolation, S and heavy-mediator rate of the "
+                                          f"GPU's eps entries at {len(widx)} of {n_w} frequencies "
+                                          f"(all {n_g} G, all {len(state)} bins), {dt:.1f} s")
+    qb.close()
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -575,6 +698,8 @@ def main():
         return main_composite(args)
     if args.workload == "kk":
         return main_kk(args)
+    if args.workload == "rates":
+        return main_rates(args)
     import torch
 
     from paper_2603_12326_amd import Context, build_info

@@ -25,10 +25,12 @@ def split(lat, q_cart, G_int, q_lfe: float):
 
 
 def composite_loss(ctx, lat, q_cart, G_int, w_eV, eta_eV: float, q_lfe: float,
-                   precision="split_bf16"):
+                   precision="split_bf16", with_inv: bool = False):
     """Loss on the context's current states: returns (inner, L_inner, outer,
     L_outer) with L_* CUDA float64 tensors [n_w][len(*)] for the G indices
-    inner / outer of G_int.  Leaves the context's pair densities replaced."""
+    inner / outer of G_int; with_inv adds (D_inner, D_outer), CUDA complex128
+    [n_w][len(*)] holding 1/eps(w, q+G) (the diagonal of eps^-1 inside the
+    block, 1/eps_GG beyond).  Leaves the context's pair densities replaced."""
     import torch
 
     G = np.asarray(G_int, np.int32).reshape(-1, 3)
@@ -36,10 +38,19 @@ def composite_loss(ctx, lat, q_cart, G_int, w_eV, eta_eV: float, q_lfe: float,
     w = np.asarray(w_eV, np.float64)
     ctx.pair_density(G[inner])
     ctx.chi0(w, eta_eV, precision, True)
-    ctx.eps_inv(True)
+    D_in = D_out = None
+    if with_inv:
+        D_in = torch.empty((len(w), len(inner)), dtype=torch.complex128, device="cuda")
+    ctx.eps_inv(True, diag_out=D_in)
     L_in = torch.empty((len(w), len(inner)), dtype=torch.float64, device="cuda")
     ctx.loss(L_in)
-    L_out = ctx.loss_diag(G[outer], w, eta_eV, precision) if len(outer) else None
+    L_out = None
+    if len(outer):
+        if with_inv:
+            D_out = torch.empty((len(w), len(outer)), dtype=torch.complex128, device="cuda")
+        L_out = ctx.loss_diag(G[outer], w, eta_eV, precision, inv_out=D_out)
+    if with_inv:
+        return inner, L_in, outer, L_out, D_in, D_out
     return inner, L_in, outer, L_out
 
 
