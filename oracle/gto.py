@@ -187,6 +187,61 @@ def overlap_matrix(lat, xyz, shell_atom, shell_l, shell_exp, lattice_range, k_fr
     return M[:, 0]
 
 
+def grad_cell(lat, xyz, shell_atom, shell_l, shell_exp, lattice_range: int) -> np.ndarray:
+    """D[T][c][mu][nu] = int chi_mu(r - A_mu) d/dr_c chi_nu(r - A_nu - T) d^3r
+    (App. C's <i k| grad |j k> in the AO basis, before the Bloch sum).
+
+    Per axis the ket's derivative is d/dx (x-B)^j e^{-b(x-B)^2} = j (x-B)^{j-1}
+    e^{...} - 2b (x-B)^{j+1} e^{...}, so the axis factor of component c is
+    j J[i][j-1] - 2 b J[i][j+1] with J the Q = 0 axis integrals; the other
+    two axes keep their overlaps."""
+    lat = np.asarray(lat, np.float64)
+    xyz = np.asarray(xyz, np.float64)
+    cells = lattice_cells(lattice_range)
+    tvec = cells @ lat
+    off = ao_offsets(shell_l)
+    nao = int(off[-1])
+    out = np.zeros((len(cells), 3, nao, nao))
+    for sa in range(len(shell_l)):
+        la, ea = int(shell_l[sa]), float(shell_exp[sa])
+        A = xyz[shell_atom[sa]]
+        terms_a = ao_cartesian_terms(la, ea)
+        for sb in range(len(shell_l)):
+            lb, eb = int(shell_l[sb]), float(shell_exp[sb])
+            B = xyz[shell_atom[sb]][None, :] + tvec
+            terms_b = ao_cartesian_terms(lb, eb)
+            S1 = [np.real(axis_integrals(ea, eb, A[x], B[:, x], [0.0], la, lb + 1)[..., 0])
+                  for x in range(3)]                                  # [i][j][nT]
+            D1 = []
+            for x in range(3):
+                d = np.zeros((la + 1, lb + 1, len(cells)))
+                for j in range(lb + 1):
+                    d[:, j] = -2.0 * eb * S1[x][:, j + 1]
+                    if j > 0:
+                        d[:, j] += j * S1[x][:, j - 1]
+                D1.append(d)
+            for ia, ta in enumerate(terms_a):
+                for ib, tb in enumerate(terms_b):
+                    for c in range(3):
+                        acc = 0.0
+                        for ca, pa in ta:
+                            for cb, pb in tb:
+                                f = ca * cb
+                                for x in range(3):
+                                    f = f * (D1[x] if x == c else S1[x])[pa[x], pb[x]]
+                                acc = acc + f
+                        out[:, c, off[sa] + ia, off[sb] + ib] = acc
+    return out
+
+
+def grad_matrix(lat, xyz, shell_atom, shell_l, shell_exp, lattice_range, k_frac) -> np.ndarray:
+    """D(k)[k][c][mu][nu] = sum_T e^{ik.T} D[T][c][mu][nu] (anti-Hermitian per k, c)."""
+    D = grad_cell(lat, xyz, shell_atom, shell_l, shell_exp, lattice_range)
+    ph = bloch_phases(k_frac, lattice_range)
+    nT, _, n, _ = D.shape
+    return (ph @ D.reshape(nT, -1)).reshape(len(ph), 3, n, n)
+
+
 def eval_ao(lat, xyz, shell_atom, shell_l, shell_exp, r: np.ndarray, shift=None) -> np.ndarray:
     """Values of every AO chi_mu(r - A_mu - shift) on points r [npts][3]; shape [nao][npts]."""
     r = np.asarray(r, np.float64)

@@ -297,6 +297,101 @@ def chi0_kk(R, E_k, E_kq, n_occ, w_eV, eta_eV, bin_eV, volume) -> np.ndarray:
     return out
 
 
+# --------------------------------------------------------------------------
+# Optical limit (App. C): for q -> 0 the G = 0 pair densities vanish like
+# |q|, and by first-order k.p perturbation
+#     <i k| e^{-iq.r} |j k+q>  ->  -(i/m) q.<i k|grad|j k> / (w_jk - w_ik),
+# so rho_vck(q) / |q| -> -i qhat.P_cv / D and sigma_vck(q) / |q| ->
+# +i qhat.P_vc / D with P_ab = <a k|grad|b k> (anti-Hermitian), D = E_c - E_v
+# at the same k, m = 1.  With these as the G = 0 row (and the Coulomb factor
+# of that row sqrt(4 pi), |q| cancelled) the head and wings of Eq. (RPA) are
+# their q -> 0 limits; the G != 0 rows are the pair densities at q = 0.
+# --------------------------------------------------------------------------
+def momentum_bands(cell, basis, lattice_range, k_frac, C_k) -> np.ndarray:
+    """P[k][c][a][b] = <a k| d/dr_c |b k> in the band basis (bohr^-1)."""
+    D = gto.grad_matrix(cell.lat, cell.xyz, basis.shell_atom, basis.shell_l, basis.shell_exp,
+                        lattice_range, k_frac)
+    C = np.asarray(C_k)
+    return np.einsum("kma,kcmn,knb->kcab", np.conj(C), D, C)
+
+
+def optical_row(P, E_k, n_occ, qhat) -> np.ndarray:
+    """R0[s][k][v][c]: the G = 0 pair densities divided by |q| in the limit
+    (s = 0: -i qhat.P_cv / D, s = 1: +i qhat.P_vc / D)."""
+    qh = np.asarray(qhat, np.float64) / np.linalg.norm(qhat)
+    Pq = np.einsum("c,kcab->kab", qh, P)                       # qhat . P
+    ek = np.asarray(E_k, np.float64) / HARTREE_EV
+    D = ek[:, None, n_occ:] - ek[:, :n_occ, None]              # [k][v][c]
+    res = -1j * np.transpose(Pq[:, n_occ:, :n_occ], (0, 2, 1)) / D    # P_cv -> [k][v][c]
+    anti = 1j * Pq[:, :n_occ, n_occ:] / D                              # P_vc
+    return np.stack([res, anti])
+
+
+def pair_densities_optical(cell, basis, lattice_range, k_frac, G_int, C_k, E_k, n_occ, qhat):
+    """R[s][k][v][c][G] for q -> 0: G != 0 from Eq. (RPA) at q = 0 (states at k
+    on both sides), G = 0 (must be G_int[0]) from optical_row."""
+    G = np.asarray(G_int).reshape(-1, 3)
+    if np.any(G[0] != 0):
+        raise ValueError("G_int[0] must be 0")
+    R = pair_densities_from_workload(cell, basis, lattice_range, k_frac, np.zeros(3), G, C_k, C_k,
+                                     n_occ)
+    P = momentum_bands(cell, basis, lattice_range, k_frac, C_k)
+    R[..., 0] = optical_row(P, E_k, n_occ, qhat)
+    return R
+
+
+def coulomb_sqrt_optical(lat, G_int) -> np.ndarray:
+    """sqrt(4 pi) / |G| with the G = 0 entry sqrt(4 pi) (its |q| went into R)."""
+    Qc = q_plus_g(lat, np.zeros(3), G_int)
+    n = np.linalg.norm(Qc, axis=1)
+    v = np.full(len(n), math.sqrt(4.0 * math.pi))
+    v[1:] = v[1:] / n[1:]
+    return v
+
+
+def epsilon_optical(chi: np.ndarray, lat, G_int) -> np.ndarray:
+    """eps_GG' = delta - v_G v_G' chi_GG' with coulomb_sqrt_optical."""
+    v = coulomb_sqrt_optical(lat, G_int)
+    n = chi.shape[-1]
+    return np.eye(n)[None] - v[None, :, None] * chi * v[None, None, :]
+
+
+def optical_head_wings(P, E_k, n_occ, w_eV, eta_eV, qhat, volume, rho, gnorm):
+    """App. C's head eps_00 and wings eps_0G', eps_G0 written out as sums over
+    (k, v, c) and both orderings (i, j) of each transition, with 1/N_k (R1).
+    Signs: the wing eps_0G' as printed; the head and eps_G0 with the signs
+    that Eq. (RPA) gives in the limit (the appendix prints + in front of the
+    head sum, which makes Im eps_00 < 0 for w > 0, and - in front of eps_G0,
+    which breaks eps_G0 = conj(eps_0G) for real w below the gap at eta -> 0).
+    rho: [2][k][v][c][G] pair densities at q = 0 of the G != 0 columns
+    (<c|e^{iGr}|v>, <v|e^{iGr}|c>), gnorm [G] their |G|.
+    Returns (eps00[w], eps0G[w][G], epsG0[w][G])."""
+    qh = np.asarray(qhat, np.float64) / np.linalg.norm(qhat)
+    Pq = np.einsum("c,kcab->kab", qh, P)
+    ek = np.asarray(E_k, np.float64) / HARTREE_EV
+    D = ek[:, None, n_occ:] - ek[:, :n_occ, None]              # [k][v][c]
+    w = np.asarray(w_eV, np.float64)[:, None, None, None] / HARTREE_EV
+    eta = float(eta_eV) / HARTREE_EV
+    nk = ek.shape[0]
+    pre = 4.0 * math.pi / (float(volume) * nk)
+    Pcv = np.transpose(Pq[:, n_occ:, :n_occ], (0, 2, 1))      # qhat.<c|grad|v> as [k][v][c]
+    Pvc = Pq[:, :n_occ, n_occ:]                                # qhat.<v|grad|c>
+    # (i, j) = (v, c): f_i - f_j = 2, w_j - w_i = D, denominator w - D + i eta;
+    # (i, j) = (c, v): f_i - f_j = -2, w_j - w_i = -D, denominator w + D - i eta
+    dr = 1.0 / (w - D[None] + 1j * eta)
+    da = 1.0 / (w + D[None] - 1j * eta)
+    head = 1.0 - pre * np.sum(2.0 * np.abs(Pvc[None]) ** 2 / D[None] ** 2 * (dr - da), axis=(1, 2, 3))
+    # eps_0G' = 4 pi i / (V |G'|) sum (f_i - f_j)/(w_j - w_i) qhat.<i|grad|j> <j|e^{iG'r}|i> / den
+    t_r = (2.0 / D)[None, ..., None] * Pvc[None, ..., None] * rho[0][None] * dr[..., None]
+    t_a = (2.0 / D)[None, ..., None] * Pcv[None, ..., None] * rho[1][None] * da[..., None]
+    w0G = 1j * pre * np.sum(t_r + t_a, axis=(1, 2, 3)) / gnorm[None, :]
+    # eps_G0 = 4 pi i / (V |G|) sum (f_i - f_j)/(w_j - w_i) <i|e^{-iGr}|j> qhat.<j|grad|i> / den
+    u_r = (2.0 / D)[None, ..., None] * np.conj(rho[0])[None] * Pcv[None, ..., None] * dr[..., None]
+    u_a = (2.0 / D)[None, ..., None] * np.conj(rho[1])[None] * Pvc[None, ..., None] * da[..., None]
+    wG0 = 1j * pre * np.sum(u_r + u_a, axis=(1, 2, 3)) / gnorm[None, :]
+    return head, w0G, wG0
+
+
 def eps_macro(eps: np.ndarray) -> np.ndarray:
     """eps_M(w) = 1 / [eps^{-1}]_00."""
     return 1.0 / inverse_diagonal(eps)[:, 0]
