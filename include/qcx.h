@@ -147,6 +147,25 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
  * Errors: QCX_ESTATE (no states), QCX_EINVAL, QCX_ENOMEM. */
 int qcx_pair_density(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out);
 
+/* Pair densities in the optical limit q -> 0 (App. C) for the head and wings
+ * of eps: the states must have been set with q_cart = (0, 0, 0); the k states
+ * serve on both sides (the k+q states are not read).  Rows G != 0 are the
+ * pair densities of qcx_pair_density at q = 0; the G = 0 row, which vanishes
+ * like |q|, is replaced by its limit divided by |q| from k.p perturbation
+ * theory,
+ *   rho_vck(0) / |q|   -> -i qhat.<c k|grad|v k> / (E_c(k) - E_v(k)),
+ *   sigma_vck(0) / |q| -> +i qhat.<v k|grad|c k> / (E_c(k) - E_v(k)),
+ * with the momentum matrix elements from Gaussian gradient integrals (the
+ * same 27-cell Bloch sum), and the Coulomb factor of that row becomes
+ * sqrt(4 pi) (|q| cancels).  qcx_chi0 / qcx_chi0_kk / qcx_eps_inv / qcx_loss
+ * then give eps and the loss as q -> 0 along qhat (the G = 0 loss is the
+ * optical loss function).  Transition energies are recomputed at the same k.
+ *   qhat  host [3], any nonzero length (normalised)
+ * Other arguments as for qcx_pair_density.
+ * Errors: QCX_ESTATE, QCX_EINVAL (q != 0, qhat zero, G list). */
+int qcx_pair_density_optical(qcx_ctx* ctx, int n_G, const int* G_int, const double* qhat,
+                             void* rho_out);
+
 /* Independent-particle response of Eq. (RPA) at finite broadening:
  *   chi0_GG'(w) = 1/(N_k V) sum_{k,v,c} [ 2 rho(G)^* rho(G') / (w - D + i eta)
  *                                        - 2 sigma(G)^* sigma(G') / (w + D' - i eta) ]

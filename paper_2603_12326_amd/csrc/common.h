@@ -62,6 +62,13 @@ struct ShellTab {
 };
 void launch_cell_ft(const ShellTab& sh, const double* tvec, int n_t, const double* Q, int n_q,
                     cplx* F, hipStream_t st);
+// optical limit (App. C): D[T][c][mu][nu] = <chi_mu| d/dr_c |chi_nu(. - T)>
+// (real values in complex storage), and the G = 0 row R0[t] = -/+ i qhat.P / dt
+// from the band matrices Rp[c][t] (stride ldt) of the resonant / anti-resonant
+// transitions
+void launch_grad_ft(const ShellTab& sh, const double* tvec, int n_t, cplx* D, hipStream_t st);
+void launch_optical_row(const cplx* Rp, size_t ldt, const double* dt, int n_t, const double qhat[3],
+                        cplx* R0, hipStream_t st);
 // e^{2 pi i kf.n_T} for kf = k_frac[k] + shift
 void launch_bloch_phase(const double* k_frac, int n_k, const double shift[3], const int* cells,
                         int n_t, cplx* ph, hipStream_t st);

@@ -229,6 +229,121 @@ __global__ void __launch_bounds__(256) k_cell_ft(ShellTab sh, const double* tvec
   }
 }
 
+// Gradient integrals of App. C, <chi_mu| d/dr_c |chi_nu(. - T)>: at Q = 0 the
+// axis integrals are the Hermite overlaps S[i][j] = E^{ij}_0 (times the common
+// factor), and d/dx of the ket's (x - B_x)^j e^{-b (x - B_x)^2} gives the
+// axis factor j S[i][j-1] - 2 b S[i][j+1]; the other axes keep S.
+template <int LA, int LB>
+__device__ void pair_grad(double a, double b, const double* A, const double* B, double* out,
+                          int ld, size_t cstride) {
+  const double p = a + b, ip = 1.0 / p, i2p = 0.5 * ip;
+  double P[3], ab2 = 0.0;
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    P[x] = (a * A[x] + b * B[x]) * ip;
+    const double d = A[x] - B[x];
+    ab2 += d * d;
+  }
+  const double mag = pow(kPi * ip, 1.5) * exp(-a * b * ip * ab2);
+  double S[3][LA + 1][LB + 2], G[3][LA + 1][LB + 1];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    cplx J[LA + 1][LB + 2];
+    axis_j<LA, LB + 1>(P[x] - A[x], P[x] - B[x], i2p, 0.0, J);
+#pragma unroll
+    for (int i = 0; i <= LA; ++i) {
+#pragma unroll
+      for (int j = 0; j <= LB + 1; ++j) S[x][i][j] = J[i][j].re;
+#pragma unroll
+      for (int j = 0; j <= LB; ++j) G[x][i][j] = (j > 0 ? j * S[x][i][j - 1] : 0.0) - 2.0 * b * S[x][i][j + 1];
+    }
+  }
+  constexpr int NCA = Shape<LA>::ncart, NCB = Shape<LB>::ncart;
+  constexpr int NSA = Shape<LA>::nsph, NSB = Shape<LB>::nsph;
+  const double nn = prim_norm(LA, a) * prim_norm(LB, b) * mag;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double cart[NCA][NCB];
+#pragma unroll
+    for (int ca = 0; ca < NCA; ++ca) {
+      const int* pa = kCartPow[Shape<LA>::first + ca];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int* pb = kCartPow[Shape<LB>::first + cb];
+        double v = 1.0;
+#pragma unroll
+        for (int x = 0; x < 3; ++x) v *= (x == c) ? G[x][pa[x]][pb[x]] : S[x][pa[x]][pb[x]];
+        cart[ca][cb] = v;
+      }
+    }
+#pragma unroll
+    for (int ma = 0; ma < NSA; ++ma) {
+      double tmp[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        double r = 0.0;
+#pragma unroll
+        for (int ca = 0; ca < NCA; ++ca) r += sph_coef(LA, ma, ca) * cart[ca][cb];
+        tmp[cb] = r;
+      }
+#pragma unroll
+      for (int mb = 0; mb < NSB; ++mb) {
+        double r = 0.0;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) r += sph_coef(LB, mb, cb) * tmp[cb];
+        // stored as complex (imaginary part 0) so the Bloch sum of the
+        // overlap path applies unchanged
+        out[2 * (c * cstride + (size_t)ma * ld + mb)] = r * nn;
+        out[2 * (c * cstride + (size_t)ma * ld + mb) + 1] = 0.0;
+      }
+    }
+  }
+}
+
+// One thread per (shell pair, cell): D[T][c][mu][nu], c = x, y, z.
+__global__ void __launch_bounds__(256) k_grad_ft(ShellTab sh, const double* tvec, int n_t,
+                                                 cplx* D) {
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long total = (long)n_t * sh.n_sh * sh.n_sh;
+  if (tid >= total) return;
+  const int sp = (int)(tid / n_t), it = (int)(tid % n_t);
+  const int sa = sp / sh.n_sh, sb = sp % sh.n_sh;
+  const double a = sh.ex[sa], b = sh.ex[sb];
+  double A[3], B[3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    A[x] = sh.ctr[3 * sa + x];
+    B[x] = sh.ctr[3 * sb + x] + tvec[3 * it + x];
+  }
+  const int n = sh.n_ao;
+  const size_t cs = (size_t)n * n;
+  double* out = reinterpret_cast<double*>(D + (size_t)it * 3 * cs + (size_t)sh.off[sa] * n + sh.off[sb]);
+  switch (sh.l[sa] * 3 + sh.l[sb]) {
+    case 0: pair_grad<0, 0>(a, b, A, B, out, n, cs); break;
+    case 1: pair_grad<0, 1>(a, b, A, B, out, n, cs); break;
+    case 2: pair_grad<0, 2>(a, b, A, B, out, n, cs); break;
+    case 3: pair_grad<1, 0>(a, b, A, B, out, n, cs); break;
+    case 4: pair_grad<1, 1>(a, b, A, B, out, n, cs); break;
+    case 5: pair_grad<1, 2>(a, b, A, B, out, n, cs); break;
+    case 6: pair_grad<2, 0>(a, b, A, B, out, n, cs); break;
+    case 7: pair_grad<2, 1>(a, b, A, B, out, n, cs); break;
+    default: pair_grad<2, 2>(a, b, A, B, out, n, cs); break;
+  }
+}
+
+// G = 0 row of the pair densities divided by |q| in the optical limit:
+// Rp[c][t] holds <c|d/dr_c|v> (resonant t) or <v|d/dr_c|c> (anti-resonant t)
+// at the same k; the row is -i qhat.P / D or +i qhat.P / D, D = dt[t] > 0.
+__global__ void k_optical_row(const cplx* __restrict__ Rp, size_t ldt, const double* __restrict__ dt,
+                              int n_t, double q0, double q1, double q2, cplx* __restrict__ R0) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_t) return;
+  const cplx a = Rp[t], b = Rp[ldt + t], c = Rp[2 * ldt + t];
+  const double pr = q0 * a.re + q1 * b.re + q2 * c.re, pi = q0 * a.im + q1 * b.im + q2 * c.im;
+  const double id = 1.0 / dt[t];
+  R0[t] = t < n_t / 2 ? cplx{pi * id, -pr * id} : cplx{-pi * id, pr * id};
+}
+
 __global__ void k_bloch_phase(const double* kf, int n_k, double s0, double s1, double s2,
                               const int* cells, int n_t, cplx* ph) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -471,6 +586,18 @@ void launch_cell_ft(const ShellTab& sh, const double* tvec, int n_t, const doubl
   const int blk = 256;
   hipLaunchKernelGGL(k_cell_ft, dim3((unsigned)((total + blk - 1) / blk)), dim3(blk), 0, st, sh,
                      tvec, n_t, Q, n_q, F);
+}
+
+void launch_grad_ft(const ShellTab& sh, const double* tvec, int n_t, cplx* D, hipStream_t st) {
+  const long total = (long)sh.n_sh * sh.n_sh * n_t;
+  hipLaunchKernelGGL(k_grad_ft, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, sh, tvec,
+                     n_t, D);
+}
+
+void launch_optical_row(const cplx* Rp, size_t ldt, const double* dt, int n_t, const double qhat[3],
+                        cplx* R0, hipStream_t st) {
+  hipLaunchKernelGGL(k_optical_row, dim3((unsigned)((n_t + 255) / 256)), dim3(256), 0, st, Rp, ldt,
+                     dt, n_t, qhat[0], qhat[1], qhat[2], R0);
 }
 
 void launch_bloch_phase(const double* k_frac, int n_k, const double shift[3], const int* cells,

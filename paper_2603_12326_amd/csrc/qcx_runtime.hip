@@ -413,12 +413,26 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
 
 // Pair densities of the G list into ctx->d_R (shared by qcx_pair_density and
 // the chunks of qcx_loss_diag, which has no G = 0 requirement).
-static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out, bool need_g0) {
+// Pair densities R[G][t] for the G list (G = 0 first when need_g0).  With
+// qhat (the optical limit, App. C) the states must have q = 0; the k states
+// serve on both sides, and the G = 0 row is replaced by its q -> 0 limit
+// divided by |q| (k.p form, launch_optical_row) with Coulomb factor sqrt(4 pi).
+static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out, bool need_g0,
+                             const double* qhat = nullptr) {
   if (!ctx) return QCX_EINVAL;
   if (!ctx->have_states) return fail(ctx, QCX_ESTATE, "set_states first");
   if (n_G < 1 || n_G > 4096 || !G_int) return fail(ctx, QCX_EINVAL, "need 1 <= n_G <= 4096");
   if (need_g0 && (G_int[0] != 0 || G_int[1] != 0 || G_int[2] != 0))
     return fail(ctx, QCX_EINVAL, "G_int[0] must be (0,0,0)");
+  const bool optical = qhat != nullptr;
+  double qh[3] = {0.0, 0.0, 0.0};
+  if (optical) {
+    if (ctx->q[0] != 0.0 || ctx->q[1] != 0.0 || ctx->q[2] != 0.0)
+      return fail(ctx, QCX_EINVAL, "the optical limit needs states set with q = 0");
+    const double nq = std::sqrt(qhat[0] * qhat[0] + qhat[1] * qhat[1] + qhat[2] * qhat[2]);
+    if (!(nq > 0.0) || !std::isfinite(nq)) return fail(ctx, QCX_EINVAL, "qhat must be a nonzero direction");
+    for (int x = 0; x < 3; ++x) qh[x] = qhat[x] / nq;
+  }
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
   hipStream_t st = ctx->stream;
@@ -430,6 +444,10 @@ static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_
       for (int j = 0; j < 3; ++j) v += G_int[3 * g + j] * ctx->rec[3 * j + x];
       Q[3 * g + x] = v;
       n2 += v * v;
+    }
+    if (optical && g == 0) {
+      vq[0] = sqrt(4.0 * kPi);  // |q| went into the k.p row
+      continue;
     }
     if (!(n2 > 0.0)) return fail(ctx, QCX_EINVAL, "q + G vanishes for G index " + std::to_string(g));
     vq[g] = sqrt(4.0 * kPi) / sqrt(n2);
@@ -452,14 +470,38 @@ static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_
   launch_cell_ft(shell_tab(ctx), ctx->d_tvec.as<double>(), nT, ctx->d_Q.as<double>(), n_G,
                  ctx->d_F.as<cplx>(), st);
   LAUNCHCK("cell_ft");
+  // the bra states: k + q, or in the optical limit k itself
+  const cplx* bra = optical ? ctx->d_Ck.as<cplx>() : ctx->d_Ckq.as<cplx>();
   for (int k0 = 0; k0 < ctx->n_k; k0 += kc) {
     const int nk = std::min(kc, ctx->n_k - k0);
     launch_phase_sum(ctx->d_F.as<cplx>(), ctx->d_ph.as<cplx>(), nT, n_G, (int)nee, k0, nk,
                      ctx->d_M.as<cplx>(), st);
-    launch_band_contract(ctx->d_M.as<cplx>(), ctx->d_Ck.as<cplx>(), ctx->d_Ckq.as<cplx>(), nao,
-                         ctx->n_b, ctx->n_occ, ctx->n_k, k0, nk, n_G, ctx->d_R.as<cplx>(),
-                         ctx->ldt, st);
+    launch_band_contract(ctx->d_M.as<cplx>(), ctx->d_Ck.as<cplx>(), bra, nao, ctx->n_b,
+                         ctx->n_occ, ctx->n_k, k0, nk, n_G, ctx->d_R.as<cplx>(), ctx->ldt, st);
     LAUNCHCK("phase_sum/band_contract");
+  }
+  if (optical) {
+    // transitions at the same k; then P = C^H D(k) C for the three components
+    // (the band contraction with the gradient matrices in place of M) and the
+    // k.p row
+    launch_transition_energies(ctx->d_Ek.as<double>(), ctx->d_Ek.as<double>(), ctx->n_k, ctx->n_b,
+                               ctx->n_occ, ctx->d_dt.as<double>(), st);
+    ctx->dt_valid = false;
+    HIPCK(ctx->d_Fg.reserve(sizeof(cplx) * nT * 3 * nee));
+    HIPCK(ctx->d_Rp.reserve(sizeof(cplx) * 3 * ctx->ldt));
+    launch_grad_ft(shell_tab(ctx), ctx->d_tvec.as<double>(), nT, ctx->d_Fg.as<cplx>(), st);
+    const int kg = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, per_k * kc / (3 * sizeof(cplx) * nee)));
+    for (int k0 = 0; k0 < ctx->n_k; k0 += kg) {
+      const int nk = std::min(kg, ctx->n_k - k0);
+      launch_phase_sum(ctx->d_Fg.as<cplx>(), ctx->d_ph.as<cplx>(), nT, 3, (int)nee, k0, nk,
+                       ctx->d_M.as<cplx>(), st);
+      launch_band_contract(ctx->d_M.as<cplx>(), ctx->d_Ck.as<cplx>(), ctx->d_Ck.as<cplx>(), nao,
+                           ctx->n_b, ctx->n_occ, ctx->n_k, k0, nk, 3, ctx->d_Rp.as<cplx>(), ctx->ldt,
+                           st);
+    }
+    launch_optical_row(ctx->d_Rp.as<cplx>(), ctx->ldt, ctx->d_dt.as<double>(), ctx->n_t, qh,
+                       ctx->d_R.as<cplx>(), st);
+    LAUNCHCK("optical limit");
   }
   HIPCK(span_end(ctx, sp_rho));
   if (rho_out) {
@@ -472,6 +514,13 @@ static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_
 
 int qcx_pair_density(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_out) {
   return pair_density_impl(ctx, n_G, G_int, rho_out, true);
+}
+
+int qcx_pair_density_optical(qcx_ctx* ctx, int n_G, const int* G_int, const double* qhat,
+                             void* rho_out) {
+  if (!ctx) return QCX_EINVAL;
+  if (!qhat) return fail(ctx, QCX_EINVAL, "qhat is NULL");
+  return pair_density_impl(ctx, n_G, G_int, rho_out, true, qhat);
 }
 
 int qcx_loss_diag(qcx_ctx* ctx, int n_G, const int* G_int, int n_w, const double* w_eV,

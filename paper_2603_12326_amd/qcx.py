@@ -50,6 +50,7 @@ _SIGS = {
     "qcx_set_cell_basis": [_P, _P, _I, _P, _I, _P, _P, _P, _I, _I],
     "qcx_set_states": [_P, _P, _I, _P, _I, _I, _P, _P, _P, _P, _I],
     "qcx_pair_density": [_P, _I, _P, _P],
+    "qcx_pair_density_optical": [_P, _I, _P, _P, _P],
     "qcx_chi0": [_P, _I, _P, _D, _I, _I, _P],
     "qcx_eps_inv": [_P, _I, _P, _P],
     "qcx_loss": [_P, _P, _I],
@@ -229,6 +230,19 @@ class Context:
             n_c = self.n_bands - self.n_occ
             out = _dev_ptr(rho_out, "c128", 2 * self.n_k * self.n_occ * n_c * len(G), "rho_out")
         self._check(self.lib.qcx_pair_density(self._h, len(G), _ptr_host(G), out))
+        self.n_g = len(G)
+
+    def pair_density_optical(self, G_int, qhat, rho_out=None):
+        """Pair densities as q -> 0 along qhat (qcx_pair_density_optical); the
+        states must have been set with q = 0."""
+        G = _host(G_int, np.int32).reshape(-1, 3)
+        qh = _host(qhat, np.float64).reshape(3)
+        out = None
+        if rho_out is not None:
+            n_c = self.n_bands - self.n_occ
+            out = _dev_ptr(rho_out, "c128", 2 * self.n_k * self.n_occ * n_c * len(G), "rho_out")
+        self._check(self.lib.qcx_pair_density_optical(self._h, len(G), _ptr_host(G), _ptr_host(qh),
+                                                      out))
         self.n_g = len(G)
 
     def chi0(self, w_eV, eta_eV: float, precision=FP64, headwings_fp64: bool = True,

@@ -1,0 +1,96 @@
+"""Optical limit (qcx_pair_density_optical) against the oracle's App. C route.
+
+The states are set with q = 0; the library's G = 0 row is the k.p limit of the
+pair densities over |q| (Gaussian gradient integrals, Bloch sum, band
+contraction), the other rows the q = 0 pair densities.  Bars: pair densities
+1e-12 (FP64), loss 1e-10 (FP64 route and Kramers-Kronig route), 1e-4
+(split-BF16 bulk), on the tiny s/p/d cell and the smallest workload, for a
+direction off the axes.
+"""
+import numpy as np
+import pytest
+
+from oracle import rpa
+from tests.gpu_helpers import normwise, relmax
+
+pytestmark = pytest.mark.gpu
+
+QHAT = (0.3, -0.5, 0.81)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2603_12326_amd import Context
+
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _set_q0(ctx, wl):
+    st = wl.states(0)
+    b = wl.basis
+    ctx.set_cell_basis(wl.cell.lat, wl.cell.xyz, b.shell_atom, b.shell_l, b.shell_exp, 1,
+                       wl.lattice_range)
+    ctx.set_states(np.zeros(3), wl.k_frac, wl.n_occ, st.C_k, st.E_k, st.C_k, st.E_k)
+    return st
+
+
+def _vol(wl):
+    return abs(float(np.linalg.det(np.asarray(wl.cell.lat, np.float64))))
+
+
+@pytest.mark.parametrize("name", ["tiny", "cfg1"])
+def test_optical_against_oracle(ctx, request, name):
+    import torch
+
+    wl = request.getfixturevalue(name)
+    st = _set_q0(ctx, wl)
+    G = wl.G_int
+    n_c = st.C_k.shape[2] - wl.n_occ
+    rho = torch.empty((2, len(wl.k_frac), wl.n_occ, n_c, len(G)), dtype=torch.complex128,
+                      device="cuda")
+    ctx.pair_density_optical(G, QHAT, rho)
+    R = rpa.pair_densities_optical(wl.cell, wl.basis, wl.lattice_range, wl.k_frac, G, st.C_k,
+                                   st.E_k, wl.n_occ, QHAT)
+    rg = rho.cpu().numpy()
+    e0, e1 = relmax(rg[..., 0], R[..., 0]), relmax(rg[..., 1:], R[..., 1:])
+    print(name, "k.p row", e0, "G != 0 rows", e1)
+    assert e0 < 1e-12 and e1 < 1e-12
+    w = wl.w_eV[::2]
+    W = rpa.transition_weights(st.E_k, st.E_k, wl.n_occ, w, wl.eta_eV, _vol(wl))
+    Lref = rpa.loss_lfe(rpa.epsilon_optical(rpa.chi0(R, W), wl.cell.lat, G))
+    for prec, tol in (("fp64", 1e-10), ("split_bf16", 1e-4)):
+        ctx.chi0(w, wl.eta_eV, prec, True)
+        ctx.eps_inv(True)
+        e = normwise(ctx.loss(), Lref)
+        print(name, prec, "loss", e)
+        assert e < tol
+    # the Kramers-Kronig route on the same optical pair densities
+    ctx.chi0_kk(w, wl.eta_eV, 0.05)
+    ctx.eps_inv(True)
+    ck = rpa.chi0_kk(R, st.E_k, st.E_k, wl.n_occ, w, wl.eta_eV, 0.05, _vol(wl))
+    e = normwise(ctx.loss(), rpa.loss_lfe(rpa.epsilon_optical(ck, wl.cell.lat, G)))
+    print(name, "kk loss", e)
+    assert e < 1e-10
+
+
+def test_optical_errors(ctx, cfg1):
+    from paper_2603_12326_amd import QcxError
+    from paper_2603_12326_amd import qcx as q
+    from tests.gpu_helpers import set_inputs
+
+    set_inputs(ctx, cfg1)                     # q != 0
+    with pytest.raises(QcxError) as e:
+        ctx.pair_density_optical(cfg1.G_int, QHAT)
+    assert e.value.code == q.EINVAL
+    _set_q0(ctx, cfg1)
+    with pytest.raises(QcxError) as e:
+        ctx.pair_density_optical(cfg1.G_int, (0.0, 0.0, 0.0))
+    assert e.value.code == q.EINVAL
+    with pytest.raises(QcxError) as e:        # q + G = 0 without the optical limit
+        ctx.pair_density(cfg1.G_int)
+    assert e.value.code == q.EINVAL
