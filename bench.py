@@ -23,6 +23,8 @@ route on the same inputs.  --workload rates adds to the composite workload
 the momentum binning of all ~71,000 (q + G) entries (shells of 0.02 bohr^-1
 to 25 bohr^-1, 9 x 16 angular bins), the isotropic S(w, q) and the halo
 rate for a 1 GeV dark-matter particle (heavy and light mediator).
+--workload optical runs the same cell at q -> 0 (App. C: k.p head and wings)
+along x, y and z per step.
 """
 from __future__ import annotations
 
@@ -60,7 +62,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample-w", type=int, default=400)
-    ap.add_argument("--workload", choices=["si-ng113", "mixed-batch", "composite", "kk", "rates"],
+    ap.add_argument("--workload",
+                    choices=["si-ng113", "mixed-batch", "composite", "kk", "rates", "optical"],
                     default="si-ng113")
     ap.add_argument("--kk-bin", type=float, default=0.025, help="bin width (eV) of --workload kk")
     ap.add_argument("--calib-copy", action="store_true",
@@ -685,6 +688,94 @@ def main_rates(args):
     print(json.dumps(out))
 
 
+def main_optical(args):
+    """Optical limit of the Si-like N_G = 113 workload along x, y, z."""
+    import torch
+
+    from paper_2603_12326_amd import Context, build_info
+    from synth import make_config2
+
+    wl = make_config2(n_q=1)
+    st0 = wl.states(0)
+    dev = "cuda"
+    C = torch.from_numpy(np.ascontiguousarray(st0.C_k)).to(dev)
+    E = torch.from_numpy(np.ascontiguousarray(st0.E_k)).to(dev)
+    kf = torch.from_numpy(np.ascontiguousarray(wl.k_frac)).to(dev)
+    n_g, n_w = len(wl.G_int), len(wl.w_eV)
+    dirs = np.eye(3)
+    loss = [torch.empty((n_w, n_g), dtype=torch.float64, device=dev) for _ in dirs]
+    ctx = Context(0)
+    b = wl.basis
+    ctx.set_cell_basis(wl.cell.lat, wl.cell.xyz, b.shell_atom, b.shell_l, b.shell_exp, 1, 1)
+
+    def step():
+        ctx.set_states(np.zeros(3), kf, wl.n_occ, C, E, C, E)
+        for i, qh in enumerate(dirs):
+            ctx.pair_density_optical(wl.G_int, qh)
+            ctx.chi0(wl.w_eV, wl.eta_eV, "split_bf16", True)
+            ctx.eps_inv(True)
+            ctx.loss(loss[i])
+
+    log(f"optical: {args.warmup} warmup + {args.steps} timed steps")
+    for _ in range(max(1, args.warmup)):
+        step()
+    ctx.sync()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    st = ctx.stage_times()
+    ctx.set_timing(False)
+    points = 3 * n_w
+    L = [x.cpu().numpy() for x in loss]
+    out = {
+        "metric": "optical-limit (direction, w) loss points/s at N_G=113 (k.p head and wings)",
+        "value": points * args.steps / sec,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "Si-like fcc a=10.26, 28 GTO, 4+16 bands, 8^3 k, q -> 0 along x, y, z, "
+                               "N_G=113, 400 w over 0-60 eV, eta=0.1 eV, split-BF16 bulk, FP64 "
+                               "head/wings and inversion"},
+        "stages_ms_per_step": {k: (v / args.steps if k.endswith("_ms") else v) for k, v in st.items()},
+        "build": build_info(),
+    }
+    out["loss_G0_peak_eV"] = [float(wl.w_eV[int(np.argmax(x[:, 0]))]) for x in L]
+    if not args.no_cpu_baseline:
+        from oracle import rpa
+        KS = 8
+        log(f"cpu baseline (oracle optical limit along x, every {KS}th k point, 400 w)")
+        t0 = time.perf_counter()
+        kfs = wl.k_frac[::KS]
+        R = rpa.pair_densities_optical(wl.cell, wl.basis, wl.lattice_range, kfs, wl.G_int,
+                                       st0.C_k[::KS], st0.E_k[::KS], wl.n_occ, dirs[0])
+        vol = abs(float(np.linalg.det(np.asarray(wl.cell.lat))))
+        W = rpa.transition_weights(st0.E_k[::KS], st0.E_k[::KS], wl.n_occ, wl.w_eV, wl.eta_eV, vol)
+        rpa.loss_lfe(rpa.epsilon_optical(rpa.chi0(R, W), wl.cell.lat, wl.G_int))
+        dt = time.perf_counter() - t0
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        except Exception:
+            threads = os.cpu_count()
+        out["cpu_baseline"] = dict(
+            value=n_w / (dt * KS), unit="points/s", cores=int(threads), kind="oracle",
+            sample=f"direction x, {len(kfs)} of {len(wl.k_frac)} k points (every {KS}th), all 113 G "
+                   f"and 400 w, {dt:.1f} s; scaled by the k fraction (linear in the transitions)")
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -700,6 +791,8 @@ def main():
         return main_kk(args)
     if args.workload == "rates":
         return main_rates(args)
+    if args.workload == "optical":
+        return main_optical(args)
     import torch
 
     from paper_2603_12326_amd import Context, build_info
