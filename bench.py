@@ -49,8 +49,7 @@ HARTREE_EV = 27.211386245988
 # (one pass each) and scaled by the same counters on a copy of known size;
 # valid only while the kernel source hashes to the recorded value.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_bf16_config2_hbm_traffic.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_12326_amd", "csrc", f)
-                  for f in ("k_chi0.hip", "common.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_12326_amd", "csrc", f) for f in ("k_chi0.hip",)]
 
 
 def parse():
