@@ -81,8 +81,9 @@ struct qcx_ctx {
   // transition energies copied to pinned host memory right after
   // qcx_set_states computes them, once the Kramers-Kronig route has been
   // used (its host-side sort then overlaps the pair densities on the device)
-  // rocBLAS handle for the plain FP64 product of the Kramers-Kronig route
-  // (created on first use, bound to the context's stream)
+  // rocBLAS handle for the plain products (the lattice Bloch sums of the pair
+  // densities, the Kramers-Kronig transform), created on first use and bound
+  // to the context's stream
   rocblas_handle blas = nullptr;
   double* h_dt = nullptr;
   size_t h_dt_cap = 0;

@@ -413,6 +413,35 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
 
 // Pair densities of the G list into ctx->d_R (shared by qcx_pair_density and
 // the chunks of qcx_loss_diag, which has no G = 0 requirement).
+// The context's rocBLAS handle on its stream (created on first use).
+static int ensure_blas(qcx_ctx* ctx) {
+  if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
+    ctx->blas = nullptr;
+    return fail(ctx, QCX_EDEVICE, "rocblas_create_handle failed");
+  }
+  if (rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success)
+    return fail(ctx, QCX_EDEVICE, "rocblas_set_stream failed");
+  return QCX_OK;
+}
+
+// M[k][g][e] = sum_T ph[k0 + k][T] F[T][g][e] for k < nk: the lattice Bloch
+// sum is a plain complex product [nk x n_t] [n_t x n_q n_e] (column-major
+// view M^T = F^T ph^T), done by rocBLAS zgemm.
+static int phase_sum_blas(qcx_ctx* ctx, const cplx* F, const cplx* ph, int n_t, int n_q, int n_e,
+                          int k0, int nk, cplx* M) {
+  if (int rc = ensure_blas(ctx)) return rc;
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  const int n_el = n_q * n_e;
+  const rocblas_status bs =
+      rocblas_zgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, n_el, nk, n_t, &one,
+                    reinterpret_cast<const rocblas_double_complex*>(F), n_el,
+                    reinterpret_cast<const rocblas_double_complex*>(ph + (size_t)k0 * n_t), n_t,
+                    &zero, reinterpret_cast<rocblas_double_complex*>(M), n_el);
+  if (bs != rocblas_status_success)
+    return fail(ctx, QCX_EDEVICE, "rocblas_zgemm failed (status " + std::to_string((int)bs) + ")");
+  return QCX_OK;
+}
+
 // Pair densities R[G][t] for the G list (G = 0 first when need_g0).  With
 // qhat (the optical limit, App. C) the states must have q = 0; the k states
 // serve on both sides, and the G = 0 row is replaced by its q -> 0 limit
@@ -474,8 +503,9 @@ static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_
   const cplx* bra = optical ? ctx->d_Ck.as<cplx>() : ctx->d_Ckq.as<cplx>();
   for (int k0 = 0; k0 < ctx->n_k; k0 += kc) {
     const int nk = std::min(kc, ctx->n_k - k0);
-    launch_phase_sum(ctx->d_F.as<cplx>(), ctx->d_ph.as<cplx>(), nT, n_G, (int)nee, k0, nk,
-                     ctx->d_M.as<cplx>(), st);
+    if (int rc = phase_sum_blas(ctx, ctx->d_F.as<cplx>(), ctx->d_ph.as<cplx>(), nT, n_G, (int)nee,
+                                k0, nk, ctx->d_M.as<cplx>()))
+      return rc;
     launch_band_contract(ctx->d_M.as<cplx>(), ctx->d_Ck.as<cplx>(), bra, nao, ctx->n_b,
                          ctx->n_occ, ctx->n_k, k0, nk, n_G, ctx->d_R.as<cplx>(), ctx->ldt, st);
     LAUNCHCK("phase_sum/band_contract");
@@ -493,8 +523,9 @@ static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_
     const int kg = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, per_k * kc / (3 * sizeof(cplx) * nee)));
     for (int k0 = 0; k0 < ctx->n_k; k0 += kg) {
       const int nk = std::min(kg, ctx->n_k - k0);
-      launch_phase_sum(ctx->d_Fg.as<cplx>(), ctx->d_ph.as<cplx>(), nT, 3, (int)nee, k0, nk,
-                       ctx->d_M.as<cplx>(), st);
+      if (int rc = phase_sum_blas(ctx, ctx->d_Fg.as<cplx>(), ctx->d_ph.as<cplx>(), nT, 3, (int)nee,
+                                  k0, nk, ctx->d_M.as<cplx>()))
+        return rc;
       launch_band_contract(ctx->d_M.as<cplx>(), ctx->d_Ck.as<cplx>(), ctx->d_Ck.as<cplx>(), nao,
                            ctx->n_b, ctx->n_occ, ctx->n_k, k0, nk, 3, ctx->d_Rp.as<cplx>(), ctx->ldt,
                            st);
@@ -975,12 +1006,7 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
                    ctx->d_kk_K.as<double>(), st);
   // C64[2 n_w][2 n_pairs] = Kt[2 n_w][rows] S[rows][2 n_pairs], row-major:
   // the column-major product C64^T = S^T Kt^T
-  if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
-    ctx->blas = nullptr;
-    return fail(ctx, QCX_EDEVICE, "rocblas_create_handle failed");
-  }
-  if (rocblas_set_stream(ctx->blas, st) != rocblas_status_success)
-    return fail(ctx, QCX_EDEVICE, "rocblas_set_stream failed");
+  if (int rc = ensure_blas(ctx)) return rc;
   const double one = 1.0, zero = 0.0;
   const int nc = (int)(2 * n_pairs);
   HIPCK(span_begin(ctx, 6, &sp_tr));
