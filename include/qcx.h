@@ -453,11 +453,18 @@ int qcx_qbin_rate_halo(qcx_qbin* b, const double* w_eV, const double* S_iso, con
  * for shapes whose single launch is estimated above 0.5 s.
  * Errors: QCX_EINVAL (mode). */
 int qcx_set_autotune(qcx_ctx* ctx, int mode);
-/* Configuration of the last bulk launch: cfg = {K split, pipeline stages,
+/* Configuration of the last bulk launch: cfg = {K split, pipeline (2 or 3 LDS stages;
+ * 4: three stages with the transition slab one step ahead of the weights),
  * row fragments per wave} (zeros if there was no bulk), and the time spent
  * tuning in that call (ms, 0 when the shape was cached).  Errors:
  * QCX_ESTATE before qcx_chi0. */
 int qcx_bulk_config(qcx_ctx* ctx, int cfg[3], double* tune_ms);
+/* Force the LDS pipeline of the chi0 bulk kernel (2, 3 or 4 as reported by
+ * qcx_bulk_config; the K split stays heuristic and tuning is skipped), or
+ * restore the tuned / heuristic choice with 0.  For tests and experiments.
+ * Errors: QCX_EINVAL (other values; at qcx_chi0 if the pipeline does not fit
+ * the shape). */
+int qcx_set_bulk_pipeline(qcx_ctx* ctx, int nst);
 
 /* Per-stage device time of the most recent calls, in milliseconds, measured
  * with HIP events on the context's stream (enabled by qcx_set_timing):

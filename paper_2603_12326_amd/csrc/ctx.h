@@ -57,7 +57,9 @@ struct qcx_ctx {
   double eta = 0.0;
   Chi0Geom geom{};
   int ks64 = 1, n_pairs64 = 0;
-  int bulk_nst = 2;           // LDS pipeline stages of the last bulk launch
+  int bulk_nst = 2;           // LDS pipeline of the last bulk launch (2, 3; 4: three
+                              // stages with the slab one step ahead of the weights)
+  int force_nst = 0;          // 0: tuned or heuristic pipeline; 2..4: this one
   int bulk_af = 4;            // row fragments per wave of the last bulk launch
   int autotune = 1;           // 0: fixed heuristic, 1: time candidates per shape
   double tune_ms = 0.0;       // time spent tuning in the last qcx_chi0

@@ -254,13 +254,20 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
   // Copies of K step tb into stage d: MAXR + MAXA per wave, always.  R
   // chunks beyond the slab copy a valid row into the unused tail of the
   // stage's R buffer (RCH = 4 MAXR chunks).
-  auto stage = [&](int tb, L& d) {
+  auto stage_r = [&](int tb, L& d) {
 #pragma unroll
     for (int i = 0; i < MAXR; ++i)
       lds_dma16(R32 + (size_t)tb * nr4 + r_off[i], d.r + 64 * (wave + 4 * i));
+  };
+  auto stage_a = [&](int tb, L& d) {
 #pragma unroll
     for (int i = 0; i < MAXA; ++i)
       lds_dma16(a_src[i] + (size_t)tb * ASTEP, d.a + 64 * a_chunk(i));
+  };
+  // RAHEAD (NST = 4): a stage holds the slab of the step after its weights
+  auto stage = [&](int tb, L& d) {
+    stage_r(NST == 4 ? min(tb + 1, tb0 + steps - 1) : tb, d);
+    stage_a(tb, d);
   };
   constexpr int NCOPY = MAXR + MAXA;  // copies per wave per stage (vmcnt of one stage)
   // s_waitcnt with only the vector-memory counter limited (expcnt 7 and
@@ -279,31 +286,39 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
     }
   }
 
-  auto compute = [&](const L& cur) {
-    // B operand: P_t(G, G') for this lane's pair and 8 transitions (FP32)
-    const float4* rG = cur.r + G * SLAB_LD4 + 4 * h;    // 8 complex = 4 float4
-    const float4* rGp = cur.r + Gp * SLAB_LD4 + 4 * h;
+  // B operand of one K step: P_t(G, G') for this lane's pair and 8
+  // transitions, from the slab held by `src` (FP32, or its bf16 hi/lo split)
+  struct Bops {
     float pre[8], pim[8];
+    bf16x8 rh, rl, ih, il;
+  };
+  auto formB = [&](const L& src, Bops& o) {
+    const float4* rG = src.r + G * SLAB_LD4 + 4 * h;    // 8 complex = 4 float4
+    const float4* rGp = src.r + Gp * SLAB_LD4 + 4 * h;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const float4 xg = rG[i], yg = rGp[i];
-      pre[2 * i] = xg.x * yg.x + xg.y * yg.y;
-      pim[2 * i] = xg.x * yg.y - xg.y * yg.x;
-      pre[2 * i + 1] = xg.z * yg.z + xg.w * yg.w;
-      pim[2 * i + 1] = xg.z * yg.w - xg.w * yg.z;
+      o.pre[2 * i] = xg.x * yg.x + xg.y * yg.y;
+      o.pim[2 * i] = xg.x * yg.y - xg.y * yg.x;
+      o.pre[2 * i + 1] = xg.z * yg.z + xg.w * yg.w;
+      o.pim[2 * i + 1] = xg.z * yg.w - xg.w * yg.z;
     }
-    const float4* As = cur.a;
     if constexpr (BF16) {
-      bf16x8 bre_hi, bre_lo, bim_hi, bim_lo;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const __bf16 rh = (__bf16)pre[i];
-        const __bf16 ih = (__bf16)pim[i];
-        bre_hi[i] = rh;
-        bim_hi[i] = ih;
-        bre_lo[i] = (__bf16)(pre[i] - (float)rh);
-        bim_lo[i] = (__bf16)(pim[i] - (float)ih);
+        const __bf16 rh = (__bf16)o.pre[i];
+        const __bf16 ih = (__bf16)o.pim[i];
+        o.rh[i] = rh;
+        o.ih[i] = ih;
+        o.rl[i] = (__bf16)(o.pre[i] - (float)rh);
+        o.il[i] = (__bf16)(o.pim[i] - (float)ih);
       }
+    }
+  };
+  // the MFMAs of one K step: A fragments of `cur`, B operand given
+  auto mfma = [&](const L& cur, const Bops& B) {
+    const float4* As = cur.a;
+    if constexpr (BF16) {
       // three sweeps over the 2*AF independent accumulators, so that no MFMA
       // waits on the one issued just before it
       bf16x8 ah[AF];
@@ -311,19 +326,19 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
       for (int f = 0; f < AF; ++f) ah[f] = __builtin_bit_cast(bf16x8, As[f * 128 + lane]);
 #pragma unroll
       for (int f = 0; f < AF; ++f) {
-        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], bre_hi, acc[f][0], 0, 0, 0);
-        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], bim_hi, acc[f][1], 0, 0, 0);
+        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], B.rh, acc[f][0], 0, 0, 0);
+        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], B.ih, acc[f][1], 0, 0, 0);
       }
 #pragma unroll
       for (int f = 0; f < AF; ++f) {
-        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], bre_lo, acc[f][0], 0, 0, 0);
-        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], bim_lo, acc[f][1], 0, 0, 0);
+        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], B.rl, acc[f][0], 0, 0, 0);
+        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], B.il, acc[f][1], 0, 0, 0);
       }
 #pragma unroll
       for (int f = 0; f < AF; ++f) {
         const bf16x8 al = __builtin_bit_cast(bf16x8, As[f * 128 + 64 + lane]);
-        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bre_hi, acc[f][0], 0, 0, 0);
-        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bim_hi, acc[f][1], 0, 0, 0);
+        acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, B.rh, acc[f][0], 0, 0, 0);
+        acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, B.ih, acc[f][1], 0, 0, 0);
       }
     } else {
 #pragma unroll
@@ -332,11 +347,16 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
         const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], pre[s], acc[f][0], 0, 0, 0);
-          acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], pim[s], acc[f][1], 0, 0, 0);
+          acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], B.pre[s], acc[f][0], 0, 0, 0);
+          acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], B.pim[s], acc[f][1], 0, 0, 0);
         }
       }
     }
+  };
+  auto compute = [&](const L& cur) {
+    Bops B;
+    formB(cur, B);
+    mfma(cur, B);
   };
 
   // Workgroup barrier without the release fence of __syncthreads(): that
@@ -358,16 +378,57 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
     barrier();
   };
 
-  stage(tb0, s0);
-  if constexpr (NST == 3) {
-    stage(min(tb0 + 1, tb_last), s1);
+  // RAHEAD (NST = 4, three LDS stages): step st issues the weights of st + 2
+  // and the slab of st + 3, forms the B operand of st + 1 from its own stage
+  // and runs the MFMAs of st with the B operand formed one step earlier, so
+  // the VALU work of the next step overlaps the matrix work of this one.
+  Bops Bc;
+  auto one4 = [&](int st, const L& cur, L& nxt) {
+    stage(min(tb0 + st + 2, tb_last), nxt);
+    Bops Bn;
+    mfma(cur, Bc);
+    if (st + 1 < steps) formB(cur, Bn);
+    if (st + 1 < steps) Bc = Bn;
+    // interleave: each MFMA followed by a few VALU and LDS-read instructions
+    // of the next step's B operand
+#pragma unroll
+    for (int i = 0; i < 6 * AF; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
+    }
+    __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(WAIT_ONE);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    barrier();
+  };
+
+  if constexpr (NST == 4) {
+    stage_r(tb0, s2);                         // slab of the first step
+    stage(tb0, s0);
+    stage(min(tb0 + 1, tb_last), s1);
+    __builtin_amdgcn_s_waitcnt(WAIT_ONE);     // all but the last stage landed
+    barrier();
+    formB(s2, Bc);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    barrier();                                // s2 is refilled by step 0
   } else {
-    __builtin_amdgcn_s_waitcnt(WAIT_ALL);
-  }
-  barrier();
-  for (int st = 0; st < steps; st += NST) {
+    stage(tb0, s0);
     if constexpr (NST == 3) {
+      stage(min(tb0 + 1, tb_last), s1);
+      __builtin_amdgcn_s_waitcnt(WAIT_ONE);
+    } else {
+      __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+    }
+    barrier();
+  }
+  constexpr int NB = NST == 4 ? 3 : NST;  // LDS stages
+  for (int st = 0; st < steps; st += NB) {
+    if constexpr (NST == 4) {
+      one4(st, s0, s2);
+      if (st + 1 < steps) one4(st + 1, s1, s0);
+      if (st + 2 < steps) one4(st + 2, s2, s1);
+    } else if constexpr (NST == 3) {
       one(st, s0, s2);
       if (st + 1 < steps) one(st + 1, s1, s0);
       if (st + 2 < steps) one(st + 2, s2, s1);
@@ -401,9 +462,9 @@ k_bulk(const float4* __restrict__ Ahi, const float4* __restrict__ Alo,
        const int* __restrict__ rows, Chi0Geom g, float* __restrict__ C) {
   using L = BulkStage<4 * MAXR, 2 * AF>;
   const Blk3 bk = xcd_block(g.n_bulkp / 128, g.c_rows / (32 * AF), g.ksplit);
-  if constexpr (NST == 3) {
+  if constexpr (NST >= 3) {
     __shared__ L s0, s1, s2;
-    bulk_tile<BF16, AF, MAXR, 3, GATHER>(Ahi, Alo, R32, pairs, rows, g, C, bk, s0, s1, s2);
+    bulk_tile<BF16, AF, MAXR, NST, GATHER>(Ahi, Alo, R32, pairs, rows, g, C, bk, s0, s1, s2);
   } else {
     __shared__ L s0, s1;
     bulk_tile<BF16, AF, MAXR, 2, GATHER>(Ahi, Alo, R32, pairs, rows, g, C, bk, s0, s1, s0);
@@ -439,7 +500,8 @@ __global__ void k_set_int(int* p, int v) { *p = v; }
 size_t lds_bytes_of(int n_g, int af, int nst) {
   const int maxr = bulk_maxr(n_g);
   if (maxr == 0) return (size_t)1 << 40;  // no bucket: never fits
-  return (size_t)nst * sizeof(float4) * 64 * (4 * maxr + 2 * af);
+  // nst = 4 is the three-stage pipeline with the slab one step ahead
+  return (size_t)(nst == 4 ? 3 : nst) * sizeof(float4) * 64 * (4 * maxr + 2 * af);
 }
 
 template <bool BF16, int AF, int NST>
@@ -725,10 +787,14 @@ int bulk_row_frags(const Chi0Geom& g) {
 void launch_bulk_f32(const float* Aw, const float* R32, const int* pairs, const int* rows,
                      const Chi0Geom& g, int nst, float* C, hipStream_t st) {
   const bool af5 = g.n_rowsp % 160 == 0 && bulk_row_frags(g) == 5;
-  if (af5 && nst == 3)
+  if (af5 && nst == 4)
+    launch_bulk_t<false, 5, 4>(Aw, nullptr, R32, pairs, rows, g, C, st);
+  else if (af5 && nst == 3)
     launch_bulk_t<false, 5, 3>(Aw, nullptr, R32, pairs, rows, g, C, st);
   else if (af5)
     launch_bulk_t<false, 5, 2>(Aw, nullptr, R32, pairs, rows, g, C, st);
+  else if (nst == 4)
+    launch_bulk_t<false, 4, 4>(Aw, nullptr, R32, pairs, rows, g, C, st);
   else if (nst == 3)
     launch_bulk_t<false, 4, 3>(Aw, nullptr, R32, pairs, rows, g, C, st);
   else
@@ -739,10 +805,14 @@ void launch_bulk_bf16(const uint16_t* Ahi, const uint16_t* Alo, const float* R32
                       const int* pairs, const int* rows, const Chi0Geom& g, int nst, float* C,
                       hipStream_t st) {
   const bool af5 = g.n_rowsp % 160 == 0 && bulk_row_frags(g) == 5;
-  if (af5 && nst == 3)
+  if (af5 && nst == 4)
+    launch_bulk_t<true, 5, 4>(Ahi, Alo, R32, pairs, rows, g, C, st);
+  else if (af5 && nst == 3)
     launch_bulk_t<true, 5, 3>(Ahi, Alo, R32, pairs, rows, g, C, st);
   else if (af5)
     launch_bulk_t<true, 5, 2>(Ahi, Alo, R32, pairs, rows, g, C, st);
+  else if (nst == 4)
+    launch_bulk_t<true, 4, 4>(Ahi, Alo, R32, pairs, rows, g, C, st);
   else if (nst == 3)
     launch_bulk_t<true, 4, 3>(Ahi, Alo, R32, pairs, rows, g, C, st);
   else

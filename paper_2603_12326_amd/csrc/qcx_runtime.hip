@@ -105,7 +105,7 @@ std::vector<Cand> bulk_candidates(const Chi0Geom& g, int af, int ks_min) {
     if (ks > ks_min && ntb / ks < 4) break;
     if (ks > ks_min && (size_t)ks * g.c_rows * 2 * g.n_bulkp * sizeof(float) > kPartialBudget)
       break;
-    for (int nst = 2; nst <= 3; ++nst)
+    for (int nst = 2; nst <= 4; ++nst)  // 4: three stages, slab one step ahead
       if (bulk_lds_bytes(g.n_g, af, nst) <= kLdsBytes) c.push_back({ks, nst});
   }
   return c;
@@ -180,6 +180,13 @@ int qcx_set_autotune(qcx_ctx* ctx, int mode) {
   if (!ctx) return QCX_EINVAL;
   if (mode != 0 && mode != 1) return fail(ctx, QCX_EINVAL, "mode must be 0 or 1");
   ctx->autotune = mode;
+  return QCX_OK;
+}
+
+int qcx_set_bulk_pipeline(qcx_ctx* ctx, int nst) {
+  if (!ctx) return QCX_EINVAL;
+  if (nst != 0 && (nst < 2 || nst > 4)) return fail(ctx, QCX_EINVAL, "pipeline must be 0, 2, 3 or 4");
+  ctx->force_nst = nst;
   return QCX_OK;
 }
 
@@ -747,6 +754,18 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
         pick = {it->second.ks, it->second.nst};
       else
         tune = ctx->autotune != 0;
+    }
+    if (ctx->force_nst) {  // a pipeline forced by qcx_set_bulk_pipeline
+      tune = false;
+      const int ks = std::max(ks_acc, pick_ksplit(blocks, g.n_tp / KSTEP_T));
+      auto it = std::find_if(cands.begin(), cands.end(), [&](const Cand& c) {
+        return c.nst == ctx->force_nst && c.ks == ks;
+      });
+      if (it == cands.end())
+        it = std::find_if(cands.begin(), cands.end(),
+                          [&](const Cand& c) { return c.nst == ctx->force_nst; });
+      if (it == cands.end()) return fail(ctx, QCX_EINVAL, "the forced bulk pipeline does not fit");
+      pick = *it;
     }
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIPCK(hipStreamIsCapturing(st, &cap));

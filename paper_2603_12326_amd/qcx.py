@@ -59,6 +59,7 @@ _SIGS = {
     "qcx_build_info": [],
     "qcx_set_autotune": [_P, _I],
     "qcx_bulk_config": [_P, _P, _P],
+    "qcx_set_bulk_pipeline": [_P, _I],
     "qcx_run_batch": [_P, _I, _P, _I, _I, _I, _I],
     "qcx_batch_sync": [_P],
     "qcx_batch_config": [_P, _P, _P],
@@ -317,6 +318,10 @@ class Context:
         self._check(self.lib.qcx_bulk_config(self._h, _ptr_host(cfg), ctypes.byref(ms)))
         return dict(ksplit=int(cfg[0]), stages=int(cfg[1]), row_frags=int(cfg[2]),
                     tune_ms=ms.value)
+
+    def set_bulk_pipeline(self, nst: int):
+        """Force the bulk kernel's LDS pipeline (2, 3, 4) or restore the tuned choice (0)."""
+        self._check(self.lib.qcx_set_bulk_pipeline(self._h, int(nst)))
 
     def batch_config(self) -> dict:
         """Plan of the last batch whose first context is this one."""

@@ -180,7 +180,7 @@ def test_autotuned_bulk(ctx, cfg1):
     print("tuned", c1, "then", c2)
     assert c1["tune_ms"] > 0.0 and c2["tune_ms"] == 0.0
     assert (c1["ksplit"], c1["stages"]) == (c2["ksplit"], c2["stages"])
-    assert c1["ksplit"] in (1, 2, 4, 8, 16, 32, 64) and c1["stages"] in (2, 3)
+    assert c1["ksplit"] in (1, 2, 4, 8, 16, 32, 64) and c1["stages"] in (2, 3, 4)
     assert c1["row_frags"] in (4, 5)
     assert np.array_equal(a["loss"], b["loss"])
     ctx.set_autotune(0)
@@ -188,6 +188,25 @@ def test_autotuned_bulk(ctx, cfg1):
     ctx.set_autotune(1)
     for out in (a, h):
         assert normwise(out["loss"], ref["loss"]) < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("nst", [2, 3, 4])
+def test_bulk_pipelines(ctx, cfg1, prec, nst):
+    """Every LDS pipeline of the bulk kernel (two stages, three stages, three
+    stages with the slab one step ahead of the weights) against the oracle,
+    with a frequency count that leaves a ragged last row tile."""
+    w = np.linspace(0.3, 38.0, 61)
+    ref = _oracle(cfg1, w=w)
+    ctx.set_bulk_pipeline(nst)
+    try:
+        out = gpu_solve(ctx, cfg1, precision=prec, w_eV=w)
+        assert ctx.bulk_config()["stages"] == nst
+    finally:
+        ctx.set_bulk_pipeline(0)
+    e = normwise(out["loss"], ref["loss"])
+    print("pipeline", nst, prec, e)
+    assert e < 1e-4
 
 
 @pytest.mark.parametrize("q_frac", [(0.25, 0.0, 0.0), (2.25, 0.0, 0.0), (1.5, 1.5, 1.5)])
