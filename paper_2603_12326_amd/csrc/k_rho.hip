@@ -407,7 +407,9 @@ __global__ void __launch_bounds__(256) k_phase_sum_any(const cplx* __restrict__ 
   }
 }
 
-// Band contraction.  A block owns one k and a contiguous range of G tiles
+// Band contraction in the ket-first order (used when 2 n_occ >= n_b, where it
+// needs fewer multiply-adds than the valence-first kernel below, and when no
+// tile of that kernel fits).  A block owns one k and a contiguous range of G tiles
 // (GT vectors each); C(k) and C(k+q) are staged in LDS once and read as
 // broadcasts.  Per tile:
 //   step 1: T1_G[mu][b] = sum_nu M_G[mu][nu] C_k[nu][b]; a thread owns
@@ -537,6 +539,175 @@ __global__ void __launch_bounds__(256) k_band_contract(const cplx* __restrict__ 
   }
 }
 
+// Valence-first band contraction.  The pair densities need only the n_occ
+// valence columns on one side of M_G, so with C_v / C_c the valence /
+// conduction columns:
+//   X_G = M_G C_v(k)         [mu][v]   (ket side)
+//   U_G = C_v(k+q)^H M_G     [v][nu]   (bra side)
+//   rho_G[v][c]   = sum_mu conj(C_c(k+q)[mu][c]) X_G[mu][v]
+//   sigma_G[v][c] = sum_nu U_G[v][nu] C_c(k)[nu][c]
+// i.e. 2 n_ao^2 n_occ + 2 n_occ n_c n_ao complex multiply-adds per (k, G)
+// against n_ao^2 n_b + 2 n_occ n_c n_ao in the ket-first order above.
+// Both halves of each step run the same branch-free loop (an item picks its
+// operand strides and the conjugation sign), so a wave never splits between
+// them.  Step 1 item: one row of X or column of U for 4 valence bands; step 2
+// item: one conduction band c for 2 valence bands, lanes along c.
+// ALIAS: X and U overwrite the M tile after a barrier (every thread owns at
+// most one step-1 item).
+constexpr int kVB1 = 4;
+constexpr int kVB2 = 2;
+
+template <int GT, bool ALIAS>
+__global__ void __launch_bounds__(256) k_band_vf(const cplx* __restrict__ M,
+                                                 const cplx* __restrict__ Ck,
+                                                 const cplx* __restrict__ Ckq, int n_ao, int n_b,
+                                                 int n_occ, int n_k, int k0, int n_g,
+                                                 int tiles_per_block, cplx* __restrict__ R,
+                                                 size_t ldt) {
+  extern __shared__ cplx lds[];
+  const int kk = blockIdx.x;
+  const int k = k0 + kk;
+  const int n_tiles = (n_g + GT - 1) / GT;
+  const int tile0 = blockIdx.y * tiles_per_block;
+  const int tile1 = min(n_tiles, tile0 + tiles_per_block);
+  const int n_c = n_b - n_occ;
+  const int nab = n_ao * n_b, naa = n_ao * n_ao, lda = n_ao + 1;
+  const int nthr = blockDim.x, tid = threadIdx.x;
+  cplx* sCk = lds;
+  cplx* sCq = sCk + nab;
+  cplx* sM = sCq + nab;                                   // [GT][n_ao][lda]
+  cplx* sX = ALIAS ? sM : sM + (size_t)GT * n_ao * lda;   // [GT][n_ao][n_occ]
+  cplx* sU = sX + (size_t)GT * n_ao * n_occ;              // [GT][n_occ][n_ao]
+  for (int i = tid; i < nab; i += nthr) {
+    sCk[i] = Ck[(size_t)kk * nab + i];
+    sCq[i] = Ckq[(size_t)kk * nab + i];
+  }
+  const int nvc = n_occ * n_c;
+  const size_t t_res = (size_t)k * nvc;
+  const size_t t_anti = ((size_t)n_k + k) * nvc;
+  const int nvg = (n_occ + kVB1 - 1) / kVB1;
+  const int nvp = (n_occ + kVB2 - 1) / kVB2;
+
+  cplx pf[kMPF];
+  auto fetch = [&](int tile) {
+    const int g0 = tile * GT, ng = min(GT, n_g - g0);
+    const cplx* Mk = M + ((size_t)kk * n_g + g0) * naa;
+#pragma unroll
+    for (int j = 0; j < kMPF; ++j) {
+      const int i = tid + j * nthr;
+      if (i < ng * naa) pf[j] = Mk[i];
+    }
+  };
+  auto put = [&](int tile) {
+    const int g0 = tile * GT, ng = min(GT, n_g - g0);
+    const cplx* Mk = M + ((size_t)kk * n_g + g0) * naa;
+    auto store = [&](int i, cplx v) {
+      const int g = i / naa, e = i - g * naa;
+      const int mu = e / n_ao, nu = e - mu * n_ao;
+      sM[(g * n_ao + mu) * lda + nu] = v;
+    };
+#pragma unroll
+    for (int j = 0; j < kMPF; ++j) {
+      const int i = tid + j * nthr;
+      if (i < ng * naa) store(i, pf[j]);
+    }
+    for (int i = tid + kMPF * nthr; i < ng * naa; i += nthr) store(i, Mk[i]);
+  };
+  if (tile0 < tile1) fetch(tile0);
+  for (int tile = tile0; tile < tile1; ++tile) {
+    const int g0 = tile * GT, ng = min(GT, n_g - g0);
+    __syncthreads();  // the previous tile's step 2 has finished with the LDS
+    put(tile);
+    __syncthreads();
+    if (tile + 1 < tile1) fetch(tile + 1);
+    // step 1: item (g, side, vg, row); side 0: X row mu = row, side 1: U
+    // column nu = row
+    const int per_g1 = 2 * nvg * n_ao;
+    const int n1 = ng * per_g1;
+    for (int w0 = 0; w0 < n1; w0 += nthr) {
+      const int w = w0 + tid;
+      const bool live = w < n1;
+      const int ww = live ? w : 0;
+      const int g = ww / per_g1, r = ww - g * per_g1;
+      const int side = r / (nvg * n_ao), r2 = r - side * nvg * n_ao;
+      const int vg = r2 / n_ao, row = r2 - vg * n_ao;
+      const int v0 = vg * kVB1;
+      // X: M[g][row][i] C_k[i][v];  U: M[g][i][row] conj(C_kq[i][v])
+      const cplx* mp = sM + g * n_ao * lda + (side ? row : row * lda);
+      const int ms = side ? lda : 1;
+      const cplx* cp = side ? sCq : sCk;
+      const double sg = side ? -1.0 : 1.0;
+      int vc[kVB1];
+#pragma unroll
+      for (int j = 0; j < kVB1; ++j) vc[j] = min(v0 + j, n_occ - 1);
+      double re[kVB1], im[kVB1];
+#pragma unroll
+      for (int j = 0; j < kVB1; ++j) re[j] = im[j] = 0.0;
+#pragma unroll 4
+      for (int i = 0; i < n_ao; ++i) {
+        const cplx m = mp[i * ms];
+#pragma unroll
+        for (int j = 0; j < kVB1; ++j) {
+          const cplx c = cp[i * n_b + vc[j]];
+          const double ci = sg * c.im;
+          re[j] += m.re * c.re - m.im * ci;
+          im[j] += m.re * ci + m.im * c.re;
+        }
+      }
+      if (ALIAS) __syncthreads();  // every read of M done before X and U overwrite it
+      if (live) {
+#pragma unroll
+        for (int j = 0; j < kVB1; ++j) {
+          if (v0 + j < n_occ) {
+            if (side)
+              sU[(g * n_occ + v0 + j) * n_ao + row] = {re[j], im[j]};
+            else
+              sX[(g * n_ao + row) * n_occ + v0 + j] = {re[j], im[j]};
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // step 2: item (g, side, vp, c); side 0: rho with conj(C_kq[i][n_occ+c])
+    // and X[g][i][v], side 1: sigma with C_k[i][n_occ+c] and U[g][v][i]
+    const int per_g2 = 2 * nvp * n_c;
+    const int n2 = ng * per_g2;
+    for (int w = tid; w < n2; w += nthr) {
+      const int g = w / per_g2, r = w - g * per_g2;
+      const int side = r / (nvp * n_c), r2 = r - side * nvp * n_c;
+      const int vp = r2 / n_c, c = r2 - vp * n_c;
+      const int v0 = vp * kVB2;
+      const cplx* ap = (side ? sCk : sCq) + n_occ + c;
+      const double sg = side ? 1.0 : -1.0;
+      const cplx* bp[kVB2];
+#pragma unroll
+      for (int j = 0; j < kVB2; ++j) {
+        const int v = min(v0 + j, n_occ - 1);
+        bp[j] = side ? sU + (g * n_occ + v) * n_ao : sX + g * n_ao * n_occ + v;
+      }
+      const int bs = side ? 1 : n_occ;
+      double re[kVB2], im[kVB2];
+#pragma unroll
+      for (int j = 0; j < kVB2; ++j) re[j] = im[j] = 0.0;
+#pragma unroll 4
+      for (int i = 0; i < n_ao; ++i) {
+        const cplx a = ap[i * n_b];
+        const double ai = sg * a.im;
+#pragma unroll
+        for (int j = 0; j < kVB2; ++j) {
+          const cplx b = bp[j][i * bs];
+          re[j] += a.re * b.re - ai * b.im;
+          im[j] += a.re * b.im + ai * b.re;
+        }
+      }
+      const size_t tb = (side ? t_anti : t_res) + c;
+#pragma unroll
+      for (int j = 0; j < kVB2; ++j)
+        if (v0 + j < n_occ) R[(size_t)(g0 + g) * ldt + tb + (size_t)(v0 + j) * n_c] = {re[j], im[j]};
+    }
+  }
+}
+
 // dev[k] = max |C^H S C - I| (one block per k)
 __global__ void __launch_bounds__(256) k_orth_check(const cplx* __restrict__ S,
                                                     const cplx* __restrict__ C, int n_ao,
@@ -639,6 +810,11 @@ size_t band_contract_lds(int n_ao, int n_b, int /*n_occ*/) {
   return band_lds(n_ao, n_b, 1, false);
 }
 
+static size_t band_vf_lds(int n_ao, int n_b, int n_occ, int gt, bool alias) {
+  const size_t m = (size_t)gt * n_ao * (n_ao + 1), xu = 2 * (size_t)gt * n_ao * n_occ;
+  return sizeof(cplx) * (2 * (size_t)n_ao * n_b + (alias ? std::max(m, xu) : m + xu));
+}
+
 void launch_band_contract(const cplx* M, const cplx* Ck, const cplx* Ckq, int n_ao, int n_b,
                           int n_occ, int n_k, int k0, int nk, int n_g, cplx* R, size_t ldt,
                           hipStream_t st) {
@@ -662,15 +838,41 @@ void launch_band_contract(const cplx* M, const cplx* Ck, const cplx* Ckq, int n_
                        dim3(256), band_lds(n_ao, n_b, GT, AL), st, M, ck, cq, n_ao, n_b, n_occ,   \
                        n_k, k0, n_g, tb.first, R, ldt);                                         \
   } while (0)
-  if (4 * n_ao * nbq <= 256 && band_lds(n_ao, n_b, 4, true) <= cap)
+  // the valence-first order when it needs fewer multiply-adds (2 n_occ < n_b)
+  // and a tile of at least one G fits two blocks per CU
+  const int nvg = (n_occ + kVB1 - 1) / kVB1;
+  const bool vf = 2 * n_occ < n_b;
+#define QCX_VF(GT, AL)                                                                          \
+  do {                                                                                          \
+    const auto tb = grid_y(GT);                                                                 \
+    hipLaunchKernelGGL((k_band_vf<GT, AL>), dim3(nk, (unsigned)((n_g + GT - 1) / GT +          \
+                                                                tb.first - 1) / tb.first),       \
+                       dim3(256), band_vf_lds(n_ao, n_b, n_occ, GT, AL), st, M, ck, cq, n_ao,    \
+                       n_b, n_occ, n_k, k0, n_g, tb.first, R, ldt);                             \
+  } while (0)
+  auto vf_alias = [&](int gt) {
+    return gt * 2 * nvg * n_ao <= 256 && band_vf_lds(n_ao, n_b, n_occ, gt, true) <= cap;
+  };
+  if (vf && vf_alias(4))
+    QCX_VF(4, true);
+  else if (vf && vf_alias(2))
+    QCX_VF(2, true);
+  else if (vf && vf_alias(1))
+    QCX_VF(1, true);
+  else if (4 * n_ao * nbq <= 256 && band_lds(n_ao, n_b, 4, true) <= cap)
     QCX_BC(4, true);
   else if (2 * n_ao * nbq <= 256 && band_lds(n_ao, n_b, 2, true) <= cap)
     QCX_BC(2, true);
+  else if (n_ao * nbq <= 256 && band_lds(n_ao, n_b, 1, true) <= cap)
+    QCX_BC(1, true);
+  else if (vf && band_vf_lds(n_ao, n_b, n_occ, 1, false) <= 160 * 1024)
+    QCX_VF(1, false);
   else if (n_ao * nbq <= 256)
     QCX_BC(1, true);
   else
     QCX_BC(1, false);
 #undef QCX_BC
+#undef QCX_VF
 }
 
 // Device-side state checks (deferred reporting): flags[0] = smallest k whose

@@ -50,6 +50,21 @@ def test_rho_fp64(ctx, maker):
     assert err < 1e-10
 
 
+def test_rho_ket_first_order(ctx):
+    """Twelve valence bands of twenty (2 n_occ >= n_b): the library contracts
+    the ket side with every band first (the other workloads take the
+    valence-first order); pair densities and FP64 loss against the oracle."""
+    import dataclasses
+
+    wl = dataclasses.replace(make_tiny(), n_occ=12,
+                             energy_ranges=[(12, -12.0, 0.0), (8, 1.1, 30.0)])
+    ref = _oracle(wl)
+    out = gpu_solve(ctx, wl, precision="fp64", want_rho=True)
+    e_rho, e_loss = relmax(out["rho"], ref["R"]), normwise(out["loss"], ref["loss"])
+    print("ket-first rho", e_rho, "loss", e_loss)
+    assert e_rho < 1e-10 and e_loss < 1e-10
+
+
 @pytest.mark.parametrize("maker", [make_tiny, make_config1])
 def test_chi0_and_loss_fp64(ctx, maker):
     wl = maker()
