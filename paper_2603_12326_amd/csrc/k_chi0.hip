@@ -900,6 +900,28 @@ void launch_pairs_f64(const cplx* R, size_t ldt, const double* w, const double* 
                        g.n_t, pairs, g.n_ps, g.chunk_t, g.n_rowsp, g.n_colp, out);
 }
 
+// Blocks of the FP64 pairs kernel that the current device holds at once (CUs
+// x resident blocks per CU for the variant launch_pairs_f64 picks for n_g).
+static int pairs64_slots(int n_g) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  hipError_t e;
+  if (n_g <= 128)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pairs_mfma64<128>, 256, 0);
+  else if (n_g <= 256)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pairs_mfma64<256>, 256, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pairs_mfma64_direct, 256, 0);
+  return e == hipSuccess ? cus * per : 0;
+}
+
+// K split of the FP64 pairs kernel: the launch runs in ceil(blocks / slots)
+// rounds of blocks that each walk their share of the KC-transition chunks, so
+// the split minimises rounds x (chunks per split + a fixed cost of two chunks
+// per block: start-up and the partial-sum tile), within the partial-sum
+// budget; a split that needs no more splits than a smaller one is skipped.
 void geom64_init(Geom64& g, int n_g, int n_w, int n_t, int n_ps, size_t max_bytes) {
   g.n_g = n_g;
   g.n_w = n_w;
@@ -908,13 +930,25 @@ void geom64_init(Geom64& g, int n_g, int n_w, int n_t, int n_ps, size_t max_byte
   g.n_rowsp = (2 * n_w + 63) / 64 * 64;
   g.n_colp = (2 * n_ps + COLS64 - 1) / COLS64 * COLS64;
   const int blocks = (g.n_colp / COLS64) * (g.n_rowsp / 64);
-  const int chunks = (n_t + KC - 1) / KC;
-  int ks = 1;
-  while (ks < 128 && blocks * ks < 2048 && chunks / (2 * ks) >= 4 &&
-         (size_t)(2 * ks) * g.n_rowsp * g.n_colp * sizeof(double) <= max_bytes)
-    ks *= 2;
-  g.ksplit = ks;
-  g.chunk_t = (chunks + ks - 1) / ks * KC;
+  const int chunks = std::max(1, (n_t + KC - 1) / KC);
+  int slots = pairs64_slots(n_g);
+  if (slots <= 0) slots = 2048;
+  const size_t split_bytes = (size_t)g.n_rowsp * g.n_colp * sizeof(double);
+  int best = 1;
+  double best_cost = 1e300;
+  for (int ks = 1; ks <= std::min(256, chunks); ++ks) {
+    const int per = (chunks + ks - 1) / ks;
+    if ((chunks + per - 1) / per != ks) continue;
+    if (ks > 1 && (size_t)ks * split_bytes > max_bytes) break;
+    const long rounds = ((long)blocks * ks + slots - 1) / slots;
+    const double cost = (double)rounds * (per + 2);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = ks;
+    }
+  }
+  g.ksplit = best;
+  g.chunk_t = (chunks + best - 1) / best * KC;
 }
 
 }  // namespace qcx
