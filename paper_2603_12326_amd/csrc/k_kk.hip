@@ -51,17 +51,16 @@ __device__ inline void tile_of(int p, int T, int& ti, int& tj) {
   tj = r + p;
 }
 
-__global__ void __launch_bounds__(256) k_kk_bin(const cplx* __restrict__ Rs, int n_gp, int n_g,
-                                                const int* __restrict__ ib,
-                                                const double* __restrict__ xf,
-                                                const KkChunk* __restrict__ chunks,
-                                                double* __restrict__ S) {
-  __shared__ cplx sa[KB_TC][kKkTile], sb[KB_TC][kKkTile];
-  __shared__ int sib[KB_TC];
-  __shared__ double sx[KB_TC];
-  int ti, tj;
-  tile_of(blockIdx.y, n_gp / kKkTile, ti, tj);
-  const KkChunk ch = chunks[blockIdx.x];
+// One (chunk, tile) of the binning.  DIAG (a tile on the diagonal, ti = tj):
+// a thread's 16 x 16 sub-blocks (k, l) below the diagonal (k > l) hold only
+// G > G' and are not computed, and both operands come from one staged slice.
+template <bool DIAG>
+__device__ __forceinline__ void kk_bin_tile(const cplx* __restrict__ Rs, int n_gp, int n_g,
+                                            const int* __restrict__ ib,
+                                            const double* __restrict__ xf, const KkChunk ch,
+                                            int ti, int tj, double* __restrict__ S,
+                                            cplx (&sa)[KB_TC][kKkTile], cplx (&sb)[KB_TC][kKkTile],
+                                            int (&sib)[KB_TC], double (&sx)[KB_TC]) {
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int g0 = ti * kKkTile, h0 = tj * kKkTile;
   const size_t n_pairs = (size_t)n_g * (n_g + 1) / 2;
@@ -107,10 +106,10 @@ __global__ void __launch_bounds__(256) k_kk_bin(const cplx* __restrict__ Rs, int
       if (tt < nt) {
         const cplx* row = Rs + (size_t)(t0 + tt) * n_gp;
         va = row[g0 + gg];
-        vb = row[h0 + gg];
+        if (!DIAG) vb = row[h0 + gg];
       }
       sa[tt][gg] = va;
-      sb[tt][gg] = vb;
+      if (!DIAG) sb[tt][gg] = vb;
     }
     if (tid < nt) {
       sib[tid] = ib[t0 + tid];
@@ -144,12 +143,13 @@ __global__ void __launch_bounds__(256) k_kk_bin(const cplx* __restrict__ Rs, int
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         a[k] = sa[tt][ty + 16 * k];
-        b[k] = sb[tt][tx + 16 * k];
+        b[k] = DIAG ? sa[tt][tx + 16 * k] : sb[tt][tx + 16 * k];
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
+          if (DIAG && k > l) continue;
           const double pr = a[k].re * b[l].re + a[k].im * b[l].im;  // conj(a) b
           const double pi = a[k].re * b[l].im - a[k].im * b[l].re;
           lr[k][l] += wl * pr;
@@ -162,6 +162,23 @@ __global__ void __launch_bounds__(256) k_kk_bin(const cplx* __restrict__ Rs, int
   put(cur - ch.k0, lr, li);
   put(cur + 1 - ch.k0, hr, hi);
   for (; wn < ch.nb; ++wn) store(wn, lr, li, true);
+}
+
+__global__ void __launch_bounds__(256) k_kk_bin(const cplx* __restrict__ Rs, int n_gp, int n_g,
+                                                const int* __restrict__ ib,
+                                                const double* __restrict__ xf,
+                                                const KkChunk* __restrict__ chunks,
+                                                double* __restrict__ S) {
+  __shared__ cplx sa[KB_TC][kKkTile], sb[KB_TC][kKkTile];
+  __shared__ int sib[KB_TC];
+  __shared__ double sx[KB_TC];
+  int ti, tj;
+  tile_of(blockIdx.y, n_gp / kKkTile, ti, tj);
+  const KkChunk ch = chunks[blockIdx.x];
+  if (ti == tj)  // the same for the whole block
+    kk_bin_tile<true>(Rs, n_gp, n_g, ib, xf, ch, ti, tj, S, sa, sb, sib, sx);
+  else
+    kk_bin_tile<false>(Rs, n_gp, n_g, ib, xf, ch, ti, tj, S, sa, sb, sib, sx);
 }
 
 // ---------------------------------------------------------------- transform
