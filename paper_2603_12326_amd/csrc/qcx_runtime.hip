@@ -85,6 +85,10 @@ constexpr double kKkSpectralBudget = 16.0 * (1 << 30);
 // each) in its FP32 accumulators; the splits are added in FP64
 constexpr int kMaxStepsPerSplit = 1024;
 constexpr size_t kLdsBytes = 160 * 1024;
+// Bloch sums M(k; G) of one pass of the pair densities (k points in chunks
+// within this budget): large enough that the Bloch-sum product has a wide
+// k dimension for long G lists
+constexpr size_t kMBudget = (size_t)8 << 30;
 
 struct Cand {
   int ks, nst;
@@ -499,7 +503,7 @@ static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_
   HIPCK(ctx->d_R.reserve(sizeof(cplx) * ctx->ldt * n_G));
   HIPCK(hipMemsetAsync(ctx->d_R.p, 0, sizeof(cplx) * ctx->ldt * n_G, st));
   const size_t per_k = sizeof(cplx) * (size_t)n_G * nee;
-  int kc = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, ((size_t)1 << 30) / per_k));
+  int kc = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, kMBudget / per_k));
   HIPCK(ctx->d_M.reserve(per_k * kc));
   int sp_rho;
   HIPCK(span_begin(ctx, 0, &sp_rho));
