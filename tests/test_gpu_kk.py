@@ -8,7 +8,8 @@ weights.  Bars: chi0 to 1e-11 of its largest element, the loss to 1e-10
 per G curve (the FP64 bars of the direct route).  Cases: the smallest
 workload at eta = 0.2 eV and at eta = 0 (pure spectral part + its
 Kramers-Kronig transform), one bin wider than every transition energy, the
-tiny s/p/d cell (9 G, one 64 x 64 tile, ragged), repeatability, and second
+tiny s/p/d cell (9 G, one 64 x 64 tile, ragged), 137 G (3 x 3 tiles, the
+last ragged), repeatability, and second
 order convergence to the direct FP64 route on the GPU itself.
 """
 import numpy as np
@@ -67,6 +68,22 @@ def test_kk_matches_oracle(ctx, cfg1, cfg1_oracle, eta):
     cref, Lref = _oracle_kk(cfg1, w, eta, 0.05, cfg1_oracle["R"])
     ec, el = relmax(chi, cref), normwise(L, Lref)
     print("eta", eta, "chi0", ec, "loss", el)
+    assert ec < TOL_CHI and el < TOL_LOSS
+
+
+def test_kk_multi_tile(ctx, cfg1):
+    """137 G: a 3 x 3 grid of 64 x 64 tiles of the (G, G') plane (diagonal and
+    off-diagonal tiles, a last tile with 9 real G) against the oracle."""
+    import dataclasses
+
+    from synth.generator import g_shells
+
+    wl = dataclasses.replace(cfg1, G_int=g_shells(cfg1.cell.lat, 137))
+    w = cfg1.w_eV[::8]
+    chi, L = _gpu_kk(ctx, wl, w, 0.2, 0.05)
+    cref, Lref = _oracle_kk(wl, w, 0.2, 0.05)
+    ec, el = relmax(chi, cref), normwise(L, Lref)
+    print("137 G chi0", ec, "loss", el)
     assert ec < TOL_CHI and el < TOL_LOSS
 
 
