@@ -87,8 +87,10 @@ __device__ inline float bf16_val(uint16_t b) {
 }
 
 // Fragment order for v_mfma_f32_32x32x16_bf16: lane l holds
-// A[rb*32 + l%32][tb*16 + 8(l/32) + 0..7]; hi = bf16(x), lo = bf16(x - hi) with
-// the residual taken from the FP64 weight.
+// A[rb*32 + l%32][tb*16 + 8(l/32) + 0..7]; hi = bf16(x), lo = bf16(x - hi).
+// The energy difference s w - D is formed in FP64 (it cancels near resonance),
+// the reciprocal in FP32: its error (~1e-7 relative) is far below the 2^-16
+// that hi + lo keep.
 __global__ void k_weights_bf16(const double* w, const double* dt, double eta, Chi0Geom g,
                                uint16_t* Ahi, uint16_t* Alo) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -100,14 +102,22 @@ __global__ void k_weights_bf16(const double* w, const double* dt, double eta, Ch
   const int tb = (int)(fr % ntb), rb = (int)(fr / ntb);
   const int row = rb * 32 + lane % 32;
   const int j = row >> 1, ri = row & 1;
+  const bool live_row = j < g.n_w;
+  const double wj = live_row ? w[j] : 0.0;
+  const float ef = (float)eta;
   uint16_t hi[8], lo[8];
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int t = tb * KSTEP + 8 * (lane / 32) + s;
-    const cplx wt = weight(w, dt, eta, j, t, g.n_w, g.n_t);
-    const double x = ri ? wt.im : wt.re;
-    hi[s] = bf16_bits((float)x);
-    lo[s] = bf16_bits((float)(x - (double)bf16_val(hi[s])));
+    float x = 0.0f;
+    if (live_row && t < g.n_t) {
+      const double sg = (t < g.n_t / 2) ? 1.0 : -1.0;
+      const float xf = (float)(sg * wj - dt[t]);
+      const float r = 1.0f / (xf * xf + ef * ef);
+      x = ri ? -ef * r : xf * r;
+    }
+    hi[s] = bf16_bits(x);
+    lo[s] = bf16_bits(x - bf16_val(hi[s]));
   }
   uint4 h, l;
   h.x = hi[0] | ((uint32_t)hi[1] << 16); h.y = hi[2] | ((uint32_t)hi[3] << 16);
