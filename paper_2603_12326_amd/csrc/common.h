@@ -75,7 +75,8 @@ void launch_bloch_phase(const double* k_frac, int n_k, const double shift[3], co
 // M[k][g][e] = sum_T ph[k0+k][T] F[T][g][e], e = mu*n_ao+nu, for k in [0, nk)
 void launch_phase_sum(const cplx* F, const cplx* ph, int n_t, int n_q, int n_e, int k0, int nk,
                       cplx* M, hipStream_t st);
-// R64[g][t] (t fastest, stride ldt) for k in [k0, k0+nk) from M chunk
+// R64[g][t] (t fastest, stride ldt) for k in [k0, k0+nk) from M chunk, in the
+// valence-first order when 2 n_occ < n_b and a tile fits, else ket-first
 void launch_band_contract(const cplx* M, const cplx* Ck, const cplx* Ckq, int n_ao, int n_b,
                           int n_occ, int n_k, int k0, int nk, int n_g, cplx* R, size_t ldt,
                           hipStream_t st);

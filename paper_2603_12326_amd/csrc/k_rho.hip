@@ -9,10 +9,12 @@
 // Lambda_t = d^t/dP^t e^{-p (x-P)^2}, whose Fourier transform is
 // sqrt(pi/p) e^{-Q^2/4p} (iQ)^t e^{iQP}.
 //
-// Three kernels per q: cell_ft (one thread per shell pair, cell and Q),
-// phase_sum (the 27-cell Bloch sum, one thread per AO pair element holding its
-// 27 lattice terms in registers while it walks over k), band_contract (one
-// block per k and G tile; C(k), C(k+q) and one M(k;Q) staged in LDS).
+// Per q: cell_ft (one thread per shell pair, cell and Q); the 27-cell Bloch
+// sum M(k;Q) (a complex product issued by the runtime on rocBLAS; phase_sum
+// here serves the overlaps S(k) and the generic case); then the band
+// contraction (one block per k and G tile; C(k), C(k+q) and M(k;Q) tiles
+// staged in LDS), valence side first (k_band_vf) or ket side first
+// (k_band_contract), whichever needs fewer multiply-adds.
 #include <algorithm>
 #include <utility>
 
