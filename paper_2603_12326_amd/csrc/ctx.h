@@ -24,6 +24,12 @@ struct BatchPlan;
 void destroy_plan(BatchPlan* p);
 }  // namespace qcx
 
+namespace qcx {
+// pinned staging ring of a context: buffers and bytes per buffer
+constexpr int kStageSlots = 4;
+constexpr size_t kStageBytes = (size_t)16 << 20;
+}  // namespace qcx
+
 struct qcx_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -75,11 +81,18 @@ struct qcx_ctx {
   bool have_eps = false;
   DevBuf d_eps, d_diag, d_epsM, d_loss, d_sing;
 
-  // pinned staging for host -> device copies: reset at the start of each
-  // call once the previous call's copies have completed
-  void* stage = nullptr;
-  size_t stage_cap = 0, stage_off = 0;
-  hipEvent_t stage_done = nullptr;
+  // pinned staging for host -> device copies: a ring of kStageSlots buffers,
+  // one per call in turn; a call waits only until the copies of the call that
+  // used its buffer kStageSlots calls earlier have completed, so the host can
+  // run several calls ahead of the device
+  struct StageSlot {
+    void* p = nullptr;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+  };
+  StageSlot stage_ring[qcx::kStageSlots];
+  int stage_cur = -1;
+  size_t stage_off = 0;
   // transition energies copied to pinned host memory right after
   // qcx_set_states computes them, once the Kramers-Kronig route has been
   // used (its host-side sort then overlaps the pair densities on the device)
@@ -91,7 +104,6 @@ struct qcx_ctx {
   size_t h_dt_cap = 0;
   hipEvent_t ev_dt = nullptr;
   bool dt_prefetch = false, dt_valid = false, dt_pending = false;
-  bool stage_pending = false;
 
   // timing: event pairs recorded on the stream without synchronising,
   // resolved by qcx_stage_times
@@ -122,8 +134,11 @@ struct qcx_ctx {
       (void)hipEventDestroy(sp.b);
     }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-    if (stage_done) (void)hipEventDestroy(stage_done);
-    if (stage) (void)hipHostFree(stage);
+    for (StageSlot& sl : stage_ring) {
+      if (sl.pending && sl.done) (void)hipEventSynchronize(sl.done);
+      if (sl.done) (void)hipEventDestroy(sl.done);
+      if (sl.p) (void)hipHostFree(sl.p);
+    }
     if (dt_pending && ev_dt) (void)hipEventSynchronize(ev_dt);
     if (h_dt) (void)hipHostFree(h_dt);
     if (blas) (void)rocblas_destroy_handle(blas);
@@ -159,25 +174,29 @@ inline int fail(qcx_ctx* c, int code, const std::string& msg) {
 
 inline size_t roundup(size_t x, size_t m) { return (x + m - 1) / m * m; }
 
-constexpr size_t kStageBytes = (size_t)64 << 20;
 
-// Begin a call that stages host data: wait until the copies of the previous
-// call have left the pinned buffer.
+// Begin a call that stages host data: take the next buffer of the ring and
+// wait until the copies staged in it kStageSlots calls ago have left it.  All
+// buffers are allocated on the first call (never inside a later, possibly
+// captured, call).
 inline hipError_t stage_begin(qcx_ctx* c) {
-  if (!c->stage) {
-    hipError_t e = hipHostMalloc(&c->stage, kStageBytes);
-    if (e != hipSuccess) {
-      c->stage = nullptr;
-      return e;
+  if (!c->stage_ring[0].p) {
+    for (qcx_ctx::StageSlot& sl : c->stage_ring) {
+      hipError_t e = hipHostMalloc(&sl.p, kStageBytes);
+      if (e != hipSuccess) {
+        sl.p = nullptr;
+        return e;
+      }
+      e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
     }
-    c->stage_cap = kStageBytes;
-    e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming);
-    if (e != hipSuccess) return e;
   }
-  if (c->stage_pending) {
-    hipError_t e = hipEventSynchronize(c->stage_done);
+  c->stage_cur = (c->stage_cur + 1) % kStageSlots;
+  qcx_ctx::StageSlot& sl = c->stage_ring[c->stage_cur];
+  if (sl.pending) {
+    hipError_t e = hipEventSynchronize(sl.done);
     if (e != hipSuccess) return e;
-    c->stage_pending = false;
+    sl.pending = false;
   }
   c->stage_off = 0;
   return hipSuccess;
@@ -193,16 +212,17 @@ inline hipError_t upload(qcx_ctx* c, DevBuf& b, const T* src, size_t n, bool dev
   if (e != hipSuccess) return e;
   if (dev_src) return hipMemcpyAsync(b.p, src, bytes, hipMemcpyDeviceToDevice, c->stream);
   const size_t off = (c->stage_off + 255) / 256 * 256;
-  if (c->stage && off + bytes <= c->stage_cap) {
-    char* h = static_cast<char*>(c->stage) + off;
+  qcx_ctx::StageSlot* sl = c->stage_cur >= 0 ? &c->stage_ring[c->stage_cur] : nullptr;
+  if (sl && sl->p && off + bytes <= kStageBytes) {
+    char* h = static_cast<char*>(sl->p) + off;
     memcpy(h, src, bytes);
     c->stage_off = off + bytes;
     e = hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return e;
     // record after every staged copy so that an early error return still
-    // leaves the arena guarded
-    e = hipEventRecord(c->stage_done, c->stream);
-    if (e == hipSuccess) c->stage_pending = true;
+    // leaves the buffer guarded
+    e = hipEventRecord(sl->done, c->stream);
+    if (e == hipSuccess) sl->pending = true;
     return e;
   }
   e = hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, c->stream);
