@@ -71,6 +71,8 @@ struct qcx_ctx {
   double tune_ms = 0.0;       // time spent tuning in the last qcx_chi0
   Geom64 geom64{};
   DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_rows, d_pairs64, d_C, d_C64, d_XY;
+  // what d_pairs, d_rows and d_pairs64 last received (upload_cached)
+  std::vector<int> h_pairs_up, h_rows_up, h_pairs64_up;
   // Kramers-Kronig route: energy order, sorted energies and sides, K ranges
   // per row tile, reduced bins, transform matrix
   DevBuf d_kk_order, d_kk_ib, d_kk_xf, d_kk_chunks, d_kk_Rs, d_kk_S, d_kk_K;
@@ -175,6 +177,13 @@ inline int fail(qcx_ctx* c, int code, const std::string& msg) {
 inline size_t roundup(size_t x, size_t m) { return (x + m - 1) / m * m; }
 
 
+// Upload an index table unless the buffer already holds exactly these values
+// (the pair tables repeat from call to call); `last` mirrors what `b` last
+// received and must be the only record of writes to it.
+template <class B>
+inline hipError_t upload_cached(B* c, DevBuf& b, std::vector<int>& last,
+                                const std::vector<int>& v);
+
 // Begin a call that stages host data: take the next buffer of the ring and
 // wait until the copies staged in it kStageSlots calls ago have left it.  All
 // buffers are allocated on the first call (never inside a later, possibly
@@ -228,6 +237,16 @@ inline hipError_t upload(qcx_ctx* c, DevBuf& b, const T* src, size_t n, bool dev
   e = hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(c->stream);
+}
+
+template <class B>
+inline hipError_t upload_cached(B* c, DevBuf& b, std::vector<int>& last,
+                                const std::vector<int>& v) {
+  if (b.p && !v.empty() && last == v) return hipSuccess;
+  last.clear();  // unknown contents until the copy below is queued
+  hipError_t e = upload(c, b, v.data(), v.size());
+  if (e == hipSuccess) last = v;
+  return e;
 }
 
 // Queue a copy of the transition energies (d_dt, n_t values) to h_dt on the

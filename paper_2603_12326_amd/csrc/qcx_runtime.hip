@@ -632,10 +632,10 @@ int qcx_loss_diag(qcx_ctx* ctx, int n_G, const int* G_int, int n_w, const double
         std::vector<int> local, rows;
         if (!bulk_gather_tables(pairs, local, rows))
           return fail(ctx, QCX_EDEVICE, "internal: a pair tile needs more rows than staged");
-        HIPCK(upload(ctx, ctx->d_pairs, local.data(), local.size()));
-        HIPCK(upload(ctx, ctx->d_rows, rows.data(), rows.size()));
+        HIPCK(upload_cached(ctx, ctx->d_pairs, ctx->h_pairs_up, local));
+        HIPCK(upload_cached(ctx, ctx->d_rows, ctx->h_rows_up, rows));
       } else {
-        HIPCK(upload(ctx, ctx->d_pairs, pairs.data(), pairs.size()));
+        HIPCK(upload_cached(ctx, ctx->d_pairs, ctx->h_pairs_up, pairs));
       }
       const int blocks = (g.n_bulkp / 128) * (g.n_rowsp / (32 * af));
       g.ksplit = std::max(ksplit_for_accuracy(g.n_tp / KSTEP_T), pick_ksplit(blocks, g.n_tp / KSTEP_T));
@@ -658,7 +658,7 @@ int qcx_loss_diag(qcx_ctx* ctx, int n_G, const int* G_int, int n_w, const double
     } else {
       pairs.resize(nch);
       for (int b = 0; b < nch; ++b) pairs[b] = b | (b << 16);
-      HIPCK(upload(ctx, ctx->d_pairs64, pairs.data(), pairs.size()));
+      HIPCK(upload_cached(ctx, ctx->d_pairs64, ctx->h_pairs64_up, pairs));
       Geom64& g64 = ctx->geom64;
       geom64_init(g64, nch, n_w, ctx->n_t, nch, (size_t)512 << 20);
       HIPCK(ctx->d_XY.reserve(sizeof(double) * (size_t)g64.ksplit * g64.n_rowsp * g64.n_colp));
@@ -799,10 +799,10 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
       std::vector<int> local, rows;
       if (!bulk_gather_tables(pairs, local, rows))
         return fail(ctx, QCX_EDEVICE, "internal: a pair tile needs more rows than staged");
-      HIPCK(upload(ctx, ctx->d_pairs, local.data(), local.size()));
-      HIPCK(upload(ctx, ctx->d_rows, rows.data(), rows.size()));
+      HIPCK(upload_cached(ctx, ctx->d_pairs, ctx->h_pairs_up, local));
+      HIPCK(upload_cached(ctx, ctx->d_rows, ctx->h_rows_up, rows));
     } else {
-      HIPCK(upload(ctx, ctx->d_pairs, pairs.data(), pairs.size()));
+      HIPCK(upload_cached(ctx, ctx->d_pairs, ctx->h_pairs_up, pairs));
     }
     const int* rows_dev = g.gather ? ctx->d_rows.as<int>() : nullptr;
     const bool bf = precision == QCX_SPLIT_BF16;
@@ -894,7 +894,7 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
       for (int G = 0; G < ctx->n_g && p < ctx->n_pairs64; ++G)
         for (int Gp = G; Gp < ctx->n_g && p < ctx->n_pairs64; ++Gp, ++p) tab[p] = G | (Gp << 16);
     }
-    HIPCK(upload(ctx, ctx->d_pairs64, tab.data(), tab.size()));
+    HIPCK(upload_cached(ctx, ctx->d_pairs64, ctx->h_pairs64_up, tab));
     HIPCK(ctx->d_XY.reserve(sizeof(double) * (size_t)g64.ksplit * g64.n_rowsp * g64.n_colp));
     HIPCK(span_begin(ctx, 2, &sp_hw));
     launch_pairs_f64(ctx->d_R.as<cplx>(), ctx->ldt, ctx->d_w.as<double>(), ctx->d_dt.as<double>(),
