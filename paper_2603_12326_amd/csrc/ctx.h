@@ -75,7 +75,7 @@ struct qcx_ctx {
   std::vector<int> h_pairs_up, h_rows_up, h_pairs64_up;
   // Kramers-Kronig route: energy order, sorted energies and sides, K ranges
   // per row tile, reduced bins, transform matrix
-  DevBuf d_kk_order, d_kk_ib, d_kk_xf, d_kk_chunks, d_kk_Rs, d_kk_S, d_kk_K;
+  DevBuf d_kk_rank, d_kk_ib, d_kk_xf, d_kk_chunks, d_kk_Rs, d_kk_S, d_kk_K;
   DevBuf d_Fg, d_Rp;  // optical limit: gradient integrals, band momentum matrices
   bool bulk_c64 = false;      // bulk partials reduced to FP64 (row chunks)
 
@@ -128,7 +128,7 @@ struct qcx_ctx {
                      &d_S,    &d_F0,    &d_dev,    &d_flags,    &d_Q,      &d_vq,    &d_F,    &d_M,
                      &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_rows, &d_pairs64, &d_C, &d_C64,
                      &d_XY,   &d_eps,   &d_diag,   &d_epsM,   &d_loss,  &d_sing,
-                     &d_kk_order, &d_kk_ib, &d_kk_xf, &d_kk_chunks, &d_kk_Rs, &d_kk_S, &d_kk_K,
+                     &d_kk_rank, &d_kk_ib, &d_kk_xf, &d_kk_chunks, &d_kk_Rs, &d_kk_S, &d_kk_K,
                      &d_Fg, &d_Rp};
     for (DevBuf* b : all) b->release();
     for (const Span& sp : spans) {

@@ -22,12 +22,26 @@ namespace qcx {
 namespace {
 
 // ------------------------------------------------------------------ packing
-__global__ void k_kk_pack(const cplx* __restrict__ R, size_t ldt, int n_g, int n_gp, int n_t,
-                          const int* __restrict__ order, cplx* __restrict__ Rs) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)n_t * n_gp) return;
-  const int t = (int)(i / n_gp), g = (int)(i % n_gp);
-  Rs[i] = g < n_g ? R[(size_t)g * ldt + order[t]] : cplx{0.0, 0.0};
+// Rs[rank[t]][g] = R[g][t] (zero for g >= n_g): a tiled transpose, 32
+// transitions x 64 G per block, so that the reads walk rows of R and the
+// writes walk rows of Rs (rank is the energy order of the transitions).
+constexpr int KP_T = 32;
+__global__ void __launch_bounds__(256) k_kk_pack(const cplx* __restrict__ R, size_t ldt, int n_g,
+                                                 int n_gp, int n_t, const int* __restrict__ rank,
+                                                 cplx* __restrict__ Rs) {
+  __shared__ cplx tile[KP_T][kKkTile + 1];
+  const int t0 = blockIdx.x * KP_T, g0 = blockIdx.y * kKkTile;
+  for (int e = threadIdx.x; e < KP_T * kKkTile; e += 256) {
+    const int gg = e / KP_T, tt = e % KP_T;
+    const int g = g0 + gg, t = t0 + tt;
+    tile[tt][gg] = (g < n_g && t < n_t) ? R[(size_t)g * ldt + t] : cplx{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < KP_T * kKkTile; e += 256) {
+    const int tt = e / kKkTile, gg = e % kKkTile;
+    const int t = t0 + tt;
+    if (t < n_t) Rs[(size_t)rank[t] * n_gp + g0 + gg] = tile[tt][gg];
+  }
 }
 
 // ------------------------------------------------------------------ binning
@@ -238,11 +252,10 @@ __global__ void k_kk_matrix(const double* __restrict__ w, int n_w, double eta, d
 
 }  // namespace
 
-void launch_kk_pack(const cplx* R, size_t ldt, int n_g, int n_gp, int n_t, const int* order,
+void launch_kk_pack(const cplx* R, size_t ldt, int n_g, int n_gp, int n_t, const int* rank,
                     cplx* Rs, hipStream_t st) {
-  const long total = (long)n_t * n_gp;
-  hipLaunchKernelGGL(k_kk_pack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, R, ldt,
-                     n_g, n_gp, n_t, order, Rs);
+  const dim3 grid((unsigned)((n_t + KP_T - 1) / KP_T), (unsigned)(n_gp / kKkTile));
+  hipLaunchKernelGGL(k_kk_pack, grid, dim3(256), 0, st, R, ldt, n_g, n_gp, n_t, rank, Rs);
 }
 
 void launch_kk_bin(const cplx* Rs, int n_gp, int n_g, const int* ib, const double* xf,

@@ -24,8 +24,8 @@ struct KkChunk {
 
 constexpr int kKkTile = 64;  // G and G' rows of one binning block
 
-// Rs[t'][n_gp] = R[G][order[t']] (zero for G >= n_g)
-void launch_kk_pack(const cplx* R, size_t ldt, int n_g, int n_gp, int n_t, const int* order,
+// Rs[rank[t]][n_gp] = R[G][t] (zero for G >= n_g); rank = energy order of t
+void launch_kk_pack(const cplx* R, size_t ldt, int n_g, int n_gp, int n_t, const int* rank,
                     cplx* Rs, hipStream_t st);
 // S[row][2][n_pairs] (Re, Im) for every chunk and upper-triangle pair (G <= G')
 void launch_kk_bin(const cplx* Rs, int n_gp, int n_g, const int* ib, const double* xf,

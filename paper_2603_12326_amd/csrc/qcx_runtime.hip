@@ -951,7 +951,7 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
 
   // Per side: interval floor(D / d) of every transition relative to the
   // side's lowest, a stable counting sort by interval, and the chunks.
-  std::vector<int> order(n_t), ib(n_t);
+  std::vector<int> rank(n_t), ib(n_t);  // rank[t]: position of t in energy order
   std::vector<double> xf(n_t);
   std::vector<KkChunk> chunks;
   int base[2] = {0, 0}, nbin[2] = {0, 0}, rows = 0;
@@ -980,7 +980,7 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
     for (int t = 0; t < cnt_t; ++t) {
       const int k = t_lo + pos[iv[t]]++;
       const double u = dt[t_lo + t] / d;
-      order[k] = t_lo + t;
+      rank[t_lo + t] = k;
       ib[k] = iv[t];
       xf[k] = u - std::floor(u);
     }
@@ -1003,7 +1003,7 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
 
   HIPCK(stage_begin(ctx));
   HIPCK(upload(ctx, ctx->d_w, w.data(), w.size()));
-  HIPCK(upload(ctx, ctx->d_kk_order, order.data(), order.size()));
+  HIPCK(upload(ctx, ctx->d_kk_rank, rank.data(), rank.size()));
   HIPCK(upload(ctx, ctx->d_kk_ib, ib.data(), ib.size()));
   HIPCK(upload(ctx, ctx->d_kk_xf, xf.data(), xf.size()));
   HIPCK(upload(ctx, ctx->d_kk_chunks, chunks.data(), chunks.size()));
@@ -1018,7 +1018,7 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
   ctx->n_pairs64 = 0;
   int sp_all, sp_bin, sp_tr;
   HIPCK(span_begin(ctx, 3, &sp_all));
-  launch_kk_pack(ctx->d_R.as<cplx>(), ctx->ldt, n_g, n_gp, n_t, ctx->d_kk_order.as<int>(),
+  launch_kk_pack(ctx->d_R.as<cplx>(), ctx->ldt, n_g, n_gp, n_t, ctx->d_kk_rank.as<int>(),
                  ctx->d_kk_Rs.as<cplx>(), st);
   HIPCK(span_begin(ctx, 1, &sp_bin));
   launch_kk_bin(ctx->d_kk_Rs.as<cplx>(), n_gp, n_g, ctx->d_kk_ib.as<int>(), ctx->d_kk_xf.as<double>(),
