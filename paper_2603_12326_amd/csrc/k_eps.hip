@@ -110,6 +110,13 @@ __device__ inline cplx opaque(cplx x) {
   return x;
 }
 
+// The same for an integer: row indices derived from it inside a loop are then
+// recomputed there instead of being hoisted (and spilled) as RP constants.
+__device__ inline int opaque_i(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 __device__ inline double readlane_d(double v, int lane) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
@@ -332,10 +339,11 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
   cplx wk = {0.0, 0.0};
 
   auto choose = [&](const cplx (&c)[RP], int kc, int pb) {
+    const int lo = opaque_i(l);
     unsigned long long best = 0ull;
 #pragma unroll
     for (int a = 0; a < RP; ++a) {
-      const int i = l + 64 * a;
+      const int i = lo + 64 * a;
       if (i < n && !((used >> a) & 1u)) best = max(best, pivot_key(c[a], i));
     }
     best = wave_max_u64(best);
@@ -350,7 +358,7 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
     const cplx inv = cinv(pv);
 #pragma unroll
     for (int a = 0; a < RP; ++a) {
-      const int i = l + 64 * a;
+      const int i = lo + 64 * a;
       cplx y = c[a];
       if (i == p) y.re -= 1.0;
       if (i < n) ucol[pb * 64 * RP + i] = cmul(y, inv);
@@ -369,10 +377,13 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
     const int jc = k0 + v;
     __syncthreads();  // the previous panel's update is complete
     cplx pm[RP];
+    {
+      const int lo = opaque_i(l);
 #pragma unroll
-    for (int a = 0; a < RP; ++a) {
-      const int i = l + 64 * a;
-      pm[a] = (hascol && i < n) ? A[(size_t)i * n + jc] : cplx{0.0, 0.0};
+      for (int a = 0; a < RP; ++a) {
+        const int i = lo + 64 * a;
+        pm[a] = (hascol && i < n) ? A[(size_t)i * n + jc] : cplx{0.0, 0.0};
+      }
     }
     if (v == 0) choose(pm, k0, k0 & 1);
     for (int kk = 0; kk < mb; ++kk) {
@@ -382,6 +393,7 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
       const int pl = p & 63, pa = p >> 6;
       if (l == pl) used |= 1u << pa;
       if (hascol) {
+        const int lo = opaque_i(l);
         cplx x = pm[0];
 #pragma unroll
         for (int a = 1; a < RP; ++a)
@@ -390,7 +402,7 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
         if (v == kk) w = wk;  // owner of column k: w_k = piv + 1
 #pragma unroll
         for (int a = 0; a < RP; ++a) {
-          const int i = l + 64 * a;
+          const int i = lo + 64 * a;
           const cplx u = i < n ? ucol[par * 64 * RP + i] : cplx{0.0, 0.0};
           pm[a].re = fma(-u.re, w.re, pm[a].re);
           pm[a].re = fma(u.im, w.im, pm[a].re);
@@ -403,9 +415,10 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
       }
     }
     if (hascol) {
+      const int lo = opaque_i(l);
 #pragma unroll
       for (int a = 0; a < RP; ++a) {
-        const int i = l + 64 * a;
+        const int i = lo + 64 * a;
         if (i < n) A[(size_t)i * n + jc] = pm[a];
       }
     }
