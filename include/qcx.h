@@ -25,6 +25,10 @@
  *     PyTorch: torch.cuda.current_stream().cuda_stream).  The library never
  *     creates or destroys that stream.  Calls that return results on the host
  *     synchronise it; all others are asynchronous.
+ *   - Calls that stage host data (qcx_set_cell_basis, qcx_set_states,
+ *     qcx_pair_density*, qcx_chi0, qcx_chi0_kk, qcx_loss_diag, qcx_qbin_add /
+ *     _finish / _rate_halo, and qcx_run_batch when it builds a plan) return
+ *     QCX_EINVAL while the context's stream is being captured into a graph.
  *   - A context is not thread-safe; use one context per host thread.
  *   - The call order is qcx_set_cell_basis -> qcx_set_states ->
  *     qcx_pair_density -> qcx_chi0 -> qcx_eps_inv -> qcx_loss.  A call made
@@ -193,6 +197,34 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
  * Errors: QCX_ESTATE (no chi0), QCX_EINVAL, QCX_ENOMEM. */
 int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out);
 
+/* Diagonal of the inverse of caller-supplied dielectric matrices (Eq.
+ * eps_LFE with lfe = 1, Gauss-Jordan with partial pivoting in FP64 as in
+ * qcx_eps_inv; Eq. eps_noLFE, d_G = 1 / eps_GG, with lfe = 0) and the loss
+ * -Im d_G: for an eps formed outside the library, e.g. from a model of the
+ * screening or another response route.  The context supplies the device,
+ * the stream and its working buffers; its pair densities, chi0 and results
+ * of qcx_eps_inv are not used (qcx_loss afterwards needs qcx_eps_inv again).
+ *   n_w, n_G   matrices and their size, 1 <= n_w <= 65536, 1 <= n_G <= 2048
+ *   eps        device [n_w][n_G][n_G] c128 (read only; copied to a working
+ *              buffer of the context)
+ *   loss_out   device [n_w][n_G] float64
+ *   diag_out   NULL or device [n_w][n_G] c128 receiving d
+ *   epsM_out   NULL or device [n_w] c128 receiving eps_M = 1 / d_0
+ * Asynchronous.  A zero or non-finite pivot (or eps_GG for lfe = 0) is
+ * reported by the next qcx_sync as QCX_ESINGULAR naming the lowest such
+ * frequency index.
+ * Errors: QCX_EINVAL (sizes, NULL buffers), QCX_ENOMEM. */
+int qcx_eps_inv_given(qcx_ctx* ctx, int n_w, int n_G, const void* eps, int lfe, double* loss_out,
+                      void* diag_out, void* epsM_out);
+
+/* Cap the device memory the context's own buffers may hold (all of them but
+ * a batch plan's, a surrogate's and a q-binning table's): a call that would
+ * grow them beyond `bytes` returns QCX_ENOMEM and keeps the buffers it had;
+ * 0 removes the cap (the default).  qcx_memory_used reports their current
+ * total.  Errors: QCX_EINVAL (NULL). */
+int qcx_set_memory_limit(qcx_ctx* ctx, size_t bytes);
+int qcx_memory_used(const qcx_ctx* ctx, size_t* bytes);
+
 /* Loss function at momentum q + G: out[w][G] = Im(-1/eps(w, q+G)) = -Im d_G
  * (Eq. eps_LFE, or Eq. eps_noLFE when qcx_eps_inv ran with lfe = 0).
  *   out  [n_w][n_G] doubles, host (mem = QCX_MEM_HOST: synchronises and
@@ -218,8 +250,9 @@ int qcx_loss(qcx_ctx* ctx, double* out, int mem);
  * part and its real part the Kramers-Kronig transform of it.  Everything
  * runs in FP64: the binning on the vector units over energy-sorted
  * transitions (each bin written once, no atomics: the result does not depend
- * on the launch), the transform as one FP64 MFMA product of the
- * [2 n_w][bins] kernel matrix with the [bins][2 n_pairs] spectral function.
+ * on the launch), the transform as one FP64 matrix product (rocBLAS dgemm)
+ * of the [2 n_w][bins] kernel matrix with the [bins][2 n_pairs] spectral
+ * function.
  * Afterwards qcx_eps_inv / qcx_loss work as after qcx_chi0.  The transition
  * energies are read back to the host (the call synchronises the stream).
  *   n_w, w_eV, eta_eV (>= 0), chi0_out as for qcx_chi0; bin_eV > 0
@@ -276,11 +309,14 @@ typedef struct qcx_item {
  * (splits are added in FP64).  With autotuning on (qcx_set_autotune, FP32 and
  * split-BF16), the first call of a signature builds a plan for each target in
  * {128, 256, 512, 1024}, replays and times each with HIP events on ctxs[0]'s
- * stream and keeps the fastest (that call synchronises the stream; tuning is
- * skipped while the stream is being captured).  Every replay computes the
- * complete result, so the outputs are those of the kept plan.
- * Asynchronous otherwise; qcx_batch_sync(ctxs[0]) waits and reports
- * QCX_ESINGULAR.  With timing on (qcx_set_timing on ctxs[0]),
+ * stream and keeps the fastest (that call synchronises the stream).  Every
+ * replay computes the complete result, so the outputs are those of the kept
+ * plan.  Contexts may use different streams: the batch waits on ctxs[0]'s
+ * stream for the work already queued on the others, and the others wait for
+ * the batch before any later work of theirs.  Asynchronous otherwise;
+ * qcx_batch_sync(ctxs[0]) waits and reports QCX_ESINGULAR, and the deferred
+ * state checks (QCX_EINVAL / QCX_ENONORTH, as qcx_sync) of every context of
+ * the batch, which must all stay alive until then.  With timing on (qcx_set_timing on ctxs[0]),
  * qcx_stage_times reports t[1] the persistent bulk launch, t[4] head/wings +
  * assembly + inversion + loss, t[3] the whole batch.
  * Errors: QCX_EINVAL (sizes, devices, NULL loss_out), QCX_ESTATE (a context
@@ -444,13 +480,14 @@ int qcx_qbin_rate_halo(qcx_qbin* b, const double* w_eV, const double* S_iso, con
  * N_G, padded N_T, padded rows), every candidate configuration - K split
  * (a power of two up to 64, at least enough that no split sums more than
  * 1024 MFMA steps of 16 transitions in FP32: the splits are added in FP64)
- * and a 2- or 3-stage LDS pipeline, within 160 KB of LDS - is timed on the
+ * and the LDS pipeline (2 or 3 stages, or 3 stages with the transition slab
+ * one step ahead of the weights), within 160 KB of LDS - is timed on the
  * real operands with HIP events and the fastest is kept for the process;
  * that call synchronises the stream.  Shapes whose FP32 partial sums would
  * exceed 8 GB run in chunks of frequency rows reduced into FP64.  The
  * result used is always computed with the chosen configuration.  mode 0: a
- * fixed heuristic.  Tuning is skipped while the stream is being captured and
- * for shapes whose single launch is estimated above 0.5 s.
+ * fixed heuristic.  Tuning is skipped for shapes whose single launch is
+ * estimated above 0.5 s.
  * Errors: QCX_EINVAL (mode). */
 int qcx_set_autotune(qcx_ctx* ctx, int mode);
 /* Configuration of the last bulk launch: cfg = {K split, pipeline (2 or 3 LDS stages;

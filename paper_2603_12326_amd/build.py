@@ -3,7 +3,7 @@
     python -m paper_2603_12326_amd.build          # or build() from Python
 
 Every .hip file under csrc/ is compiled with hipcc in parallel and linked into
-one shared library (with rocBLAS, used for the one plain FP64 product of the
+one shared library (with rocBLAS, used for the plain FP64 product of the
 Kramers-Kronig route).  Packed FP32 instructions are disabled
 (-target-feature -packed-fp32-ops); the host pass warns that it does not know
 the feature, which is harmless.

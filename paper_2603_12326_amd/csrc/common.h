@@ -27,20 +27,33 @@ __host__ __device__ inline cplx cmulc(cplx a, cplx b) {  // conj(a) * b
 __host__ __device__ inline cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
 
 // Device buffer owned by a context; grows, never shrinks, freed on destroy.
+// With a budget attached, a growth that would take the budget's total above
+// its limit (limit 0: none) fails with hipErrorOutOfMemory and keeps the old
+// buffer.
+struct DevBudget {
+  size_t used = 0, limit = 0;
+};
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  DevBudget* budget = nullptr;
   hipError_t reserve(size_t n) {
     if (n <= bytes) return hipSuccess;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
+    if (budget && budget->limit && budget->used - bytes + n > budget->limit)
+      return hipErrorOutOfMemory;
+    release();
     hipError_t e = hipMalloc(&p, n);
-    if (e == hipSuccess) bytes = n;
+    if (e == hipSuccess) {
+      bytes = n;
+      if (budget) budget->used += n;
+    } else {
+      p = nullptr;
+    }
     return e;
   }
   void release() {
     if (p) (void)hipFree(p);
+    if (budget) budget->used -= bytes;
     p = nullptr;
     bytes = 0;
   }
@@ -177,7 +190,10 @@ struct AsmArgs {
   double pref;
 };
 void launch_eps_assemble(const AsmArgs& a, const Chi0Geom& g, cplx* eps, hipStream_t st);
-void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st);
+// Gauss-Jordan diag(eps^-1) of n_w matrices; a zero or non-finite pivot in
+// matrix j sets *sing to at most w_base + j (atomic minimum)
+void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st,
+                    int w_base = 0);
 // noLFE loss from diagonal-only partials of n_g G (chunk columns 0..n_g-1)
 // into loss[j * ldl + g0 + b]
 // loss[w][g0 + b] (and, if inv is not null, inv[w][g0 + b] = 1 / eps_GG) for
@@ -196,7 +212,9 @@ struct GjJob {
 // launch); class 8 has no multi-item form.
 int gj_class(int n_g);
 void launch_gj_jobs(int cls, const GjJob* jobs, int n_jobs, int n_blocks, int max_n, hipStream_t st);
-void launch_nolfe_diag(const cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st);
+void launch_nolfe_diag(const cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st,
+                       int w_base = 0);
+// loss = -Im diag and, if epsM is not null, eps_M = 1 / diag[w][0]
 void launch_loss(const cplx* diag, int n_g, int n_w, double* loss, cplx* epsM, hipStream_t st);
 void launch_chi0_export(const AsmArgs& a, const Chi0Geom& g, cplx* chi, hipStream_t st);
 void launch_rho_export(const cplx* R, size_t ldt, int n_g, int n_t, cplx* out, hipStream_t st);

@@ -81,7 +81,13 @@ struct qcx_ctx {
 
   // eps
   bool have_eps = false;
+  bool sing_armed = false;  // d_sing holds the flag of an inversion not yet reported
   DevBuf d_eps, d_diag, d_epsM, d_loss, d_sing;
+
+  // device memory of the buffers above (qcx_set_memory_limit)
+  DevBudget budget;
+  // event for ordering a batch against the streams of its other contexts
+  hipEvent_t ev_order = nullptr;
 
   // pinned staging for host -> device copies: a ring of kStageSlots buffers,
   // one per call in turn; a call waits only until the copies of the call that
@@ -121,16 +127,22 @@ struct qcx_ctx {
   // batch plan owned by the first context of a batch (see qcx_batch.hip)
   qcx::BatchPlan* plan = nullptr;
 
-  ~qcx_ctx() {
-    if (plan) qcx::destroy_plan(plan);
-    DevBuf* all[] = {&d_sh_l, &d_sh_ex, &d_sh_ctr, &d_sh_off, &d_cells, &d_tvec, &d_kf,
+  std::vector<DevBuf*> buffers() {
+    return {&d_sh_l, &d_sh_ex, &d_sh_ctr, &d_sh_off, &d_cells, &d_tvec, &d_kf,
                      &d_Ck,   &d_Ek,    &d_Ckq,    &d_Ekq,    &d_dt,    &d_ph,   &d_phq,
                      &d_S,    &d_F0,    &d_dev,    &d_flags,    &d_Q,      &d_vq,    &d_F,    &d_M,
                      &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_rows, &d_pairs64, &d_C, &d_C64,
                      &d_XY,   &d_eps,   &d_diag,   &d_epsM,   &d_loss,  &d_sing,
                      &d_kk_rank, &d_kk_ib, &d_kk_xf, &d_kk_chunks, &d_kk_Rs, &d_kk_S, &d_kk_K,
                      &d_Fg, &d_Rp};
-    for (DevBuf* b : all) b->release();
+  }
+  qcx_ctx() {
+    for (DevBuf* b : buffers()) b->budget = &budget;
+  }
+  ~qcx_ctx() {
+    if (plan) qcx::destroy_plan(plan);
+    for (DevBuf* b : buffers()) b->release();
+    if (ev_order) (void)hipEventDestroy(ev_order);
     for (const Span& sp : spans) {
       (void)hipEventDestroy(sp.a);
       (void)hipEventDestroy(sp.b);
@@ -175,6 +187,18 @@ inline int fail(qcx_ctx* c, int code, const std::string& msg) {
   } while (0)
 
 inline size_t roundup(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+// Calls that stage host data (pinned ring, index tables cached by content,
+// synchronous fallbacks) cannot be recorded into a graph: they return
+// QCX_EINVAL while the context's stream is capturing.
+inline int reject_capture(qcx_ctx* c) {
+  hipStreamCaptureStatus s = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(c->stream, &s);
+  if (e != hipSuccess) return fail(c, QCX_EDEVICE, std::string("hipStreamIsCapturing: ") + hipGetErrorString(e));
+  if (s != hipStreamCaptureStatusNone)
+    return fail(c, QCX_EINVAL, "this call stages host data and cannot be captured into a graph");
+  return QCX_OK;
+}
 
 
 // Upload an index table unless the buffer already holds exactly these values

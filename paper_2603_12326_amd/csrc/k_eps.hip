@@ -89,6 +89,13 @@ __device__ inline cplx cinv(cplx a) {
   return {a.re * d, -a.im * d};
 }
 
+// A pivot of modulus zero, or a non-finite one (NaN or infinite entries, e.g.
+// eta = 0 with w on a transition energy), makes the matrix count as singular.
+__device__ inline bool bad_pivot(cplx v) {
+  const double m = fabs(v.re) + fabs(v.im);
+  return !(m > 0.0 && m < INFINITY);
+}
+
 // Pivot key for an LDS atomic maximum: the modulus |re| + |im| in the high
 // bits (non-negative doubles order like their bit patterns), the complement
 // of the row index in the low 12 bits, so that moduli equal to 40 bits go to
@@ -209,7 +216,7 @@ __device__ __forceinline__ void gj_reg_body(const cplx* __restrict__ A, int n,
       const cplx x = {readlane_d(c[a].re, pl), readlane_d(c[a].im, pl)};
       if (a == pa) pv = x;
     }
-    if (pv.re == 0.0 && pv.im == 0.0) singular = true;
+    if (bad_pivot(pv)) singular = true;
     const cplx inv = cinv(pv);
 #pragma unroll
     for (int a = 0; a < RP; ++a) {
@@ -354,7 +361,7 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
     for (int a = 1; a < RP; ++a)
       if (a == pa) x = opaque(c[a]);
     const cplx pv = {readlane_d(x.re, pl), readlane_d(x.im, pl)};
-    if (pv.re == 0.0 && pv.im == 0.0) singular = true;
+    if (bad_pivot(pv)) singular = true;
     const cplx inv = cinv(pv);
 #pragma unroll
     for (int a = 0; a < RP; ++a) {
@@ -500,16 +507,16 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
 
 template <int RP, int CP>
 __global__ void __launch_bounds__(1024) k_gj_reg(const cplx* __restrict__ eps, int n,
-                                                 cplx* __restrict__ diag, int* sing) {
+                                                 cplx* __restrict__ diag, int* sing, int w_base) {
   gj_reg_body<RP, CP>(eps + (size_t)blockIdx.x * n * n, n, diag + (size_t)blockIdx.x * n, sing,
-                      blockIdx.x);
+                      w_base + (int)blockIdx.x);
 }
 
 template <int RP>
 __global__ void __launch_bounds__(1024) k_gj_panel(cplx* __restrict__ eps, int n,
-                                                   cplx* __restrict__ diag, int* sing) {
+                                                   cplx* __restrict__ diag, int* sing, int w_base) {
   gj_panel_body<RP>(eps + (size_t)blockIdx.x * n * n, n, diag + (size_t)blockIdx.x * n, sing,
-                    blockIdx.x);
+                    w_base + (int)blockIdx.x);
 }
 
 // The job of this block in a multi-item launch: blocks [block0, block0 +
@@ -582,7 +589,8 @@ __device__ inline void block_argmax(double v, int i, double* redv, int* redi, in
 
 template <int MB>
 __global__ void __launch_bounds__(256) k_gj_blocked(cplx* __restrict__ eps, int n,
-                                                    cplx* __restrict__ diag, int* sing) {
+                                                    cplx* __restrict__ diag, int* sing,
+                                                    int w_base) {
   extern __shared__ char smem[];
   cplx* panel = reinterpret_cast<cplx*>(smem);  // [n][MB]
   cplx* ucol = panel + (size_t)n * MB;            // [n]
@@ -634,7 +642,7 @@ __global__ void __launch_bounds__(256) k_gj_blocked(cplx* __restrict__ eps, int 
       for (int c = tid; c < mb; c += 256) wrow[c] = panel[p * MB + c];
       __syncthreads();
       const cplx pv = wrow[kk];
-      if (pv.re == 0.0 && pv.im == 0.0) singular = true;
+      if (bad_pivot(pv)) singular = true;
       const cplx inv = cinv(pv);
       for (int e = tid; e < n * mb; e += 256) {
         const int i = e / mb, c = e % mb;
@@ -700,19 +708,19 @@ __global__ void __launch_bounds__(256) k_gj_blocked(cplx* __restrict__ eps, int 
   }
   __syncthreads();
   for (int k = tid; k < n; k += 256) diag[(size_t)blockIdx.x * n + k] = A[(size_t)piv[k] * n + sor[k]];
-  if (singular && tid == 0) atomicMin(sing, (int)blockIdx.x);
+  if (singular && tid == 0) atomicMin(sing, w_base + (int)blockIdx.x);
 }
 
 size_t gj_blocked_lds(int n, int mb) {
   return sizeof(cplx) * ((size_t)n * mb + n + mb + (size_t)mb * GJ_YT) + sizeof(int) * (3 * (size_t)n + mb);
 }
 
-__global__ void k_nolfe(const cplx* eps, int n, int n_w, cplx* diag, int* sing) {
+__global__ void k_nolfe(const cplx* eps, int n, int n_w, cplx* diag, int* sing, int w_base) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long)n * n_w) return;
   const int j = (int)(i / n), G = (int)(i % n);
   const cplx e = eps[((size_t)j * n + G) * n + G];
-  if (e.re == 0.0 && e.im == 0.0) atomicMin(sing, j);
+  if (bad_pivot(e)) atomicMin(sing, w_base + j);
   diag[i] = cinv(e);
 }
 
@@ -721,7 +729,7 @@ __global__ void k_loss(const cplx* diag, int n, int n_w, double* loss, cplx* eps
   if (i >= (long)n * n_w) return;
   const cplx d = diag[i];
   loss[i] = -d.im;
-  if (i % n == 0) epsM[i / n] = cinv(d);
+  if (epsM && i % n == 0) epsM[i / n] = cinv(d);
 }
 
 // noLFE loss of Eq. (eps_noLFE) for a list of G from diagonal-only partial
@@ -789,28 +797,29 @@ int gj_class(int n_g) {
   return 8;  // LDS-blocked kernel, single item only
 }
 
-void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st) {
+void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st,
+                    int w_base) {
   const dim3 g(n_w), b(1024);
   switch (gj_class(n_g)) {
-    case 0: hipLaunchKernelGGL((k_gj_reg<1, 4>), g, b, 0, st, eps, n_g, diag, sing); return;
-    case 1: hipLaunchKernelGGL((k_gj_reg<2, 8>), g, b, 0, st, eps, n_g, diag, sing); return;
-    case 2: hipLaunchKernelGGL(k_gj_panel<3>, g, b, gj_panel_lds(n_g, 3), st, eps, n_g, diag, sing); return;
-    case 3: hipLaunchKernelGGL(k_gj_panel<4>, g, b, gj_panel_lds(n_g, 4), st, eps, n_g, diag, sing); return;
-    case 4: hipLaunchKernelGGL(k_gj_panel<5>, g, b, gj_panel_lds(n_g, 5), st, eps, n_g, diag, sing); return;
-    case 5: hipLaunchKernelGGL(k_gj_panel<8>, g, b, gj_panel_lds(n_g, 8), st, eps, n_g, diag, sing); return;
-    case 6: hipLaunchKernelGGL(k_gj_panel<12>, g, b, gj_panel_lds(n_g, 12), st, eps, n_g, diag, sing); return;
-    case 7: hipLaunchKernelGGL(k_gj_panel<16>, g, b, gj_panel_lds(n_g, 16), st, eps, n_g, diag, sing); return;
+    case 0: hipLaunchKernelGGL((k_gj_reg<1, 4>), g, b, 0, st, eps, n_g, diag, sing, w_base); return;
+    case 1: hipLaunchKernelGGL((k_gj_reg<2, 8>), g, b, 0, st, eps, n_g, diag, sing, w_base); return;
+    case 2: hipLaunchKernelGGL(k_gj_panel<3>, g, b, gj_panel_lds(n_g, 3), st, eps, n_g, diag, sing, w_base); return;
+    case 3: hipLaunchKernelGGL(k_gj_panel<4>, g, b, gj_panel_lds(n_g, 4), st, eps, n_g, diag, sing, w_base); return;
+    case 4: hipLaunchKernelGGL(k_gj_panel<5>, g, b, gj_panel_lds(n_g, 5), st, eps, n_g, diag, sing, w_base); return;
+    case 5: hipLaunchKernelGGL(k_gj_panel<8>, g, b, gj_panel_lds(n_g, 8), st, eps, n_g, diag, sing, w_base); return;
+    case 6: hipLaunchKernelGGL(k_gj_panel<12>, g, b, gj_panel_lds(n_g, 12), st, eps, n_g, diag, sing, w_base); return;
+    case 7: hipLaunchKernelGGL(k_gj_panel<16>, g, b, gj_panel_lds(n_g, 16), st, eps, n_g, diag, sing, w_base); return;
     default: break;
   }
   if (gj_blocked_lds(n_g, 32) <= 160 * 1024)
     hipLaunchKernelGGL(k_gj_blocked<32>, dim3(n_w), dim3(256), gj_blocked_lds(n_g, 32), st, eps,
-                       n_g, diag, sing);
+                       n_g, diag, sing, w_base);
   else if (gj_blocked_lds(n_g, 16) <= 160 * 1024)
     hipLaunchKernelGGL(k_gj_blocked<16>, dim3(n_w), dim3(256), gj_blocked_lds(n_g, 16), st, eps,
-                       n_g, diag, sing);
+                       n_g, diag, sing, w_base);
   else
     hipLaunchKernelGGL(k_gj_blocked<8>, dim3(n_w), dim3(256), gj_blocked_lds(n_g, 8), st, eps,
-                       n_g, diag, sing);
+                       n_g, diag, sing, w_base);
 }
 
 void launch_gj_jobs(int cls, const GjJob* jobs, int n_jobs, int n_blocks, int max_n, hipStream_t st) {
@@ -828,10 +837,11 @@ void launch_gj_jobs(int cls, const GjJob* jobs, int n_jobs, int n_blocks, int ma
   }
 }
 
-void launch_nolfe_diag(const cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st) {
+void launch_nolfe_diag(const cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st,
+                       int w_base) {
   const long total = (long)n_g * n_w;
   hipLaunchKernelGGL(k_nolfe, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, eps, n_g,
-                     n_w, diag, sing);
+                     n_w, diag, sing, w_base);
 }
 
 void launch_loss(const cplx* diag, int n_g, int n_w, double* loss, cplx* epsM, hipStream_t st) {

@@ -35,6 +35,7 @@ struct PlanItem {
 
 struct BatchPlan {
   std::vector<double> key;
+  std::vector<qcx_ctx*> ctxs;  // the batch's contexts (part of the key)
   int precision = 0, lfe = 1, hw64 = 1, n_items = 0;
   std::vector<PlanItem> items;
   std::vector<DevBuf> r32;  // per context
@@ -422,12 +423,24 @@ int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_
   HIPCK(hipSetDevice(ctx->device));
   const int hw64 = headwings_fp64 ? 1 : 0;
   std::vector<double> key = batch_key(ctxs, n_ctx, items, n_items, precision, lfe ? 1 : 0, hw64);
+  // the other contexts' pair densities and energies were produced on their
+  // own streams: the batch (on ctxs[0]'s stream) waits for them
+  std::vector<hipStream_t> others;
+  for (int c = 1; c < n_ctx; ++c) {
+    hipStream_t s = ctxs[c]->stream;
+    if (s != ctx->stream && std::find(others.begin(), others.end(), s) == others.end()) {
+      others.push_back(s);
+      if (!ctxs[c]->ev_order) HIPCK(hipEventCreateWithFlags(&ctxs[c]->ev_order, hipEventDisableTiming));
+      HIPCK(hipEventRecord(ctxs[c]->ev_order, s));
+      HIPCK(hipStreamWaitEvent(ctx->stream, ctxs[c]->ev_order, 0));
+    }
+  }
   if (!ctx->plan || ctx->plan->key != key) {
+    // building a plan stages host tables and captures graphs of its own
+    if (int rc = reject_capture(ctx)) return rc;
     if (ctx->plan) destroy_plan(ctx->plan);
     ctx->plan = nullptr;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    HIPCK(hipStreamIsCapturing(ctx->stream, &cs));
-    const bool tune = ctx->autotune && precision != QCX_FP64 && cs == hipStreamCaptureStatusNone;
+    const bool tune = ctx->autotune && precision != QCX_FP64;
     std::vector<int> cands = tune ? std::vector<int>{128, 256, 512, 1024} : std::vector<int>{256};
     const auto t0 = std::chrono::steady_clock::now();
     BatchPlan* best = nullptr;
@@ -454,9 +467,17 @@ int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_
     best->tune_ms = cands.size() > 1
                         ? std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count()
                         : 0.0;
+    best->ctxs.assign(ctxs, ctxs + n_ctx);
     ctx->plan = best;
   }
   HIPCK(launch_plan(ctx, ctx->plan));
+  // and the other streams do not overwrite those buffers before the batch
+  // has read them
+  if (!others.empty()) {
+    if (!ctx->ev_order) HIPCK(hipEventCreateWithFlags(&ctx->ev_order, hipEventDisableTiming));
+    HIPCK(hipEventRecord(ctx->ev_order, ctx->stream));
+    for (hipStream_t s : others) HIPCK(hipStreamWaitEvent(s, ctx->ev_order, 0));
+  }
   return QCX_OK;
 }
 
@@ -476,6 +497,14 @@ int qcx_batch_sync(qcx_ctx* ctx) {
   HIPCK(hipStreamSynchronize(ctx->stream));
   if (int rc = check_deferred(ctx)) return rc;
   if (!ctx->plan) return QCX_OK;
+  // deferred state checks of every context of the batch (their streams were
+  // waited for by the batch itself)
+  for (size_t c = 1; c < ctx->plan->ctxs.size(); ++c) {
+    qcx_ctx* x = ctx->plan->ctxs[c];
+    if (x == ctx) continue;
+    HIPCK(hipStreamSynchronize(x->stream));
+    if (int rc = check_deferred(x)) return fail(ctx, rc, "context " + std::to_string(c) + ": " + x->err);
+  }
   std::vector<int> s(ctx->plan->n_items);
   HIPCK(hipMemcpy(s.data(), ctx->plan->d_sing.p, sizeof(int) * s.size(), hipMemcpyDeviceToHost));
   for (size_t i = 0; i < s.size(); ++i)

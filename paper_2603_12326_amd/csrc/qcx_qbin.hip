@@ -266,6 +266,7 @@ int qcx_qbin_add(qcx_qbin* b, int n, const double* qvec, const void* vals, int l
   if (kind != QCX_QBIN_EPS && kind != QCX_QBIN_INV) return fail(ctx, QCX_EINVAL, "bad kind");
   for (int e = 0; e < 3 * n; ++e)
     if (!std::isfinite(qvec[e])) return fail(ctx, QCX_EINVAL, "non-finite momentum");
+  if (int rc = reject_capture(ctx)) return rc;
   HIPCK(hipSetDevice(ctx->device));
   // entries grouped by bin (entry order kept inside a bin)
   std::vector<std::pair<int, int>> be;
@@ -303,6 +304,7 @@ int qcx_qbin_finish(qcx_qbin* b, void* eps_out, double* S_out, int* state_out) {
   if (!b) return QCX_EINVAL;
   qcx_ctx* ctx = b->ctx;
   if (!S_out) return fail(ctx, QCX_EINVAL, "S_out is required");
+  if (int rc = reject_capture(ctx)) return rc;
   HIPCK(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   const int nb = b->n_bins, n_w = b->n_w;
@@ -385,6 +387,7 @@ int qcx_qbin_rate_halo(qcx_qbin* b, const double* w_eV, const double* S_iso, con
     if (!(w_eV[a] >= 0.0) || !std::isfinite(w_eV[a])) return fail(ctx, QCX_EINVAL, "frequencies must be >= 0");
     w[a] = w_eV[a];
   }
+  if (int rc = reject_capture(ctx)) return rc;
   HIPCK(hipSetDevice(ctx->device));
   const double mu = h->m_chi_eV * kMeEV / (h->m_chi_eV + kMeEV);
   const double n_chi = h->rho_chi_GeV_cm3 * 1e9 / h->m_chi_eV * std::pow(kHbarcEVcm, 3);   // eV^3

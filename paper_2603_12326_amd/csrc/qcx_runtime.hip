@@ -217,12 +217,15 @@ int qcx_sync(qcx_ctx* ctx) {
   HIPCK(hipSetDevice(ctx->device));
   HIPCK(hipStreamSynchronize(ctx->stream));
   if (int rc = check_deferred(ctx)) return rc;
-  if (ctx->have_eps && ctx->d_sing.p) {
+  if (ctx->sing_armed && ctx->d_sing.p) {
     int s = INT_MAX;
     HIPCK(hipMemcpy(&s, ctx->d_sing.p, sizeof(int), hipMemcpyDeviceToHost));
-    if (s != INT_MAX)
+    if (s != INT_MAX) {
+      // reported once; a later inversion arms the flag again
+      ctx->sing_armed = false;
       return fail(ctx, QCX_ESINGULAR,
-                  "zero pivot in eps at frequency index " + std::to_string(s));
+                  "zero or non-finite pivot in eps at frequency index " + std::to_string(s));
+    }
   }
   return QCX_OK;
 }
@@ -241,6 +244,7 @@ int qcx_set_cell_basis(qcx_ctx* ctx, const double lat[9], int n_atoms, const dou
                      lat[1] * (lat[3] * lat[8] - lat[5] * lat[6]) +
                      lat[2] * (lat[3] * lat[7] - lat[4] * lat[6]);
   if (!(fabs(det) > 1e-12)) return fail(ctx, QCX_EINVAL, "singular lattice");
+  if (int rc = reject_capture(ctx)) return rc;
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_basis = ctx->have_states = ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
   memcpy(ctx->lat, lat, sizeof(double) * 9);
@@ -317,6 +321,7 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
   if (n_t > (size_t)1 << 30) return fail(ctx, QCX_EINVAL, "too many transitions");
   if (band_contract_lds(ctx->n_ao, n_bands, n_occ) > 160 * 1024)
     return fail(ctx, QCX_EINVAL, "N_AO x n_bands too large for the band kernel");
+  if (int rc = reject_capture(ctx)) return rc;
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_states = ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
   hipStream_t st = ctx->stream;
@@ -473,6 +478,7 @@ static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_
     if (!(nq > 0.0) || !std::isfinite(nq)) return fail(ctx, QCX_EINVAL, "qhat must be a nonzero direction");
     for (int x = 0; x < 3; ++x) qh[x] = qhat[x] / nq;
   }
+  if (int rc = reject_capture(ctx)) return rc;
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
   hipStream_t st = ctx->stream;
@@ -574,6 +580,7 @@ int qcx_loss_diag(qcx_ctx* ctx, int n_G, const int* G_int, int n_w, const double
   if (!(eta_eV >= 0.0) || !std::isfinite(eta_eV)) return fail(ctx, QCX_EINVAL, "eta must be >= 0");
   if (precision < QCX_FP64 || precision > QCX_SPLIT_BF16) return fail(ctx, QCX_EINVAL, "bad precision");
   if (!loss_out) return fail(ctx, QCX_EINVAL, "loss_out must be a device buffer");
+  if (int rc = reject_capture(ctx)) return rc;
   HIPCK(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   std::vector<double> w(n_w);
@@ -691,6 +698,7 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
   if (precision < QCX_FP64 || precision > QCX_SPLIT_BF16)
     return fail(ctx, QCX_EINVAL, "bad precision");
 
+  if (int rc = reject_capture(ctx)) return rc;
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_chi0 = ctx->have_eps = false;
   hipStream_t st = ctx->stream;
@@ -929,6 +937,7 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
   if (n_w < 1 || n_w > 65536 || !w_eV) return fail(ctx, QCX_EINVAL, "need 1 <= n_w <= 65536");
   if (!(eta_eV >= 0.0) || !std::isfinite(eta_eV)) return fail(ctx, QCX_EINVAL, "eta must be >= 0");
   if (!(bin_eV > 0.0) || !std::isfinite(bin_eV)) return fail(ctx, QCX_EINVAL, "bin width must be > 0");
+  if (int rc = reject_capture(ctx)) return rc;
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_chi0 = ctx->have_eps = false;
   hipStream_t st = ctx->stream;
@@ -1082,7 +1091,8 @@ int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out) {
   HIPCK(ctx->d_epsM.reserve(sizeof(cplx) * (size_t)nw));
   HIPCK(ctx->d_loss.reserve(sizeof(double) * (size_t)nw * n));
   HIPCK(ctx->d_sing.reserve(sizeof(int)));
-  HIPCK(hipMemsetD32Async((hipDeviceptr_t)ctx->d_sing.p, INT_MAX, 1, st));
+  launch_set_int(ctx->d_sing.as<int>(), INT_MAX, st);
+  ctx->sing_armed = true;
   int sp_eps;
   HIPCK(span_begin(ctx, 4, &sp_eps));
   AsmArgs a{};
@@ -1113,6 +1123,50 @@ int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out) {
     HIPCK(hipMemcpyAsync(epsM_out, ctx->d_epsM.p, sizeof(cplx) * (size_t)nw,
                          hipMemcpyDeviceToDevice, st));
   ctx->have_eps = true;
+  return QCX_OK;
+}
+
+int qcx_eps_inv_given(qcx_ctx* ctx, int n_w, int n_G, const void* eps, int lfe, double* loss_out,
+                      void* diag_out, void* epsM_out) {
+  if (!ctx) return QCX_EINVAL;
+  if (n_w < 1 || n_w > 65536) return fail(ctx, QCX_EINVAL, "need 1 <= n_w <= 65536");
+  if (n_G < 1 || n_G > 2048) return fail(ctx, QCX_EINVAL, "need 1 <= n_G <= 2048");
+  if (!eps || !loss_out) return fail(ctx, QCX_EINVAL, "eps and loss_out must be device buffers");
+  HIPCK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const size_t n = (size_t)n_G, nw = (size_t)n_w;
+  // the inversion overwrites its matrices: work on a copy
+  HIPCK(ctx->d_eps.reserve(sizeof(cplx) * nw * n * n));
+  cplx* diag = static_cast<cplx*>(diag_out);
+  if (!diag) {
+    HIPCK(ctx->d_diag.reserve(sizeof(cplx) * nw * n));
+    diag = ctx->d_diag.as<cplx>();
+  }
+  HIPCK(ctx->d_sing.reserve(sizeof(int)));
+  // the context's own inversion results are no longer the latest
+  ctx->have_eps = false;
+  HIPCK(hipMemcpyAsync(ctx->d_eps.p, eps, sizeof(cplx) * nw * n * n, hipMemcpyDeviceToDevice, st));
+  launch_set_int(ctx->d_sing.as<int>(), INT_MAX, st);
+  ctx->sing_armed = true;
+  if (lfe)
+    launch_gj_diag(ctx->d_eps.as<cplx>(), n_G, n_w, diag, ctx->d_sing.as<int>(), st);
+  else
+    launch_nolfe_diag(ctx->d_eps.as<cplx>(), n_G, n_w, diag, ctx->d_sing.as<int>(), st);
+  LAUNCHCK("inverse (given eps)");
+  launch_loss(diag, n_G, n_w, loss_out, static_cast<cplx*>(epsM_out), st);
+  LAUNCHCK("loss (given eps)");
+  return QCX_OK;
+}
+
+int qcx_set_memory_limit(qcx_ctx* ctx, size_t bytes) {
+  if (!ctx) return QCX_EINVAL;
+  ctx->budget.limit = bytes;
+  return QCX_OK;
+}
+
+int qcx_memory_used(const qcx_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return QCX_EINVAL;
+  *bytes = ctx->budget.used;
   return QCX_OK;
 }
 

@@ -53,6 +53,9 @@ _SIGS = {
     "qcx_pair_density_optical": [_P, _I, _P, _P, _P],
     "qcx_chi0": [_P, _I, _P, _D, _I, _I, _P],
     "qcx_eps_inv": [_P, _I, _P, _P],
+    "qcx_eps_inv_given": [_P, _I, _I, _P, _I, _P, _P, _P],
+    "qcx_set_memory_limit": [_P, ctypes.c_size_t],
+    "qcx_memory_used": [_P, ctypes.POINTER(ctypes.c_size_t)],
     "qcx_loss": [_P, _P, _I],
     "qcx_stage_times": [_P, _P],
     "qcx_set_timing": [_P, _I],
@@ -272,6 +275,33 @@ class Context:
         d = None if diag_out is None else _dev_ptr(diag_out, "c128", self.n_w * self.n_g, "diag_out")
         e = None if epsM_out is None else _dev_ptr(epsM_out, "c128", self.n_w, "epsM_out")
         self._check(self.lib.qcx_eps_inv(self._h, 1 if lfe else 0, d, e))
+
+    def eps_inv_given(self, eps, lfe: bool = True, loss_out=None, diag_out=None, epsM_out=None):
+        """diag(eps^-1) and the loss of caller-supplied matrices (qcx_eps_inv_given):
+        eps a CUDA complex128 tensor [n_w][n_G][n_G]; returns loss_out (CUDA
+        float64 [n_w][n_G], allocated when None)."""
+        import torch
+
+        n_w, n_g, n_g2 = eps.shape
+        if n_g != n_g2:
+            raise ValueError("eps must be [n_w][n_G][n_G]")
+        if loss_out is None:
+            loss_out = torch.empty((n_w, n_g), dtype=torch.float64, device=eps.device)
+        self._check(self.lib.qcx_eps_inv_given(
+            self._h, n_w, n_g, _dev_ptr(eps, "c128", n_w * n_g * n_g, "eps"), 1 if lfe else 0,
+            _dev_ptr(loss_out, "f64", n_w * n_g, "loss_out"),
+            None if diag_out is None else _dev_ptr(diag_out, "c128", n_w * n_g, "diag_out"),
+            None if epsM_out is None else _dev_ptr(epsM_out, "c128", n_w, "epsM_out")))
+        return loss_out
+
+    def set_memory_limit(self, nbytes: int):
+        """Cap the context's own device buffers (0: no cap)."""
+        self._check(self.lib.qcx_set_memory_limit(self._h, int(nbytes)))
+
+    def memory_used(self) -> int:
+        v = ctypes.c_size_t(0)
+        self._check(self.lib.qcx_memory_used(self._h, ctypes.byref(v)))
+        return int(v.value)
 
     def loss(self, out=None):
         """Host numpy [n_w][n_G] (synchronising) when out is None, else a CUDA tensor."""
