@@ -189,12 +189,13 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
 /* FP64 dielectric matrix eps_GG' = delta_GG' - 4 pi chi0_GG' / (|q+G||q+G'|)
  * (the symmetrised form of Eq. RPA) and, per frequency:
  *   lfe = 1: d_G = [eps^-1]_GG by Gauss-Jordan inversion with partial
- *            pivoting (Eq. eps_LFE);
+ *            pivoting (Eq. eps_LFE), for n_G <= 1024;
  *   lfe = 0: d_G = 1 / eps_GG (Eq. eps_noLFE).
  *   diag_out  NULL or device [n_w][n_G] c128 receiving d
  *   epsM_out  NULL or device [n_w] c128 receiving eps_M = 1/d_0
- * A zero pivot is reported by qcx_sync / qcx_loss as QCX_ESINGULAR.
- * Errors: QCX_ESTATE (no chi0), QCX_EINVAL, QCX_ENOMEM. */
+ * A zero or non-finite pivot is reported by qcx_sync / qcx_loss as
+ * QCX_ESINGULAR.
+ * Errors: QCX_ESTATE (no chi0), QCX_EINVAL (lfe with n_G > 1024), QCX_ENOMEM. */
 int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out);
 
 /* Diagonal of the inverse of caller-supplied dielectric matrices (Eq.
@@ -204,7 +205,8 @@ int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out);
  * screening or another response route.  The context supplies the device,
  * the stream and its working buffers; its pair densities, chi0 and results
  * of qcx_eps_inv are not used (qcx_loss afterwards needs qcx_eps_inv again).
- *   n_w, n_G   matrices and their size, 1 <= n_w <= 65536, 1 <= n_G <= 2048
+ *   n_w, n_G   matrices and their size, 1 <= n_w <= 65536, 1 <= n_G <= 1024
+ *              (lfe = 1) or 65536 (lfe = 0), at most 2^33 elements
  *   eps        device [n_w][n_G][n_G] c128 (read only; copied to a working
  *              buffer of the context)
  *   loss_out   device [n_w][n_G] float64

@@ -547,174 +547,6 @@ size_t gj_panel_lds(int n, int rp) {
   return sizeof(double) * ((size_t)32 * zr + 2 * 32 * 64) + sizeof(int) * 2 * (size_t)n;
 }
 
-// Blocked Gauss-Jordan for n > 128 (one block of 256 threads per matrix; the
-// matrix stays in global memory).  Columns are processed in panels of MB: the
-// MB pivot steps are applied to the n x MB panel in LDS only (same pivots as the
-// unblocked sweep, which depends on the panel columns alone), the panel is
-// written back, and the remaining columns J receive the combined rank-MB
-// update  T[:, J] += Z Y  with Y = T[P][J] (pivot rows, before the update) and
-// Z = panel with 1 subtracted at (p_a, a), which turns the pivot rows into
-// B^-1 Y and the others into T - T[:,K] B^-1 Y.
-constexpr int GJ_YT = 32;  // trailing-update column tile
-
-__device__ inline void block_argmax(double v, int i, double* redv, int* redi, int* out) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(v, off, 64);
-    const int oi = __shfl_xor(i, off, 64);
-    if (oi != INT_MAX && (i == INT_MAX || ov > v || (ov == v && oi < i))) {
-      v = ov;
-      i = oi;
-    }
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    redv[wave] = v;
-    redi[wave] = i;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double b = -1.0;
-    int bi = INT_MAX;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      if (redi[w] == INT_MAX) continue;
-      if (bi == INT_MAX || redv[w] > b || (redv[w] == b && redi[w] < bi)) {
-        b = redv[w];
-        bi = redi[w];
-      }
-    }
-    *out = bi == INT_MAX ? 0 : bi;
-  }
-}
-
-template <int MB>
-__global__ void __launch_bounds__(256) k_gj_blocked(cplx* __restrict__ eps, int n,
-                                                    cplx* __restrict__ diag, int* sing,
-                                                    int w_base) {
-  extern __shared__ char smem[];
-  cplx* panel = reinterpret_cast<cplx*>(smem);  // [n][MB]
-  cplx* ucol = panel + (size_t)n * MB;            // [n]
-  cplx* wrow = ucol + n;                          // [MB]
-  cplx* ytile = wrow + MB;                        // [MB][GJ_YT]
-  int* used = reinterpret_cast<int*>(ytile + MB * GJ_YT);
-  int* piv = used + n;
-  int* sor = piv + n;
-  int* pb = sor + n;  // [MB] pivot rows of the current panel
-  __shared__ double redv[4];
-  __shared__ int redi[4];
-  __shared__ int pivrow;
-  cplx* A = eps + (size_t)blockIdx.x * n * n;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < n; i += 256) used[i] = 0;
-  bool singular = false;
-  for (int k0 = 0; k0 < n; k0 += MB) {
-    const int mb = min(MB, n - k0);
-    __syncthreads();
-    for (int e = tid; e < n * mb; e += 256) {
-      const int i = e / mb, c = e % mb;
-      panel[i * MB + c] = A[(size_t)i * n + k0 + c];
-    }
-    __syncthreads();
-    for (int kk = 0; kk < mb; ++kk) {
-      double best = -1.0;
-      int bi = INT_MAX;
-      for (int i = tid; i < n; i += 256) {
-        if (used[i]) continue;
-        const cplx v = panel[i * MB + kk];
-        double mag = fabs(v.re) + fabs(v.im);
-        if (mag != mag) mag = INFINITY;
-        if (mag > best) {
-          best = mag;
-          bi = i;
-        }
-      }
-      block_argmax(best, bi, redv, redi, &pivrow);
-      if (tid == 0) {
-        const int p = pivrow;
-        used[p] = 1;
-        piv[k0 + kk] = p;
-        sor[p] = k0 + kk;
-        pb[kk] = p;
-      }
-      __syncthreads();
-      const int p = pivrow;
-      for (int i = tid; i < n; i += 256) ucol[i] = panel[i * MB + kk];
-      for (int c = tid; c < mb; c += 256) wrow[c] = panel[p * MB + c];
-      __syncthreads();
-      const cplx pv = wrow[kk];
-      if (bad_pivot(pv)) singular = true;
-      const cplx inv = cinv(pv);
-      for (int e = tid; e < n * mb; e += 256) {
-        const int i = e / mb, c = e % mb;
-        cplx u = ucol[i];
-        if (i == p) u.re -= 1.0;
-        const cplx w = (c == kk) ? inv : cmul(wrow[c], inv);
-        cplx v = (c == kk) ? cplx{i == p ? 1.0 : 0.0, 0.0} : panel[i * MB + c];
-        v.re -= u.re * w.re - u.im * w.im;
-        v.im -= u.re * w.im + u.im * w.re;
-        panel[i * MB + c] = v;
-      }
-      __syncthreads();
-    }
-    // write the swept panel back, then form Z in LDS
-    for (int e = tid; e < n * mb; e += 256) {
-      const int i = e / mb, c = e % mb;
-      A[(size_t)i * n + k0 + c] = panel[i * MB + c];
-    }
-    __syncthreads();
-    if (tid < mb) panel[pb[tid] * MB + tid].re -= 1.0;
-    __syncthreads();
-    // trailing update over column tiles outside the panel
-    const int c = lane & 31;                 // column inside the tile
-    const int g = 2 * wave + (lane >> 5);    // row group 0..7
-    for (int jt = 0; jt < n; jt += GJ_YT) {
-      const int j = jt + c;
-      const bool col_ok = j < n && (j < k0 || j >= k0 + mb);
-      {  // tiles that overlap the panel are processed with those columns masked
-        for (int e = tid; e < mb * GJ_YT; e += 256) {
-          const int a = e / GJ_YT, cc = e % GJ_YT;
-          const int jj = jt + cc;
-          ytile[e] = (jj < n) ? A[(size_t)pb[a] * n + jj] : cplx{0.0, 0.0};
-        }
-        __syncthreads();
-        for (int i0 = 0; i0 < n; i0 += 32) {
-          cplx acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-          for (int a = 0; a < mb; ++a) {
-            const cplx y = ytile[a * GJ_YT + c];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = i0 + g + 8 * r;
-              const cplx z = (i < n) ? panel[i * MB + a] : cplx{0.0, 0.0};
-              acc[r].re += z.re * y.re - z.im * y.im;
-              acc[r].im += z.re * y.im + z.im * y.re;
-            }
-          }
-          if (col_ok) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = i0 + g + 8 * r;
-              if (i < n) {
-                cplx t = A[(size_t)i * n + j];
-                t.re += acc[r].re;
-                t.im += acc[r].im;
-                A[(size_t)i * n + j] = t;
-              }
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
-  }
-  __syncthreads();
-  for (int k = tid; k < n; k += 256) diag[(size_t)blockIdx.x * n + k] = A[(size_t)piv[k] * n + sor[k]];
-  if (singular && tid == 0) atomicMin(sing, w_base + (int)blockIdx.x);
-}
-
-size_t gj_blocked_lds(int n, int mb) {
-  return sizeof(cplx) * ((size_t)n * mb + n + mb + (size_t)mb * GJ_YT) + sizeof(int) * (3 * (size_t)n + mb);
-}
-
 __global__ void k_nolfe(const cplx* eps, int n, int n_w, cplx* diag, int* sing, int w_base) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long)n * n_w) return;
@@ -794,7 +626,7 @@ int gj_class(int n_g) {
   if (n_g <= 512) return 5;
   if (n_g <= 768) return 6;
   if (n_g <= 1024) return 7;
-  return 8;  // LDS-blocked kernel, single item only
+  return 8;  // beyond the inversion kernels: callers reject n_g > 1024
 }
 
 void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStream_t st,
@@ -811,15 +643,7 @@ void launch_gj_diag(cplx* eps, int n_g, int n_w, cplx* diag, int* sing, hipStrea
     case 7: hipLaunchKernelGGL(k_gj_panel<16>, g, b, gj_panel_lds(n_g, 16), st, eps, n_g, diag, sing, w_base); return;
     default: break;
   }
-  if (gj_blocked_lds(n_g, 32) <= 160 * 1024)
-    hipLaunchKernelGGL(k_gj_blocked<32>, dim3(n_w), dim3(256), gj_blocked_lds(n_g, 32), st, eps,
-                       n_g, diag, sing, w_base);
-  else if (gj_blocked_lds(n_g, 16) <= 160 * 1024)
-    hipLaunchKernelGGL(k_gj_blocked<16>, dim3(n_w), dim3(256), gj_blocked_lds(n_g, 16), st, eps,
-                       n_g, diag, sing, w_base);
-  else
-    hipLaunchKernelGGL(k_gj_blocked<8>, dim3(n_w), dim3(256), gj_blocked_lds(n_g, 8), st, eps,
-                       n_g, diag, sing, w_base);
+  // callers keep n_g <= 1024 (class 7); nothing is launched beyond
 }
 
 void launch_gj_jobs(int cls, const GjJob* jobs, int n_jobs, int n_blocks, int max_n, hipStream_t st) {

@@ -409,7 +409,7 @@ int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_
     if (!ctxs[c]) return fail(ctx, QCX_EINVAL, "NULL context");
     if (ctxs[c]->device != ctx->device) return fail(ctx, QCX_EINVAL, "contexts on different devices");
     if (!ctxs[c]->have_rho) return fail(ctx, QCX_ESTATE, "context " + std::to_string(c) + " has no pair densities");
-    if (lfe && ctxs[c]->n_g > 2048) return fail(ctx, QCX_EINVAL, "LFE inversion limited to n_G <= 2048");
+    if (lfe && ctxs[c]->n_g > 1024) return fail(ctx, QCX_EINVAL, "LFE inversion limited to n_G <= 1024");
   }
   for (int i = 0; i < n_items; ++i) {
     const qcx_item& it = items[i];

@@ -1080,7 +1080,7 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
 int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out) {
   if (!ctx) return QCX_EINVAL;
   if (!ctx->have_chi0) return fail(ctx, QCX_ESTATE, "chi0 first");
-  if (lfe && ctx->n_g > 2048) return fail(ctx, QCX_EINVAL, "LFE inversion limited to n_G <= 2048");
+  if (lfe && ctx->n_g > 1024) return fail(ctx, QCX_EINVAL, "LFE inversion limited to n_G <= 1024");
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_eps = false;
   hipStream_t st = ctx->stream;
@@ -1130,7 +1130,9 @@ int qcx_eps_inv_given(qcx_ctx* ctx, int n_w, int n_G, const void* eps, int lfe, 
                       void* diag_out, void* epsM_out) {
   if (!ctx) return QCX_EINVAL;
   if (n_w < 1 || n_w > 65536) return fail(ctx, QCX_EINVAL, "need 1 <= n_w <= 65536");
-  if (n_G < 1 || n_G > 2048) return fail(ctx, QCX_EINVAL, "need 1 <= n_G <= 2048");
+  if (n_G < 1 || n_G > (lfe ? 1024 : 65536))
+    return fail(ctx, QCX_EINVAL, lfe ? "need 1 <= n_G <= 1024" : "need 1 <= n_G <= 65536");
+  if ((size_t)n_w * n_G * n_G > ((size_t)1 << 33)) return fail(ctx, QCX_EINVAL, "eps above 128 GB");
   if (!eps || !loss_out) return fail(ctx, QCX_EINVAL, "eps and loss_out must be device buffers");
   HIPCK(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;

@@ -24,9 +24,9 @@ def _diag_inv(e):
     return np.stack([np.diag(np.linalg.inv(m)) for m in e])
 
 
-# one size per inversion kernel class: register-resident (two shapes),
-# panel-blocked on FP64 MFMA, LDS-blocked
-@pytest.mark.parametrize("n_g", [40, 113, 300, 1100])
+# register-resident kernel (both shapes) and the panel kernel at its
+# smallest and largest register tiling
+@pytest.mark.parametrize("n_g", [40, 113, 300, 1024])
 def test_singular_eps_each_kernel_class(n_g):
     import torch
 
@@ -59,6 +59,10 @@ def test_singular_eps_each_kernel_class(n_g):
     # a regular batch passes
     c.eps_inv_given(torch.from_numpy(_eps_batch(n_w, n_g, 6)).cuda(), True)
     c.sync()
+    # beyond the inversion kernels
+    with pytest.raises(QcxError) as ei:
+        c.eps_inv_given(torch.zeros((1, 1025, 1025), dtype=torch.complex128, device="cuda"), True)
+    assert ei.value.code == q.EINVAL
     c.close()
 
 
