@@ -219,6 +219,25 @@ int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out);
 int qcx_eps_inv_given(qcx_ctx* ctx, int n_w, int n_G, const void* eps, int lfe, double* loss_out,
                       void* diag_out, void* epsM_out);
 
+/* qcx_eps_inv_given without any device allocation, for callers that cannot
+ * allocate (code under graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and results as qcx_eps_inv_given (the
+ * same kernels, identical bits), except that the singular check is reported
+ * in status_out instead of through qcx_sync:
+ *   status_out  device int, set to INT_MAX, or to the lowest frequency index
+ *               with a zero or non-finite pivot (eps_GG for lfe = 0)
+ * The working copy of eps and, when diag_out is NULL, the diagonal live in a
+ * 64 MiB array the library holds on each GPU for the life of the process;
+ * frequencies run in chunks that fit it (for lfe = 1 a frequency takes
+ * 16 n_G^2 bytes, plus 16 n_G without diag_out).  Only kernels and
+ * device-to-device copies are enqueued on the context's stream: no
+ * allocation, no memset, no synchronisation.  All calls on one GPU share its
+ * array, so calls that overlap on one GPU (other streams or contexts) race.
+ * Errors: QCX_EINVAL (sizes as qcx_eps_inv_given; a frequency that does not
+ * fit 64 MiB; NULL eps, loss_out or status_out), QCX_EDEVICE. */
+int qcx_eps_inv_given_noalloc(qcx_ctx* ctx, int n_w, int n_G, const void* eps, int lfe,
+                              double* loss_out, void* diag_out, void* epsM_out, int* status_out);
+
 /* Cap the device memory the context's own buffers may hold (all of them but
  * a batch plan's, a surrogate's and a q-binning table's): a call that would
  * grow them beyond `bytes` returns QCX_ENOMEM and keeps the buffers it had;

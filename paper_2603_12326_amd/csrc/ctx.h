@@ -164,6 +164,9 @@ namespace qcx {
 
 // deferred state checks of device-resident inputs (qcx_runtime.hip)
 int check_deferred(qcx_ctx* ctx);
+// address of the no-allocation scratch array on `device`, looked up once per
+// device with that device current (qcx_noalloc.hip)
+hipError_t noalloc_init(int device);
 
 inline int fail(qcx_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;

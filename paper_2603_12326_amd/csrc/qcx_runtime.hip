@@ -153,6 +153,10 @@ int qcx_create(qcx_ctx** out, int device, void* hip_stream) {
     g_create_err = "hipSetDevice failed";
     return QCX_EDEVICE;
   }
+  if (const hipError_t es = qcx::noalloc_init(device); es != hipSuccess) {
+    g_create_err = std::string("scratch address: ") + hipGetErrorString(es);
+    return QCX_EDEVICE;
+  }
   qcx_ctx* c = new qcx_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);

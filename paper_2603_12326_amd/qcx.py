@@ -54,6 +54,7 @@ _SIGS = {
     "qcx_chi0": [_P, _I, _P, _D, _I, _I, _P],
     "qcx_eps_inv": [_P, _I, _P, _P],
     "qcx_eps_inv_given": [_P, _I, _I, _P, _I, _P, _P, _P],
+    "qcx_eps_inv_given_noalloc": [_P, _I, _I, _P, _I, _P, _P, _P, _P],
     "qcx_set_memory_limit": [_P, ctypes.c_size_t],
     "qcx_memory_used": [_P, ctypes.POINTER(ctypes.c_size_t)],
     "qcx_loss": [_P, _P, _I],
@@ -293,6 +294,18 @@ class Context:
             None if diag_out is None else _dev_ptr(diag_out, "c128", n_w * n_g, "diag_out"),
             None if epsM_out is None else _dev_ptr(epsM_out, "c128", n_w, "epsM_out")))
         return loss_out
+
+    def eps_inv_given_noalloc(self, eps, lfe: bool, loss_out, status_out, diag_out=None,
+                              epsM_out=None):
+        """qcx_eps_inv_given_noalloc: the caller passes every output (CUDA
+        tensors: loss_out float64 [n_w][n_G], status_out int32 [1])."""
+        n_w, n_g, _ = eps.shape
+        self._check(self.lib.qcx_eps_inv_given_noalloc(
+            self._h, n_w, n_g, _dev_ptr(eps, "c128", n_w * n_g * n_g, "eps"), 1 if lfe else 0,
+            _dev_ptr(loss_out, "f64", n_w * n_g, "loss_out"),
+            None if diag_out is None else _dev_ptr(diag_out, "c128", n_w * n_g, "diag_out"),
+            None if epsM_out is None else _dev_ptr(epsM_out, "c128", n_w, "epsM_out"),
+            _dev_ptr(status_out, "i32", 1, "status_out")))
 
     def set_memory_limit(self, nbytes: int):
         """Cap the context's own device buffers (0: no cap)."""
