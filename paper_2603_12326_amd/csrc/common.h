@@ -73,9 +73,19 @@ struct ShellTab {
   int n_sh;
   int n_ao;
 };
-void launch_cell_ft(const ShellTab& sh, const double* tvec, int n_t, const double* Q, int n_q,
-                    cplx* F, hipStream_t st);
-// optical limit (App. C): D[T][c][mu][nu] = <chi_mu| d/dr_c |chi_nu(. - T)>
+// F[g][T][mu][nu] (G-major); pair_order lists the shell pairs sa * n_sh + sb
+// sorted by (l_a, l_b)
+void launch_cell_ft(const ShellTab& sh, const int* pair_order, const double* tvec, int n_t,
+                    const double* Q, int n_q, cplx* F, hipStream_t st);
+// Pair densities in one pass (Bloch sum on FP64 MFMA, valence-first band
+// contraction, M in LDS only) into R[g][t] (stride ldt) for every k and the
+// n_g rows of F[g][T][mu][nu]; Cb holds the bra states.  rho_fused_fits:
+// N_AO <= 32, n_occ <= 4, at most 28 cells.
+bool rho_fused_fits(int n_ao, int n_occ, int n_t);
+void launch_rho_fused(const cplx* F, const cplx* ph, const cplx* Ck, const cplx* Cb, int n_ao,
+                      int n_b, int n_occ, int n_k, int n_t, int n_g, cplx* R, size_t ldt,
+                      hipStream_t st);
+// optical limit (App. C): D[c][T][mu][nu] = <chi_mu| d/dr_c |chi_nu(. - T)>
 // (real values in complex storage), and the G = 0 row R0[t] = -/+ i qhat.P / dt
 // from the band matrices Rp[c][t] (stride ldt) of the resonant / anti-resonant
 // transitions
@@ -85,7 +95,7 @@ void launch_optical_row(const cplx* Rp, size_t ldt, const double* dt, int n_t, c
 // e^{2 pi i kf.n_T} for kf = k_frac[k] + shift
 void launch_bloch_phase(const double* k_frac, int n_k, const double shift[3], const int* cells,
                         int n_t, cplx* ph, hipStream_t st);
-// M[k][g][e] = sum_T ph[k0+k][T] F[T][g][e], e = mu*n_ao+nu, for k in [0, nk)
+// M[k][g][e] = sum_T ph[k0+k][T] F[g][T][e], e = mu*n_ao+nu, for k in [0, nk)
 void launch_phase_sum(const cplx* F, const cplx* ph, int n_t, int n_q, int n_e, int k0, int nk,
                       cplx* M, hipStream_t st);
 // R64[g][t] (t fastest, stride ldt) for k in [k0, k0+nk) from M chunk, in the

@@ -41,7 +41,7 @@ struct qcx_ctx {
   int n_atoms = 0, n_sh = 0, n_ao = 0, lrange = 1, n_cells = 0;
   std::vector<int> sh_l, sh_off, cells;
   std::vector<double> sh_ex, sh_ctr, tvec;
-  DevBuf d_sh_l, d_sh_ex, d_sh_ctr, d_sh_off, d_cells, d_tvec;
+  DevBuf d_sh_l, d_sh_ex, d_sh_ctr, d_sh_off, d_cells, d_tvec, d_shp;
 
   // states
   bool have_states = false;
@@ -104,9 +104,8 @@ struct qcx_ctx {
   // transition energies copied to pinned host memory right after
   // qcx_set_states computes them, once the Kramers-Kronig route has been
   // used (its host-side sort then overlaps the pair densities on the device)
-  // rocBLAS handle for the plain products (the lattice Bloch sums of the pair
-  // densities, the Kramers-Kronig transform), created on first use and bound
-  // to the context's stream
+  // rocBLAS handle for the plain FP64 product of the Kramers-Kronig
+  // transform, created on first use and bound to the context's stream
   rocblas_handle blas = nullptr;
   double* h_dt = nullptr;
   size_t h_dt_cap = 0;
@@ -128,7 +127,7 @@ struct qcx_ctx {
   qcx::BatchPlan* plan = nullptr;
 
   std::vector<DevBuf*> buffers() {
-    return {&d_sh_l, &d_sh_ex, &d_sh_ctr, &d_sh_off, &d_cells, &d_tvec, &d_kf,
+    return {&d_sh_l, &d_sh_ex, &d_sh_ctr, &d_sh_off, &d_cells, &d_tvec, &d_shp, &d_kf,
                      &d_Ck,   &d_Ek,    &d_Ckq,    &d_Ekq,    &d_dt,    &d_ph,   &d_phq,
                      &d_S,    &d_F0,    &d_dev,    &d_flags,    &d_Q,      &d_vq,    &d_F,    &d_M,
                      &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_rows, &d_pairs64, &d_C, &d_C64,

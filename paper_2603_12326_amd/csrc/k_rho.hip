@@ -9,12 +9,14 @@
 // Lambda_t = d^t/dP^t e^{-p (x-P)^2}, whose Fourier transform is
 // sqrt(pi/p) e^{-Q^2/4p} (iQ)^t e^{iQP}.
 //
-// Per q: cell_ft (one thread per shell pair, cell and Q); the 27-cell Bloch
-// sum M(k;Q) (a complex product issued by the runtime on rocBLAS; phase_sum
-// here serves the overlaps S(k) and the generic case); then the band
-// contraction (one block per k and G tile; C(k), C(k+q) and M(k;Q) tiles
-// staged in LDS), valence side first (k_band_vf) or ket side first
-// (k_band_contract), whichever needs fewer multiply-adds.
+// Per q: cell_ft (one thread per shell pair, Q and cell, G-major output); then
+// the Bloch sum and the band
+// contraction in one pass (k_rho_fused.hip, M in LDS only) whenever the
+// basis and the valence bands fit its tiles.  Otherwise the 27-cell Bloch sum
+// M(k;Q) runs here (phase_sum, also used for the overlaps S(k)) in k chunks,
+// followed by the band contraction (one block per k and G tile; C(k), C(k+q)
+// and M(k;Q) tiles staged in LDS), valence side first (k_band_vf) or ket side
+// first (k_band_contract), whichever needs fewer multiply-adds.
 #include <algorithm>
 #include <utility>
 
@@ -195,17 +197,22 @@ __device__ void pair_block(double a, double b, const double* A, const double* B,
   }
 }
 
-// One thread per (shell pair, cell T, Q).  Threads of one shell pair are
-// consecutive, so a wave sees one (la, lb) combination.
-__global__ void __launch_bounds__(256) k_cell_ft(ShellTab sh, const double* tvec, int n_t,
-                                                 const double* Q, int n_q, cplx* F) {
+// One thread per (shell pair, Q, cell T), cells fastest: F[Q][T][mu][nu]
+// (G-major, the layout the Bloch sum reads per G).  The Hermite evaluation of
+// a d-d pair needs the whole register file, so the kernel runs one wave per
+// SIMD; staging whole slabs through LDS (one block per (Q, T)) left most
+// lanes idle at the barrier and took 4x longer, so every thread writes its
+// shell pair's block directly.
+__global__ void __launch_bounds__(256) k_cell_ft(ShellTab sh, const int* __restrict__ pair_order,
+                                                 const double* __restrict__ tvec, int n_t,
+                                                 const double* __restrict__ Q, int n_q,
+                                                 cplx* __restrict__ F) {
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long per_pair = (long)n_t * n_q;
-  const long total = per_pair * sh.n_sh * sh.n_sh;
-  if (tid >= total) return;
-  const int sp = (int)(tid / per_pair);
+  if (tid >= per_pair * sh.n_sh * sh.n_sh) return;
+  const int sp = pair_order[tid / per_pair];
   const int rem = (int)(tid % per_pair);
-  const int it = rem / n_q, g = rem % n_q;
+  const int g = rem / n_t, it = rem % n_t;
   const int sa = sp / sh.n_sh, sb = sp % sh.n_sh;
   const double a = sh.ex[sa], b = sh.ex[sb];
   double A[3], B[3], q[3];
@@ -216,9 +223,8 @@ __global__ void __launch_bounds__(256) k_cell_ft(ShellTab sh, const double* tvec
     q[x] = Q[3 * g + x];
   }
   const int n = sh.n_ao;
-  cplx* out = F + ((size_t)it * n_q + g) * n * n + (size_t)sh.off[sa] * n + sh.off[sb];
-  const int la = sh.l[sa], lb = sh.l[sb];
-  switch (la * 3 + lb) {
+  cplx* out = F + ((size_t)g * n_t + it) * n * n + (size_t)sh.off[sa] * n + sh.off[sb];
+  switch (sh.l[sa] * 3 + sh.l[sb]) {
     case 0: pair_block<0, 0>(a, b, A, B, q, out, n); break;
     case 1: pair_block<0, 1>(a, b, A, B, q, out, n); break;
     case 2: pair_block<0, 2>(a, b, A, B, q, out, n); break;
@@ -302,7 +308,8 @@ __device__ void pair_grad(double a, double b, const double* A, const double* B, 
   }
 }
 
-// One thread per (shell pair, cell): D[T][c][mu][nu], c = x, y, z.
+// One thread per (shell pair, cell): D[c][T][mu][nu], c = x, y, z (the
+// components take the place of the G list of F).
 __global__ void __launch_bounds__(256) k_grad_ft(ShellTab sh, const double* tvec, int n_t,
                                                  cplx* D) {
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -318,8 +325,8 @@ __global__ void __launch_bounds__(256) k_grad_ft(ShellTab sh, const double* tvec
     B[x] = sh.ctr[3 * sb + x] + tvec[3 * it + x];
   }
   const int n = sh.n_ao;
-  const size_t cs = (size_t)n * n;
-  double* out = reinterpret_cast<double*>(D + (size_t)it * 3 * cs + (size_t)sh.off[sa] * n + sh.off[sb]);
+  const size_t cs = (size_t)n * n * n_t;  // component stride: D[c][T][mu][nu]
+  double* out = reinterpret_cast<double*>(D + (size_t)it * n * n + (size_t)sh.off[sa] * n + sh.off[sb]);
   switch (sh.l[sa] * 3 + sh.l[sb]) {
     case 0: pair_grad<0, 0>(a, b, A, B, out, n, cs); break;
     case 1: pair_grad<0, 1>(a, b, A, B, out, n, cs); break;
@@ -365,7 +372,7 @@ __global__ void k_bloch_phase(const double* kf, int n_k, double s0, double s1, d
 // the chunk are broadcast from LDS.  Consecutive threads write consecutive e.
 template <int NT>
 __global__ void __launch_bounds__(256) k_phase_sum(const cplx* __restrict__ F,
-                                                   const cplx* __restrict__ ph, long n_el,
+                                                   const cplx* __restrict__ ph, long n_el, int n_e,
                                                    int k0, int nk, int kch,
                                                    cplx* __restrict__ M) {
   extern __shared__ cplx sph[];  // [kch][NT]
@@ -375,9 +382,11 @@ __global__ void __launch_bounds__(256) k_phase_sum(const cplx* __restrict__ F,
   for (int i = threadIdx.x; i < kn * NT; i += blockDim.x) sph[i] = ph[(size_t)(k0 + kb) * NT + i];
   __syncthreads();
   if (e >= n_el) return;
+  // element e of the G list is (G, mu nu) = (e / n_e, e % n_e); F is G-major
+  const cplx* Fe = F + (size_t)(e / n_e) * NT * n_e + e % n_e;
   cplx f[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) f[t] = F[(size_t)t * n_el + e];
+  for (int t = 0; t < NT; ++t) f[t] = Fe[(size_t)t * n_e];
   for (int kk = 0; kk < kn; ++kk) {
     double re = 0.0, im = 0.0;
 #pragma unroll
@@ -393,15 +402,16 @@ __global__ void __launch_bounds__(256) k_phase_sum(const cplx* __restrict__ F,
 // Generic lattice range: loop over cells from global memory.
 __global__ void __launch_bounds__(256) k_phase_sum_any(const cplx* __restrict__ F,
                                                        const cplx* __restrict__ ph, int n_t,
-                                                       long n_el, int k0, int nk,
+                                                       long n_el, int n_e, int k0, int nk,
                                                        cplx* __restrict__ M) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_el) return;
+  const cplx* Fe = F + (size_t)(e / n_e) * n_t * n_e + e % n_e;
   for (int kk = 0; kk < nk; ++kk) {
     double re = 0.0, im = 0.0;
     for (int t = 0; t < n_t; ++t) {
       const cplx p = ph[(size_t)(k0 + kk) * n_t + t];
-      const cplx f = F[(size_t)t * n_el + e];
+      const cplx f = Fe[(size_t)t * n_e];
       re += p.re * f.re - p.im * f.im;
       im += p.re * f.im + p.im * f.re;
     }
@@ -753,12 +763,11 @@ __global__ void __launch_bounds__(256) k_orth_check(const cplx* __restrict__ S,
 
 }  // namespace
 
-void launch_cell_ft(const ShellTab& sh, const double* tvec, int n_t, const double* Q, int n_q,
-                    cplx* F, hipStream_t st) {
+void launch_cell_ft(const ShellTab& sh, const int* pair_order, const double* tvec, int n_t,
+                    const double* Q, int n_q, cplx* F, hipStream_t st) {
   const long total = (long)sh.n_sh * sh.n_sh * n_t * n_q;
-  const int blk = 256;
-  hipLaunchKernelGGL(k_cell_ft, dim3((unsigned)((total + blk - 1) / blk)), dim3(blk), 0, st, sh,
-                     tvec, n_t, Q, n_q, F);
+  hipLaunchKernelGGL(k_cell_ft, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, sh,
+                     pair_order, tvec, n_t, Q, n_q, F);
 }
 
 void launch_grad_ft(const ShellTab& sh, const double* tvec, int n_t, cplx* D, hipStream_t st) {
@@ -792,12 +801,14 @@ void launch_phase_sum(const cplx* F, const cplx* ph, int n_t, int n_q, int n_e, 
     const dim3 grid((unsigned)etiles, (unsigned)((nk + kch - 1) / kch));
     const size_t lds = sizeof(cplx) * kch * n_t;
     if (n_t == 27)
-      hipLaunchKernelGGL(k_phase_sum<27>, grid, dim3(256), lds, st, F, ph, n_el, k0, nk, (int)kch, M);
+      hipLaunchKernelGGL(k_phase_sum<27>, grid, dim3(256), lds, st, F, ph, n_el, n_e, k0, nk,
+                         (int)kch, M);
     else
-      hipLaunchKernelGGL(k_phase_sum<1>, grid, dim3(256), lds, st, F, ph, n_el, k0, nk, (int)kch, M);
+      hipLaunchKernelGGL(k_phase_sum<1>, grid, dim3(256), lds, st, F, ph, n_el, n_e, k0, nk,
+                         (int)kch, M);
   } else {
     hipLaunchKernelGGL(k_phase_sum_any, dim3((unsigned)etiles), dim3(256), 0, st, F, ph, n_t, n_el,
-                       k0, nk, M);
+                       n_e, k0, nk, M);
   }
 }
 

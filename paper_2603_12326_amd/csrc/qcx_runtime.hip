@@ -85,9 +85,8 @@ constexpr double kKkSpectralBudget = 16.0 * (1 << 30);
 // each) in its FP32 accumulators; the splits are added in FP64
 constexpr int kMaxStepsPerSplit = 1024;
 constexpr size_t kLdsBytes = 160 * 1024;
-// Bloch sums M(k; G) of one pass of the pair densities (k points in chunks
-// within this budget): large enough that the Bloch-sum product has a wide
-// k dimension for long G lists
+// Bloch sums M(k; G) of one pass of the pair densities when they are not
+// fused with the band contraction (k points in chunks within this budget)
 constexpr size_t kMBudget = (size_t)8 << 30;
 
 struct Cand {
@@ -119,7 +118,8 @@ std::vector<Cand> bulk_candidates(const Chi0Geom& g, int af, int ks_min) {
 extern "C" {
 
 const char* qcx_build_info(void) {
-  return "libqcx gfx950: rho FP64 (Hermite FT, 27-cell Bloch sum), chi0 bulk FP32-MFMA "
+  return "libqcx gfx950: rho FP64 (Hermite FT, 27-cell Bloch sum on FP64 MFMA fused with the "
+         "band contraction), chi0 bulk FP32-MFMA "
          "32x32x2 / split-BF16-MFMA 32x32x16 (hi*hi+hi*lo+lo*hi), FP64 head/wings, FP64 "
          "Gauss-Jordan diag(eps^-1)";
 }
@@ -296,6 +296,15 @@ int qcx_set_cell_basis(qcx_ctx* ctx, const double lat[9], int n_atoms, const dou
   HIPCK(upload(ctx, ctx->d_sh_off, ctx->sh_off.data(), ctx->sh_off.size()));
   HIPCK(upload(ctx, ctx->d_cells, ctx->cells.data(), ctx->cells.size()));
   HIPCK(upload(ctx, ctx->d_tvec, ctx->tvec.data(), ctx->tvec.size()));
+  // shell pairs in the order the Fourier-integral kernel takes them: sorted
+  // by (l_a, l_b), so that a wave mostly evaluates one angular case
+  std::vector<int> order(n_shells * n_shells);
+  for (int i = 0; i < n_shells * n_shells; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return shell_l[x / n_shells] * 3 + shell_l[x % n_shells] <
+           shell_l[y / n_shells] * 3 + shell_l[y % n_shells];
+  });
+  HIPCK(upload(ctx, ctx->d_shp, order.data(), order.size()));
   ctx->have_basis = true;
   return QCX_OK;
 }
@@ -376,7 +385,8 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
   HIPCK(ctx->d_S.reserve(sizeof(cplx) * (size_t)n_k * nao * nao));
   HIPCK(ctx->d_dev.reserve(sizeof(double) * 2 * (size_t)n_k));
   ShellTab sh = shell_tab(ctx);
-  launch_cell_ft(sh, ctx->d_tvec.as<double>(), nT, ctx->d_Q.as<double>(), 1, ctx->d_F0.as<cplx>(), st);
+  launch_cell_ft(sh, ctx->d_shp.as<int>(), ctx->d_tvec.as<double>(), nT, ctx->d_Q.as<double>(), 1,
+                 ctx->d_F0.as<cplx>(), st);
   LAUNCHCK("cell_ft(S)");
   launch_bloch_phase(ctx->d_kf.as<double>(), n_k, zero3, ctx->d_cells.as<int>(), nT,
                      ctx->d_ph.as<cplx>(), st);
@@ -444,24 +454,6 @@ static int ensure_blas(qcx_ctx* ctx) {
   return QCX_OK;
 }
 
-// M[k][g][e] = sum_T ph[k0 + k][T] F[T][g][e] for k < nk: the lattice Bloch
-// sum is a plain complex product [nk x n_t] [n_t x n_q n_e] (column-major
-// view M^T = F^T ph^T), done by rocBLAS zgemm.
-static int phase_sum_blas(qcx_ctx* ctx, const cplx* F, const cplx* ph, int n_t, int n_q, int n_e,
-                          int k0, int nk, cplx* M) {
-  if (int rc = ensure_blas(ctx)) return rc;
-  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
-  const int n_el = n_q * n_e;
-  const rocblas_status bs =
-      rocblas_zgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, n_el, nk, n_t, &one,
-                    reinterpret_cast<const rocblas_double_complex*>(F), n_el,
-                    reinterpret_cast<const rocblas_double_complex*>(ph + (size_t)k0 * n_t), n_t,
-                    &zero, reinterpret_cast<rocblas_double_complex*>(M), n_el);
-  if (bs != rocblas_status_success)
-    return fail(ctx, QCX_EDEVICE, "rocblas_zgemm failed (status " + std::to_string((int)bs) + ")");
-  return QCX_OK;
-}
-
 // Pair densities R[G][t] for the G list (G = 0 first when need_g0).  With
 // qhat (the optical limit, App. C) the states must have q = 0; the k states
 // serve on both sides, and the G = 0 row is replaced by its q -> 0 limit
@@ -512,45 +504,49 @@ static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_
   ctx->ldt = roundup(ctx->n_t + 16, 256);  // zero tail: chunked readers may run past n_t
   HIPCK(ctx->d_R.reserve(sizeof(cplx) * ctx->ldt * n_G));
   HIPCK(hipMemsetAsync(ctx->d_R.p, 0, sizeof(cplx) * ctx->ldt * n_G, st));
+  const bool fused = rho_fused_fits(nao, ctx->n_occ, nT);
+  // Bloch sums M(k; G) of one pass of the fallback (k points in chunks)
   const size_t per_k = sizeof(cplx) * (size_t)n_G * nee;
-  int kc = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, kMBudget / per_k));
-  HIPCK(ctx->d_M.reserve(per_k * kc));
+  const int kc = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, kMBudget / per_k));
+  if (!fused) HIPCK(ctx->d_M.reserve(per_k * kc));
   int sp_rho;
   HIPCK(span_begin(ctx, 0, &sp_rho));
-  launch_cell_ft(shell_tab(ctx), ctx->d_tvec.as<double>(), nT, ctx->d_Q.as<double>(), n_G,
-                 ctx->d_F.as<cplx>(), st);
+  launch_cell_ft(shell_tab(ctx), ctx->d_shp.as<int>(), ctx->d_tvec.as<double>(), nT,
+                 ctx->d_Q.as<double>(), n_G, ctx->d_F.as<cplx>(), st);
   LAUNCHCK("cell_ft");
   // the bra states: k + q, or in the optical limit k itself
   const cplx* bra = optical ? ctx->d_Ck.as<cplx>() : ctx->d_Ckq.as<cplx>();
-  for (int k0 = 0; k0 < ctx->n_k; k0 += kc) {
-    const int nk = std::min(kc, ctx->n_k - k0);
-    if (int rc = phase_sum_blas(ctx, ctx->d_F.as<cplx>(), ctx->d_ph.as<cplx>(), nT, n_G, (int)nee,
-                                k0, nk, ctx->d_M.as<cplx>()))
-      return rc;
-    launch_band_contract(ctx->d_M.as<cplx>(), ctx->d_Ck.as<cplx>(), bra, nao, ctx->n_b,
-                         ctx->n_occ, ctx->n_k, k0, nk, n_G, ctx->d_R.as<cplx>(), ctx->ldt, st);
-    LAUNCHCK("phase_sum/band_contract");
-  }
+  // Bloch sum and band contraction of the rows of a G-major F: in one pass
+  // with M in LDS, or (large bases, many valence bands) through M chunks
+  auto densities = [&](const cplx* F, int rows, cplx* Rout) -> int {
+    if (fused) {
+      launch_rho_fused(F, ctx->d_ph.as<cplx>(), ctx->d_Ck.as<cplx>(), bra, nao, ctx->n_b,
+                       ctx->n_occ, ctx->n_k, nT, rows, Rout, ctx->ldt, st);
+      LAUNCHCK("rho_fused");
+      return QCX_OK;
+    }
+    const size_t per = sizeof(cplx) * (size_t)rows * nee;
+    const int kch = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, per_k * kc / per));
+    for (int k0 = 0; k0 < ctx->n_k; k0 += kch) {
+      const int nk = std::min(kch, ctx->n_k - k0);
+      launch_phase_sum(F, ctx->d_ph.as<cplx>(), nT, rows, (int)nee, k0, nk, ctx->d_M.as<cplx>(), st);
+      launch_band_contract(ctx->d_M.as<cplx>(), ctx->d_Ck.as<cplx>(), bra, nao, ctx->n_b,
+                           ctx->n_occ, ctx->n_k, k0, nk, rows, Rout, ctx->ldt, st);
+      LAUNCHCK("phase_sum/band_contract");
+    }
+    return QCX_OK;
+  };
+  if (int rc = densities(ctx->d_F.as<cplx>(), n_G, ctx->d_R.as<cplx>())) return rc;
   if (optical) {
-    // transitions at the same k; then P = C^H D(k) C for the three components
-    // (the band contraction with the gradient matrices in place of M) and the
-    // k.p row
+    // transitions at the same k; then P = C^H D(k) C for the three gradient
+    // components (their Bloch sums take the place of M) and the k.p row
     launch_transition_energies(ctx->d_Ek.as<double>(), ctx->d_Ek.as<double>(), ctx->n_k, ctx->n_b,
                                ctx->n_occ, ctx->d_dt.as<double>(), st);
     ctx->dt_valid = false;
     HIPCK(ctx->d_Fg.reserve(sizeof(cplx) * nT * 3 * nee));
     HIPCK(ctx->d_Rp.reserve(sizeof(cplx) * 3 * ctx->ldt));
     launch_grad_ft(shell_tab(ctx), ctx->d_tvec.as<double>(), nT, ctx->d_Fg.as<cplx>(), st);
-    const int kg = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, per_k * kc / (3 * sizeof(cplx) * nee)));
-    for (int k0 = 0; k0 < ctx->n_k; k0 += kg) {
-      const int nk = std::min(kg, ctx->n_k - k0);
-      if (int rc = phase_sum_blas(ctx, ctx->d_Fg.as<cplx>(), ctx->d_ph.as<cplx>(), nT, 3, (int)nee,
-                                  k0, nk, ctx->d_M.as<cplx>()))
-        return rc;
-      launch_band_contract(ctx->d_M.as<cplx>(), ctx->d_Ck.as<cplx>(), ctx->d_Ck.as<cplx>(), nao,
-                           ctx->n_b, ctx->n_occ, ctx->n_k, k0, nk, 3, ctx->d_Rp.as<cplx>(), ctx->ldt,
-                           st);
-    }
+    if (int rc = densities(ctx->d_Fg.as<cplx>(), 3, ctx->d_Rp.as<cplx>())) return rc;
     launch_optical_row(ctx->d_Rp.as<cplx>(), ctx->ldt, ctx->d_dt.as<double>(), ctx->n_t, qh,
                        ctx->d_R.as<cplx>(), st);
     LAUNCHCK("optical limit");

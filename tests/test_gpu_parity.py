@@ -50,6 +50,24 @@ def test_rho_fp64(ctx, maker):
     assert err < 1e-10
 
 
+@pytest.mark.parametrize("maker", [make_tiny, make_config1])
+def test_rho_independent_of_stale_lds(ctx, maker):
+    """LDS keeps whatever the previous kernel left there.  A NaN-filled FP64
+    product (its tiles pass through LDS) runs right before the pair densities,
+    which must not read any LDS they did not write (0 * NaN = NaN)."""
+    import torch
+
+    wl = maker()
+    ref = _oracle(wl)
+    a = torch.full((2048, 2048), float("nan"), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        b = a @ a
+        out = gpu_solve(ctx, wl, precision="fp64", want_rho=True)
+        assert np.all(np.isfinite(out["rho"])) and np.all(np.isfinite(out["loss"]))
+        assert relmax(out["rho"], ref["R"]) < 1e-10
+    del a, b
+
+
 def test_rho_ket_first_order(ctx):
     """Twelve valence bands of twenty (2 n_occ >= n_b): the library contracts
     the ket side with every band first (the other workloads take the
