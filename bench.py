@@ -50,7 +50,7 @@ HARTREE_EV = 27.211386245988
 # HBM traffic of the bulk kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (one pass each) and scaled by the same counters on a copy of known size;
 # valid only while the kernel source hashes to the recorded value.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_bf16_config2_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_bf16_si_ng113_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_12326_amd", "csrc", f) for f in ("k_chi0.hip",)]
 
 
@@ -229,9 +229,9 @@ def main_batch(args):
     import torch
 
     from paper_2603_12326_amd import Context, batch_sync, build_info, run_batch
-    from synth import make_config3_items
+    from synth import make_mixed_batch_items
 
-    items = make_config3_items()
+    items = make_mixed_batch_items()
     log(f"generating and uploading {len(items)} items")
     ctxs, data = [], []
     for wl in items:
@@ -378,10 +378,10 @@ def main_composite(args):
 
     from paper_2603_12326_amd import Context, build_info
     from paper_2603_12326_amd import composite as C
-    from synth import make_config2
+    from synth import make_si_ng113
 
     Q_MAX, Q_LFE = 25.0, 6.0
-    wl = make_config2(n_q=1)
+    wl = make_si_ng113(n_q=1)
     qs, kf = upload_workload(wl, 1, torch)
     d = qs[0]
     G = composite_g(wl.cell.lat, d["q"], Q_MAX)
@@ -506,10 +506,10 @@ def main_kk(args):
     import torch
 
     from paper_2603_12326_amd import Context, build_info
-    from synth import make_config2
+    from synth import make_si_ng113
 
     BIN = args.kk_bin
-    wl = make_config2(n_q=args.n_q)
+    wl = make_si_ng113(n_q=args.n_q)
     log(f"generating and uploading {args.n_q} q points")
     states = [wl.states(iq) for iq in range(args.n_q)]
     qs, kf = upload_workload(wl, args.n_q, torch)
@@ -633,11 +633,11 @@ def main_rates(args):
     from paper_2603_12326_amd import Context, QBins, build_info
     from paper_2603_12326_amd import composite as C
     from paper_2603_12326_amd import rates as RT
-    from synth import make_config2
+    from synth import make_si_ng113
 
     Q_MAX, Q_LFE, DQ, NT, NP = 25.0, 6.0, 0.02, 9, 16
     M_CHI, SIG, RHO_T = 1e9, 1e-39, 2.33
-    wl = make_config2(n_q=1)
+    wl = make_si_ng113(n_q=1)
     qs, kf = upload_workload(wl, 1, torch)
     d = qs[0]
     G = composite_g(wl.cell.lat, d["q"], Q_MAX)
@@ -749,9 +749,9 @@ def main_optical(args):
     import torch
 
     from paper_2603_12326_amd import Context, build_info
-    from synth import make_config2
+    from synth import make_si_ng113
 
-    wl = make_config2(n_q=1)
+    wl = make_si_ng113(n_q=1)
     st0 = wl.states(0)
     dev = "cuda"
     C = torch.from_numpy(np.ascontiguousarray(st0.C_k)).to(dev)
@@ -833,15 +833,15 @@ def main_optical(args):
 
 
 def main_allelectron(args):
-    """Config 4: the all-electron Si-like cell at N_G = 749 (one q, 12^3 k,
+    """The all-electron Si-like cell at N_G = 749 (one q, 12^3 k,
     870,912 transitions, 1000 frequencies over 0-100 eV), split-BF16 bulk,
     FP64 head/wings and FP64 inversion of 749 x 749 eps per frequency."""
     import torch
 
     from paper_2603_12326_amd import Context, build_info
-    from synth import make_config4
+    from synth import make_all_electron
 
-    wl = make_config4()
+    wl = make_all_electron()
     log("all-electron: generating and uploading the states")
     qs, kf = upload_workload(wl, 1, torch)
     d = qs[0]
@@ -933,11 +933,11 @@ def main():
     import torch
 
     from paper_2603_12326_amd import Context, build_info
-    from synth import make_config2
+    from synth import make_si_ng113
 
     if args.calib_copy:
         calib_copy(torch)
-    wl = make_config2(n_q=args.n_q)
+    wl = make_si_ng113(n_q=args.n_q)
     log(f"generating and uploading {args.n_q} q points")
     qs, kf = upload_workload(wl, args.n_q, torch)
     n_g, n_w = len(wl.G_int), len(wl.w_eV)

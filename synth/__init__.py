@@ -12,10 +12,10 @@ from .generator import (  # noqa: F401
     Basis,
     Workload,
     QStates,
-    make_config1,
-    make_config2,
-    make_config3_items,
-    make_config4,
+    make_smallest,
+    make_si_ng113,
+    make_mixed_batch_items,
+    make_all_electron,
     make_tiny,
     fcc_cell,
     reciprocal_rows,

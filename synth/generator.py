@@ -385,7 +385,7 @@ def draw_states(wl: Workload, iq: int) -> QStates:
 # --------------------------------------------------------------------------
 # the workloads
 # --------------------------------------------------------------------------
-def make_config1(smooth: bool = True) -> Workload:
+def make_smallest(smooth: bool = True) -> Workload:
     """Smallest FP64 instance: 10 GTOs, 4+6 bands, 4^3 k, one q, 27 G, 128 w."""
     seed = BASE_SEED + 1
     cell = fcc_cell(10.26, "Si-like")
@@ -402,7 +402,7 @@ def make_config1(smooth: bool = True) -> Workload:
 SI_SPEC = [(0, 3, 0.1, 50.0), (1, 2, 0.1, 50.0), (2, 1, 0.1, 50.0)]
 
 
-def make_config2(n_q: int = 10, n_w: int = 400, kgrid: int = 8, smooth: bool = True) -> Workload:
+def make_si_ng113(n_q: int = 10, n_w: int = 400, kgrid: int = 8, smooth: bool = True) -> Workload:
     """Si-scale precision study: 28 AO, 4+16 bands, 8^3 k, 10 q on [100], N_G=113, 400 w."""
     seed = BASE_SEED + 2
     cell = fcc_cell(10.26, "Si-like")
@@ -417,23 +417,23 @@ def make_config2(n_q: int = 10, n_w: int = 400, kgrid: int = 8, smooth: bool = T
         energy_ranges=[(4, -12.0, 0.0), (16, 1.1, 15.0)], smooth=smooth)
 
 
-CONFIG3_CELLS = [
+MIXED_CELLS = [
     ("diamond-like", 6.74, ("C", "C")),
     ("Si-like", 10.26, ("Si", "Si")),
     ("Ge-like", 10.69, ("Ge", "Ge")),
     ("GaAs-like", 10.68, ("Ga", "As")),
     ("SiC-like", 8.24, ("Si", "C")),
 ]
-CONFIG3_NG = [59, 113, 181, 259]
+MIXED_NG = [59, 113, 181, 259]
 
 
-def make_config3_items(n_items: int = 20, kgrid_override: Optional[int] = None) -> List[Workload]:
+def make_mixed_batch_items(n_items: int = 20, kgrid_override: Optional[int] = None) -> List[Workload]:
     """Mixed batch: item i uses cell i mod 5, N_G = [59,113,181,259][i div 5],
     an n^3 k grid with n = 6 + (3i mod 5), q = (0.1+0.04 i) 2pi/a along x,
     n_w = 10 i + 5 frequencies over 0-60 eV, eta = 0.1 eV."""
     items = []
     for i in range(n_items):
-        name, a, species = CONFIG3_CELLS[i % 5]
+        name, a, species = MIXED_CELLS[i % 5]
         seed = BASE_SEED + 300 + i
         cell = fcc_cell(a, name, species)
         rng = np.random.default_rng(np.random.SeedSequence(BASE_SEED + 3 + 1000 * (i % 5)).spawn(3)[2])
@@ -441,14 +441,14 @@ def make_config3_items(n_items: int = 20, kgrid_override: Optional[int] = None) 
         n = kgrid_override if kgrid_override else 6 + (3 * i) % 5
         items.append(Workload(
             name=f"c3_item{i}_{name}", cell=cell, basis=basis, lattice_range=1, n_occ=4, n_bands=10,
-            k_frac=gamma_grid(n), G_int=g_shells(cell.lat, CONFIG3_NG[(i // 5) % 4]),
+            k_frac=gamma_grid(n), G_int=g_shells(cell.lat, MIXED_NG[(i // 5) % 4]),
             w_eV=np.linspace(0.0, 60.0, 10 * i + 5), eta_eV=0.1,
             q_list=[np.array([(0.1 + 0.04 * i) * 2 * math.pi / a, 0.0, 0.0])], seed=seed,
             energy_ranges=[(4, -12.0, 0.0), (6, 1.1, 15.0)]))
     return items
 
 
-def make_config4(n_w: int = 1000, kgrid: int = 12, q_list=None) -> Workload:
+def make_all_electron(n_w: int = 1000, kgrid: int = 12, q_list=None) -> Workload:
     """High-momentum all-electron case: 6s+5p+1d per atom (26 AO), 5 core + 4 valence
     + 28 conduction bands, 12^3 k, N_G = 749, 1000 w over 0-100 eV."""
     seed = BASE_SEED + 4

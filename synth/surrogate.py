@@ -17,7 +17,7 @@ import math
 
 import numpy as np
 
-from .generator import (BASE_SEED, CONFIG3_CELLS, Workload, _basis_small, fcc_cell, gamma_grid,
+from .generator import (BASE_SEED, MIXED_CELLS, Workload, _basis_small, fcc_cell, gamma_grid,
                         g_shells, reciprocal_rows)
 
 SURR_SEED = BASE_SEED + 5
@@ -25,11 +25,11 @@ N_G = 259                 # G set whose largest |q+G| bounds the query domain
 W_MAX_EV = 60.0
 
 
-def make_config5(q_list, kgrid: int = 9, n_g: int = N_G, n_w: int = 16, eta_eV: float = 0.1) -> Workload:
+def make_surrogate_workload(q_list, kgrid: int = 9, n_g: int = N_G, n_w: int = 16, eta_eV: float = 0.1) -> Workload:
     """Si-like cell of the mixed batch (a = 10.26 bohr, two s and one p shell
     per atom), 4 valence + 6 conduction smooth bands, n^3 k grid, closed G
     shells; q_list gives the momenta whose states are drawn."""
-    name, a, species = CONFIG3_CELLS[1]
+    name, a, species = MIXED_CELLS[1]
     cell = fcc_cell(a, name, species)
     rng = np.random.default_rng(np.random.SeedSequence(BASE_SEED + 3 + 1000 * 1).spawn(3)[2])
     basis = _basis_small(rng, 2, species)

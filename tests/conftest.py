@@ -14,15 +14,15 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def cfg1():
-    from synth import make_config1
-    return make_config1()
+def small_wl():
+    from synth import make_smallest
+    return make_smallest()
 
 
 @pytest.fixture(scope="session")
-def cfg1_oracle(cfg1):
+def small_oracle(small_wl):
     from oracle import rpa
-    return rpa.solve_workload(cfg1, 0, return_all=True)
+    return rpa.solve_workload(small_wl, 0, return_all=True)
 
 
 @pytest.fixture(scope="session")

@@ -21,9 +21,9 @@ def test_bulk_flop_count_of_the_benchmark():
     """2 (multiply-add) x 2 n_w rows x 2 (Re, Im) x (upper-triangle pairs
     without the G = 0 row) x N_T, for N_G = 113, 400 w, 8^3 k, 4 + 16 bands."""
     import bench
-    from synth import make_config2
+    from synth import make_si_ng113
 
-    wl = make_config2(n_q=1)
+    wl = make_si_ng113(n_q=1)
     pairs = 113 * 114 // 2 - 113
     assert pairs == 6328 and wl.n_t == 2 * 4 * 16 * 512
     assert bench.bulk_flops_per_launch(wl) == pytest.approx(2.0 * 800 * 2 * pairs * 65536)

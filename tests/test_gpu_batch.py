@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 from oracle import rpa
-from synth import make_config3_items
+from synth import make_mixed_batch_items
 from tests.gpu_helpers import normwise, set_inputs
 
 pytestmark = pytest.mark.gpu
@@ -60,7 +60,7 @@ def _single(ctx, wl, precision, lfe=True):
 
 @pytest.fixture(scope="module")
 def full_batch():
-    items = make_config3_items()
+    items = make_mixed_batch_items()
     ctxs = _contexts(items)
     yield items, ctxs
     for c in ctxs:
@@ -143,7 +143,7 @@ def test_batch_plan_tuned_and_fixed(full_batch):
 def test_batch_against_oracle():
     """Items 0, 6, 12, 19 (N_G 59, 113, 181, 259; n_w 5..195) on a 2^3 k grid."""
     pick = [0, 6, 12, 19]
-    allv = make_config3_items(kgrid_override=2)
+    allv = make_mixed_batch_items(kgrid_override=2)
     items = [allv[i] for i in pick]
     ctxs = _contexts(items)
     refs = []

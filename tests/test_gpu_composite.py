@@ -43,24 +43,24 @@ def _g_list(lat, n):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split_bf16"])
-def test_loss_diag_config1(ctx, cfg1, cfg1_oracle, prec):
-    set_inputs(ctx, cfg1)
-    L = ctx.loss_diag(cfg1.G_int, cfg1.w_eV, cfg1.eta_eV, prec).cpu().numpy()
-    ref = rpa.loss_nolfe(cfg1_oracle["eps"])
+def test_loss_diag_smallest(ctx, small_wl, small_oracle, prec):
+    set_inputs(ctx, small_wl)
+    L = ctx.loss_diag(small_wl.G_int, small_wl.w_eV, small_wl.eta_eV, prec).cpu().numpy()
+    ref = rpa.loss_nolfe(small_oracle["eps"])
     e = normwise(L, ref)
     print(prec, "loss_diag normwise", e)
     assert e < TOL[prec]
 
 
-def test_loss_diag_many_g(ctx, cfg1):
-    st = set_inputs(ctx, cfg1)
-    G = _g_list(cfg1.cell.lat, 4500)
-    w = cfg1.w_eV[::8]
-    L64 = ctx.loss_diag(G, w, cfg1.eta_eV, "fp64").cpu().numpy()
-    Lsp = ctx.loss_diag(G, w, cfg1.eta_eV, "split_bf16").cpu().numpy()
+def test_loss_diag_many_g(ctx, small_wl):
+    st = set_inputs(ctx, small_wl)
+    G = _g_list(small_wl.cell.lat, 4500)
+    w = small_wl.w_eV[::8]
+    L64 = ctx.loss_diag(G, w, small_wl.eta_eV, "fp64").cpu().numpy()
+    Lsp = ctx.loss_diag(G, w, small_wl.eta_eV, "split_bf16").cpu().numpy()
     pick = np.array([0, 1, 100, 2047, 4094, 4095, 4096, 4097, 4300, 4498, 4499])
-    ref = rpa.loss_diag(cfg1.cell, cfg1.basis, cfg1.lattice_range, cfg1.k_frac, cfg1.n_occ,
-                        G[pick], st, w, cfg1.eta_eV)
+    ref = rpa.loss_diag(small_wl.cell, small_wl.basis, small_wl.lattice_range, small_wl.k_frac, small_wl.n_occ,
+                        G[pick], st, w, small_wl.eta_eV)
     e64, esp = normwise(L64[:, pick], ref), normwise(Lsp[:, pick], ref)
     print("4500 G: fp64", e64, "split", esp)
     assert e64 < 1e-10 and esp < 1e-4
@@ -68,40 +68,40 @@ def test_loss_diag_many_g(ctx, cfg1):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
-def test_composite_matches_oracle(ctx, cfg1, prec):
+def test_composite_matches_oracle(ctx, small_wl, prec):
     from paper_2603_12326_amd import composite as C
 
-    st = set_inputs(ctx, cfg1)
-    G = _g_list(cfg1.cell.lat, 300)
-    Q = rpa.q_plus_g(cfg1.cell.lat, st.q_cart, G)
+    st = set_inputs(ctx, small_wl)
+    G = _g_list(small_wl.cell.lat, 300)
+    Q = rpa.q_plus_g(small_wl.cell.lat, st.q_cart, G)
     qn = np.sort(np.linalg.norm(Q, axis=1))
     q_lfe = 0.5 * (qn[26] + qn[27])                   # 27 innermost G in the LFE block
-    w = cfg1.w_eV[::4]
-    parts = C.composite_loss(ctx, cfg1.cell.lat, st.q_cart, G, w, cfg1.eta_eV, q_lfe, prec)
+    w = small_wl.w_eV[::4]
+    parts = C.composite_loss(ctx, small_wl.cell.lat, st.q_cart, G, w, small_wl.eta_eV, q_lfe, prec)
     assert len(parts[0]) == 27
     got = C.assemble(len(G), *parts)
-    ref = rpa.loss_composite(cfg1.cell, cfg1.basis, cfg1.lattice_range, cfg1.k_frac, cfg1.n_occ, G,
-                             st, w, cfg1.eta_eV, q_lfe)
+    ref = rpa.loss_composite(small_wl.cell, small_wl.basis, small_wl.lattice_range, small_wl.k_frac, small_wl.n_occ, G,
+                             st, w, small_wl.eta_eV, q_lfe)
     e = normwise(got, ref)
     print(prec, "composite normwise", e)
     assert e < TOL[prec]
 
 
-def test_loss_diag_errors(cfg1):
+def test_loss_diag_errors(small_wl):
     from paper_2603_12326_amd import Context, QcxError
     from paper_2603_12326_amd import qcx as q
 
     c = Context(0)
-    b = cfg1.basis
-    c.set_cell_basis(cfg1.cell.lat, cfg1.cell.xyz, b.shell_atom, b.shell_l, b.shell_exp, 1, 1)
+    b = small_wl.basis
+    c.set_cell_basis(small_wl.cell.lat, small_wl.cell.xyz, b.shell_atom, b.shell_l, b.shell_exp, 1, 1)
     with pytest.raises(QcxError) as e:
-        c.loss_diag(cfg1.G_int, cfg1.w_eV, 0.1)
+        c.loss_diag(small_wl.G_int, small_wl.w_eV, 0.1)
     assert e.value.code == q.ESTATE
-    set_inputs(c, cfg1)
+    set_inputs(c, small_wl)
     with pytest.raises(QcxError) as e:
-        c.loss_diag(cfg1.G_int, [np.nan], 0.1)
+        c.loss_diag(small_wl.G_int, [np.nan], 0.1)
     assert e.value.code == q.EINVAL
     with pytest.raises(QcxError) as e:
-        c.loss_diag(cfg1.G_int, cfg1.w_eV, -1.0)
+        c.loss_diag(small_wl.G_int, small_wl.w_eV, -1.0)
     assert e.value.code == q.EINVAL
     c.close()

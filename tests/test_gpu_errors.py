@@ -7,7 +7,7 @@ qcx_batch_sync), with contexts on different streams."""
 import numpy as np
 import pytest
 
-from synth import make_config3_items
+from synth import make_mixed_batch_items
 from tests.gpu_helpers import normwise, set_inputs
 
 pytestmark = pytest.mark.gpu
@@ -84,30 +84,30 @@ def test_singular_nolfe_diagonal():
     c.close()
 
 
-def test_memory_limit_enomem(cfg1):
+def test_memory_limit_enomem(small_wl):
     from oracle import rpa
     from paper_2603_12326_amd import Context, QcxError
     from paper_2603_12326_amd import qcx as q
 
     c = Context(0)
-    set_inputs(c, cfg1)
+    set_inputs(c, small_wl)
     used = c.memory_used()
     assert used > 0
     c.set_memory_limit(used + 64 * 1024)
     with pytest.raises(QcxError) as ei:
-        c.pair_density(cfg1.G_int)
+        c.pair_density(small_wl.G_int)
     assert ei.value.code == q.ENOMEM
     assert c.memory_used() <= used + 64 * 1024
     c.set_memory_limit(0)
-    c.pair_density(cfg1.G_int)
-    c.chi0(cfg1.w_eV, cfg1.eta_eV, "fp64")
+    c.pair_density(small_wl.G_int)
+    c.chi0(small_wl.w_eV, small_wl.eta_eV, "fp64")
     c.eps_inv()
-    ref = rpa.solve_workload(cfg1, 0)
+    ref = rpa.solve_workload(small_wl, 0)
     assert normwise(c.loss(), ref) < 1e-10
     c.close()
 
 
-def test_capture_rejected(cfg1):
+def test_capture_rejected(small_wl):
     """A call that stages host data, issued while its stream is capturing,
     returns QCX_EINVAL and records nothing."""
     import torch
@@ -117,16 +117,16 @@ def test_capture_rejected(cfg1):
 
     s = torch.cuda.Stream()
     c = Context(0, stream=s.cuda_stream)
-    set_inputs(c, cfg1)
+    set_inputs(c, small_wl)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
-    st = cfg1.states(0)
+    st = small_wl.states(0)
     codes = []
     with torch.cuda.stream(s):
         g.capture_begin()
         try:
-            for call in (lambda: c.pair_density(cfg1.G_int),
-                         lambda: c.set_states(st.q_cart, cfg1.k_frac, cfg1.n_occ, st.C_k, st.E_k,
+            for call in (lambda: c.pair_density(small_wl.G_int),
+                         lambda: c.set_states(st.q_cart, small_wl.k_frac, small_wl.n_occ, st.C_k, st.E_k,
                                               st.C_kq, st.E_kq)):
                 try:
                     call()
@@ -138,7 +138,7 @@ def test_capture_rejected(cfg1):
     assert [x[0] for x in codes] == [q.EINVAL, q.EINVAL], codes
     assert all("captured" in x[1] for x in codes), codes
     # the context is unaffected
-    c.pair_density(cfg1.G_int)
+    c.pair_density(small_wl.G_int)
     c.close()
 
 
@@ -152,7 +152,7 @@ def test_batch_other_streams_and_deferred_checks():
     from paper_2603_12326_amd import Context, QcxError, batch_sync, run_batch
     from paper_2603_12326_amd import qcx as q
 
-    items = make_config3_items()[:3]
+    items = make_mixed_batch_items()[:3]
     streams = [torch.cuda.Stream() for _ in items]
 
     def build(per_stream):

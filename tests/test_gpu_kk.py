@@ -62,24 +62,24 @@ def _oracle_kk(wl, w, eta, b, R=None):
 
 
 @pytest.mark.parametrize("eta", [0.2, 0.0])
-def test_kk_matches_oracle(ctx, cfg1, cfg1_oracle, eta):
-    w = cfg1.w_eV[::2]
-    chi, L = _gpu_kk(ctx, cfg1, w, eta, 0.05)
-    cref, Lref = _oracle_kk(cfg1, w, eta, 0.05, cfg1_oracle["R"])
+def test_kk_matches_oracle(ctx, small_wl, small_oracle, eta):
+    w = small_wl.w_eV[::2]
+    chi, L = _gpu_kk(ctx, small_wl, w, eta, 0.05)
+    cref, Lref = _oracle_kk(small_wl, w, eta, 0.05, small_oracle["R"])
     ec, el = relmax(chi, cref), normwise(L, Lref)
     print("eta", eta, "chi0", ec, "loss", el)
     assert ec < TOL_CHI and el < TOL_LOSS
 
 
-def test_kk_multi_tile(ctx, cfg1):
+def test_kk_multi_tile(ctx, small_wl):
     """137 G: a 3 x 3 grid of 64 x 64 tiles of the (G, G') plane (diagonal and
     off-diagonal tiles, a last tile with 9 real G) against the oracle."""
     import dataclasses
 
     from synth.generator import g_shells
 
-    wl = dataclasses.replace(cfg1, G_int=g_shells(cfg1.cell.lat, 137))
-    w = cfg1.w_eV[::8]
+    wl = dataclasses.replace(small_wl, G_int=g_shells(small_wl.cell.lat, 137))
+    w = small_wl.w_eV[::8]
     chi, L = _gpu_kk(ctx, wl, w, 0.2, 0.05)
     cref, Lref = _oracle_kk(wl, w, 0.2, 0.05)
     ec, el = relmax(chi, cref), normwise(L, Lref)
@@ -87,11 +87,11 @@ def test_kk_multi_tile(ctx, cfg1):
     assert ec < TOL_CHI and el < TOL_LOSS
 
 
-def test_kk_one_wide_bin(ctx, cfg1, cfg1_oracle):
+def test_kk_one_wide_bin(ctx, small_wl, small_oracle):
     """bin_eV above every transition energy: one or two intervals per side."""
-    w = cfg1.w_eV[::8]
-    chi, L = _gpu_kk(ctx, cfg1, w, 0.2, 60.0)
-    cref, Lref = _oracle_kk(cfg1, w, 0.2, 60.0, cfg1_oracle["R"])
+    w = small_wl.w_eV[::8]
+    chi, L = _gpu_kk(ctx, small_wl, w, 0.2, 60.0)
+    cref, Lref = _oracle_kk(small_wl, w, 0.2, 60.0, small_oracle["R"])
     assert relmax(chi, cref) < TOL_CHI and normwise(L, Lref) < TOL_LOSS
 
 
@@ -104,49 +104,49 @@ def test_kk_tiny_ragged(ctx, tiny):
     assert ec < TOL_CHI and el < TOL_LOSS
 
 
-def test_kk_repeatable(ctx, cfg1):
+def test_kk_repeatable(ctx, small_wl):
     """No atomics: two calls give the same bits."""
-    w = cfg1.w_eV[::4]
-    a, La = _gpu_kk(ctx, cfg1, w, 0.1, 0.03)
-    b, Lb = _gpu_kk(ctx, cfg1, w, 0.1, 0.03)
+    w = small_wl.w_eV[::4]
+    a, La = _gpu_kk(ctx, small_wl, w, 0.1, 0.03)
+    b, Lb = _gpu_kk(ctx, small_wl, w, 0.1, 0.03)
     assert np.array_equal(a, b) and np.array_equal(La, Lb)
 
 
-def test_kk_converges_to_direct_on_gpu(ctx, cfg1):
+def test_kk_converges_to_direct_on_gpu(ctx, small_wl):
     """Halving the bin divides the difference to the direct FP64 route
     (qcx_chi0 at the same eta) by about four."""
     import torch
 
-    w = cfg1.w_eV[::8]
-    n = len(cfg1.G_int)
-    set_inputs(ctx, cfg1)
-    ctx.pair_density(cfg1.G_int)
+    w = small_wl.w_eV[::8]
+    n = len(small_wl.G_int)
+    set_inputs(ctx, small_wl)
+    ctx.pair_density(small_wl.G_int)
     ref = torch.empty((len(w), n, n), dtype=torch.complex128, device="cuda")
-    ctx.chi0(w, cfg1.eta_eV, "fp64", True, ref)
+    ctx.chi0(w, small_wl.eta_eV, "fp64", True, ref)
     ref = ref.cpu().numpy()
     errs = []
     for b in (0.08, 0.04, 0.02):
         chi = torch.empty((len(w), n, n), dtype=torch.complex128, device="cuda")
-        ctx.chi0_kk(w, cfg1.eta_eV, b, chi)
+        ctx.chi0_kk(w, small_wl.eta_eV, b, chi)
         errs.append(relmax(chi.cpu().numpy(), ref))
     print("kk vs direct", errs)
     assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0, errs
 
 
-def test_kk_errors(ctx, cfg1):
+def test_kk_errors(ctx, small_wl):
     from paper_2603_12326_amd import Context, QcxError
     from paper_2603_12326_amd import qcx as q
 
-    set_inputs(ctx, cfg1)
-    ctx.pair_density(cfg1.G_int)
+    set_inputs(ctx, small_wl)
+    ctx.pair_density(small_wl.G_int)
     for eta, b in ((0.2, 0.0), (-0.1, 0.05), (0.2, float("nan")), (0.2, 1e-9)):
         with pytest.raises(QcxError) as e:
-            ctx.chi0_kk(cfg1.w_eV, eta, b)
+            ctx.chi0_kk(small_wl.w_eV, eta, b)
         assert e.value.code == q.EINVAL
     c = Context(0)
-    bs = cfg1.basis
-    c.set_cell_basis(cfg1.cell.lat, cfg1.cell.xyz, bs.shell_atom, bs.shell_l, bs.shell_exp, 1, 1)
+    bs = small_wl.basis
+    c.set_cell_basis(small_wl.cell.lat, small_wl.cell.xyz, bs.shell_atom, bs.shell_l, bs.shell_exp, 1, 1)
     with pytest.raises(QcxError) as e:
-        c.chi0_kk(cfg1.w_eV, 0.2, 0.05)
+        c.chi0_kk(small_wl.w_eV, 0.2, 0.05)
     assert e.value.code == q.ESTATE
     c.close()

@@ -43,7 +43,7 @@ def _vol(wl):
     return abs(float(np.linalg.det(np.asarray(wl.cell.lat, np.float64))))
 
 
-@pytest.mark.parametrize("name", ["tiny", "cfg1"])
+@pytest.mark.parametrize("name", ["tiny", "small_wl"])
 def test_optical_against_oracle(ctx, request, name):
     import torch
 
@@ -78,19 +78,19 @@ def test_optical_against_oracle(ctx, request, name):
     assert e < 1e-10
 
 
-def test_optical_errors(ctx, cfg1):
+def test_optical_errors(ctx, small_wl):
     from paper_2603_12326_amd import QcxError
     from paper_2603_12326_amd import qcx as q
     from tests.gpu_helpers import set_inputs
 
-    set_inputs(ctx, cfg1)                     # q != 0
+    set_inputs(ctx, small_wl)                     # q != 0
     with pytest.raises(QcxError) as e:
-        ctx.pair_density_optical(cfg1.G_int, QHAT)
+        ctx.pair_density_optical(small_wl.G_int, QHAT)
     assert e.value.code == q.EINVAL
-    _set_q0(ctx, cfg1)
+    _set_q0(ctx, small_wl)
     with pytest.raises(QcxError) as e:
-        ctx.pair_density_optical(cfg1.G_int, (0.0, 0.0, 0.0))
+        ctx.pair_density_optical(small_wl.G_int, (0.0, 0.0, 0.0))
     assert e.value.code == q.EINVAL
     with pytest.raises(QcxError) as e:        # q + G = 0 without the optical limit
-        ctx.pair_density(cfg1.G_int)
+        ctx.pair_density(small_wl.G_int)
     assert e.value.code == q.EINVAL

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import rpa
-from synth import make_config1, make_config2, make_config4, make_tiny
+from synth import make_smallest, make_si_ng113, make_all_electron, make_tiny
 from tests.gpu_helpers import gpu_solve, normwise, relmax, set_inputs
 
 pytestmark = pytest.mark.gpu
@@ -40,7 +40,7 @@ def test_native_library_loaded(ctx):
     assert "gfx950" in build_info()
 
 
-@pytest.mark.parametrize("maker", [make_tiny, make_config1])
+@pytest.mark.parametrize("maker", [make_tiny, make_smallest])
 def test_rho_fp64(ctx, maker):
     wl = maker()
     ref = _oracle(wl)
@@ -50,7 +50,7 @@ def test_rho_fp64(ctx, maker):
     assert err < 1e-10
 
 
-@pytest.mark.parametrize("maker", [make_tiny, make_config1])
+@pytest.mark.parametrize("maker", [make_tiny, make_smallest])
 def test_rho_independent_of_stale_lds(ctx, maker):
     """LDS keeps whatever the previous kernel left there.  A NaN-filled FP64
     product (its tiles pass through LDS) runs right before the pair densities,
@@ -83,7 +83,7 @@ def test_rho_ket_first_order(ctx):
     assert e_rho < 1e-10 and e_loss < 1e-10
 
 
-@pytest.mark.parametrize("maker", [make_tiny, make_config1])
+@pytest.mark.parametrize("maker", [make_tiny, make_smallest])
 def test_chi0_and_loss_fp64(ctx, maker):
     wl = maker()
     ref = _oracle(wl)
@@ -96,14 +96,14 @@ def test_chi0_and_loss_fp64(ctx, maker):
     assert np.max(np.abs(out["loss"] - ref["loss"])) < 1e-10 * np.max(np.abs(ref["loss"]))
 
 
-def test_nolfe_fp64(ctx, cfg1):
-    ref = _oracle(cfg1)
-    out = gpu_solve(ctx, cfg1, precision="fp64", lfe=False)
+def test_nolfe_fp64(ctx, small_wl):
+    ref = _oracle(small_wl)
+    out = gpu_solve(ctx, small_wl, precision="fp64", lfe=False)
     assert normwise(out["loss"], rpa.loss_nolfe(ref["eps"])) < 1e-10
 
 
 @pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
-@pytest.mark.parametrize("maker", [make_tiny, make_config1])
+@pytest.mark.parametrize("maker", [make_tiny, make_smallest])
 def test_loss_reduced_precision(ctx, maker, prec):
     wl = maker()
     ref = _oracle(wl)
@@ -114,21 +114,21 @@ def test_loss_reduced_precision(ctx, maker, prec):
 
 
 @pytest.mark.parametrize("iq", [0, 9])
-def test_config2_full_size_sampled(ctx, iq):
+def test_si_ng113_full_size_sampled(ctx, iq):
     """N_G = 113, 8^3 k, 4+16 bands, 400 w in one launch as the benchmark runs
     it; every 16th frequency is checked against the oracle (FP32 and
     split-BF16 bulk), and the FP64 path at those 25 frequencies."""
-    wl = make_config2()
+    wl = make_si_ng113()
     idx = np.arange(0, 400, 16)
     ref = _oracle(wl, iq, w=wl.w_eV[idx])
     for prec in ("split_bf16", "fp32"):
         out = gpu_solve(ctx, wl, iq, precision=prec)
         e = normwise(out["loss"][idx], ref["loss"])
-        print("config2 q", iq, prec, "normwise", e)
+        print("si_ng113 q", iq, prec, "normwise", e)
         assert e < 1e-4
     out = gpu_solve(ctx, wl, iq, precision="fp64", w_eV=wl.w_eV[idx])
     e64 = normwise(out["loss"], ref["loss"])
-    print("config2 q", iq, "fp64", e64)
+    print("si_ng113 q", iq, "fp64", e64)
     assert e64 < 1e-10
 
 
@@ -143,31 +143,31 @@ def test_ragged_shapes(ctx):
             assert normwise(out["loss"], ref["loss"]) < tol, (prec, len(w))
 
 
-def test_headwings_flag_consistent(ctx, cfg1):
-    ref = _oracle(cfg1)
+def test_headwings_flag_consistent(ctx, small_wl):
+    ref = _oracle(small_wl)
     for hw in (True, False):
-        out = gpu_solve(ctx, cfg1, precision="split_bf16", hw64=hw)
+        out = gpu_solve(ctx, small_wl, precision="split_bf16", hw64=hw)
         assert normwise(out["loss"], ref["loss"]) < 1e-4
 
 
-def test_deterministic(ctx, cfg1):
+def test_deterministic(ctx, small_wl):
     for prec in ("fp64", "split_bf16"):
-        a = gpu_solve(ctx, cfg1, precision=prec)["loss"]
-        b = gpu_solve(ctx, cfg1, precision=prec)["loss"]
+        a = gpu_solve(ctx, small_wl, precision=prec)["loss"]
+        b = gpu_solve(ctx, small_wl, precision=prec)["loss"]
         assert np.array_equal(a, b)
 
 
-def test_error_paths(ctx, cfg1):
+def test_error_paths(ctx, small_wl):
     from paper_2603_12326_amd import Context, QcxError
     from paper_2603_12326_amd import qcx as q
 
     c2 = Context(0)
     with pytest.raises(QcxError) as e:
-        c2.pair_density(cfg1.G_int)
+        c2.pair_density(small_wl.G_int)
     assert e.value.code == q.ESTATE
-    st = set_inputs(c2, cfg1)
+    st = set_inputs(c2, small_wl)
     with pytest.raises(QcxError) as e:
-        c2.pair_density(cfg1.G_int[1:])          # G[0] != 0
+        c2.pair_density(small_wl.G_int[1:])          # G[0] != 0
     assert e.value.code == q.EINVAL
     with pytest.raises(QcxError) as e:
         c2.eps_inv()
@@ -175,20 +175,21 @@ def test_error_paths(ctx, cfg1):
     bad = st.C_kq.copy()
     bad[3] *= 1.001
     with pytest.raises(QcxError) as e:
-        c2.set_states(st.q_cart, cfg1.k_frac, cfg1.n_occ, st.C_k, st.E_k, bad, st.E_kq)
+        c2.set_states(st.q_cart, small_wl.k_frac, small_wl.n_occ, st.C_k, st.E_k, bad, st.E_kq)
     assert e.value.code == q.ENONORTH
     ebad = st.E_k.copy()
-    ebad[0, cfg1.n_occ] = -20.0
+    ebad[0, small_wl.n_occ] = -20.0
     with pytest.raises(QcxError) as e:
-        c2.set_states(st.q_cart, cfg1.k_frac, cfg1.n_occ, st.C_k, ebad, st.C_kq, st.E_kq)
+        c2.set_states(st.q_cart, small_wl.k_frac, small_wl.n_occ, st.C_k, ebad, st.C_kq, st.E_kq)
     assert e.value.code == q.EINVAL
     c2.close()
 
 
 @pytest.mark.parametrize("n_g", [181, 259])
-def test_large_ng_blocked_inversion(ctx, n_g):
-    """N_G above the register-resident limit: blocked Gauss-Jordan (panels of
-    32 columns in LDS, rank-32 trailing updates) and the 256-row FP64 stage."""
+def test_large_ng_panel_inversion(ctx, n_g):
+    """N_G above the register-resident limit: panel Gauss-Jordan (panels of 16
+    columns swept in registers, rank-16 trailing updates on FP64 MFMA) and the
+    256-row FP64 stage."""
     wl = make_tiny(kgrid=2, n_g=n_g, n_w=12)
     ref = _oracle(wl)
     out = gpu_solve(ctx, wl, precision="fp64")
@@ -200,16 +201,16 @@ def test_large_ng_blocked_inversion(ctx, n_g):
     assert esp < 1e-4
 
 
-def test_autotuned_bulk(ctx, cfg1):
+def test_autotuned_bulk(ctx, small_wl):
     """The bulk autotuner: the first call of a new shape times every candidate
     (tune_ms > 0), later calls reuse the choice (tune_ms == 0); the heuristic
     configuration and the tuned one both meet the oracle bar."""
     w = np.linspace(0.5, 35.0, 77)            # 77 frequencies: a shape no other test uses
-    ref = _oracle(cfg1, w=w)
+    ref = _oracle(small_wl, w=w)
     ctx.set_autotune(1)
-    a = gpu_solve(ctx, cfg1, precision="split_bf16", w_eV=w)
+    a = gpu_solve(ctx, small_wl, precision="split_bf16", w_eV=w)
     c1 = ctx.bulk_config()
-    b = gpu_solve(ctx, cfg1, precision="split_bf16", w_eV=w)
+    b = gpu_solve(ctx, small_wl, precision="split_bf16", w_eV=w)
     c2 = ctx.bulk_config()
     print("tuned", c1, "then", c2)
     assert c1["tune_ms"] > 0.0 and c2["tune_ms"] == 0.0
@@ -218,7 +219,7 @@ def test_autotuned_bulk(ctx, cfg1):
     assert c1["row_frags"] in (4, 5)
     assert np.array_equal(a["loss"], b["loss"])
     ctx.set_autotune(0)
-    h = gpu_solve(ctx, cfg1, precision="split_bf16", w_eV=w)
+    h = gpu_solve(ctx, small_wl, precision="split_bf16", w_eV=w)
     ctx.set_autotune(1)
     for out in (a, h):
         assert normwise(out["loss"], ref["loss"]) < 1e-4
@@ -226,15 +227,15 @@ def test_autotuned_bulk(ctx, cfg1):
 
 @pytest.mark.parametrize("prec", ["split_bf16", "fp32"])
 @pytest.mark.parametrize("nst", [2, 3, 4])
-def test_bulk_pipelines(ctx, cfg1, prec, nst):
+def test_bulk_pipelines(ctx, small_wl, prec, nst):
     """Every LDS pipeline of the bulk kernel (two stages, three stages, three
     stages with the slab one step ahead of the weights) against the oracle,
     with a frequency count that leaves a ragged last row tile."""
     w = np.linspace(0.3, 38.0, 61)
-    ref = _oracle(cfg1, w=w)
+    ref = _oracle(small_wl, w=w)
     ctx.set_bulk_pipeline(nst)
     try:
-        out = gpu_solve(ctx, cfg1, precision=prec, w_eV=w)
+        out = gpu_solve(ctx, small_wl, precision=prec, w_eV=w)
         assert ctx.bulk_config()["stages"] == nst
     finally:
         ctx.set_bulk_pipeline(0)
@@ -244,7 +245,7 @@ def test_bulk_pipelines(ctx, cfg1, prec, nst):
 
 
 @pytest.mark.parametrize("q_frac", [(0.25, 0.0, 0.0), (2.25, 0.0, 0.0), (1.5, 1.5, 1.5)])
-def test_config4_all_electron_full_ng(ctx, q_frac):
+def test_all_electron_full_ng(ctx, q_frac):
     """The high-momentum all-electron case at its full N_G = 749 and full
     basis (6s5p1d per atom with core exponents up to 1e4, 5 core + 4 valence
     + 28 conduction bands) on a 2^3 k grid, for q in the first zone, along
@@ -252,19 +253,19 @@ def test_config4_all_electron_full_ng(ctx, q_frac):
     128-pair tile stages only its own slab rows)."""
     import math
 
-    wl0 = make_config4(n_w=8, kgrid=2)
+    wl0 = make_all_electron(n_w=8, kgrid=2)
     a = wl0.cell.a
-    wl = make_config4(n_w=8, kgrid=2, q_list=[np.array(q_frac) * 2 * math.pi / a])
+    wl = make_all_electron(n_w=8, kgrid=2, q_list=[np.array(q_frac) * 2 * math.pi / a])
     ref = _oracle(wl)
     for prec, tol in (("fp64", 1e-10), ("split_bf16", 1e-4), ("fp32", 1e-4)):
         out = gpu_solve(ctx, wl, precision=prec)
         e = normwise(out["loss"], ref["loss"])
-        print("config4 q", q_frac, prec, e)
+        print("all-electron q", q_frac, prec, e)
         assert e < tol, (prec, e)
 
 
-def test_config4_full_size():
-    """Config 4 at full size on the GPU: 12^3 k (N_T = 870,912), N_G = 749,
+def test_all_electron_full_size():
+    """The all-electron workload at full size on the GPU: 12^3 k (N_T = 870,912), N_G = 749,
     1000 frequencies over 0-100 eV in one call, split-BF16 bulk.  The FP64
     path (parity-pinned above) is run on 4 sampled frequencies and the
     split-BF16 loss must agree with it there; every loss is finite and >= 0."""
@@ -274,7 +275,7 @@ def test_config4_full_size():
 
     from paper_2603_12326_amd import Context
 
-    wl = make_config4()
+    wl = make_all_electron()
     c = Context(0)
     t0 = time.perf_counter()
     out = gpu_solve(c, wl, precision="split_bf16")
@@ -285,12 +286,12 @@ def test_config4_full_size():
     idx = np.array([10, 250, 500, 900])
     o64 = gpu_solve(c, wl, precision="fp64", w_eV=wl.w_eV[idx])
     e = normwise(L[idx], o64["loss"])
-    print(f"config4 full size: split 1000 w in {t1 - t0:.2f} s, split vs fp64 {e:.3g}")
+    print(f"all-electron full size: split 1000 w in {t1 - t0:.2f} s, split vs fp64 {e:.3g}")
     assert e < 1e-4
     c.close()
 
 
-def test_device_state_checks_deferred(cfg1):
+def test_device_state_checks_deferred(small_wl):
     """Device-resident states are checked on the stream: a bad coefficient
     matrix does not raise at set_states but at the next synchronising call;
     good states pass and the check is reset."""
@@ -300,29 +301,29 @@ def test_device_state_checks_deferred(cfg1):
     from paper_2603_12326_amd import qcx as q
 
     c = Context(0)
-    st = set_inputs(c, cfg1)
+    st = set_inputs(c, small_wl)
     dev = lambda a, t: torch.from_numpy(np.ascontiguousarray(a)).to(t).cuda()  # noqa: E731
-    kf = dev(cfg1.k_frac, torch.float64)
+    kf = dev(small_wl.k_frac, torch.float64)
     bad = st.C_kq.copy()
     bad[5] *= 1.001
-    c.set_states(st.q_cart, kf, cfg1.n_occ, dev(st.C_k, torch.complex128),
+    c.set_states(st.q_cart, kf, small_wl.n_occ, dev(st.C_k, torch.complex128),
                  dev(st.E_k, torch.float64), dev(bad, torch.complex128), dev(st.E_kq, torch.float64))
     with pytest.raises(QcxError) as e:
         c.sync()
     assert e.value.code == q.ENONORTH and "k+q 5" in str(e.value)
     ebad = st.E_k.copy()
-    ebad[3, cfg1.n_occ] = -20.0
-    c.set_states(st.q_cart, kf, cfg1.n_occ, dev(st.C_k, torch.complex128),
+    ebad[3, small_wl.n_occ] = -20.0
+    c.set_states(st.q_cart, kf, small_wl.n_occ, dev(st.C_k, torch.complex128),
                  dev(ebad, torch.float64), dev(st.C_kq, torch.complex128), dev(st.E_kq, torch.float64))
     with pytest.raises(QcxError) as e:
         c.sync()
     assert e.value.code == q.EINVAL and "k 3" in str(e.value)
-    c.set_states(st.q_cart, kf, cfg1.n_occ, dev(st.C_k, torch.complex128),
+    c.set_states(st.q_cart, kf, small_wl.n_occ, dev(st.C_k, torch.complex128),
                  dev(st.E_k, torch.float64), dev(st.C_kq, torch.complex128), dev(st.E_kq, torch.float64))
     c.sync()
-    c.pair_density(cfg1.G_int)
-    c.chi0(cfg1.w_eV, cfg1.eta_eV, "fp64")
+    c.pair_density(small_wl.G_int)
+    c.chi0(small_wl.w_eV, small_wl.eta_eV, "fp64")
     c.eps_inv()
-    ref = _oracle(cfg1)
+    ref = _oracle(small_wl)
     assert normwise(c.loss(), ref["loss"]) < 1e-10
     c.close()

@@ -87,35 +87,35 @@ def test_binning_random(ctx):
     qb.close()
 
 
-def test_binning_workload(ctx, cfg1, cfg1_oracle):
+def test_binning_workload(ctx, small_wl, small_oracle):
     import torch
 
     from paper_2603_12326_amd import QBins
 
-    st = set_inputs(ctx, cfg1)
-    w = cfg1.w_eV[::4]
-    n_w, n_g = len(w), len(cfg1.G_int)
-    ctx.pair_density(cfg1.G_int)
-    ctx.chi0(w, cfg1.eta_eV, "fp64", True)
+    st = set_inputs(ctx, small_wl)
+    w = small_wl.w_eV[::4]
+    n_w, n_g = len(w), len(small_wl.G_int)
+    ctx.pair_density(small_wl.G_int)
+    ctx.chi0(w, small_wl.eta_eV, "fp64", True)
     d = torch.empty((n_w, n_g), dtype=torch.complex128, device="cuda")
     ctx.eps_inv(True, diag_out=d)
-    Q = rpa.q_plus_g(cfg1.cell.lat, st.q_cart, cfg1.G_int)
+    Q = rpa.q_plus_g(small_wl.cell.lat, st.q_cart, small_wl.G_int)
     # noLFE entries: 300 G beyond the LFE block
     r = np.arange(-4, 5)
     G = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
-    b = 2.0 * np.pi * np.linalg.inv(np.asarray(cfg1.cell.lat, np.float64)).T
+    b = 2.0 * np.pi * np.linalg.inv(np.asarray(small_wl.cell.lat, np.float64)).T
     G = G[np.argsort(np.linalg.norm(G @ b, axis=1), kind="stable")][27:327].astype(np.int32)
-    Qn = rpa.q_plus_g(cfg1.cell.lat, st.q_cart, G)
+    Qn = rpa.q_plus_g(small_wl.cell.lat, st.q_cart, G)
     inv = torch.empty((n_w, len(G)), dtype=torch.complex128, device="cuda")
-    ctx.loss_diag(G, w, cfg1.eta_eV, "fp64", inv_out=inv)
+    ctx.loss_diag(G, w, small_wl.eta_eV, "fp64", inv_out=inv)
     dq, n_shell = 0.1, 40
     qb = QBins(ctx, n_w, n_shell, dq, NT, NP)
     qb.add(Q, d, "inv")
     qb.add(Qn, inv, "inv")
     gpu = qb.finish(want_eps=True)
-    eps_lfe = 1.0 / rpa.inverse_diagonal(cfg1_oracle["eps"][::4])
-    eps_nol = rpa.eps_diag(cfg1.cell, cfg1.basis, cfg1.lattice_range, cfg1.k_frac, cfg1.n_occ, G,
-                           st, w, cfg1.eta_eV)
+    eps_lfe = 1.0 / rpa.inverse_diagonal(small_oracle["eps"][::4])
+    eps_nol = rpa.eps_diag(small_wl.cell, small_wl.basis, small_wl.lattice_range, small_wl.k_frac, small_wl.n_occ, G,
+                           st, w, small_wl.eta_eV)
     ref = _oracle([(Q, eps_lfe), (Qn, eps_nol)], n_w, dq, n_shell)
     # FP64 path: the library's eps agrees with the oracle's to ~1e-13
     S_ref = ref[3]

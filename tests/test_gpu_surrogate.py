@@ -25,7 +25,7 @@ import time
 import numpy as np
 import pytest
 
-from synth.surrogate import (SURR_SEED, batch_order, holdout_split, make_config5, mlp_init, q_max,
+from synth.surrogate import (SURR_SEED, batch_order, holdout_split, make_surrogate_workload, mlp_init, q_max,
                              random_q, random_w)
 
 pytestmark = pytest.mark.gpu
@@ -37,10 +37,10 @@ def test_surrogate_end_to_end():
     from paper_2603_12326_amd import Context
     from paper_2603_12326_amd import surrogate as S
 
-    base = make_config5([])
+    base = make_surrogate_workload([])
     tq = random_q(SURR_SEED + 10, base.cell.lat, 48)
     qq = random_q(SURR_SEED + 20, base.cell.lat, 40)
-    wl = make_config5(list(tq) + list(qq))
+    wl = make_surrogate_workload(list(tq) + list(qq))
     tw = random_w(SURR_SEED + 11, len(tq), 16)
     wq = [np.linspace(0.0, 60.0, 97)] * len(qq)
     ctx = Context(0)

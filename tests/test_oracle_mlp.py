@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp
-from synth.surrogate import batch_order, holdout_split, make_config5, mlp_init, random_q
+from synth.surrogate import batch_order, holdout_split, make_surrogate_workload, mlp_init, random_q
 
 SMALL = (5, 8, 8, 8, 8, 1)
 
@@ -158,7 +158,7 @@ def test_training_loop_fits_smooth_target():
 def test_smooth_band_workload_is_periodic_and_ordered():
     from synth.generator import _band_energies, _band_model
 
-    wl = make_config5(random_q(1, make_config5([]).cell.lat, 2), kgrid=3)
+    wl = make_surrogate_workload(random_q(1, make_surrogate_workload([]).cell.lat, 2), kgrid=3)
     st = wl.states(0)
     assert np.all(np.diff(st.E_k[:, :4], axis=1) >= 0) and np.all(np.diff(st.E_k[:, 4:], axis=1) >= 0)
     assert st.E_k[:, :4].max() <= 0.0 and st.E_k[:, 4:].min() >= 1.1

@@ -161,11 +161,11 @@ def test_eps_length_scaling():
     assert np.max(np.abs((sc - I) * s - (base - I))) < 1e-10 * np.max(np.abs(base - I))
 
 
-def test_eps_tends_to_one_at_large_q(cfg1_oracle):
-    eps = cfg1_oracle["eps"]
-    R = cfg1_oracle["R"].reshape(-1, eps.shape[1])
-    W = cfg1_oracle["W"]
-    Q = cfg1_oracle["Q"]
+def test_eps_tends_to_one_at_large_q(small_oracle):
+    eps = small_oracle["eps"]
+    R = small_oracle["R"].reshape(-1, eps.shape[1])
+    W = small_oracle["W"]
+    Q = small_oracle["Q"]
     q2 = np.sum(Q * Q, axis=1)
     bound = 4 * math.pi / q2[None, :] * (np.abs(W) @ (np.abs(R) ** 2))
     dev = np.abs(np.diagonal(eps, axis1=1, axis2=2) - 1.0)
@@ -174,15 +174,15 @@ def test_eps_tends_to_one_at_large_q(cfg1_oracle):
     assert dev[:, np.argmax(q2)].max() < 0.1 * dev[:, 0].max()
 
 
-def test_eps_antihermitian_part_psd(cfg1_oracle):
-    for e in cfg1_oracle["eps"][::8]:
+def test_eps_antihermitian_part_psd(small_oracle):
+    for e in small_oracle["eps"][::8]:
         ev = np.linalg.eigvalsh((e - e.conj().T) / 2j)
         assert ev.min() > -1e-12 * np.abs(ev).max()
 
 
 # ---------------------------------------------------------------- inverse and loss
-def test_lfe_equals_nolfe_without_offdiagonals(cfg1_oracle):
-    eps = cfg1_oracle["eps"]
+def test_lfe_equals_nolfe_without_offdiagonals(small_oracle):
+    eps = small_oracle["eps"]
     d = np.einsum("wgg->wg", eps)
     diag_only = np.zeros_like(eps)
     idx = np.arange(eps.shape[1])
@@ -192,17 +192,17 @@ def test_lfe_equals_nolfe_without_offdiagonals(cfg1_oracle):
     assert np.max(np.abs(rpa.loss_lfe(one) - rpa.loss_nolfe(one))) < 1e-15
 
 
-def test_loss_nonnegative(cfg1_oracle):
-    assert cfg1_oracle["loss"].min() > -1e-15
-    assert rpa.loss_nolfe(cfg1_oracle["eps"]).min() > -1e-15
+def test_loss_nonnegative(small_oracle):
+    assert small_oracle["loss"].min() > -1e-15
+    assert rpa.loss_nolfe(small_oracle["eps"]).min() > -1e-15
 
 
-def test_inverse_diagonal_invariances(cfg1_oracle):
+def test_inverse_diagonal_invariances(small_oracle):
     """diag(eps^-1) is unchanged by transposition and by the non-symmetric
     Coulomb form eps' = 1 - v(q+G) chi0 (a similar matrix)."""
-    eps = cfg1_oracle["eps"][::16]
-    chi = cfg1_oracle["chi0"][::16]
-    Q = cfg1_oracle["Q"]
+    eps = small_oracle["eps"][::16]
+    chi = small_oracle["chi0"][::16]
+    Q = small_oracle["Q"]
     d = rpa.inverse_diagonal(eps)
     assert np.max(np.abs(rpa.inverse_diagonal(np.swapaxes(eps, 1, 2)) - d)) < 1e-12
     v = 4 * math.pi / np.sum(Q * Q, axis=1)
@@ -214,56 +214,56 @@ def test_inverse_diagonal_invariances(cfg1_oracle):
         assert res < 1e-13
 
 
-def test_macroscopic_eps_is_inverse_head(cfg1_oracle):
-    eps = cfg1_oracle["eps"]
+def test_macroscopic_eps_is_inverse_head(small_oracle):
+    eps = small_oracle["eps"]
     em = rpa.eps_macro(eps)
     assert np.allclose(em, 1.0 / np.linalg.inv(eps)[:, 0, 0], rtol=1e-14, atol=0)
     # loss at G = 0 is Im(-1/eps_M)
-    assert np.allclose(cfg1_oracle["loss"][:, 0], np.imag(-1.0 / em), rtol=1e-12, atol=1e-15)
+    assert np.allclose(small_oracle["loss"][:, 0], np.imag(-1.0 / em), rtol=1e-12, atol=1e-15)
 
 
 # ---------------------------------------------------------------- noLFE diagonal and composite
-def test_chi0_diagonal_is_diagonal_of_chi0(cfg1_oracle):
-    d = rpa.chi0_diagonal(cfg1_oracle["R"], cfg1_oracle["W"])
-    full = np.einsum("wgg->wg", cfg1_oracle["chi0"])
+def test_chi0_diagonal_is_diagonal_of_chi0(small_oracle):
+    d = rpa.chi0_diagonal(small_oracle["R"], small_oracle["W"])
+    full = np.einsum("wgg->wg", small_oracle["chi0"])
     assert np.max(np.abs(d - full)) <= 1e-14 * np.max(np.abs(full))
 
 
-def test_loss_diag_matches_nolfe_of_full_path(cfg1, cfg1_oracle):
-    st = cfg1.states(0)
-    L = rpa.loss_diag(cfg1.cell, cfg1.basis, cfg1.lattice_range, cfg1.k_frac, cfg1.n_occ,
-                      cfg1.G_int, st, cfg1.w_eV, cfg1.eta_eV)
-    ref = rpa.loss_nolfe(cfg1_oracle["eps"])
+def test_loss_diag_matches_nolfe_of_full_path(small_wl, small_oracle):
+    st = small_wl.states(0)
+    L = rpa.loss_diag(small_wl.cell, small_wl.basis, small_wl.lattice_range, small_wl.k_frac, small_wl.n_occ,
+                      small_wl.G_int, st, small_wl.w_eV, small_wl.eta_eV)
+    ref = rpa.loss_nolfe(small_oracle["eps"])
     assert np.max(np.abs(L - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
-def test_loss_diag_per_g_independent_of_list(cfg1):
+def test_loss_diag_per_g_independent_of_list(small_wl):
     """Each G's diagonal depends on that G alone: any subset, order or
     duplication (no G = 0) gives the same columns."""
-    st = cfg1.states(0)
-    G = np.asarray(cfg1.G_int)
-    args = (cfg1.cell, cfg1.basis, cfg1.lattice_range, cfg1.k_frac, cfg1.n_occ)
-    w = cfg1.w_eV[::16]
-    full = rpa.loss_diag(*args, G, st, w, cfg1.eta_eV)
+    st = small_wl.states(0)
+    G = np.asarray(small_wl.G_int)
+    args = (small_wl.cell, small_wl.basis, small_wl.lattice_range, small_wl.k_frac, small_wl.n_occ)
+    w = small_wl.w_eV[::16]
+    full = rpa.loss_diag(*args, G, st, w, small_wl.eta_eV)
     pick = np.array([5, 3, 26, 5, 11])
-    sub = rpa.loss_diag(*args, G[pick], st, w, cfg1.eta_eV)
+    sub = rpa.loss_diag(*args, G[pick], st, w, small_wl.eta_eV)
     assert np.max(np.abs(sub - full[:, pick])) <= 1e-13 * np.max(np.abs(full))
 
 
-def test_composite_limits(cfg1, cfg1_oracle):
+def test_composite_limits(small_wl, small_oracle):
     """q_lfe above every |q+G|: the LFE loss; q_lfe between |q| and the next
     |q+G|: a 1 x 1 LFE block, i.e. the noLFE loss everywhere."""
-    st = cfg1.states(0)
-    args = (cfg1.cell, cfg1.basis, cfg1.lattice_range, cfg1.k_frac, cfg1.n_occ, cfg1.G_int, st,
-            cfg1.w_eV, cfg1.eta_eV)
-    qn = np.linalg.norm(cfg1_oracle["Q"], axis=1)
+    st = small_wl.states(0)
+    args = (small_wl.cell, small_wl.basis, small_wl.lattice_range, small_wl.k_frac, small_wl.n_occ, small_wl.G_int, st,
+            small_wl.w_eV, small_wl.eta_eV)
+    qn = np.linalg.norm(small_oracle["Q"], axis=1)
     hi = rpa.loss_composite(*args, q_lfe=qn.max() * 1.01)
-    assert np.max(np.abs(hi - cfg1_oracle["loss"])) <= 1e-13 * np.max(np.abs(cfg1_oracle["loss"]))
+    assert np.max(np.abs(hi - small_oracle["loss"])) <= 1e-13 * np.max(np.abs(small_oracle["loss"]))
     lo = rpa.loss_composite(*args, q_lfe=0.5 * (qn[0] + np.sort(qn)[1]))
-    ref = rpa.loss_nolfe(cfg1_oracle["eps"])
+    ref = rpa.loss_nolfe(small_oracle["eps"])
     assert np.max(np.abs(lo - ref)) <= 1e-13 * np.max(np.abs(ref))
     with pytest.raises(ValueError):
-        rpa.composite_split(cfg1.cell.lat, st.q_cart, np.asarray(cfg1.G_int)[1:], qn.max())
+        rpa.composite_split(small_wl.cell.lat, st.q_cart, np.asarray(small_wl.G_int)[1:], qn.max())
 
 
 # ---------------------------------------------------------------- Kramers-Kronig route
@@ -317,39 +317,39 @@ def test_spectral_bins_partition_of_unity():
     assert np.max(np.abs(c @ H - E)) < 1e-13       # first moment kept too
 
 
-def test_chi0_kk_converges_to_direct(cfg1_oracle, cfg1):
+def test_chi0_kk_converges_to_direct(small_oracle, small_wl):
     """At fixed eta the binned route tends to Eq. (RPA) at second order in the
     bin width: halving the width divides the error by about four."""
-    st = cfg1.states(0)
-    vol = _vol(cfg1.cell)
-    w = cfg1.w_eV[::8]
-    W = rpa.transition_weights(st.E_k, st.E_kq, cfg1.n_occ, w, cfg1.eta_eV, vol)
-    direct = rpa.chi0(cfg1_oracle["R"], W)
+    st = small_wl.states(0)
+    vol = _vol(small_wl.cell)
+    w = small_wl.w_eV[::8]
+    W = rpa.transition_weights(st.E_k, st.E_kq, small_wl.n_occ, w, small_wl.eta_eV, vol)
+    direct = rpa.chi0(small_oracle["R"], W)
     errs = []
     for b in (0.08, 0.04, 0.02):
-        kk = rpa.chi0_kk(cfg1_oracle["R"], st.E_k, st.E_kq, cfg1.n_occ, w, cfg1.eta_eV, b, vol)
+        kk = rpa.chi0_kk(small_oracle["R"], st.E_k, st.E_kq, small_wl.n_occ, w, small_wl.eta_eV, b, vol)
         errs.append(np.max(np.abs(kk - direct)) / np.max(np.abs(direct)))
     assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0, errs
     assert errs[2] < 2e-3
 
 
-def test_chi0_kk_zero_eta_is_kramers_kronig_pair(cfg1_oracle, cfg1):
+def test_chi0_kk_zero_eta_is_kramers_kronig_pair(small_oracle, small_wl):
     """eta = 0: Im chi0 is -pi times the binned spectral density, and Re chi0
     is its Kramers-Kronig (Hilbert) transform, checked for the head by an
     independent quadrature over the piecewise-linear density."""
     from scipy.integrate import quad
-    st = cfg1.states(0)
-    vol = _vol(cfg1.cell)
+    st = small_wl.states(0)
+    vol = _vol(small_wl.cell)
     b = 0.1
     w = np.array([3.03, 7.57, 12.01, 20.04])   # poles inside segments, not on bin centres
-    kk = rpa.chi0_kk(cfg1_oracle["R"], st.E_k, st.E_kq, cfg1.n_occ, w, 0.0, b, vol)[:, 0, 0]
+    kk = rpa.chi0_kk(small_oracle["R"], st.E_k, st.E_kq, small_wl.n_occ, w, 0.0, b, vol)[:, 0, 0]
     # spectral densities (per Ha) of the head, both sides, as piecewise-linear functions
-    d_res, d_anti = rpa.transition_energies(st.E_k, st.E_kq, cfg1.n_occ)
-    norm = 2.0 / (len(cfg1.k_frac) * vol)
+    d_res, d_anti = rpa.transition_energies(st.E_k, st.E_kq, small_wl.n_occ)
+    norm = 2.0 / (len(small_wl.k_frac) * vol)
     dens = []
     for side, E in ((0, d_res.reshape(-1)), (1, d_anti.reshape(-1))):
         c, H = rpa.spectral_bins(E, b)
-        S = norm * (H @ (np.abs(cfg1_oracle["R"][side].reshape(-1, 27)[:, 0]) ** 2))
+        S = norm * (H @ (np.abs(small_oracle["R"][side].reshape(-1, 27)[:, 0]) ** 2))
         dens.append((c, S / (b / rpa.HARTREE_EV)))
     wh = w / rpa.HARTREE_EV
     for j in range(len(w)):
