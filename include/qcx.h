@@ -271,7 +271,7 @@ int qcx_loss(qcx_ctx* ctx, double* out, int mem);
  * part and its real part the Kramers-Kronig transform of it.  Everything
  * runs in FP64: the binning on the vector units over energy-sorted
  * transitions (each bin written once, no atomics: the result does not depend
- * on the launch), the transform as one FP64 matrix product (rocBLAS dgemm)
+ * on the launch), the transform as one FP64 matrix product on FP64 MFMA
  * of the [2 n_w][bins] kernel matrix with the [bins][2 n_pairs] spectral
  * function.
  * Afterwards qcx_eps_inv / qcx_loss work as after qcx_chi0.  The transition
@@ -355,8 +355,9 @@ int qcx_batch_config(qcx_ctx* ctx, int cfg[3], double* tune_ms);
  * Surrogate of the loss (not part of the paper's method): an ensemble of
  * small networks mapping a momentum transfer and an energy to
  * log Im[-1/eps_LFE](Q, w), the quantity of Eq. (eps_LFE) that the rate
- * integral sweeps.  Each member is 5 -> 256 -> 256 -> 256 -> 256 -> 1 with
- * SiLU after the hidden layers; FP32 master weights, bf16 copies for the
+ * integral sweeps.  Each member is 49 -> 256 -> 256 -> 256 -> 256 -> 1 with
+ * SiLU after the hidden layers (the 49 inputs are the features that
+ * qcx_mlp_encode forms); FP32 master weights, bf16 copies for the
  * products (v_mfma_f32_32x32x16_bf16, FP32 accumulation), Adam training on
  * the mean squared error.  Members run on the device and stream of the
  * context they were created from; errors are reported through
@@ -365,7 +366,8 @@ int qcx_batch_config(qcx_ctx* ctx, int cfg[3], double* tune_ms);
  * Parameter vector (QCX_MLP_NPARAM floats): per layer l = 1..5 the weight
  * matrix W_l[n_out][n_in] (row-major), then the bias b_l[n_out].
  * ------------------------------------------------------------------------ */
-#define QCX_MLP_NPARAM 199169
+#define QCX_MLP_NIN 49
+#define QCX_MLP_NPARAM 210433
 typedef struct qcx_mlp qcx_mlp;
 
 /* Create n_members (1..16) networks with zero parameters on ctx. */
@@ -377,30 +379,40 @@ int qcx_mlp_destroy(qcx_mlp* m);
 int qcx_mlp_set_params(qcx_mlp* m, int member, const float* params);
 /* Copy member `member`'s FP32 parameters to host params.  Synchronous. */
 int qcx_mlp_get_params(qcx_mlp* m, int member, float* params);
-/* Network output y[i] for device inputs x[n][5] (device y[n]).  Async. */
+/* Network output y[i] for device inputs x[n][QCX_MLP_NIN] (device y[n]).
+ * Async. */
 int qcx_mlp_forward(qcx_mlp* m, int member, int n, const float* x, float* y);
-/* Gradient of mean_i (y_i - t_i)^2 over device x[n][5], t[n] (n <= 16384)
+/* Gradient of mean_i (y_i - t_i)^2 over device x[n][QCX_MLP_NIN], t[n] (n <= 16384)
  * into host grad[QCX_MLP_NPARAM]; the loss into *loss if not NULL.  No
  * update.  Synchronous. */
 int qcx_mlp_grad(qcx_mlp* m, int member, int n, const float* x, const float* t, float* grad,
                  float* loss);
 /* n_steps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on
  * mini-batches: step s uses samples order[s*batch .. (s+1)*batch) of the
- * device data x[n_data][5], t[n_data]; order is a device int array of
+ * device data x[n_data][QCX_MLP_NIN], t[n_data]; order is a device int array of
  * n_steps*batch indices in [0, n_data) (checked before the first step).
  * Learning rate lr1 + (lr0 - lr1)(1 + cos(pi s / n_steps))/2.  batch
  * 1..16384.  Per-step losses into host loss_hist[n_steps] if not NULL (then
  * synchronous; otherwise asynchronous). */
 int qcx_mlp_train(qcx_mlp* m, int member, int n_data, const float* x, const float* t, int batch,
                   int n_steps, const int* order, float lr0, float lr1, float* loss_hist);
-/* Input and output scaling shared by qcx_mlp_encode and qcx_mlp_query:
- * features x = (2|Q|/q_max - 1, Q/|Q|, 2w/w_max - 1) and target
+/* Input and output scaling shared by qcx_mlp_encode and qcx_mlp_query.
+ * The QCX_MLP_NIN features of a query (Q, w), formed in FP64 and rounded to
+ * FP32, are
+ *   2|Q|/q_max - 1;  Q/|Q| (zero for Q = 0);  2w/w_max - 1;
+ *   sin, cos of pi 2^(j/2) w/w_max for j = 0..7;
+ *   sin, cos of pi 2^(j/2) |Q|/q_max for j = 0..7;
+ *   sin, cos of h Q.a_i for i = 1..3, h = 1, 2,
+ * with a_i the primitive vectors lattice[3i .. 3i+2] (host, bohr) of the
+ * crystal the loss belongs to; the target is
  * t = (log max(L, 1e-30) - mu)/sigma; the error estimate of a query is
  * calib * sigma * (sample standard deviation of the members' outputs), an
- * estimate of the relative error of the returned loss. */
-int qcx_mlp_set_encoding(qcx_mlp* m, double q_max, double w_max_eV, double mu, double sigma,
-                         double calib);
-/* Features x[n][5] (device float) of device queries qw[n][4] = (Qx, Qy, Qz
+ * estimate of the relative error of the returned loss.  Errors: QCX_EINVAL
+ * (non-positive scales or sigma, negative calib, non-finite values, NULL
+ * lattice). */
+int qcx_mlp_set_encoding(qcx_mlp* m, double q_max, double w_max_eV, const double* lattice,
+                         double mu, double sigma, double calib);
+/* Features x[n][QCX_MLP_NIN] (device float) of device queries qw[n][4] = (Qx, Qy, Qz
  * in bohr^-1, w in eV), and, if loss (device double [n]) and t are not
  * NULL, the training targets t[n].  Errors: QCX_ESTATE before
  * qcx_mlp_set_encoding.  Async. */
@@ -414,6 +426,23 @@ int qcx_mlp_encode(qcx_mlp* m, int n, const double* qw, const double* loss, floa
  * rejecting, otherwise asynchronous. */
 int qcx_mlp_query(qcx_mlp* m, int n, const double* qw, double* loss, double* err, double tol,
                   int* reject_idx, int* n_reject);
+/* Surrogate answer with fallback to the method for one momentum: the loss at
+ * Q = q + G (q of the states last set on ctx, G the list G_int[n_G][3] in
+ * the reciprocal basis with G_int[0] = (0,0,0), as for qcx_pair_density) and
+ * the frequencies w_eV (host [n_w], eV), into loss_out (device double
+ * [n_w][n_G]).  The networks answer every point; every frequency with a
+ * point whose error estimate exceeds tol is recomputed by the method on ctx
+ * (qcx_pair_density for G_int, qcx_chi0 at those frequencies with
+ * `precision` and FP64 head/wings, qcx_eps_inv with LFE, qcx_loss) and its
+ * row replaced.  err_out (device double [n_w][n_G], may be NULL) receives
+ * the networks' estimates; *n_fallback (may be NULL) the number of
+ * recomputed frequencies.  ctx's pair densities and results are overwritten
+ * when a fallback runs.  The networks and ctx must be on one device.
+ * Synchronous.  Errors: as the calls above; QCX_EINVAL beyond 2^26 points,
+ * QCX_ESTATE before qcx_mlp_set_encoding or qcx_set_states. */
+int qcx_mlp_infer(qcx_mlp* m, qcx_ctx* ctx, int n_G, const int* G_int, int n_w,
+                  const double* w_eV, double eta_eV, double tol, int precision, double* loss_out,
+                  double* err_out, int* n_fallback);
 
 /* ------------------------------------------------------------------------
  * From the dielectric function to scattering rates (Sec. III binning, Eq.

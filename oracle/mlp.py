@@ -3,10 +3,10 @@
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 The surrogate is not part of the paper: it is a small fully connected
-network that maps a momentum transfer and an energy, (|Q|, Q/|Q|, w), to
-log Im[-1/eps_LFE](Q, w), the quantity of Eq. (eps_LFE) that the rate
-integral of Sec. II sweeps over a dense grid.  Architecture: widths
-5 -> 256 -> 256 -> 256 -> 256 -> 1 with the SiLU activation
+network that maps a momentum transfer and an energy (Q, w), through the 49
+features of encode(), to log Im[-1/eps_LFE](Q, w), the quantity of Eq.
+(eps_LFE) that the rate integral of Sec. II sweeps over a dense grid.
+Architecture: widths 49 -> 256 -> 256 -> 256 -> 256 -> 1 with the SiLU activation
 silu(z) = z / (1 + e^{-z}) after every hidden layer and a linear output;
 mean-squared-error loss; Adam (Kingma and Ba, ICLR 2015) with bias
 correction.  Every function here is generic in the widths so that small
@@ -21,7 +21,7 @@ Two arithmetic modes:
   every weight matrix is rounded to bfloat16 (round to nearest even) before
   use; the hidden-layer products (layers 2..L-1 and the output layer) round
   their activation operand h to bfloat16, and the backward products round
-  dz to bfloat16; the first layer (5 inputs), the biases, the activation
+  dz to bfloat16; the first layer's inputs (the features), the biases, the activation
   function, the loss and the bias gradients are not rounded.  The gradient
   in this mode is the straight-through one (rounding treated as identity).
 
@@ -37,7 +37,9 @@ from typing import List, Sequence, Tuple
 
 import numpy as np
 
-WIDTHS = (5, 256, 256, 256, 256, 1)
+N_FREQ = 8
+N_IN = 5 + 4 * N_FREQ + 12
+WIDTHS = (N_IN, 256, 256, 256, 256, 1)
 
 
 def n_params(widths: Sequence[int] = WIDTHS) -> int:
@@ -181,13 +183,34 @@ def train(theta, X, t, order, batch, lr0, lr1, widths=WIDTHS, bf16=False):
 # ---------------------------------------------------------------------------
 # surrogate input / output scaling
 # ---------------------------------------------------------------------------
-def encode(qw: np.ndarray, q_max: float, w_max: float) -> np.ndarray:
-    """Features of queries qw[n] = (Qx, Qy, Qz, w): (2|Q|/q_max - 1, Q/|Q|,
-    2 w/w_max - 1); the direction of Q = 0 is taken as (0, 0, 0)."""
-    Q = np.asarray(qw, np.float64)[:, :3]
+def frequencies(n: int = N_FREQ) -> np.ndarray:
+    """pi 2^(j/2), j < n: the angular frequencies of the Fourier features
+    (per unit of the scaled variable w/w_max or |Q|/q_max)."""
+    return np.array([math.pi * (math.sqrt(2.0) if j % 2 else 1.0) * 2 ** (j // 2) for j in range(n)])
+
+
+def encode(qw: np.ndarray, q_max: float, w_max: float, lattice) -> np.ndarray:
+    """Features of queries qw[n] = (Qx, Qy, Qz, w) (the surrogate's own
+    choice, not the paper's):
+      2|Q|/q_max - 1;  Q/|Q| (zero for Q = 0);  2 w/w_max - 1;
+      sin, cos of f_j w/w_max;  sin, cos of f_j |Q|/q_max  (f = frequencies());
+      sin, cos of h Q.a_i for the primitive vectors a_i (rows of lattice) and
+      h = 1, 2, which are unchanged by Q -> Q + any reciprocal lattice vector."""
+    qw = np.asarray(qw, np.float64)
+    Q, w = qw[:, :3], qw[:, 3]
     q = np.linalg.norm(Q, axis=1)
     d = np.where(q[:, None] > 0, Q / np.where(q > 0, q, 1.0)[:, None], 0.0)
-    return np.column_stack([2 * q / q_max - 1, d, 2 * np.asarray(qw)[:, 3] / w_max - 1])
+    cols = [2 * q / q_max - 1, d[:, 0], d[:, 1], d[:, 2], 2 * w / w_max - 1]
+    for f in frequencies():
+        cols += [np.sin(f * w / w_max), np.cos(f * w / w_max)]
+    for f in frequencies():
+        cols += [np.sin(f * q / q_max), np.cos(f * q / q_max)]
+    A = np.asarray(lattice, np.float64).reshape(3, 3)
+    for i in range(3):
+        ph = Q @ A[i]
+        for h in (1, 2):
+            cols += [np.sin(h * ph), np.cos(h * ph)]
+    return np.column_stack(cols)
 
 
 def target(loss: np.ndarray, mu: float, sigma: float) -> np.ndarray:

@@ -64,19 +64,21 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const uint16_t* __restrict__ A,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = tid >> 2, lk = (tid & 3) * 8;
-  const uint16_t* pa = A + (size_t)(m0 + lr) * K + lk;
-  const uint16_t* pb = B + (size_t)(n0 + lr) * K + lk;
+  // K range of this block: split z of gridDim.z (EPI_STORE only; 1 otherwise)
+  const int kper = K / gridDim.z, kb = blockIdx.z * kper, ke = kb + kper;
+  const uint16_t* pa = A + (size_t)(m0 + lr) * K + kb + lk;
+  const uint16_t* pb = B + (size_t)(n0 + lr) * K + kb + lk;
   f32x16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
   uint4 ra = *reinterpret_cast<const uint4*>(pa);
   uint4 rb = *reinterpret_cast<const uint4*>(pb);
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  for (int k0 = 0; k0 < ke - kb; k0 += 32) {
     __syncthreads();
     *reinterpret_cast<uint4*>(sA + lr * LDK + lk) = ra;
     *reinterpret_cast<uint4*>(sB + lr * LDK + lk) = rb;
     __syncthreads();
-    if (k0 + 32 < K) {  // prefetch the next K step while this one computes
+    if (k0 + 32 < ke - kb) {  // prefetch the next K step while this one computes
       ra = *reinterpret_cast<const uint4*>(pa + k0 + 32);
       rb = *reinterpret_cast<const uint4*>(pb + k0 + 32);
     }
@@ -94,8 +96,9 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const uint16_t* __restrict__ A,
   for (int g = 0; g < 4; ++g) {
     const int mb = m0 + wm + 8 * g + 4 * (lane >> 5);  // rows mb .. mb+3
     if constexpr (EPI == EPI_STORE) {
+      float* C = e.C + (size_t)blockIdx.z * M * N;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) e.C[(size_t)(mb + i) * N + n] = acc[4 * g + i];
+      for (int i = 0; i < 4; ++i) C[(size_t)(mb + i) * N + n] = acc[4 * g + i];
     } else if constexpr (EPI == EPI_FWD) {
       const float bias = e.f.bias[n];
       uint16_t hb[4];
@@ -141,14 +144,14 @@ __global__ void __launch_bounds__(256) k_layer1(const float* __restrict__ x,
                                                 uint16_t* H1b, uint16_t* H1T, int ldt) {
   __shared__ float sx[L1_ROWS][kIn];
   const int j = threadIdx.x, r0 = blockIdx.x * L1_ROWS;
-  if (j < L1_ROWS * kIn) {
-    const int r = r0 + j / kIn, c = j % kIn;
+  for (int e = j; e < L1_ROWS * kIn; e += 256) {
+    const int r = r0 + e / kIn, c = e % kIn;
     float v = 0.0f;
     if (r < n) {
       const long src = order ? (long)order[off + r] : (long)r;
       v = x[src * kIn + c];
     }
-    sx[j / kIn][c] = v;
+    sx[e / kIn][c] = v;
   }
   __syncthreads();
   float w[kIn];
@@ -246,54 +249,62 @@ __global__ void __launch_bounds__(256) k_output(const uint16_t* __restrict__ H4b
 // column reductions over the batch (deterministic: fixed per-thread strides,
 // fixed LDS tree).  Block = 256 threads = 4 row streams x 64 columns.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ A, int rows, int cols,
-                                                float* out) {
+// Column sums over rows run in two stages, so that a batch of thousands of
+// rows spreads over hundreds of blocks and the result does not depend on
+// timing: blocks of kRedRows rows write one partial per column, then the
+// partials are added in chunk order.
+//   P[ch][c] = sum over rows r of chunk ch of A[r][c]
+__global__ void __launch_bounds__(256) k_colsum_part(const float* __restrict__ A, int rows, int cols,
+                                                     float* P) {
   __shared__ float part[4][64];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), s = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * kRedRows, r1 = min(rows, r0 + kRedRows);
   float acc = 0.0f;
   if (c < cols)
-    for (int r = s; r < rows; r += 4) acc += A[(size_t)r * cols + c];
+    for (int r = r0 + s; r < r1; r += 4) acc += A[(size_t)r * cols + c];
   part[s][threadIdx.x & 63] = acc;
   __syncthreads();
   if (s == 0 && c < cols)
-    out[c] = (part[0][threadIdx.x] + part[1][threadIdx.x]) +
-             (part[2][threadIdx.x] + part[3][threadIdx.x]);
+    P[(size_t)blockIdx.y * cols + c] = (part[0][threadIdx.x] + part[1][threadIdx.x]) +
+                                       (part[2][threadIdx.x] + part[3][threadIdx.x]);
 }
 
-__global__ void __launch_bounds__(256) k_out_grad(const uint16_t* __restrict__ H4b,
-                                                  const float* __restrict__ dy, int rows,
-                                                  float* dw5, float* db5) {
-  __shared__ float part[4][64];
+// P[ch][c] = sum over chunk rows of dy[r] bf16(h4)[r][c] for c < kW, and
+// P[ch][kW] = sum of dy[r]
+__global__ void __launch_bounds__(256) k_out_grad_part(const uint16_t* __restrict__ H4b,
+                                                       const float* __restrict__ dy, int rows,
+                                                       float* P) {
+  __shared__ float part[4][64], partb[4];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), s = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * kRedRows, r1 = min(rows, r0 + kRedRows);
   float acc = 0.0f, accb = 0.0f;
-  for (int r = s; r < rows; r += 4) {
+  for (int r = r0 + s; r < r1; r += 4) {
     const float d = dy[r];
     acc += d * from_bf16(H4b[(size_t)r * kW + c]);
     accb += d;
   }
   part[s][threadIdx.x & 63] = acc;
+  if ((threadIdx.x & 63) == 0) partb[s] = accb;
   __syncthreads();
+  float* Pc = P + (size_t)blockIdx.y * (kW + 1);
   if (s == 0)
-    dw5[c] = (part[0][threadIdx.x] + part[1][threadIdx.x]) +
-             (part[2][threadIdx.x] + part[3][threadIdx.x]);
-  if (blockIdx.x == 0) {
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) part[s][0] = accb;
-    __syncthreads();
-    if (threadIdx.x == 0) db5[0] = (part[0][0] + part[1][0]) + (part[2][0] + part[3][0]);
-  }
+    Pc[c] = (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) Pc[kW] = (partb[0] + partb[1]) + (partb[2] + partb[3]);
 }
 
-__global__ void __launch_bounds__(256) k_w1_grad(const float* __restrict__ dZ1,
-                                                 const float* __restrict__ x,
-                                                 const int* __restrict__ order, long off, int n,
-                                                 float* dW1, float* db1) {
+// P[ch][c][i] = sum over chunk rows of dz1[r][c] x[idx(r)][i] for i < kIn,
+// P[ch][c][kIn] = sum of dz1[r][c]
+__global__ void __launch_bounds__(256) k_w1_grad_part(const float* __restrict__ dZ1,
+                                                      const float* __restrict__ x,
+                                                      const int* __restrict__ order, long off,
+                                                      int n, float* P) {
   __shared__ float part[4][64][kIn + 1];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), s = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * kRedRows, r1 = min(n, r0 + kRedRows);
   float acc[kIn + 1];
 #pragma unroll
   for (int i = 0; i <= kIn; ++i) acc[i] = 0.0f;
-  for (int r = s; r < n; r += 4) {
+  for (int r = r0 + s; r < r1; r += 4) {
     const float d = dZ1[(size_t)r * kW + c];
     const long src = order ? (long)order[off + r] : (long)r;
 #pragma unroll
@@ -303,16 +314,40 @@ __global__ void __launch_bounds__(256) k_w1_grad(const float* __restrict__ dZ1,
 #pragma unroll
   for (int i = 0; i <= kIn; ++i) part[s][threadIdx.x & 63][i] = acc[i];
   __syncthreads();
-  if (s == 0) {
-    const int cc = threadIdx.x;
+  float* Pc = P + (size_t)blockIdx.y * kW * (kIn + 1);
+  for (int e = threadIdx.x; e < 64 * (kIn + 1); e += 256) {
+    const int cc = e / (kIn + 1), i = e % (kIn + 1);
+    Pc[(size_t)(blockIdx.x * 64 + cc) * (kIn + 1) + i] =
+        (part[0][cc][i] + part[1][cc][i]) + (part[2][cc][i] + part[3][cc][i]);
+  }
+}
+
+// out_j = sum over chunks of P[ch][j], in chunk order.  With stride = 0 it
+// goes to out_a[j]; with stride > 0 the partial rows hold groups of stride
+// values (c, i): i < stride - 1 goes to out_a[c (stride - 1) + i] and the
+// last of each group to out_b[c] (a weight block and its bias).
+__global__ void k_sum_parts(const float* __restrict__ P, int n_ch, int n, int stride, float* out_a,
+                            float* out_b) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  float acc = 0.0f;
+  int ch = 0;
+  for (; ch + 8 <= n_ch; ch += 8) {  // eight loads in flight, added in order
+    float v[8];
 #pragma unroll
-    for (int i = 0; i <= kIn; ++i) {
-      const float v = (part[0][cc][i] + part[1][cc][i]) + (part[2][cc][i] + part[3][cc][i]);
-      if (i < kIn)
-        dW1[c * kIn + i] = v;
-      else
-        db1[c] = v;
-    }
+    for (int u = 0; u < 8; ++u) v[u] = P[(size_t)(ch + u) * n + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; ch < n_ch; ++ch) acc += P[(size_t)ch * n + j];
+  if (stride > 0) {
+    const int c = j / stride, i = j % stride;
+    if (i < stride - 1)
+      out_a[c * (stride - 1) + i] = acc;
+    else
+      out_b[c] = acc;
+  } else {
+    out_a[j] = acc;
   }
 }
 
@@ -357,18 +392,54 @@ __global__ void __launch_bounds__(256) k_mean(const float* __restrict__ sq, int 
   if (threadIdx.x == 0) out[0] = part[0] / (float)n;
 }
 
+// Features of a query (Q, w), computed in FP64 and rounded to FP32:
+//   0      2|Q|/q_max - 1
+//   1..3   Q/|Q| (zero for Q = 0)
+//   4      2w/w_max - 1
+//   then for j < kNFreq: sin, cos of pi 2^(j/2) w / w_max,
+//   then for j < kNFreq: sin, cos of pi 2^(j/2) |Q| / q_max,
+//   then for each primitive vector a_i and h = 1, 2: sin, cos of h Q.a_i.
+// The last twelve are periodic under Q -> Q + any reciprocal lattice vector,
+// which is how the loss of a crystal depends on the part of Q inside the
+// zone; the Fourier features give the first layer scales finer than the
+// plain coordinates.
 __global__ void k_encode(const double* __restrict__ qw, const double* __restrict__ loss, int n,
-                         double qmax, double wmax, double mu, double sigma, float* x, float* t) {
+                         double qmax, double wmax, Lattice lat, double mu, double sigma, float* x,
+                         float* t) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double qx = qw[4 * i], qy = qw[4 * i + 1], qz = qw[4 * i + 2], w = qw[4 * i + 3];
   const double q = sqrt(qx * qx + qy * qy + qz * qz);
   const double inv = q > 0.0 ? 1.0 / q : 0.0;
-  x[kIn * i + 0] = (float)(2.0 * q / qmax - 1.0);
-  x[kIn * i + 1] = (float)(qx * inv);
-  x[kIn * i + 2] = (float)(qy * inv);
-  x[kIn * i + 3] = (float)(qz * inv);
-  x[kIn * i + 4] = (float)(2.0 * w / wmax - 1.0);
+  float* xi = x + (size_t)kIn * i;
+  xi[0] = (float)(2.0 * q / qmax - 1.0);
+  xi[1] = (float)(qx * inv);
+  xi[2] = (float)(qy * inv);
+  xi[3] = (float)(qz * inv);
+  xi[4] = (float)(2.0 * w / wmax - 1.0);
+  const double pi = 3.141592653589793;
+  int c = 5;
+#pragma unroll
+  for (int j = 0; j < kNFreq; ++j) {
+    const double f = pi * ((j & 1) ? 1.4142135623730951 : 1.0) * (double)(1 << (j >> 1));
+    xi[c++] = (float)sin(f * w / wmax);
+    xi[c++] = (float)cos(f * w / wmax);
+  }
+#pragma unroll
+  for (int j = 0; j < kNFreq; ++j) {
+    const double f = pi * ((j & 1) ? 1.4142135623730951 : 1.0) * (double)(1 << (j >> 1));
+    xi[c++] = (float)sin(f * q / qmax);
+    xi[c++] = (float)cos(f * q / qmax);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double ph = qx * lat.a[3 * a] + qy * lat.a[3 * a + 1] + qz * lat.a[3 * a + 2];
+#pragma unroll
+    for (int h = 1; h <= 2; ++h) {
+      xi[c++] = (float)sin(h * ph);
+      xi[c++] = (float)cos(h * ph);
+    }
+  }
   if (loss && t) t[i] = (float)((log(fmax(loss[i], 1e-30)) - mu) / sigma);
 }
 
@@ -449,8 +520,9 @@ __global__ void __launch_bounds__(SEL_BLOCK) k_select_write(const double* __rest
 // ------------------------------------------------------------------ launchers
 template <int EPI>
 static void gemm(const uint16_t* A, const uint16_t* B, int M, int N, int K, const EpiAll& e,
-                 hipStream_t st) {
-  hipLaunchKernelGGL(k_gemm_nt<EPI>, dim3(N / 64, M / 64), dim3(256), 0, st, A, B, M, N, K, e);
+                 hipStream_t st, int ksplit = 1) {
+  hipLaunchKernelGGL(k_gemm_nt<EPI>, dim3(N / 64, M / 64, ksplit), dim3(256), 0, st, A, B, M, N, K,
+                     e);
 }
 
 void launch_gemm_fwd(const uint16_t* A, const uint16_t* B, int M, int N, int K, const EpiFwd& f,
@@ -465,11 +537,21 @@ void launch_gemm_bwd(const uint16_t* A, const uint16_t* B, int M, int N, int K, 
   e.b = b;
   gemm<EPI_BWD>(A, B, M, N, K, e, st);
 }
+int store_ksplit(int K) {
+  int ks = 1;  // at least 8 K steps of 32 per split, K / ks a multiple of 32
+  while (ks < 16 && K % (64 * ks) == 0 && K / (2 * ks) >= 256) ks *= 2;
+  return ks;
+}
+
 void launch_gemm_store(const uint16_t* A, const uint16_t* B, int M, int N, int K, float* C,
-                       hipStream_t st) {
+                       float* P, hipStream_t st) {
   EpiAll e{};
-  e.C = C;
-  gemm<EPI_STORE>(A, B, M, N, K, e, st);
+  const int ks = store_ksplit(K);
+  e.C = ks > 1 ? P : C;
+  gemm<EPI_STORE>(A, B, M, N, K, e, st, ks);
+  if (ks > 1)
+    hipLaunchKernelGGL(k_sum_parts, dim3((M * N + 255) / 256), dim3(256), 0, st, P, ks, M * N, 0, C,
+                       nullptr);
 }
 
 void launch_layer1(const float* x, const int* order, long off, int n, int rows_p,
@@ -487,18 +569,33 @@ void launch_output(const uint16_t* H4b, const uint16_t* w5b, const float* b5, in
                      order, off, dy, sq, Z4, dZ, dZb, dZbT, ldt);
 }
 
-void launch_colsum(const float* A, int rows, int cols, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_colsum, dim3((cols + 63) / 64), dim3(256), 0, st, A, rows, cols, out);
+int red_chunks(int rows) { return (rows + kRedRows - 1) / kRedRows; }
+
+size_t red_floats(int rows) { return (size_t)red_chunks(rows) * kW * (kIn + 1); }
+
+void launch_colsum(const float* A, int rows, int cols, float* out, float* P, hipStream_t st) {
+  const int nch = red_chunks(rows);
+  hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, nch), dim3(256), 0, st, A, rows, cols, P);
+  hipLaunchKernelGGL(k_sum_parts, dim3((cols + 255) / 256), dim3(256), 0, st, P, nch, cols, 0, out,
+                     nullptr);
 }
 
 void launch_out_grad(const uint16_t* H4b, const float* dy, int rows, float* dw5, float* db5,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_out_grad, dim3(kW / 64), dim3(256), 0, st, H4b, dy, rows, dw5, db5);
+                     float* P, hipStream_t st) {
+  const int nch = red_chunks(rows);
+  hipLaunchKernelGGL(k_out_grad_part, dim3(kW / 64, nch), dim3(256), 0, st, H4b, dy, rows, P);
+  // dw5 (kW values) then db5: one row of kW + 1 per chunk, the last element to db5
+  hipLaunchKernelGGL(k_sum_parts, dim3((kW + 1 + 255) / 256), dim3(256), 0, st, P, nch, kW + 1,
+                     kW + 1, dw5, db5);
 }
 
 void launch_w1_grad(const float* dZ1, const float* x, const int* order, long off, int n,
-                    float* dW1, float* db1, hipStream_t st) {
-  hipLaunchKernelGGL(k_w1_grad, dim3(kW / 64), dim3(256), 0, st, dZ1, x, order, off, n, dW1, db1);
+                    float* dW1, float* db1, float* P, hipStream_t st) {
+  const int nch = red_chunks(n);
+  hipLaunchKernelGGL(k_w1_grad_part, dim3(kW / 64, nch), dim3(256), 0, st, dZ1, x, order, off, n, P);
+  const int tot = kW * (kIn + 1);
+  hipLaunchKernelGGL(k_sum_parts, dim3((tot + 255) / 256), dim3(256), 0, st, P, nch, tot, kIn + 1,
+                     dW1, db1);
 }
 
 void launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float beta1,
@@ -516,9 +613,10 @@ void launch_mean(const float* sq, int rows, int n, float* out, hipStream_t st) {
 }
 
 void launch_encode(const double* qw, const double* loss, int n, double qmax, double wmax,
-                   double mu, double sigma, float* x, float* t, hipStream_t st) {
+                   const Lattice& lat, double mu, double sigma, float* x, float* t,
+                   hipStream_t st) {
   hipLaunchKernelGGL(k_encode, dim3((n + 255) / 256), dim3(256), 0, st, qw, loss, n, qmax, wmax,
-                     mu, sigma, x, t);
+                     lat, mu, sigma, x, t);
 }
 
 void launch_decode(const float* ys, int K, int n, double mu, double sigma, double calib,

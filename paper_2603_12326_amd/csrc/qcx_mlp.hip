@@ -1,8 +1,11 @@
 // C ABI of the loss surrogate (include/qcx.h, "Surrogate"): an ensemble of
-// 5 -> 256x4 -> 1 SiLU networks trained and evaluated by the kernels of
+// 49 -> 256x4 -> 1 SiLU networks trained and evaluated by the kernels of
 // k_mlp.hip on the owning context's device and stream.
 #include "ctx.h"
 #include "mlp.h"
+
+static_assert(qcx::mlp::kIn == QCX_MLP_NIN && qcx::mlp::kNParam == QCX_MLP_NPARAM,
+              "network shape of the C ABI");
 
 using namespace qcx::mlp;
 
@@ -38,22 +41,48 @@ struct qcx_mlp {
   std::vector<Member> mem;
   // training workspace (rows_p = batch padded to 64)
   int cap_rows = 0;
-  DevBuf Z[4], Hb[4], HT[3], dZ[2], dZb[2], dZbT[2], y, dy, sq, hist, flag;
+  DevBuf Z[4], Hb[4], HT[3], dZ[2], dZb[2], dZbT[2], y, dy, sq, hist, flag, red;
   // inference / query workspace
   DevBuf xq, ys, sel_counts;
+  // qcx_mlp_infer: Q list, frequencies, the query grid, estimates, rejected
+  // indices, the method's rows and where they go
+  DevBuf iQ, iw, iqw, ierr, iidx, irows, isel;
   int cap_query = 0;
   double qmax = 1.0, wmax = 1.0, mu = 0.0, sigma = 1.0, calib = 1.0;
+  Lattice lat{};
   bool have_encoding = false;
   ~qcx_mlp() {
     for (Member& m : mem) m.release();
     DevBuf* all[] = {&Z[0], &Z[1], &Z[2], &Z[3], &Hb[0], &Hb[1], &Hb[2], &Hb[3], &HT[0], &HT[1],
                      &HT[2], &dZ[0], &dZ[1], &dZb[0], &dZb[1], &dZbT[0], &dZbT[1], &y, &dy, &sq,
-                     &hist, &flag, &xq, &ys, &sel_counts};
+                     &hist, &flag, &red, &xq, &ys, &sel_counts, &iQ, &iw, &iqw, &ierr, &iidx, &irows,
+                     &isel};
     for (DevBuf* b : all) b->release();
   }
 };
 
 namespace {
+
+// qw[(iw, g)] = (Q_g, w_iw): the query grid of one momentum, w-major.
+__global__ void k_fill_qw(const double* __restrict__ Q, int n_g, const double* __restrict__ w,
+                          int n_w, double* qw) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_g * n_w) return;
+  const int g = (int)(i % n_g), iw = (int)(i / n_g);
+  qw[4 * i] = Q[3 * g];
+  qw[4 * i + 1] = Q[3 * g + 1];
+  qw[4 * i + 2] = Q[3 * g + 2];
+  qw[4 * i + 3] = w[iw];
+}
+
+// out[sel[r]][g] = rows[r][g]: the method's rows into the answer.
+__global__ void k_scatter_rows(const double* __restrict__ rows, const int* __restrict__ sel,
+                               int n_sel, int n_g, double* out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_sel * n_g) return;
+  const int r = (int)(i / n_g), g = (int)(i % n_g);
+  out[(size_t)sel[r] * n_g + g] = rows[i];
+}
 
 int reserve_rows(qcx_mlp* m, int rows_p, bool training) {
   qcx_ctx* ctx = m->ctx;
@@ -71,6 +100,8 @@ int reserve_rows(qcx_mlp* m, int rows_p, bool training) {
     }
     HIPCK(m->dy.reserve(sizeof(float) * r));
     HIPCK(m->sq.reserve(sizeof(float) * r));
+    HIPCK(m->red.reserve(sizeof(float) * std::max(red_floats(rows_p),
+                                                   (size_t)store_ksplit(rows_p) * kW * kW)));
   }
   HIPCK(m->y.reserve(sizeof(float) * r));
   return QCX_OK;
@@ -108,13 +139,15 @@ void grad_rows(qcx_mlp* m, Member& w, const float* x, const float* t, const int*
   launch_output(m->Hb[3].as<uint16_t>(), wb.w5, p + kOffB5, n, rows_p, m->y.as<float>(), t, order,
                 off, m->dy.as<float>(), m->sq.as<float>(), m->Z[3].as<float>(), m->dZ[0].as<float>(),
                 m->dZb[0].as<uint16_t>(), m->dZbT[0].as<uint16_t>(), rows_p, st);
-  launch_out_grad(m->Hb[3].as<uint16_t>(), m->dy.as<float>(), rows_p, g + kOffW5, g + kOffB5, st);
+  float* red = m->red.as<float>();
+  launch_out_grad(m->Hb[3].as<uint16_t>(), m->dy.as<float>(), rows_p, g + kOffW5, g + kOffB5, red,
+                  st);
   int s = 0;  // dZ set holding dz of the current layer
   for (int l = 4; l >= 2; --l) {
     // weight gradient dW_l = bf16(dz_l)^T bf16(h_{l-1}), bias gradient sum dz_l
     launch_gemm_store(m->dZbT[s].as<uint16_t>(), m->HT[l - 2].as<uint16_t>(), kW, kW, rows_p,
-                      g + off_w(l), st);
-    launch_colsum(m->dZ[s].as<float>(), rows_p, kW, g + off_b(l), st);
+                      g + off_w(l), red, st);
+    launch_colsum(m->dZ[s].as<float>(), rows_p, kW, g + off_b(l), red, st);
     EpiBwd e;
     e.Zprev = m->Z[l - 2].as<float>();
     e.dZ = m->dZ[1 - s].as<float>();
@@ -124,7 +157,7 @@ void grad_rows(qcx_mlp* m, Member& w, const float* x, const float* t, const int*
     launch_gemm_bwd(m->dZb[s].as<uint16_t>(), wb.wt[l - 2], rows_p, kW, kW, e, st);
     s = 1 - s;
   }
-  launch_w1_grad(m->dZ[s].as<float>(), x, order, off, n, g + kOffW1, g + kOffB1, st);
+  launch_w1_grad(m->dZ[s].as<float>(), x, order, off, n, g + kOffW1, g + kOffB1, red, st);
   launch_mean(m->sq.as<float>(), rows_p, n, loss_dev, st);
 }
 
@@ -305,12 +338,16 @@ int qcx_mlp_train(qcx_mlp* m, int member, int n_data, const float* x, const floa
   return QCX_OK;
 }
 
-int qcx_mlp_set_encoding(qcx_mlp* m, double q_max, double w_max_eV, double mu, double sigma,
-                         double calib) {
+int qcx_mlp_set_encoding(qcx_mlp* m, double q_max, double w_max_eV, const double* lattice,
+                         double mu, double sigma, double calib) {
   if (!m) return QCX_EINVAL;
   if (!(q_max > 0.0) || !(w_max_eV > 0.0) || !(sigma > 0.0) || !(calib >= 0.0) ||
-      !std::isfinite(mu))
+      !std::isfinite(mu) || !lattice)
     return fail(m->ctx, QCX_EINVAL, "bad encoding constants");
+  for (int i = 0; i < 9; ++i) {
+    if (!std::isfinite(lattice[i])) return fail(m->ctx, QCX_EINVAL, "non-finite lattice");
+    m->lat.a[i] = lattice[i];
+  }
   m->qmax = q_max;
   m->wmax = w_max_eV;
   m->mu = mu;
@@ -327,7 +364,7 @@ int qcx_mlp_encode(qcx_mlp* m, int n, const double* qw, const double* loss, floa
   if (n < 0 || (n > 0 && (!qw || !x))) return fail(ctx, QCX_EINVAL, "bad n or NULL buffer");
   if (n == 0) return QCX_OK;
   HIPCK(hipSetDevice(ctx->device));
-  launch_encode(qw, loss, n, m->qmax, m->wmax, m->mu, m->sigma, x, t, ctx->stream);
+  launch_encode(qw, loss, n, m->qmax, m->wmax, m->lat, m->mu, m->sigma, x, t, ctx->stream);
   LAUNCHCK("encode");
   return QCX_OK;
 }
@@ -347,7 +384,8 @@ int qcx_mlp_query(qcx_mlp* m, int n, const double* qw, double* loss, double* err
   const int K = (int)m->mem.size();
   HIPCK(m->xq.reserve(sizeof(float) * kIn * (size_t)n));
   HIPCK(m->ys.reserve(sizeof(float) * (size_t)K * n));
-  launch_encode(qw, nullptr, n, m->qmax, m->wmax, m->mu, m->sigma, m->xq.as<float>(), nullptr, st);
+  launch_encode(qw, nullptr, n, m->qmax, m->wmax, m->lat, m->mu, m->sigma, m->xq.as<float>(),
+                nullptr, st);
   for (int k = 0; k < K; ++k)
     for (int r0 = 0; r0 < n; r0 += kInferChunk) {
       const int nn = std::min(kInferChunk, n - r0), rp = rows_padded(nn);
@@ -366,6 +404,84 @@ int qcx_mlp_query(qcx_mlp* m, int n, const double* qw, double* loss, double* err
     HIPCK(hipMemcpyAsync(n_reject, counts + nb, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
   }
+  return QCX_OK;
+}
+
+// Surrogate answer for the momentum of ctx's states with fallback to the
+// method (include/qcx.h): the networks answer every (w, q + G); the
+// frequencies with any rejected point are recomputed by the method's own
+// calls on ctx and their rows replaced.
+int qcx_mlp_infer(qcx_mlp* m, qcx_ctx* ctx, int n_G, const int* G_int, int n_w,
+                  const double* w_eV, double eta_eV, double tol, int precision, double* loss_out,
+                  double* err_out, int* n_fallback) {
+  if (!m || !ctx) return QCX_EINVAL;
+  qcx_ctx* mc = m->ctx;
+  if (n_fallback) *n_fallback = 0;
+  if (mc->device != ctx->device) return fail(ctx, QCX_EINVAL, "networks and context on different devices");
+  if (!m->have_encoding) return fail(ctx, QCX_ESTATE, "qcx_mlp_set_encoding first");
+  if (!ctx->have_states) return fail(ctx, QCX_ESTATE, "set_states first");
+  if (n_G < 1 || n_G > 4096 || !G_int) return fail(ctx, QCX_EINVAL, "need 1 <= n_G <= 4096");
+  if (G_int[0] != 0 || G_int[1] != 0 || G_int[2] != 0)
+    return fail(ctx, QCX_EINVAL, "G_int[0] must be (0,0,0)");
+  if (n_w < 1 || n_w > 65536 || !w_eV) return fail(ctx, QCX_EINVAL, "need 1 <= n_w <= 65536");
+  if ((long)n_w * n_G > (1L << 26)) return fail(ctx, QCX_EINVAL, "n_w * n_G above 2^26");
+  for (int i = 0; i < n_w; ++i)
+    if (!std::isfinite(w_eV[i])) return fail(ctx, QCX_EINVAL, "non-finite frequency");
+  if (!(eta_eV >= 0.0) || !std::isfinite(eta_eV)) return fail(ctx, QCX_EINVAL, "eta must be >= 0");
+  if (!(tol >= 0.0)) return fail(ctx, QCX_EINVAL, "tol must be >= 0");
+  if (precision < QCX_FP64 || precision > QCX_SPLIT_BF16) return fail(ctx, QCX_EINVAL, "bad precision");
+  if (!loss_out) return fail(ctx, QCX_EINVAL, "loss_out must be a device buffer");
+  if (int rc = reject_capture(ctx)) return rc;
+  if (int rc = reject_capture(mc)) return rc;
+  HIPCK(hipSetDevice(ctx->device));
+  // Q = q + G as qcx_pair_density forms it
+  std::vector<double> Q(3 * (size_t)n_G);
+  for (int g = 0; g < n_G; ++g)
+    for (int x = 0; x < 3; ++x) {
+      double v = ctx->q[x];
+      for (int j = 0; j < 3; ++j) v += G_int[3 * g + j] * ctx->rec[3 * j + x];
+      Q[3 * g + x] = v;
+    }
+  const size_t n = (size_t)n_w * n_G;
+  hipStream_t ms = mc->stream;
+  HIPCK(stage_begin(mc));
+  HIPCK(upload(mc, m->iQ, Q.data(), Q.size()));
+  HIPCK(upload(mc, m->iw, w_eV, (size_t)n_w));
+  HIPCK(m->iqw.reserve(sizeof(double) * 4 * n));
+  HIPCK(m->iidx.reserve(sizeof(int) * n));
+  double* err = err_out;
+  if (!err) {
+    HIPCK(m->ierr.reserve(sizeof(double) * n));
+    err = m->ierr.as<double>();
+  }
+  hipLaunchKernelGGL(k_fill_qw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ms,
+                     m->iQ.as<double>(), n_G, m->iw.as<double>(), n_w, m->iqw.as<double>());
+  LAUNCHCK("infer grid");
+  int nrej = 0;
+  if (int rc = qcx_mlp_query(m, (int)n, m->iqw.as<double>(), loss_out, err, tol, m->iidx.as<int>(), &nrej))
+    return rc;  // synchronous: the answers and rejections are complete
+  if (nrej == 0) return QCX_OK;
+  // frequencies with any rejected point (indices ascend, rows are w-major)
+  std::vector<int> idx(nrej), sel;
+  HIPCK(hipMemcpy(idx.data(), m->iidx.p, sizeof(int) * nrej, hipMemcpyDeviceToHost));
+  for (int i : idx)
+    if (sel.empty() || sel.back() != i / n_G) sel.push_back(i / n_G);
+  std::vector<double> wsel(sel.size());
+  for (size_t r = 0; r < sel.size(); ++r) wsel[r] = w_eV[sel[r]];
+  const int ns = (int)sel.size();
+  if (int rc = qcx_pair_density(ctx, n_G, G_int, nullptr)) return rc;
+  if (int rc = qcx_chi0(ctx, ns, wsel.data(), eta_eV, precision, 1, nullptr)) return rc;
+  if (int rc = qcx_eps_inv(ctx, 1, nullptr, nullptr)) return rc;
+  HIPCK(m->irows.reserve(sizeof(double) * (size_t)ns * n_G));
+  if (int rc = qcx_loss(ctx, m->irows.as<double>(), QCX_MEM_DEVICE)) return rc;
+  HIPCK(stage_begin(ctx));
+  HIPCK(upload(ctx, m->isel, sel.data(), sel.size()));
+  const size_t nr = (size_t)ns * n_G;
+  hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, ctx->stream,
+                     m->irows.as<double>(), m->isel.as<int>(), ns, n_G, loss_out);
+  LAUNCHCK("infer fallback rows");
+  if (int rc = qcx_sync(ctx)) return rc;  // deferred checks and a singular eps of these rows
+  if (n_fallback) *n_fallback = ns;
   return QCX_OK;
 }
 

@@ -76,9 +76,10 @@ _SIGS = {
     "qcx_mlp_forward": [_P, _I, _I, _P, _P],
     "qcx_mlp_grad": [_P, _I, _I, _P, _P, _P, _P],
     "qcx_mlp_train": [_P, _I, _I, _P, _P, _I, _I, _P, ctypes.c_float, ctypes.c_float, _P],
-    "qcx_mlp_set_encoding": [_P, _D, _D, _D, _D, _D],
+    "qcx_mlp_set_encoding": [_P, _D, _D, _P, _D, _D, _D],
     "qcx_mlp_encode": [_P, _I, _P, _P, _P, _P],
     "qcx_mlp_query": [_P, _I, _P, _P, _P, _D, _P, _P],
+    "qcx_mlp_infer": [_P, _P, _I, _P, _I, _P, _D, _D, _I, _P, _P, _P],
     "qcx_qbin_create": [ctypes.POINTER(_P), _P, _I, _I, _D, _I, _I],
     "qcx_qbin_destroy": [_P],
     "qcx_qbin_reset": [_P],
@@ -87,7 +88,8 @@ _SIGS = {
     "qcx_qbin_rate_halo": [_P, _P, _P, _P, _P],
 }
 QBIN_EPS, QBIN_INV = 0, 1
-MLP_NPARAM = 199169
+MLP_NIN = 49
+MLP_NPARAM = 210433
 
 
 class QcxHalo(ctypes.Structure):
@@ -448,7 +450,7 @@ class Mlp:
 
     def forward(self, member: int, x, y):
         n = x.shape[0]
-        self.ctx._check(self.lib.qcx_mlp_forward(self._h, member, n, _dev_ptr(x, "f32", n * 5, "x"),
+        self.ctx._check(self.lib.qcx_mlp_forward(self._h, member, n, _dev_ptr(x, "f32", n * MLP_NIN, "x"),
                                                  _dev_ptr(y, "f32", n, "y")))
         return y
 
@@ -456,7 +458,7 @@ class Mlp:
         n = x.shape[0]
         g = np.empty(MLP_NPARAM, np.float32)
         loss = ctypes.c_float()
-        self.ctx._check(self.lib.qcx_mlp_grad(self._h, member, n, _dev_ptr(x, "f32", n * 5, "x"),
+        self.ctx._check(self.lib.qcx_mlp_grad(self._h, member, n, _dev_ptr(x, "f32", n * MLP_NIN, "x"),
                                               _dev_ptr(t, "f32", n, "t"), _ptr_host(g),
                                               ctypes.byref(loss)))
         return g, loss.value
@@ -467,20 +469,24 @@ class Mlp:
         n_steps = order.numel() // batch
         hist = np.empty(n_steps, np.float32) if want_hist else None
         self.ctx._check(self.lib.qcx_mlp_train(
-            self._h, member, n, _dev_ptr(x, "f32", n * 5, "x"), _dev_ptr(t, "f32", n, "t"), batch,
+            self._h, member, n, _dev_ptr(x, "f32", n * MLP_NIN, "x"), _dev_ptr(t, "f32", n, "t"), batch,
             n_steps, _dev_ptr(order, "i32", order.numel(), "order"), float(lr0), float(lr1),
             _ptr_host(hist) if want_hist else None))
         return hist
 
-    def set_encoding(self, q_max, w_max_eV, mu, sigma, calib=1.0):
-        self.ctx._check(self.lib.qcx_mlp_set_encoding(self._h, q_max, w_max_eV, mu, sigma, calib))
+    def set_encoding(self, q_max, w_max_eV, lattice, mu, sigma, calib=1.0):
+        lat = _host(lattice, np.float64).reshape(-1)
+        if lat.size != 9:
+            raise ValueError("lattice: three primitive vectors (3 x 3)")
+        self.ctx._check(self.lib.qcx_mlp_set_encoding(self._h, q_max, w_max_eV, _ptr_host(lat), mu,
+                                                      sigma, calib))
 
     def encode(self, qw, loss=None, x=None, t=None):
         n = qw.shape[0]
         self.ctx._check(self.lib.qcx_mlp_encode(
             self._h, n, _dev_ptr(qw, "f64", n * 4, "qw"),
             None if loss is None else _dev_ptr(loss, "f64", n, "loss"),
-            _dev_ptr(x, "f32", n * 5, "x"), None if t is None else _dev_ptr(t, "f32", n, "t")))
+            _dev_ptr(x, "f32", n * MLP_NIN, "x"), None if t is None else _dev_ptr(t, "f32", n, "t")))
 
     def query(self, qw, loss, err=None, tol=None, reject_idx=None):
         """Returns the number of rejected points when reject_idx is given."""
@@ -494,6 +500,27 @@ class Mlp:
             _dev_ptr(reject_idx, "i32", n, "reject_idx") if rej else None,
             ctypes.byref(nrej) if rej else None))
         return nrej.value if rej else None
+
+    def infer(self, ctx: "Context", G_int, w_eV, eta_eV: float, tol: float, precision="split_bf16",
+              loss_out=None, err_out=None):
+        """Loss at (q + G, w) for the momentum of ctx's states with fallback
+        to the method (qcx_mlp_infer): (loss [n_w][n_G], err or None, number
+        of recomputed frequencies)."""
+        import torch
+
+        G = _host(G_int, np.int32).reshape(-1, 3)
+        w = _host(w_eV, np.float64).reshape(-1)
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        if loss_out is None:
+            loss_out = torch.empty((len(w), len(G)), dtype=torch.float64, device="cuda")
+        nfb = ctypes.c_int(0)
+        n = len(w) * len(G)
+        ctx._check(self.lib.qcx_mlp_infer(
+            self._h, ctx._h, len(G), _ptr_host(G), len(w), _ptr_host(w), float(eta_eV), float(tol),
+            int(precision), _dev_ptr(loss_out, "f64", n, "loss_out"),
+            None if err_out is None else _dev_ptr(err_out, "f64", n, "err_out"), ctypes.byref(nfb)))
+        return loss_out, err_out, nfb.value
 
 
 class QBins:

@@ -12,9 +12,11 @@ Sampling: for a momentum q and frequencies w_1..w_m, one pass of the method
 Q = q + G of the G set (Eq. eps_LFE: [eps^-1]_GG is the response at q + G),
 so each pass yields m * N_G samples ((Qx, Qy, Qz, w), L).
 
-Query with fallback: the networks answer every (Q, w); points whose error
-estimate exceeds the tolerance are recomputed by the method, one pass per
-distinct q with the distinct frequencies that were rejected for it.
+Query with fallback (qcx_mlp_infer, one call per momentum q): the networks
+answer every (Q, w); each frequency with a point whose error estimate
+exceeds the tolerance is recomputed by the method inside the library (one
+pass per q over the rejected frequencies), since the inverse of eps gives
+all G of a frequency at once.
 """
 from __future__ import annotations
 
@@ -88,25 +90,28 @@ class Surrogate:
         self.net = qcx.Mlp(ctx, n_members)
         self.K = n_members
         self.q_max = self.w_max = self.mu = self.sigma = None
+        self.lattice = None
         self.calib = 1.0
 
-    def fit(self, s: Samples, train_idx: np.ndarray, q_max: float, w_max: float,
+    def fit(self, s: Samples, train_idx: np.ndarray, q_max: float, w_max: float, lattice,
             init_params: Callable[[int], np.ndarray], orders: Callable[[int, int, int], np.ndarray],
             batch: int = 1024, epochs: int = 40, lr0: float = 2e-3, lr1: float = 2e-5):
-        """Train every member on the samples train_idx; init_params(k) gives
-        member k's initial parameters and orders(k, n, batch) its sample
-        order (indices into train_idx)."""
+        """Train every member on the samples train_idx; lattice (3 x 3, rows
+        the primitive vectors, bohr) sets the periodic features of the
+        encoding; init_params(k) gives member k's initial parameters and
+        orders(k, n, batch) its sample order (indices into train_idx)."""
         import torch
 
         tl = np.log(np.maximum(s.loss.cpu().numpy()[train_idx], 1e-30))
         self.q_max, self.w_max = float(q_max), float(w_max)
         self.mu, self.sigma = float(tl.mean()), float(tl.std())
-        self.net.set_encoding(self.q_max, self.w_max, self.mu, self.sigma, self.calib)
+        self.lattice = np.asarray(lattice, np.float64).reshape(3, 3)
+        self._encoding(self.calib)
         ti = torch.from_numpy(np.ascontiguousarray(train_idx)).cuda()
         qw = s.qw[ti].contiguous()
         loss = s.loss[ti].contiguous()
         n = len(train_idx)
-        x = torch.empty((n, 5), dtype=torch.float32, device="cuda")
+        x = torch.empty((n, qcx.MLP_NIN), dtype=torch.float32, device="cuda")
         t = torch.empty(n, dtype=torch.float32, device="cuda")
         self.net.encode(qw, loss, x, t)
         hists = []
@@ -124,7 +129,7 @@ class Surrogate:
         the held-out points idx at the given quantile."""
         import torch
 
-        self.net.set_encoding(self.q_max, self.w_max, self.mu, self.sigma, 1.0)
+        self._encoding(1.0)
         ii = torch.from_numpy(np.ascontiguousarray(idx)).cuda()
         qw = s.qw[ii].contiguous()
         L = torch.empty(len(idx), dtype=torch.float64, device="cuda")
@@ -135,8 +140,11 @@ class Surrogate:
         rel = np.abs(got / np.maximum(ref, 1e-300) - 1.0)
         ratio = rel / np.maximum(spread, 1e-12)
         self.calib = float(np.quantile(ratio, quantile))
-        self.net.set_encoding(self.q_max, self.w_max, self.mu, self.sigma, self.calib)
+        self._encoding(self.calib)
         return dict(rel_err=rel, spread=spread, calib=self.calib)
+
+    def _encoding(self, calib: float):
+        self.net.set_encoding(self.q_max, self.w_max, self.lattice, self.mu, self.sigma, calib)
 
     def query(self, qw, tol: Optional[float] = None):
         """Device (loss, err, reject indices or None, number rejected)."""
@@ -152,46 +160,39 @@ class Surrogate:
         nrej = self.net.query(qw, L, E, tol, idx)
         return L, E, idx[:nrej], nrej
 
+    def infer(self, ctx, G_int, w, eta_eV: float, tol: float, precision="split_bf16", err_out=None):
+        """qcx_mlp_infer for the momentum of ctx's states: (loss [n_w][n_G],
+        err, number of frequencies the method recomputed)."""
+        return self.net.infer(ctx, G_int, w, eta_eV, tol, precision, err_out=err_out)
+
     def close(self):
         self.net.close()
 
 
-def query_with_fallback(sur: Surrogate, ctx, set_states, q_list, G_int, lat, w_lists, eta_eV,
+def query_with_fallback(sur: Surrogate, ctx, set_states, n_q: int, G_int, w_lists, eta_eV,
                         tol: float, precision="split_bf16"):
-    """Answer every (q + G, w) of the grid (q_list x w_lists x G) with the
-    surrogate; recompute the rejected points with the method.  Returns
-    (loss per q as device [n_w][n_G] tensors, statistics)."""
+    """Answer every (q + G, w) of the grid (n_q momenta x w_lists x G) with
+    the surrogate and the method as fallback: for each momentum, set its
+    states (set_states(iq)) and call qcx_mlp_infer, which recomputes every
+    frequency row holding a rejected point.  Returns (loss per q as device
+    [n_w][n_G] tensors, statistics)."""
     import torch
 
-    Gc = g_cart(G_int, lat)
-    n_g = len(Gc)
+    n_g = len(G_int)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    blocks = [torch.from_numpy(query_points(q, Gc, w)).cuda() for q, w in zip(q_list, w_lists)]
-    qw = torch.cat(blocks)
-    L, E, rej, nrej = sur.query(qw, tol)
+    out, errs = [], []
+    n_rows = n_pass = 0
+    for iq in range(n_q):
+        set_states(iq)
+        E = torch.empty((len(w_lists[iq]), n_g), dtype=torch.float64, device="cuda")
+        L, _, nfb = sur.infer(ctx, G_int, w_lists[iq], eta_eV, tol, precision, err_out=E)
+        out.append(L)
+        errs.append(E.reshape(-1))
+        n_rows += nfb
+        n_pass += nfb > 0
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    # group rejected points by momentum and frequency
-    sizes = [len(w) * n_g for w in w_lists]
-    starts = np.concatenate([[0], np.cumsum(sizes)])
-    rej_h = rej.cpu().numpy()
-    n_pass = 0
-    n_pts = 0
-    for iq in range(len(q_list)):
-        r = rej_h[(rej_h >= starts[iq]) & (rej_h < starts[iq + 1])] - starts[iq]
-        if len(r) == 0:
-            continue
-        wsel = np.unique(r // n_g)
-        Lq = method_loss(ctx, set_states, iq, G_int, np.asarray(w_lists[iq])[wsel], eta_eV,
-                         precision)
-        view = L[starts[iq]:starts[iq + 1]].view(len(w_lists[iq]), n_g)
-        view[torch.from_numpy(wsel).cuda()] = Lq
-        n_pass += 1
-        n_pts += len(wsel)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    out = [L[starts[i]:starts[i + 1]].view(len(w_lists[i]), n_g) for i in range(len(q_list))]
-    return out, dict(n_queries=int(qw.shape[0]), n_rejected=int(nrej), fallback_passes=n_pass,
-                     fallback_points=n_pts, t_surrogate=t1 - t0, t_fallback=t2 - t1,
-                     t_total=t2 - t0, err=E)
+    err = torch.cat(errs)
+    return out, dict(n_queries=int(err.numel()), n_rejected=int((err > tol).sum().item()),
+                     fallback_passes=n_pass, fallback_points=n_rows, t_total=t1 - t0, err=err)

@@ -62,7 +62,7 @@ def q_max(wl: Workload) -> float:
     return float(g + np.linalg.norm(corners @ b, axis=1).max())
 
 
-def mlp_init(seed: int, widths=(5, 256, 256, 256, 256, 1)) -> np.ndarray:
+def mlp_init(seed: int, widths=(49, 256, 256, 256, 256, 1)) -> np.ndarray:
     """Flat FP32 parameters (W_l row-major then b_l per layer): hidden
     weights N(0, 2/fan_in), output weights N(0, 1/fan_in), biases zero."""
     rng = np.random.default_rng(seed)

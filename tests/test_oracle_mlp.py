@@ -20,7 +20,7 @@ def _rand_theta(widths, seed=0, scale=0.5):
 
 def test_parameter_count():
     # 5*256+256 + 3*(256*256+256) + 256+1
-    assert mlp.n_params() == 199169
+    assert mlp.n_params() == 210433
     th = np.arange(mlp.n_params(SMALL), dtype=np.float64)
     assert np.array_equal(mlp.pack(mlp.unpack(th, SMALL)), th)
 
@@ -76,7 +76,7 @@ def test_gradient_against_autograd_full_size():
 
     th = mlp_init(7).astype(np.float64)
     rng = np.random.default_rng(8)
-    X = rng.standard_normal((64, 5))
+    X = rng.standard_normal((64, mlp.N_IN))
     t = rng.standard_normal(64)
     loss, g = mlp.loss_and_grad(th, X, t)
     T = torch.tensor(th, requires_grad=True)
@@ -100,7 +100,7 @@ def test_gradient_against_autograd_full_size():
 def test_bf16_mode_close_to_exact():
     th = mlp_init(9).astype(np.float64)
     rng = np.random.default_rng(10)
-    X = rng.standard_normal((128, 5))
+    X = rng.standard_normal((128, mlp.N_IN))
     t = rng.standard_normal(128)
     y0, _ = mlp.forward(th, X)
     y1, _ = mlp.forward(th, X, bf16=True)
@@ -169,3 +169,47 @@ def test_smooth_band_workload_is_periodic_and_ordered():
                        _band_energies(model, wl.energy_ranges, kf + shift), atol=1e-12)
     tr, ho = holdout_split(2, 100)
     assert len(ho) == 10 and len(np.intersect1d(tr, ho)) == 0 and len(tr) + len(ho) == 100
+
+
+def test_encode_features():
+    """The encoding against properties it must have, on a lattice that is not
+    symmetric (so that Q.a_i and Q.a^i-type index mistakes differ): unit
+    directions, the lowest frequency pi per w_max, successive frequencies in
+    the ratio sqrt(2) (read from the slope of sin at a tiny argument), every
+    (sin, cos) pair on the unit circle, and lattice features unchanged by any
+    reciprocal lattice vector while the other features change."""
+    A = np.array([[4.1, 0.3, -0.7], [0.5, 5.2, 0.2], [-0.4, 0.9, 6.3]])   # rows: primitive vectors
+    B = 2 * math.pi * np.linalg.inv(A).T                                   # rows: reciprocal vectors
+    assert np.allclose(A @ B.T, 2 * math.pi * np.eye(3))
+    rng = np.random.default_rng(40)
+    qw = np.column_stack([rng.uniform(-2, 2, size=(50, 3)), rng.uniform(0, 60, 50)])
+    qw[0, :3] = 0.0
+    x = mlp.encode(qw, 4.0, 60.0, A)
+    assert x.shape == (50, mlp.N_IN) == (50, 49)
+    assert np.allclose(np.linalg.norm(x[1:, 1:4], axis=1), 1.0) and np.all(x[0, 1:4] == 0.0)
+    nf = mlp.N_FREQ
+    pairs = x[:, 5:].reshape(50, -1, 2)
+    assert np.allclose((pairs ** 2).sum(axis=2), 1.0, atol=1e-14)
+    # w = w_max: the first w pair is (sin pi, cos pi)
+    top = mlp.encode(np.array([[1.0, 0.0, 0.0, 60.0]]), 4.0, 60.0, A)[0]
+    assert abs(top[5]) < 1e-14 and abs(top[6] + 1.0) < 1e-14
+    # slopes at a tiny w and a tiny |Q|: pi 2^(j/2) / scale
+    eps = 1e-7
+    small = mlp.encode(np.array([[eps, 0.0, 0.0, eps]]), 4.0, 60.0, A)[0]
+    sw = small[5:5 + 2 * nf:2] / (eps / 60.0)
+    sq = small[5 + 2 * nf:5 + 4 * nf:2] / (eps / 4.0)
+    for s in (sw, sq):
+        assert abs(s[0] - math.pi) < 1e-6
+        assert np.allclose(s[1:] / s[:-1], math.sqrt(2.0), rtol=1e-9)
+    # periodic part: invariant under Q -> Q + G for reciprocal lattice G
+    G = np.array([2, -1, 3]) @ B
+    shifted = qw.copy()
+    shifted[:, :3] += G
+    xs = mlp.encode(shifted, 4.0, 60.0, A)
+    lat_cols = slice(5 + 4 * nf, mlp.N_IN)
+    assert np.allclose(xs[:, lat_cols], x[:, lat_cols], atol=1e-11)
+    assert not np.allclose(xs[:, :lat_cols.start], x[:, :lat_cols.start])
+    # and a primitive vector itself is not a period of them
+    moved = qw.copy()
+    moved[:, :3] += A[0]
+    assert not np.allclose(mlp.encode(moved, 4.0, 60.0, A)[:, lat_cols], x[:, lat_cols])
