@@ -207,6 +207,25 @@ def cpu_baseline(wl, n_w_sample, gpu_loss_split, gpu_loss_fp32, n_w_1thread=50):
                 err_fp32=normwise(gpu_loss_fp32[idx], ref) if gpu_loss_fp32 is not None else None)
 
 
+def composite_rooflines(wl, n_w, n_g, n_in, n_out, stm):
+    """Rooflines of the composite step's two heavy kernels from the per-step
+    stage times: the pair densities of every G (FP64) and the chi0 bulk (the
+    LFE block's pairs plus one diagonal pair per noLFE G; split BF16, three
+    products).  Returns ({"rho": ..., "bulk": ...}, key of the dominant one)."""
+    rho_fl = rho_flops_per_kg(wl.n_ao, wl.n_occ, wl.n_cond) * wl.n_k * n_g
+    bulk_fl = 3.0 * 2.0 * (2 * n_w) * 2 * (n_in * (n_in + 1) // 2 - n_in + n_out) * wl.n_t
+    rho_s, bulk_s = 1e-3 * stm["pair_density_ms"], 1e-3 * stm["chi0_bulk_ms"]
+    rl = {"rho": {"bound": "mfma", "achieved": rho_fl / rho_s / 1e12, "peak": PEAK_FP64_TFLOPS,
+                  "unit": "TFLOP/s", "frac": rho_fl / rho_s / 1e12 / PEAK_FP64_TFLOPS,
+                  "traffic": None, "kernel": "k_cell_ft + k_rho_fused (all G, per step)",
+                  "ms_per_step": 1e3 * rho_s},
+          "bulk": {"bound": "mfma", "achieved": bulk_fl / bulk_s / 1e12, "peak": PEAK_BF16_TFLOPS,
+                   "unit": "TFLOP/s", "frac": bulk_fl / bulk_s / 1e12 / PEAK_BF16_TFLOPS,
+                   "traffic": None, "kernel": "k_bulk<bf16> (LFE pairs and noLFE diagonal)",
+                   "ms_per_step": 1e3 * bulk_s}}
+    return rl, ("rho" if rho_s >= bulk_s else "bulk")
+
+
 def rho_flops_per_kg(n_ao, n_occ, n_c, n_cells=27):
     """Algorithmic FP64 flops of the pair densities per (k, G): the Bloch sum
     (n_cells N_AO^2 complex multiply-adds) and the valence-first band
@@ -412,22 +431,7 @@ def main_composite(args):
     inner, L_in, outer, L_out = res["parts"]
     vals = n_w * n_g
     stm = {k: (v / args.steps if k.endswith("_ms") else v) for k, v in st.items()}
-    # the two heavy kernels: pair densities of every G (FP64) and the chi0
-    # bulk (the LFE block's pairs plus one diagonal pair per noLFE G; split
-    # BF16, three products)
-    rho_fl = rho_flops_per_kg(wl.n_ao, wl.n_occ, wl.n_cond) * wl.n_k * n_g
-    n_in = len(inner)
-    bulk_fl = 3.0 * 2.0 * (2 * n_w) * 2 * (n_in * (n_in + 1) // 2 - n_in + len(outer)) * wl.n_t
-    rho_s, bulk_s = 1e-3 * stm["pair_density_ms"], 1e-3 * stm["chi0_bulk_ms"]
-    rl = {"rho": {"bound": "mfma", "achieved": rho_fl / rho_s / 1e12, "peak": PEAK_FP64_TFLOPS,
-                  "unit": "TFLOP/s", "frac": rho_fl / rho_s / 1e12 / PEAK_FP64_TFLOPS,
-                  "traffic": None, "kernel": "k_cell_ft + k_rho_fused (all G, per step)",
-                  "ms_per_step": 1e3 * rho_s},
-          "bulk": {"bound": "mfma", "achieved": bulk_fl / bulk_s / 1e12, "peak": PEAK_BF16_TFLOPS,
-                   "unit": "TFLOP/s", "frac": bulk_fl / bulk_s / 1e12 / PEAK_BF16_TFLOPS,
-                   "traffic": None, "kernel": "k_bulk<bf16> (LFE pairs and noLFE diagonal)",
-                   "ms_per_step": 1e3 * bulk_s}}
-    dom = "rho" if rho_s >= bulk_s else "bulk"
+    rl, dom = composite_rooflines(wl, n_w, n_g, len(inner), len(outer), stm)
     out = {
         "metric": "composite loss (w, q+G) values/s: LFE block inverted, noLFE diagonal beyond",
         "value": vals * args.steps / sec,
@@ -581,7 +585,7 @@ def main_kk(args):
         "roofline": {"bound": "mfma", "achieved": gemm_flops / gemm_s / 1e12,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": gemm_flops / gemm_s / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "rocblas_dgemm (transform, [2 n_w][bins] x [bins][2 n_pairs])",
+                     "kernel": "k_kk_gemm (transform on FP64 MFMA, [2 n_w] x [2 n_pairs] over the bins)",
                      "avg_launch_ms": 1e3 * gemm_s, "flops_per_launch": gemm_flops},
         "binning_roofline": {"bound": "alu", "achieved": bin_flops / bin_s / 1e12,
                              "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
@@ -682,8 +686,10 @@ def main_rates(args):
     bin_dev_ms = ev[0].elapsed_time(ev[1])
     state = res["state"]
     w = np.asarray(wl.w_eV)
-    rh, rl = res["rh"].cpu().numpy(), res["rl"].cpu().numpy()
+    rh, rl_ = res["rh"].cpu().numpy(), res["rl"].cpu().numpy()
     dw = w[1] - w[0]
+    stm = {k: (v / args.steps if k.endswith("_ms") else v) for k, v in st.items()}
+    rl, dom = composite_rooflines(wl, n_w, n_g, len(res["parts"][0]), len(res["parts"][2]), stm)
     out = {
         "metric": "(w, q+G) values taken to binned S(w,q) and dR/dw per second (composite eps, one q)",
         "value": n_w * n_g * args.steps / sec,
@@ -706,8 +712,10 @@ def main_rates(args):
         "bins": {"with_entries": int((state == 1).sum()), "interpolated": int((state == 2).sum()),
                  "empty": int((state == 0).sum())},
         "binning_and_rate_ms_last_step": {"wall": 1e3 * res["host_s"], "device_events": bin_dev_ms},
-        "rate_events_per_kg_year": {"heavy": float(np.sum(rh) * dw), "light": float(np.sum(rl) * dw)},
-        "stages_ms_per_step": {k: (v / args.steps if k.endswith("_ms") else v) for k, v in st.items()},
+        "rate_events_per_kg_year": {"heavy": float(np.sum(rh) * dw), "light": float(np.sum(rl_) * dw)},
+        "roofline": rl[dom],
+        "other_roofline": rl["bulk" if dom == "rho" else "rho"],
+        "stages_ms_per_step": stm,
         "build": build_info(),
     }
     if not args.no_cpu_baseline:
@@ -787,6 +795,9 @@ def main_optical(args):
     ctx.set_timing(False)
     points = 3 * n_w
     L = [x.cpu().numpy() for x in loss]
+    bulk_s = 1e-3 * st["chi0_bulk_ms"] / max(1, st["bulk_launches"])
+    alg = bulk_flops_per_launch(wl)
+    achieved = 3.0 * alg / bulk_s / 1e12
     out = {
         "metric": "optical-limit (direction, w) loss points/s at N_G=113 (k.p head and wings)",
         "value": points * args.steps / sec,
@@ -803,6 +814,10 @@ def main_optical(args):
         "config": {"workload": "Si-like fcc a=10.26, 28 GTO, 4+16 bands, 8^3 k, q -> 0 along x, y, z, "
                                "N_G=113, 400 w over 0-60 eV, eta=0.1 eV, split-BF16 bulk, FP64 "
                                "head/wings and inversion"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                     "kernel": "k_bulk<bf16> (chi0 bulk, one launch per direction)",
+                     "avg_launch_ms": 1e3 * bulk_s, "flops_per_launch_fp32_equiv": alg},
         "stages_ms_per_step": {k: (v / args.steps if k.endswith("_ms") else v) for k, v in st.items()},
         "build": build_info(),
     }

@@ -3,8 +3,8 @@
     python -m paper_2603_12326_amd.build          # or build() from Python
 
 Every .hip file under csrc/ is compiled with hipcc in parallel and linked into
-one shared library (with rocBLAS, used for the plain FP64 product of the
-Kramers-Kronig route).  Packed FP32 instructions are disabled
+one shared library (HIP runtime only: every kernel is in csrc/).  Packed FP32
+instructions are disabled
 (-target-feature -packed-fp32-ops); the host pass warns that it does not know
 the feature, which is harmless.
 """
@@ -56,7 +56,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lrocblas"]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

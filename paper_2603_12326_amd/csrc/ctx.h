@@ -13,7 +13,6 @@
 #include <string>
 #include <vector>
 
-#include <rocblas/rocblas.h>
 
 #include "common.h"
 
@@ -104,9 +103,6 @@ struct qcx_ctx {
   // transition energies copied to pinned host memory right after
   // qcx_set_states computes them, once the Kramers-Kronig route has been
   // used (its host-side sort then overlaps the pair densities on the device)
-  // rocBLAS handle for the plain FP64 product of the Kramers-Kronig
-  // transform, created on first use and bound to the context's stream
-  rocblas_handle blas = nullptr;
   double* h_dt = nullptr;
   size_t h_dt_cap = 0;
   hipEvent_t ev_dt = nullptr;
@@ -154,7 +150,6 @@ struct qcx_ctx {
     }
     if (dt_pending && ev_dt) (void)hipEventSynchronize(ev_dt);
     if (h_dt) (void)hipHostFree(h_dt);
-    if (blas) (void)rocblas_destroy_handle(blas);
     if (ev_dt) (void)hipEventDestroy(ev_dt);
   }
 };

@@ -13,8 +13,9 @@
 // between the three logarithms.
 //
 // Binning is a sparse accumulation (two bins per transition), done on the
-// FP64 vector units; the transform is a plain dense FP64 product, left to
-// rocBLAS (qcx_chi0_kk).
+// FP64 vector units; the transform is a dense FP64 product over the bins on
+// FP64 MFMA (k_kk_gemm), with the kernel matrix laid out bin-major so that
+// both operands stream in rows of the bin index.
 #include "kk.h"
 
 namespace qcx {
@@ -228,14 +229,17 @@ __device__ inline c64 hat_kernel(c64 z) {
   return {a.re - 2.0 * b.re + c.re, a.im - 2.0 * b.im + c.im};
 }
 
+// Kb[c][row] (bin-major, rows_p bins x ldm rows, zero past the last bin and
+// past row 2 n_w): row 2j + ri is the real (ri = 0) or imaginary part of the
+// transform of bin c at frequency j.
 __global__ void k_kk_matrix(const double* __restrict__ w, int n_w, double eta, double d, int nr,
-                            int na, int br, int ba, int ldk, double* __restrict__ Kt) {
+                            int na, int br, int ba, int rows_p, int ldm, double* __restrict__ Kb) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)2 * n_w * ldk) return;
-  const int row = (int)(i / ldk), c = (int)(i % ldk);
+  if (i >= (long)rows_p * ldm) return;
+  const int c = (int)(i / ldm), row = (int)(i % ldm);
   const int j = row >> 1, ri = row & 1;
   double v = 0.0;
-  if (c < nr + na) {
+  if (c < nr + na && row < 2 * n_w) {
     c64 k;
     if (c < nr) {  // resonant: K(w - w_b + i eta), limit from above at eta = 0
       const double wb = (br + c) * d;
@@ -247,7 +251,114 @@ __global__ void k_kk_matrix(const double* __restrict__ w, int n_w, double eta, d
     }
     v = (ri ? k.im : k.re) / d;
   }
-  Kt[i] = v;
+  Kb[i] = v;
+}
+
+// --------------------------------------------------------------- transform
+// C[m][n] = sum_k Kb[k][m] S[k][n] on FP64 MFMA (v_mfma_f64_16x16x4f64):
+// m < M = 2 n_w rows (frequency, re/im), n < N = 2 pairs columns, k over
+// rows_p bins (a multiple of KG_K; Kb and S are zero in the padding).  A
+// block of 256 threads owns KG_M x KG_N of C; its four waves own KG_M / 2 x
+// KG_N / 2 each (5 x 4 MFMA tiles of 16 x 16).  Tiles of KG_K bins of both
+// operands go through LDS in two buffers: the copies of the next tile into
+// one are issued before the MFMAs on the other, one barrier per tile.  LDS
+// rows are padded by 16 doubles so that the 16-lane groups of a fragment
+// read hit different banks.  Blocks are
+// placed so that the KG_M-row tiles sharing a column tile of S run on one
+// XCD (S, the large operand, is then read from memory once).
+// MFMA layouts: A 16x4, lane l holds A[l%16][l/16]; B 4x16, lane l holds
+// B[l/16][l%16]; D 16x16, lane l holds D[4r + l/16][l%16], r = 0..3.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int KG_M = 160, KG_N = 128, KG_K = 16;
+constexpr int KG_LA = KG_M + 16, KG_LB = KG_N + 16;  // padded LDS rows (doubles)
+constexpr int KG_FA = KG_M / 32, KG_FB = KG_N / 32;   // fragments per wave: 5 x 4
+constexpr int KG_VA = KG_K * KG_M / 2 / 256;          // 16-byte loads per thread: 5
+
+// The next tile of bins k0 .. k0 + KG_K - 1, copied from memory straight into
+// LDS (global_load_lds_dwordx4: one wave instruction moves 1 KB, lane l's 16
+// bytes landing at the destination + 16 l): rows of S (KG_N doubles = 1 KB)
+// and the first 128 columns of the Kb rows go one row per instruction into
+// padded rows; the last 32 columns of the Kb rows (256 B each) go four rows
+// per instruction into an unpadded block.
+constexpr int KG_M1 = 128, KG_M2 = KG_M - KG_M1;
+constexpr int KG_LA1 = KG_M1 + 16;
+typedef __attribute__((address_space(3))) void* kg_lds_t;
+__device__ __forceinline__ void kg_issue(const double* __restrict__ Kb, int ldm,
+                                         const double* __restrict__ S, int N, int m0, int n0, int k0,
+                                         int lane, int wave, double* sA1, double* sA2, double* sB) {
+#pragma unroll
+  for (int i = 0; i < KG_K / 4; ++i) {
+    const int r = wave + 4 * i;
+    __builtin_amdgcn_global_load_lds((const void*)(S + (size_t)(k0 + r) * N + n0 + 2 * lane),
+                                     (kg_lds_t)(sB + r * KG_LB), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)(Kb + (size_t)(k0 + r) * ldm + m0 + 2 * lane),
+                                     (kg_lds_t)(sA1 + r * KG_LA1), 16, 0, 0);
+  }
+  const int r2 = 4 * wave + (lane >> 4);
+  __builtin_amdgcn_global_load_lds(
+      (const void*)(Kb + (size_t)(k0 + r2) * ldm + m0 + KG_M1 + 2 * (lane & 15)),
+      (kg_lds_t)(sA2 + 4 * wave * KG_M2), 16, 0, 0);
+}
+
+__global__ void __launch_bounds__(256) k_kk_gemm(const double* __restrict__ Kb, int ldm,
+                                                 const double* __restrict__ S, int N, int rows_p,
+                                                 int M, int n_mt, int n_nt,
+                                                 double* __restrict__ C) {
+  __shared__ __attribute__((aligned(16))) double sA1[2][KG_K * KG_LA1];
+  __shared__ __attribute__((aligned(16))) double sA2[2][KG_K * KG_M2];
+  __shared__ __attribute__((aligned(16))) double sB[2][KG_K * KG_LB];
+  // XCD-aware placement: consecutive logical tiles on one XCD share n
+  const int total = n_mt * n_nt, per = (total + 7) / 8;
+  const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (logical >= total) return;
+  const int nt = logical / n_mt, mt = logical % n_mt;
+  const int m0 = mt * KG_M, n0 = nt * KG_N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * (KG_M / 2), wn = (wave & 1) * (KG_N / 2);
+  f64x4 acc[KG_FA][KG_FB];
+#pragma unroll
+  for (int a = 0; a < KG_FA; ++a)
+#pragma unroll
+    for (int b = 0; b < KG_FB; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int nk = rows_p / KG_K;
+  kg_issue(Kb, ldm, S, N, m0, n0, 0, lane, wave, sA1[0], sA2[0], sB[0]);
+  __syncthreads();  // its fence waits for the copies into LDS as well
+  for (int s = 0; s < nk; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nk)
+      kg_issue(Kb, ldm, S, N, m0, n0, (s + 1) * KG_K, lane, wave, sA1[buf ^ 1], sA2[buf ^ 1],
+               sB[buf ^ 1]);
+#pragma unroll
+    for (int kk = 0; kk < KG_K; kk += 4) {
+      const int k = kk + (lane >> 4);
+      double fa[KG_FA], fb[KG_FB];
+#pragma unroll
+      for (int a = 0; a < KG_FA; ++a) {
+        const int mm = wm + 16 * a;  // wave-uniform: which block holds the fragment
+        fa[a] = mm < KG_M1 ? sA1[buf][k * KG_LA1 + mm + (lane & 15)]
+                           : sA2[buf][k * KG_M2 + mm - KG_M1 + (lane & 15)];
+      }
+#pragma unroll
+      for (int b = 0; b < KG_FB; ++b) fb[b] = sB[buf][k * KG_LB + wn + 16 * b + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < KG_FA; ++a)
+#pragma unroll
+        for (int b = 0; b < KG_FB; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();  // the fence also waits for this wave's copies of the next tile
+  }
+#pragma unroll
+  for (int a = 0; a < KG_FA; ++a)
+#pragma unroll
+    for (int b = 0; b < KG_FB; ++b) {
+      const int n = n0 + wn + 16 * b + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * a + 4 * r + (lane >> 4);
+        if (m < M && n < N) C[(size_t)m * N + n] = acc[a][b][r];
+      }
+    }
 }
 
 }  // namespace
@@ -266,10 +377,22 @@ void launch_kk_bin(const cplx* Rs, int n_gp, int n_g, const int* ib, const doubl
 }
 
 void launch_kk_matrix(const double* w, int n_w, double eta, double d, int nr, int na, int br,
-                      int ba, int ldk, double* Kt, hipStream_t st) {
-  const long total = (long)2 * n_w * ldk;
+                      int ba, int rows_p, int ldm, double* Kb, hipStream_t st) {
+  const long total = (long)rows_p * ldm;
   hipLaunchKernelGGL(k_kk_matrix, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, w, n_w,
-                     eta, d, nr, na, br, ba, ldk, Kt);
+                     eta, d, nr, na, br, ba, rows_p, ldm, Kb);
+}
+
+int kk_rows_padded(int rows) { return (rows + KG_K - 1) / KG_K * KG_K; }
+int kk_ldm(int n_w) { return (2 * n_w + KG_M - 1) / KG_M * KG_M; }
+size_t kk_s_slack() { return KG_N; }
+
+void launch_kk_transform(const double* Kb, int ldm, const double* S, int N, int rows_p, int M,
+                         double* C, hipStream_t st) {
+  const int n_mt = ldm / KG_M, n_nt = (N + KG_N - 1) / KG_N;
+  const int total = n_mt * n_nt;
+  hipLaunchKernelGGL(k_kk_gemm, dim3((unsigned)(8 * ((total + 7) / 8))), dim3(256), 0, st, Kb, ldm,
+                     S, N, rows_p, M, n_mt, n_nt, C);
 }
 
 }  // namespace qcx

@@ -7,8 +7,8 @@
 // is a piecewise-linear spectral density carrying the zeroth and first
 // energy moments of every transition exactly.  The full response follows
 // from S by the exact transform of each hat piece through the energy
-// denominator (see k_kk.hip), one dense FP64 product over the bins
-// (rocBLAS dgemm).
+// denominator (see k_kk.hip), one dense FP64 product over the bins on FP64
+// MFMA.
 #pragma once
 
 #include "common.h"
@@ -30,10 +30,21 @@ void launch_kk_pack(const cplx* R, size_t ldt, int n_g, int n_gp, int n_t, const
 // S[row][2][n_pairs] (Re, Im) for every chunk and upper-triangle pair (G <= G')
 void launch_kk_bin(const cplx* Rs, int n_gp, int n_g, const int* ib, const double* xf,
                    const KkChunk* chunks, int n_chunks, double* S, hipStream_t st);
-// Kt[2 n_w][ldk]: row 2j = Re, 2j + 1 = Im of the transform kernel of w_j for
-// bin column c: resonant bins c < nr at (br + c) d, anti-resonant bins
-// nr <= c < nr + na at (ba + c - nr) d, zero for nr + na <= c < ldk
+// Kb[rows_p][ldm] (bin-major): entry (c, 2j) = Re, (c, 2j + 1) = Im of the
+// transform kernel of w_j for bin c: resonant bins c < nr at (br + c) d,
+// anti-resonant bins nr <= c < nr + na at (ba + c - nr) d; zero for
+// c >= nr + na and for rows >= 2 n_w
 void launch_kk_matrix(const double* w, int n_w, double eta, double d, int nr, int na, int br,
-                      int ba, int ldk, double* Kt, hipStream_t st);
+                      int ba, int rows_p, int ldm, double* Kb, hipStream_t st);
+// Padded sizes of the transform: bins rounded up to the K tile, the row
+// length of Kb (2 n_w rounded up to the M tile), and the slack S needs past
+// its last row (the last column tile reads up to one tile beyond N).
+int kk_rows_padded(int rows);
+int kk_ldm(int n_w);
+size_t kk_s_slack();
+// C[M][N] = Kb^T S over rows_p bins (S: rows_p x N, row-major, rows past the
+// last bin zero, kk_s_slack() doubles of addressable memory after it)
+void launch_kk_transform(const double* Kb, int ldm, const double* S, int N, int rows_p, int M,
+                         double* C, hipStream_t st);
 
 }  // namespace qcx

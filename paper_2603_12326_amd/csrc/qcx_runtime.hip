@@ -441,20 +441,8 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
   return QCX_OK;
 }
 
-// Pair densities of the G list into ctx->d_R (shared by qcx_pair_density and
-// the chunks of qcx_loss_diag, which has no G = 0 requirement).
-// The context's rocBLAS handle on its stream (created on first use).
-static int ensure_blas(qcx_ctx* ctx) {
-  if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
-    ctx->blas = nullptr;
-    return fail(ctx, QCX_EDEVICE, "rocblas_create_handle failed");
-  }
-  if (rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success)
-    return fail(ctx, QCX_EDEVICE, "rocblas_set_stream failed");
-  return QCX_OK;
-}
-
-// Pair densities R[G][t] for the G list (G = 0 first when need_g0).  With
+// Pair densities R[G][t] into ctx->d_R for the G list (G = 0 first when
+// need_g0; qcx_loss_diag's chunks have no G = 0 requirement).  With
 // qhat (the optical limit, App. C) the states must have q = 0; the k states
 // serve on both sides, and the G = 0 row is replaced by its q -> 0 limit
 // divided by |q| (k.p form, launch_optical_row) with Coulomb factor sqrt(4 pi).
@@ -1005,7 +993,7 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
   }
   const int n_gp = (int)roundup(n_g, kKkTile);
   const size_t n_pairs = (size_t)n_g * (n_g + 1) / 2;
-  const int ldk = (int)roundup(rows, 2);
+  const int rows_p = kk_rows_padded(rows), ldm = kk_ldm(n_w);
   if ((double)rows * 2 * n_pairs * sizeof(double) > kKkSpectralBudget)
     return fail(ctx, QCX_EINVAL, "binned spectral function exceeds 16 GB: widen bin_eV");
   if (chunks.size() > (size_t)INT_MAX) return fail(ctx, QCX_EINVAL, "too many bins");
@@ -1017,8 +1005,12 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
   HIPCK(upload(ctx, ctx->d_kk_xf, xf.data(), xf.size()));
   HIPCK(upload(ctx, ctx->d_kk_chunks, chunks.data(), chunks.size()));
   HIPCK(ctx->d_kk_Rs.reserve(sizeof(cplx) * (size_t)n_t * n_gp));
-  HIPCK(ctx->d_kk_S.reserve(sizeof(double) * (size_t)rows * 2 * n_pairs));
-  HIPCK(ctx->d_kk_K.reserve(sizeof(double) * (size_t)2 * n_w * ldk));
+  HIPCK(ctx->d_kk_S.reserve(sizeof(double) * ((size_t)rows_p * 2 * n_pairs + kk_s_slack())));
+  HIPCK(ctx->d_kk_K.reserve(sizeof(double) * (size_t)rows_p * ldm));
+  // bins past the last (padding of the transform's K tiles) are zero; the
+  // binning writes every real bin
+  HIPCK(hipMemsetAsync(ctx->d_kk_S.as<double>() + (size_t)rows * 2 * n_pairs, 0,
+                       sizeof(double) * ((size_t)(rows_p - rows) * 2 * n_pairs + kk_s_slack()), st));
   HIPCK(ctx->d_C64.reserve(sizeof(double) * (size_t)2 * n_w * 2 * n_pairs));
   ctx->n_w = n_w;
   ctx->eta = eta;
@@ -1034,21 +1026,14 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
                 ctx->d_kk_chunks.as<KkChunk>(), (int)chunks.size(), ctx->d_kk_S.as<double>(), st);
   HIPCK(span_end(ctx, sp_bin));
   LAUNCHCK("kk binning");
-  launch_kk_matrix(ctx->d_w.as<double>(), n_w, eta, d, nbin[0], nbin[1], base[0], base[1], ldk,
-                   ctx->d_kk_K.as<double>(), st);
-  // C64[2 n_w][2 n_pairs] = Kt[2 n_w][rows] S[rows][2 n_pairs], row-major:
-  // the column-major product C64^T = S^T Kt^T
-  if (int rc = ensure_blas(ctx)) return rc;
-  const double one = 1.0, zero = 0.0;
+  launch_kk_matrix(ctx->d_w.as<double>(), n_w, eta, d, nbin[0], nbin[1], base[0], base[1], rows_p,
+                   ldm, ctx->d_kk_K.as<double>(), st);
+  // C64[2 n_w][2 n_pairs] = Kb^T S over the bins on FP64 MFMA
   const int nc = (int)(2 * n_pairs);
   HIPCK(span_begin(ctx, 6, &sp_tr));
-  const rocblas_status bs = rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none,
-                                          nc, 2 * n_w, rows, &one, ctx->d_kk_S.as<double>(), nc,
-                                          ctx->d_kk_K.as<double>(), ldk, &zero,
-                                          ctx->d_C64.as<double>(), nc);
+  launch_kk_transform(ctx->d_kk_K.as<double>(), ldm, ctx->d_kk_S.as<double>(), nc, rows_p, 2 * n_w,
+                      ctx->d_C64.as<double>(), st);
   HIPCK(span_end(ctx, sp_tr));
-  if (bs != rocblas_status_success)
-    return fail(ctx, QCX_EDEVICE, "rocblas_dgemm failed (status " + std::to_string((int)bs) + ")");
   LAUNCHCK("kk transform");
   HIPCK(span_end(ctx, sp_all));
   // what the assembly reads: one FP64 value of 2 n_w rows (Re K, Im K) x
