@@ -188,6 +188,15 @@ struct Geom64 {
 void geom64_init(Geom64& g, int n_g, int n_w, int n_t, int n_ps, size_t max_bytes);
 void launch_pairs_f64(const cplx* R, size_t ldt, const double* w, const double* dt, double eta,
                       const Geom64& g, const int* pairs, double* out, hipStream_t st);
+// Head and wings (few pairs, all transitions): the same partials XY from an
+// FP64 GEMM over a per-q table P[t][col] of the pair products (held in P,
+// hw_ptable_doubles(g) doubles).  Geometry: rows padded to 160, columns to
+// 128, K split to fill the device in one round.
+void geom_hw_init(Geom64& g, int n_g, int n_w, int n_t, int n_ps, size_t max_bytes);
+size_t hw_ptable_doubles(const Geom64& g);
+void launch_headwings_f64(const cplx* R, size_t ldt, const double* w, const double* dt, double eta,
+                          const Geom64& g, const int* pairs, double* P, double* out,
+                          hipStream_t st);
 // eps assembly (symmetrised Coulomb, prefactor 2/(N_k V))
 struct AsmArgs {
   const float* C;       // bulk partials [ks][n_rowsp][2][n_bulkp] or null

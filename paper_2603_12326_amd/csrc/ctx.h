@@ -69,7 +69,7 @@ struct qcx_ctx {
   int autotune = 1;           // 0: fixed heuristic, 1: time candidates per shape
   double tune_ms = 0.0;       // time spent tuning in the last qcx_chi0
   Geom64 geom64{};
-  DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_rows, d_pairs64, d_C, d_C64, d_XY;
+  DevBuf d_w, d_A, d_Alo, d_R32, d_pairs, d_rows, d_pairs64, d_C, d_C64, d_XY, d_hwP;
   // what d_pairs, d_rows and d_pairs64 last received (upload_cached)
   std::vector<int> h_pairs_up, h_rows_up, h_pairs64_up;
   // Kramers-Kronig route: energy order, sorted energies and sides, K ranges
@@ -127,7 +127,7 @@ struct qcx_ctx {
                      &d_Ck,   &d_Ek,    &d_Ckq,    &d_Ekq,    &d_dt,    &d_ph,   &d_phq,
                      &d_S,    &d_F0,    &d_dev,    &d_flags,    &d_Q,      &d_vq,    &d_F,    &d_M,
                      &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_rows, &d_pairs64, &d_C, &d_C64,
-                     &d_XY,   &d_eps,   &d_diag,   &d_epsM,   &d_loss,  &d_sing,
+                     &d_XY,   &d_hwP,   &d_eps,    &d_diag,   &d_epsM,  &d_loss,  &d_sing,
                      &d_kk_rank, &d_kk_ib, &d_kk_xf, &d_kk_chunks, &d_kk_Rs, &d_kk_S, &d_kk_K,
                      &d_Fg, &d_Rp};
   }

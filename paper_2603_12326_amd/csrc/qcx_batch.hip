@@ -40,6 +40,7 @@ struct BatchPlan {
   std::vector<PlanItem> items;
   std::vector<DevBuf> r32;  // per context
   DevBuf d_items, d_tiles, d_counter, d_sing;
+  DevBuf hwP;  // pair-product table of the head/wing GEMMs (items run one after another)
   // multi-item inversion launches, one per kernel class present
   struct GjGroup {
     int cls = 0, n_jobs = 0, n_blocks = 0, max_n = 0;
@@ -65,6 +66,7 @@ struct BatchPlan {
     for (GjGroup& g : gj) g.jobs.release();
     d_items.release();
     d_tiles.release();
+    hwP.release();
     d_counter.release();
     d_sing.release();
   }
@@ -228,7 +230,12 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
       g.n_tp = (int)roundup(g.n_t, 16);
     }
     if (it.n_pairs64 > 0) {
-      geom64_init(it.g64, c->n_g, in.n_w, c->n_t, it.n_pairs64, (size_t)256 << 20);
+      if (it.n_pairs64 == c->n_g) {
+        geom_hw_init(it.g64, c->n_g, in.n_w, c->n_t, it.n_pairs64, (size_t)256 << 20);
+        HIPCK(P->hwP.reserve(sizeof(double) * hw_ptable_doubles(it.g64)));
+      } else {
+        geom64_init(it.g64, c->n_g, in.n_w, c->n_t, it.n_pairs64, (size_t)256 << 20);
+      }
       std::vector<int> tab(it.n_pairs64);
       int p = 0;
       for (int G = 0; G < c->n_g && p < it.n_pairs64; ++G)
@@ -331,7 +338,11 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
     for (int i = 0; i < n_items; ++i) {
       PlanItem& it = P->items[i];
       qcx_ctx* c = ctxs[it.ctx];
-      if (it.n_pairs64 > 0)
+      if (it.n_pairs64 > 0 && it.n_pairs64 == c->n_g)
+        launch_headwings_f64(c->d_R.as<cplx>(), c->ldt, it.w.as<double>(), c->d_dt.as<double>(),
+                             it.eta, it.g64, it.pairs64.as<int>(), P->hwP.as<double>(),
+                             it.XY.as<double>(), cs);
+      else if (it.n_pairs64 > 0)
         launch_pairs_f64(c->d_R.as<cplx>(), c->ldt, it.w.as<double>(), c->d_dt.as<double>(),
                          it.eta, it.g64, it.pairs64.as<int>(), it.XY.as<double>(), cs);
     }

@@ -882,7 +882,13 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
   }
   if (ctx->n_pairs64 > 0) {
     Geom64& g64 = ctx->geom64;
-    geom64_init(g64, ctx->n_g, n_w, ctx->n_t, ctx->n_pairs64, (size_t)512 << 20);
+    // head and wings alone (the pairs (0, G')): FP64 GEMM over a table of the
+    // pair products; every pair (the FP64 path): products formed on the fly
+    const bool hw = ctx->n_pairs64 == ctx->n_g;
+    if (hw)
+      geom_hw_init(g64, ctx->n_g, n_w, ctx->n_t, ctx->n_pairs64, (size_t)512 << 20);
+    else
+      geom64_init(g64, ctx->n_g, n_w, ctx->n_t, ctx->n_pairs64, (size_t)512 << 20);
     ctx->ks64 = g64.ksplit;
     std::vector<int> tab(ctx->n_pairs64);
     {
@@ -892,9 +898,15 @@ int qcx_chi0(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, int preci
     }
     HIPCK(upload_cached(ctx, ctx->d_pairs64, ctx->h_pairs64_up, tab));
     HIPCK(ctx->d_XY.reserve(sizeof(double) * (size_t)g64.ksplit * g64.n_rowsp * g64.n_colp));
+    if (hw) HIPCK(ctx->d_hwP.reserve(sizeof(double) * hw_ptable_doubles(g64)));
     HIPCK(span_begin(ctx, 2, &sp_hw));
-    launch_pairs_f64(ctx->d_R.as<cplx>(), ctx->ldt, ctx->d_w.as<double>(), ctx->d_dt.as<double>(),
-                     ctx->eta, g64, ctx->d_pairs64.as<int>(), ctx->d_XY.as<double>(), st);
+    if (hw)
+      launch_headwings_f64(ctx->d_R.as<cplx>(), ctx->ldt, ctx->d_w.as<double>(),
+                           ctx->d_dt.as<double>(), ctx->eta, g64, ctx->d_pairs64.as<int>(),
+                           ctx->d_hwP.as<double>(), ctx->d_XY.as<double>(), st);
+    else
+      launch_pairs_f64(ctx->d_R.as<cplx>(), ctx->ldt, ctx->d_w.as<double>(), ctx->d_dt.as<double>(),
+                       ctx->eta, g64, ctx->d_pairs64.as<int>(), ctx->d_XY.as<double>(), st);
     LAUNCHCK("pairs_f64");
     HIPCK(span_end(ctx, sp_hw));
   }

@@ -143,6 +143,39 @@ def test_ragged_shapes(ctx):
             assert normwise(out["loss"], ref["loss"]) < tol, (prec, len(w))
 
 
+@pytest.mark.parametrize("case", ["smallest", "ragged", "si_ng113"])
+def test_headwings_row_fp64(ctx, case):
+    """The head and wings of the split-BF16 path (the FP64 GEMM over the
+    table of pair products) against the oracle's chi0 in FP64: row G = 0 and
+    column G = 0 to 1e-12.  Cases: the smallest workload; 7 G (ragged column
+    tile) and 37 frequencies (ragged row tile); the N_G = 113 workload at
+    full size (8^3 k, 400 frequencies) on its largest q."""
+    if case == "smallest":
+        wl, iq, w, G = make_smallest(), 0, None, None
+    elif case == "ragged":
+        wl, iq = make_smallest(), 0
+        w, G = wl.w_eV[::3][:37], wl.G_int[:7]
+    else:
+        wl, iq = make_si_ng113(), 9
+        w, G = wl.w_eV, None
+    G = wl.G_int if G is None else G
+    w = wl.w_eV if w is None else w
+    print("head/wings case", case, flush=True)
+    out = gpu_solve(ctx, wl, iq, precision="split_bf16", w_eV=w, G_int=G, want_chi0=True)
+    if case == "si_ng113":
+        # the oracle's chi0 at every 40th frequency (the full grid takes minutes)
+        idx = np.arange(0, len(w), 40)
+        ref = _oracle(wl, iq, w=w[idx], G=G)["chi0"]
+        got = out["chi0"][idx]
+    else:
+        ref = _oracle(wl, iq, w=w, G=G)["chi0"]
+        got = out["chi0"]
+    for name, a, b in (("row", got[:, 0, :], ref[:, 0, :]), ("column", got[:, :, 0], ref[:, :, 0])):
+        e = np.max(np.abs(a - b)) / np.max(np.abs(b))
+        print(case, name, e)
+        assert e < 1e-12, (case, name, e)
+
+
 def test_headwings_flag_consistent(ctx, small_wl):
     ref = _oracle(small_wl)
     for hw in (True, False):
