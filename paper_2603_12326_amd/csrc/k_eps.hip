@@ -314,16 +314,18 @@ __device__ __forceinline__ void gj_reg_body(const cplx* __restrict__ A, int n,
 //  2. the swept panel is written back, and every other column j receives the
 //     deferred rank-16 update  T[:, j] += Z Y[:, j]  with Y = T[P][j] (the 16
 //     pivot rows before this update) and Z = swept panel with 1 subtracted
-//     at (p_a, a).
+//     at (p_a, a): first every row but the pivot rows, one chunk of Z at a
+//     time, then the 16 pivot rows.
 // The update runs on FP64 MFMA (v_mfma_f64_16x16x4f64) as two real products
 // with K = 32:  Re T += [Re Z | Im Z] [Re Y ; -Im Y],
 //               Im T += [Re Z | Im Z] [Im Y ;  Re Y].
 // Z (chunks of at most ZR rows) and a 64-column tile of Y are staged in LDS
 // k-major (lane-consecutive rows / columns); each wave owns 32 x 16 output
 // blocks (2 MFMA tiles, re and im) and updates them in place.  A K step reads
-// 4 doubles per lane for 4 MFMAs.  Y tiles are read before any row of
-// that tile is updated, so pivot rows see their old values; with several Z
-// chunks, all chunks of one column tile are done before the next tile.
+// 4 doubles per lane for 4 MFMAs.  Since the pivot rows change only in the
+// last pass, every Y tile read before it holds their old values, and each Z
+// chunk is staged once per panel (with the column tiles inside the chunk
+// loop) rather than once per column tile.
 // MFMA layouts: A 16x4, lane l holds A[l%16][l/16]; B 4x16, lane l holds
 // B[l/16][l%16]; D 16x16, lane l holds D[4r + l/16][l%16], r = 0..3.
 template <int RP>
@@ -432,11 +434,34 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
     __syncthreads();  // swept panel in memory; pivot buffers free
     // ---- deferred rank-mb update of every column outside the panel
     const int nch = (n + ZR - 1) / ZR;
+    // The panel's pivot rows are left out of the chunk passes (their Z rows
+    // are zero there) and updated in a pass of their own at the end, so every
+    // chunk pass reads Y = the pivot rows before this update straight from
+    // the matrix, and each Z chunk is staged once per panel.
+    auto is_piv = [&](int i) {
+      bool f = false;
+      for (int a = 0; a < mb; ++a) f |= piv[k0 + a] == i;
+      return f;
+    };
     auto load_z = [&](int r0) {
       for (int e = tid; e < ZR * MB; e += 1024) {
         const int r = e >> 4, a = e & 15, i = r0 + r;
-        cplx z = (i < n && a < mb) ? A[(size_t)i * n + k0 + a] : cplx{0.0, 0.0};
-        if (a < mb && i == piv[k0 + a]) z.re -= 1.0;
+        const cplx z =
+            (i < n && a < mb && !is_piv(i)) ? A[(size_t)i * n + k0 + a] : cplx{0.0, 0.0};
+        Zt[a * ZR + r] = z.re;
+        Zt[(MB + a) * ZR + r] = z.im;
+      }
+    };
+    // Z of the pivot rows: row r < mb is the pivot row of step k0 + r, with 1
+    // subtracted at (r, r)
+    auto load_zp = [&]() {
+      for (int e = tid; e < ZR * MB; e += 1024) {
+        const int r = e >> 4, a = e & 15;
+        cplx z = {0.0, 0.0};
+        if (r < mb && a < mb) {
+          z = A[(size_t)piv[k0 + r] * n + k0 + a];
+          if (a == r) z.re -= 1.0;
+        }
         Zt[a * ZR + r] = z.re;
         Zt[(MB + a) * ZR + r] = z.im;
       }
@@ -452,8 +477,9 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
       }
     };
     const int li = l & 15, lk = l >> 4;
-    // one 32 x 16 output block: rows r0 + 32 rb .., columns jt + 16 cb ..
-    auto block = [&](int r0, int rb, int jt, int cb) {
+    // one 32 x 16 output block: rows r0 + 32 rb .. (the pivot rows of steps
+    // k0 + 32 rb .. in the pivot pass), columns jt + 16 cb ..
+    auto block = [&](int r0, int rb, int jt, int cb, bool pivot_pass) {
       f64x4 acc[2][2];
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
@@ -477,8 +503,9 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
       for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int rr = 32 * rb + 16 * rt + 4 * r + lk, i = r0 + rr;
-          if (rr >= ZR || i >= n) continue;
+          const int rr = 32 * rb + 16 * rt + 4 * r + lk;
+          if (pivot_pass ? rr >= mb : (rr >= ZR || r0 + rr >= n)) continue;
+          const int i = pivot_pass ? piv[k0 + rr] : r0 + rr;
           cplx t = A[(size_t)i * n + j];
           t.re += acc[rt][0][r];
           t.im += acc[rt][1][r];
@@ -486,18 +513,23 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
         }
     };
     constexpr int NRB = (ZR + 31) / 32, NU = NRB * (JT / 16);
-    if (nch == 1) load_z(0);
-    for (int jt = 0; jt < n; jt += JT) {
-      load_y(jt);
-      for (int c = 0; c < nch; ++c) {
-        __syncthreads();  // Y staged; Z staged or the previous chunk's reads done
-        if (nch > 1) {
-          load_z(c * ZR);
-          __syncthreads();
-        }
-        for (int u = v; u < NU; u += NW) block(c * ZR, u % NRB, jt, u / NRB);
+    for (int c = 0; c < nch; ++c) {
+      __syncthreads();  // the previous chunk's Z reads done
+      load_z(c * ZR);
+      for (int jt = 0; jt < n; jt += JT) {
+        __syncthreads();  // Z staged; the previous tile's Y reads done
+        load_y(jt);
+        __syncthreads();  // Y staged
+        for (int u = v; u < NU; u += NW) block(c * ZR, u % NRB, jt, u / NRB, false);
       }
-      __syncthreads();  // this tile's updates and Y reads done before the next Y
+    }
+    __syncthreads();  // the chunk passes' Z reads done
+    load_zp();
+    for (int jt = 0; jt < n; jt += JT) {
+      __syncthreads();  // Z staged; the previous tile's Y reads done
+      load_y(jt);
+      __syncthreads();  // Y staged
+      for (int u = v; u < JT / 16; u += NW) block(0, 0, jt, u, true);
     }
   }
   __syncthreads();
