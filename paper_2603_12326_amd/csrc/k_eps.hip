@@ -305,36 +305,40 @@ __device__ __forceinline__ void gj_reg_body(const cplx* __restrict__ A, int n,
 }
 
 // Blocked Gauss-Jordan for 128 < n <= 64 RP (RP <= 16) with 1024 threads per
-// matrix; the matrix stays in global memory and is swept in panels of 16
-// columns.  For each panel:
-//  1. lane l of wave v holds rows l + 64 a of panel column k0 + v in
-//     registers, and the panel's 16 pivot steps run as in k_gj_reg (one
+// matrix; the matrix stays in global memory and is swept in panels of MB = 32
+// columns, each made of two sub-panels of 16.  For each panel:
+//  1. lane l of wave v holds rows l + 64 a of sub-panel column s0 + v in
+//     registers, and the sub-panel's 16 pivot steps run as in k_gj_reg (one
 //     barrier per step, the next column's owner chooses its pivot while the
-//     others update), restricted to the panel columns;
-//  2. the swept panel is written back, and every other column j receives the
-//     deferred rank-16 update  T[:, j] += Z Y[:, j]  with Y = T[P][j] (the 16
-//     pivot rows before this update) and Z = swept panel with 1 subtracted
-//     at (p_a, a): first every row but the pivot rows, one chunk of Z at a
-//     time, then the 16 pivot rows.
+//     others update), restricted to the sub-panel's columns;
+//  2. the second sub-panel's columns first receive the first sub-panel's
+//     rank-16 update, and after their own sweep the first sub-panel's columns
+//     receive theirs (the same deferred update as below, on 16 columns), so
+//     that the panel holds what 32 single steps would leave there;
+//  3. every other column j receives the deferred rank-32 update
+//     T[:, j] += Z Y[:, j]  with Y = T[P][j] (the 32 pivot rows before this
+//     update) and Z = swept panel with 1 subtracted at (p_a, a): first every
+//     row but the pivot rows, one chunk of ZR rows of Z at a time, then the 32
+//     pivot rows.  Two sub-panels per pass halve the passes over the matrix,
+//     which bound this kernel (each pass reads and writes all of it).
 // The update runs on FP64 MFMA (v_mfma_f64_16x16x4f64) as two real products
-// with K = 32:  Re T += [Re Z | Im Z] [Re Y ; -Im Y],
+// with K = 64:  Re T += [Re Z | Im Z] [Re Y ; -Im Y],
 //               Im T += [Re Z | Im Z] [Im Y ;  Re Y].
-// Z (chunks of at most ZR rows) and a 64-column tile of Y are staged in LDS
-// k-major (lane-consecutive rows / columns); each wave owns 32 x 16 output
-// blocks (2 MFMA tiles, re and im) and updates them in place.  A K step reads
-// 4 doubles per lane for 4 MFMAs.  Since the pivot rows change only in the
-// last pass, every Y tile read before it holds their old values, and each Z
-// chunk is staged once per panel (with the column tiles inside the chunk
-// loop) rather than once per column tile.
+// Z (chunks of ZR rows) and a JT-column tile of Y are staged in LDS k-major
+// (lane-consecutive rows / columns); each wave owns a 32 x 16 output block
+// (2 MFMA tiles, re and im) per tile and updates it in place.  Since the pivot
+// rows change only in the last pass, every Y tile read before it holds their
+// old values, and each Z chunk is staged once per panel.
 // MFMA layouts: A 16x4, lane l holds A[l%16][l/16]; B 4x16, lane l holds
 // B[l/16][l%16]; D 16x16, lane l holds D[4r + l/16][l%16], r = 0..3.
+constexpr int GJP_MS = 16, GJP_MB = 2 * GJP_MS, GJP_JT = 64, GJP_KR = 2 * GJP_MB, GJP_ZR = 128;
+
 template <int RP>
 __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
                                               cplx* __restrict__ drow, int* sing, int widx) {
-  constexpr int NW = 16, MB = 16, JT = 64, KR = 2 * MB;
-  constexpr int ZR = 64 * RP < 384 ? 64 * RP : 384;
+  constexpr int NW = 16, MS = GJP_MS, MB = GJP_MB, JT = GJP_JT, KR = GJP_KR, ZR = GJP_ZR;
   extern __shared__ __align__(16) char smem[];
-  double* Zt = reinterpret_cast<double*>(smem);    // [KR][ZR]: k' < 16 Re Z, else Im Z
+  double* Zt = reinterpret_cast<double*>(smem);    // [KR][ZR]: k' < MB Re Z, else Im Z
   cplx* ucol = reinterpret_cast<cplx*>(smem);      // [2][64 RP] during the pivot steps
   double* Yr = Zt + (size_t)KR * ZR;               // [KR][JT]: Re Y ; -Im Y
   double* Yi = Yr + KR * JT;                       // [KR][JT]: Im Y ;  Re Y
@@ -380,23 +384,63 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
     wk = {pv.re + 1.0, pv.im};
   };
 
-  for (int k0 = 0; k0 < n; k0 += MB) {
-    const int mb = min(MB, n - k0);
-    const bool hascol = v < mb;
-    const int jc = k0 + v;
-    __syncthreads();  // the previous panel's update is complete
-    cplx pm[RP];
-    {
-      const int lo = opaque_i(l);
+  auto load_col = [&](cplx (&pm)[RP], int jc) {
+    const int lo = opaque_i(l);
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const int i = lo + 64 * a;
+      pm[a] = i < n ? A[(size_t)i * n + jc] : cplx{0.0, 0.0};
+    }
+  };
+  auto store_col = [&](const cplx (&pm)[RP], int jc) {
+    const int lo = opaque_i(l);
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const int i = lo + 64 * a;
+      if (i < n) A[(size_t)i * n + jc] = pm[a];
+    }
+  };
+  // The deferred update of one column jc held in pm by the steps z0 .. z0 +
+  // zs - 1 (already swept, their columns in A):
+  //   pm[i] += sum_b (A[i][z0 + b] - [i == piv[z0 + b]]) A[piv[z0 + b]][jc],
+  // the second factor read from A, which still holds the column before it.
+  auto defer = [&](cplx (&pm)[RP], int jc, int z0, int zs) {
+    const int lo = opaque_i(l);
+    for (int b0 = 0; b0 < zs; b0 += 4) {
+      cplx y[4];
+      int pr[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int b = b0 + q;
+        pr[q] = b < zs ? piv[z0 + b] : -1;
+        y[q] = b < zs ? A[(size_t)pr[q] * n + jc] : cplx{0.0, 0.0};
+      }
 #pragma unroll
       for (int a = 0; a < RP; ++a) {
         const int i = lo + 64 * a;
-        pm[a] = (hascol && i < n) ? A[(size_t)i * n + jc] : cplx{0.0, 0.0};
+        if (i >= n) continue;
+        cplx acc = pm[a];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (b0 + q >= zs) continue;
+          cplx z = A[(size_t)i * n + z0 + b0 + q];
+          if (i == pr[q]) z.re -= 1.0;
+          acc.re = fma(z.re, y[q].re, acc.re);
+          acc.re = fma(-z.im, y[q].im, acc.re);
+          acc.im = fma(z.re, y[q].im, acc.im);
+          acc.im = fma(z.im, y[q].re, acc.im);
+        }
+        pm[a] = acc;
       }
     }
-    if (v == 0) choose(pm, k0, k0 & 1);
-    for (int kk = 0; kk < mb; ++kk) {
-      const int k = k0 + kk, par = k & 1;
+  };
+  // The pivot steps s0 .. s0 + ms - 1 on their columns, held by waves v < ms
+  // in pm; each wave's column goes back to A afterwards.
+  auto sweep = [&](cplx (&pm)[RP], int s0, int ms) {
+    const bool hascol = v < ms;
+    if (v == 0) choose(pm, s0, s0 & 1);
+    for (int kk = 0; kk < ms; ++kk) {
+      const int k = s0 + kk, par = k & 1;
       __syncthreads();  // u, p of column k published
       const int p = __builtin_amdgcn_readfirstlane(prow[par]);
       const int pl = p & 63, pa = p >> 6;
@@ -420,15 +464,34 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
           // keep the scheduler from hoisting all RP loads of u at once
           if ((a & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
-        if (kk + 1 < mb && v == kk + 1) choose(pm, k + 1, par ^ 1);
+        if (kk + 1 < ms && v == kk + 1) choose(pm, k + 1, par ^ 1);
       }
     }
-    if (hascol) {
-      const int lo = opaque_i(l);
-#pragma unroll
-      for (int a = 0; a < RP; ++a) {
-        const int i = lo + 64 * a;
-        if (i < n) A[(size_t)i * n + jc] = pm[a];
+    if (hascol) store_col(pm, s0 + v);
+  };
+
+  for (int k0 = 0; k0 < n; k0 += MB) {
+    const int mb = min(MB, n - k0);
+    const int ms1 = min(MS, mb), ms2 = mb - ms1;
+    __syncthreads();  // the previous panel's update is complete
+    cplx pm[RP];
+    // first sub-panel
+    if (v < ms1) load_col(pm, k0 + v);
+    sweep(pm, k0, ms1);
+    if (ms2 > 0) {
+      __syncthreads();  // its swept columns in A; pivot buffers free
+      // second sub-panel: the first one's update, then its own steps
+      if (v < ms2) {
+        load_col(pm, k0 + ms1 + v);
+        defer(pm, k0 + ms1 + v, k0, ms1);
+      }
+      sweep(pm, k0 + ms1, ms2);
+      __syncthreads();  // its swept columns in A
+      // the first sub-panel's columns: the second one's update
+      if (v < ms1) {
+        load_col(pm, k0 + v);
+        defer(pm, k0 + v, k0 + ms1, ms2);
+        store_col(pm, k0 + v);
       }
     }
     __syncthreads();  // swept panel in memory; pivot buffers free
@@ -445,7 +508,7 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
     };
     auto load_z = [&](int r0) {
       for (int e = tid; e < ZR * MB; e += 1024) {
-        const int r = e >> 4, a = e & 15, i = r0 + r;
+        const int r = e / MB, a = e % MB, i = r0 + r;
         const cplx z =
             (i < n && a < mb && !is_piv(i)) ? A[(size_t)i * n + k0 + a] : cplx{0.0, 0.0};
         Zt[a * ZR + r] = z.re;
@@ -456,7 +519,7 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
     // subtracted at (r, r)
     auto load_zp = [&]() {
       for (int e = tid; e < ZR * MB; e += 1024) {
-        const int r = e >> 4, a = e & 15;
+        const int r = e / MB, a = e % MB;
         cplx z = {0.0, 0.0};
         if (r < mb && a < mb) {
           z = A[(size_t)piv[k0 + r] * n + k0 + a];
@@ -512,7 +575,7 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
           A[(size_t)i * n + j] = t;
         }
     };
-    constexpr int NRB = (ZR + 31) / 32, NU = NRB * (JT / 16);
+    constexpr int NRB = ZR / 32, NU = NRB * (JT / 16);
     for (int c = 0; c < nch; ++c) {
       __syncthreads();  // the previous chunk's Z reads done
       load_z(c * ZR);
@@ -575,8 +638,9 @@ __global__ void __launch_bounds__(1024) k_gj_panel_jobs(const GjJob* __restrict_
 }
 
 size_t gj_panel_lds(int n, int rp) {
-  const int zr = 64 * rp < 384 ? 64 * rp : 384;
-  return sizeof(double) * ((size_t)32 * zr + 2 * 32 * 64) + sizeof(int) * 2 * (size_t)n;
+  (void)rp;
+  return sizeof(double) * ((size_t)GJP_KR * GJP_ZR + 2 * GJP_KR * GJP_JT) +
+         sizeof(int) * 2 * (size_t)n;
 }
 
 __global__ void k_nolfe(const cplx* eps, int n, int n_w, cplx* diag, int* sing, int w_base) {
