@@ -340,9 +340,8 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
   extern __shared__ __align__(16) char smem[];
   double* Zt = reinterpret_cast<double*>(smem);    // [KR][ZR]: k' < MB Re Z, else Im Z
   cplx* ucol = reinterpret_cast<cplx*>(smem);      // [2][64 RP] during the pivot steps
-  double* Yr = Zt + (size_t)KR * ZR;               // [KR][JT]: Re Y ; -Im Y
-  double* Yi = Yr + KR * JT;                       // [KR][JT]: Im Y ;  Re Y
-  int* piv = reinterpret_cast<int*>(Yi + KR * JT);  // [n] pivot row of step k
+  cplx* Ys = reinterpret_cast<cplx*>(Zt + (size_t)KR * ZR);  // [2][MB][JT]: Y tiles
+  int* piv = reinterpret_cast<int*>(Ys + 2 * MB * JT);  // [n] pivot row of step k
   int* sor = piv + n;                               // [n] step of pivot row i
   __shared__ int prow[2];
   const int tid = threadIdx.x, l = tid & 63;
@@ -529,30 +528,40 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
         Zt[(MB + a) * ZR + r] = z.im;
       }
     };
-    auto load_y = [&](int jt) {
-      for (int e = tid; e < MB * JT; e += 1024) {
-        const int a = e / JT, c = e % JT, j = jt + c;
-        const cplx y = (a < mb && j < n) ? A[(size_t)piv[k0 + a] * n + j] : cplx{0.0, 0.0};
-        Yr[a * JT + c] = y.re;
-        Yr[(MB + a) * JT + c] = -y.im;
-        Yi[a * JT + c] = y.im;
-        Yi[(MB + a) * JT + c] = y.re;
+    // Y tile of columns jt ..: two elements per thread, loaded into registers
+    // a tile ahead and stored into the other buffer after this tile's MFMAs
+    constexpr int YE = MB * JT / 1024;
+    cplx yreg[YE];
+    auto y_load = [&](int jt) {
+#pragma unroll
+      for (int q = 0; q < YE; ++q) {
+        const int e = tid + 1024 * q, a = e / JT, c = e % JT, j = jt + c;
+        yreg[q] = (a < mb && j < n) ? A[(size_t)piv[k0 + a] * n + j] : cplx{0.0, 0.0};
       }
+    };
+    auto y_store = [&](int buf) {
+#pragma unroll
+      for (int q = 0; q < YE; ++q) Ys[buf * MB * JT + tid + 1024 * q] = yreg[q];
     };
     const int li = l & 15, lk = l >> 4;
     // one 32 x 16 output block: rows r0 + 32 rb .. (the pivot rows of steps
-    // k0 + 32 rb .. in the pivot pass), columns jt + 16 cb ..
-    auto block = [&](int r0, int rb, int jt, int cb, bool pivot_pass) {
+    // k0 + 32 rb .. in the pivot pass), columns jt + 16 cb ..  The B operands
+    // come from the stored Y: rows kr < MB give Re Y (for Re T) and Im Y (for
+    // Im T), rows kr >= MB give -Im Y and Re Y.
+    auto block = [&](int r0, int rb, int jt, int cb, int buf, bool pivot_pass) {
       f64x4 acc[2][2];
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
         acc[rt][0] = f64x4{0.0, 0.0, 0.0, 0.0};
         acc[rt][1] = f64x4{0.0, 0.0, 0.0, 0.0};
       }
+      const cplx* Yb = Ys + buf * MB * JT;
 #pragma unroll 2
       for (int s = 0; s < KR / 4; ++s) {
         const int kr = 4 * s + lk;
-        const double br = Yr[kr * JT + 16 * cb + li], bi = Yi[kr * JT + 16 * cb + li];
+        const cplx y = Yb[(kr % MB) * JT + 16 * cb + li];
+        const bool lower = 4 * s < MB;  // wave-uniform
+        const double br = lower ? y.re : -y.im, bi = lower ? y.im : y.re;
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
           const double za = Zt[kr * ZR + 32 * rb + 16 * rt + li];
@@ -575,25 +584,33 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
           A[(size_t)i * n + j] = t;
         }
     };
-    constexpr int NRB = ZR / 32, NU = NRB * (JT / 16);
-    for (int c = 0; c < nch; ++c) {
-      __syncthreads();  // the previous chunk's Z reads done
-      load_z(c * ZR);
+    // the column tiles of one pass (rows r0 .. of Z in Zt, or the pivot
+    // rows): Y of the first tile staged beforehand, one barrier per tile
+    auto pass = [&](int r0, bool pivot_pass) {
+      y_load(0);
+      y_store(0);
+      __syncthreads();  // Z and the first Y tile staged
+      int buf = 0;
       for (int jt = 0; jt < n; jt += JT) {
-        __syncthreads();  // Z staged; the previous tile's Y reads done
-        load_y(jt);
-        __syncthreads();  // Y staged
-        for (int u = v; u < NU; u += NW) block(c * ZR, u % NRB, jt, u / NRB, false);
+        const bool more = jt + JT < n;
+        if (more) y_load(jt + JT);
+        constexpr int NRB = ZR / 32, NU = NRB * (JT / 16);
+        if (pivot_pass) {
+          for (int u = v; u < JT / 16; u += NW) block(0, 0, jt, u, buf, true);
+        } else {
+          for (int u = v; u < NU; u += NW) block(r0, u % NRB, jt, u / NRB, buf, false);
+        }
+        if (more) y_store(buf ^ 1);
+        __syncthreads();  // this tile's Y reads and updates done; the next Y staged
+        buf ^= 1;
       }
+    };
+    for (int c = 0; c < nch; ++c) {
+      load_z(c * ZR);
+      pass(c * ZR, false);
     }
-    __syncthreads();  // the chunk passes' Z reads done
     load_zp();
-    for (int jt = 0; jt < n; jt += JT) {
-      __syncthreads();  // Z staged; the previous tile's Y reads done
-      load_y(jt);
-      __syncthreads();  // Y staged
-      for (int u = v; u < JT / 16; u += NW) block(0, 0, jt, u, true);
-    }
+    pass(0, true);
   }
   __syncthreads();
   for (int k = tid; k < n; k += 1024) drow[k] = A[(size_t)piv[k] * n + sor[k]];
@@ -639,7 +656,7 @@ __global__ void __launch_bounds__(1024) k_gj_panel_jobs(const GjJob* __restrict_
 
 size_t gj_panel_lds(int n, int rp) {
   (void)rp;
-  return sizeof(double) * ((size_t)GJP_KR * GJP_ZR + 2 * GJP_KR * GJP_JT) +
+  return sizeof(double) * (size_t)GJP_KR * GJP_ZR + sizeof(cplx) * 2 * GJP_MB * GJP_JT +
          sizeof(int) * 2 * (size_t)n;
 }
 
