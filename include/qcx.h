@@ -27,7 +27,7 @@
  *     synchronise it; all others are asynchronous.
  *   - Calls that stage host data (qcx_set_cell_basis, qcx_set_states,
  *     qcx_pair_density*, qcx_chi0, qcx_chi0_kk, qcx_loss_diag, qcx_qbin_add /
- *     _finish / _rate_halo, and qcx_run_batch when it builds a plan) return
+ *     _finish / _rate_halo, and qcx_run_batch[_rho] when it builds a plan) return
  *     QCX_EINVAL while the context's stream is being captured into a graph.
  *   - A context is not thread-safe; use one context per host thread.
  *   - The call order is qcx_set_cell_basis -> qcx_set_states ->
@@ -344,6 +344,27 @@ typedef struct qcx_item {
  * without pair densities), QCX_ENOMEM, QCX_EDEVICE. */
 int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_items,
                   int precision, int headwings_fp64, int lfe);
+/* qcx_run_batch with the pair densities of Eq. (RPA) computed inside the
+ * batch: for every context c, the G list G_int[c] (host [n_G[c]][3] integer
+ * coordinates in the reciprocal basis, G = 0 first, 1 <= n_G[c] <= 1024 with
+ * lfe, 4096 without) replaces a qcx_pair_density call.  Every context needs
+ * states (qcx_set_states, host or device) and may appear only once in ctxs.
+ * q + G, the Coulomb factors, the cell Fourier integrals and the densities
+ * (27-cell Bloch sum and band contraction of Sec. III) are part of the
+ * captured plan; the q of each context is read from the device copy that
+ * qcx_set_states makes, so new states of the same shapes, including a new q,
+ * are picked up by the replay.  The G lists and the shapes of the states are
+ * part of the plan's signature.  A vanishing q + G is rejected on the host
+ * (QCX_EINVAL) from the q last set.  On return (and on success) each
+ * context holds the pair densities of its G list, as after qcx_pair_density
+ * (usable by qcx_chi0 etc. once the batch has run on the device).  With
+ * timing on, t[0] is the pair densities of all contexts.  Arrays n_G and
+ * G_int have n_ctx entries; the rest is as for qcx_run_batch.
+ * Errors: as qcx_run_batch, and QCX_ESTATE (a context without states),
+ * QCX_EINVAL (G lists, a context listed twice). */
+int qcx_run_batch_rho(qcx_ctx* const* ctxs, int n_ctx, const int* n_G, const int* const* G_int,
+                      const qcx_item* items, int n_items, int precision, int headwings_fp64,
+                      int lfe);
 int qcx_batch_sync(qcx_ctx* ctx);
 /* Plan of the last batch run on ctx (the ctxs[0] of qcx_run_batch):
  * cfg = {target MFMA steps per K split, tiles in the persistent list, blocks

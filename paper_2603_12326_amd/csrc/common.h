@@ -111,6 +111,17 @@ void launch_state_flags(const double* Ek, const double* Ekq, int n_k, int n_b, i
 void launch_orth_check(const cplx* S, const cplx* C, int n_ao, int n_b, int n_k, double* dev,
                        hipStream_t st);
 size_t band_contract_lds(int n_ao, int n_b, int n_occ);
+// 3x3 matrix passed by value to a kernel
+struct Mat3 {
+  double m[9];
+};
+// Q[g] = q + G_g (G_int[g] in reciprocal-vector units, rec rows b_j) and
+// vq[g] = sqrt(4 pi)/|Q[g]| (the G = 0 row sqrt(4 pi) in the optical limit);
+// q is read from device memory
+void launch_q_plus_g(const double* q, const int* G_int, const double rec[9], int n_g, bool optical,
+                     double* Q, double* vq, hipStream_t st);
+// zero columns n_t .. ldt-1 of the n_g rows of R
+void launch_zero_tail(cplx* R, size_t ldt, int n_t, int n_g, hipStream_t st);
 
 // chi0 pieces
 struct Chi0Geom {
@@ -136,6 +147,12 @@ void launch_weights_bf16(const double* w, const double* dt, double eta, const Ch
 void launch_pack_r32(const cplx* R, size_t ldt, const Chi0Geom& g, int perm, float* R32,
                      hipStream_t st);
 constexpr int KSTEP_T = 16;  // transitions per bulk K step (one MFMA K block)
+// Largest K split of a bulk launch; the bulk's operands are padded to
+// KSTEP_T * kMaxKsplit transitions, and the pair-density rows R[g][t] have a
+// stride (ldt) of at least n_t + 16 rounded up to that padding, with zeros past
+// n_t, so that every padded or chunked reader stays inside its own row.
+constexpr int kMaxKsplit = 64;
+constexpr int kLdtAlign = KSTEP_T * kMaxKsplit;
 // Row-gather mode of the bulk kernel: a tile of 128 consecutive upper-triangle
 // pairs touches at most 129 distinct G (checked when the tables are built),
 // so for large N_G each tile stages only its own slab rows, listed in

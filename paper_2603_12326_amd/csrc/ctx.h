@@ -54,7 +54,7 @@ struct qcx_ctx {
   bool have_rho = false;
   int n_g = 0;
   size_t ldt = 0;
-  DevBuf d_Q, d_vq, d_F, d_M, d_R;
+  DevBuf d_qc, d_G, d_Q, d_vq, d_F, d_M, d_R;  // q (set by qcx_set_states), G list, q + G, ...
 
   // chi0
   bool have_chi0 = false;
@@ -125,7 +125,7 @@ struct qcx_ctx {
   std::vector<DevBuf*> buffers() {
     return {&d_sh_l, &d_sh_ex, &d_sh_ctr, &d_sh_off, &d_cells, &d_tvec, &d_shp, &d_kf,
                      &d_Ck,   &d_Ek,    &d_Ckq,    &d_Ekq,    &d_dt,    &d_ph,   &d_phq,
-                     &d_S,    &d_F0,    &d_dev,    &d_flags,    &d_Q,      &d_vq,    &d_F,    &d_M,
+                     &d_S,    &d_F0,    &d_dev,    &d_flags,    &d_qc, &d_G, &d_Q,      &d_vq,    &d_F,    &d_M,
                      &d_R,    &d_w,     &d_A,      &d_Alo,    &d_R32,   &d_pairs, &d_rows, &d_pairs64, &d_C, &d_C64,
                      &d_XY,   &d_hwP,   &d_eps,    &d_diag,   &d_epsM,  &d_loss,  &d_sing,
                      &d_kk_rank, &d_kk_ib, &d_kk_xf, &d_kk_chunks, &d_kk_Rs, &d_kk_S, &d_kk_K,
@@ -158,6 +158,14 @@ namespace qcx {
 
 // deferred state checks of device-resident inputs (qcx_runtime.hip)
 int check_deferred(qcx_ctx* ctx);
+// Pair densities in two parts (qcx_runtime.hip): rho_prepare checks a G list
+// on the host against the context's q (G = 0 first, q + G nonzero unless
+// optical) and reserves the buffers for n_G rows; rho_enqueue launches
+// kernels only (q + G and Coulomb factors from the device copy of q and the
+// device G list, tail zeroing, cell Fourier integrals, densities), so that
+// it can be captured into a graph.
+int rho_prepare(qcx_ctx* ctx, int n_G, const int* G_int, bool need_g0, bool optical);
+int rho_enqueue(qcx_ctx* ctx, const int* d_G, int n_G, bool optical, hipStream_t st);
 // address of the no-allocation scratch array on `device`, looked up once per
 // device with that device current (qcx_noalloc.hip)
 hipError_t noalloc_init(int device);

@@ -923,6 +923,50 @@ void launch_state_flags(const double* Ek, const double* Ekq, int n_k, int n_b, i
                      tol, flags);
 }
 
+// Q = q + G in Cartesian coordinates (G = sum_j n_j b_j, the reciprocal
+// vectors b_j being the rows of rec) and the symmetrised Coulomb factor
+// v_G = sqrt(4 pi)/|q + G| of every row (Eq. RPA).  In the optical limit the
+// G = 0 row keeps sqrt(4 pi) alone: its 1/|q| goes into the k.p row.  The
+// host rejects a vanishing q + G before enqueueing; such a row would get 0.
+__global__ void k_q_plus_g(const double* __restrict__ q, const int* __restrict__ G, Mat3 rec,
+                           int n_g, int optical, double* __restrict__ Q, double* __restrict__ vq) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_g) return;
+  double n2 = 0.0;
+  for (int x = 0; x < 3; ++x) {
+    double v = q[x];
+    for (int j = 0; j < 3; ++j) v += G[3 * g + j] * rec.m[3 * j + x];
+    Q[3 * g + x] = v;
+    n2 += v * v;
+  }
+  const double s4pi = sqrt(4.0 * kPi);
+  vq[g] = (optical && g == 0) ? s4pi : (n2 > 0.0 ? s4pi / sqrt(n2) : 0.0);
+}
+
+// Zero the columns n_t..ldt-1 of every row of R[n_g][ldt] (readers that work
+// in K chunks run past n_t into them)
+__global__ void k_zero_tail(cplx* R, size_t ldt, int n_t, int n_g) {
+  const size_t tail = ldt - n_t;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tail * n_g) return;
+  R[(i / tail) * ldt + n_t + i % tail] = cplx{0.0, 0.0};
+}
+
+void launch_q_plus_g(const double* q, const int* G, const double rec[9], int n_g, bool optical,
+                     double* Q, double* vq, hipStream_t st) {
+  Mat3 r;
+  for (int i = 0; i < 9; ++i) r.m[i] = rec[i];
+  hipLaunchKernelGGL(k_q_plus_g, dim3((n_g + 255) / 256), dim3(256), 0, st, q, G, r, n_g,
+                     optical ? 1 : 0, Q, vq);
+}
+
+void launch_zero_tail(cplx* R, size_t ldt, int n_t, int n_g, hipStream_t st) {
+  const size_t n = (ldt - n_t) * (size_t)n_g;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_zero_tail, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, R, ldt, n_t,
+                     n_g);
+}
+
 void launch_orth_check(const cplx* S, const cplx* C, int n_ao, int n_b, int n_k, double* dev,
                        hipStream_t st) {
   const size_t lds = sizeof(cplx) * ((size_t)n_ao * n_ao + 2 * (size_t)n_ao * n_b);

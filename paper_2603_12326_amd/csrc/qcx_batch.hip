@@ -1,14 +1,19 @@
 // Batched path for many uneven (cell, q, frequency list, N_G) items.
 //
-// The pair densities of each item come from its own context (qcx_pair_density
-// already called).  A plan is built once per batch signature: per-item
+// The pair densities of each context either come from the context itself
+// (qcx_run_batch: qcx_pair_density already called) or are computed inside the
+// plan from a G list per context (qcx_run_batch_rho: q + G and Coulomb factors
+// from the device copy of q, cell Fourier integrals, fused Bloch sum and band
+// contraction, all captured; new states set on the contexts between calls are
+// picked up by the next replay).  A plan is built once per batch signature: per-item
 // weights, R32 packs per context, pair tables, one tile list for the
 // persistent bulk kernel (ordered by decreasing cost, so that small items fill
 // the gaps left by large ones), per-item FP64 head/wings, and per-item
 // assembly, inversion (one launch per inversion kernel class, covering every
-// item of that class) and loss.  The sequence is captured into three hipGraphs
-// (operand preparation, the persistent bulk launch, everything after it) so
-// that the bulk kernel can be timed on its own; later calls with the same
+// item of that class) and loss.  The sequence is captured into up to four
+// hipGraphs (pair densities, operand preparation, the persistent bulk launch,
+// everything after it) so that the stages can be timed on their own; later
+// calls with the same
 // signature replay them.  Capture records kernels only (counters and flags are
 // reset by a one-thread kernel, not by memset nodes).
 //
@@ -40,7 +45,8 @@ struct BatchPlan {
   std::vector<PlanItem> items;
   std::vector<DevBuf> r32;  // per context
   DevBuf d_items, d_tiles, d_counter, d_sing;
-  DevBuf hwP;  // pair-product table of the head/wing GEMMs (items run one after another)
+  static constexpr int kBranches = 4;  // parallel paths of a graph (see capture)
+  DevBuf hwP[kBranches];  // pair-product tables of the head/wing GEMMs, one per path
   // multi-item inversion launches, one per kernel class present
   struct GjGroup {
     int cls = 0, n_jobs = 0, n_blocks = 0, max_n = 0;
@@ -50,10 +56,13 @@ struct BatchPlan {
   int n_tiles = 0, max_ng = 0, target_steps = 0, grid = 0;
   double tune_ms = 0.0;
   bool gather = false;
-  hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
-  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+  bool rho = false;         // pair densities inside the plan (graph 0)
+  std::vector<DevBuf> gs;   // per context: its G list (rho plans)
+  static constexpr int kGraphs = 4;
+  hipGraph_t graph[kGraphs] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[kGraphs] = {nullptr, nullptr, nullptr, nullptr};
   ~BatchPlan() {
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < kGraphs; ++i) {
       if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
       if (graph[i]) (void)hipGraphDestroy(graph[i]);
     }
@@ -63,10 +72,11 @@ struct BatchPlan {
       for (DevBuf* x : b) x->release();
     }
     for (DevBuf& b : r32) b.release();
+    for (DevBuf& b : gs) b.release();
     for (GjGroup& g : gj) g.jobs.release();
     d_items.release();
     d_tiles.release();
-    hwP.release();
+    for (DevBuf& b : hwP) b.release();
     d_counter.release();
     d_sing.release();
   }
@@ -76,10 +86,15 @@ void destroy_plan(BatchPlan* p) { delete p; }
 
 namespace {
 
+// Everything a plan's graphs bake in: buffer addresses, shapes, frequencies,
+// output addresses, and for rho plans the G lists and what the pair-density
+// kernels read (basis and state buffers, reciprocal vectors, M chunk buffer)
 std::vector<double> batch_key(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_items,
-                              int precision, int lfe, int hw64) {
+                              int precision, int lfe, int hw64, const int* n_G,
+                              const int* const* G_int) {
   std::vector<double> k = {(double)n_items, (double)precision, (double)lfe, (double)hw64,
-                           (double)n_ctx};
+                           (double)n_ctx, n_G ? 1.0 : 0.0};
+  auto ptr = [&](const DevBuf& b) { k.push_back((double)(uintptr_t)b.p); };
   for (int c = 0; c < n_ctx; ++c) {
     const qcx_ctx* x = ctxs[c];
     k.push_back((double)(uintptr_t)x);
@@ -91,6 +106,15 @@ std::vector<double> batch_key(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* i
     k.push_back((double)x->ldt);
     k.push_back((double)x->n_k);
     k.push_back(x->vol);
+    if (!n_G) continue;
+    for (const DevBuf* b : {&x->d_qc, &x->d_Q, &x->d_F, &x->d_M, &x->d_Ck, &x->d_Ckq, &x->d_ph,
+                            &x->d_shp, &x->d_tvec, &x->d_sh_l, &x->d_sh_ex, &x->d_sh_ctr,
+                            &x->d_sh_off})
+      ptr(*b);
+    k.push_back((double)x->d_M.bytes);
+    for (int v : {x->n_cells, x->n_sh, x->n_ao, x->n_b, x->n_occ}) k.push_back((double)v);
+    for (int i = 0; i < 9; ++i) k.push_back(x->rec[i]);
+    for (int i = 0; i < 3 * n_G[c]; ++i) k.push_back((double)G_int[c][i]);
   }
   for (int i = 0; i < n_items; ++i) {
     k.push_back((double)items[i].ctx);
@@ -107,28 +131,79 @@ std::vector<double> batch_key(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* i
 // than 1024 steps in FP32 (the splits are added in FP64 by the assembly).
 int ksplit_for(int ntb, int target_steps) {
   int ks = 1;
-  while (ks < 64 && ntb / (2 * ks) >= target_steps) ks *= 2;
-  while (ks < 64 && ntb > ks * 1024) ks *= 2;
+  while (ks < kMaxKsplit && ntb / (2 * ks) >= target_steps) ks *= 2;
+  while (ks < kMaxKsplit && ntb > ks * 1024) ks *= 2;
   return ks;
 }
 
-// Capture the work enqueued by fn on a private stream into P->graph[i] and
-// instantiate it (the caller's stream may be the legacy default stream, which
-// cannot be captured).
+// Streams of one capture: the capturing stream and kBranches streams forked
+// from it.  Work enqueued on different branches between a fork() and the next
+// join() forms independent paths of the graph (no order between them), so
+// that small per-item kernels can overlap; join() makes the main stream wait
+// for every branch (nothing if none was forked).
+struct Branches {
+  hipStream_t main = nullptr;
+  hipStream_t br[BatchPlan::kBranches] = {};
+  std::vector<hipEvent_t> events;
+  hipError_t err = hipSuccess;
+  bool forked = false;
+  hipStream_t operator[](int i) const { return br[i % BatchPlan::kBranches]; }
+  void chk(hipError_t e) {
+    if (err == hipSuccess) err = e;
+  }
+  hipEvent_t event() {
+    hipEvent_t ev = nullptr;
+    chk(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    events.push_back(ev);
+    return ev;
+  }
+  void fork() {
+    hipEvent_t ev = event();
+    chk(hipEventRecord(ev, main));
+    for (hipStream_t b : br) chk(hipStreamWaitEvent(b, ev, 0));
+    forked = true;
+  }
+  void join() {
+    if (!forked) return;
+    forked = false;
+    for (hipStream_t b : br) {
+      hipEvent_t ev = event();
+      chk(hipEventRecord(ev, b));
+      chk(hipStreamWaitEvent(main, ev, 0));
+    }
+  }
+};
+
+// Capture the work enqueued by fn(Branches&) into P->graph[i] and
+// instantiate it; the capture runs on private streams (the caller's stream
+// may be the legacy default stream, which cannot be captured), and branches
+// left open by fn are joined at the end.
 template <class F>
 int capture(qcx_ctx* ctx, BatchPlan* P, int i, F&& fn) {
-  hipStream_t cap = nullptr;
-  HIPCK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  Branches B;
+  HIPCK(hipStreamCreateWithFlags(&B.main, hipStreamNonBlocking));
+  for (hipStream_t& b : B.br) B.chk(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+  auto cleanup = [&]() {
+    for (hipStream_t b : B.br)
+      if (b) (void)hipStreamDestroy(b);
+    (void)hipStreamDestroy(B.main);
+    for (hipEvent_t ev : B.events) (void)hipEventDestroy(ev);
+  };
+  hipError_t e = B.err != hipSuccess ? B.err : hipStreamBeginCapture(B.main, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
-    (void)hipStreamDestroy(cap);
+    cleanup();
     return fail(ctx, QCX_EDEVICE, std::string("begin capture: ") + hipGetErrorString(e));
   }
-  fn(cap);
+  fn(B);
+  B.join();
   hipGraph_t graph = nullptr;
-  e = hipStreamEndCapture(cap, &graph);
-  (void)hipStreamDestroy(cap);
-  if (e != hipSuccess) return fail(ctx, QCX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipStreamEndCapture(B.main, &graph);
+  if (e == hipSuccess) e = B.err;
+  cleanup();
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(ctx, QCX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  }
   P->graph[i] = graph;
   e = hipGraphInstantiate(&P->exec[i], graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return fail(ctx, QCX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
@@ -136,24 +211,28 @@ int capture(qcx_ctx* ctx, BatchPlan* P, int i, F&& fn) {
 }
 
 // Replay a plan on the context's stream; timed spans (when timing is on):
-// stage 1 the persistent bulk launch, stage 4 head/wings + assembly +
-// inversion + loss, stage 3 the whole batch.
+// stage 0 the pair densities (rho plans), stage 1 the persistent bulk launch,
+// stage 4 head/wings + assembly + inversion + loss, stage 3 the whole batch.
 hipError_t launch_plan(qcx_ctx* ctx, const BatchPlan* P) {
+  static constexpr int stage_of[BatchPlan::kGraphs] = {0, -1, 1, 4};
   int sp_all = -1, sp = -1;
   hipError_t e = span_begin(ctx, 3, &sp_all);
   if (e != hipSuccess) return e;
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < BatchPlan::kGraphs; ++i) {
     if (!P->exec[i]) continue;
-    if (i > 0 && (e = span_begin(ctx, i == 1 ? 1 : 4, &sp)) != hipSuccess) return e;
+    const bool span = stage_of[i] >= 0;
+    if (span && (e = span_begin(ctx, stage_of[i], &sp)) != hipSuccess) return e;
     if ((e = hipGraphLaunch(P->exec[i], ctx->stream)) != hipSuccess) return e;
-    if (i > 0 && (e = span_end(ctx, sp)) != hipSuccess) return e;
+    if (span && (e = span_end(ctx, sp)) != hipSuccess) return e;
   }
   return span_end(ctx, sp_all);
 }
 
 int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_items,
-               int precision, int lfe, int hw64, int target_steps, BatchPlan* P) {
+               int precision, int lfe, int hw64, int target_steps, const int* n_G,
+               const int* const* G_int, BatchPlan* P) {
   hipStream_t st = ctx->stream;
+  P->rho = n_G != nullptr;
   P->target_steps = target_steps;
   P->precision = precision;
   P->lfe = lfe;
@@ -172,6 +251,10 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
     for (int i = 0; i < n_items; ++i)
       P->gather = P->gather || ctxs[items[i].ctx]->n_g >= kGatherMinNg;
   HIPCK(stage_begin(ctx));
+  if (P->rho) {
+    P->gs.resize(n_ctx);
+    for (int c = 0; c < n_ctx; ++c) HIPCK(upload(ctx, P->gs[c], G_int[c], 3 * (size_t)n_G[c]));
+  }
   for (int i = 0; i < n_items; ++i) {
     PlanItem& it = P->items[i];
     const qcx_item& in = items[i];
@@ -232,7 +315,7 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
     if (it.n_pairs64 > 0) {
       if (it.n_pairs64 == c->n_g) {
         geom_hw_init(it.g64, c->n_g, in.n_w, c->n_t, it.n_pairs64, (size_t)256 << 20);
-        HIPCK(P->hwP.reserve(sizeof(double) * hw_ptable_doubles(it.g64)));
+        HIPCK(P->hwP[i % BatchPlan::kBranches].reserve(sizeof(double) * hw_ptable_doubles(it.g64)));
       } else {
         geom64_init(it.g64, c->n_g, in.n_w, c->n_t, it.n_pairs64, (size_t)256 << 20);
       }
@@ -302,15 +385,27 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
   HIPCK(hipStreamSynchronize(st));  // uploads complete before capture begins
 
   P->grid = std::min(P->n_tiles, 2 * 256);
+  if (P->rho) {
+    int rc_in = QCX_OK, c_bad = 0;
+    int rc = capture(ctx, P, 0, [&](Branches& B) {
+      B.fork();
+      for (int c = 0; c < n_ctx && rc_in == QCX_OK; ++c)
+        if ((rc_in = rho_enqueue(ctxs[c], P->gs[c].as<int>(), n_G[c], false, B[c])) != QCX_OK) c_bad = c;
+    });
+    if (rc != QCX_OK) return rc;
+    if (rc_in != QCX_OK)
+      return fail(ctx, rc_in, "context " + std::to_string(c_bad) + ": " + ctxs[c_bad]->err);
+  }
   if (bulk) {
-    int rc = capture(ctx, P, 0, [&](hipStream_t cs) {
+    int rc = capture(ctx, P, 1, [&](Branches& B) {
+      B.fork();
       for (int c = 0; c < n_ctx; ++c) {
         if (ctx_ntp[c] == 0) continue;
         Chi0Geom gp{};
         gp.n_g = ctxs[c]->n_g;
         gp.n_tp = ctx_ntp[c];
         launch_pack_r32(ctxs[c]->d_R.as<cplx>(), ctxs[c]->ldt, gp, bf ? 0 : 1,
-                        P->r32[c].as<float>(), cs);
+                        P->r32[c].as<float>(), B[c]);
       }
       for (int i = 0; i < n_items; ++i) {
         PlanItem& it = P->items[i];
@@ -318,37 +413,37 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
         if (it.g.n_bulk == 0) continue;
         if (bf)
           launch_weights_bf16(it.w.as<double>(), c->d_dt.as<double>(), it.eta, it.g,
-                              it.A.as<uint16_t>(), it.Alo.as<uint16_t>(), cs);
+                              it.A.as<uint16_t>(), it.Alo.as<uint16_t>(), B[i]);
         else
           launch_weights_f32(it.w.as<double>(), c->d_dt.as<double>(), it.eta, it.g,
-                             it.A.as<float>(), cs);
+                             it.A.as<float>(), B[i]);
       }
     });
     if (rc != QCX_OK) return rc;
   }
   if (P->n_tiles > 0) {
-    int rc = capture(ctx, P, 1, [&](hipStream_t cs) {
-      launch_set_int(P->d_counter.as<int>(), 0, cs);
+    int rc = capture(ctx, P, 2, [&](Branches& B) {
+      launch_set_int(P->d_counter.as<int>(), 0, B.main);
       launch_bulk_persistent(bf, P->gather, P->d_items.as<BulkItem>(), P->d_tiles.as<int4>(),
-                             P->n_tiles, P->d_counter.as<int>(), P->max_ng, P->grid, cs);
+                             P->n_tiles, P->d_counter.as<int>(), P->max_ng, P->grid, B.main);
     });
     if (rc != QCX_OK) return rc;
   }
-  return capture(ctx, P, 2, [&](hipStream_t cs) {
+  return capture(ctx, P, 3, [&](Branches& B) {
+    // per item, each on one path: head/wings (or every pair in FP64), then
+    // the assembly of eps
+    B.fork();
     for (int i = 0; i < n_items; ++i) {
       PlanItem& it = P->items[i];
       qcx_ctx* c = ctxs[it.ctx];
+      hipStream_t cs = B[i];
       if (it.n_pairs64 > 0 && it.n_pairs64 == c->n_g)
         launch_headwings_f64(c->d_R.as<cplx>(), c->ldt, it.w.as<double>(), c->d_dt.as<double>(),
-                             it.eta, it.g64, it.pairs64.as<int>(), P->hwP.as<double>(),
-                             it.XY.as<double>(), cs);
+                             it.eta, it.g64, it.pairs64.as<int>(),
+                             P->hwP[i % BatchPlan::kBranches].as<double>(), it.XY.as<double>(), cs);
       else if (it.n_pairs64 > 0)
         launch_pairs_f64(c->d_R.as<cplx>(), c->ldt, it.w.as<double>(), c->d_dt.as<double>(),
                          it.eta, it.g64, it.pairs64.as<int>(), it.XY.as<double>(), cs);
-    }
-    for (int i = 0; i < n_items; ++i) {
-      PlanItem& it = P->items[i];
-      qcx_ctx* c = ctxs[it.ctx];
       launch_set_int(P->d_sing.as<int>() + i, INT_MAX, cs);
       AsmArgs a{};
       a.C = (bulk && it.g.n_bulk > 0) ? it.C.as<float>() : nullptr;
@@ -362,6 +457,8 @@ int build_plan(qcx_ctx* ctx, qcx_ctx* const* ctxs, int n_ctx, const qcx_item* it
       a.pref = it.pref;
       launch_eps_assemble(a, it.g, it.eps.as<cplx>(), cs);
     }
+    B.join();
+    hipStream_t cs = B.main;
     if (lfe) {
       for (const BatchPlan::GjGroup& g : P->gj)
         launch_gj_jobs(g.cls, g.jobs.as<GjJob>(), g.n_jobs, g.n_blocks, g.max_n, cs);
@@ -405,13 +502,9 @@ int time_plan(qcx_ctx* ctx, const BatchPlan* P, double* ms) {
   return QCX_OK;
 }
 
-}  // namespace
-}  // namespace qcx
-
-extern "C" {
-
-int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_items,
-                  int precision, int headwings_fp64, int lfe) {
+// Both batch entry points; n_G and G_int are null for qcx_run_batch
+int run_batch_impl(qcx_ctx* const* ctxs, int n_ctx, const int* n_G, const int* const* G_int,
+                   const qcx_item* items, int n_items, int precision, int headwings_fp64, int lfe) {
   if (!ctxs || n_ctx < 1 || !ctxs[0]) return QCX_EINVAL;
   qcx_ctx* ctx = ctxs[0];
   if (!items || n_items < 1) return fail(ctx, QCX_EINVAL, "no items");
@@ -419,8 +512,17 @@ int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_
   for (int c = 0; c < n_ctx; ++c) {
     if (!ctxs[c]) return fail(ctx, QCX_EINVAL, "NULL context");
     if (ctxs[c]->device != ctx->device) return fail(ctx, QCX_EINVAL, "contexts on different devices");
-    if (!ctxs[c]->have_rho) return fail(ctx, QCX_ESTATE, "context " + std::to_string(c) + " has no pair densities");
-    if (lfe && ctxs[c]->n_g > 1024) return fail(ctx, QCX_EINVAL, "LFE inversion limited to n_G <= 1024");
+    const std::string cs = "context " + std::to_string(c);
+    for (int d = 0; d < c; ++d)
+      if (n_G && ctxs[d] == ctxs[c]) return fail(ctx, QCX_EINVAL, cs + " is listed twice");
+    if (n_G) {
+      if (!ctxs[c]->have_states) return fail(ctx, QCX_ESTATE, cs + " has no states");
+      if (!G_int[c]) return fail(ctx, QCX_EINVAL, cs + ": NULL G list");
+    } else if (!ctxs[c]->have_rho) {
+      return fail(ctx, QCX_ESTATE, cs + " has no pair densities");
+    }
+    const int ng = n_G ? n_G[c] : ctxs[c]->n_g;
+    if (lfe && ng > 1024) return fail(ctx, QCX_EINVAL, "LFE inversion limited to n_G <= 1024");
   }
   for (int i = 0; i < n_items; ++i) {
     const qcx_item& it = items[i];
@@ -432,8 +534,13 @@ int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_
       if (!std::isfinite(it.w_eV[j])) return fail(ctx, QCX_EINVAL, "non-finite frequency");
   }
   HIPCK(hipSetDevice(ctx->device));
+  // the G lists: host checks against each context's q, buffers sized
+  for (int c = 0; n_G && c < n_ctx; ++c)
+    if (int rc = rho_prepare(ctxs[c], n_G[c], G_int[c], true, false))
+      return fail(ctx, rc, "context " + std::to_string(c) + ": " + ctxs[c]->err);
   const int hw64 = headwings_fp64 ? 1 : 0;
-  std::vector<double> key = batch_key(ctxs, n_ctx, items, n_items, precision, lfe ? 1 : 0, hw64);
+  std::vector<double> key =
+      batch_key(ctxs, n_ctx, items, n_items, precision, lfe ? 1 : 0, hw64, n_G, G_int);
   // the other contexts' pair densities and energies were produced on their
   // own streams: the batch (on ctxs[0]'s stream) waits for them
   std::vector<hipStream_t> others;
@@ -459,7 +566,8 @@ int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_
     for (int target : cands) {
       BatchPlan* P = new BatchPlan();
       P->key = key;
-      int rc = build_plan(ctx, ctxs, n_ctx, items, n_items, precision, lfe ? 1 : 0, hw64, target, P);
+      int rc = build_plan(ctx, ctxs, n_ctx, items, n_items, precision, lfe ? 1 : 0, hw64, target,
+                          n_G, G_int, P);
       double ms = 0.0;
       if (rc == QCX_OK && cands.size() > 1) rc = time_plan(ctx, P, &ms);
       if (rc != QCX_OK) {
@@ -482,6 +590,7 @@ int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_
     ctx->plan = best;
   }
   HIPCK(launch_plan(ctx, ctx->plan));
+  for (int c = 0; n_G && c < n_ctx; ++c) ctxs[c]->have_rho = true;
   // and the other streams do not overwrite those buffers before the batch
   // has read them
   if (!others.empty()) {
@@ -490,6 +599,24 @@ int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_
     for (hipStream_t s : others) HIPCK(hipStreamWaitEvent(s, ctx->ev_order, 0));
   }
   return QCX_OK;
+}
+
+}  // namespace
+}  // namespace qcx
+
+extern "C" {
+
+int qcx_run_batch(qcx_ctx* const* ctxs, int n_ctx, const qcx_item* items, int n_items,
+                  int precision, int headwings_fp64, int lfe) {
+  return run_batch_impl(ctxs, n_ctx, nullptr, nullptr, items, n_items, precision, headwings_fp64, lfe);
+}
+
+int qcx_run_batch_rho(qcx_ctx* const* ctxs, int n_ctx, const int* n_G, const int* const* G_int,
+                      const qcx_item* items, int n_items, int precision, int headwings_fp64,
+                      int lfe) {
+  if (!ctxs || n_ctx < 1 || !ctxs[0]) return QCX_EINVAL;
+  if (!n_G || !G_int) return fail(ctxs[0], QCX_EINVAL, "NULL G lists");
+  return run_batch_impl(ctxs, n_ctx, n_G, G_int, items, n_items, precision, headwings_fp64, lfe);
 }
 
 int qcx_batch_config(qcx_ctx* ctx, int cfg[3], double* tune_ms) {

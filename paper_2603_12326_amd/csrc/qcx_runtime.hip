@@ -72,7 +72,6 @@ struct TuneVal {
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
 
-constexpr int kMaxKsplit = 64;
 // FP32 partial sums of one launch are kept within this budget; larger shapes
 // run in chunks of frequency rows, each reduced into FP64 partials
 constexpr size_t kPartialBudget = (size_t)8 << 30;
@@ -365,6 +364,7 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
   ctx->n_t = (int)n_t;
   const size_t ncoef = (size_t)n_k * ctx->n_ao * n_bands * 2;
   HIPCK(stage_begin(ctx));
+  HIPCK(upload(ctx, ctx->d_qc, q_cart, 3));
   HIPCK(upload(ctx, ctx->d_kf, k_frac, (size_t)n_k * 3, dev));
   HIPCK(upload(ctx, ctx->d_Ck, C_k, ncoef, dev));
   HIPCK(upload(ctx, ctx->d_Ckq, C_kq, ncoef, dev));
@@ -441,6 +441,85 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
   return QCX_OK;
 }
 
+}  // extern "C"
+
+// Bytes of one k point's Bloch sums M(k; G) for n_G rows (fallback path)
+static size_t m_bytes_per_k(const qcx_ctx* ctx, int n_G) {
+  return sizeof(cplx) * (size_t)n_G * ctx->n_ao * ctx->n_ao;
+}
+
+int qcx::rho_prepare(qcx_ctx* ctx, int n_G, const int* G_int, bool need_g0, bool optical) {
+  if (n_G < 1 || n_G > 4096 || !G_int) return fail(ctx, QCX_EINVAL, "need 1 <= n_G <= 4096");
+  if (need_g0 && (G_int[0] != 0 || G_int[1] != 0 || G_int[2] != 0))
+    return fail(ctx, QCX_EINVAL, "G_int[0] must be (0,0,0)");
+  for (int g = 0; g < n_G; ++g) {
+    if (optical && g == 0) continue;
+    double n2 = 0.0;
+    for (int x = 0; x < 3; ++x) {
+      double v = ctx->q[x];
+      for (int j = 0; j < 3; ++j) v += G_int[3 * g + j] * ctx->rec[3 * j + x];
+      n2 += v * v;
+    }
+    if (!(n2 > 0.0)) return fail(ctx, QCX_EINVAL, "q + G vanishes for G index " + std::to_string(g));
+  }
+  HIPCK(hipSetDevice(ctx->device));
+  ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
+  const int nT = ctx->n_cells;
+  HIPCK(ctx->d_Q.reserve(sizeof(double) * 3 * (size_t)n_G));
+  HIPCK(ctx->d_vq.reserve(sizeof(double) * (size_t)n_G));
+  HIPCK(ctx->d_F.reserve(m_bytes_per_k(ctx, n_G) * nT));
+  ctx->ldt = roundup(ctx->n_t + 16, kLdtAlign);  // zero tail for padded and chunked readers
+  HIPCK(ctx->d_R.reserve(sizeof(cplx) * ctx->ldt * n_G));
+  if (!rho_fused_fits(ctx->n_ao, ctx->n_occ, nT)) {
+    // Bloch sums M(k; G) of one pass of the fallback (k points in chunks)
+    const size_t per_k = m_bytes_per_k(ctx, n_G);
+    const int kc = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, kMBudget / per_k));
+    HIPCK(ctx->d_M.reserve(per_k * kc));
+  }
+  ctx->n_g = n_G;
+  return QCX_OK;
+}
+
+// Bloch sum and band contraction of the `rows` rows of a G-major F: in one
+// pass with M in LDS, or (large bases, many valence bands) through M chunks
+// in ctx->d_M, whose capacity sets the k chunk
+static int densities(qcx_ctx* ctx, const cplx* F, int rows, const cplx* bra, cplx* Rout,
+                     hipStream_t st) {
+  const int nT = ctx->n_cells, nao = ctx->n_ao;
+  if (rho_fused_fits(nao, ctx->n_occ, nT)) {
+    launch_rho_fused(F, ctx->d_ph.as<cplx>(), ctx->d_Ck.as<cplx>(), bra, nao, ctx->n_b, ctx->n_occ,
+                     ctx->n_k, nT, rows, Rout, ctx->ldt, st);
+    LAUNCHCK("rho_fused");
+    return QCX_OK;
+  }
+  const size_t nee = (size_t)nao * nao;
+  const size_t per = sizeof(cplx) * (size_t)rows * nee;
+  const int kch = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, ctx->d_M.bytes / per));
+  for (int k0 = 0; k0 < ctx->n_k; k0 += kch) {
+    const int nk = std::min(kch, ctx->n_k - k0);
+    launch_phase_sum(F, ctx->d_ph.as<cplx>(), nT, rows, (int)nee, k0, nk, ctx->d_M.as<cplx>(), st);
+    launch_band_contract(ctx->d_M.as<cplx>(), ctx->d_Ck.as<cplx>(), bra, nao, ctx->n_b, ctx->n_occ,
+                         ctx->n_k, k0, nk, rows, Rout, ctx->ldt, st);
+    LAUNCHCK("phase_sum/band_contract");
+  }
+  return QCX_OK;
+}
+
+int qcx::rho_enqueue(qcx_ctx* ctx, const int* d_G, int n_G, bool optical, hipStream_t st) {
+  launch_q_plus_g(ctx->d_qc.as<double>(), d_G, ctx->rec, n_G, optical, ctx->d_Q.as<double>(),
+                  ctx->d_vq.as<double>(), st);
+  launch_zero_tail(ctx->d_R.as<cplx>(), ctx->ldt, ctx->n_t, n_G, st);
+  LAUNCHCK("q_plus_g/zero_tail");
+  launch_cell_ft(shell_tab(ctx), ctx->d_shp.as<int>(), ctx->d_tvec.as<double>(), ctx->n_cells,
+                 ctx->d_Q.as<double>(), n_G, ctx->d_F.as<cplx>(), st);
+  LAUNCHCK("cell_ft");
+  // the bra states: k + q, or in the optical limit k itself
+  const cplx* bra = optical ? ctx->d_Ck.as<cplx>() : ctx->d_Ckq.as<cplx>();
+  return densities(ctx, ctx->d_F.as<cplx>(), n_G, bra, ctx->d_R.as<cplx>(), st);
+}
+
+extern "C" {
+
 // Pair densities R[G][t] into ctx->d_R for the G list (G = 0 first when
 // need_g0; qcx_loss_diag's chunks have no G = 0 requirement).  With
 // qhat (the optical limit, App. C) the states must have q = 0; the k states
@@ -450,9 +529,6 @@ static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_
                              const double* qhat = nullptr) {
   if (!ctx) return QCX_EINVAL;
   if (!ctx->have_states) return fail(ctx, QCX_ESTATE, "set_states first");
-  if (n_G < 1 || n_G > 4096 || !G_int) return fail(ctx, QCX_EINVAL, "need 1 <= n_G <= 4096");
-  if (need_g0 && (G_int[0] != 0 || G_int[1] != 0 || G_int[2] != 0))
-    return fail(ctx, QCX_EINVAL, "G_int[0] must be (0,0,0)");
   const bool optical = qhat != nullptr;
   double qh[3] = {0.0, 0.0, 0.0};
   if (optical) {
@@ -463,78 +539,26 @@ static int pair_density_impl(qcx_ctx* ctx, int n_G, const int* G_int, void* rho_
     for (int x = 0; x < 3; ++x) qh[x] = qhat[x] / nq;
   }
   if (int rc = reject_capture(ctx)) return rc;
-  HIPCK(hipSetDevice(ctx->device));
-  ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
+  if (int rc = rho_prepare(ctx, n_G, G_int, need_g0, optical)) return rc;
   hipStream_t st = ctx->stream;
-  std::vector<double> Q(3 * (size_t)n_G), vq(n_G);
-  for (int g = 0; g < n_G; ++g) {
-    double n2 = 0.0;
-    for (int x = 0; x < 3; ++x) {
-      double v = ctx->q[x];
-      for (int j = 0; j < 3; ++j) v += G_int[3 * g + j] * ctx->rec[3 * j + x];
-      Q[3 * g + x] = v;
-      n2 += v * v;
-    }
-    if (optical && g == 0) {
-      vq[0] = sqrt(4.0 * kPi);  // |q| went into the k.p row
-      continue;
-    }
-    if (!(n2 > 0.0)) return fail(ctx, QCX_EINVAL, "q + G vanishes for G index " + std::to_string(g));
-    vq[g] = sqrt(4.0 * kPi) / sqrt(n2);
-  }
-  ctx->n_g = n_G;
   HIPCK(stage_begin(ctx));
-  HIPCK(upload(ctx, ctx->d_Q, Q.data(), Q.size()));
-  HIPCK(upload(ctx, ctx->d_vq, vq.data(), vq.size()));
-  const int nT = ctx->n_cells, nao = ctx->n_ao;
-  const size_t nee = (size_t)nao * nao;
-  HIPCK(ctx->d_F.reserve(sizeof(cplx) * nT * (size_t)n_G * nee));
-  ctx->ldt = roundup(ctx->n_t + 16, 256);  // zero tail: chunked readers may run past n_t
-  HIPCK(ctx->d_R.reserve(sizeof(cplx) * ctx->ldt * n_G));
-  HIPCK(hipMemsetAsync(ctx->d_R.p, 0, sizeof(cplx) * ctx->ldt * n_G, st));
-  const bool fused = rho_fused_fits(nao, ctx->n_occ, nT);
-  // Bloch sums M(k; G) of one pass of the fallback (k points in chunks)
-  const size_t per_k = sizeof(cplx) * (size_t)n_G * nee;
-  const int kc = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, kMBudget / per_k));
-  if (!fused) HIPCK(ctx->d_M.reserve(per_k * kc));
+  HIPCK(upload(ctx, ctx->d_G, G_int, 3 * (size_t)n_G));
   int sp_rho;
   HIPCK(span_begin(ctx, 0, &sp_rho));
-  launch_cell_ft(shell_tab(ctx), ctx->d_shp.as<int>(), ctx->d_tvec.as<double>(), nT,
-                 ctx->d_Q.as<double>(), n_G, ctx->d_F.as<cplx>(), st);
-  LAUNCHCK("cell_ft");
-  // the bra states: k + q, or in the optical limit k itself
-  const cplx* bra = optical ? ctx->d_Ck.as<cplx>() : ctx->d_Ckq.as<cplx>();
-  // Bloch sum and band contraction of the rows of a G-major F: in one pass
-  // with M in LDS, or (large bases, many valence bands) through M chunks
-  auto densities = [&](const cplx* F, int rows, cplx* Rout) -> int {
-    if (fused) {
-      launch_rho_fused(F, ctx->d_ph.as<cplx>(), ctx->d_Ck.as<cplx>(), bra, nao, ctx->n_b,
-                       ctx->n_occ, ctx->n_k, nT, rows, Rout, ctx->ldt, st);
-      LAUNCHCK("rho_fused");
-      return QCX_OK;
-    }
-    const size_t per = sizeof(cplx) * (size_t)rows * nee;
-    const int kch = (int)std::max<size_t>(1, std::min<size_t>(ctx->n_k, per_k * kc / per));
-    for (int k0 = 0; k0 < ctx->n_k; k0 += kch) {
-      const int nk = std::min(kch, ctx->n_k - k0);
-      launch_phase_sum(F, ctx->d_ph.as<cplx>(), nT, rows, (int)nee, k0, nk, ctx->d_M.as<cplx>(), st);
-      launch_band_contract(ctx->d_M.as<cplx>(), ctx->d_Ck.as<cplx>(), bra, nao, ctx->n_b,
-                           ctx->n_occ, ctx->n_k, k0, nk, rows, Rout, ctx->ldt, st);
-      LAUNCHCK("phase_sum/band_contract");
-    }
-    return QCX_OK;
-  };
-  if (int rc = densities(ctx->d_F.as<cplx>(), n_G, ctx->d_R.as<cplx>())) return rc;
+  if (int rc = rho_enqueue(ctx, ctx->d_G.as<int>(), n_G, optical, st)) return rc;
   if (optical) {
     // transitions at the same k; then P = C^H D(k) C for the three gradient
     // components (their Bloch sums take the place of M) and the k.p row
+    const int nT = ctx->n_cells;
+    const size_t nee = (size_t)ctx->n_ao * ctx->n_ao;
     launch_transition_energies(ctx->d_Ek.as<double>(), ctx->d_Ek.as<double>(), ctx->n_k, ctx->n_b,
                                ctx->n_occ, ctx->d_dt.as<double>(), st);
     ctx->dt_valid = false;
     HIPCK(ctx->d_Fg.reserve(sizeof(cplx) * nT * 3 * nee));
     HIPCK(ctx->d_Rp.reserve(sizeof(cplx) * 3 * ctx->ldt));
     launch_grad_ft(shell_tab(ctx), ctx->d_tvec.as<double>(), nT, ctx->d_Fg.as<cplx>(), st);
-    if (int rc = densities(ctx->d_Fg.as<cplx>(), 3, ctx->d_Rp.as<cplx>())) return rc;
+    if (int rc = densities(ctx, ctx->d_Fg.as<cplx>(), 3, ctx->d_Ck.as<cplx>(), ctx->d_Rp.as<cplx>(), st))
+      return rc;
     launch_optical_row(ctx->d_Rp.as<cplx>(), ctx->ldt, ctx->d_dt.as<double>(), ctx->n_t, qh,
                        ctx->d_R.as<cplx>(), st);
     LAUNCHCK("optical limit");

@@ -65,6 +65,7 @@ _SIGS = {
     "qcx_bulk_config": [_P, _P, _P],
     "qcx_set_bulk_pipeline": [_P, _I],
     "qcx_run_batch": [_P, _I, _P, _I, _I, _I, _I],
+    "qcx_run_batch_rho": [_P, _I, _P, _P, _P, _I, _I, _I, _I],
     "qcx_batch_sync": [_P],
     "qcx_batch_config": [_P, _P, _P],
     "qcx_loss_diag": [_P, _I, _P, _I, _P, _D, _I, _P, _P],
@@ -385,30 +386,48 @@ class Context:
 
 
 def run_batch(contexts, items, precision=SPLIT_BF16, headwings_fp64: bool = True,
-              lfe: bool = True):
-    """Batched chi0 -> eps -> loss (qcx_run_batch).
+              lfe: bool = True, G_lists=None):
+    """Batched chi0 -> eps -> loss (qcx_run_batch, or qcx_run_batch_rho).
 
-    contexts: list of Context with pair densities; items: list of dicts with
-    keys ctx (index), w_eV, eta_eV, loss_out (CUDA float64 tensor [n_w][n_G]).
-    Asynchronous; call batch_sync(contexts[0]) to wait and check errors.
+    contexts: list of Context with pair densities, or with states only when
+    G_lists (one int array [n_G][3] per context, G = 0 first) is given: the
+    pair densities are then computed inside the batch.  items: list of dicts
+    with keys ctx (index), w_eV, eta_eV, loss_out (CUDA float64 tensor
+    [n_w][n_G]).  Asynchronous; call batch_sync(contexts[0]) to wait and
+    check errors.
     """
     lib = load_library()
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     handles = (ctypes.c_void_p * len(contexts))(*[c._h.value for c in contexts])
-    arr = (QcxItem * len(items))()
     keep = []
+    if G_lists is not None:
+        if len(G_lists) != len(contexts):
+            raise ValueError("one G list per context")
+        gl = [_host(g, np.int32).reshape(-1, 3) for g in G_lists]
+        keep += gl
+        n_g = np.array([len(g) for g in gl], np.int32)
+        gptr = (ctypes.c_void_p * len(gl))(*[g.ctypes.data for g in gl])
+    arr = (QcxItem * len(items))()
     for i, it in enumerate(items):
         w = _host(it["w_eV"], np.float64).reshape(-1)
         keep.append(w)
-        c = contexts[it["ctx"]]
-        out = _dev_ptr(it["loss_out"], "f64", len(w) * c.n_g, "loss_out")
+        ng = len(gl[it["ctx"]]) if G_lists is not None else contexts[it["ctx"]].n_g
+        out = _dev_ptr(it["loss_out"], "f64", len(w) * ng, "loss_out")
         arr[i] = QcxItem(int(it["ctx"]), len(w), w.ctypes.data, float(it["eta_eV"]), out.value)
-    rc = lib.qcx_run_batch(handles, len(contexts), ctypes.cast(arr, ctypes.c_void_p), len(items),
-                           int(precision), 1 if headwings_fp64 else 0, 1 if lfe else 0)
+    flags = (int(precision), 1 if headwings_fp64 else 0, 1 if lfe else 0)
+    if G_lists is None:
+        rc = lib.qcx_run_batch(handles, len(contexts), ctypes.cast(arr, ctypes.c_void_p), len(items),
+                               *flags)
+    else:
+        rc = lib.qcx_run_batch_rho(handles, len(contexts), _ptr_host(n_g), ctypes.cast(gptr, ctypes.c_void_p),
+                                   ctypes.cast(arr, ctypes.c_void_p), len(items), *flags)
     del keep
     if rc != OK:
         raise QcxError(rc, lib.qcx_last_error(contexts[0]._h).decode())
+    if G_lists is not None:
+        for c, g in zip(contexts, gl):
+            c.n_g = len(g)
 
 
 def batch_sync(ctx0):

@@ -11,6 +11,10 @@ Checks, through the C ABI:
   * reduced k grids against the FP64 oracle (1e-4 split-BF16, 1e-10 FP64);
   * replay: bit-identical results, and new states of the same shapes are
     picked up without a rebuild;
+  * pair densities inside the batch (qcx_run_batch_rho): bit-identical to
+    the batch over densities from qcx_pair_density (same kernels, same plan
+    with tuning off), new states with a new q picked up by the replay, the
+    FP64 oracle on reduced k grids;
   * error paths.
 """
 import numpy as np
@@ -35,7 +39,7 @@ def _contexts(items):
     return ctxs
 
 
-def _batch(ctxs, items, precision, lfe=True, outs=None):
+def _batch(ctxs, items, precision, lfe=True, outs=None, rho=False):
     import torch
 
     from paper_2603_12326_amd import batch_sync, run_batch
@@ -47,7 +51,8 @@ def _batch(ctxs, items, precision, lfe=True, outs=None):
         o.fill_(np.nan)
     spec = [dict(ctx=i, w_eV=wl.w_eV, eta_eV=wl.eta_eV, loss_out=outs[i])
             for i, wl in enumerate(items)]
-    run_batch(ctxs, spec, precision=precision, lfe=lfe)
+    run_batch(ctxs, spec, precision=precision, lfe=lfe,
+              G_lists=[wl.G_int for wl in items] if rho else None)
     batch_sync(ctxs[0])
     return [o.cpu().numpy() for o in outs], spec
 
@@ -140,28 +145,118 @@ def test_batch_plan_tuned_and_fixed(full_batch):
     c.close()
 
 
-def test_batch_against_oracle():
+@pytest.mark.parametrize("rho", [False, True], ids=["densities-given", "densities-in-batch"])
+def test_batch_against_oracle(rho):
     """Items 0, 6, 12, 19 (N_G 59, 113, 181, 259; n_w 5..195) on a 2^3 k grid."""
+    from paper_2603_12326_amd import Context
+
     pick = [0, 6, 12, 19]
     allv = make_mixed_batch_items(kgrid_override=2)
     items = [allv[i] for i in pick]
-    ctxs = _contexts(items)
+    if rho:
+        ctxs = []
+        for wl in items:
+            ctxs.append(Context(0))
+            set_inputs(ctxs[-1], wl)
+    else:
+        ctxs = _contexts(items)
     refs = []
     for wl in items:
         st = wl.states(0)
         refs.append(rpa.solve(wl.cell, wl.basis, wl.lattice_range, wl.k_frac, wl.n_occ, wl.G_int,
                               st, wl.w_eV, wl.eta_eV, return_all=True))
     for prec, tol in (("split_bf16", 1e-4), ("fp64", 1e-10)):
-        got, _ = _batch(ctxs, items, prec)
+        got, _ = _batch(ctxs, items, prec, rho=rho)
         for wl, g, r in zip(items, got, refs):
             e = normwise(g, r["loss"])
             print(wl.name, len(wl.G_int), prec, e)
             assert e < tol, (wl.name, prec, e)
-    got, _ = _batch(ctxs, items, "fp64", lfe=False)
+    got, _ = _batch(ctxs, items, "fp64", lfe=False, rho=rho)
     for wl, g, r in zip(items, got, refs):
         assert normwise(g, rpa.loss_nolfe(r["eps"])) < 1e-10
     for c in ctxs:
         c.close()
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "fp64"])
+def test_batch_rho_equals_given_densities(full_batch, prec):
+    """The full mixed batch with its pair densities computed inside the plan
+    against the batch over densities from qcx_pair_density: the same kernels
+    on the same inputs, and with tuning off the same bulk plan, so the losses
+    agree bit for bit."""
+    items, ctxs = full_batch
+    ctxs[0].set_autotune(0)
+    try:
+        a, _ = _batch(ctxs, items, prec)
+        b, _ = _batch(ctxs, items, prec, rho=True)
+        c, _ = _batch(ctxs, items, prec, rho=True)    # replay
+    finally:
+        ctxs[0].set_autotune(1)
+    for i in range(len(items)):
+        assert np.all(np.isfinite(b[i])), i
+        assert np.array_equal(a[i], b[i]), (i, normwise(b[i], a[i]))
+        assert np.array_equal(b[i], c[i]), i
+
+
+def test_batch_rho_new_states(full_batch):
+    """New states with another q on context 0 between two replays of a plan
+    that computes the pair densities: the replay reads the new q from the
+    device (q + G, Coulomb factors, Fourier integrals all change), the other
+    items are untouched, and item 0 matches the single path on those states."""
+    import torch
+
+    items, ctxs = full_batch
+    outs = [torch.empty((len(wl.w_eV), len(wl.G_int)), dtype=torch.float64, device="cuda")
+            for wl in items]
+    a, _ = _batch(ctxs, items, "split_bf16", outs=outs, rho=True)
+    cfg_a = ctxs[0].batch_config()
+    other = items[5]                        # item 0's cell, basis and k grid, another q
+    st = other.states(0)
+    assert not np.allclose(st.q_cart, items[0].states(0).q_cart)
+    ctxs[0].set_states(st.q_cart, other.k_frac, other.n_occ, st.C_k, st.E_k, st.C_kq, st.E_kq)
+    c, _ = _batch(ctxs, items, "split_bf16", outs=outs, rho=True)
+    assert ctxs[0].batch_config() == cfg_a      # replayed, not rebuilt (tuning would rerun)
+    assert not np.allclose(c[0], a[0])
+    for i in range(1, len(items)):
+        assert np.array_equal(c[i], a[i])
+    ctxs[0].pair_density(items[0].G_int)
+    ref = _single(ctxs[0], items[0], "split_bf16")
+    assert normwise(c[0], ref) < 1e-4
+    set_inputs(ctxs[0], items[0])
+    ctxs[0].pair_density(items[0].G_int)
+
+
+def test_batch_rho_errors(full_batch):
+    import torch
+
+    from paper_2603_12326_amd import Context, QcxError, run_batch
+    from paper_2603_12326_amd import qcx as q
+
+    items, ctxs = full_batch
+    wl = items[0]
+    out = torch.empty((len(wl.w_eV), len(wl.G_int)), dtype=torch.float64, device="cuda")
+    spec = [dict(ctx=0, w_eV=wl.w_eV, eta_eV=wl.eta_eV, loss_out=out)]
+    fresh = Context(0)
+    b = wl.basis
+    fresh.set_cell_basis(wl.cell.lat, wl.cell.xyz, b.shell_atom, b.shell_l, b.shell_exp, 1,
+                         wl.lattice_range)
+    with pytest.raises(QcxError) as e:         # no states
+        run_batch([fresh], spec, G_lists=[wl.G_int])
+    assert e.value.code == q.ESTATE
+    with pytest.raises(QcxError) as e:         # a context twice
+        run_batch([ctxs[0], ctxs[0]], spec, G_lists=[wl.G_int, wl.G_int])
+    assert e.value.code == q.EINVAL
+    bad = np.array(wl.G_int)
+    bad[0] = (1, 0, 0)                         # G = 0 not first
+    with pytest.raises(QcxError) as e:
+        run_batch([ctxs[0]], spec, G_lists=[bad])
+    assert e.value.code == q.EINVAL
+    st = wl.states(0)                          # q = 0: q + G vanishes at G = 0
+    fresh.set_states(np.zeros(3), wl.k_frac, wl.n_occ, st.C_k, st.E_k, st.C_k, st.E_k)
+    with pytest.raises(QcxError) as e:
+        run_batch([fresh], spec, G_lists=[wl.G_int])
+    assert e.value.code == q.EINVAL and "vanishes" in str(e.value)
+    fresh.close()
 
 
 def test_batch_errors(full_batch):
