@@ -305,38 +305,47 @@ __device__ __forceinline__ void gj_reg_body(const cplx* __restrict__ A, int n,
 }
 
 // Blocked Gauss-Jordan for 128 < n <= 64 RP (RP <= 16) with 1024 threads per
-// matrix; the matrix stays in global memory and is swept in panels of MB = 32
-// columns, each made of two sub-panels of 16.  For each panel:
+// matrix; the matrix stays in global memory and is swept in panels of MB
+// columns, made of one or two sub-panels of 16.  For each panel:
 //  1. lane l of wave v holds rows l + 64 a of sub-panel column s0 + v in
 //     registers, and the sub-panel's 16 pivot steps run as in k_gj_reg (one
 //     barrier per step, the next column's owner chooses its pivot while the
 //     others update), restricted to the sub-panel's columns;
-//  2. the second sub-panel's columns first receive the first sub-panel's
-//     rank-16 update, and after their own sweep the first sub-panel's columns
+//  2. with two sub-panels, the second one's columns first receive the first
+//     one's rank-16 update, and after their own sweep the first one's columns
 //     receive theirs (the same deferred update as below, on 16 columns), so
 //     that the panel holds what 32 single steps would leave there;
-//  3. every other column j receives the deferred rank-32 update
-//     T[:, j] += Z Y[:, j]  with Y = T[P][j] (the 32 pivot rows before this
-//     update) and Z = swept panel with 1 subtracted at (p_a, a): first every
-//     row but the pivot rows, one chunk of ZR rows of Z at a time, then the 32
-//     pivot rows.  Two sub-panels per pass halve the passes over the matrix,
-//     which bound this kernel (each pass reads and writes all of it).
+//  3. every other column j receives the deferred rank-MB update
+//     T[:, j] += Z Y[:, j]  with Y = T[P][j] (the MB pivot rows before this
+//     update) and Z = swept panel with 1 subtracted at (p_a, a), one chunk of
+//     ZR rows of Z at a time.  With several chunks the pivot rows are left
+//     out of the chunk passes and updated in a last pass of their own, so
+//     that every chunk pass reads their old values; with one chunk they are
+//     updated with the other rows.
 // The update runs on FP64 MFMA (v_mfma_f64_16x16x4f64) as two real products
-// with K = 64:  Re T += [Re Z | Im Z] [Re Y ; -Im Y],
-//               Im T += [Re Z | Im Z] [Im Y ;  Re Y].
+// with K = 2 MB:  Re T += [Re Z | Im Z] [Re Y ; -Im Y],
+//                 Im T += [Re Z | Im Z] [Im Y ;  Re Y].
 // Z (chunks of ZR rows) and a JT-column tile of Y are staged in LDS k-major
 // (lane-consecutive rows / columns); each wave owns a 32 x 16 output block
-// (2 MFMA tiles, re and im) per tile and updates it in place.  Since the pivot
-// rows change only in the last pass, every Y tile read before it holds their
-// old values, and each Z chunk is staged once per panel.
+// (2 MFMA tiles, re and im) per tile and updates it in place.  Each Y tile is
+// loaded into registers while the previous tile's MFMAs run and stored into
+// the other of two LDS buffers: one barrier per column tile.
 // MFMA layouts: A 16x4, lane l holds A[l%16][l/16]; B 4x16, lane l holds
 // B[l/16][l%16]; D 16x16, lane l holds D[4r + l/16][l%16], r = 0..3.
-constexpr int GJP_MS = 16, GJP_MB = 2 * GJP_MS, GJP_JT = 64, GJP_KR = 2 * GJP_MB, GJP_ZR = 128;
+// Panel shape by row class: up to 320 rows (RP <= 5) a panel is one sub-panel
+// of 16 columns and Z is staged in one chunk of every row (one pass per
+// panel); larger matrices take two sub-panels per panel (rank-32 updates,
+// half the passes over the matrix, which bound them) and Z in chunks of 128
+// rows, which is what fits the LDS with the wider panel.
+__host__ __device__ constexpr int gjp_nsub(int rp) { return rp <= 5 ? 1 : 2; }
+__host__ __device__ constexpr int gjp_zr(int rp) { return rp <= 5 ? 64 * rp : 128; }
+constexpr int GJP_MS = 16, GJP_JT = 64;
 
 template <int RP>
 __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
                                               cplx* __restrict__ drow, int* sing, int widx) {
-  constexpr int NW = 16, MS = GJP_MS, MB = GJP_MB, JT = GJP_JT, KR = GJP_KR, ZR = GJP_ZR;
+  constexpr int NW = 16, MS = GJP_MS, MB = gjp_nsub(RP) * MS, JT = GJP_JT, KR = 2 * MB,
+                ZR = gjp_zr(RP);
   extern __shared__ __align__(16) char smem[];
   double* Zt = reinterpret_cast<double*>(smem);    // [KR][ZR]: k' < MB Re Z, else Im Z
   cplx* ucol = reinterpret_cast<cplx*>(smem);      // [2][64 RP] during the pivot steps
@@ -496,10 +505,14 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
     __syncthreads();  // swept panel in memory; pivot buffers free
     // ---- deferred rank-mb update of every column outside the panel
     const int nch = (n + ZR - 1) / ZR;
-    // The panel's pivot rows are left out of the chunk passes (their Z rows
-    // are zero there) and updated in a pass of their own at the end, so every
-    // chunk pass reads Y = the pivot rows before this update straight from
-    // the matrix, and each Z chunk is staged once per panel.
+    // With several chunks the panel's pivot rows are left out of the chunk
+    // passes (their Z rows are zero there) and updated in a pass of their own
+    // at the end, so every chunk pass reads Y = the pivot rows before this
+    // update straight from the matrix, and each Z chunk is staged once per
+    // panel.  With one chunk, a column tile's Y is staged before any of its
+    // columns changes, so the pivot rows take their update in the same pass
+    // (Z with 1 subtracted at (p_a, a)).
+    const bool one = nch == 1;
     auto is_piv = [&](int i) {
       bool f = false;
       for (int a = 0; a < mb; ++a) f |= piv[k0 + a] == i;
@@ -508,8 +521,11 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
     auto load_z = [&](int r0) {
       for (int e = tid; e < ZR * MB; e += 1024) {
         const int r = e / MB, a = e % MB, i = r0 + r;
-        const cplx z =
-            (i < n && a < mb && !is_piv(i)) ? A[(size_t)i * n + k0 + a] : cplx{0.0, 0.0};
+        cplx z = {0.0, 0.0};
+        if (i < n && a < mb && (one || !is_piv(i))) {
+          z = A[(size_t)i * n + k0 + a];
+          if (i == piv[k0 + a]) z.re -= 1.0;
+        }
         Zt[a * ZR + r] = z.re;
         Zt[(MB + a) * ZR + r] = z.im;
       }
@@ -609,8 +625,10 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
       load_z(c * ZR);
       pass(c * ZR, false);
     }
-    load_zp();
-    pass(0, true);
+    if (!one) {
+      load_zp();
+      pass(0, true);
+    }
   }
   __syncthreads();
   for (int k = tid; k < n; k += 1024) drow[k] = A[(size_t)piv[k] * n + sor[k]];
@@ -655,8 +673,8 @@ __global__ void __launch_bounds__(1024) k_gj_panel_jobs(const GjJob* __restrict_
 }
 
 size_t gj_panel_lds(int n, int rp) {
-  (void)rp;
-  return sizeof(double) * (size_t)GJP_KR * GJP_ZR + sizeof(cplx) * 2 * GJP_MB * GJP_JT +
+  const int mb = gjp_nsub(rp) * GJP_MS;
+  return sizeof(double) * (size_t)(2 * mb) * gjp_zr(rp) + sizeof(cplx) * 2 * mb * GJP_JT +
          sizeof(int) * 2 * (size_t)n;
 }
 
