@@ -204,7 +204,10 @@ inline int bulk_maxr(int n_g) {
 // step s + NST - 1 into the stage freed by step s - 1, then computes from its
 // own stage; the end-of-step wait covers only the copies of step s + 1, so
 // with NST = 3 the load latency hides behind two steps of MFMA work.
-template <bool BF16, int AF, int MAXR, int NST, bool GATHER, class L>
+// Only the first NF of the tile's AF 32-row fragments take MFMAs (the others,
+// wholly past an item's 2 n_w rows in a batch, keep zero accumulators); the
+// copies into LDS do not depend on NF, so every wait counts the same copies.
+template <bool BF16, int AF, int MAXR, int NST, bool GATHER, class L, int NF = AF>
 __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
                                           const float4* __restrict__ Alo,
                                           const float4* __restrict__ R32,
@@ -329,30 +332,30 @@ __device__ __forceinline__ void bulk_tile(const float4* __restrict__ Ahi,
   auto mfma = [&](const L& cur, const Bops& B) {
     const float4* As = cur.a;
     if constexpr (BF16) {
-      // three sweeps over the 2*AF independent accumulators, so that no MFMA
+      // three sweeps over the 2*NF independent accumulators, so that no MFMA
       // waits on the one issued just before it
-      bf16x8 ah[AF];
+      bf16x8 ah[NF];
 #pragma unroll
-      for (int f = 0; f < AF; ++f) ah[f] = __builtin_bit_cast(bf16x8, As[f * 128 + lane]);
+      for (int f = 0; f < NF; ++f) ah[f] = __builtin_bit_cast(bf16x8, As[f * 128 + lane]);
 #pragma unroll
-      for (int f = 0; f < AF; ++f) {
+      for (int f = 0; f < NF; ++f) {
         acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], B.rh, acc[f][0], 0, 0, 0);
         acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], B.ih, acc[f][1], 0, 0, 0);
       }
 #pragma unroll
-      for (int f = 0; f < AF; ++f) {
+      for (int f = 0; f < NF; ++f) {
         acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], B.rl, acc[f][0], 0, 0, 0);
         acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[f], B.il, acc[f][1], 0, 0, 0);
       }
 #pragma unroll
-      for (int f = 0; f < AF; ++f) {
+      for (int f = 0; f < NF; ++f) {
         const bf16x8 al = __builtin_bit_cast(bf16x8, As[f * 128 + 64 + lane]);
         acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, B.rh, acc[f][0], 0, 0, 0);
         acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, B.ih, acc[f][1], 0, 0, 0);
       }
     } else {
 #pragma unroll
-      for (int f = 0; f < AF; ++f) {
+      for (int f = 0; f < NF; ++f) {
         const float4 a0 = As[f * 128 + lane], a1 = As[f * 128 + 64 + lane];
         const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
 #pragma unroll
@@ -499,8 +502,27 @@ k_bulk_persistent(const BulkItem* __restrict__ items, const int4* __restrict__ t
     if (t >= n_tiles) break;
     const int4 td = tiles[t];
     const BulkItem& it = items[td.x];
-    bulk_tile<BF16, AF, MAXR, 2, GATHER>(it.A, it.Alo, it.R32, it.pairs, it.rows, it.g, it.C,
-                                         Blk3{td.y, td.z, td.w}, s0, s1, s0);
+    // row fragments of this tile that hold rows of the item's frequencies
+    const int nf = min(AF, (it.g.n_rows + 31) / 32 - (it.g.row_tile0 + td.z) * AF);
+    const Blk3 bk{td.y, td.z, td.w};
+#define QCX_TILE(NFV)                                                                          \
+  bulk_tile<BF16, AF, MAXR, 2, GATHER, L, NFV>(it.A, it.Alo, it.R32, it.pairs, it.rows, it.g, \
+                                               it.C, bk, s0, s1, s0)
+    if (nf >= AF)
+      QCX_TILE(AF);
+    else if (nf <= 1)
+      QCX_TILE(1);
+    else if constexpr (AF > 2) {
+      if (nf == 2)
+        QCX_TILE(2);
+      else if constexpr (AF > 3) {
+        if (nf == 3)
+          QCX_TILE(3);
+        else if constexpr (AF > 4)
+          QCX_TILE(4);
+      }
+    }
+#undef QCX_TILE
     __syncthreads();  // tix and the LDS stages are reused by the next tile
   }
 }
