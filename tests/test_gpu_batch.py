@@ -226,6 +226,48 @@ def test_batch_rho_new_states(full_batch):
     ctxs[0].pair_density(items[0].G_int)
 
 
+def test_batch_rho_fallback_path():
+    """Pair densities inside the batch for a basis beyond the fused kernel's
+    tiles (the all-electron basis: 52 AO, 9 occupied bands, so the Bloch sums
+    go through M chunks and the valence-first contraction) beside an item on
+    the fused path, on 2^3 k grids: equal bit for bit to the batch over
+    densities from qcx_pair_density (FP64 and split-BF16, tuning off), and to
+    the oracle (1e-10 in FP64)."""
+    import dataclasses
+
+    from paper_2603_12326_amd import Context
+    from synth import make_all_electron
+
+    ae = make_all_electron(n_w=8, kgrid=2)
+    ae = dataclasses.replace(ae, G_int=np.asarray(ae.G_int)[:181])
+    items = [ae, make_mixed_batch_items(kgrid_override=2)[6]]
+    ctxs = []
+    for wl in items:
+        ctxs.append(Context(0))
+        set_inputs(ctxs[-1], wl)
+    ctxs[0].set_autotune(0)
+    try:
+        for prec in ("fp64", "split_bf16"):
+            got, _ = _batch(ctxs, items, prec, rho=True)
+            for c, wl in zip(ctxs, items):
+                c.pair_density(wl.G_int)
+            given, _ = _batch(ctxs, items, prec)
+            for i in range(len(items)):
+                assert np.all(np.isfinite(got[i])), (prec, i)
+                assert np.array_equal(got[i], given[i]), (prec, i, normwise(got[i], given[i]))
+            if prec == "fp64":
+                st = ae.states(0)
+                ref = rpa.solve(ae.cell, ae.basis, ae.lattice_range, ae.k_frac, ae.n_occ, ae.G_int,
+                                st, ae.w_eV, ae.eta_eV)
+                e = normwise(got[0], ref)
+                print("all-electron basis, densities in the batch, FP64 vs oracle", e)
+                assert e < 1e-10
+    finally:
+        ctxs[0].set_autotune(1)
+        for c in ctxs:
+            c.close()
+
+
 def test_batch_rho_errors(full_batch):
     import torch
 
