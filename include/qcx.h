@@ -464,8 +464,13 @@ int qcx_mlp_query(qcx_mlp* m, int n, const double* qw, double* loss, double* err
  * non-finite estimate or prediction counts as infinite); *n_fallback (may be
  * NULL) the number of recomputed frequencies.  ctx's pair densities and results are overwritten
  * when a fallback runs.  The networks and ctx must be on one device.
- * Synchronous.  Errors: as the calls above; QCX_EINVAL beyond 2^26 points,
- * QCX_ESTATE before qcx_mlp_set_encoding or qcx_set_states. */
+ * The call waits for the networks' answers and the rejections (on the
+ * networks' stream); the fallback rows are then enqueued on ctx's stream and
+ * the call returns: loss_out is complete once ctx's stream has run them, and
+ * their deferred state checks and a singular eps are reported by the next
+ * synchronising call on ctx (qcx_sync).  Errors: as the calls above;
+ * QCX_EINVAL beyond 2^26 points, QCX_ESTATE before qcx_mlp_set_encoding or
+ * qcx_set_states. */
 int qcx_mlp_infer(qcx_mlp* m, qcx_ctx* ctx, int n_G, const int* G_int, int n_w,
                   const double* w_eV, double eta_eV, double tol, int precision, double* loss_out,
                   double* err_out, int* n_fallback);

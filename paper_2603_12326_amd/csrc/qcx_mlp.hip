@@ -512,7 +512,8 @@ int qcx_mlp_infer(qcx_mlp* m, qcx_ctx* ctx, int n_G, const int* G_int, int n_w,
   hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, ctx->stream,
                      m->irows.as<double>(), m->isel.as<int>(), ns, n_G, loss_out);
   LAUNCHCK("infer fallback rows");
-  if (int rc = qcx_sync(ctx)) return rc;  // deferred checks and a singular eps of these rows
+  // asynchronous from here: deferred state checks and a singular eps of these
+  // rows are reported by the next synchronising call on ctx
   if (n_fallback) *n_fallback = ns;
   return QCX_OK;
 }

@@ -176,8 +176,9 @@ def query_with_fallback(sur: Surrogate, ctx, set_states, n_q: int, G_int, w_list
     """Answer every (q + G, w) of the grid (n_q momenta x w_lists x G) with
     the surrogate and the method as fallback: for each momentum, set its
     states (set_states(iq)) and call qcx_mlp_infer, which recomputes every
-    frequency row holding a rejected point.  Returns (loss per q as device
-    [n_w][n_G] tensors, statistics)."""
+    frequency row holding a rejected point (enqueued without waiting, so the
+    host moves on to the next momentum while the device runs them).  Returns
+    (loss per q as device [n_w][n_G] tensors, statistics)."""
     import torch
 
     n_g = len(G_int)
@@ -193,6 +194,7 @@ def query_with_fallback(sur: Surrogate, ctx, set_states, n_q: int, G_int, w_list
         errs.append(E.reshape(-1))
         n_rows += nfb
         n_pass += nfb > 0
+    ctx.sync()  # the last fallback rows, and the checks of every fallback pass
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     err = torch.cat(errs)

@@ -85,12 +85,17 @@ def run():
           f"q50 {np.quantile(cal['rel_err'], .5):.3g} q90 {np.quantile(cal['rel_err'], .9):.3g}; "
           f"calibration factor {cal['calib']:.3g}", flush=True)
 
-    # the method alone on the query grid
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ref = [S.method_loss(ctx, set_query, i, wl.G_int, wq[i], wl.eta_eV) for i in range(len(qq))]
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
+    # the method alone on the query grid (a first pass tunes the bulk for this
+    # shape; the second is timed)
+    def method_all():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = [S.method_loss(ctx, set_query, i, wl.G_int, wq[i], wl.eta_eV) for i in range(len(qq))]
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    method_all()
+    ref, t_plain = method_all()
     refh = np.stack([r.cpu().numpy() for r in ref])
 
     # the networks alone
@@ -118,6 +123,8 @@ def run():
 
     fb = {}
     for tol in TOLS:
+        # a first pass tunes the bulk for the fallback's row counts; the second is timed
+        S.query_with_fallback(sur, ctx, set_query, len(qq), wl.G_int, wq, wl.eta_eV, tol)
         out, st = S.query_with_fallback(sur, ctx, set_query, len(qq), wl.G_int, wq, wl.eta_eV, tol)
         got = np.stack([o.cpu().numpy() for o in out])
         E = st.pop("err").cpu().numpy().reshape(refh.shape)     # estimates in curve units
