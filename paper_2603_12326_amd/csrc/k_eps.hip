@@ -131,6 +131,18 @@ __device__ inline double readlane_d(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Element pa (wave-uniform) of a per-lane register array, as held by lane pl:
+// one scalar branch per slot, so that only the readlanes of slot pa run and
+// they read the registers in place (no VALU copy of the chosen element).
+template <int RP>
+__device__ inline cplx readlane_slot(const cplx (&c)[RP], int pa, int pl) {
+  cplx r = {0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < RP; ++a)
+    if (a == pa) r = {readlane_d(c[a].re, pl), readlane_d(c[a].im, pl)};
+  return r;
+}
+
 // Maximum of a 64-bit value over the wave: butterflies inside each row of 16
 // lanes by DPP (lane xor 1, xor 2, half-row mirror, row mirror), then the four
 // row results by readlane.  Needs every lane active.
@@ -157,6 +169,58 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long x) {
   return r;
 }
 
+// 32-bit pivot key: the modulus |re| + |im| rounded down to a float with 11
+// mantissa bits in the high 20 bits (non-negative floats order like their
+// bit patterns), the complement of the row index in the low 12 bits, so that
+// moduli equal to that precision go to the smaller row.  Partial pivoting
+// then takes a pivot within a factor 1 - 2^-11 of the largest modulus, which
+// bounds the growth of the elimination as the exact choice does.  A NaN entry
+// counts as infinite.  Every key of a live row is > 0 except for modulus 0.
+__device__ inline unsigned pivot_key32(cplx v, int row) {
+  double mag = fabs(v.re) + fabs(v.im);
+  if (mag != mag) mag = INFINITY;
+  const unsigned b = __float_as_uint((float)mag);
+  return (b & ~0xFFFu) | (unsigned)(0xFFF - row);
+}
+
+// Maximum of a 32-bit value over the wave: DPP butterflies inside each row of
+// 16 lanes, then the four row results by readlane.  Needs every lane active.
+__device__ inline unsigned wave_max_u32(unsigned x) {
+  auto step = [&](auto ctrl) {
+    constexpr int c = decltype(ctrl)::value;
+    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, c, 0xF, 0xF, false);
+    x = o > x ? o : x;
+  };
+  step(std::integral_constant<int, 0xB1>{});   // quad_perm [1,0,3,2]
+  step(std::integral_constant<int, 0x4E>{});   // quad_perm [2,3,0,1]
+  step(std::integral_constant<int, 0x141>{});  // row_half_mirror
+  step(std::integral_constant<int, 0x140>{});  // row_mirror
+  unsigned r = 0u;
+#pragma unroll
+  for (int row = 0; row < 4; ++row) {
+    const unsigned o = (unsigned)__builtin_amdgcn_readlane((int)x, 16 * row);
+    r = o > r ? o : r;
+  }
+  return r;
+}
+
+// 1/|a|^2 from a single-precision estimate refined by two Newton steps in
+// FP64 (24 -> 48 -> 96 bits: within an ulp of the FP64 reciprocal), a shorter
+// chain of dependent instructions than the IEEE division; outside the
+// single-precision range, the division.
+__device__ inline cplx cinv_nr(cplx a) {
+  const double d = a.re * a.re + a.im * a.im;
+  double r;
+  if (!(d > 1e-30 && d < 1e30)) {
+    r = 1.0 / d;
+  } else {
+    r = (double)__builtin_amdgcn_rcpf((float)d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+  }
+  return {a.re * r, -a.im * r};
+}
+
 // Register-resident Gauss-Jordan for n <= 64 RP and n <= 16 CP with 16 waves:
 // lane l of wave v owns rows l + 64 a and columns v + 16 b, so column k lives
 // in wave k % 16 alone.  Step k applies m <- m - u w^T with the pivot folded
@@ -165,15 +229,17 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long x) {
 // Gauss-Jordan sweep (row p / piv, column k -c / piv, pivot 1 / piv, the rest
 // m - c row_p / piv) with no per-element fix-ups.
 //
-// One barrier per step.  Before it, the owner of column k has chosen the pivot
-// (largest unused |re| + |im|, by a wave-wide maximum of 64-bit keys) and
-// published u and p through LDS.  After it, every wave reads row p of its own
-// columns from its lane p % 64 with readlane (scalar registers, no LDS
-// traffic: the LDS pipe is shared by all 16 waves and is the tighter
-// resource) and updates its block; the owner of column k + 1 updates that
-// column first and then chooses and publishes the next pivot while the other
-// waves are still in their FMAs.  u and p are double-buffered by the parity
-// of k; u is zero past row n; used-row marks live in registers.
+// One barrier per step.  Between two barriers the wave that owns column k + 1
+// runs the chain that bounds the step: read p and u, update column k + 1,
+// choose its pivot (largest unused modulus by pivot_key32 and DPP maxima),
+// publish u and p through LDS.  It runs that chain before any of its other
+// columns, while the other waves do their FMAs.  Every wave then reads row p
+// of its columns from lane p % 64 with readlane (scalar registers, no LDS
+// traffic: the LDS pipe is shared by all 16 waves); the row slot p / 64 is
+// dispatched once per step by a scalar branch, so the readlanes take the
+// registers in place instead of a VALU copy of the chosen slot.  u and p are
+// double-buffered by the parity of k; u is zero past row n; used-row marks
+// live in registers.
 // Body of one 1024-thread block: matrix A (n x n), diagonal of the inverse
 // into drow[n]; a zero pivot sets *sing to at most widx.
 template <int RP, int CP>
@@ -201,23 +267,18 @@ __device__ __forceinline__ void gj_reg_body(const cplx* __restrict__ A, int n,
   // Owner wave of column kc (current values c): choose the pivot, publish u
   // into buffer pb, p and sor[p].
   auto choose = [&](const cplx (&c)[RP], int kc, int pb) {
-    unsigned long long best = 0ull;
+    unsigned best = 0u;
 #pragma unroll
     for (int a = 0; a < RP; ++a) {
       const int i = l + 64 * a;
-      if (i < n && !((used >> a) & 1u)) best = max(best, pivot_key(c[a], i));
+      if (i < n && !((used >> a) & 1u)) best = max(best, pivot_key32(c[a], i));
     }
-    best = wave_max_u64(best);
-    const int p = __builtin_amdgcn_readfirstlane(0xFFF - (int)(best & 0xFFFull));
+    best = wave_max_u32(best);
+    const int p = __builtin_amdgcn_readfirstlane(0xFFF - (int)(best & 0xFFFu));
     const int pl = p & 63, pa = p >> 6;
-    cplx pv = {0.0, 0.0};
-#pragma unroll
-    for (int a = 0; a < RP; ++a) {
-      const cplx x = {readlane_d(c[a].re, pl), readlane_d(c[a].im, pl)};
-      if (a == pa) pv = x;
-    }
+    const cplx pv = readlane_slot<RP>(c, pa, pl);
     if (bad_pivot(pv)) singular = true;
-    const cplx inv = cinv(pv);
+    const cplx inv = cinv_nr(pv);
 #pragma unroll
     for (int a = 0; a < RP; ++a) {
       const int i = l + 64 * a;
@@ -238,54 +299,69 @@ __device__ __forceinline__ void gj_reg_body(const cplx* __restrict__ A, int n,
     for (int a = 0; a < RP; ++a) c[a] = m[a][0];
     choose(c, 0, 0);
   }
-  // Step k = 16 kb + kk; with kb and t unrolled every register index is
-  // static.  Columns are visited from slot kb onwards, so column k + 1 (slot
-  // kb, or kb + 1 when kk = 15) is updated first or second by its owner.
+  // Step k = 16 kb + kk; with kb, t and the row slot unrolled every register
+  // index is static.  The owner of column k + 1 (slot kb, or kb + 1 when
+  // kk = 15) updates it and chooses before its other columns.
 #pragma unroll
   for (int kb = 0; kb < CP; ++kb) {
     for (int kk = 0; kk < NW; ++kk) {
       const int k = NW * kb + kk;
       if (k >= n) break;
       const int par = k & 1;
+      // the owner of column k + 1 runs at raised wave priority until it has
+      // published, so that its chain is issued ahead of the other waves' FMAs
+      if (v == (k + 1) % NW) __builtin_amdgcn_s_setprio(3);
       __syncthreads();  // u, p of column k published
       const int p = __builtin_amdgcn_readfirstlane(prow[par]);
       const int pl = p & 63, pa = p >> 6;
-      if (l == pl) used |= 1u << pa;
-      cplx wr[CP];  // row p of this wave's columns (lane pl), wave-uniform
-#pragma unroll
-      for (int b = 0; b < CP; ++b) {
-        cplx x = m[0][b];
-#pragma unroll
-        for (int a = 1; a < RP; ++a)
-          if (a == pa) x = opaque(m[a][b]);
-        wr[b] = {readlane_d(x.re, pl), readlane_d(x.im, pl)};
-      }
-      if (v == kk) wr[kb] = wk;  // owner of column k: w_k = piv + 1
       cplx u[RP];
 #pragma unroll
       for (int a = 0; a < RP; ++a) u[a] = ucol[par][l + 64 * a];
+      if (l == pl) used |= 1u << pa;
       const int k1 = k + 1;
       const bool owner1 = k1 < n && v == k1 % NW;  // owns column k + 1
       const bool next = kk == NW - 1;               // column k + 1 in slot kb + 1
+      // m[.][b] -= u w^T for one column
+      auto update = [&](int b, cplx w) __attribute__((always_inline)) {
 #pragma unroll
-      for (int t = 0; t < CP; ++t) {
-        const int b = (kb + t) % CP;
-        if (v + NW * b < n) {
-          const cplx w = wr[b];
-#pragma unroll
-          for (int a = 0; a < RP; ++a) {
-            m[a][b].re = fma(-u[a].re, w.re, m[a][b].re);
-            m[a][b].re = fma(u[a].im, w.im, m[a][b].re);
-            m[a][b].im = fma(-u[a].re, w.im, m[a][b].im);
-            m[a][b].im = fma(-u[a].im, w.re, m[a][b].im);
-          }
+        for (int a = 0; a < RP; ++a) {
+          m[a][b].re = fma(-u[a].re, w.re, m[a][b].re);
+          m[a][b].re = fma(u[a].im, w.im, m[a][b].re);
+          m[a][b].im = fma(-u[a].re, w.im, m[a][b].im);
+          m[a][b].im = fma(-u[a].im, w.re, m[a][b].im);
         }
-        if (owner1 && ((t == 0 && !next) || (t == 1 && next))) {
+      };
+      if (owner1) {
+        auto update_choose = [&](int b) __attribute__((always_inline)) {
           cplx c[RP];
 #pragma unroll
           for (int a = 0; a < RP; ++a) c[a] = m[a][b];
+          update(b, readlane_slot<RP>(c, pa, pl));  // column k + 1 is never column k
+#pragma unroll
+          for (int a = 0; a < RP; ++a) c[a] = m[a][b];
           choose(c, k1, par ^ 1);
+        };
+        if (!next)
+          update_choose(kb);
+        else
+          update_choose(kb + 1 < CP ? kb + 1 : CP - 1);  // k1 < n keeps kb + 1 < CP
+      }
+      __builtin_amdgcn_s_setprio(0);
+      cplx wr[CP];  // row p of this wave's columns (lane pl), wave-uniform
+      // pa is wave-uniform: one scalar branch per row slot, and inside it
+      // the readlanes take the registers in place (no VALU copies)
+#pragma unroll
+      for (int a = 0; a < RP; ++a)
+        if (a == pa) {
+#pragma unroll
+          for (int b = 0; b < CP; ++b) wr[b] = {readlane_d(m[a][b].re, pl), readlane_d(m[a][b].im, pl)};
         }
+      if (v == kk) wr[kb] = wk;  // owner of column k: w_k = piv + 1
+#pragma unroll
+      for (int t = 0; t < CP; ++t) {
+        const int b = (kb + t) % CP;
+        const bool done = owner1 && ((t == 0 && !next) || (t == 1 && next));
+        if (v + NW * b < n && !done) update(b, wr[b]);
       }
     }
   }
