@@ -5,29 +5,30 @@ method, compared point by point with the method alone.
 
 Workload: the Si-like cell of the mixed batch with smooth bands (the loss
 must be a function of Q = q + G), 9^3 k, N_G = 259, eta = 0.1 eV.
-Training: N_TRAIN_Q random q x 16 random w x 259 G samples, 10% held out.
-Query grid: 40 other random q x 97 w x 259 G = 1,004,920 points.
+Training: N_TRAIN_Q random q x N_W_TRAIN random w x 259 G samples, 10% held
+out.  Query grid: 40 other random q x 97 w x 259 G = 1,004,920 points.
 
-Accuracy is measured per loss curve: for each (q, G), the curve along the 97
-frequencies, the error of a point in units of the curve's maximum,
-|L - L_method| / max_w |L_method|, and the curve's error the largest of
-those (a normwise measure).  qcx_mlp_infer accepts a frequency row when every
-point's estimate in these units is within the tolerance, and recomputes it
-with the method otherwise.
+Accuracy is measured pointwise (relative error of the loss) and per loss
+curve: for each (q, G), the curve along the 97 frequencies, the error of a
+point in units of the curve's maximum, |L - L_method| / max_w |L_method|, and
+the curve's error the largest of those (a normwise measure).
+qcx_mlp_infer accepts a frequency row when every point's estimate in these
+units is within the tolerance, and recomputes it with the method otherwise.
 
 The expensive part runs once (module fixture); the tests below read its
 numbers.  Met, and asserted:
   * training lowers every member's loss by 10x;
   * the networks answer the grid far faster than the method;
+  * the networks alone reach a median relative error within 2e-2, on
+    held-out samples of the training momenta and on the new momenta;
   * every (q, w) row the estimate rejects is recomputed and carries the
     method's own values; the other rows keep the networks' answers;
   * at every tolerance (2e-2, 1e-1, 3e-1), at least 95% of the accepted
     points are within it, and after fallback 99% of the curves are;
   * at 2e-2, surrogate plus fallback is faster than the method alone.
-Not met, marked xfail with the measured values: the networks alone reach
-2e-2 neither as a median relative error (about 4e-2 on held-out samples and
-5e-2 on new momenta) nor per curve (the peaks of the curves are where they
-err most), so about half of the rows fall back at 2e-2.
+Not met, marked xfail with the measured value: per curve the networks alone
+are not within 2e-2 (median curve error about 0.1: the curves' peaks are
+where they err most), so about half of the rows fall back at 2e-2.
 """
 import time
 
@@ -37,10 +38,12 @@ import pytest
 from synth.surrogate import (SURR_SEED, batch_order, holdout_split, make_surrogate_workload, mlp_init, q_max,
                              random_q, random_w)
 
-pytestmark = pytest.mark.gpu
+# sampling and training take a few minutes: the fixture's time counts towards the first test
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
-N_TRAIN_Q = 768
-EPOCHS = 20
+N_TRAIN_Q = 2048
+N_W_TRAIN = 24
+EPOCHS = 40
 BATCH = 4096
 TOLS = (2e-2, 1e-1, 3e-1)
 
@@ -56,7 +59,7 @@ def run():
     tq = random_q(SURR_SEED + 10, base.cell.lat, N_TRAIN_Q)
     qq = random_q(SURR_SEED + 20, base.cell.lat, 40)
     wl = make_surrogate_workload(list(tq) + list(qq))
-    tw = random_w(SURR_SEED + 11, len(tq), 16)
+    tw = random_w(SURR_SEED + 11, len(tq), N_W_TRAIN)
     wq = [np.linspace(0.0, 60.0, 97)] * len(qq)
     ctx = Context(0)
     b = wl.basis
@@ -71,10 +74,18 @@ def run():
         st = qstates[iq]
         ctx.set_states(st.q_cart, wl.k_frac, wl.n_occ, st.C_k, st.E_k, st.C_kq, st.E_kq)
 
-    print(f"surrogate: sampling {N_TRAIN_Q} training momenta", flush=True)
-    smp = S.sample(ctx, set_train, tq, wl.G_int, wl.cell.lat, tw, wl.eta_eV)
+    print(f"surrogate: sampling {N_TRAIN_Q} training momenta x {N_W_TRAIN} frequencies", flush=True)
+    parts = []
+    for c0 in range(0, N_TRAIN_Q, 512):     # in chunks, with a progress line each
+        c1 = min(c0 + 512, N_TRAIN_Q)
+        parts.append(S.sample(ctx, lambda i, o=c0: set_train(i + o), tq[c0:c1], wl.G_int, wl.cell.lat,
+                              tw[c0:c1], wl.eta_eV))
+        print(f"surrogate: sampled {c1} of {N_TRAIN_Q} momenta", flush=True)
+    smp = S.Samples(torch.cat([p.qw for p in parts]), torch.cat([p.loss for p in parts]),
+                    np.concatenate([p.q_index + c0 for p, c0 in zip(parts, range(0, N_TRAIN_Q, 512))]),
+                    np.concatenate([p.w_index for p in parts]))
     n = smp.qw.shape[0]
-    assert n == N_TRAIN_Q * 16 * 259
+    assert n == N_TRAIN_Q * N_W_TRAIN * 259
     tr, ho = holdout_split(SURR_SEED + 12, n)
     sur = S.Surrogate(ctx, 4)
     hists = sur.fit(smp, tr, q_max(wl), 60.0, wl.cell.lat, lambda k: mlp_init(SURR_SEED + 100 + k),
@@ -186,10 +197,17 @@ def test_gain_at_2e2(run):
     assert f["gain"] > 1.0
 
 
-@pytest.mark.xfail(reason="not met: the networks reach a held-out median relative error of "
-                          "about 4e-2 and about 5e-2 on new momenta, not 2e-2; per curve their "
-                          "median error is about 0.25 (at the peaks)", strict=False)
-def test_network_alone_meets_2e2(run):
-    assert np.median(run["cal"]["rel_err"]) <= 2e-2
-    assert np.median(run["rel_net"]) <= 2e-2
+def test_network_alone_median_within_2e2(run):
+    """The networks alone, without fallback: median relative error of the
+    loss within 2e-2 on held-out samples and on the new momenta."""
+    ho, new = np.median(run["cal"]["rel_err"]), np.median(run["rel_net"])
+    print(f"networks alone: held-out median {ho:.4g}, new momenta median {new:.4g}")
+    assert ho <= 2e-2
+    assert new <= 2e-2
+
+
+@pytest.mark.xfail(reason="not met: per loss curve (error in units of the curve's maximum) the "
+                          "networks alone have a median curve error of about 0.1, at the peaks",
+                   strict=False)
+def test_network_alone_per_curve_2e2(run):
     assert np.median(run["curve_net"]) <= 2e-2
