@@ -467,6 +467,39 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
     }
     wk = {pv.re + 1.0, pv.im};
   };
+  // Up to five row slots (N_G <= 320) the sweep takes the register kernel's
+  // short pivot chain (32-bit keys, the pivot read under a scalar branch on its
+  // slot, Newton-refined reciprocal, the owner at raised priority); the larger
+  // classes keep the form above, which spills fewer registers there.
+  constexpr bool SHORT = RP <= 5;
+  auto choose_short = [&](const cplx (&c)[RP], int kc, int pb) {
+    const int lo = opaque_i(l);
+    unsigned best = 0u;
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const int i = lo + 64 * a;
+      if (i < n && !((used >> a) & 1u)) best = max(best, pivot_key32(c[a], i));
+    }
+    best = wave_max_u32(best);
+    const int p = __builtin_amdgcn_readfirstlane(0xFFF - (int)(best & 0xFFFu));
+    const int pl = p & 63, pa = p >> 6;
+    const cplx pv = readlane_slot<RP>(c, pa, pl);
+    if (bad_pivot(pv)) singular = true;
+    const cplx inv = cinv_nr(pv);
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const int i = lo + 64 * a;
+      cplx y = c[a];
+      if (i == p) y.re -= 1.0;
+      if (i < n) ucol[pb * 64 * RP + i] = cmul(y, inv);
+    }
+    if (l == 0) {
+      prow[pb] = p;
+      piv[kc] = p;
+      sor[p] = kc;
+    }
+    wk = {pv.re + 1.0, pv.im};
+  };
 
   auto load_col = [&](cplx (&pm)[RP], int jc) {
     const int lo = opaque_i(l);
@@ -522,9 +555,16 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
   // in pm; each wave's column goes back to A afterwards.
   auto sweep = [&](cplx (&pm)[RP], int s0, int ms) {
     const bool hascol = v < ms;
-    if (v == 0) choose(pm, s0, s0 & 1);
+    if (v == 0) {
+      if constexpr (SHORT)
+        choose_short(pm, s0, s0 & 1);
+      else
+        choose(pm, s0, s0 & 1);
+    }
     for (int kk = 0; kk < ms; ++kk) {
       const int k = s0 + kk, par = k & 1;
+      // the owner of column k + 1 at raised priority until it has published
+      if (SHORT && v == kk + 1) __builtin_amdgcn_s_setprio(3);
       __syncthreads();  // u, p of column k published
       const int p = __builtin_amdgcn_readfirstlane(prow[par]);
       const int pl = p & 63, pa = p >> 6;
@@ -534,8 +574,9 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
         cplx x = pm[0];
 #pragma unroll
         for (int a = 1; a < RP; ++a)
-          if (a == pa) x = opaque(pm[a]);
+          if (!SHORT && a == pa) x = opaque(pm[a]);
         cplx w = {readlane_d(x.re, pl), readlane_d(x.im, pl)};
+        if constexpr (SHORT) w = readlane_slot<RP>(pm, pa, pl);
         if (v == kk) w = wk;  // owner of column k: w_k = piv + 1
 #pragma unroll
         for (int a = 0; a < RP; ++a) {
@@ -548,8 +589,14 @@ __device__ __forceinline__ void gj_panel_body(cplx* __restrict__ A, int n,
           // keep the scheduler from hoisting all RP loads of u at once
           if ((a & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
-        if (kk + 1 < ms && v == kk + 1) choose(pm, k + 1, par ^ 1);
+        if (kk + 1 < ms && v == kk + 1) {
+          if constexpr (SHORT)
+            choose_short(pm, k + 1, par ^ 1);
+          else
+            choose(pm, k + 1, par ^ 1);
+        }
       }
+      if (SHORT) __builtin_amdgcn_s_setprio(0);
     }
     if (hascol) store_col(pm, s0 + v);
   };
