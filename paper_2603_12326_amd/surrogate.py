@@ -97,11 +97,13 @@ class Surrogate:
 
     def fit(self, s: Samples, train_idx: np.ndarray, q_max: float, w_max: float, lattice,
             init_params: Callable[[int], np.ndarray], orders: Callable[[int, int, int], np.ndarray],
-            batch: int = 1024, epochs: int = 40, lr0: float = 2e-3, lr1: float = 2e-5):
+            batch: int = 1024, epochs: int = 40, lr0: float = 2e-3, lr1: float = 2e-5,
+            progress: Optional[Callable[[int], None]] = None):
         """Train every member on the samples train_idx; lattice (3 x 3, rows
         the primitive vectors, bohr) sets the periodic features of the
         encoding; init_params(k) gives member k's initial parameters and
-        orders(k, n, batch) its sample order (indices into train_idx)."""
+        orders(k, n, batch) its sample order (indices into train_idx);
+        progress(k), if given, is called once member k has trained."""
         import torch
 
         tl = np.log(np.maximum(s.loss.cpu().numpy()[train_idx], 1e-30))
@@ -122,6 +124,9 @@ class Surrogate:
             self.net.set_params(k, init_params(k))
             order = torch.from_numpy(orders(k, n, batch)).cuda()
             hists.append(self.net.train(k, x, t, batch, order, lr0, lr1))
+            if progress is not None:
+                torch.cuda.synchronize()
+                progress(k)
         torch.cuda.synchronize()
         self.train_seconds = time.perf_counter() - t0
         return hists

@@ -49,8 +49,19 @@ TOLS = (2e-2, 1e-1, 3e-1)
 
 
 @pytest.fixture(scope="module")
-def run():
+def run(request):
     import torch
+
+    # progress lines reach the terminal even under output capture, so that a
+    # run of several minutes is never silent for long
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+
+    def say(msg):
+        if capman is None:
+            print(msg, flush=True)
+            return
+        with capman.global_and_fixture_disabled():
+            print(msg, flush=True)
 
     from paper_2603_12326_amd import Context
     from paper_2603_12326_amd import surrogate as S
@@ -74,13 +85,13 @@ def run():
         st = qstates[iq]
         ctx.set_states(st.q_cart, wl.k_frac, wl.n_occ, st.C_k, st.E_k, st.C_kq, st.E_kq)
 
-    print(f"surrogate: sampling {N_TRAIN_Q} training momenta x {N_W_TRAIN} frequencies", flush=True)
+    say(f"surrogate: sampling {N_TRAIN_Q} training momenta x {N_W_TRAIN} frequencies")
     parts = []
     for c0 in range(0, N_TRAIN_Q, 512):     # in chunks, with a progress line each
         c1 = min(c0 + 512, N_TRAIN_Q)
         parts.append(S.sample(ctx, lambda i, o=c0: set_train(i + o), tq[c0:c1], wl.G_int, wl.cell.lat,
                               tw[c0:c1], wl.eta_eV))
-        print(f"surrogate: sampled {c1} of {N_TRAIN_Q} momenta", flush=True)
+        say(f"surrogate: sampled {c1} of {N_TRAIN_Q} momenta")
     smp = S.Samples(torch.cat([p.qw for p in parts]), torch.cat([p.loss for p in parts]),
                     np.concatenate([p.q_index + c0 for p, c0 in zip(parts, range(0, N_TRAIN_Q, 512))]),
                     np.concatenate([p.w_index for p in parts]))
@@ -90,11 +101,12 @@ def run():
     sur = S.Surrogate(ctx, 4)
     hists = sur.fit(smp, tr, q_max(wl), 60.0, wl.cell.lat, lambda k: mlp_init(SURR_SEED + 100 + k),
                     lambda k, nn, bs: batch_order(SURR_SEED + 200 + k, nn, bs, EPOCHS),
-                    batch=BATCH, epochs=EPOCHS, lr0=3e-3, lr1=1e-5)
+                    batch=BATCH, epochs=EPOCHS, lr0=3e-3, lr1=1e-5,
+                    progress=lambda k: say(f"surrogate: member {k + 1} of 4 trained"))
     cal = sur.calibrate(smp, ho)
-    print(f"trained 4 members in {sur.train_seconds:.1f} s; held-out relative error "
-          f"q50 {np.quantile(cal['rel_err'], .5):.3g} q90 {np.quantile(cal['rel_err'], .9):.3g}; "
-          f"calibration factor {cal['calib']:.3g}", flush=True)
+    say(f"trained 4 members in {sur.train_seconds:.1f} s; held-out relative error "
+        f"q50 {np.quantile(cal['rel_err'], .5):.3g} q90 {np.quantile(cal['rel_err'], .9):.3g}; "
+        f"calibration factor {cal['calib']:.3g}")
 
     # the method alone on the query grid (a first pass tunes the bulk for this
     # shape; the second is timed)
@@ -121,16 +133,16 @@ def run():
     net = Ls.cpu().numpy().reshape(refh.shape)
     rel_net = np.abs(net / refh - 1)
     est = Es.cpu().numpy().reshape(refh.shape)
-    print(f"{grid.shape[0]} queries: method {t_plain:.3f} s, networks {1e3 * t_net:.2f} ms "
-          f"({t_plain / t_net:.0f}x); networks alone: median {np.median(rel_net):.3g}, "
-          f"within 2e-2 {np.mean(rel_net <= 2e-2):.3f}", flush=True)
+    say(f"{grid.shape[0]} queries: method {t_plain:.3f} s, networks {1e3 * t_net:.2f} ms "
+        f"({t_plain / t_net:.0f}x); networks alone: median {np.median(rel_net):.3g}, "
+        f"within 2e-2 {np.mean(rel_net <= 2e-2):.3f}")
 
     # errors in units of each (q, G) curve's maximum along the frequencies
     refmax = np.abs(refh).max(axis=1, keepdims=True)
     pt_net = np.abs(net - refh) / refmax
     curve_net = pt_net.max(axis=1)
-    print(f"networks alone per curve: median {np.median(curve_net):.3g}, "
-          f"within 2e-2 {np.mean(curve_net <= 2e-2):.3f}", flush=True)
+    say(f"networks alone per curve: median {np.median(curve_net):.3g}, "
+        f"within 2e-2 {np.mean(curve_net <= 2e-2):.3f}")
 
     fb = {}
     for tol in TOLS:
@@ -146,11 +158,11 @@ def run():
                        rows_kept=float(kept.mean()),
                        accepted_within=float(np.mean(pt_net[acc] <= tol)) if acc.any() else 1.0,
                        curves_within=float(np.mean(curve <= tol)), curve_max=float(curve.max()))
-        print(f"tol {tol}: rows answered by the networks {fb[tol]['rows_kept']:.3f} "
-              f"(their points within tol {fb[tol]['accepted_within']:.4f}), curves within tol "
-              f"after fallback {fb[tol]['curves_within']:.4f} (largest {fb[tol]['curve_max']:.3g}), "
-              f"fallback rows {st['fallback_points']}/{refh.shape[0] * refh.shape[1]}, "
-              f"time {st['t_total']:.3f} s, gain {fb[tol]['gain']:.2f}x", flush=True)
+        say(f"tol {tol}: rows answered by the networks {fb[tol]['rows_kept']:.3f} "
+            f"(their points within tol {fb[tol]['accepted_within']:.4f}), curves within tol "
+            f"after fallback {fb[tol]['curves_within']:.4f} (largest {fb[tol]['curve_max']:.3g}), "
+            f"fallback rows {st['fallback_points']}/{refh.shape[0] * refh.shape[1]}, "
+            f"time {st['t_total']:.3f} s, gain {fb[tol]['gain']:.2f}x")
     yield dict(hists=hists, cal=cal, refh=refh, net=net, rel_net=rel_net, est=est, t_plain=t_plain,
                t_net=t_net, fb=fb, curve_net=curve_net)
     sur.close()
