@@ -215,6 +215,11 @@ int qcx_eps_inv(qcx_ctx* ctx, int lfe, void* diag_out, void* epsM_out);
  * Asynchronous.  A zero or non-finite pivot (or eps_GG for lfe = 0) is
  * reported by the next qcx_sync as QCX_ESINGULAR naming the lowest such
  * frequency index.
+ * Accuracy: the elimination folds each pivot into its rank-1 update (u_p =
+ * (piv - 1) / piv, w_k = piv + 1), which keeps FP64 accuracy for pivots of
+ * order one or below, as in eps = 1 - v chi0, at any scale down to the
+ * smallest normal doubles; pivots far above one lose about eps |piv|
+ * relative accuracy in their row, so such matrices should be scaled first.
  * Errors: QCX_EINVAL (sizes, NULL buffers), QCX_ENOMEM. */
 int qcx_eps_inv_given(qcx_ctx* ctx, int n_w, int n_G, const void* eps, int lfe, double* loss_out,
                       void* diag_out, void* epsM_out);

@@ -84,9 +84,21 @@ __global__ void k_assemble(AsmArgs a, Chi0Geom g, int mode, cplx* __restrict__ o
   if (G != Gp) out[base + (size_t)Gp * g.n_g + G] = cba;
 }
 
+// 1/a = conj(a) / |a|^2 with a first scaled by the binary exponent of
+// max(|re|, |im|) (exact), so that |a|^2 neither underflows nor overflows for
+// any finite nonzero a; zero and non-finite a take the plain formula (they
+// are reported as singular pivots).
 __device__ inline cplx cinv(cplx a) {
-  const double d = 1.0 / (a.re * a.re + a.im * a.im);
-  return {a.re * d, -a.im * d};
+  const double s = fmax(fabs(a.re), fabs(a.im));
+  if (!(s > 0.0 && s < INFINITY)) {
+    const double d = 1.0 / (a.re * a.re + a.im * a.im);
+    return {a.re * d, -a.im * d};
+  }
+  int e;
+  (void)frexp(s, &e);
+  const double x = ldexp(a.re, -e), y = ldexp(a.im, -e);
+  const double d = 1.0 / (x * x + y * y);
+  return {ldexp(x * d, -e), ldexp(-y * d, -e)};
 }
 
 // A pivot of modulus zero, or a non-finite one (NaN or infinite entries, e.g.
@@ -169,18 +181,18 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long x) {
   return r;
 }
 
-// 32-bit pivot key: the modulus |re| + |im| rounded down to a float with 11
-// mantissa bits in the high 20 bits (non-negative floats order like their
-// bit patterns), the complement of the row index in the low 12 bits, so that
-// moduli equal to that precision go to the smaller row.  Partial pivoting
-// then takes a pivot within a factor 1 - 2^-11 of the largest modulus, which
-// bounds the growth of the elimination as the exact choice does.  A NaN entry
-// counts as infinite.  Every key of a live row is > 0 except for modulus 0.
+// 32-bit pivot key: the high word of the modulus |re| + |im| as a double (its
+// exponent and 8 mantissa bits; non-negative doubles order like their bit
+// patterns, over the whole double range) with the low 12 bits replaced by the
+// complement of the row index, so that moduli equal to that precision go to
+// the smaller row.  Partial pivoting then takes a pivot within a factor
+// 1 - 2^-8 of the largest modulus.  A NaN entry counts as infinite.  Every key
+// of a live row is > 0 except for modulus 0.
 __device__ inline unsigned pivot_key32(cplx v, int row) {
   double mag = fabs(v.re) + fabs(v.im);
   if (mag != mag) mag = INFINITY;
-  const unsigned b = __float_as_uint((float)mag);
-  return (b & ~0xFFFu) | (unsigned)(0xFFF - row);
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(mag) >> 32);
+  return (hi & ~0xFFFu) | (unsigned)(0xFFF - row);
 }
 
 // Maximum of a 32-bit value over the wave: DPP butterflies inside each row of
@@ -204,21 +216,24 @@ __device__ inline unsigned wave_max_u32(unsigned x) {
   return r;
 }
 
-// 1/|a|^2 from a single-precision estimate refined by two Newton steps in
-// FP64 (24 -> 48 -> 96 bits: within an ulp of the FP64 reciprocal), a shorter
-// chain of dependent instructions than the IEEE division; outside the
-// single-precision range, the division.
+// 1/a as cinv, with 1/|a|^2 of the scaled a (in [1/4, 2)) from a
+// single-precision estimate refined by two Newton steps in FP64 (24 -> 48 ->
+// 96 bits: within an ulp of the FP64 reciprocal), a shorter chain of
+// dependent instructions than the IEEE division.
 __device__ inline cplx cinv_nr(cplx a) {
-  const double d = a.re * a.re + a.im * a.im;
-  double r;
-  if (!(d > 1e-30 && d < 1e30)) {
-    r = 1.0 / d;
-  } else {
-    r = (double)__builtin_amdgcn_rcpf((float)d);
-    r = fma(r, fma(-d, r, 1.0), r);
-    r = fma(r, fma(-d, r, 1.0), r);
+  const double s = fmax(fabs(a.re), fabs(a.im));
+  if (!(s > 0.0 && s < INFINITY)) {
+    const double d = 1.0 / (a.re * a.re + a.im * a.im);
+    return {a.re * d, -a.im * d};
   }
-  return {a.re * r, -a.im * r};
+  int e;
+  (void)frexp(s, &e);
+  const double x = ldexp(a.re, -e), y = ldexp(a.im, -e);
+  const double d = x * x + y * y;
+  double r = (double)__builtin_amdgcn_rcpf((float)d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return {ldexp(x * r, -e), ldexp(-y * r, -e)};
 }
 
 // Register-resident Gauss-Jordan for n <= 64 RP and n <= 16 CP with 16 waves:

@@ -234,6 +234,41 @@ def test_large_ng_panel_inversion(ctx, n_g):
     assert esp < 1e-4
 
 
+# every Gauss-Jordan kernel class at both ends of its range: register-resident
+# (n <= 64, 65..128), panel (129..192, ..256, ..320, ..512, ..768, ..1024)
+_GJ_SIZES = [1, 2, 17, 64, 65, 113, 128, 129, 192, 193, 256, 257, 320, 321, 512, 513, 768, 769, 1024]
+
+
+@pytest.mark.parametrize("n_g", _GJ_SIZES)
+def test_inverse_diagonal_every_class(ctx, n_g):
+    """diag(eps^-1) of caller-supplied matrices (qcx_eps_inv_given) against the
+    oracle's inverse, on matrices that need row exchanges (complex Gaussian
+    entries, not diagonally dominant, one with a zero leading entry), and on
+    one scaled by 1e-200, where |a|^2 underflows: the pivot order and the
+    reciprocal must hold at that scale.  (Pivots far above one are outside
+    the kernels' accuracy statement: the pivot is folded into the update.)
+    FP64 bar 1e-10 (normwise over each matrix, the inverse's condition
+    included: these matrices have condition numbers of a few hundred to a few
+    thousand)."""
+    import torch
+
+    rng = np.random.default_rng(1000 + n_g)
+    n_w = 3
+    e = (rng.normal(size=(n_w, n_g, n_g)) + 1j * rng.normal(size=(n_w, n_g, n_g))) / np.sqrt(n_g)
+    if n_g > 1:
+        e[0, 0, 0] = 0.0                       # the first pivot must come from another row
+    e[2] *= 1e-200                             # |entries|^2 underflows
+    print("inverse diagonal, n_G", n_g, flush=True)
+    diag = torch.empty((n_w, n_g), dtype=torch.complex128, device="cuda")
+    ctx.eps_inv_given(torch.from_numpy(e).cuda(), True, diag_out=diag)
+    ctx.sync()
+    got = diag.cpu().numpy()
+    for i in range(n_w):
+        ref = rpa.inverse_diagonal(e[i:i + 1])[0]
+        err = np.max(np.abs(got[i] - ref)) / np.max(np.abs(ref))
+        assert err < 1e-10, (n_g, i, err)
+
+
 def test_autotuned_bulk(ctx, small_wl):
     """The bulk autotuner: the first call of a new shape times every candidate
     (tune_ms > 0), later calls reuse the choice (tune_ms == 0); the heuristic
