@@ -108,10 +108,10 @@ __device__ inline bool bad_pivot(cplx v) {
   return !(m > 0.0 && m < INFINITY);
 }
 
-// Pivot key for an LDS atomic maximum: the modulus |re| + |im| in the high
+// 64-bit pivot key for a wave maximum: the modulus |re| + |im| in the high
 // bits (non-negative doubles order like their bit patterns), the complement
-// of the row index in the low 12 bits, so that moduli equal to 40 bits go to
-// the smaller row.  A NaN entry counts as infinite so that it still selects a
+// of the row index in the low 12 bits, so that moduli equal to 40 mantissa
+// bits go to the smaller row.  A NaN entry counts as infinite so that it still selects a
 // row (and poisons the result instead of hiding).  Every key is > 0.
 __device__ inline unsigned long long pivot_key(cplx v, int row) {
   double mag = fabs(v.re) + fabs(v.im);
