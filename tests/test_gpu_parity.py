@@ -359,6 +359,26 @@ def test_all_electron_full_size():
     c.close()
 
 
+def test_all_electron_full_size_nolfe_against_oracle(ctx):
+    """The all-electron workload at its full 12^3 k grid (N_T = 870,912; 5 core
+    bands, tight core exponents) against the oracle on sampled G: the noLFE
+    loss Im(-1/eps_GG) (qcx_loss_diag: pair densities at those G over the
+    whole k grid, the diagonal contraction) at 7 G spread over the 749 and 6
+    frequencies, FP64 within 1e-10 and split-BF16 within 1e-4 (normwise)."""
+    wl = make_all_electron()
+    st = set_inputs(ctx, wl)
+    G = wl.G_int[[0, 1, 50, 200, 400, 600, 748]]
+    w = wl.w_eV[[10, 100, 250, 500, 750, 900]]
+    print("all-electron full size, noLFE on 7 G", flush=True)
+    ref = rpa.loss_diag(wl.cell, wl.basis, wl.lattice_range, wl.k_frac, wl.n_occ, G, st, w,
+                        wl.eta_eV)
+    e64 = normwise(ctx.loss_diag(G, w, wl.eta_eV, "fp64").cpu().numpy(), ref)
+    esp = normwise(ctx.loss_diag(G, w, wl.eta_eV, "split_bf16").cpu().numpy(), ref)
+    print(f"all-electron full size noLFE vs oracle: fp64 {e64:.3g}, split {esp:.3g}")
+    assert e64 < 1e-10
+    assert esp < 1e-4
+
+
 def test_device_state_checks_deferred(small_wl):
     """Device-resident states are checked on the stream: a bad coefficient
     matrix does not raise at set_states but at the next synchronising call;
