@@ -143,6 +143,48 @@ def test_ragged_shapes(ctx):
             assert normwise(out["loss"], ref["loss"]) < tol, (prec, len(w))
 
 
+def test_size_limits_and_empty_inputs(ctx):
+    """Edge sizes through the C ABI: only G = 0 (n_G = 1, where the LFE and
+    noLFE forms coincide); the largest frequency count of one call (65536),
+    checked against the oracle on sampled frequencies in FP64 and
+    split-BF16; and empty or oversized requests (no frequency, 65537
+    frequencies, no G, 4097 G) returned as QCX_EINVAL, after which the
+    context still works."""
+    from paper_2603_12326_amd import QcxError
+    from paper_2603_12326_amd import qcx as q
+
+    wl = make_tiny(kgrid=1, n_g=9)
+    w = np.linspace(0.5, 33.0, 5)
+    G1 = wl.G_int[:1]
+    ref = _oracle(wl, w=w, G=G1)
+    for lfe in (True, False):
+        out = gpu_solve(ctx, wl, precision="fp64", w_eV=w, G_int=G1, lfe=lfe)
+        assert normwise(out["loss"], ref["loss"]) < 1e-10
+    G = wl.G_int[:7]
+    wbig = np.linspace(0.05, 40.0, 65536)
+    idx = np.append(np.arange(0, 65536, 4099), 65535)
+    ref = _oracle(wl, w=wbig[idx], G=G)
+    for prec, tol in (("fp64", 1e-10), ("split_bf16", 1e-4)):
+        out = gpu_solve(ctx, wl, precision=prec, w_eV=wbig, G_int=G)
+        assert out["loss"].shape == (65536, 7)
+        e = normwise(out["loss"][idx], ref["loss"])
+        print("65536 frequencies", prec, e)
+        assert e < tol
+    set_inputs(ctx, wl)
+    ctx.pair_density(G)
+    for bad_w in (np.zeros(0), np.linspace(1.0, 2.0, 65537)):
+        with pytest.raises(QcxError) as e:
+            ctx.chi0(bad_w, wl.eta_eV, "fp64")
+        assert e.value.code == q.EINVAL
+    for bad_g in (np.zeros((0, 3), np.int32), np.zeros((4097, 3), np.int32)):
+        with pytest.raises(QcxError) as e:
+            ctx.pair_density(bad_g)
+        assert e.value.code == q.EINVAL
+    ref = _oracle(wl, w=w, G=G)
+    out = gpu_solve(ctx, wl, precision="fp64", w_eV=w, G_int=G)
+    assert normwise(out["loss"], ref["loss"]) < 1e-10
+
+
 @pytest.mark.parametrize("case", ["smallest", "ragged", "si_ng113"])
 def test_headwings_row_fp64(ctx, case):
     """The head and wings of the split-BF16 path (the FP64 GEMM over the
