@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--cpu-sample-w", type=int, default=400)
     ap.add_argument("--workload",
                     choices=["si-ng113", "mixed-batch", "composite", "kk", "rates", "optical",
-                             "all-electron"],
+                             "all-electron", "surrogate"],
                     default="si-ng113")
     ap.add_argument("--kk-bin", type=float, default=0.025, help="bin width (eV) of --workload kk")
     ap.add_argument("--calib-copy", action="store_true",
@@ -939,6 +939,185 @@ def main_allelectron(args):
     print(json.dumps(out))
 
 
+def main_surrogate(args):
+    """Loss surrogate (not in the paper): the dense (q + G, w) grid a rate
+    integral sweeps, answered by the networks with the method as fallback.
+    Untimed set-up: 2048 momenta x 24 frequencies sampled from the method
+    (N_G = 259, 9^3 k, smooth bands), four members trained for 40 epochs by
+    the library's kernels, the error estimate calibrated on held-out
+    samples (the setting of tests/test_gpu_surrogate.py).  Timed on the
+    1,004,920-point grid of 40 new momenta x 97 w x 259 G, each after one
+    untimed pass: the method alone, the networks alone, and the networks
+    with fallback at tolerance 2e-2 (qcx_mlp_infer), whose queries/s is the
+    value.  Roofline: the chi0 bulk of the fallback rows (the dominant
+    kernel of that pass, stage timing on the library's stream), and the
+    networks' BF16 MFMA work over the networks-alone pass.  CPU baseline:
+    the FP64 oracle network (four members, same parameters) on a sample of
+    the grid."""
+    import torch
+
+    from paper_2603_12326_amd import Context, build_info
+    from paper_2603_12326_amd import surrogate as S
+    from synth.surrogate import (SURR_SEED, batch_order, holdout_split, make_surrogate_workload,
+                                 mlp_init, q_max, random_q, random_w)
+
+    NQ, NW, EPOCHS, TOL = 2048, 24, 40, 2e-2
+    base = make_surrogate_workload([])
+    tq = random_q(SURR_SEED + 10, base.cell.lat, NQ)
+    qq = random_q(SURR_SEED + 20, base.cell.lat, 40)
+    wl = make_surrogate_workload(list(tq) + list(qq))
+    tw = random_w(SURR_SEED + 11, NQ, NW)
+    wq = [np.linspace(0.0, 60.0, 97)] * len(qq)
+    n_g = len(wl.G_int)
+    ctx = Context(0)
+    b = wl.basis
+    ctx.set_cell_basis(wl.cell.lat, wl.cell.xyz, b.shell_atom, b.shell_l, b.shell_exp, 1, 1)
+    qstates = [wl.states(NQ + i) for i in range(len(qq))]
+
+    def set_train(iq):
+        st = wl.states(iq)
+        ctx.set_states(st.q_cart, wl.k_frac, wl.n_occ, st.C_k, st.E_k, st.C_kq, st.E_kq)
+
+    def set_query(iq):
+        st = qstates[iq]
+        ctx.set_states(st.q_cart, wl.k_frac, wl.n_occ, st.C_k, st.E_k, st.C_kq, st.E_kq)
+
+    parts = []
+    for c0 in range(0, NQ, 512):
+        c1 = min(c0 + 512, NQ)
+        parts.append(S.sample(ctx, lambda i, o=c0: set_train(i + o), tq[c0:c1], wl.G_int,
+                              wl.cell.lat, tw[c0:c1], wl.eta_eV))
+        log(f"sampled {c1} of {NQ} momenta")
+    smp = S.Samples(torch.cat([x.qw for x in parts]), torch.cat([x.loss for x in parts]),
+                    np.concatenate([x.q_index + c0 for x, c0 in zip(parts, range(0, NQ, 512))]),
+                    np.concatenate([x.w_index for x in parts]))
+    tr, ho = holdout_split(SURR_SEED + 12, smp.qw.shape[0])
+    sur = S.Surrogate(ctx, 4)
+    sur.fit(smp, tr, q_max(wl), 60.0, wl.cell.lat, lambda k: mlp_init(SURR_SEED + 100 + k),
+            lambda k, nn, bs: batch_order(SURR_SEED + 200 + k, nn, bs, EPOCHS),
+            batch=4096, epochs=EPOCHS, lr0=3e-3, lr1=1e-5,
+            progress=lambda k: log(f"member {k + 1} of 4 trained"))
+    cal = sur.calibrate(smp, ho)
+    del smp, parts
+    n_query = len(qq) * 97 * n_g
+
+    def method_all():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = [S.method_loss(ctx, set_query, i, wl.G_int, wq[i], wl.eta_eV) for i in range(len(qq))]
+        ctx.sync()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    log("method alone: 1 untimed + 1 timed pass")
+    method_all()
+    ref, t_method = method_all()
+    refh = np.stack([r.cpu().numpy() for r in ref])
+
+    Gc = S.g_cart(wl.G_int, wl.cell.lat)
+    grid = torch.cat([torch.from_numpy(S.query_points(q, Gc, w)).cuda() for q, w in zip(qq, wq)])
+    log("networks alone: 1 untimed + 1 timed pass")
+    sur.query(grid)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    Ls, _, _, _ = sur.query(grid)
+    e1.record()
+    torch.cuda.synchronize()
+    t_net = time.perf_counter() - t0
+    net_dev_s = 1e-3 * e0.elapsed_time(e1)
+    net = Ls.cpu().numpy().reshape(refh.shape)
+    rel_net = np.abs(net / refh - 1)
+
+    log(f"networks with fallback at {TOL}: 1 untimed + 1 timed pass")
+    S.query_with_fallback(sur, ctx, set_query, len(qq), wl.G_int, wq, wl.eta_eV, TOL)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    got, st = S.query_with_fallback(sur, ctx, set_query, len(qq), wl.G_int, wq, wl.eta_eV, TOL)
+    stage = ctx.stage_times()
+    ctx.set_timing(False)
+    goth = np.stack([o.cpu().numpy() for o in got])
+    E = st.pop("err").cpu().numpy().reshape(refh.shape)
+    kept = ~(E > TOL).any(axis=2)
+    refmax = np.abs(refh).max(axis=1, keepdims=True)
+    curve = (np.abs(goth - refh) / refmax).max(axis=1)
+
+    # roofline of the fallback's chi0 bulk: Hermitian-form flops of the rows it
+    # recomputed (8 pairs n_t per frequency row, three BF16 products each)
+    pairs = n_g * (n_g + 1) // 2 - n_g
+    bulk_s = 1e-3 * stage["chi0_bulk_ms"]
+    nb = max(1, stage["bulk_launches"])
+    bulk_flops = 3.0 * 8.0 * pairs * wl.n_t * st["fallback_points"]
+    achieved = bulk_flops / bulk_s / 1e12 if bulk_s > 0 else 0.0
+    # the networks: 2 flops per weight per member and query
+    widths = (49, 256, 256, 256, 256, 1)
+    weights = sum(widths[i] * widths[i + 1] for i in range(len(widths) - 1))
+    net_flops = 2.0 * 4 * weights * n_query
+    out = {
+        "metric": "surrogate (q+G, w) loss queries/s with fallback to the method at 2e-2",
+        "value": n_query / st["t_total"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": 1e3 * st["t_total"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "Si-like fcc a=10.26 (mixed-batch cell), 10 GTO, 4+6 smooth bands, "
+                               "9^3 k, N_G=259, eta=0.1 eV; 4 networks 49->256x4->1 SiLU trained on "
+                               "2048 q x 24 w x 259 G; grid 40 new q x 97 w over 0-60 eV x 259 G",
+                   "n_query": n_query, "n_train_q": NQ, "n_train_w": NW, "epochs": EPOCHS,
+                   "tol": TOL},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                     "kernel": "k_bulk<bf16> (chi0 bulk of the fallback rows)",
+                     "avg_launch_ms": 1e3 * bulk_s / nb, "launches": nb,
+                     "flops_fp32_equiv_x3": bulk_flops},
+        "network_roofline": {"bound": "mfma", "achieved": net_flops / net_dev_s / 1e12,
+                             "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                             "frac": net_flops / net_dev_s / 1e12 / PEAK_BF16_TFLOPS,
+                             "kernel": "k_mlp (encode, 4 members x 5 layers, decode; one query "
+                                       "pass)", "ms": 1e3 * net_dev_s},
+        "method_alone_value": n_query / t_method,
+        "networks_alone_value": n_query / t_net,
+        "gain_vs_method": t_method / st["t_total"],
+        "rows_answered_by_networks": float(kept.mean()),
+        "fallback_rows": st["fallback_points"],
+        "networks_alone_median_rel_err_new_q": float(np.median(rel_net)),
+        "networks_alone_median_rel_err_held_out": float(np.median(cal["rel_err"])),
+        "curves_within_tol_after_fallback": float(np.mean(curve <= TOL)),
+        "largest_curve_err_after_fallback": float(curve.max()),
+        "stages_ms_fallback_pass": stage,
+        "train_s": sur.train_seconds,
+        "build": build_info(),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import mlp as omlp
+
+        n_s = 20000
+        sel = np.random.default_rng(SURR_SEED + 30).choice(n_query, n_s, replace=False)
+        qw = grid.cpu().numpy()[np.sort(sel)]
+        thetas = [sur.net.get_params(k).astype(np.float64) for k in range(4)]
+        log(f"cpu baseline (oracle network, {n_s} queries)")
+        t0 = time.perf_counter()
+        X = omlp.encode(qw, sur.q_max, sur.w_max, sur.lattice)
+        ys = [omlp.forward(th, X)[0] for th in thetas]
+        omlp.decode(ys, sur.mu, sur.sigma, sur.calib)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=n_s / dt, unit="queries/s", cores=int(blas_threads()),
+                                   kind="oracle",
+                                   sample=f"{n_s} random queries of the grid through the FP64 "
+                                          f"oracle network (4 members, the trained parameters, "
+                                          f"encode to decode), {dt:.1f} s")
+    sur.close()
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -958,6 +1137,8 @@ def main():
         return main_optical(args)
     if args.workload == "all-electron":
         return main_allelectron(args)
+    if args.workload == "surrogate":
+        return main_surrogate(args)
     import torch
 
     from paper_2603_12326_amd import Context, build_info
