@@ -143,6 +143,26 @@ def test_ragged_shapes(ctx):
             assert normwise(out["loss"], ref["loss"]) < tol, (prec, len(w))
 
 
+def test_chi0_static_limit_hermitian(ctx, small_wl):
+    """chi0 at eta = 0 below the gap (w = 0 and 0.5 eV, no transition
+    resonates): Hermitian, chi0_GG' = conj(chi0_G'G), as the oracle's pin
+    states for the same limit, and equal to the oracle's chi0 (FP64 1e-10,
+    split-BF16 1e-4, relative to the largest element of each frequency)."""
+    import dataclasses
+
+    wl = dataclasses.replace(small_wl, eta_eV=0.0)
+    w = np.array([0.0, 0.5])
+    ref = _oracle(wl, w=w)["chi0"]
+    for prec, tol in (("fp64", 1e-10), ("split_bf16", 1e-4)):
+        chi = gpu_solve(ctx, wl, precision=prec, w_eV=w, want_chi0=True)["chi0"]
+        scale = np.abs(ref).max(axis=(1, 2))[:, None, None]
+        err = np.max(np.abs(chi - ref) / scale)
+        herm = np.max(np.abs(chi - np.conj(np.swapaxes(chi, 1, 2))) / scale)
+        print("static chi0", prec, err, herm)
+        assert err < tol
+        assert herm < (1e-13 if prec == "fp64" else tol)
+
+
 def test_size_limits_and_empty_inputs(ctx):
     """Edge sizes through the C ABI: only G = 0 (n_G = 1, where the LFE and
     noLFE forms coincide); the largest frequency count of one call (65536),
