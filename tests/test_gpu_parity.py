@@ -168,8 +168,8 @@ def test_size_limits_and_empty_inputs(ctx):
     noLFE forms coincide); the largest frequency count of one call (65536),
     checked against the oracle on sampled frequencies in FP64 and
     split-BF16; and empty or oversized requests (no frequency, 65537
-    frequencies, no G, 4097 G) returned as QCX_EINVAL, after which the
-    context still works."""
+    frequencies, no G, 4097 G, no occupied or no empty band) returned as
+    QCX_EINVAL, after which the context still works."""
     from paper_2603_12326_amd import QcxError
     from paper_2603_12326_amd import qcx as q
 
@@ -199,6 +199,11 @@ def test_size_limits_and_empty_inputs(ctx):
     for bad_g in (np.zeros((0, 3), np.int32), np.zeros((4097, 3), np.int32)):
         with pytest.raises(QcxError) as e:
             ctx.pair_density(bad_g)
+        assert e.value.code == q.EINVAL
+    st = wl.states(0)
+    for n_occ in (0, st.E_k.shape[1]):          # no occupied or no empty band
+        with pytest.raises(QcxError) as e:
+            ctx.set_states(st.q_cart, wl.k_frac, n_occ, st.C_k, st.E_k, st.C_kq, st.E_kq)
         assert e.value.code == q.EINVAL
     ref = _oracle(wl, w=w, G=G)
     out = gpu_solve(ctx, wl, precision="fp64", w_eV=w, G_int=G)
