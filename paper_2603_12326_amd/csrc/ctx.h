@@ -36,6 +36,7 @@ struct qcx_ctx {
 
   // cell and basis
   bool have_basis = false;
+  bool f0_valid = false;  // d_F0 holds the Q = 0 integrals of the current basis
   double lat[9], rec[9], vol = 0.0;
   int n_atoms = 0, n_sh = 0, n_ao = 0, lrange = 1, n_cells = 0;
   std::vector<int> sh_l, sh_off, cells;

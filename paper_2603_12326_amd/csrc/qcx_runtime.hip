@@ -250,6 +250,7 @@ int qcx_set_cell_basis(qcx_ctx* ctx, const double lat[9], int n_atoms, const dou
   if (int rc = reject_capture(ctx)) return rc;
   HIPCK(hipSetDevice(ctx->device));
   ctx->have_basis = ctx->have_states = ctx->have_rho = ctx->have_chi0 = ctx->have_eps = false;
+  ctx->f0_valid = false;
   memcpy(ctx->lat, lat, sizeof(double) * 9);
   double inv[9];
   inv3(lat, inv);
@@ -378,16 +379,19 @@ int qcx_set_states(qcx_ctx* ctx, const double q_cart[3], int n_k, const double* 
   for (int i = 0; i < 3; ++i)
     qf[i] = (ctx->lat[3 * i] * q_cart[0] + ctx->lat[3 * i + 1] * q_cart[1] +
              ctx->lat[3 * i + 2] * q_cart[2]) / (2.0 * kPi);
-  HIPCK(upload(ctx, ctx->d_Q, zero3, 3));
-  HIPCK(ctx->d_F0.reserve(sizeof(cplx) * nT * (size_t)nao * nao));
   HIPCK(ctx->d_ph.reserve(sizeof(cplx) * (size_t)n_k * nT));
   HIPCK(ctx->d_phq.reserve(sizeof(cplx) * (size_t)n_k * nT));
   HIPCK(ctx->d_S.reserve(sizeof(cplx) * (size_t)n_k * nao * nao));
   HIPCK(ctx->d_dev.reserve(sizeof(double) * 2 * (size_t)n_k));
-  ShellTab sh = shell_tab(ctx);
-  launch_cell_ft(sh, ctx->d_shp.as<int>(), ctx->d_tvec.as<double>(), nT, ctx->d_Q.as<double>(), 1,
-                 ctx->d_F0.as<cplx>(), st);
-  LAUNCHCK("cell_ft(S)");
+  if (!ctx->f0_valid) {  // the Q = 0 integrals depend on the basis only
+    HIPCK(upload(ctx, ctx->d_Q, zero3, 3));
+    HIPCK(ctx->d_F0.reserve(sizeof(cplx) * nT * (size_t)nao * nao));
+    ShellTab sh = shell_tab(ctx);
+    launch_cell_ft(sh, ctx->d_shp.as<int>(), ctx->d_tvec.as<double>(), nT, ctx->d_Q.as<double>(),
+                   1, ctx->d_F0.as<cplx>(), st);
+    LAUNCHCK("cell_ft(S)");
+    ctx->f0_valid = true;
+  }
   launch_bloch_phase(ctx->d_kf.as<double>(), n_k, zero3, ctx->d_cells.as<int>(), nT,
                      ctx->d_ph.as<cplx>(), st);
   launch_bloch_phase(ctx->d_kf.as<double>(), n_k, qf, ctx->d_cells.as<int>(), nT,
