@@ -94,3 +94,39 @@ def test_optical_errors(ctx, small_wl):
     with pytest.raises(QcxError) as e:        # q + G = 0 without the optical limit
         ctx.pair_density(small_wl.G_int)
     assert e.value.code == q.EINVAL
+
+
+def test_optical_benchmark_size(ctx):
+    """The benchmark cell at its full size (28 AO, 4 + 16 bands, 8^3 k, N_G =
+    113) at q = 0 along x, as bench.py's optical workload runs it: the k.p row
+    and the other rows of the pair densities (1e-12) and the loss on six
+    frequencies across 0-60 eV (FP64 1e-10, split-BF16 1e-4) against the
+    oracle's App. C route."""
+    import torch
+
+    from synth import make_si_ng113
+
+    wl = make_si_ng113()
+    st = _set_q0(ctx, wl)
+    G = wl.G_int
+    qh = (1.0, 0.0, 0.0)
+    n_c = st.C_k.shape[2] - wl.n_occ
+    rho = torch.empty((2, len(wl.k_frac), wl.n_occ, n_c, len(G)), dtype=torch.complex128,
+                      device="cuda")
+    print("optical, benchmark size", flush=True)
+    ctx.pair_density_optical(G, qh, rho)
+    R = rpa.pair_densities_optical(wl.cell, wl.basis, wl.lattice_range, wl.k_frac, G, st.C_k,
+                                   st.E_k, wl.n_occ, qh)
+    rg = rho.cpu().numpy()
+    e0, e1 = relmax(rg[..., 0], R[..., 0]), relmax(rg[..., 1:], R[..., 1:])
+    print("benchmark size: k.p row", e0, "G != 0 rows", e1)
+    assert e0 < 1e-12 and e1 < 1e-12
+    w = wl.w_eV[[20, 60, 100, 160, 240, 399]]
+    W = rpa.transition_weights(st.E_k, st.E_k, wl.n_occ, w, wl.eta_eV, _vol(wl))
+    Lref = rpa.loss_lfe(rpa.epsilon_optical(rpa.chi0(R, W), wl.cell.lat, G))
+    for prec, tol in (("fp64", 1e-10), ("split_bf16", 1e-4)):
+        ctx.chi0(w, wl.eta_eV, prec, True)
+        ctx.eps_inv(True)
+        e = normwise(ctx.loss(), Lref)
+        print("benchmark size", prec, "loss", e)
+        assert e < tol
