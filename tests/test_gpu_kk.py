@@ -150,3 +150,20 @@ def test_kk_errors(ctx, small_wl):
         c.chi0_kk(small_wl.w_eV, 0.2, 0.05)
     assert e.value.code == q.ESTATE
     c.close()
+
+
+def test_kk_benchmark_size(ctx):
+    """The benchmark workload at full size (28 AO, 4 + 16 bands, 8^3 k,
+    N_G = 113, first q) through the Kramers-Kronig route with bins of
+    0.1 eV (about 600 per side), six frequencies across 0-60 eV, against the
+    oracle's binned route: chi0 and the loss at the FP64 bars."""
+    from synth import make_si_ng113
+
+    wl = make_si_ng113()
+    w = wl.w_eV[[20, 60, 100, 160, 240, 399]]
+    print("Kramers-Kronig route, benchmark size", flush=True)
+    chi, L = _gpu_kk(ctx, wl, w, wl.eta_eV, 0.1)
+    cref, Lref = _oracle_kk(wl, w, wl.eta_eV, 0.1)
+    ec, el = relmax(chi, cref), normwise(L, Lref)
+    print("benchmark size: chi0", ec, "loss", el)
+    assert ec < TOL_CHI and el < TOL_LOSS
