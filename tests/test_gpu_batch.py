@@ -178,6 +178,27 @@ def test_batch_against_oracle(rho):
         c.close()
 
 
+def test_full_batch_against_oracle_sampled(full_batch):
+    """The batch at its full sizes (k grids 6^3 to 10^3) against the oracle
+    on four frequencies of items 0, 6, 12 and 19 (N_G 59, 113, 181, 259):
+    split-BF16 within 1e-4 and FP64 within 1e-10 (normwise per G curve)."""
+    items, ctxs = full_batch
+    pick = [0, 6, 12, 19]
+    refs = {}
+    for i in pick:
+        wl = items[i]
+        idx = np.unique(np.linspace(0, len(wl.w_eV) - 1, 4).astype(int))
+        refs[i] = (idx, rpa.solve(wl.cell, wl.basis, wl.lattice_range, wl.k_frac, wl.n_occ,
+                                  wl.G_int, wl.states(0), wl.w_eV[idx], wl.eta_eV))
+    for prec, tol in (("split_bf16", 1e-4), ("fp64", 1e-10)):
+        got, _ = _batch(ctxs, items, prec)
+        for i in pick:
+            idx, ref = refs[i]
+            e = normwise(got[i][idx], ref)
+            print("full batch vs oracle", items[i].name, len(items[i].G_int), prec, e)
+            assert e < tol, (items[i].name, prec, e)
+
+
 @pytest.mark.parametrize("prec", ["split_bf16", "fp64"])
 def test_batch_rho_equals_given_densities(full_batch, prec):
     """The full mixed batch with its pair densities computed inside the plan
