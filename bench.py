@@ -603,7 +603,7 @@ def main_kk(args):
         "binning_roofline": {"bound": "alu", "achieved": bin_flops / bin_s / 1e12,
                              "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                              "frac": bin_flops / bin_s / 1e12 / PEAK_FP64_TFLOPS,
-                             "kernel": "k_kk_bin", "avg_launch_ms": 1e3 * bin_s,
+                             "kernel": "k_kk_bin + k_kk_tail", "avg_launch_ms": 1e3 * bin_s,
                              "flops_per_launch": bin_flops},
         "stages_ms_per_step": {k: (v / args.steps if k.endswith("_ms") else v) for k, v in st.items()},
         "direct_value": points * args.steps / sec_d,

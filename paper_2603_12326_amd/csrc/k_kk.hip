@@ -47,23 +47,34 @@ __global__ void __launch_bounds__(256) k_kk_pack(const cplx* __restrict__ R, siz
 
 // ------------------------------------------------------------------ binning
 // Block = one 64 x 64 tile (ti <= tj) of the (G, G') plane and one chunk of
-// bins; thread (ty, tx) owns G = g0 + ty + 16 k, G' = h0 + tx + 16 l
-// (k, l < 4).  The transitions of the chunk are walked in energy order, 16 at
-// a time staged in LDS.  Two accumulators per pair hold the bins i and i + 1
-// of the current interval; when the interval changes, finished bins are
-// stored (each bin of the chunk exactly once, empty bins as zero), so the
-// result needs no atomics and does not depend on the launch.
-constexpr int KB_TC = 16;
+// intervals; thread (ty, tx) owns G = g0 + ty + 16 k, G' = h0 + tx + 16 l
+// (k, l < 4).  The transitions of the chunk are walked in energy order, 32 at
+// a time staged in LDS (two blocks of 66 KB fit a CU).  Two accumulators per
+// pair hold the bins i and i + 1 of the current interval; when the interval
+// changes, finished bins are stored (each bin of the chunk exactly once,
+// empty bins as zero).  The share of the chunk's last interval in the bin
+// after the chunk goes to the chunk's own row of E and is added to that bin
+// by k_kk_tail, so every transition is read once, no atomics are needed and
+// the result does not depend on the launch.
+constexpr int KB_TC = 32;
 
+// Tile pair p of the upper triangle of T x T tiles: the T (T - 1) / 2
+// off-diagonal pairs first, then the T diagonal ones, which hold about 10/16
+// of the work, so that the short blocks are the last to be dispatched.
 __device__ inline void tile_of(int p, int T, int& ti, int& tj) {
-  int r = 0, s = T;
-  while (p >= s) {  // row r of the upper triangle holds T - r tiles
+  const int n_off = T * (T - 1) / 2;
+  if (p >= n_off) {
+    ti = tj = p - n_off;
+    return;
+  }
+  int r = 0, s = T - 1;
+  while (p >= s) {  // row r holds the T - 1 - r pairs (r, r + 1 ..)
     p -= s;
     ++r;
     --s;
   }
   ti = r;
-  tj = r + p;
+  tj = r + 1 + p;
 }
 
 // One (chunk, tile) of the binning.  DIAG (a tile on the diagonal, ti = tj):
@@ -74,6 +85,7 @@ __device__ __forceinline__ void kk_bin_tile(const cplx* __restrict__ Rs, int n_g
                                             const int* __restrict__ ib,
                                             const double* __restrict__ xf, const KkChunk ch,
                                             int ti, int tj, double* __restrict__ S,
+                                            double* __restrict__ E,
                                             cplx (&sa)[KB_TC][kKkTile], cplx (&sb)[KB_TC][kKkTile],
                                             int (&sib)[KB_TC], double (&sx)[KB_TC]) {
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
@@ -86,9 +98,9 @@ __device__ __forceinline__ void kk_bin_tile(const cplx* __restrict__ Rs, int n_g
 #pragma unroll
     for (int l = 0; l < 4; ++l) lr[k][l] = li[k][l] = hr[k][l] = hi[k][l] = 0.0;
 
-  // bin j of the chunk (0 <= j < nb) <- (vr, vi) for this thread's pairs
-  auto store = [&](int j, const double (&vr)[4][4], const double (&vi)[4][4], bool zero) {
-    const size_t base = (size_t)(ch.row0 + j) * 2 * n_pairs;
+  // row (Re at base, Im at base + n_pairs) <- (vr, vi) for this thread's pairs
+  auto store_at = [&](double* __restrict__ base, const double (&vr)[4][4],
+                      const double (&vi)[4][4], bool zero) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int G = g0 + ty + 16 * k;
@@ -97,11 +109,15 @@ __device__ __forceinline__ void kk_bin_tile(const cplx* __restrict__ Rs, int n_g
         const int Gp = h0 + tx + 16 * l;
         if (G < n_g && Gp < n_g && G <= Gp) {
           const size_t p = (size_t)G * n_g - (size_t)G * (G - 1) / 2 + (Gp - G);
-          S[base + p] = zero ? 0.0 : vr[k][l];
-          S[base + n_pairs + p] = zero ? 0.0 : vi[k][l];
+          base[p] = zero ? 0.0 : vr[k][l];
+          base[n_pairs + p] = zero ? 0.0 : vi[k][l];
         }
       }
     }
+  };
+  // bin j of the chunk (0 <= j < nb)
+  auto store = [&](int j, const double (&vr)[4][4], const double (&vi)[4][4], bool zero) {
+    store_at(S + (size_t)(ch.row0 + j) * 2 * n_pairs, vr, vi, zero);
   };
   int wn = 0;  // next bin of the chunk not yet stored
   auto put = [&](int j, const double (&vr)[4][4], const double (&vi)[4][4]) {
@@ -175,15 +191,17 @@ __device__ __forceinline__ void kk_bin_tile(const cplx* __restrict__ Rs, int n_g
     }
   }
   put(cur - ch.k0, lr, li);
-  put(cur + 1 - ch.k0, hr, hi);
+  put(cur + 1 - ch.k0, hr, hi);  // bin nb (past the chunk) is not stored here
   for (; wn < ch.nb; ++wn) store(wn, lr, li, true);
+  // bin nb: zero unless the last interval of the chunk held transitions
+  store_at(E + (size_t)blockIdx.x * 2 * n_pairs, hr, hi, cur + 1 != ch.k0 + ch.nb);
 }
 
 __global__ void __launch_bounds__(256) k_kk_bin(const cplx* __restrict__ Rs, int n_gp, int n_g,
                                                 const int* __restrict__ ib,
                                                 const double* __restrict__ xf,
                                                 const KkChunk* __restrict__ chunks,
-                                                double* __restrict__ S) {
+                                                double* __restrict__ S, double* __restrict__ E) {
   __shared__ cplx sa[KB_TC][kKkTile], sb[KB_TC][kKkTile];
   __shared__ int sib[KB_TC];
   __shared__ double sx[KB_TC];
@@ -191,9 +209,23 @@ __global__ void __launch_bounds__(256) k_kk_bin(const cplx* __restrict__ Rs, int
   tile_of(blockIdx.y, n_gp / kKkTile, ti, tj);
   const KkChunk ch = chunks[blockIdx.x];
   if (ti == tj)  // the same for the whole block
-    kk_bin_tile<true>(Rs, n_gp, n_g, ib, xf, ch, ti, tj, S, sa, sb, sib, sx);
+    kk_bin_tile<true>(Rs, n_gp, n_g, ib, xf, ch, ti, tj, S, E, sa, sb, sib, sx);
   else
-    kk_bin_tile<false>(Rs, n_gp, n_g, ib, xf, ch, ti, tj, S, sa, sb, sib, sx);
+    kk_bin_tile<false>(Rs, n_gp, n_g, ib, xf, ch, ti, tj, S, E, sa, sb, sib, sx);
+}
+
+// Bin tail of every chunk: S[tail] = E[chunk] (+ S[tail] when the next chunk
+// of the side has stored its own share of that bin).  Rows are distinct per
+// chunk, so the order of the additions is fixed.
+__global__ void __launch_bounds__(256) k_kk_tail(const KkChunk* __restrict__ chunks,
+                                                 size_t row_len, const double* __restrict__ E,
+                                                 double* __restrict__ S) {
+  const KkChunk ch = chunks[blockIdx.y];
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= row_len) return;
+  double* dst = S + (size_t)ch.tail_row * row_len + i;
+  const double e = E[(size_t)blockIdx.y * row_len + i];
+  *dst = ch.tail_add ? *dst + e : e;
 }
 
 // ---------------------------------------------------------------- transform
@@ -370,10 +402,13 @@ void launch_kk_pack(const cplx* R, size_t ldt, int n_g, int n_gp, int n_t, const
 }
 
 void launch_kk_bin(const cplx* Rs, int n_gp, int n_g, const int* ib, const double* xf,
-                   const KkChunk* chunks, int n_chunks, double* S, hipStream_t st) {
+                   const KkChunk* chunks, int n_chunks, double* S, double* E, hipStream_t st) {
   const int T = n_gp / kKkTile;
   hipLaunchKernelGGL(k_kk_bin, dim3((unsigned)n_chunks, (unsigned)(T * (T + 1) / 2)), dim3(256), 0,
-                     st, Rs, n_gp, n_g, ib, xf, chunks, S);
+                     st, Rs, n_gp, n_g, ib, xf, chunks, S, E);
+  const size_t row_len = (size_t)n_g * (n_g + 1);  // 2 n_pairs
+  hipLaunchKernelGGL(k_kk_tail, dim3((unsigned)((row_len + 255) / 256), (unsigned)n_chunks),
+                     dim3(256), 0, st, chunks, row_len, E, S);
 }
 
 void launch_kk_matrix(const double* w, int n_w, double eta, double d, int nr, int na, int br,

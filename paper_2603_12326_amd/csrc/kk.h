@@ -15,11 +15,15 @@
 
 namespace qcx {
 
-// One run of consecutive bins [k0, k0 + nb) of one side, rows row0 + (0..nb)
-// of S, and the transitions [ta, tb) (energy order) whose hat functions reach
-// them: intervals k0 - 1 .. k0 + nb - 1.
+// One run of consecutive intervals [k0, k0 + nb) of one side and their
+// transitions [ta, tb) (energy order).  The chunk stores the bins k0 ..
+// k0 + nb - 1 (rows row0 + (0..nb) of S; bin k0 without the share of
+// interval k0 - 1) and leaves the share of its last interval in bin k0 + nb
+// in its row of E, which the tail pass adds to S row tail_row (tail_add = 1:
+// the next chunk has stored its share of that bin) or stores there
+// (tail_add = 0: the side's last bin).
 struct KkChunk {
-  int row0, k0, nb, ta, tb;
+  int row0, k0, nb, ta, tb, tail_row, tail_add;
 };
 
 constexpr int kKkTile = 64;  // G and G' rows of one binning block
@@ -27,9 +31,11 @@ constexpr int kKkTile = 64;  // G and G' rows of one binning block
 // Rs[rank[t]][n_gp] = R[G][t] (zero for G >= n_g); rank = energy order of t
 void launch_kk_pack(const cplx* R, size_t ldt, int n_g, int n_gp, int n_t, const int* rank,
                     cplx* Rs, hipStream_t st);
-// S[row][2][n_pairs] (Re, Im) for every chunk and upper-triangle pair (G <= G')
+// S[row][2][n_pairs] (Re, Im) for every bin and upper-triangle pair
+// (G <= G'): the binning, then the tail pass; E holds n_chunks rows of
+// 2 n_pairs doubles of scratch
 void launch_kk_bin(const cplx* Rs, int n_gp, int n_g, const int* ib, const double* xf,
-                   const KkChunk* chunks, int n_chunks, double* S, hipStream_t st);
+                   const KkChunk* chunks, int n_chunks, double* S, double* E, hipStream_t st);
 // Kb[rows_p][ldm] (bin-major): entry (c, 2j) = Re, (c, 2j + 1) = Im of the
 // transform kernel of w_j for bin c: resonant bins c < nr at (br + c) d,
 // anti-resonant bins nr <= c < nr + na at (ba + c - nr) d; zero for

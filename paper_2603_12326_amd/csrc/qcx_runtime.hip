@@ -1021,12 +1021,14 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
       ib[k] = iv[t];
       xf[k] = u - std::floor(u);
     }
-    // bins [k0, k1) take the transitions of intervals k0 - 1 .. k1 - 1
-    for (int k0 = 0; k0 < nbin[s];) {
-      const int a = std::max(k0 - 1, 0);
+    // chunks of whole intervals [k0, k1), at most kKkChunkT transitions
+    // unless one interval holds more; bin n_int (the side's last) is stored
+    // by the tail pass of the last chunk
+    for (int k0 = 0; k0 < n_int;) {
       int k1 = k0 + 1;
-      while (k1 < nbin[s] && off[std::min(k1 + 1, n_int)] - off[a] <= kKkChunkT) ++k1;
-      chunks.push_back({rows + k0, k0, k1 - k0, t_lo + off[a], t_lo + off[std::min(k1, n_int)]});
+      while (k1 < n_int && off[k1 + 1] - off[k0] <= kKkChunkT) ++k1;
+      chunks.push_back({rows + k0, k0, k1 - k0, t_lo + off[k0], t_lo + off[k1], rows + k1,
+                        k1 < n_int ? 1 : 0});
       k0 = k1;
     }
     rows += nbin[s];
@@ -1034,7 +1036,8 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
   const int n_gp = (int)roundup(n_g, kKkTile);
   const size_t n_pairs = (size_t)n_g * (n_g + 1) / 2;
   const int rows_p = kk_rows_padded(rows), ldm = kk_ldm(n_w);
-  if ((double)rows * 2 * n_pairs * sizeof(double) > kKkSpectralBudget)
+  // S (rows_p bins) and E (one row per chunk) share one buffer
+  if ((double)(rows + chunks.size()) * 2 * n_pairs * sizeof(double) > kKkSpectralBudget)
     return fail(ctx, QCX_EINVAL, "binned spectral function exceeds 16 GB: widen bin_eV");
   if (chunks.size() > (size_t)INT_MAX) return fail(ctx, QCX_EINVAL, "too many bins");
 
@@ -1045,7 +1048,8 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
   HIPCK(upload(ctx, ctx->d_kk_xf, xf.data(), xf.size()));
   HIPCK(upload(ctx, ctx->d_kk_chunks, chunks.data(), chunks.size()));
   HIPCK(ctx->d_kk_Rs.reserve(sizeof(cplx) * (size_t)n_t * n_gp));
-  HIPCK(ctx->d_kk_S.reserve(sizeof(double) * ((size_t)rows_p * 2 * n_pairs + kk_s_slack())));
+  const size_t e_off = (size_t)rows_p * 2 * n_pairs + kk_s_slack();
+  HIPCK(ctx->d_kk_S.reserve(sizeof(double) * (e_off + chunks.size() * 2 * n_pairs)));
   HIPCK(ctx->d_kk_K.reserve(sizeof(double) * (size_t)rows_p * ldm));
   // bins past the last (padding of the transform's K tiles) are zero; the
   // binning writes every real bin
@@ -1063,7 +1067,8 @@ int qcx_chi0_kk(qcx_ctx* ctx, int n_w, const double* w_eV, double eta_eV, double
                  ctx->d_kk_Rs.as<cplx>(), st);
   HIPCK(span_begin(ctx, 1, &sp_bin));
   launch_kk_bin(ctx->d_kk_Rs.as<cplx>(), n_gp, n_g, ctx->d_kk_ib.as<int>(), ctx->d_kk_xf.as<double>(),
-                ctx->d_kk_chunks.as<KkChunk>(), (int)chunks.size(), ctx->d_kk_S.as<double>(), st);
+                ctx->d_kk_chunks.as<KkChunk>(), (int)chunks.size(), ctx->d_kk_S.as<double>(),
+                ctx->d_kk_S.as<double>() + e_off, st);
   HIPCK(span_end(ctx, sp_bin));
   LAUNCHCK("kk binning");
   launch_kk_matrix(ctx->d_w.as<double>(), n_w, eta, d, nbin[0], nbin[1], base[0], base[1], rows_p,
