@@ -48,15 +48,28 @@ __global__ void __launch_bounds__(256) k_kk_pack(const cplx* __restrict__ R, siz
 // ------------------------------------------------------------------ binning
 // Block = one 64 x 64 tile (ti <= tj) of the (G, G') plane and one chunk of
 // intervals; thread (ty, tx) owns G = g0 + ty + 16 k, G' = h0 + tx + 16 l
-// (k, l < 4).  The transitions of the chunk are walked in energy order, 32 at
-// a time staged in LDS (two blocks of 66 KB fit a CU).  Two accumulators per
+// (k, l < 4).  The transitions of the chunk are walked in energy order, 16 at
+// a time staged in LDS by direct global-to-LDS loads into one of two buffers
+// while the other is consumed (two blocks of 64 KB fit a CU).  Two accumulators per
 // pair hold the bins i and i + 1 of the current interval; when the interval
 // changes, finished bins are stored (each bin of the chunk exactly once,
 // empty bins as zero).  The share of the chunk's last interval in the bin
 // after the chunk goes to the chunk's own row of E and is added to that bin
 // by k_kk_tail, so every transition is read once, no atomics are needed and
 // the result does not depend on the launch.
-constexpr int KB_TC = 32;
+constexpr int KB_TC = 16;
+typedef __attribute__((address_space(3))) void lds_void;
+
+// 16 bytes per lane from g into LDS at l + 16 * lane (l the same for the
+// wave).  Written as asm so that the compiler does not order every LDS read
+// after it (it cannot tell that the reads use the other buffer); the kernel
+// waits for it itself (s_waitcnt vmcnt(0) before the barrier that publishes
+// the stage).  It has no register result.
+__device__ __forceinline__ void lds_load16(const void* g, lds_void* l) {
+  const unsigned base = __builtin_amdgcn_readfirstlane((unsigned)(size_t)l);
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(base)
+               : "memory", "m0");
+}
 
 // Tile pair p of the upper triangle of T x T tiles: the T (T - 1) / 2
 // off-diagonal pairs first, then the T diagonal ones, which hold about 10/16
@@ -86,8 +99,9 @@ __device__ __forceinline__ void kk_bin_tile(const cplx* __restrict__ Rs, int n_g
                                             const double* __restrict__ xf, const KkChunk ch,
                                             int ti, int tj, double* __restrict__ S,
                                             double* __restrict__ E,
-                                            cplx (&sa)[KB_TC][kKkTile], cplx (&sb)[KB_TC][kKkTile],
-                                            int (&sib)[KB_TC], double (&sx)[KB_TC]) {
+                                            cplx (&sa)[2][KB_TC][kKkTile],
+                                            cplx (&sb)[2][KB_TC][kKkTile],
+                                            int (&sib)[2][KB_TC], double (&sx)[2][KB_TC]) {
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int g0 = ti * kKkTile, h0 = tj * kKkTile;
   const size_t n_pairs = (size_t)n_g * (n_g + 1) / 2;
@@ -127,28 +141,51 @@ __device__ __forceinline__ void kk_bin_tile(const cplx* __restrict__ Rs, int n_g
     wn = j + 1;
   };
 
-  int cur = ch.k0 - 1;  // interval of the accumulators (bins cur, cur + 1)
-  for (int t0 = ch.ta; t0 < ch.tb; t0 += KB_TC) {
+  // Stage at t0 into buffer q: wave w moves the rows tt = w, w + 4, ..
+  // (tt < nt) of the tile's 64 G columns (and the 64 G' columns), one
+  // 16-byte complex per lane, straight into LDS; rows tt >= nt are not read.
+  // The interval and weight of each transition go through registers.
+  const int wv = tid >> 6, lane = tid & 63;
+  int r_ib = 0;
+  double r_x = 0.0;
+  auto issue = [&](int t0, int q) {
     const int nt = min(KB_TC, ch.tb - t0);
-    __syncthreads();
-    for (int e = tid; e < KB_TC * kKkTile; e += 256) {
-      const int tt = e / kKkTile, gg = e % kKkTile;
-      cplx va = {0.0, 0.0}, vb = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < KB_TC / 4; ++j) {
+      const int tt = wv + 4 * j;
       if (tt < nt) {
         const cplx* row = Rs + (size_t)(t0 + tt) * n_gp;
-        va = row[g0 + gg];
-        if (!DIAG) vb = row[h0 + gg];
+        lds_load16(row + g0 + lane, (lds_void*)&sa[q][tt][0]);
+        if (!DIAG) lds_load16(row + h0 + lane, (lds_void*)&sb[q][tt][0]);
       }
-      sa[tt][gg] = va;
-      if (!DIAG) sb[tt][gg] = vb;
     }
     if (tid < nt) {
-      sib[tid] = ib[t0 + tid];
-      sx[tid] = xf[t0 + tid];
+      r_ib = ib[t0 + tid];
+      r_x = xf[t0 + tid];
     }
+  };
+  auto put_meta = [&](int q) {
+    if (tid < KB_TC) {
+      sib[q][tid] = r_ib;
+      sx[q][tid] = r_x;
+    }
+  };
+
+  int cur = ch.k0 - 1;  // interval of the accumulators (bins cur, cur + 1)
+  int q = 0;
+  if (ch.ta < ch.tb) {
+    issue(ch.ta, 0);
+    put_meta(0);
+  }
+  for (int t0 = ch.ta; t0 < ch.tb; t0 += KB_TC) {
+    const int nt = min(KB_TC, ch.tb - t0), t1 = t0 + KB_TC;
+    // the direct loads of this stage (issued one stage ahead) have landed in
+    // every wave, and every wave is done with the buffer the next stage fills
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    if (t1 < ch.tb) issue(t1, q ^ 1);
     for (int tt = 0; tt < nt; ++tt) {
-      const int i = sib[tt];
+      const int i = sib[q][tt];
       if (i != cur) {  // the same for every thread of the block
         put(cur - ch.k0, lr, li);
         if (i == cur + 1) {
@@ -169,12 +206,12 @@ __device__ __forceinline__ void kk_bin_tile(const cplx* __restrict__ Rs, int n_g
         }
         cur = i;
       }
-      const double x = sx[tt], wl = 1.0 - x;
+      const double x = sx[q][tt], wl = 1.0 - x;
       cplx a[4], b[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        a[k] = sa[tt][ty + 16 * k];
-        b[k] = DIAG ? sa[tt][tx + 16 * k] : sb[tt][tx + 16 * k];
+        a[k] = sa[q][tt][ty + 16 * k];
+        b[k] = DIAG ? sa[q][tt][tx + 16 * k] : sb[q][tt][tx + 16 * k];
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -189,6 +226,8 @@ __device__ __forceinline__ void kk_bin_tile(const cplx* __restrict__ Rs, int n_g
           hi[k][l] += x * pi;
         }
     }
+    if (t1 < ch.tb) put_meta(q ^ 1);
+    q ^= 1;
   }
   put(cur - ch.k0, lr, li);
   put(cur + 1 - ch.k0, hr, hi);  // bin nb (past the chunk) is not stored here
@@ -202,9 +241,9 @@ __global__ void __launch_bounds__(256) k_kk_bin(const cplx* __restrict__ Rs, int
                                                 const double* __restrict__ xf,
                                                 const KkChunk* __restrict__ chunks,
                                                 double* __restrict__ S, double* __restrict__ E) {
-  __shared__ cplx sa[KB_TC][kKkTile], sb[KB_TC][kKkTile];
-  __shared__ int sib[KB_TC];
-  __shared__ double sx[KB_TC];
+  __shared__ cplx sa[2][KB_TC][kKkTile], sb[2][KB_TC][kKkTile];
+  __shared__ int sib[2][KB_TC];
+  __shared__ double sx[2][KB_TC];
   int ti, tj;
   tile_of(blockIdx.y, n_gp / kKkTile, ti, tj);
   const KkChunk ch = chunks[blockIdx.x];
