@@ -7,7 +7,9 @@ transforms on FP64 MFMA; the oracle forms every bin from the dense hat
 weights.  Bars: chi0 to 1e-11 of its largest element, the loss to 1e-10
 per G curve (the FP64 bars of the direct route).  Cases: the smallest
 workload at eta = 0.2 eV and at eta = 0 (pure spectral part + its
-Kramers-Kronig transform), one bin wider than every transition energy, the
+Kramers-Kronig transform), one bin wider than every transition energy,
+chunk boundaries (very fine bins with empty intervals, intervals above the
+chunk budget), the
 tiny s/p/d cell (9 G, one 64 x 64 tile, ragged), 137 G (3 x 3 tiles, the
 last ragged), repeatability, and second
 order convergence to the direct FP64 route on the GPU itself.
@@ -93,6 +95,22 @@ def test_kk_one_wide_bin(ctx, small_wl, small_oracle):
     chi, L = _gpu_kk(ctx, small_wl, w, 0.2, 60.0)
     cref, Lref = _oracle_kk(small_wl, w, 0.2, 60.0, small_oracle["R"])
     assert relmax(chi, cref) < TOL_CHI and normwise(L, Lref) < TOL_LOSS
+
+
+@pytest.mark.parametrize("bin_eV", [0.004, 5.0])
+def test_kk_chunk_boundaries(ctx, small_wl, small_oracle, bin_eV):
+    """The binning walks chunks of whole energy intervals (at most 256
+    transitions unless one interval holds more) and adds the share of each
+    chunk's last interval in the next bin in a pass of its own.  0.004 eV:
+    about 6,200 intervals per side of at most 5 transitions, several chunks
+    ending on empty intervals (a zero tail); 5 eV: intervals of 328, 518 and
+    428 transitions, each a chunk above the 256 budget.  Against the oracle."""
+    w = small_wl.w_eV[::8]
+    chi, L = _gpu_kk(ctx, small_wl, w, 0.2, bin_eV)
+    cref, Lref = _oracle_kk(small_wl, w, 0.2, bin_eV, small_oracle["R"])
+    ec, el = relmax(chi, cref), normwise(L, Lref)
+    print(bin_eV, "eV bins: chi0", ec, "loss", el)
+    assert ec < TOL_CHI and el < TOL_LOSS
 
 
 def test_kk_tiny_ragged(ctx, tiny):
